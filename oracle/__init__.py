@@ -1,0 +1,28 @@
+"""CPU oracle for implicit imaginary-time evolution of matrix product states.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports, calls or links
+this package; only the test suite, the smoke check and the CPU-baseline leg of
+the benchmark do.  It shares no code with the HIP library (no kernels, headers,
+helpers or table generators); the two meet only in the seeded inputs of the
+``workload`` module.
+
+Everything is plain FP64 numpy, written so that a reader can check it against
+"Fast Tensor Network Imaginary Time Evolution by Implicit Stepping on
+Logarithmic Grids" (Zima, Stoudenmire, White, Parcollet, Kaye) by eye:
+
+* ``oracle.ed``   -- full state-vector level: Hamiltonians built from Kronecker
+  products, exact evolution through the spectral decomposition (Method, Eq. 1),
+  the implicit trapezoid / backward-Euler full-vector step (Method, Eq. 4),
+  logarithmic and panel grids (Method), the local trapezoid error E(mu) and the
+  explicit steppers used as negative controls (Appendix A).
+* ``oracle.mpo``  -- MPO builders for the Heisenberg chain and the star-geometry
+  Anderson impurity model (Appendix B: MPOs generated exactly, compressed to
+  machine precision) and their contraction to dense matrices.
+* ``oracle.mps``  -- the dense-tensor MPS algorithm: the two-site DMRG-style
+  linear solve of (I + h (H - s)) x = b with b projected into x's basis, GMRES
+  local solves, SVD truncation by discarded weight, normalisation and energy
+  shift after every step (Method; Appendices B and D).
+
+Parity status of every function is stated in its module header; the pins live
+in ``tests/test_oracle_*.py``.
+"""
