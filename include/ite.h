@@ -1,0 +1,286 @@
+/*
+ * ite.h -- C ABI of the MI355X (gfx950) implicit imaginary-time evolution
+ * library for matrix product states.
+ *
+ * The library advances an MPS |psi> under an MPO Hamiltonian H by A-stable
+ * implicit steps on logarithmic tau grids, following "Fast Tensor Network
+ * Imaginary Time Evolution by Implicit Stepping on Logarithmic Grids"
+ * (Zima, Stoudenmire, White, Parcollet, Kaye):
+ *
+ *   trapezoid rule (Method, Eq. 4):  (I + h (H - s)) x = (I - h (H - s)) psi,
+ *                                    h = dtau / 2;
+ *   backward Euler:                  (I + h (H - s)) x = psi, h = dtau;
+ *
+ * solved in MPS form by a two-site DMRG-style sweep whose local problems are
+ * GMRES solves with the effective Hamiltonian (Method, last paragraph;
+ * Appendix B), followed by normalisation and, optionally, a shift s equal to
+ * the energy of the current state (Appendix D).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Numbers on the boundary are real FP64.  Arrays are row-major, last
+ *    index fastest.  Site tensors A_i[D_(i-1)][d_i][D_i]; MPO tensors
+ *    W_i[w_i][w_(i+1)][d_i (out)][d_i (in)] with w_0 = w_L = 1.
+ *  - Host arrays passed in are copied before the call returns; the caller
+ *    keeps ownership.  Outputs go to caller-allocated host memory.
+ *  - Device memory is owned by the context and obtained from the caller's
+ *    allocator (or hipMalloc when none is given).  Handles own their device
+ *    tensors until *_destroy.
+ *  - All device work of a context is ordered on the HIP stream given at
+ *    creation.  Calls return after their work has finished (synchronous at
+ *    step granularity).  A context is not thread-safe: one context per host
+ *    thread.
+ *  - Every function returns an int status (ITE_OK = 0 or a negative code).
+ *    No C++ exception crosses the ABI.  ite_last_error() gives the text of
+ *    the last failure on a context.
+ */
+#ifndef ITE_H
+#define ITE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define ITE_OK          0
+#define ITE_EINVAL     (-1)   /* invalid argument (shape, range, non-finite input) */
+#define ITE_ENOMEM     (-2)   /* allocator returned NULL, or an admission cap was exceeded */
+#define ITE_EDEVICE    (-3)   /* a HIP call failed; see ite_last_error */
+#define ITE_ESTATE     (-4)   /* objects do not fit together (e.g. MPS and MPO of different L) */
+#define ITE_ENONFINITE (-5)   /* the step produced a non-finite state; psi was left unchanged */
+
+/* ---- enumerations ------------------------------------------------------ */
+enum { ITE_SCHEME_TRAP = 0, ITE_SCHEME_BE = 1 };
+enum { ITE_SHIFT_FIXED = 0, ITE_SHIFT_TRACK = 1 };
+enum { ITE_PREC_FP64 = 0, ITE_PREC_FP32_IR = 1, ITE_PREC_BF16_IR = 2 };
+
+/* report flags */
+#define ITE_FLAG_BUDGET_EXHAUSTED 1  /* a local solve ended on its Krylov budget above tol_loc (normal in budget mode) */
+#define ITE_FLAG_BREAKDOWN        2  /* an Arnoldi step found an invariant subspace (exact local solve) */
+#define ITE_FLAG_REFINE_LIMIT     4  /* mixed precision: refinement stopped at max_refine above tol_refine */
+
+/* ---- opaque handles ---------------------------------------------------- */
+typedef struct ite_ctx ite_ctx;
+typedef struct ite_mpo ite_mpo;
+typedef struct ite_mps ite_mps;
+
+/* Device allocator supplied by the caller (e.g. a framework's caching
+ * allocator).  alloc returns device memory of at least `bytes` bytes usable on
+ * the context's stream, or NULL; free releases it.  Both are called from the
+ * thread that calls the library. */
+typedef struct ite_allocator {
+    void* (*alloc)(size_t bytes, void* user);
+    void  (*free)(void* ptr, void* user);
+    void* user;
+} ite_allocator;
+
+/* Options of one implicit step.  ite_default_opts() fills the paper's budget:
+ * trapezoid, shift tracking, Krylov dimension 10, one GMRES cycle, one sweep
+ * (Appendix D), cutoff 1e-10 (Heisenberg chain section). */
+typedef struct ite_step_opts {
+    int    scheme;       /* ITE_SCHEME_TRAP or ITE_SCHEME_BE */
+    int    shift_mode;   /* ITE_SHIFT_FIXED (use `shift`) or ITE_SHIFT_TRACK (s = energy of psi) */
+    double shift;
+    int    chi_max;      /* bond dimension cap, >= 1 */
+    double cutoff;       /* discarded-weight fraction; 0 keeps min(rows, cols, chi_max) values */
+    double tie_rel;      /* a cut inside a group of values closer than tie_rel*sigma_0 moves below it */
+    int    krylov_dim;   /* Arnoldi steps per GMRES cycle, 1..64 */
+    int    max_cycles;   /* GMRES cycles per local solve, >= 1 */
+    double tol_loc;      /* relative residual target; 0 = fixed budget (no early exit) */
+    int    nsweeps;      /* full (left-right-left) sweeps per step, >= 1 */
+    int    precision;    /* ITE_PREC_*: inner matvec precision of the local solves */
+    int    max_refine;   /* mixed precision: refinement rounds per local solve */
+    double tol_refine;   /* mixed precision: FP64 relative residual target (0: run max_refine rounds) */
+} ite_step_opts;
+
+/* Per-step report. */
+typedef struct ite_step_report {
+    double tau;          /* tau after the step */
+    double dtau;         /* step length (2h for the trapezoid rule, h for backward Euler) */
+    double h;
+    double shift;
+    double energy;       /* <psi|H|psi> of the normalised new state */
+    double norm_before;  /* ||x|| before renormalisation */
+    int    max_chi;
+    int    flags;        /* ITE_FLAG_* */
+    double max_disc;     /* largest discarded-weight fraction over the splits */
+    double sum_disc;
+    double max_res_rel;  /* largest local relative residual estimate */
+    double mean_res_rel;
+    long long matvecs_fp64;  /* effective-Hamiltonian products in FP64 */
+    long long matvecs_lo;    /* ... in FP32 or BF16 */
+    double ms_total, ms_rhs, ms_solve, ms_split, ms_env;   /* device time per phase */
+} ite_step_report;
+
+/* ---- context ----------------------------------------------------------- */
+
+/* Create a context on HIP device `device`.  hip_stream: a hipStream_t (NULL =
+ * the default stream).  alloc: NULL for hipMalloc/hipFree.  Errors: EINVAL
+ * (bad device or NULL out), EDEVICE. */
+int ite_ctx_create(int device, void* hip_stream, const ite_allocator* alloc, ite_ctx** out);
+int ite_ctx_destroy(ite_ctx* ctx);
+/* Text of the last error on ctx (never NULL; empty when none).  Valid until
+ * the next call on ctx. */
+const char* ite_last_error(const ite_ctx* ctx);
+/* Library version string. */
+const char* ite_version(void);
+
+/* Fill `o` with the defaults described at ite_step_opts. */
+void ite_default_opts(ite_step_opts* o);
+
+/* ---- Hamiltonian ------------------------------------------------------- */
+
+/* Load an MPO (Method: H represented as an MPO).  d[L] local dimensions,
+ * w[L+1] MPO bond dimensions with w[0] = w[L] = 1, W[i] points to
+ * w[i]*w[i+1]*d[i]*d[i] doubles in [wl][wr][out][in] order (host memory).
+ * Errors: EINVAL (L < 2, d < 1, w[0] != 1, w[L] != 1, w > 16, d > 8,
+ * non-finite entries, NULL pointers), ENOMEM, EDEVICE. */
+int ite_mpo_load(ite_ctx* ctx, int L, const int* d, const int* w,
+                 const double* const* W, ite_mpo** out);
+int ite_mpo_destroy(ite_mpo* mpo);
+
+/* ---- states ------------------------------------------------------------ */
+
+/* Product state from L normalised real spinors (spinors[i] has d[i] entries,
+ * host memory; each is normalised again on entry).  chi_max bounds every
+ * bond of the state for its lifetime.  pad_full = 0: all bonds have dimension
+ * 1.  pad_full = 1: the state is embedded in bonds of dimension
+ * D_i = min(d_1..d_i, d_(i+1)..d_L, chi_max) (products of local dimensions):
+ * row 0 of site i (as a D_(i-1) x (d_i D_i) matrix) is spinor_i (x) e_0 and
+ * the other rows are the remaining rows of the Householder reflector that maps
+ * e_0 to it, so the tensors are right-orthonormal and the state is unchanged.
+ * Errors: EINVAL (L < 2, chi_max < 1, zero or non-finite spinor), ENOMEM,
+ * EDEVICE. */
+int ite_mps_create(ite_ctx* ctx, int L, const int* d, const double* const* spinors,
+                   int chi_max, int pad_full, ite_mps** out);
+
+/* Load site tensors (host memory, A[i] has chi[i]*d[i]*chi[i+1] doubles).  The
+ * tensors must be right-orthonormal (each A_i as a chi[i] x (d_i chi[i+1])
+ * matrix has orthonormal rows for i >= 2) with the norm on site 1 -- the form
+ * every step leaves behind; this is not checked beyond finiteness.  chi[0] =
+ * chi[L] = 1, chi[i] <= chi_max.  Used for checkpoints and tests. */
+int ite_mps_load(ite_ctx* ctx, int L, const int* d, const int* chi,
+                 const double* const* A, int chi_max, ite_mps** out);
+
+/* Export bond dimensions (chi[L+1], required) and, when A is not NULL, the
+ * site tensors into caller buffers A[i] of at least chi[i]*d[i]*chi[i+1]
+ * doubles (call first with A = NULL to learn the sizes). */
+int ite_mps_export(ite_mps* psi, int* chi, double* const* A);
+int ite_mps_destroy(ite_mps* psi);
+
+/* Imaginary time carried by the state (advanced by every step, set to 0 at
+ * creation); ite_mps_set_tau changes it (checkpoint resume). */
+int ite_mps_get_tau(const ite_mps* psi, double* tau);
+int ite_mps_set_tau(ite_mps* psi, double tau);
+
+/* ---- the method ---------------------------------------------------------- */
+
+/* One implicit step (Method, Eq. 4; Appendix B; Appendix D):
+ * solve (I + h (H - s)) x = b with b = psi (BE) or (I - h (H - s)) psi (TRAP)
+ * by one or more two-site sweeps of GMRES local solves with SVD truncation,
+ * normalise, and replace psi by x.  s is opts->shift (FIXED) or <psi|H|psi>
+ * (TRACK).  tau advances by h (BE) or 2h (TRAP).  rep may be NULL.
+ * Errors: EINVAL (h <= 0 or non-finite, bad options), ESTATE (L or d of psi
+ * and H differ), ENOMEM, EDEVICE, ENONFINITE (psi left unchanged). */
+int ite_imag_step(ite_mps* psi, const ite_mpo* H, double h,
+                  const ite_step_opts* opts, ite_step_report* rep);
+
+/* Evolve along the geometric grid 0, tau0, tau0 r, tau0 r^2, ... clamped to
+ * end at tau1 (Method: logarithmic grids), starting at the first grid point
+ * after psi's current tau.  per_step (nullable) receives up to max_steps
+ * reports; *n_steps (nullable) the number of steps taken.  Errors: EINVAL
+ * (tau0 <= 0, tau1 <= tau0, ratio <= 1, non-finite), plus those of
+ * ite_imag_step (the evolution stops at the failing step). */
+int ite_evolve_loggrid(ite_mps* psi, const ite_mpo* H, double tau0, double tau1, double ratio,
+                       const ite_step_opts* opts, ite_step_report* per_step, int max_steps,
+                       int* n_steps);
+
+/* Evolve along an explicit increasing grid taus[0..n_taus) (e.g. the panel
+ * grid of the Method section), starting at the first point after psi's tau. */
+int ite_evolve_grid(ite_mps* psi, const ite_mpo* H, const double* taus, int n_taus,
+                    const ite_step_opts* opts, ite_step_report* per_step, int max_steps,
+                    int* n_steps);
+
+/* <psi|H|psi> / <psi|psi> by a transfer contraction from the right. */
+int ite_measure_energy(ite_mps* psi, const ite_mpo* H, double* energy);
+/* <a|b> (same L and local dimensions, same context). */
+int ite_mps_overlap(ite_mps* a, ite_mps* b, double* out);
+/* ||psi|| (the norm of the centre tensor on site 1). */
+int ite_mps_norm(ite_mps* psi, double* out);
+
+/* ---- grids (host only; no device work) ---------------------------------- */
+
+/* Geometric grid of ite_evolve_loggrid: writes up to cap points (0 first) to
+ * out and their number to *n.  EINVAL for bad parameters or cap too small
+ * (then *n holds the required count). */
+int ite_loggrid(double tau0, double tau1, double ratio, double* out, int cap, int* n);
+/* Panel grid (Method): P panels with endpoints {0, tau_max / 2^(P-j)},
+ * j = 1..P, and n uniform steps per panel: P*n + 1 points. */
+int ite_panel_grid(double tau_max, int P, int n, double* out, int cap, int* npts);
+
+/* ---- building blocks exposed for parity tests ---------------------------
+ * Each operates on caller device memory on the context's stream and returns
+ * after it has finished. */
+
+/* D = alpha op(A) op(B) + beta C in FP64 (row-major; op = transpose when
+ * trans* != 0; C may be NULL).  prec: ITE_PREC_FP64 (FP64 MFMA),
+ * ITE_PREC_FP32_IR (operands rounded to FP32, FP32 MFMA, FP32 accumulation),
+ * ITE_PREC_BF16_IR (operands rounded to BF16, BF16 MFMA, FP32 accumulation). */
+int ite_debug_gemm(ite_ctx* ctx, int transA, int transB, int M, int N, int K, double alpha,
+                   const double* A, int lda, const double* B, int ldb, double beta,
+                   const double* C, int ldc, double* D, int ldd, int prec);
+
+/* y = alpha theta + beta H_eff theta for the two-site effective Hamiltonian
+ * (Method; Appendix B):
+ *   H_eff theta [a', p, q, c'] = sum L[a', w, a] W1[w, v, p, s] W2[v, u, q, t]
+ *                                    R[c', u, c] theta[a, s, t, c].
+ * Shapes: L [Dxl][w0][Dyl], R [Dxr][w2][Dyr], W1 [w0][w1][d1][d1],
+ * W2 [w1][w2][d2][d2] (host), theta [Dyl][d1][d2][Dyr], y [Dxl][d1][d2][Dxr].
+ * y may not alias theta.  prec as in ite_debug_gemm. */
+int ite_debug_heff_apply(ite_ctx* ctx, int Dxl, int Dyl, int Dxr, int Dyr, int d1, int d2,
+                         int w0, int w1, int w2, const double* L, const double* W1h,
+                         const double* W2h, const double* R, const double* theta,
+                         double alpha, double beta, double* y, int prec);
+
+/* Environment updates (device pointers; W host):
+ * dir = 0 (left):  E'[b', v, b] = sum E[a', w, a] X[a', p, b'] W[w, v, p, s] Y[a, s, b]
+ *   E [Dxa][wl][Dya], X [Dxa][d][Dxb], Y [Dya][d][Dyb] -> E' [Dxb][wr][Dyb]
+ * dir = 1 (right): E'[b', w, b] = sum E[c', v, c] X[b', p, c'] W[w, v, p, s] Y[b, s, c]
+ *   E [Dxa][wr][Dya], X [Dxb][d][Dxa], Y [Dyb][d][Dya] -> E' [Dxb][wl][Dyb]
+ * W == NULL means the overlap environment (no MPO index, wl = wr = 1). */
+int ite_debug_env_update(ite_ctx* ctx, int dir, int Dxa, int Dya, int Dxb, int Dyb, int d,
+                         int wl, int wr, const double* E, const double* X, const double* Wh,
+                         const double* Y, double* Eout);
+
+/* Truncated SVD split of theta [Dl][d1][d2][Dr] seen as an (Dl d1) x (d2 Dr)
+ * matrix, by one-sided Jacobi: dir = 0 gives A1 = U, A2 = S V^T; dir = 1 gives
+ * A1 = U S, A2 = V^T.  A1 [Dl][d1][k], A2 [k][d2][Dr] (device, capacity
+ * min(rows, cols, chi_max) columns).  sigma_out (host, nullable, capacity
+ * min(rows, cols)) receives all singular values in descending order; *k_out
+ * and *disc_out (host) the kept count and discarded-weight fraction. */
+int ite_debug_svd_split(ite_ctx* ctx, int dir, int Dl, int d1, int d2, int Dr,
+                        const double* theta, int chi_max, double cutoff, double tie_rel,
+                        double* A1, double* A2, double* sigma_out, int* k_out, double* disc_out);
+
+/* One local solve: GMRES on (alpha I + beta H_eff) x = b with x0 as the
+ * initial guess (shapes as ite_debug_heff_apply with Dyl = Dxl, Dyr = Dxr).
+ * Writes x, the matvec count and the final relative residual estimate. */
+int ite_debug_local_solve(ite_ctx* ctx, int Dl, int Dr, int d1, int d2, int w0, int w1, int w2,
+                          const double* L, const double* W1h, const double* W2h, const double* R,
+                          double alpha, double beta, const double* b, const double* x0,
+                          int krylov_dim, int max_cycles, double tol, int precision,
+                          int max_refine, double tol_refine, double* x, int* matvecs,
+                          double* res_rel);
+
+/* One MFMA instruction of the given kind on fixed inputs, every lane's
+ * accumulator written to out (host, 256 doubles for kind 0): used to check the
+ * lane layout assumed by the GEMM kernels.  kind 0: FP64 16x16x4. */
+int ite_debug_mfma_probe(ite_ctx* ctx, int kind, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ITE_H */

@@ -1,0 +1,915 @@
+// The implicit step of the MPS imaginary-time evolution, driven from the host.
+//
+// One step (Method, Eq. 4 and the two operations listed after it;
+// Appendix B; Appendix D):
+//   x <- copy of psi (normalised, right-orthonormal, centre on site 1);
+//   right environments of <x|H|x>; while x = psi the mixed <x|H|psi> and
+//   <x|psi> environments equal <x|H|x> and the identity;
+//   left-to-right, then right-to-left over the blocks (j, j+1):
+//     theta_psi = psi_j psi_(j+1);
+//     b = P^T psi (backward Euler) or (1 + h s) P^T psi - h P^T H psi
+//       (trapezoid): the right-hand side projected into x's basis through the
+//       mixed environments;
+//     GMRES on (1 - h s) v + h H_eff v = b from x_j x_(j+1);
+//     SVD split (one-sided Jacobi) with truncation, environment updates;
+//   normalise, energy <x|H|x>, psi <- x.
+#include "engine.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <numeric>
+
+namespace ite {
+
+// ---------------------------------------------------------------------------
+// Memory
+// ---------------------------------------------------------------------------
+
+void* dev_alloc(ite_ctx* c, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    bytes = (bytes + 255) & ~size_t(255);
+    void* p = nullptr;
+    if (c->has_alloc) {
+        p = c->alloc.alloc(bytes, c->alloc.user);
+        if (!p) ITE_FAIL(ITE_ENOMEM, "allocator returned NULL for " + std::to_string(bytes) + " bytes");
+    } else {
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+            ITE_FAIL(ITE_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+        HIP_CHECK(e);
+    }
+    return p;
+}
+
+void dev_free(ite_ctx* c, void* p) {
+    if (!p) return;
+    if (c->has_alloc) c->alloc.free(p, c->alloc.user);
+    else (void)hipFree(p);
+}
+
+void* slot(ite_ctx* c, SlotId s, size_t bytes) {
+    if (c->slot_bytes[s] < bytes) {
+        if (c->slot_ptr[s]) {
+            // the old buffer may still be read by queued work
+            HIP_CHECK(hipStreamSynchronize(c->stream));
+            dev_free(c, c->slot_ptr[s]);
+            c->slot_ptr[s] = nullptr;
+            c->slot_bytes[s] = 0;
+        }
+        const size_t nb = bytes + bytes / 8 + 256;
+        c->slot_ptr[s] = dev_alloc(c, nb);
+        c->slot_bytes[s] = nb;
+    }
+    return c->slot_ptr[s];
+}
+
+double* pinned(ite_ctx* c, size_t doubles) {
+    const size_t bytes = std::max<size_t>(doubles, 64) * sizeof(double);
+    if (c->pinned_bytes < bytes) {
+        if (c->pinned) {
+            HIP_CHECK(hipStreamSynchronize(c->stream));
+            (void)hipHostFree(c->pinned);
+            c->pinned = nullptr;
+        }
+        void* p = nullptr;
+        HIP_CHECK(hipHostMalloc(&p, bytes, hipHostMallocDefault));
+        c->pinned = static_cast<double*>(p);
+        c->pinned_bytes = bytes;
+    }
+    return c->pinned;
+}
+
+void sync(ite_ctx* c) { HIP_CHECK(hipStreamSynchronize(c->stream)); }
+
+static void d2h(ite_ctx* c, double* host, const double* dev, size_t n) {
+    HIP_CHECK(hipMemcpyAsync(host, dev, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+}
+static void h2d(ite_ctx* c, void* dev, const void* host, size_t bytes) {
+    HIP_CHECK(hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, c->stream));
+}
+static void d2d(ite_ctx* c, double* dst, const double* src, size_t n) {
+    if (n) HIP_CHECK(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+}
+
+// ---------------------------------------------------------------------------
+// Contractions
+// ---------------------------------------------------------------------------
+
+static void gemm(ite_ctx* c, bool tA, bool tB, int M, int N, int K, double alpha, const double* A, long lda,
+                 const double* B, long ldb, double beta, const double* C, long ldc, double* D, long ldd) {
+    Gemm g;
+    g.M = M; g.N = N; g.K = K; g.tA = tA; g.tB = tB;
+    g.alpha = alpha; g.beta = beta;
+    g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc; g.D = D; g.ldd = ldd;
+    gemm_f64(g, c->stream);
+}
+
+static void stage(ite_ctx* c, const CsrDev& m, Stage st) {
+    st.I = m.I;
+    st.O = m.O;
+    st.rowptr = m.rowptr;
+    st.col = m.col;
+    st.val = m.val;
+    stage_f64(st, c->stream);
+}
+
+void two_site(ite_ctx* c, int Dl, int d1, int Dm, int d2, int Dr, const double* A1, const double* A2,
+              double* theta) {
+    gemm(c, false, false, Dl * d1, d2 * Dr, Dm, 1.0, A1, Dm, A2, (long)d2 * Dr, 0.0, nullptr, 0, theta,
+         (long)d2 * Dr);
+}
+
+// H_eff theta in three stages (Appendix B's local problem):
+//   X1[(a' w), (s t c)]   = L[(a' w), a] theta[a, (s t c)]           GEMM
+//   X3[a'][(p q u)][c]    = WW[(p q u), (w s t)] X1[a'][(w s t)][c]  sparse MPO stage
+//   y[(a' p q), c']       = X3[(a' p q), (u c)] R[c', (u c)]^T        GEMM (+ alpha Cadd)
+void heff_apply(ite_ctx* c, const HeffShape& s, const double* L, const CsrDev& ww, const double* R,
+                const double* theta, double beta, double alpha, const double* Cadd, double* y, Prec prec) {
+    (void)prec;
+    const int I = s.w0 * s.d1 * s.d2, O = s.d1 * s.d2 * s.w2;
+    const size_t nx = (size_t)s.Dxl * std::max(I, O) * s.Dyr;
+    double* X1 = slot_t<double>(c, SL_X1, nx);
+    double* X3 = slot_t<double>(c, SL_X3, nx);
+    gemm(c, false, false, s.Dxl * s.w0, s.d1 * s.d2 * s.Dyr, s.Dyl, 1.0, L, s.Dyl, theta,
+         (long)s.d1 * s.d2 * s.Dyr, 0.0, nullptr, 0, X1, (long)s.d1 * s.d2 * s.Dyr);
+    Stage st;
+    st.G = s.Dxl; st.C = s.Dyr;
+    st.in = X1; st.in_gs = (long)I * s.Dyr; st.in_s1 = s.Dyr;
+    st.out = X3; st.out_gs = (long)O * s.Dyr; st.out_s1 = s.Dyr;
+    stage(c, ww, st);
+    gemm(c, false, true, s.Dxl * s.d1 * s.d2, s.Dxr, s.w2 * s.Dyr, beta, X3, (long)s.w2 * s.Dyr, R,
+         (long)s.w2 * s.Dyr, alpha, Cadd, s.Dxr, y, s.Dxr);
+}
+
+void overlap_apply(ite_ctx* c, int Dxl, int Dyl, int Dxr, int Dyr, int d1, int d2, const double* Lo,
+                   const double* Ro, const double* theta, double alpha, double* y) {
+    const long nmid = (long)d1 * d2;
+    const double* T = theta;
+    if (Lo) {
+        double* X1 = slot_t<double>(c, SL_X1, (size_t)Dxl * nmid * Dyr);
+        gemm(c, false, false, Dxl, (int)(nmid * Dyr), Dyl, Ro ? 1.0 : alpha, Lo, Dyl, theta, nmid * Dyr, 0.0,
+             nullptr, 0, X1, nmid * Dyr);
+        T = X1;
+        if (!Ro) {
+            d2d(c, y, X1, (size_t)Dxl * nmid * Dyr);
+            return;
+        }
+    }
+    if (Ro) {
+        gemm(c, false, true, (int)(Dxl * nmid), Dxr, Dyr, alpha, T, Dyr, Ro, Dyr, 0.0, nullptr, 0, y, Dxr);
+        return;
+    }
+    axpby((size_t)Dxl * nmid * Dyr, alpha, theta, 0.0, nullptr, y, c->stream);
+}
+
+void env_left(ite_ctx* c, int Dxa, int Dya, int Dxb, int Dyb, int d, int wl, int wr, const double* E,
+              const double* X, const CsrDev* W, const double* Y, double* Eout) {
+    if (W) {
+        double* T1 = slot_t<double>(c, SL_X1, (size_t)Dxa * wl * d * Dyb);
+        double* T2 = slot_t<double>(c, SL_X3, (size_t)Dxa * d * wr * Dyb);
+        // T1[(a' w), (s b)] = E[(a' w), a] Y[a, (s b)]
+        gemm(c, false, false, Dxa * wl, d * Dyb, Dya, 1.0, E, Dya, Y, (long)d * Dyb, 0.0, nullptr, 0, T1,
+             (long)d * Dyb);
+        // T2[a'][(p v)][b] = WL[(p v), (w s)] T1[a'][(w s)][b]
+        Stage st;
+        st.G = Dxa; st.C = Dyb;
+        st.in = T1; st.in_gs = (long)wl * d * Dyb; st.in_s1 = Dyb;
+        st.out = T2; st.out_gs = (long)d * wr * Dyb; st.out_s1 = Dyb;
+        stage(c, *W, st);
+        // E'[b', (v b)] = X[(a' p), b']^T T2[(a' p), (v b)]
+        gemm(c, true, false, Dxb, wr * Dyb, Dxa * d, 1.0, X, Dxb, T2, (long)wr * Dyb, 0.0, nullptr, 0, Eout,
+             (long)wr * Dyb);
+    } else {
+        double* T1 = slot_t<double>(c, SL_X1, (size_t)Dxa * d * Dyb);
+        gemm(c, false, false, Dxa, d * Dyb, Dya, 1.0, E, Dya, Y, (long)d * Dyb, 0.0, nullptr, 0, T1,
+             (long)d * Dyb);
+        gemm(c, true, false, Dxb, Dyb, Dxa * d, 1.0, X, Dxb, T1, Dyb, 0.0, nullptr, 0, Eout, Dyb);
+    }
+}
+
+void env_right(ite_ctx* c, int Dxa, int Dya, int Dxb, int Dyb, int d, int wl, int wr, const double* E,
+               const double* X, const CsrDev* W, const double* Y, double* Eout) {
+    const int we = W ? wr : 1;
+    double* T1 = slot_t<double>(c, SL_X1, (size_t)Dxa * we * Dyb * d);
+    double* T2 = slot_t<double>(c, SL_X3, (size_t)d * Dxa * (W ? wl : 1) * Dyb);
+    // T1[(c' v), (b s)] = E[(c' v), c] Y[(b s), c]^T
+    gemm(c, false, true, Dxa * we, Dyb * d, Dya, 1.0, E, Dya, Y, Dya, 0.0, nullptr, 0, T1, (long)Dyb * d);
+    Stage st;
+    st.G = Dxa; st.C = Dyb;
+    st.in = T1; st.in_gs = (long)we * Dyb * d; st.in_div = d; st.in_s1 = (long)Dyb * d; st.in_s2 = 1;
+    st.in_cs = d;
+    st.out = T2;
+    if (W) {
+        // T2[p][c'][w][b] = WR[(p w), (v s)] T1[c'][v][b][s]
+        st.out_gs = (long)wl * Dyb; st.out_div = wl; st.out_s1 = (long)Dxa * wl * Dyb; st.out_s2 = Dyb;
+        stage(c, *W, st);
+        gemm(c, false, false, Dxb, wl * Dyb, d * Dxa, 1.0, X, (long)d * Dxa, T2, (long)wl * Dyb, 0.0, nullptr,
+             0, Eout, (long)wl * Dyb);
+    } else {
+        ITE_FAIL(ITE_EINVAL, "env_right overlap needs the identity stage");
+    }
+}
+
+void env_right_overlap_pub(ite_ctx* c, const CsrDev& ident, int Dxa, int Dya, int Dxb, int Dyb, int d,
+                              const double* E, const double* X, const double* Y, double* Eout) {
+    double* T1 = slot_t<double>(c, SL_X1, (size_t)Dxa * Dyb * d);
+    double* T2 = slot_t<double>(c, SL_X3, (size_t)d * Dxa * Dyb);
+    // T1[c', (b s)] = E[c', c] Y[(b s), c]^T
+    gemm(c, false, true, Dxa, Dyb * d, Dya, 1.0, E, Dya, Y, Dya, 0.0, nullptr, 0, T1, (long)Dyb * d);
+    // T2[s][c'][b] = T1[c'][b][s]
+    Stage st;
+    st.G = Dxa; st.C = Dyb;
+    st.in = T1; st.in_gs = (long)Dyb * d; st.in_s1 = 1; st.in_cs = d;
+    st.out = T2; st.out_gs = Dyb; st.out_s1 = (long)Dxa * Dyb;
+    stage(c, ident, st);
+    // E'[b', b] = X[b', (s c')] T2[(s c'), b]
+    gemm(c, false, false, Dxb, Dyb, d * Dxa, 1.0, X, (long)d * Dxa, T2, Dyb, 0.0, nullptr, 0, Eout, Dyb);
+}
+
+double dot(ite_ctx* c, const double* x, const double* y, size_t n) {
+    const int nb = reduce_blocks(n);
+    double* part = slot_t<double>(c, SL_PART, (size_t)nb * 64 + 64);
+    double* sm = slot_t<double>(c, SL_SMALL, 512);
+    dot_partials(x, y, n, part, c->stream);
+    finish_partials(part, 1, nb, sm + 256, 0, c->stream);
+    double* h = pinned(c, 64);
+    d2h(c, h, sm + 256, 1);
+    sync(c);
+    return h[0];
+}
+
+// ---------------------------------------------------------------------------
+// Truncated split by one-sided Jacobi
+// ---------------------------------------------------------------------------
+
+int truncation_rank(const std::vector<double>& s, double cutoff, int chi_max, double tie_rel) {
+    const int r = (int)s.size();
+    if (r == 0) return 0;
+    double total = 0.0;
+    for (double v : s) total += v * v;
+    int k = r;
+    if (cutoff > 0.0 && total > 0.0) {
+        // tail[k] = sum_{i >= k} s_i^2, accumulated from the smallest value up
+        std::vector<double> tail(r + 1, 0.0);
+        for (int i = r - 1; i >= 0; --i) tail[i] = tail[i + 1] + s[i] * s[i];
+        k = r;
+        for (int kk = 1; kk <= r; ++kk)
+            if (tail[kk] <= cutoff * total) { k = kk; break; }
+    }
+    k = std::max(1, std::min(k, chi_max));
+    const double tie = tie_rel * s[0];
+    while (k > 1 && k < r && s[k - 1] > tie && s[k - 1] - s[k] <= tie) --k;
+    return k;
+}
+
+SplitResult split(ite_ctx* c, int dir, int Dl, int d1, int d2, int Dr, const double* theta, int chi_max,
+                  double cutoff, double tie_rel, double* A1, double* A2, std::vector<double>* sigma) {
+    const int m = Dl * d1, n = d2 * Dr;
+    const int p = dir == 0 ? m : n, q = dir == 0 ? n : m, ld = p + q;
+    double* Z = slot_t<double>(c, SL_Z, (size_t)p * ld);
+    int nb = (p + 15) / 16;
+    if (nb < 2) nb = 2;
+    if (nb & 1) ++nb;
+    const int npairs = nb / 2, nchunks = std::max(1, (q + 127) / 128);
+    double* gram = slot_t<double>(c, SL_GRAM, (size_t)npairs * nchunks * 1024);
+    double* rot = slot_t<double>(c, SL_ROT, (size_t)npairs * 1024);
+    double* off = slot_t<double>(c, SL_OFF, (size_t)npairs + 16);
+    double* norms = slot_t<double>(c, SL_NORM, (size_t)p + 16);
+    int* perm = slot_t<int>(c, SL_PERM, (size_t)p + 16);
+    jacobi_input(theta, m, n, dir, Z, c->stream);
+    double* host = pinned(c, (size_t)p + 64);
+    const double tol = 8.0 * std::sqrt((double)std::max(q, 1)) * 2.220446049250313e-16;
+    JacobiResult jr = jacobi_rows(Z, p, q, ld, tol, 60, gram, rot, off, host, c->stream);
+    row_norms(Z, p, q, ld, norms, c->stream);
+    d2h(c, host, norms, p);
+    sync(c);
+    std::vector<int> idx(p);
+    std::iota(idx.begin(), idx.end(), 0);
+    std::vector<double> nv(host, host + p);
+    std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) { return nv[a] > nv[b]; });
+    const int r = std::min(m, n);
+    std::vector<double> s(r);
+    for (int i = 0; i < r; ++i) s[i] = nv[idx[i]];
+    SplitResult res;
+    res.k = truncation_rank(s, cutoff, chi_max, tie_rel);
+    double total = 0.0, kept = 0.0;
+    for (int i = 0; i < r; ++i) total += s[i] * s[i];
+    for (int i = res.k; i < r; ++i) kept += s[i] * s[i];
+    res.disc = total > 0.0 ? kept / total : 0.0;
+    res.sweeps = jr.sweeps;
+    if (sigma) *sigma = s;
+    int* hp = reinterpret_cast<int*>(host);
+    std::memcpy(hp, idx.data(), sizeof(int) * res.k);
+    h2d(c, perm, hp, sizeof(int) * res.k);
+    if (dir == 0) gather_split(Z, ld, perm, res.k, 0, q, A2, q, p, A1, c->stream);
+    else gather_split(Z, ld, perm, res.k, q, p, A2, 0, q, A1, c->stream);
+    sync(c);   // the pinned staging buffer is reused by the next call
+    return res;
+}
+
+// ---------------------------------------------------------------------------
+// GMRES local solve
+// ---------------------------------------------------------------------------
+
+static void op_apply(ite_ctx* c, const LocalOp& op, const double* v, double* y) {
+    heff_apply(c, op.s, op.L, *op.ww, op.R, v, op.beta, op.alpha, v, y, Prec::F64);
+}
+
+// GMRES(m) (Saad and Schultz) with classical Gram-Schmidt applied twice; the
+// Hessenberg column comes to the host once per Arnoldi step, where Givens
+// rotations keep the least-squares residual.
+static SolveStats gmres64(ite_ctx* c, const LocalOp& op, const double* b, double* x, int m, int max_cycles,
+                          double tol) {
+    SolveStats st;
+    const size_t n = op.n();
+    const int mm = (int)std::min<size_t>((size_t)m, n);
+    double* V = slot_t<double>(c, SL_V, (size_t)(mm + 1) * n);
+    double* w = slot_t<double>(c, SL_W, n);
+    const int nb = reduce_blocks(n);
+    double* part = slot_t<double>(c, SL_PART, (size_t)nb * 64 + 64);
+    double* sm = slot_t<double>(c, SL_SMALL, 512);   // [0,64) h1, [64,128) h2, 128 norm, [192,256) y
+    double* host = pinned(c, 512);
+    const double bnorm = std::sqrt(std::max(0.0, dot(c, b, b, n)));
+    std::vector<double> H((size_t)(mm + 1) * mm), cs(mm), sn(mm), g(mm + 1), y(mm);
+    for (int cyc = 0; cyc < max_cycles; ++cyc) {
+        // r0 = b - A x
+        op_apply(c, op, x, V);
+        st.matvecs64++;
+        axpby(n, 1.0, b, -1.0, V, V, c->stream);
+        dot_partials(V, V, n, part, c->stream);
+        finish_partials(part, 1, nb, sm + 128, 2, c->stream);
+        d2h(c, host, sm + 128, 1);
+        sync(c);
+        const double beta = host[0];
+        st.res_rel = bnorm > 0 ? beta / bnorm : 0.0;
+        if (!(beta > 0.0) || (tol > 0 && beta <= tol * bnorm)) return st;
+        scale_inv(V, sm + 128, V, n, c->stream);
+        std::fill(H.begin(), H.end(), 0.0);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int kused = 0;
+        bool converged = false;
+        for (int k = 0; k < mm; ++k) {
+            op_apply(c, op, V + (size_t)k * n, w);
+            st.matvecs64++;
+            mdot_partials(V, (long)n, k + 1, w, n, part, c->stream);
+            finish_partials(part, k + 1, nb, sm, 0, c->stream);
+            gemv_sub(V, (long)n, k + 1, sm, w, n, c->stream);
+            mdot_partials(V, (long)n, k + 1, w, n, part, c->stream);
+            finish_partials(part, k + 1, nb, sm + 64, 0, c->stream);
+            gemv_sub(V, (long)n, k + 1, sm + 64, w, n, c->stream);
+            dot_partials(w, w, n, part, c->stream);
+            finish_partials(part, 1, nb, sm + 128, 2, c->stream);
+            d2h(c, host, sm, 129);
+            sync(c);
+            for (int i = 0; i <= k; ++i) H[(size_t)i * mm + k] = host[i] + host[64 + i];
+            const double hnext = host[128];
+            // apply the previous rotations to column k
+            for (int i = 0; i < k; ++i) {
+                const double a = H[(size_t)i * mm + k], bb = H[(size_t)(i + 1) * mm + k];
+                H[(size_t)i * mm + k] = cs[i] * a + sn[i] * bb;
+                H[(size_t)(i + 1) * mm + k] = -sn[i] * a + cs[i] * bb;
+            }
+            const double a = H[(size_t)k * mm + k];
+            const double rr = std::hypot(a, hnext);
+            cs[k] = rr > 0 ? a / rr : 1.0;
+            sn[k] = rr > 0 ? hnext / rr : 0.0;
+            H[(size_t)k * mm + k] = rr;
+            g[k + 1] = -sn[k] * g[k];
+            g[k] = cs[k] * g[k];
+            kused = k + 1;
+            const double res = std::fabs(g[k + 1]);
+            st.res_rel = bnorm > 0 ? res / bnorm : 0.0;
+            if (hnext <= 1e-14 * beta) {
+                st.flags |= ITE_FLAG_BREAKDOWN;
+                converged = true;
+                break;
+            }
+            if (tol > 0 && res <= tol * bnorm) {
+                converged = true;
+                break;
+            }
+            scale_inv(w, sm + 128, V + (size_t)(k + 1) * n, n, c->stream);
+        }
+        // back substitution R y = g
+        for (int i = kused - 1; i >= 0; --i) {
+            double s = g[i];
+            for (int j = i + 1; j < kused; ++j) s -= H[(size_t)i * mm + j] * y[j];
+            const double dgn = H[(size_t)i * mm + i];
+            y[i] = dgn != 0.0 ? s / dgn : 0.0;
+        }
+        for (int i = 0; i < kused; ++i) host[256 + i] = y[i];
+        h2d(c, sm + 192, host + 256, sizeof(double) * kused);
+        gemv_add(V, (long)n, kused, sm + 192, x, n, c->stream);
+        sync(c);
+        if (converged) return st;
+        if (tol <= 0) {
+            if (cyc + 1 == max_cycles) st.flags |= ITE_FLAG_BUDGET_EXHAUSTED;
+            continue;
+        }
+        if (cyc + 1 == max_cycles) st.flags |= ITE_FLAG_BUDGET_EXHAUSTED;
+    }
+    return st;
+}
+
+SolveStats local_solve(ite_ctx* c, const LocalOp& op, const double* b, double* x, int m, int max_cycles,
+                       double tol, int precision, int max_refine, double tol_refine) {
+    (void)precision; (void)max_refine; (void)tol_refine;
+    return gmres64(c, op, b, x, m, max_cycles, tol);
+}
+
+// ---------------------------------------------------------------------------
+// MPO handle
+// ---------------------------------------------------------------------------
+
+namespace {
+struct CsrHost {
+    int I = 0, O = 0;
+    std::vector<int> rowptr, col;
+    std::vector<double> val;
+};
+
+CsrHost dense_to_csr(const std::vector<double>& M, int O, int I) {
+    CsrHost h;
+    h.I = I;
+    h.O = O;
+    h.rowptr.push_back(0);
+    for (int o = 0; o < O; ++o) {
+        for (int i = 0; i < I; ++i) {
+            const double v = M[(size_t)o * I + i];
+            if (v != 0.0) {
+                h.col.push_back(i);
+                h.val.push_back(v);
+            }
+        }
+        h.rowptr.push_back((int)h.col.size());
+    }
+    return h;
+}
+}  // namespace
+
+ite_mpo* mpo_load(ite_ctx* c, int L, const int* d, const int* w, const double* const* W) {
+    ITE_REQUIRE(L >= 2, "mpo_load: L must be >= 2");
+    ITE_REQUIRE(d && w && W, "mpo_load: NULL array");
+    ITE_REQUIRE(w[0] == 1 && w[L] == 1, "mpo_load: boundary MPO bond dimensions must be 1");
+    for (int i = 0; i < L; ++i) {
+        ITE_REQUIRE(d[i] >= 1 && d[i] <= 8, "mpo_load: local dimension must be in 1..8");
+        ITE_REQUIRE(W[i] != nullptr, "mpo_load: NULL tensor");
+    }
+    for (int i = 0; i <= L; ++i) ITE_REQUIRE(w[i] >= 1 && w[i] <= 16, "mpo_load: MPO bond dimension must be in 1..16");
+    std::unique_ptr<ite_mpo> m(new ite_mpo);
+    m->ctx = c;
+    m->L = L;
+    m->d.assign(d, d + L);
+    m->w.assign(w, w + L + 1);
+    m->Wh.resize(L);
+    for (int i = 0; i < L; ++i) {
+        const size_t n = (size_t)w[i] * w[i + 1] * d[i] * d[i];
+        m->Wh[i].assign(W[i], W[i] + n);
+        for (double v : m->Wh[i]) ITE_REQUIRE(std::isfinite(v), "mpo_load: non-finite MPO entry");
+    }
+    auto Wat = [&](int i, int a, int b, int p, int s) {
+        const int di = m->d[i];
+        return m->Wh[i][(((size_t)a * m->w[i + 1] + b) * di + p) * di + s];
+    };
+    std::vector<CsrHost> hp, hl, hr, hi;
+    for (int j = 0; j + 1 < L; ++j) {
+        const int w0 = w[j], w1 = w[j + 1], w2 = w[j + 2], d1 = d[j], d2 = d[j + 1];
+        const int I = w0 * d1 * d2, O = d1 * d2 * w2;
+        std::vector<double> M((size_t)O * I, 0.0);
+        for (int a = 0; a < w0; ++a)
+            for (int s = 0; s < d1; ++s)
+                for (int t = 0; t < d2; ++t)
+                    for (int p = 0; p < d1; ++p)
+                        for (int q = 0; q < d2; ++q)
+                            for (int u = 0; u < w2; ++u) {
+                                double acc = 0.0;
+                                for (int v = 0; v < w1; ++v) acc += Wat(j, a, v, p, s) * Wat(j + 1, v, u, q, t);
+                                M[((size_t)(p * d2 + q) * w2 + u) * I + (a * d1 + s) * d2 + t] = acc;
+                            }
+        hp.push_back(dense_to_csr(M, O, I));
+    }
+    for (int j = 0; j < L; ++j) {
+        const int wl = w[j], wr = w[j + 1], dj = d[j];
+        std::vector<double> ML((size_t)dj * wr * wl * dj), MR((size_t)dj * wl * wr * dj);
+        for (int a = 0; a < wl; ++a)
+            for (int b = 0; b < wr; ++b)
+                for (int p = 0; p < dj; ++p)
+                    for (int s = 0; s < dj; ++s) {
+                        const double v = Wat(j, a, b, p, s);
+                        ML[((size_t)p * wr + b) * (wl * dj) + a * dj + s] = v;   // (p v) <- (w s)
+                        MR[((size_t)p * wl + a) * (wr * dj) + b * dj + s] = v;   // (p w) <- (v s)
+                    }
+        hl.push_back(dense_to_csr(ML, dj * wr, wl * dj));
+        hr.push_back(dense_to_csr(MR, dj * wl, wr * dj));
+    }
+    for (int dd = 0; dd <= 8; ++dd) {
+        std::vector<double> Id((size_t)dd * dd, 0.0);
+        for (int i = 0; i < dd; ++i) Id[(size_t)i * dd + i] = 1.0;
+        hi.push_back(dense_to_csr(Id, dd, dd));
+    }
+    // one device block for all CSR arrays
+    size_t bytes = 0;
+    auto need = [&](const CsrHost& h) {
+        bytes += ((h.rowptr.size() * sizeof(int) + 255) & ~size_t(255));
+        bytes += ((h.col.size() * sizeof(int) + 255) & ~size_t(255)) + 256;
+        bytes += ((h.val.size() * sizeof(double) + 255) & ~size_t(255)) + 256;
+    };
+    for (auto& h : hp) need(h);
+    for (auto& h : hl) need(h);
+    for (auto& h : hr) need(h);
+    for (auto& h : hi) need(h);
+    m->block = dev_alloc(c, bytes);
+    std::vector<char> staging(bytes, 0);
+    size_t pos = 0;
+    auto place = [&](const CsrHost& h) {
+        CsrDev dv;
+        dv.I = h.I;
+        dv.O = h.O;
+        dv.nnz = (int)h.val.size();
+        char* base = static_cast<char*>(m->block);
+        dv.rowptr = reinterpret_cast<int*>(base + pos);
+        std::memcpy(staging.data() + pos, h.rowptr.data(), h.rowptr.size() * sizeof(int));
+        pos += ((h.rowptr.size() * sizeof(int) + 255) & ~size_t(255));
+        dv.col = reinterpret_cast<int*>(base + pos);
+        if (!h.col.empty()) std::memcpy(staging.data() + pos, h.col.data(), h.col.size() * sizeof(int));
+        pos += ((h.col.size() * sizeof(int) + 255) & ~size_t(255)) + 256;
+        dv.val = reinterpret_cast<double*>(base + pos);
+        if (!h.val.empty()) std::memcpy(staging.data() + pos, h.val.data(), h.val.size() * sizeof(double));
+        pos += ((h.val.size() * sizeof(double) + 255) & ~size_t(255)) + 256;
+        return dv;
+    };
+    for (auto& h : hp) m->pair.push_back(place(h));
+    for (auto& h : hl) m->left.push_back(place(h));
+    for (auto& h : hr) m->right.push_back(place(h));
+    for (auto& h : hi) m->ident.push_back(place(h));
+    HIP_CHECK(hipMemcpy(m->block, staging.data(), bytes, hipMemcpyHostToDevice));
+    return m.release();
+}
+
+void mpo_destroy(ite_mpo* m) {
+    if (!m) return;
+    dev_free(m->ctx, m->block);
+    delete m;
+}
+
+// ---------------------------------------------------------------------------
+// MPS handle
+// ---------------------------------------------------------------------------
+
+static std::vector<int> bond_caps(int L, const std::vector<int>& d, int chi_max) {
+    std::vector<int> cap(L + 1);
+    for (int b = 0; b <= L; ++b) {
+        double left = 1.0, right = 1.0;
+        for (int i = 0; i < b; ++i) left = std::min(left * d[i], 1e9);
+        for (int i = b; i < L; ++i) right = std::min(right * d[i], 1e9);
+        cap[b] = (int)std::min<double>(std::min(left, right), (double)chi_max);
+    }
+    return cap;
+}
+
+ite_mps* mps_new(ite_ctx* c, int L, const int* d, int chi_max) {
+    ITE_REQUIRE(L >= 2, "mps: L must be >= 2");
+    ITE_REQUIRE(chi_max >= 1, "mps: chi_max must be >= 1");
+    ITE_REQUIRE(d != nullptr, "mps: NULL d");
+    for (int i = 0; i < L; ++i) ITE_REQUIRE(d[i] >= 1 && d[i] <= 8, "mps: local dimension must be in 1..8");
+    std::unique_ptr<ite_mps> p(new ite_mps);
+    p->ctx = c;
+    p->L = L;
+    p->chi_max = chi_max;
+    p->d.assign(d, d + L);
+    p->Dcap = bond_caps(L, p->d, chi_max);
+    p->D.assign(L + 1, 1);
+    p->A.assign(L, nullptr);
+    try {
+        for (int i = 0; i < L; ++i)
+            p->A[i] = static_cast<double*>(dev_alloc(c, (size_t)p->Dcap[i] * d[i] * p->Dcap[i + 1] * sizeof(double)));
+    } catch (...) {
+        for (double* a : p->A) dev_free(c, a);
+        throw;
+    }
+    return p.release();
+}
+
+static void free_evolution(ite_mps* p) {
+    ite_ctx* c = p->ctx;
+    for (double* a : p->X) dev_free(c, a);
+    p->X.clear();
+    for (auto& e : p->env) {
+        dev_free(c, e.H);
+        dev_free(c, e.Hp);
+        dev_free(c, e.O);
+    }
+    p->env.clear();
+    p->env_w = 0;
+}
+
+void mps_destroy(ite_mps* p) {
+    if (!p) return;
+    ite_ctx* c = p->ctx;
+    free_evolution(p);
+    for (double* a : p->A) dev_free(c, a);
+    delete p;
+}
+
+static void ensure_evolution(ite_mps* p, const ite_mpo* H) {
+    ite_ctx* c = p->ctx;
+    int wmax = 1;
+    for (int v : H->w) wmax = std::max(wmax, v);
+    if (!p->env.empty() && p->env_w >= wmax) return;
+    free_evolution(p);
+    const int L = p->L;
+    p->X.assign(L, nullptr);
+    for (int i = 0; i < L; ++i)
+        p->X[i] = static_cast<double*>(dev_alloc(c, (size_t)p->Dcap[i] * p->d[i] * p->Dcap[i + 1] * sizeof(double)));
+    p->env.assign(L + 1, BondEnv{});
+    for (int b = 0; b <= L; ++b) {
+        const size_t D = p->Dcap[b];
+        p->env[b].H = static_cast<double*>(dev_alloc(c, D * wmax * D * sizeof(double)));
+        p->env[b].Hp = static_cast<double*>(dev_alloc(c, D * wmax * D * sizeof(double)));
+        p->env[b].O = static_cast<double*>(dev_alloc(c, D * D * sizeof(double)));
+    }
+    p->env_w = wmax;
+}
+
+// ---------------------------------------------------------------------------
+// Energy and overlap
+// ---------------------------------------------------------------------------
+
+// <x|H|x> / <x|x> at the block (0, 1) with R = right environment at bond 2,
+// x right-orthonormal from site 2 on.
+static double centre_energy(ite_ctx* c, const ite_mpo* H, const std::vector<double*>& A, const std::vector<int>& D,
+                            const double* R2) {
+    const int d1 = H->d[0], d2 = H->d[1];
+    const size_t n = (size_t)D[0] * d1 * d2 * D[2];
+    double* th = slot_t<double>(c, SL_TMPA, n);
+    double* y = slot_t<double>(c, SL_TMPB, n);
+    two_site(c, D[0], d1, D[1], d2, D[2], A[0], A[1], th);
+    double* L0 = slot_t<double>(c, SL_SMALL, 512) + 300;
+    fill(L0, 1.0, 1, c->stream);
+    HeffShape s{D[0], D[0], D[2], D[2], d1, d2, H->w[0], H->w[2]};
+    heff_apply(c, s, L0, H->pair[0], R2, th, 1.0, 0.0, nullptr, y, Prec::F64);
+    const double num = dot(c, th, y, n);
+    const double den = dot(c, th, th, n);
+    return num / den;
+}
+
+double measure_energy(ite_mps* psi, const ite_mpo* H) {
+    ite_ctx* c = psi->ctx;
+    ensure_evolution(psi, H);
+    const int L = psi->L;
+    auto& env = psi->env;
+    fill(env[L].H, 1.0, 1, c->stream);
+    for (int b = L - 1; b >= 2; --b)
+        env_right(c, psi->D[b + 1], psi->D[b + 1], psi->D[b], psi->D[b], psi->d[b], H->w[b], H->w[b + 1],
+                  env[b + 1].H, psi->A[b], &H->right[b], psi->A[b], env[b].H);
+    return centre_energy(c, H, psi->A, psi->D, env[2].H);
+}
+
+double overlap(ite_mps* a, ite_mps* b) {
+    ite_ctx* c = a->ctx;
+    const int L = a->L;
+    size_t mx = 1;
+    for (int i = 0; i <= L; ++i) mx = std::max(mx, (size_t)a->D[i] * b->D[i]);
+    double* E0 = slot_t<double>(c, SL_TMPA, mx);
+    double* E1 = slot_t<double>(c, SL_TMPB, mx);
+    fill(E0, 1.0, 1, c->stream);
+    for (int i = 0; i < L; ++i) {
+        env_left(c, a->D[i], b->D[i], a->D[i + 1], b->D[i + 1], a->d[i], 1, 1, E0, a->A[i], nullptr, b->A[i], E1);
+        std::swap(E0, E1);
+    }
+    double* h = pinned(c, 64);
+    d2h(c, h, E0, 1);
+    sync(c);
+    return h[0];
+}
+
+// ---------------------------------------------------------------------------
+// The implicit step
+// ---------------------------------------------------------------------------
+
+namespace {
+struct Timer {
+    ite_ctx* c;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> spans;
+    size_t next = 0;
+    explicit Timer(ite_ctx* cc) : c(cc) { c->events_used = 0; }
+    hipEvent_t ev() {
+        if (c->events_used == c->events.size()) {
+            hipEvent_t e;
+            HIP_CHECK(hipEventCreate(&e));
+            c->events.push_back(e);
+        }
+        return c->events[c->events_used++];
+    }
+    int open(int phase) {
+        hipEvent_t a = ev(), b = ev();
+        HIP_CHECK(hipEventRecord(a, c->stream));
+        spans.push_back({phase, {a, b}});
+        return (int)spans.size() - 1;
+    }
+    void close(int idx) { HIP_CHECK(hipEventRecord(spans[idx].second.second, c->stream)); }
+    void collect(double* ms) {
+        sync(c);
+        for (auto& s : spans) {
+            float t = 0.f;
+            HIP_CHECK(hipEventElapsedTime(&t, s.second.first, s.second.second));
+            ms[s.first] += t;
+        }
+    }
+};
+enum { PH_TOTAL = 0, PH_RHS, PH_SOLVE, PH_SPLIT, PH_ENV, PH_N };
+}  // namespace
+
+void imag_step(ite_mps* psi, const ite_mpo* H, double h, const ite_step_opts& o, ite_step_report* rep) {
+    ite_ctx* c = psi->ctx;
+    const int L = psi->L;
+    ITE_REQUIRE(std::isfinite(h) && h > 0.0, "imag_step: h must be finite and > 0");
+    if (H->L != L) ITE_FAIL(ITE_ESTATE, "imag_step: MPS and MPO lengths differ");
+    for (int i = 0; i < L; ++i)
+        if (H->d[i] != psi->d[i]) ITE_FAIL(ITE_ESTATE, "imag_step: local dimensions of MPS and MPO differ");
+    ITE_REQUIRE(o.scheme == ITE_SCHEME_TRAP || o.scheme == ITE_SCHEME_BE, "imag_step: unknown scheme");
+    ITE_REQUIRE(o.shift_mode == ITE_SHIFT_FIXED || o.shift_mode == ITE_SHIFT_TRACK, "imag_step: unknown shift mode");
+    ITE_REQUIRE(std::isfinite(o.shift), "imag_step: non-finite shift");
+    ITE_REQUIRE(o.chi_max >= 1, "imag_step: chi_max must be >= 1");
+    ITE_REQUIRE(o.cutoff >= 0.0 && o.cutoff < 1.0, "imag_step: cutoff must be in [0, 1)");
+    ITE_REQUIRE(o.tie_rel >= 0.0, "imag_step: tie_rel must be >= 0");
+    ITE_REQUIRE(o.krylov_dim >= 1 && o.krylov_dim <= 64, "imag_step: krylov_dim must be in 1..64");
+    ITE_REQUIRE(o.max_cycles >= 1, "imag_step: max_cycles must be >= 1");
+    ITE_REQUIRE(o.tol_loc >= 0.0, "imag_step: tol_loc must be >= 0");
+    ITE_REQUIRE(o.nsweeps >= 1, "imag_step: nsweeps must be >= 1");
+    ITE_REQUIRE(o.precision >= 0 && o.precision <= 2, "imag_step: unknown precision");
+    ensure_evolution(psi, H);
+
+    Timer tm(c);
+    const int t_all = tm.open(PH_TOTAL);
+    double s = o.shift;
+    if (o.shift_mode == ITE_SHIFT_TRACK) {
+        if (!psi->e_valid) {
+            psi->energy = measure_energy(psi, H);
+            psi->e_valid = true;
+        }
+        s = psi->energy;
+    }
+    const int chi = std::min(o.chi_max, psi->chi_max);
+    auto& env = psi->env;
+    auto& X = psi->X;
+    auto& XD = psi->XD;
+    const auto& P = psi->A;
+    const auto& PD = psi->D;
+    XD = PD;
+    for (int i = 0; i < L; ++i) d2d(c, X[i], P[i], (size_t)PD[i] * psi->d[i] * PD[i + 1]);
+    // boundary environments
+    fill(env[0].H, 1.0, 1, c->stream);
+    fill(env[0].Hp, 1.0, 1, c->stream);
+    fill(env[0].O, 1.0, 1, c->stream);
+    fill(env[L].H, 1.0, 1, c->stream);
+    fill(env[L].Hp, 1.0, 1, c->stream);
+    fill(env[L].O, 1.0, 1, c->stream);
+    env[0].hp_alias = env[0].o_ident = false;
+    env[L].hp_alias = env[L].o_ident = false;
+    for (int b = L - 1; b >= 2; --b) {
+        env_right(c, XD[b + 1], XD[b + 1], XD[b], XD[b], psi->d[b], H->w[b], H->w[b + 1], env[b + 1].H, X[b],
+                  &H->right[b], X[b], env[b].H);
+    }
+    for (int b = 2; b < L; ++b) {
+        env[b].hp_alias = true;
+        env[b].o_ident = true;
+    }
+
+    ite_step_report r{};
+    r.h = h;
+    r.shift = s;
+    r.dtau = o.scheme == ITE_SCHEME_TRAP ? 2.0 * h : h;
+    const double acoef = 1.0 - h * s;
+    int nres = 0;
+    double sum_res = 0.0;
+
+    auto block = [&](int i, int dir) {
+        const int d1 = psi->d[i], d2 = psi->d[i + 1];
+        const int Dl = XD[i], Dr = XD[i + 2], Dpl = PD[i], Dpr = PD[i + 2];
+        const size_t npsi = (size_t)Dpl * d1 * d2 * Dpr;
+        const size_t nx = (size_t)Dl * d1 * d2 * Dr;
+        double* tpsi = slot_t<double>(c, SL_TPSI, npsi);
+        double* bvec = slot_t<double>(c, SL_B, nx);
+        double* th = slot_t<double>(c, SL_TH, nx);
+        const int t_rhs = tm.open(PH_RHS);
+        two_site(c, Dpl, d1, PD[i + 1], d2, Dpr, P[i], P[i + 1], tpsi);
+        const double* Lo = env[i].o_ident ? nullptr : env[i].O;
+        const double* Ro = env[i + 2].o_ident ? nullptr : env[i + 2].O;
+        const double ovc = o.scheme == ITE_SCHEME_TRAP ? 1.0 + h * s : 1.0;
+        overlap_apply(c, Dl, Dpl, Dr, Dpr, d1, d2, Lo, Ro, tpsi, ovc, bvec);
+        if (o.scheme == ITE_SCHEME_TRAP) {
+            const double* Lh = env[i].hp_alias ? env[i].H : env[i].Hp;
+            const double* Rh = env[i + 2].hp_alias ? env[i + 2].H : env[i + 2].Hp;
+            HeffShape hs{Dl, Dpl, Dr, Dpr, d1, d2, H->w[i], H->w[i + 2]};
+            heff_apply(c, hs, Lh, H->pair[i], Rh, tpsi, -h, 1.0, bvec, bvec, Prec::F64);
+        }
+        two_site(c, Dl, d1, XD[i + 1], d2, Dr, X[i], X[i + 1], th);
+        tm.close(t_rhs);
+        const int t_solve = tm.open(PH_SOLVE);
+        LocalOp op;
+        op.s = HeffShape{Dl, Dl, Dr, Dr, d1, d2, H->w[i], H->w[i + 2]};
+        op.L = env[i].H;
+        op.R = env[i + 2].H;
+        op.ww = &H->pair[i];
+        op.alpha = acoef;
+        op.beta = h;
+        SolveStats ss = local_solve(c, op, bvec, th, o.krylov_dim, o.max_cycles, o.tol_loc, o.precision,
+                                    o.max_refine, o.tol_refine);
+        tm.close(t_solve);
+        r.matvecs_fp64 += ss.matvecs64;
+        r.matvecs_lo += ss.matvecs_lo;
+        r.flags |= ss.flags;
+        r.max_res_rel = std::max(r.max_res_rel, ss.res_rel);
+        sum_res += ss.res_rel;
+        ++nres;
+        const int t_split = tm.open(PH_SPLIT);
+        SplitResult sp = split(c, dir, Dl, d1, d2, Dr, th, chi, o.cutoff, o.tie_rel, X[i], X[i + 1], nullptr);
+        tm.close(t_split);
+        XD[i + 1] = sp.k;
+        r.max_disc = std::max(r.max_disc, sp.disc);
+        r.sum_disc += sp.disc;
+    };
+
+    for (int sw = 0; sw < o.nsweeps; ++sw) {
+        for (int i = 0; i + 1 < L; ++i) {
+            block(i, 0);
+            if (i + 2 < L) {
+                const int t_env = tm.open(PH_ENV);
+                const int b = i + 1;
+                // <x|H|x>, <x|H|psi>, <x|psi> at bond i+1 from bond i
+                env_left(c, XD[i], XD[i], XD[b], XD[b], psi->d[i], H->w[i], H->w[b], env[i].H, X[i], &H->left[i],
+                         X[i], env[b].H);
+                const double* Ehp = env[i].hp_alias ? env[i].H : env[i].Hp;
+                env_left(c, XD[i], PD[i], XD[b], PD[b], psi->d[i], H->w[i], H->w[b], Ehp, X[i], &H->left[i], P[i],
+                         env[b].Hp);
+                env_left(c, XD[i], PD[i], XD[b], PD[b], psi->d[i], 1, 1, env[i].O, X[i], nullptr, P[i], env[b].O);
+                env[b].hp_alias = false;
+                env[b].o_ident = false;
+                tm.close(t_env);
+            }
+        }
+        for (int i = L - 2; i >= 0; --i) {
+            block(i, 1);
+            if (i > 0) {
+                const int t_env = tm.open(PH_ENV);
+                const int b = i + 1, a = i + 2;
+                env_right(c, XD[a], XD[a], XD[b], XD[b], psi->d[b], H->w[b], H->w[a], env[a].H, X[b],
+                          &H->right[b], X[b], env[b].H);
+                const double* Ehp = env[a].hp_alias ? env[a].H : env[a].Hp;
+                env_right(c, XD[a], PD[a], XD[b], PD[b], psi->d[b], H->w[b], H->w[a], Ehp, X[b], &H->right[b],
+                          P[b], env[b].Hp);
+                if (env[a].o_ident) {
+                    // <x|psi> with identity to the right: plain overlap of the site tensors
+                    double* Eid = slot_t<double>(c, SL_TMPA, (size_t)XD[a] * XD[a]);
+                    eye(Eid, XD[a], c->stream);
+                    env_right_overlap_pub(c, H->ident[psi->d[b]], XD[a], PD[a], XD[b], PD[b], psi->d[b], Eid, X[b], P[b],
+                                      env[b].O);
+                } else {
+                    env_right_overlap_pub(c, H->ident[psi->d[b]], XD[a], PD[a], XD[b], PD[b], psi->d[b], env[a].O, X[b],
+                                      P[b], env[b].O);
+                }
+                env[b].hp_alias = false;
+                env[b].o_ident = false;
+                tm.close(t_env);
+            }
+        }
+    }
+    // normalise the centre (site 1) and measure
+    const size_t n0 = (size_t)XD[0] * psi->d[0] * XD[1];
+    const double nrm2 = dot(c, X[0], X[0], n0);
+    const double nrm = std::sqrt(std::max(nrm2, 0.0));
+    bool finite = std::isfinite(nrm) && nrm > 0.0;
+    double E = 0.0;
+    if (finite) {
+        scale(X[0], 1.0 / nrm, n0, c->stream);
+        E = centre_energy(c, H, X, XD, env[2].H);
+        finite = std::isfinite(E);
+    }
+    tm.close(t_all);
+    double ms[PH_N] = {0, 0, 0, 0, 0};
+    tm.collect(ms);
+    if (!finite) ITE_FAIL(ITE_ENONFINITE, "imag_step: non-finite state; psi left unchanged");
+    // psi <- x
+    std::swap(psi->A, psi->X);
+    std::swap(psi->D, psi->XD);
+    psi->tau += r.dtau;
+    psi->energy = E;
+    psi->e_valid = true;
+    r.tau = psi->tau;
+    r.energy = E;
+    r.norm_before = nrm;
+    r.max_chi = *std::max_element(psi->D.begin(), psi->D.end());
+    r.mean_res_rel = nres ? sum_res / nres : 0.0;
+    r.ms_total = ms[PH_TOTAL];
+    r.ms_rhs = ms[PH_RHS];
+    r.ms_solve = ms[PH_SOLVE];
+    r.ms_split = ms[PH_SPLIT];
+    r.ms_env = ms[PH_ENV];
+    if (rep) *rep = r;
+}
+
+}  // namespace ite

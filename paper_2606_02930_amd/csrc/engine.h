@@ -1,0 +1,159 @@
+// Host-side objects of the library: context, MPO and MPS handles, and the
+// operations of one implicit step (effective-Hamiltonian product,
+// environment updates, GMRES local solve, Jacobi split, sweep).
+#pragma once
+
+#include "internal.h"
+
+#include <array>
+#include <string>
+#include <vector>
+
+// Workspace slots of a context (grow-only device buffers).
+enum SlotId {
+    SL_X1, SL_X3,                  // contraction intermediates
+    SL_TPSI, SL_B, SL_TH,          // theta_psi, right-hand side, solution
+    SL_V, SL_W,                    // Krylov basis, work vector
+    SL_PART, SL_SMALL,             // reduction partials, small device scalars
+    SL_Z, SL_GRAM, SL_ROT, SL_OFF, SL_NORM, SL_PERM,   // Jacobi split
+    SL_TMPA, SL_TMPB,              // scratch environments (overlap, energy)
+    SL_LO_L, SL_LO_R, SL_LO_T, SL_LO_X,   // low-precision shadows (mixed precision)
+    SL_R64, SL_D64,                // refinement residual and correction
+    SL_NSLOTS
+};
+
+struct ite_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    ite_allocator alloc{};
+    bool has_alloc = false;
+    std::string err;
+    void* slot_ptr[SL_NSLOTS] = {};
+    size_t slot_bytes[SL_NSLOTS] = {};
+    double* pinned = nullptr;      // host staging (hipHostMalloc)
+    size_t pinned_bytes = 0;
+    std::vector<hipEvent_t> events;
+    size_t events_used = 0;
+};
+
+// Sparse small matrix in CSR form on the device.
+struct CsrDev {
+    int I = 0, O = 0, nnz = 0;
+    int* rowptr = nullptr;
+    int* col = nullptr;
+    double* val = nullptr;
+};
+
+struct ite_mpo {
+    ite_ctx* ctx = nullptr;
+    int L = 0;
+    std::vector<int> d, w;
+    std::vector<std::vector<double>> Wh;   // host copies [wl][wr][out][in]
+    std::vector<CsrDev> pair;   // two-site product W_j W_(j+1): (w_j, s, t) -> (p, q, w_(j+2))
+    std::vector<CsrDev> left;   // (w_j, s) -> (p, w_(j+1))
+    std::vector<CsrDev> right;  // (w_(j+1), s) -> (p, w_j)
+    std::vector<CsrDev> ident;  // identity of size d (index by d)
+    void* block = nullptr;      // one device allocation holding every CSR array
+};
+
+// Environments of one bond.
+struct BondEnv {
+    double* H = nullptr;    // <x|H|x>   [Dx][w][Dx]
+    double* Hp = nullptr;   // <x|H|psi> [Dx][w][Dpsi]
+    double* O = nullptr;    // <x|psi>   [Dx][Dpsi]
+    bool hp_alias = false;  // Hp equals H (x = psi on this side)
+    bool o_ident = false;   // O is the identity (x = psi on this side)
+};
+
+struct ite_mps {
+    ite_ctx* ctx = nullptr;
+    int L = 0;
+    int chi_max = 1;
+    std::vector<int> d;
+    std::vector<int> D;      // current bond dimensions (L + 1)
+    std::vector<int> Dcap;   // capacity of each bond
+    std::vector<double*> A;  // site tensors
+    double tau = 0.0;
+    bool e_valid = false;
+    double energy = 0.0;
+    // evolution storage (allocated on the first step)
+    std::vector<double*> X;      // working copy x
+    std::vector<int> XD;         // bond dimensions of x
+    std::vector<BondEnv> env;
+    int env_w = 0;               // MPO bond dimension the environments were sized for
+};
+
+namespace ite {
+
+void* dev_alloc(ite_ctx* c, size_t bytes);
+void dev_free(ite_ctx* c, void* p);
+void* slot(ite_ctx* c, SlotId s, size_t bytes);
+template <typename T> inline T* slot_t(ite_ctx* c, SlotId s, size_t count) {
+    return static_cast<T*>(slot(c, s, count * sizeof(T)));
+}
+double* pinned(ite_ctx* c, size_t doubles);
+void sync(ite_ctx* c);
+
+// Contraction primitives (device pointers; MPO matrices from ite_mpo).
+struct HeffShape {
+    int Dxl, Dyl, Dxr, Dyr, d1, d2, w0, w2;
+};
+// y = beta * H_eff theta + alpha * Cadd (Cadd may be null; y may alias Cadd)
+void heff_apply(ite_ctx* c, const HeffShape& s, const double* L, const CsrDev& ww, const double* R,
+                const double* theta, double beta, double alpha, const double* Cadd, double* y,
+                Prec prec);
+// y = alpha * Lo theta Ro^T with Lo [Dxl][Dyl], Ro [Dxr][Dyr] (null = identity)
+void overlap_apply(ite_ctx* c, int Dxl, int Dyl, int Dxr, int Dyr, int d1, int d2, const double* Lo,
+                   const double* Ro, const double* theta, double alpha, double* y);
+// Environment updates; W null = overlap environment.
+void env_left(ite_ctx* c, int Dxa, int Dya, int Dxb, int Dyb, int d, int wl, int wr, const double* E,
+              const double* X, const CsrDev* W, const double* Y, double* Eout);
+void env_right(ite_ctx* c, int Dxa, int Dya, int Dxb, int Dyb, int d, int wl, int wr, const double* E,
+               const double* X, const CsrDev* W, const double* Y, double* Eout);
+// Overlap environment from the right: E'[b', b] = sum E[c', c] X[b', s, c'] Y[b, s, c]
+// (ident: identity CSR of size d, used for the index permutation).
+void env_right_overlap_pub(ite_ctx* c, const CsrDev& ident, int Dxa, int Dya, int Dxb, int Dyb, int d,
+                           const double* E, const double* X, const double* Y, double* Eout);
+// C = A1 A2 for site tensors A1 [Dl][d1][Dm], A2 [Dm][d2][Dr]
+void two_site(ite_ctx* c, int Dl, int d1, int Dm, int d2, int Dr, const double* A1, const double* A2,
+              double* theta);
+
+struct SplitResult {
+    int k = 0;
+    double disc = 0.0;
+    int sweeps = 0;
+};
+SplitResult split(ite_ctx* c, int dir, int Dl, int d1, int d2, int Dr, const double* theta, int chi_max,
+                  double cutoff, double tie_rel, double* A1, double* A2, std::vector<double>* sigma);
+// Truncation rule on sigma sorted descending (host).
+int truncation_rank(const std::vector<double>& s, double cutoff, int chi_max, double tie_rel);
+
+struct SolveStats {
+    int matvecs64 = 0, matvecs_lo = 0;
+    double res_rel = 0.0;
+    int flags = 0;
+};
+// Linear operator of a local solve: y = alpha v + beta H_eff v.
+struct LocalOp {
+    HeffShape s;
+    const double* L;
+    const double* R;
+    const CsrDev* ww;
+    double alpha, beta;
+    size_t n() const { return (size_t)s.Dxl * s.d1 * s.d2 * s.Dxr; }
+};
+SolveStats local_solve(ite_ctx* c, const LocalOp& op, const double* b, double* x, int m, int max_cycles,
+                       double tol, int precision, int max_refine, double tol_refine);
+
+double dot(ite_ctx* c, const double* x, const double* y, size_t n);
+
+// Handles
+ite_mpo* mpo_load(ite_ctx* c, int L, const int* d, const int* w, const double* const* W);
+void mpo_destroy(ite_mpo* m);
+ite_mps* mps_new(ite_ctx* c, int L, const int* d, int chi_max);
+void mps_destroy(ite_mps* p);
+void imag_step(ite_mps* psi, const ite_mpo* H, double h, const ite_step_opts& o, ite_step_report* rep);
+double measure_energy(ite_mps* psi, const ite_mpo* H);
+double overlap(ite_mps* a, ite_mps* b);
+
+}  // namespace ite

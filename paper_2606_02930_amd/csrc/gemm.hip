@@ -1,0 +1,379 @@
+// Tiled MFMA GEMM for gfx950 (CDNA4): the contraction core of the
+// effective-Hamiltonian product and of the environment updates.
+//
+// D[b] = alpha op(A[b]) op(B[b]) + beta C[b], row-major.
+//
+// Tile: 128 x 128 output per workgroup of 256 threads (four 64-wide
+// wavefronts in a 2 x 2 arrangement, each owning 64 x 64 = 4 x 4 MFMA tiles of
+// 16 x 16).  K advances in slices of 16 staged through LDS with double
+// buffering: the next slice is fetched into registers while the current one
+// feeds the matrix cores.  Both operands are stored in LDS "K-contiguous"
+// (row = output row or column, 16 K values per row, padded) so that each lane
+// fetches its four K values for the four MFMA sub-steps of a slice with two
+// 16-byte LDS reads.  Within a slice, lane group g = lane / 16 supplies K
+// index 4 g + step in sub-step `step`; A and B use the same mapping, so the
+// sum over K is unchanged.
+//
+// Workgroup -> tile mapping is XCD-aware: the hardware deals workgroups to the
+// 8 XCDs round-robin, so consecutive workgroup ids are remapped to give each
+// XCD a contiguous band of output tiles that share A row panels in that XCD's
+// L2.
+#include "internal.h"
+
+namespace ite {
+namespace {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 128;
+constexpr int BN = 128;
+constexpr int BK = 16;
+constexpr int NTHREADS = 256;
+
+template <typename T> struct MfmaOp;
+template <> struct MfmaOp<double> {
+    typedef d4_t acc_t;
+    static constexpr int LDK = BK + 2;   // 144-byte rows: 16-byte aligned, few bank conflicts
+    __device__ static acc_t mma(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    // tile row of accumulator element r in lane group g = lane / 16
+    __device__ static int row(int g, int r) { return 4 * r + g; }
+};
+template <> struct MfmaOp<float> {
+    typedef f4_t acc_t;
+    static constexpr int LDK = BK + 4;   // 80-byte rows
+    __device__ static acc_t mma(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static int row(int g, int r) { return 4 * g + r; }
+};
+
+struct Params {
+    int M, N, K;
+    double alpha, beta;
+    const void* A; long lda, sA;
+    const void* B; long ldb, sB;
+    const double* C; long ldc, sC;
+    double* D; long ldd, sD;
+    int mt, nt;
+};
+
+// Bijection from the hardware workgroup id to an output tile such that XCD x
+// (workgroups with id % 8 == x) receives a contiguous range of tiles.
+__device__ inline int xcd_band_tile(int bid, int T) {
+    const int q = T >> 3, r = T & 7;
+    const int xcd = bid & 7, idx = bid >> 3;
+    const int base = xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q;
+    return base + idx;
+}
+
+// Stage one K slice of an operand into registers.  KC: the source is stored
+// with K contiguous (rows of the 128-wide tile side are strided by ld);
+// otherwise K is the slow index (rows are K, the tile side is contiguous).
+template <typename T, bool KC>
+__device__ inline void fetch_slice(const T* __restrict__ src, long ld, int side0, int sideN, int k0,
+                                   int K, int t, T (&r)[8]) {
+    if (KC) {
+        const int kk = t & 15;
+        const int k = k0 + kk;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int row = side0 + (t >> 4) + 16 * e;
+            r[e] = (row < sideN && k < K) ? src[(long)row * ld + k] : T(0);
+        }
+    } else {
+        const int col = side0 + (t & 127);
+        const int kh = (t >> 7) * 8;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int k = k0 + kh + e;
+            r[e] = (col < sideN && k < K) ? src[(long)k * ld + col] : T(0);
+        }
+    }
+}
+
+template <typename T, bool KC>
+__device__ inline void store_slice(T* __restrict__ lds, int t, const T (&r)[8]) {
+    constexpr int LDK = MfmaOp<T>::LDK;
+    if (KC) {
+        const int kk = t & 15;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) lds[((t >> 4) + 16 * e) * LDK + kk] = r[e];
+    } else {
+        const int row = t & 127;
+        const int kh = (t >> 7) * 8;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) lds[row * LDK + kh + e] = r[e];
+    }
+}
+
+template <typename T, bool TA, bool TB>
+__global__ __launch_bounds__(NTHREADS) void gemm_kernel(Params p) {
+    typedef typename MfmaOp<T>::acc_t acc_t;
+    constexpr int LDK = MfmaOp<T>::LDK;
+    __shared__ T As[2][BM * LDK];
+    __shared__ T Bs[2][BN * LDK];
+
+    const int T_tiles = p.mt * p.nt;
+    const int tile = xcd_band_tile(blockIdx.x, T_tiles);
+    const int m0 = (tile / p.nt) * BM;
+    const int n0 = (tile % p.nt) * BN;
+    const long bz = blockIdx.z;
+    const T* __restrict__ A = static_cast<const T*>(p.A) + bz * p.sA;
+    const T* __restrict__ B = static_cast<const T*>(p.B) + bz * p.sB;
+
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int wave = t >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int l16 = lane & 15, kg = lane >> 4;
+
+    acc_t acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+
+    // A: K-contiguous unless transposed.  B: K-contiguous only when transposed.
+    T ra[8], rb[8];
+    const int nk = (p.K + BK - 1) / BK;
+    fetch_slice<T, !TA>(A, p.lda, m0, p.M, 0, p.K, t, ra);
+    fetch_slice<T, TB>(B, p.ldb, n0, p.N, 0, p.K, t, rb);
+    store_slice<T, !TA>(As[0], t, ra);
+    store_slice<T, TB>(Bs[0], t, rb);
+    __syncthreads();
+
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        const bool more = kt + 1 < nk;
+        if (more) {
+            fetch_slice<T, !TA>(A, p.lda, m0, p.M, (kt + 1) * BK, p.K, t, ra);
+            fetch_slice<T, TB>(B, p.ldb, n0, p.N, (kt + 1) * BK, p.K, t, rb);
+        }
+        T a[4][4], b[4][4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const T* src = &As[cur][(wm * 64 + i * 16 + l16) * LDK + 4 * kg];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) a[i][s] = src[s];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const T* src = &Bs[cur][(wn * 64 + j * 16 + l16) * LDK + 4 * kg];
+#pragma unroll
+            for (int s = 0; s < 4; ++s) b[j][s] = src[s];
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = MfmaOp<T>::mma(a[i][s], b[j][s], acc[i][j]);
+        if (more) {
+            store_slice<T, !TA>(As[cur ^ 1], t, ra);
+            store_slice<T, TB>(Bs[cur ^ 1], t, rb);
+        }
+        __syncthreads();
+    }
+
+    // Epilogue.  Accumulator element r of lane l holds column l % 16 of its
+    // 16 x 16 tile and row 4 r + l / 16 (FP64 MFMA) or 4 (l / 16) + r (FP32).
+    const double* __restrict__ C = p.C ? p.C + bz * p.sC : nullptr;
+    double* __restrict__ D = p.D + bz * p.sD;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int col = n0 + wn * 64 + j * 16 + l16;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wm * 64 + i * 16 + MfmaOp<T>::row(kg, r);
+                if (row < p.M && col < p.N) {
+                    double v = p.alpha * (double)acc[i][j][r];
+                    if (C) v += p.beta * C[(long)row * p.ldc + col];
+                    D[(long)row * p.ldd + col] = v;
+                }
+            }
+        }
+}
+
+template <typename T>
+void launch(const Gemm& g, hipStream_t s) {
+    if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
+    Params p;
+    p.M = g.M; p.N = g.N; p.K = g.K;
+    p.alpha = g.alpha; p.beta = g.beta;
+    p.A = g.A; p.lda = g.lda; p.sA = g.sA;
+    p.B = g.B; p.ldb = g.ldb; p.sB = g.sB;
+    p.C = g.C; p.ldc = g.ldc; p.sC = g.sC;
+    p.D = g.D; p.ldd = g.ldd; p.sD = g.sD;
+    p.mt = (g.M + BM - 1) / BM;
+    p.nt = (g.N + BN - 1) / BN;
+    dim3 grid(p.mt * p.nt, 1, g.batch);
+    if (!g.tA && !g.tB) hipLaunchKernelGGL((gemm_kernel<T, false, false>), grid, dim3(NTHREADS), 0, s, p);
+    else if (!g.tA && g.tB) hipLaunchKernelGGL((gemm_kernel<T, false, true>), grid, dim3(NTHREADS), 0, s, p);
+    else if (g.tA && !g.tB) hipLaunchKernelGGL((gemm_kernel<T, true, false>), grid, dim3(NTHREADS), 0, s, p);
+    else hipLaunchKernelGGL((gemm_kernel<T, true, true>), grid, dim3(NTHREADS), 0, s, p);
+    HIP_CHECK(hipGetLastError());
+}
+
+// One v_mfma_f64_16x16x4f64 with A[i][k] = 1 + i + 16 k (i < 16, k < 4)
+// supplied by lane i + 16 k and B[k][j] = 1 / (1 + j + 16 k) by lane j + 16 k;
+// every lane writes its four accumulator values.
+__global__ void mfma_probe_kernel(double* out) {
+    const int l = threadIdx.x;
+    const double a = 1.0 + (l & 15) + 16.0 * (l >> 4);
+    const double b = 1.0 / (1.0 + (l & 15) + 16.0 * (l >> 4));
+    d4_t acc = {0, 0, 0, 0};
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    for (int r = 0; r < 4; ++r) out[l * 4 + r] = acc[r];
+}
+
+// ---------------------------------------------------------------------------
+// BF16 operands, FP32 accumulation: v_mfma_f32_16x16x32_bf16 (gfx950).  Same
+// 128 x 128 tile and wave arrangement; a K slice of 32 is one MFMA per 16 x 16
+// tile, lane group g = lane / 16 supplying K indices 8 g .. 8 g + 7.
+// ---------------------------------------------------------------------------
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+constexpr int BK16 = 32;
+constexpr int LDK16 = BK16 + 8;   // 80-byte rows, 16-byte aligned
+
+template <bool KC>
+__device__ inline void fetch_slice16(const uint16_t* __restrict__ src, long ld, int side0, int sideN, int k0,
+                                     int K, int t, uint16_t (&r)[16]) {
+    if (KC) {
+        const int kk = t & 31;
+        const int k = k0 + kk;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int row = side0 + (t >> 5) + 8 * e;
+            r[e] = (row < sideN && k < K) ? src[(long)row * ld + k] : (uint16_t)0;
+        }
+    } else {
+        const int col = side0 + (t & 127);
+        const int kh = (t >> 7) * 16;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int k = k0 + kh + e;
+            r[e] = (col < sideN && k < K) ? src[(long)k * ld + col] : (uint16_t)0;
+        }
+    }
+}
+
+template <bool KC>
+__device__ inline void store_slice16(uint16_t* __restrict__ lds, int t, const uint16_t (&r)[16]) {
+    if (KC) {
+        const int kk = t & 31;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) lds[((t >> 5) + 8 * e) * LDK16 + kk] = r[e];
+    } else {
+        const int row = t & 127;
+        const int kh = (t >> 7) * 16;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) lds[row * LDK16 + kh + e] = r[e];
+    }
+}
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(NTHREADS) void gemm_bf16_kernel(Params p) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[2][BM * LDK16];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BN * LDK16];
+    const int T_tiles = p.mt * p.nt;
+    const int tile = xcd_band_tile(blockIdx.x, T_tiles);
+    const int m0 = (tile / p.nt) * BM;
+    const int n0 = (tile % p.nt) * BN;
+    const long bz = blockIdx.z;
+    const uint16_t* __restrict__ A = static_cast<const uint16_t*>(p.A) + bz * p.sA;
+    const uint16_t* __restrict__ B = static_cast<const uint16_t*>(p.B) + bz * p.sB;
+    const int t = threadIdx.x;
+    const int lane = t & 63;
+    const int wave = t >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int l16 = lane & 15, kg = lane >> 4;
+    f4_t acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f4_t{0, 0, 0, 0};
+    uint16_t ra[16], rb[16];
+    const int nk = (p.K + BK16 - 1) / BK16;
+    fetch_slice16<!TA>(A, p.lda, m0, p.M, 0, p.K, t, ra);
+    fetch_slice16<TB>(B, p.ldb, n0, p.N, 0, p.K, t, rb);
+    store_slice16<!TA>(As[0], t, ra);
+    store_slice16<TB>(Bs[0], t, rb);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        const bool more = kt + 1 < nk;
+        if (more) {
+            fetch_slice16<!TA>(A, p.lda, m0, p.M, (kt + 1) * BK16, p.K, t, ra);
+            fetch_slice16<TB>(B, p.ldb, n0, p.N, (kt + 1) * BK16, p.K, t, rb);
+        }
+        bf8_t a[4], b[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            a[i] = *reinterpret_cast<const bf8_t*>(&As[cur][(wm * 64 + i * 16 + l16) * LDK16 + 8 * kg]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            b[j] = *reinterpret_cast<const bf8_t*>(&Bs[cur][(wn * 64 + j * 16 + l16) * LDK16 + 8 * kg]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        if (more) {
+            store_slice16<!TA>(As[cur ^ 1], t, ra);
+            store_slice16<TB>(Bs[cur ^ 1], t, rb);
+        }
+        __syncthreads();
+    }
+    const double* __restrict__ C = p.C ? p.C + bz * p.sC : nullptr;
+    double* __restrict__ D = p.D + bz * p.sD;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int col = n0 + wn * 64 + j * 16 + l16;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = m0 + wm * 64 + i * 16 + 4 * kg + r;
+                if (row < p.M && col < p.N) {
+                    double v = p.alpha * (double)acc[i][j][r];
+                    if (C) v += p.beta * C[(long)row * p.ldc + col];
+                    D[(long)row * p.ldd + col] = v;
+                }
+            }
+        }
+}
+
+}  // namespace
+
+void gemm_f64(const Gemm& g, hipStream_t s) { launch<double>(g, s); }
+void gemm_f32(const Gemm& g, hipStream_t s) { launch<float>(g, s); }
+
+void gemm_bf16(const Gemm& g, hipStream_t s) {
+    if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
+    Params p;
+    p.M = g.M; p.N = g.N; p.K = g.K;
+    p.alpha = g.alpha; p.beta = g.beta;
+    p.A = g.A; p.lda = g.lda; p.sA = g.sA;
+    p.B = g.B; p.ldb = g.ldb; p.sB = g.sB;
+    p.C = g.C; p.ldc = g.ldc; p.sC = g.sC;
+    p.D = g.D; p.ldd = g.ldd; p.sD = g.sD;
+    p.mt = (g.M + BM - 1) / BM;
+    p.nt = (g.N + BN - 1) / BN;
+    dim3 grid(p.mt * p.nt, 1, g.batch);
+    if (!g.tA && !g.tB) hipLaunchKernelGGL((gemm_bf16_kernel<false, false>), grid, dim3(NTHREADS), 0, s, p);
+    else if (!g.tA && g.tB) hipLaunchKernelGGL((gemm_bf16_kernel<false, true>), grid, dim3(NTHREADS), 0, s, p);
+    else if (g.tA && !g.tB) hipLaunchKernelGGL((gemm_bf16_kernel<true, false>), grid, dim3(NTHREADS), 0, s, p);
+    else hipLaunchKernelGGL((gemm_bf16_kernel<true, true>), grid, dim3(NTHREADS), 0, s, p);
+    HIP_CHECK(hipGetLastError());
+}
+
+void mfma_probe_f64(double* out, hipStream_t s) {
+    hipLaunchKernelGGL(mfma_probe_kernel, dim3(1), dim3(64), 0, s, out);
+    HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace ite

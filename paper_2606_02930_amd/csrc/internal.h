@@ -1,0 +1,134 @@
+// Internal declarations of the implicit imaginary-time evolution library:
+// error handling, the context (allocator, stream, workspaces) and the kernel
+// launchers shared by the sweep engine.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "ite.h"
+
+namespace ite {
+
+struct Error : std::runtime_error {
+    int code;
+    Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define ITE_FAIL(code, msg) throw ::ite::Error((code), (msg))
+#define ITE_REQUIRE(cond, msg) \
+    do { if (!(cond)) throw ::ite::Error(ITE_EINVAL, (msg)); } while (0)
+#define HIP_CHECK(expr)                                                                 \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            throw ::ite::Error(ITE_EDEVICE, std::string(#expr) + " failed: " +         \
+                                                hipGetErrorString(e_));                 \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (all asynchronous on `stream`)
+// ---------------------------------------------------------------------------
+
+// Operand precision of a contraction.
+enum class Prec { F64 = 0, F32 = 1, BF16 = 2 };
+
+// D[b] = alpha op(A[b]) op(B[b]) + beta C[b], row-major, b < batch.
+// op(A) is M x K (A stored K x M when tA), op(B) is K x N (B stored N x K when
+// tB).  C may be null (then beta is ignored).  D may alias C (same layout).
+struct Gemm {
+    int M = 0, N = 0, K = 0;
+    bool tA = false, tB = false;
+    double alpha = 1.0, beta = 0.0;
+    const void* A = nullptr; long lda = 0, sA = 0;
+    const void* B = nullptr; long ldb = 0, sB = 0;
+    const double* C = nullptr; long ldc = 0, sC = 0;
+    double* D = nullptr; long ldd = 0, sD = 0;
+    int batch = 1;
+};
+// FP64 operands, FP64 MFMA.
+void gemm_f64(const Gemm& g, hipStream_t s);
+// FP32 operands (A, B are float*), FP32 MFMA, FP32 accumulation, FP64 output.
+void gemm_f32(const Gemm& g, hipStream_t s);
+// BF16 operands (A, B are uint16 bf16 bit patterns), BF16 MFMA, FP32
+// accumulation, FP64 output.
+void gemm_bf16(const Gemm& g, hipStream_t s);
+
+// Small-matrix stage: out[g][o][c] = sum_i M[o][i] in[g][i][c] for a sparse
+// M in CSR form.  Element addresses are two-level so that index permutations
+// come for free:
+//   in  + g*in_gs  + (i / in_div)*in_s1   + (i % in_div)*in_s2   + c*in_cs
+//   out + g*out_gs + (o / out_div)*out_s1 + (o % out_div)*out_s2 + c*out_cs
+struct Stage {
+    int G = 0, I = 0, O = 0, C = 0;
+    const double* in = nullptr;
+    long in_gs = 0, in_s1 = 0, in_s2 = 0, in_cs = 1; int in_div = 1;
+    double* out = nullptr;
+    long out_gs = 0, out_s1 = 0, out_s2 = 0, out_cs = 1; int out_div = 1;
+    const int* rowptr = nullptr; const int* col = nullptr; const double* val = nullptr;
+};
+void stage_f64(const Stage& st, hipStream_t s);
+
+// Rounding copies: FP64 -> FP32 and FP64 -> BF16 (round to nearest even).
+void convert_f32(const double* x, float* y, size_t n, hipStream_t s);
+void convert_bf16(const double* x, uint16_t* y, size_t n, hipStream_t s);
+
+// Vector kernels.  Reductions are two-pass with a fixed grid so results do not
+// depend on timing (bitwise reproducible for a given n).
+int  reduce_blocks(size_t n);
+// partial[b] = sum over block b of x.y
+void dot_partials(const double* x, const double* y, size_t n, double* partial, hipStream_t s);
+// partial[j*nb + b] = block b of V_j . w for j < k (V_j = V + j*ldv)
+void mdot_partials(const double* V, long ldv, int k, const double* w, size_t n, double* partial,
+                   hipStream_t s);
+// out[j] (+)= sum_b partial[j*nb + b]; mode 0: store, 1: add, 2: store sqrt
+void finish_partials(const double* partial, int k, int nb, double* out, int mode, hipStream_t s);
+// w -= sum_j coef[j] V_j   (coef on device)
+void gemv_sub(const double* V, long ldv, int k, const double* coef, double* w, size_t n,
+              hipStream_t s);
+// x += sum_j coef[j] V_j   (coef on device)
+void gemv_add(const double* V, long ldv, int k, const double* coef, double* x, size_t n,
+              hipStream_t s);
+// out = a x + b y (host scalars; y may be null when b == 0)
+void axpby(size_t n, double a, const double* x, double b, const double* y, double* out,
+           hipStream_t s);
+// out = x / *den (device scalar); writes zeros when *den <= thresh
+void scale_inv(const double* x, const double* den, double* out, size_t n, hipStream_t s);
+// x *= a
+void scale(double* x, double a, size_t n, hipStream_t s);
+// y[i] = x[i*inc] for i < n (strided gather)
+void fill(double* x, double v, size_t n, hipStream_t s);
+// identity matrix D x D (row-major) into x
+void eye(double* x, int D, hipStream_t s);
+// sets *flag = 1 if any entry of x is not finite
+void nonfinite_any(const double* x, size_t n, int* flag, hipStream_t s);
+// out[j][i] = in[i][j]  (rows x cols -> cols x rows)
+void transpose(const double* in, int rows, int cols, double* out, hipStream_t s);
+
+// One-sided Jacobi on the rows of Z[p][ld] (the first q columns are the
+// matrix whose rows are orthogonalised; all ld columns are rotated).
+struct JacobiWork;
+struct JacobiResult { int sweeps = 0; double last_off = 0.0; };
+JacobiResult jacobi_rows(double* Z, int p, int q, int ld, double tol, int max_sweeps,
+                         double* gram_ws, double* rot_ws, double* off_ws, double* host_off,
+                         hipStream_t s);
+// Build the Jacobi work matrix [theta | I_m] (dir 0) or [theta^T | I_n]
+// (dir 1) for theta m x n; leading dimension m + n.
+void jacobi_input(const double* theta, int m, int n, int dir, double* Z, hipStream_t s);
+// norms[i] = || Z[i][0:q] ||
+void row_norms(const double* Z, int p, int q, int ld, double* norms, hipStream_t s);
+// Gather kept rows: for t < k, r = perm[t]:
+//   rowdst[t][0:nr] = Z[r][roff : roff + nr]
+//   coldst[i][t]    = Z[r][coff + i] for i < nc   (a transposed write, ldc = k)
+void gather_split(const double* Z, int ld, const int* perm, int k, int roff, int nr,
+                  double* rowdst, int coff, int nc, double* coldst, hipStream_t s);
+
+// MFMA lane-layout probe (tests only).
+void mfma_probe_f64(double* out, hipStream_t s);
+
+}  // namespace ite

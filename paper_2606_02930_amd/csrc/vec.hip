@@ -1,0 +1,355 @@
+// Bandwidth-bound kernels of the local solver: the Krylov vector operations
+// of GMRES (dots, norms, classical Gram-Schmidt updates, combinations), the
+// sparse MPO contraction stage, precision conversions and small helpers.
+//
+// Reductions are deterministic: a fixed number of blocks (a function of n
+// only), a fixed per-block order (wavefront shuffles, then LDS), and a second
+// pass that sums the block partials in index order.
+#include "internal.h"
+
+#include <cmath>
+
+namespace ite {
+namespace {
+
+constexpr int RT = 256;           // threads per reduction block
+constexpr int MAX_RED_BLOCKS = 1024;
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Block sum of v (every thread of the block gets the result).
+__device__ inline double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    __syncthreads();
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    const int nw = blockDim.x >> 6;
+    for (int i = 0; i < nw; ++i) r += sh[i];
+    return r;
+}
+
+__global__ __launch_bounds__(RT) void dot_partials_kernel(const double* __restrict__ x,
+                                                          const double* __restrict__ y, size_t n,
+                                                          double* __restrict__ partial) {
+    __shared__ double sh[RT / 64];
+    double acc = 0.0;
+    const size_t stride = (size_t)gridDim.x * RT;
+    for (size_t i = (size_t)blockIdx.x * RT + threadIdx.x; i < n; i += stride) acc += x[i] * y[i];
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+// partial[j*nb + b]: block b's share of V_j . w for j < k (k <= 64).
+template <int KMAX>
+__global__ __launch_bounds__(RT) void mdot_partials_kernel(const double* __restrict__ V, long ldv,
+                                                           int k, const double* __restrict__ w,
+                                                           size_t n, double* __restrict__ partial) {
+    __shared__ double sh[RT / 64];
+    double acc[KMAX];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) acc[j] = 0.0;
+    const size_t stride = (size_t)gridDim.x * RT;
+    for (size_t i = (size_t)blockIdx.x * RT + threadIdx.x; i < n; i += stride) {
+        const double wi = w[i];
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j)
+            if (j < k) acc[j] += V[(size_t)j * ldv + i] * wi;
+    }
+    for (int j = 0; j < k; ++j) {
+        const double s = block_sum(acc[j], sh);
+        if (threadIdx.x == 0) partial[(size_t)j * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+__global__ __launch_bounds__(RT) void finish_partials_kernel(const double* __restrict__ partial,
+                                                             int nb, double* __restrict__ out,
+                                                             int mode) {
+    __shared__ double sh[RT / 64];
+    const int j = blockIdx.x;
+    double acc = 0.0;
+    // fixed assignment of partials to threads, fixed combination order
+    for (int b = threadIdx.x; b < nb; b += RT) acc += partial[(size_t)j * nb + b];
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) {
+        if (mode == 0) out[j] = acc;
+        else if (mode == 1) out[j] += acc;
+        else out[j] = sqrt(fmax(acc, 0.0));
+    }
+}
+
+template <int KMAX, bool SUB>
+__global__ __launch_bounds__(RT) void gemv_kernel(const double* __restrict__ V, long ldv, int k,
+                                                  const double* __restrict__ coef,
+                                                  double* __restrict__ w, size_t n) {
+    double c[KMAX];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) c[j] = (j < k) ? coef[j] : 0.0;
+    const size_t stride = (size_t)gridDim.x * RT;
+    for (size_t i = (size_t)blockIdx.x * RT + threadIdx.x; i < n; i += stride) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j)
+            if (j < k) s += c[j] * V[(size_t)j * ldv + i];
+        w[i] = SUB ? w[i] - s : w[i] + s;
+    }
+}
+
+__global__ void axpby_kernel(size_t n, double a, const double* __restrict__ x, double b,
+                             const double* __restrict__ y, double* __restrict__ out) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        out[i] = y ? a * x[i] + b * y[i] : a * x[i];
+}
+
+__global__ void scale_inv_kernel(const double* __restrict__ x, const double* __restrict__ den,
+                                 double* __restrict__ out, size_t n) {
+    const double d = *den;
+    const double inv = d > 0.0 ? 1.0 / d : 0.0;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        out[i] = x[i] * inv;
+}
+
+__global__ void scale_kernel(double* __restrict__ x, double a, size_t n) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] *= a;
+}
+
+__global__ void fill_kernel(double* __restrict__ x, double v, size_t n) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) x[i] = v;
+}
+
+__global__ void eye_kernel(double* __restrict__ x, int D) {
+    const size_t n = (size_t)D * D;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        x[i] = (i / D == i % D) ? 1.0 : 0.0;
+}
+
+__global__ void nonfinite_kernel(const double* __restrict__ x, size_t n, int* flag) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    bool bad = false;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        bad |= !isfinite(x[i]);
+    if (bad) atomicOr(flag, 1);
+}
+
+__global__ void f32_kernel(const double* __restrict__ x, float* __restrict__ y, size_t n) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        y[i] = (float)x[i];
+}
+
+// FP64 -> BF16 with round to nearest even, done in two exact steps: the FP64
+// value is first rounded to FP32 with round-to-odd (so that the second
+// rounding cannot double-round), then FP32 -> BF16 by the usual
+// add-0x7fff-plus-lsb rule.  NaN stays NaN.
+__device__ inline uint16_t to_bf16(double v) {
+    float f = (float)v;
+    if (isfinite(f) && (double)f != v) {
+        // round to odd: truncate toward zero, then set the last bit
+        uint32_t u = __float_as_uint(f);
+        if (fabs((double)f) > fabs(v)) u -= 1;   // move toward zero
+        u |= 1u;
+        f = __uint_as_float(u);
+    }
+    uint32_t u = __float_as_uint(f);
+    if (isnan(f)) return (uint16_t)((u >> 16) | 0x40);
+    const uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return (uint16_t)(u >> 16);
+}
+
+__global__ void bf16_kernel(const double* __restrict__ x, uint16_t* __restrict__ y, size_t n) {
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        y[i] = to_bf16(x[i]);
+}
+
+// out[j][i] = in[i][j] through a 32 x 32 LDS tile.
+__global__ void transpose_kernel(const double* __restrict__ in, int rows, int cols,
+                                 double* __restrict__ out) {
+    __shared__ double tile[32][33];
+    const int c0 = blockIdx.x * 32, r0 = blockIdx.y * 32;
+    for (int k = threadIdx.y; k < 32; k += blockDim.y) {
+        const int r = r0 + k, c = c0 + threadIdx.x;
+        if (r < rows && c < cols) tile[k][threadIdx.x] = in[(size_t)r * cols + c];
+    }
+    __syncthreads();
+    for (int k = threadIdx.y; k < 32; k += blockDim.y) {
+        const int c = c0 + k, r = r0 + threadIdx.x;
+        if (r < rows && c < cols) out[(size_t)c * rows + r] = tile[threadIdx.x][k];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Sparse MPO stage.  A block handles one g and SC consecutive columns; the
+// I inputs of those columns are staged in LDS, then every thread produces the
+// O outputs of its column from the CSR rows (uniform across the block, so the
+// matrix entries come through scalar loads).
+// ---------------------------------------------------------------------------
+constexpr int SC = 128;
+
+__global__ __launch_bounds__(SC) void stage_kernel(Stage st) {
+    extern __shared__ double xin[];   // [I][SC]
+    const int g = blockIdx.y;
+    const int c = blockIdx.x * SC + threadIdx.x;
+    const double* __restrict__ in = st.in + (long)g * st.in_gs + (long)c * st.in_cs;
+    for (int i = 0; i < st.I; ++i) {
+        const long off = (long)(i / st.in_div) * st.in_s1 + (long)(i % st.in_div) * st.in_s2;
+        xin[i * SC + threadIdx.x] = (c < st.C) ? in[off] : 0.0;
+    }
+    __syncthreads();
+    if (c >= st.C) return;
+    double* __restrict__ out = st.out + (long)g * st.out_gs + (long)c * st.out_cs;
+    for (int o = 0; o < st.O; ++o) {
+        double acc = 0.0;
+        const int e1 = st.rowptr[o + 1];
+        for (int e = st.rowptr[o]; e < e1; ++e) acc += st.val[e] * xin[st.col[e] * SC + threadIdx.x];
+        out[(long)(o / st.out_div) * st.out_s1 + (long)(o % st.out_div) * st.out_s2] = acc;
+    }
+}
+
+inline int grid_for(size_t n, int threads, int cap = 4096) {
+    size_t b = (n + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > (size_t)cap) b = cap;
+    return (int)b;
+}
+
+}  // namespace
+
+int reduce_blocks(size_t n) {
+    size_t b = (n + RT * 4 - 1) / (RT * 4);
+    if (b < 1) b = 1;
+    if (b > MAX_RED_BLOCKS) b = MAX_RED_BLOCKS;
+    return (int)b;
+}
+
+void dot_partials(const double* x, const double* y, size_t n, double* partial, hipStream_t s) {
+    hipLaunchKernelGGL(dot_partials_kernel, dim3(reduce_blocks(n)), dim3(RT), 0, s, x, y, n, partial);
+    HIP_CHECK(hipGetLastError());
+}
+
+void mdot_partials(const double* V, long ldv, int k, const double* w, size_t n, double* partial,
+                   hipStream_t s) {
+    const int nb = reduce_blocks(n);
+    if (k <= 4)
+        hipLaunchKernelGGL((mdot_partials_kernel<4>), dim3(nb), dim3(RT), 0, s, V, ldv, k, w, n, partial);
+    else if (k <= 8)
+        hipLaunchKernelGGL((mdot_partials_kernel<8>), dim3(nb), dim3(RT), 0, s, V, ldv, k, w, n, partial);
+    else if (k <= 16)
+        hipLaunchKernelGGL((mdot_partials_kernel<16>), dim3(nb), dim3(RT), 0, s, V, ldv, k, w, n, partial);
+    else {
+        // wider bases: 16 at a time
+        for (int j0 = 0; j0 < k; j0 += 16) {
+            const int kk = k - j0 < 16 ? k - j0 : 16;
+            hipLaunchKernelGGL((mdot_partials_kernel<16>), dim3(nb), dim3(RT), 0, s, V + (size_t)j0 * ldv,
+                               ldv, kk, w, n, partial + (size_t)j0 * nb);
+        }
+    }
+    HIP_CHECK(hipGetLastError());
+}
+
+void finish_partials(const double* partial, int k, int nb, double* out, int mode, hipStream_t s) {
+    hipLaunchKernelGGL(finish_partials_kernel, dim3(k), dim3(RT), 0, s, partial, nb, out, mode);
+    HIP_CHECK(hipGetLastError());
+}
+
+template <bool SUB>
+static void gemv_launch(const double* V, long ldv, int k, const double* coef, double* w, size_t n,
+                        hipStream_t s) {
+    const int nb = grid_for(n, RT);
+    for (int j0 = 0; j0 < k; j0 += 16) {
+        const int kk = k - j0 < 16 ? k - j0 : 16;
+        if (kk <= 4)
+            hipLaunchKernelGGL((gemv_kernel<4, SUB>), dim3(nb), dim3(RT), 0, s, V + (size_t)j0 * ldv, ldv, kk,
+                               coef + j0, w, n);
+        else if (kk <= 8)
+            hipLaunchKernelGGL((gemv_kernel<8, SUB>), dim3(nb), dim3(RT), 0, s, V + (size_t)j0 * ldv, ldv, kk,
+                               coef + j0, w, n);
+        else
+            hipLaunchKernelGGL((gemv_kernel<16, SUB>), dim3(nb), dim3(RT), 0, s, V + (size_t)j0 * ldv, ldv, kk,
+                               coef + j0, w, n);
+    }
+    HIP_CHECK(hipGetLastError());
+}
+
+void gemv_sub(const double* V, long ldv, int k, const double* coef, double* w, size_t n, hipStream_t s) {
+    gemv_launch<true>(V, ldv, k, coef, w, n, s);
+}
+void gemv_add(const double* V, long ldv, int k, const double* coef, double* x, size_t n, hipStream_t s) {
+    gemv_launch<false>(V, ldv, k, coef, x, n, s);
+}
+
+void axpby(size_t n, double a, const double* x, double b, const double* y, double* out, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(axpby_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, n, a, x, b, y, out);
+    HIP_CHECK(hipGetLastError());
+}
+
+void scale_inv(const double* x, const double* den, double* out, size_t n, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(scale_inv_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, x, den, out, n);
+    HIP_CHECK(hipGetLastError());
+}
+
+void scale(double* x, double a, size_t n, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(scale_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, x, a, n);
+    HIP_CHECK(hipGetLastError());
+}
+
+void fill(double* x, double v, size_t n, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, x, v, n);
+    HIP_CHECK(hipGetLastError());
+}
+
+void eye(double* x, int D, hipStream_t s) {
+    hipLaunchKernelGGL(eye_kernel, dim3(grid_for((size_t)D * D, 256)), dim3(256), 0, s, x, D);
+    HIP_CHECK(hipGetLastError());
+}
+
+void nonfinite_any(const double* x, size_t n, int* flag, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(nonfinite_kernel, dim3(grid_for(n, 256, 1024)), dim3(256), 0, s, x, n, flag);
+    HIP_CHECK(hipGetLastError());
+}
+
+void convert_f32(const double* x, float* y, size_t n, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(f32_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, x, y, n);
+    HIP_CHECK(hipGetLastError());
+}
+
+void convert_bf16(const double* x, uint16_t* y, size_t n, hipStream_t s) {
+    if (n == 0) return;
+    hipLaunchKernelGGL(bf16_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, x, y, n);
+    HIP_CHECK(hipGetLastError());
+}
+
+void transpose(const double* in, int rows, int cols, double* out, hipStream_t s) {
+    if (rows <= 0 || cols <= 0) return;
+    dim3 grid((cols + 31) / 32, (rows + 31) / 32);
+    hipLaunchKernelGGL(transpose_kernel, grid, dim3(32, 8), 0, s, in, rows, cols, out);
+    HIP_CHECK(hipGetLastError());
+}
+
+void stage_f64(const Stage& st, hipStream_t s) {
+    if (st.G <= 0 || st.C <= 0 || st.O <= 0) return;
+    if (st.I > 128) ITE_FAIL(ITE_EINVAL, "MPO stage: more than 128 inputs per column");
+    dim3 grid((st.C + SC - 1) / SC, st.G);
+    const size_t lds = (size_t)st.I * SC * sizeof(double);
+    hipLaunchKernelGGL(stage_kernel, grid, dim3(SC), lds, s, st);
+    HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace ite

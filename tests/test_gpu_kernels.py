@@ -1,0 +1,270 @@
+"""GPU parity of the building blocks against the oracle (FP64) and numpy,
+called through the C ABI: MFMA lane layout, GEMM (all transposes, ragged
+tails, FP32 / BF16 operands), the two-site effective Hamiltonian (small
+shapes and the L=100, chi=1024 block shape), environment updates, the Jacobi
+SVD split and the GMRES local solve."""
+import numpy as np
+import pytest
+
+import paper_2606_02930_amd as ite
+from oracle import mps as omps, mpo as ompo
+from tests.gpu_util import require_gpu, dev, host, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    torch = require_gpu()
+    ctx = ite.ite_ctx_create(0)
+    yield torch, ctx
+    torch.cuda.synchronize()
+    ite.ite_ctx_destroy(ctx)
+
+
+def test_mfma_f64_lane_layout(env):
+    torch, ctx = env
+    out = ite.ite_debug_mfma_probe(ctx, 0)
+    A = np.array([[1.0 + i + 16 * k for k in range(4)] for i in range(16)])
+    B = np.array([[1.0 / (1.0 + j + 16 * k) for j in range(16)] for k in range(4)])
+    D = A @ B
+    # FP64 16x16x4: accumulator element r of lane l is D[4 r + l // 16][l % 16]
+    for lane in range(64):
+        for r in range(4):
+            row, col = 4 * r + lane // 16, lane % 16
+            assert abs(out[lane * 4 + r] - D[row, col]) < 1e-13 * abs(D[row, col]), (lane, r)
+
+
+GEMM_SHAPES = [(1, 1, 1), (37, 61, 23), (128, 128, 16), (129, 255, 300), (300, 17, 1000), (256, 384, 64)]
+
+
+@pytest.mark.parametrize("tA", [0, 1])
+@pytest.mark.parametrize("tB", [0, 1])
+@pytest.mark.parametrize("shape", GEMM_SHAPES)
+def test_gemm_f64(env, tA, tB, shape):
+    torch, ctx = env
+    M, N, K = shape
+    rng = np.random.default_rng(M * 7 + N * 3 + K + 100 * tA + 10 * tB)
+    A = rng.standard_normal((K, M) if tA else (M, K))
+    B = rng.standard_normal((N, K) if tB else (K, N))
+    Cm = rng.standard_normal((M, N))
+    want = 0.7 * ((A.T if tA else A) @ (B.T if tB else B)) - 1.3 * Cm
+    dA, dB, dC = dev(torch, A), dev(torch, B), dev(torch, Cm)
+    dD = torch.zeros((M, N), dtype=torch.float64, device="cuda")
+    ite.ite_debug_gemm(ctx, tA, tB, M, N, K, 0.7, dA, A.shape[1], dB, B.shape[1], -1.3, dC, N, dD, N, 0)
+    assert rel_err(host(dD), want) < 1e-13
+    # in-place accumulate D = alpha AB + beta D
+    ite.ite_debug_gemm(ctx, tA, tB, M, N, K, 1.0, dA, A.shape[1], dB, B.shape[1], 1.0, dD, N, dD, N, 0)
+    assert rel_err(host(dD), want + (A.T if tA else A) @ (B.T if tB else B)) < 1e-13
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("tB", [0, 1])
+def test_gemm_low_precision(env, prec, tB):
+    torch, ctx = env
+    M, N, K = 200, 136, 520
+    rng = np.random.default_rng(11 + prec + tB)
+    A = rng.standard_normal((M, K))
+    B = rng.standard_normal((N, K) if tB else (K, N))
+    # operands rounded to nearest even directly from FP64 (FP32: 24 bits,
+    # BF16: 8 significant bits), computed independently of the library
+    if prec == 1:
+        rnd = lambda x: x.astype(np.float32).astype(np.float64)
+    else:
+        def rnd(x):
+            m, e = np.frexp(x)
+            return np.ldexp(np.round(m * 256.0) / 256.0, e)
+    Ar, Br = rnd(A), rnd(B)
+    want = Ar @ (Br.T if tB else Br)
+    dD = torch.zeros((M, N), dtype=torch.float64, device="cuda")
+    ite.ite_debug_gemm(ctx, 0, tB, M, N, K, 1.0, dev(torch, A), K, dev(torch, B), B.shape[1], 0.0, None, N, dD, N,
+                       prec)
+    # FP32 accumulation of exactly rounded operands
+    assert rel_err(host(dD), want) < 2e-5
+    exact = A @ (B.T if tB else B)
+    assert rel_err(host(dD), exact) < (1e-5 if prec == 1 else 3e-2)
+
+
+def _heff_case(rng, Dxl, Dyl, Dxr, Dyr, d, W1, W2):
+    w0, w2 = W1.shape[0], W2.shape[1]
+    Lm = rng.standard_normal((Dxl, w0, Dyl))
+    Rm = rng.standard_normal((Dxr, w2, Dyr))
+    th = rng.standard_normal((Dyl, d, d, Dyr))
+    return Lm, Rm, th
+
+
+@pytest.mark.parametrize("dims", [(1, 1, 2, 2), (3, 5, 4, 2), (16, 16, 16, 16), (37, 29, 70, 130), (130, 130, 64, 64)])
+def test_heff_apply_matches_oracle(env, dims):
+    torch, ctx = env
+    Dxl, Dyl, Dxr, Dyr = dims
+    rng = np.random.default_rng(sum(dims))
+    W = ompo.heisenberg_mpo(4, Jz=0.9)
+    W1, W2 = W[1], W[2]
+    Lm, Rm, th = _heff_case(rng, Dxl, Dyl, Dxr, Dyr, 2, W1, W2)
+    want = omps.heff_apply(Lm, W1, W2, Rm, th)
+    y = torch.zeros((Dxl, 2, 2, Dxr), dtype=torch.float64, device="cuda")
+    ite.ite_debug_heff_apply(ctx, dev(torch, Lm), W1, W2, dev(torch, Rm), dev(torch, th), 0.0, 1.0, y)
+    assert rel_err(host(y), want) < 1e-13
+    if Dxl == Dyl and Dxr == Dyr:
+        ite.ite_debug_heff_apply(ctx, dev(torch, Lm), W1, W2, dev(torch, Rm), dev(torch, th), 0.3, -0.25, y)
+        assert rel_err(host(y), 0.3 * th - 0.25 * want) < 1e-13
+
+
+def test_heff_apply_fermionic_boundary_blocks(env):
+    torch, ctx = env
+    rng = np.random.default_rng(5)
+    W = ompo.aim_mpo(4.0, -2.0, np.array([-0.5, 0.0, 0.5]), np.array([0.2, 0.3, 0.1]))
+    for j in range(3):
+        W1, W2 = W[j], W[j + 1]
+        Lm, Rm, th = _heff_case(rng, 12, 12, 9, 9, 4, W1, W2)
+        want = omps.heff_apply(Lm, W1, W2, Rm, th)
+        y = torch.zeros((12, 4, 4, 9), dtype=torch.float64, device="cuda")
+        ite.ite_debug_heff_apply(ctx, dev(torch, Lm), W1, W2, dev(torch, Rm), dev(torch, th), 0.0, 1.0, y)
+        assert rel_err(host(y), want) < 1e-13
+
+
+def test_heff_apply_full_block_shape(env):
+    # the L=100, chi=1024 Heisenberg block: L, R [1024][5][1024], theta [1024][2][2][1024]
+    torch, ctx = env
+    D = 1024
+    g = torch.Generator(device="cuda").manual_seed(1234)
+    Lm = torch.randn((D, 5, D), dtype=torch.float64, device="cuda", generator=g)
+    Rm = torch.randn((D, 5, D), dtype=torch.float64, device="cuda", generator=g)
+    th = torch.randn((D, 2, 2, D), dtype=torch.float64, device="cuda", generator=g)
+    W = ompo.heisenberg_mpo(4)
+    y = torch.zeros_like(th)
+    ite.ite_debug_heff_apply(ctx, Lm, W[1], W[2], Rm, th, 0.5, 2.0, y)
+    want = 0.5 * host(th) + 2.0 * omps.heff_apply(host(Lm), W[1], W[2], host(Rm), host(th))
+    assert rel_err(host(y), want) < 1e-12
+
+
+@pytest.mark.parametrize("with_mpo", [True, False])
+@pytest.mark.parametrize("direction", [0, 1])
+@pytest.mark.parametrize("dims", [(1, 1, 2, 2), (5, 3, 7, 6), (64, 48, 100, 90)])
+def test_env_update_matches_oracle(env, with_mpo, direction, dims):
+    torch, ctx = env
+    Dxa, Dya, Dxb, Dyb = dims
+    rng = np.random.default_rng(3 * sum(dims) + direction + 2 * with_mpo)
+    d = 2
+    Wfull = ompo.heisenberg_mpo(4, Jz=0.7)[1]
+    W = Wfull if with_mpo else None
+    wl, wr = (5, 5) if with_mpo else (1, 1)
+    if direction == 0:
+        E = rng.standard_normal((Dxa, wl, Dya)) if with_mpo else rng.standard_normal((Dxa, Dya))
+        X = rng.standard_normal((Dxa, d, Dxb))
+        Y = rng.standard_normal((Dya, d, Dyb))
+        want = omps.env_left_h(E, X, W, Y) if with_mpo else omps.env_left_o(E, X, Y)
+    else:
+        E = rng.standard_normal((Dxa, wr, Dya)) if with_mpo else rng.standard_normal((Dxa, Dya))
+        X = rng.standard_normal((Dxb, d, Dxa))
+        Y = rng.standard_normal((Dyb, d, Dya))
+        want = omps.env_right_h(E, X, W, Y) if with_mpo else omps.env_right_o(E, X, Y)
+    out = torch.zeros(want.shape, dtype=torch.float64, device="cuda")
+    ite.ite_debug_env_update(ctx, direction, dev(torch, E), dev(torch, X), W, dev(torch, Y), out)
+    assert rel_err(host(out), want) < 1e-13
+
+
+SPLIT_SHAPES = [(1, 2, 2, 1), (1, 2, 2, 2), (3, 2, 2, 5), (8, 2, 2, 3), (16, 2, 2, 16), (33, 2, 2, 17),
+                (64, 4, 4, 64), (256, 2, 2, 256)]
+
+
+@pytest.mark.parametrize("direction", [0, 1])
+@pytest.mark.parametrize("shape", SPLIT_SHAPES)
+def test_svd_split_matches_numpy(env, direction, shape):
+    torch, ctx = env
+    Dl, d1, d2, Dr = shape
+    m, n = Dl * d1, d2 * Dr
+    rng = np.random.default_rng(m * 31 + n + direction)
+    # graded spectrum so that truncation decisions are well separated
+    r = min(m, n)
+    U, _ = np.linalg.qr(rng.standard_normal((m, r)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, r)))
+    s_true = np.exp(-np.linspace(0, 12, r))
+    theta = ((U * s_true) @ V.T).reshape(Dl, d1, d2, Dr)
+    chi = max(1, r - 2)
+    A1o, A2o, info = omps.split_two_site(theta, "lr" if direction == 0 else "rl", 1e-14, chi, 1e-13)
+    k_o = info["k"]
+    A1 = torch.zeros((Dl, d1, r), dtype=torch.float64, device="cuda")
+    A2 = torch.zeros((r, d2, Dr), dtype=torch.float64, device="cuda")
+    k, sig, disc = ite.ite_debug_svd_split(ctx, direction, dev(torch, theta), chi, 1e-14, 1e-13, A1, A2)
+    a1 = host(A1).reshape(-1)[: Dl * d1 * k].reshape(Dl, d1, k)
+    a2 = host(A2).reshape(-1)[: k * d2 * Dr].reshape(k, d2, Dr)
+    diag = dict(k=k, k_o=k_o, sig_err=float(np.abs(sig - info["sigma"]).max()),
+                worst=int(np.abs(sig - info["sigma"]).argmax()),
+                recon=rel_err(omps.two_site(a1, a2), omps.two_site(A1o, A2o)),
+                orth=(omps.left_orthonormality_error(a1) if direction == 0 else omps.right_orthonormality_error(a2)))
+    assert k == k_o, diag
+    assert np.allclose(sig, info["sigma"], rtol=0, atol=1e-13 * s_true[0]), diag
+    assert abs(disc - info["disc"]) < 1e-12, diag
+    # the kept rank-k approximation is unique (gauge-free) and equals the oracle's
+    assert diag["recon"] < 1e-12, diag
+    assert diag["orth"] < 5e-13, diag
+
+
+@pytest.mark.parametrize("direction", [0, 1])
+def test_svd_split_keeps_complete_basis_with_zeros(env, direction):
+    # cutoff 0 keeps min(rows, cols, chi) values including exact zeros; the
+    # factor that becomes the canonical tensor must still be orthonormal
+    torch, ctx = env
+    rng = np.random.default_rng(77)
+    Dl, d, Dr = 4, 2, 4
+    m = Dl * d
+    u = rng.standard_normal((m, 2))
+    v = rng.standard_normal((2, d * Dr))
+    theta = (u @ v).reshape(Dl, d, d, Dr)       # rank 2
+    A1 = torch.zeros((Dl, d, 8), dtype=torch.float64, device="cuda")
+    A2 = torch.zeros((8, d, Dr), dtype=torch.float64, device="cuda")
+    k, sig, disc = ite.ite_debug_svd_split(ctx, direction, dev(torch, theta), 8, 0.0, 1e-13, A1, A2)
+    assert k == 8 and np.all(sig[2:] < 1e-13 * sig[0])
+    a1 = host(A1).reshape(Dl, d, 8)
+    a2 = host(A2).reshape(8, d, Dr)
+    assert rel_err(omps.two_site(a1, a2), theta) < 1e-13
+    if direction == 0:
+        assert omps.left_orthonormality_error(a1) < 1e-13
+    else:
+        assert omps.right_orthonormality_error(a2) < 1e-13
+
+
+def _symmetric_envs(rng, D, W1, W2):
+    """Environments of a random MPS so that H_eff is symmetric."""
+    Wall = ompo.heisenberg_mpo(6)
+    A = [rng.standard_normal((1, 2, 2)), rng.standard_normal((2, 2, D))]
+    Lm = np.ones((1, 1, 1))
+    for j in range(2):
+        Lm = omps.env_left_h(Lm, A[j], Wall[j], A[j])
+    B = [rng.standard_normal((D, 2, 2)), rng.standard_normal((2, 2, 1))]
+    Rm = np.ones((1, 1, 1))
+    for j in (5, 4):
+        a = B[j - 4]
+        Rm = omps.env_right_h(Rm, a, Wall[j], a)
+    return Lm / np.abs(Lm).max(), Rm / np.abs(Rm).max(), Wall[2], Wall[3]
+
+
+@pytest.mark.parametrize("budget", ["paper", "tol"])
+def test_local_solve_matches_oracle(env, budget):
+    torch, ctx = env
+    rng = np.random.default_rng(9)
+    Lm, Rm, W1, W2 = _symmetric_envs(rng, 4, None, None)
+    Dl, Dr = Lm.shape[0], Rm.shape[0]
+    h, s = 0.3, -1.0
+    alpha, beta = 1.0 - h * s, h
+    b = rng.standard_normal((Dl, 2, 2, Dr))
+    x0 = rng.standard_normal((Dl, 2, 2, Dr))
+    op = lambda v: alpha * v + beta * omps.heff_apply(Lm, W1, W2, Rm, v)
+    if budget == "paper":
+        m, cyc, tol = 10, 1, 0.0
+    else:
+        m, cyc, tol = 4, 100, 1e-13
+    want, info = omps.gmres(op, b, x0, m, cyc, tol)
+    x = torch.zeros(b.shape, dtype=torch.float64, device="cuda")
+    mv, res = ite.ite_debug_local_solve(ctx, dev(torch, Lm), W1, W2, dev(torch, Rm), alpha, beta, dev(torch, b),
+                                        dev(torch, x0), x, krylov_dim=m, max_cycles=cyc, tol=tol)
+    got = host(x)
+    if budget == "paper":
+        assert mv == info["matvecs"] == 11
+        assert rel_err(got, want) < 1e-10
+    else:
+        exact = np.linalg.solve(np.column_stack([op(e.reshape(b.shape)).reshape(-1) for e in np.eye(b.size)]),
+                                b.reshape(-1)).reshape(b.shape)
+        assert rel_err(got, exact) < 1e-11
+        assert res <= 1e-13

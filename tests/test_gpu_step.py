@@ -1,0 +1,240 @@
+"""GPU parity of the whole implicit step against the oracle, through the C ABI.
+
+* L=10 Heisenberg, complete bonds (chi 32), backward Euler, GMRES to 1e-12:
+  every step's energy equals the oracle's and the exact-diagonalisation
+  full-vector step's to 1e-10 (relative); the final state's overlap with both
+  to 1e-8.
+* The same chain with the trapezoid rule and the shift tracking the energy.
+* The paper's fixed budget (Krylov 10, one cycle, one sweep) with truncation by
+  discarded weight on a 14-site chain, and on the Anderson impurity model.
+* Energy measurement, overlap, norm, checkpoint/resume, determinism and the
+  error paths of the boundary.
+"""
+import numpy as np
+import pytest
+
+import paper_2606_02930_amd as ite
+from paper_2606_02930_amd import hamiltonians
+from oracle import ed, mpo as ompo, mps as omps
+from workload import rng_for, random_spinors, aim_bath
+from tests.gpu_util import require_gpu, mps_vector, mps_overlap
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    torch = require_gpu()
+    c = ite.ite_ctx_create(0)
+    yield c
+    torch.cuda.synchronize()
+    ite.ite_ctx_destroy(c)
+
+
+def _opts(**kw):
+    o = ite.ite_default_opts()
+    conv = {"scheme": {"trap": ite.SCHEME_TRAP, "be": ite.SCHEME_BE},
+            "shift_mode": {"fixed": ite.SHIFT_FIXED, "track": ite.SHIFT_TRACK}}
+    for k, v in kw.items():
+        setattr(o, k, conv[k][v] if k in conv and isinstance(v, str) else v)
+    return o
+
+
+def _oracle_opts(**kw):
+    return omps.StepOptions(**kw)
+
+
+def _run_both(ctx, L, d, Wprod, Woracle, spinors, chi, pad, grid, **kw):
+    psi = ite.ite_mps_create(ctx, spinors, chi, pad_full=pad)
+    H = ite.ite_mpo_load(ctx, Wprod)
+    try:
+        reps = ite.ite_evolve_grid(ctx, psi, H, grid, _opts(chi_max=chi, **kw))
+        out = ite.ite_mps_export(ctx, psi, [d] * L)
+    finally:
+        ite.ite_mps_destroy(psi)
+        ite.ite_mpo_destroy(H)
+    o_psi = omps.product_state(spinors, chi, pad_full=pad)
+    o_out, o_reps = omps.evolve_grid(o_psi, Woracle, grid, _oracle_opts(chi_max=chi, **kw))
+    return reps, out, o_reps, o_out
+
+
+@pytest.mark.parametrize("shift_mode", ["fixed", "track"])
+def test_heis10_backward_euler_matches_oracle_and_ed(ctx, shift_mode):
+    L, chi = 10, 32
+    sp = random_spinors(rng_for(0), L, 2)
+    H = ed.heisenberg_dense(L)
+    e0 = ed.ground_state(H)[0]
+    grid = ed.loggrid(0.01, 100.0, 1.5)
+    kw = dict(scheme="be", shift_mode=shift_mode, shift=e0, cutoff=0.0, krylov_dim=10, max_cycles=100,
+              tol_loc=1e-12)
+    reps, out, o_reps, o_out = _run_both(ctx, L, 2, hamiltonians.heisenberg(L), ompo.heisenberg_mpo(L), sp, chi,
+                                         True, grid, **kw)
+    assert len(reps) == 24
+    states, en, norms, _ = ed.evolve_dense(H, mps_vector(omps.product_state(sp)), grid, "be", shift_mode, e0)
+    for r, orr, e in zip(reps, o_reps, en[1:]):
+        assert abs(r["energy"] - orr.energy) <= 1e-10 * abs(orr.energy)
+        assert abs(r["energy"] - e) <= 1e-10 * abs(e)
+        assert abs(r["norm_before"] - orr.norm_before) <= 1e-9 * orr.norm_before
+    v = mps_vector(out)
+    assert abs(np.linalg.norm(v) - 1) < 1e-12
+    assert 1 - abs(v @ mps_vector(o_out)) <= 1e-8
+    assert 1 - abs(v @ states[-1]) <= 1e-8
+    E = [r["energy"] for r in reps]
+    if shift_mode == "fixed":
+        assert np.all(np.diff(E) <= 1e-12)
+        assert E[-1] - e0 < 1e-7
+
+
+def test_heis10_trapezoid_matches_oracle_and_ed(ctx):
+    L, chi = 10, 32
+    sp = random_spinors(rng_for(0, 1), L, 2)
+    H = ed.heisenberg_dense(L)
+    grid = ed.loggrid(0.01, 100.0, 1.5)
+    kw = dict(scheme="trap", shift_mode="track", cutoff=0.0, krylov_dim=10, max_cycles=100, tol_loc=1e-12)
+    reps, out, o_reps, o_out = _run_both(ctx, L, 2, hamiltonians.heisenberg(L), ompo.heisenberg_mpo(L), sp, chi,
+                                         True, grid, **kw)
+    states, en, _, _ = ed.evolve_dense(H, mps_vector(omps.product_state(sp)), grid, "trap", "track")
+    for r, orr, e in zip(reps, o_reps, en[1:]):
+        assert abs(r["energy"] - orr.energy) <= 1e-10 * abs(orr.energy)
+        assert abs(r["energy"] - e) <= 1e-9 * abs(e)
+    assert 1 - abs(mps_vector(out) @ mps_vector(o_out)) <= 1e-8
+
+
+def test_paper_budget_with_truncation_matches_oracle(ctx):
+    # the paper's budget: Krylov 10, one cycle, one sweep; cutoff 1e-10, chi <= 16
+    L, chi = 14, 16
+    sp = random_spinors(rng_for(1), L, 2)
+    grid = ed.loggrid(0.01, 20.0, 1.3)
+    kw = dict(scheme="trap", shift_mode="track", cutoff=1e-10, krylov_dim=10, max_cycles=1, tol_loc=0.0)
+    reps, out, o_reps, o_out = _run_both(ctx, L, 2, hamiltonians.heisenberg(L), ompo.heisenberg_mpo(L), sp, chi,
+                                         False, grid, **kw)
+    for r, orr in zip(reps, o_reps):
+        assert r["max_chi"] == orr.max_chi
+        assert abs(r["energy"] - orr.energy) <= 1e-10 * abs(orr.energy)
+        assert r["matvecs_fp64"] == orr.matvecs
+    ov = mps_overlap(out, o_out)
+    assert 1 - abs(ov) <= 1e-8
+
+
+def test_anderson_impurity_matches_oracle(ctx):
+    nb = 5
+    eb, V = aim_bath(nb, gamma=0.3)
+    U = 4.0
+    L = nb + 1
+    sp = random_spinors(rng_for(3), L, 4)
+    grid = ed.loggrid(0.01, 20.0, 1.5)
+    kw = dict(scheme="trap", shift_mode="track", cutoff=1e-9, krylov_dim=10, max_cycles=1, tol_loc=0.0)
+    reps, out, o_reps, o_out = _run_both(ctx, L, 4, hamiltonians.anderson_star(U, -U / 2, eb, V),
+                                         ompo.aim_mpo(U, -U / 2, eb, V), sp, 32, False, grid, **kw)
+    for r, orr in zip(reps, o_reps):
+        assert abs(r["energy"] - orr.energy) <= 1e-10 * abs(orr.energy)
+    assert 1 - abs(mps_overlap(out, o_out)) <= 1e-8
+
+
+def test_anderson_complete_bonds_equal_ed(ctx):
+    nb = 3
+    eb, V = aim_bath(nb, gamma=0.4)
+    U = 2.0
+    sp = random_spinors(rng_for(3, 2), nb + 1, 4)
+    grid = ed.loggrid(0.01, 50.0, 1.5)
+    kw = dict(scheme="be", shift_mode="track", cutoff=0.0, krylov_dim=10, max_cycles=200, tol_loc=1e-12)
+    reps, out, o_reps, o_out = _run_both(ctx, nb + 1, 4, hamiltonians.anderson_star(U, -U / 2, eb, V),
+                                         ompo.aim_mpo(U, -U / 2, eb, V), sp, 16, True, grid, **kw)
+    Hk = ed.aim_dense(U, -U / 2, eb, V)
+    p = ed.aim_basis_permutation(nb + 1)
+    v0 = mps_vector(omps.product_state(sp))
+    v0k = np.empty_like(v0)
+    v0k[p] = v0
+    states, en, _, _ = ed.evolve_dense(Hk, v0k, grid, "be", "track")
+    for r, e in zip(reps, en[1:]):
+        assert abs(r["energy"] - e) <= 1e-9 * abs(e)
+
+
+def test_measure_overlap_norm_and_checkpoint(ctx):
+    L, chi = 12, 16
+    sp = random_spinors(rng_for(1, 5), L, 2)
+    Wp = hamiltonians.heisenberg(L)
+    H = ite.ite_mpo_load(ctx, Wp)
+    psi = ite.ite_mps_create(ctx, sp, chi)
+    try:
+        e_prod = ite.ite_measure_energy(ctx, psi, H)
+        assert abs(e_prod - omps.expectation(omps.product_state(sp), ompo.heisenberg_mpo(L))) < 1e-12
+        o = _opts(chi_max=chi, cutoff=1e-10)
+        ite.ite_evolve_loggrid(ctx, psi, H, 0.01, 1.0, 1.3, o)
+        tensors = ite.ite_mps_export(ctx, psi, [2] * L)
+        assert abs(ite.ite_measure_energy(ctx, psi, H) - omps.expectation(tensors, ompo.heisenberg_mpo(L))) < 1e-11
+        assert abs(ite.ite_mps_norm(ctx, psi) - 1.0) < 1e-12
+        assert abs(ite.ite_mps_overlap(ctx, psi, psi) - 1.0) < 1e-12
+        tau = ite.ite_mps_get_tau(psi)
+        assert abs(tau - 1.0) < 1e-12
+        # checkpoint: reload and continue == continue directly (bitwise)
+        psi2 = ite.ite_mps_load(ctx, tensors, chi)
+        ite.ite_mps_set_tau(psi2, tau)
+        r1 = ite.ite_evolve_loggrid(ctx, psi, H, 0.01, 10.0, 1.3, o)
+        r2 = ite.ite_evolve_loggrid(ctx, psi2, H, 0.01, 10.0, 1.3, o)
+        assert len(r1) == len(r2) > 0
+        assert [r["energy"] for r in r1] == [r["energy"] for r in r2]
+        ov = ite.ite_mps_overlap(ctx, psi, psi2)
+        assert abs(ov - 1) < 1e-12
+        ite.ite_mps_destroy(psi2)
+    finally:
+        ite.ite_mps_destroy(psi)
+        ite.ite_mpo_destroy(H)
+
+
+def test_runs_are_deterministic(ctx):
+    L, chi = 16, 24
+    sp = random_spinors(rng_for(1, 6), L, 2)
+    H = ite.ite_mpo_load(ctx, hamiltonians.heisenberg(L))
+    out = []
+    for _ in range(2):
+        psi = ite.ite_mps_create(ctx, sp, chi)
+        reps = ite.ite_evolve_loggrid(ctx, psi, H, 0.01, 5.0, 1.3, _opts(chi_max=chi, cutoff=1e-10))
+        out.append(([(r["energy"], r["norm_before"], r["max_chi"], r["max_disc"]) for r in reps],
+                    [a.copy() for a in ite.ite_mps_export(ctx, psi, [2] * L)]))
+        ite.ite_mps_destroy(psi)
+    ite.ite_mpo_destroy(H)
+    assert out[0][0] == out[1][0]
+    assert all(np.array_equal(a, b) for a, b in zip(out[0][1], out[1][1]))
+
+
+def test_boundary_error_paths(ctx):
+    L = 6
+    H = ite.ite_mpo_load(ctx, hamiltonians.heisenberg(L))
+    H8 = ite.ite_mpo_load(ctx, hamiltonians.heisenberg(8))
+    psi = ite.ite_mps_create(ctx, random_spinors(rng_for(9), L, 2), 8)
+    try:
+        with pytest.raises(ite.IteError) as e:
+            ite.ite_mps_create(ctx, [np.array([np.nan, 1.0])] * L, 8)
+        assert e.value.code == ite.ITE_EINVAL
+        with pytest.raises(ite.IteError) as e:
+            ite.ite_mps_create(ctx, [np.zeros(2)] * L, 8)
+        assert e.value.code == ite.ITE_EINVAL
+        with pytest.raises(ite.IteError) as e:
+            ite.ite_imag_step(ctx, psi, H8, 0.1, _opts())
+        assert e.value.code == ite.ITE_ESTATE
+        for h in (0.0, -1.0, float("inf")):
+            with pytest.raises(ite.IteError) as e:
+                ite.ite_imag_step(ctx, psi, H, h, _opts())
+            assert e.value.code == ite.ITE_EINVAL
+        for bad in (dict(krylov_dim=0), dict(chi_max=0), dict(cutoff=-1.0), dict(nsweeps=0), dict(scheme=7)):
+            with pytest.raises(ite.IteError) as e:
+                ite.ite_imag_step(ctx, psi, H, 0.1, _opts(**bad))
+            assert e.value.code == ite.ITE_EINVAL
+        with pytest.raises(ite.IteError) as e:
+            ite.ite_evolve_loggrid(ctx, psi, H, 0.1, 0.05, 1.3, _opts())
+        assert e.value.code == ite.ITE_EINVAL
+        W = hamiltonians.heisenberg(L)
+        W[2] = W[2].copy()
+        W[2][0, 0, 0, 0] = np.inf
+        with pytest.raises(ite.IteError) as e:
+            ite.ite_mpo_load(ctx, W)
+        assert e.value.code == ite.ITE_EINVAL
+        assert "non-finite" in ite.ite_last_error(ctx)
+        # a failed call leaves the state usable
+        r = ite.ite_imag_step(ctx, psi, H, 0.1, _opts(chi_max=8))
+        assert np.isfinite(r["energy"])
+    finally:
+        ite.ite_mps_destroy(psi)
+        ite.ite_mpo_destroy(H)
+        ite.ite_mpo_destroy(H8)
