@@ -127,6 +127,15 @@ const char* ite_last_error(const ite_ctx* ctx);
 /* Library version string. */
 const char* ite_version(void);
 
+/* GEMM launch profiler (observability, used by the benchmark): with enable =
+ * 1 the context brackets every FP64 contraction launch with HIP events on its
+ * stream and counts its algorithmic work 2 M N K; enabling resets the totals,
+ * enable = 0 stops recording.  ite_ctx_profile_read synchronises the stream
+ * and returns the launch count, the summed device time (ms) and the summed
+ * algorithmic flops since the last enable. */
+int ite_ctx_profile(ite_ctx* ctx, int enable);
+int ite_ctx_profile_read(ite_ctx* ctx, long long* launches, double* ms, double* flops);
+
 /* Fill `o` with the defaults described at ite_step_opts. */
 void ite_default_opts(ite_step_opts* o);
 

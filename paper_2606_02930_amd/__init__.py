@@ -71,6 +71,8 @@ _SIGNATURES = {
     "ite_ctx_create": (_I, [_I, _P, C.POINTER(ite_allocator), C.POINTER(_P)]),
     "ite_ctx_destroy": (_I, [_P]),
     "ite_last_error": (C.c_char_p, [_P]),
+    "ite_ctx_profile": (_I, [_P, _I]),
+    "ite_ctx_profile_read": (_I, [_P, C.POINTER(C.c_longlong), _PD, _PD]),
     "ite_mpo_load": (_I, [_P, _I, _PI, _PI, _PPD, C.POINTER(_P)]),
     "ite_mpo_destroy": (_I, [_P]),
     "ite_mps_create": (_I, [_P, _I, _PI, _PPD, _I, _I, C.POINTER(_P)]),
@@ -208,6 +210,19 @@ def ite_ctx_destroy(ctx: Ctx) -> None:
 
 def ite_last_error(ctx: Ctx) -> str:
     return load_library().ite_last_error(ctx.handle).decode()
+
+
+def ite_ctx_profile(ctx: Ctx, enable: bool) -> None:
+    _check(load_library().ite_ctx_profile(ctx.handle, int(bool(enable))), ctx.handle)
+
+
+def ite_ctx_profile_read(ctx: Ctx) -> tuple[int, float, float]:
+    """(GEMM launches, summed device ms, summed algorithmic flops)."""
+    n = C.c_longlong()
+    ms = C.c_double()
+    fl = C.c_double()
+    _check(load_library().ite_ctx_profile_read(ctx.handle, C.byref(n), C.byref(ms), C.byref(fl)), ctx.handle)
+    return n.value, ms.value, fl.value
 
 
 # ---------------------------------------------------------------------------

@@ -149,6 +149,31 @@ int ite_ctx_destroy(ite_ctx* c) {
 
 const char* ite_last_error(const ite_ctx* c) { return c ? c->err.c_str() : "NULL context"; }
 
+int ite_ctx_profile(ite_ctx* c, int enable) {
+    if (!c) return ITE_EINVAL;
+    return guarded(c, [&] {
+        set_device(c);
+        prof_collect(c);
+        c->prof_on = enable != 0;
+        if (c->prof_on) {
+            c->prof_launches = 0;
+            c->prof_ms = 0.0;
+            c->prof_total_flops = 0.0;
+        }
+    });
+}
+
+int ite_ctx_profile_read(ite_ctx* c, long long* launches, double* ms, double* flops) {
+    if (!c || !launches || !ms || !flops) return ITE_EINVAL;
+    return guarded(c, [&] {
+        set_device(c);
+        prof_collect(c);
+        *launches = c->prof_launches;
+        *ms = c->prof_ms;
+        *flops = c->prof_total_flops;
+    });
+}
+
 int ite_mpo_load(ite_ctx* c, int L, const int* d, const int* w, const double* const* W, ite_mpo** out) {
     if (!c || !out) return ITE_EINVAL;
     *out = nullptr;

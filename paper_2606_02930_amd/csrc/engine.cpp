@@ -97,12 +97,44 @@ static void d2d(ite_ctx* c, double* dst, const double* src, size_t n) {
 // Contractions
 // ---------------------------------------------------------------------------
 
+static hipEvent_t prof_event(ite_ctx* c) {
+    if (c->prof_used == c->prof_events.size()) {
+        hipEvent_t e;
+        HIP_CHECK(hipEventCreate(&e));
+        c->prof_events.push_back(e);
+    }
+    return c->prof_events[c->prof_used++];
+}
+
+// Fold the recorded launch spans into the totals (synchronises the stream).
+void prof_collect(ite_ctx* c) {
+    if (c->prof_flops.empty()) return;
+    HIP_CHECK(hipStreamSynchronize(c->stream));
+    for (size_t i = 0; i < c->prof_flops.size(); ++i) {
+        float ms = 0.f;
+        HIP_CHECK(hipEventElapsedTime(&ms, c->prof_events[2 * i], c->prof_events[2 * i + 1]));
+        c->prof_ms += ms;
+        c->prof_total_flops += c->prof_flops[i];
+        c->prof_launches++;
+    }
+    c->prof_flops.clear();
+    c->prof_used = 0;
+}
+
 static void gemm(ite_ctx* c, bool tA, bool tB, int M, int N, int K, double alpha, const double* A, long lda,
                  const double* B, long ldb, double beta, const double* C, long ldc, double* D, long ldd) {
     Gemm g;
     g.M = M; g.N = N; g.K = K; g.tA = tA; g.tB = tB;
     g.alpha = alpha; g.beta = beta;
     g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc; g.D = D; g.ldd = ldd;
+    if (c->prof_on && M > 0 && N > 0) {
+        if (c->prof_flops.size() >= 4096) prof_collect(c);
+        HIP_CHECK(hipEventRecord(prof_event(c), c->stream));
+        gemm_f64(g, c->stream);
+        HIP_CHECK(hipEventRecord(prof_event(c), c->stream));
+        c->prof_flops.push_back(2.0 * M * N * (double)K);
+        return;
+    }
     gemm_f64(g, c->stream);
 }
 
@@ -269,13 +301,11 @@ SplitResult split(ite_ctx* c, int dir, int Dl, int d1, int d2, int Dr, const dou
     const int m = Dl * d1, n = d2 * Dr;
     const int p = dir == 0 ? m : n, q = dir == 0 ? n : m, ld = p + q;
     double* Z = slot_t<double>(c, SL_Z, (size_t)p * ld);
-    int nb = (p + 15) / 16;
-    if (nb < 2) nb = 2;
-    if (nb & 1) ++nb;
-    const int npairs = nb / 2, nchunks = std::max(1, (q + 127) / 128);
-    double* gram = slot_t<double>(c, SL_GRAM, (size_t)npairs * nchunks * 1024);
-    double* rot = slot_t<double>(c, SL_ROT, (size_t)npairs * 1024);
-    double* off = slot_t<double>(c, SL_OFF, (size_t)npairs + 16);
+    size_t ngram = 0, nrot = 0, noff = 0;
+    jacobi_workspace(p, q, &ngram, &nrot, &noff);
+    double* gram = slot_t<double>(c, SL_GRAM, ngram);
+    double* rot = slot_t<double>(c, SL_ROT, nrot);
+    double* off = slot_t<double>(c, SL_OFF, noff);
     double* norms = slot_t<double>(c, SL_NORM, (size_t)p + 16);
     int* perm = slot_t<int>(c, SL_PERM, (size_t)p + 16);
     jacobi_input(theta, m, n, dir, Z, c->stream);

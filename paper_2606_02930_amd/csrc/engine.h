@@ -34,6 +34,13 @@ struct ite_ctx {
     size_t pinned_bytes = 0;
     std::vector<hipEvent_t> events;
     size_t events_used = 0;
+    // GEMM launch profiler: event pairs around each GEMM launch
+    bool prof_on = false;
+    std::vector<hipEvent_t> prof_events;
+    size_t prof_used = 0;
+    std::vector<double> prof_flops;    // algorithmic flops (2 M N K) per recorded launch
+    long long prof_launches = 0;
+    double prof_ms = 0.0, prof_total_flops = 0.0;
 };
 
 // Sparse small matrix in CSR form on the device.
@@ -93,6 +100,7 @@ template <typename T> inline T* slot_t(ite_ctx* c, SlotId s, size_t count) {
 }
 double* pinned(ite_ctx* c, size_t doubles);
 void sync(ite_ctx* c);
+void prof_collect(ite_ctx* c);
 
 // Contraction primitives (device pointers; MPO matrices from ite_mpo).
 struct HeffShape {

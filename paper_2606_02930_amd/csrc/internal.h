@@ -120,6 +120,8 @@ JacobiResult jacobi_rows(double* Z, int p, int q, int ld, double tol, int max_sw
 // Build the Jacobi work matrix [theta | I_m] (dir 0) or [theta^T | I_n]
 // (dir 1) for theta m x n; leading dimension m + n.
 void jacobi_input(const double* theta, int m, int n, int dir, double* Z, hipStream_t s);
+// Workspace sizes (doubles) of jacobi_rows for p rows of length q.
+void jacobi_workspace(int p, int q, size_t* gram, size_t* rot, size_t* off);
 // norms[i] = || Z[i][0:q] ||
 void row_norms(const double* Z, int p, int q, int ld, double* norms, hipStream_t s);
 // Gather kept rows: for t < k, r = perm[t]:

@@ -31,8 +31,7 @@ typedef double d4_t __attribute__((ext_vector_type(4)));
 
 constexpr int RB = 16;       // rows per block
 constexpr int PR = 2 * RB;   // rows per pair
-constexpr int GW = 128;      // columns per gram chunk
-constexpr int RW = 256;      // columns per rotate block
+constexpr int GW = 256;      // columns per gram chunk
 
 // Block index at position `pos` of the circle schedule in round r
 // (nb blocks, nb even; position 0 is fixed).
@@ -40,9 +39,13 @@ __device__ inline int circle_block(int pos, int r, int nb) {
     return pos == 0 ? 0 : ((pos - 1 + r) % (nb - 1)) + 1;
 }
 
+// Local row lr of pair P in round r; the first 16 local rows always belong to
+// the block with the lower index, so that the sorting rotations below move
+// larger rows towards lower global indices.
 __device__ inline int pair_row(int P, int lr, int r, int nb) {
-    const int bi = circle_block(P, r, nb);
-    const int bj = circle_block(nb - 1 - P, r, nb);
+    const int b0 = circle_block(P, r, nb);
+    const int b1 = circle_block(nb - 1 - P, r, nb);
+    const int bi = b0 < b1 ? b0 : b1, bj = b0 < b1 ? b1 : b0;
     return lr < RB ? bi * RB + lr : bj * RB + (lr - RB);
 }
 
@@ -53,11 +56,11 @@ __global__ __launch_bounds__(256) void gram_kernel(const double* __restrict__ Z,
     const int P = blockIdx.y, chunk = blockIdx.x;
     const int c0 = chunk * GW;
     const int t = threadIdx.x;
-    for (int e = 0; e < PR / 2; ++e) {
-        const int lr = 2 * e + (t >> 7);
-        const int c = c0 + (t & 127);
+    for (int e = t; e < PR * GW; e += 256) {
+        const int lr = e / GW, cc = e % GW;
+        const int c = c0 + cc;
         const int row = pair_row(P, lr, r, nb);
-        Xs[lr][t & 127] = (row < p && c < q) ? Z[(long)row * ld + c] : 0.0;
+        Xs[lr][cc] = (row < p && c < q) ? Z[(long)row * ld + c] : 0.0;
     }
     __syncthreads();
     const int lane = t & 63, w = t >> 6;
@@ -78,160 +81,263 @@ __device__ inline void atomic_max_pos(double* addr, double v) {
     atomicMax(reinterpret_cast<unsigned long long*>(addr), (unsigned long long)__double_as_longlong(v));
 }
 
-// One wavefront per pair: sum the chunk partials, diagonalise by cyclic
-// Jacobi, write Q (32 x 32) and whether any rotation was applied.
+// Orthogonality measure of rows i, j with Gram entries g_ii, g_jj, g_ij:
+//   |g_ij| / (d_i d_j + kappa s1 (d_i + d_j)),   d = sqrt(g), s1 ~ sigma_max.
+// The second term is the rounding floor: rotations with large rows leave an
+// absolute error of order eps s1 in every row, so small rows cannot be made
+// orthogonal relative to their own length (their singular values and
+// vectors are then accurate in absolute terms, as for any backward-stable
+// SVD).
+__device__ inline double off_den(double gi, double gj, double kappa_s1) {
+    const double di = sqrt(fmax(gi, 0.0)), dj = sqrt(fmax(gj, 0.0));
+    return di * dj + kappa_s1 * (di + dj);
+}
+
+// One wavefront per pair: sum the chunk partials, then one cyclic sweep of
+// two-sided Jacobi rotations on the 32 x 32 Gram matrix (each rotation the
+// one of the two diagonalising angles that keeps the larger row at the lower
+// index), then a Newton-Schulz step on the accumulated Q; writes Q and
+// whether any rotation was applied.  sigma1sq: largest row norm squared seen
+// in the previous sweep (0: use this pair's own).
+//
+// The 16 disjoint rotations of a round act as new_i = al_i old_i + be_i
+// old_partner(i) on rows and columns, so every entry of G' = J^T G J and of
+// Q' = Q J is an independent combination of at most four old entries: one
+// double-buffered update per round with all LDS loads of a lane in flight
+// together.
 __global__ __launch_bounds__(64) void inner_kernel(const double* __restrict__ gram, int nchunks,
-                                                   int p, int r, int nb, double tol,
-                                                   int inner_sweeps, double* __restrict__ rot,
-                                                   int* __restrict__ rotated,
+                                                   int p, int r, int nb, double tol, double kappa,
+                                                   double sigma1sq, int inner_sweeps,
+                                                   double* __restrict__ rot, int* __restrict__ rotated,
                                                    double* __restrict__ sweep_off) {
-    __shared__ double G[PR][PR + 1];
-    __shared__ double Q[PR][PR + 1];
-    __shared__ double cs[PR / 2], sn[PR / 2];
-    __shared__ int pa[PR / 2], pb[PR / 2];
-    __shared__ int any_rot;
+    __shared__ double Gb[2][PR][PR + 1];
+    __shared__ double Qb[2][PR][PR + 1];
+    __shared__ double al[PR], be[PR];
+    __shared__ int part[PR];
     const int P = blockIdx.x;
     const int l = threadIdx.x;
+    const int y = l & 31, xh = l >> 5;   // this lane's column and half
     const double* src = gram + (long)P * nchunks * (PR * PR);
-    for (int e = l; e < PR * PR; e += 64) {
-        double s = 0.0;
-        for (int c = 0; c < nchunks; ++c) s += src[(long)c * PR * PR + e];
-        G[e / PR][e % PR] = s;
-        Q[e / PR][e % PR] = (e / PR == e % PR) ? 1.0 : 0.0;
-    }
-    if (l == 0) any_rot = 0;
-    __syncthreads();
-    // symmetrise (the two triangles come from different MFMA tiles)
-    for (int e = l; e < PR * PR; e += 64) {
-        const int i = e / PR, j = e % PR;
-        if (i < j) {
-            const double v = 0.5 * (G[i][j] + G[j][i]);
-            G[i][j] = v;
-            G[j][i] = v;
+    {
+        // chunk-outer so that the 16 loads of a chunk are in flight together
+        double s[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) s[t] = 0.0;
+        for (int c = 0; c < nchunks; ++c) {
+            const double* g = src + (long)c * PR * PR + y;
+            double v[16];
+#pragma unroll
+            for (int t = 0; t < 16; ++t) v[t] = g[(xh + 2 * t) * PR];
+#pragma unroll
+            for (int t = 0; t < 16; ++t) s[t] += v[t];
+        }
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const int x = xh + 2 * t;
+            Gb[0][x][y] = s[t];
+            Qb[0][x][y] = (x == y) ? 1.0 : 0.0;
         }
     }
     __syncthreads();
-    // relative off-diagonal measure before rotating
+    // symmetrise (the two triangles come from different MFMA tiles)
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int x = xh + 2 * t;
+        if (x < y) {
+            const double v = 0.5 * (Gb[0][x][y] + Gb[0][y][x]);
+            Gb[0][x][y] = v;
+            Gb[0][y][x] = v;
+        }
+    }
+    __syncthreads();
+    // off-diagonal measure before rotating; largest diagonal for the next sweep
+    double gmax_local = 0.0;
+    for (int i = 0; i < PR; ++i) gmax_local = fmax(gmax_local, Gb[0][i][i]);
+    const double kappa_s1 = kappa * sqrt(fmax(sigma1sq, gmax_local));
     double off = 0.0;
-    for (int e = l; e < PR * PR; e += 64) {
-        const int i = e / PR, j = e % PR;
-        if (i < j) {
-            const double dd = G[i][i] * G[j][j];
-            if (dd > 0.0) off = fmax(off, fabs(G[i][j]) / sqrt(dd));
+    {
+        const double gyy = Gb[0][y][y];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const int x = xh + 2 * t;
+            if (x < y) {
+                const double den = off_den(Gb[0][x][x], gyy, kappa_s1);
+                if (den > 0.0) off = fmax(off, fabs(Gb[0][x][y]) / den);
+            }
         }
     }
     for (int o = 32; o > 0; o >>= 1) off = fmax(off, __shfl_xor(off, o, 64));
-    if (l == 0) atomic_max_pos(sweep_off, off);
+    if (l == 0) {
+        atomic_max_pos(sweep_off, off);
+        atomic_max_pos(sweep_off + 1, gmax_local);
+    }
     if (off <= tol) {
         if (l == 0) rotated[P] = 0;
         return;
     }
+    int cur = 0;
+    bool any_rot = false;
     for (int sw = 0; sw < inner_sweeps; ++sw) {
-        int swept = 0;
+        bool swept = false;
         for (int rr = 0; rr < PR - 1; ++rr) {
+            bool mine = false;
             if (l < PR / 2) {
                 const int a0 = l == 0 ? 0 : ((l - 1 + rr) % (PR - 1)) + 1;
                 const int b0 = ((PR - 1 - l - 1 + rr) % (PR - 1)) + 1;
                 const int a = a0 < b0 ? a0 : b0, b = a0 < b0 ? b0 : a0;
-                const double gaa = G[a][a], gbb = G[b][b], gab = G[a][b];
+                const double gaa = Gb[cur][a][a], gbb = Gb[cur][b][b], gab = Gb[cur][a][b];
                 double c = 1.0, s = 0.0;
-                if (gab != 0.0 && fabs(gab) > 1e-300 + 0.25 * tol * sqrt(fmax(gaa * gbb, 0.0))) {
+                if (gab != 0.0 && fabs(gab) > 0.25 * tol * off_den(gaa, gbb, kappa_s1)) {
                     const double tau = (gbb - gaa) / (2.0 * gab);
                     double tt;
                     if (fabs(tau) > 1e150) tt = 0.5 / tau;
                     else tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
                     c = 1.0 / sqrt(1.0 + tt * tt);
                     s = tt * c;
-                    swept = 1;
+                    // the other diagonalising angle if this one leaves the
+                    // smaller row at the lower index
+                    const double naa = c * c * gaa - 2.0 * c * s * gab + s * s * gbb;
+                    const double nbb = s * s * gaa + 2.0 * c * s * gab + c * c * gbb;
+                    if (naa < nbb) {
+                        const double c0 = c;
+                        c = -s;
+                        s = c0;
+                    }
+                    mine = true;
                 }
-                cs[l] = c;
-                sn[l] = s;
-                pa[l] = a;
-                pb[l] = b;
+                // new_a = c a - s b, new_b = s a + c b
+                al[a] = c;
+                be[a] = -s;
+                al[b] = c;
+                be[b] = s;
+                part[a] = b;
+                part[b] = a;
             }
-            swept = __any(swept) ? 1 : 0;
+            const bool round_rot = __any(mine);
             __syncthreads();
-            // rows: G <- J^T G
-            for (int e = l; e < (PR / 2) * PR; e += 64) {
-                const int k = e / PR, j = e % PR;
-                const double c = cs[k], s = sn[k];
-                if (s != 0.0) {
-                    const double gp = G[pa[k]][j], gq = G[pb[k]][j];
-                    G[pa[k]][j] = c * gp - s * gq;
-                    G[pb[k]][j] = s * gp + c * gq;
-                }
+            if (!round_rot) continue;
+            swept = true;
+            const int nxt = cur ^ 1;
+            const int yp = part[y];
+            const double ay = al[y], by = be[y];
+            double gv[16], qv[16];
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                const int x = xh + 2 * t;
+                const int xp = part[x];
+                const double ax = al[x], bx = be[x];
+                gv[t] = ax * (ay * Gb[cur][x][y] + by * Gb[cur][x][yp]) +
+                        bx * (ay * Gb[cur][xp][y] + by * Gb[cur][xp][yp]);
+                qv[t] = ay * Qb[cur][x][y] + by * Qb[cur][x][yp];
+            }
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                const int x = xh + 2 * t;
+                Gb[nxt][x][y] = gv[t];
+                Qb[nxt][x][y] = qv[t];
             }
             __syncthreads();
-            // columns: G <- G J, Q <- Q J
-            for (int e = l; e < (PR / 2) * PR; e += 64) {
-                const int k = e / PR, i = e % PR;
-                const double c = cs[k], s = sn[k];
-                if (s != 0.0) {
-                    const double gp = G[i][pa[k]], gq = G[i][pb[k]];
-                    G[i][pa[k]] = c * gp - s * gq;
-                    G[i][pb[k]] = s * gp + c * gq;
-                    const double qp = Q[i][pa[k]], qq = Q[i][pb[k]];
-                    Q[i][pa[k]] = c * qp - s * qq;
-                    Q[i][pb[k]] = s * qp + c * qq;
-                }
-            }
-            __syncthreads();
-            if (swept && l == 0) any_rot = 1;
+            cur = nxt;
         }
-        __syncthreads();
-        if (!__any(swept)) break;
+        any_rot = any_rot || swept;
+        if (!swept) break;
     }
-    __syncthreads();
     // One Newton-Schulz step towards the nearest orthogonal matrix,
     // Q <- Q (3 I - Q^T Q) / 2: the product of Givens rotations is orthogonal
     // only to a few hundred ulps, and every row meets such a rotation in each
     // round of every sweep, so the defect would otherwise accumulate.
-    __shared__ double T[PR][PR + 1];
-    for (int e = l; e < PR * PR; e += 64) {
-        const int i = e / PR, j = e % PR;
-        double acc = 0.0;
-        for (int k = 0; k < PR; ++k) acc += Q[k][i] * Q[k][j];
-        G[i][j] = acc;
-    }
-    __syncthreads();
-    for (int e = l; e < PR * PR; e += 64) {
-        const int i = e / PR, j = e % PR;
-        double acc = 0.0;
-        for (int k = 0; k < PR; ++k) acc += Q[i][k] * G[k][j];
-        T[i][j] = 1.5 * Q[i][j] - 0.5 * acc;
+    double (*Q)[PR + 1] = Qb[cur];
+    double (*S)[PR + 1] = Gb[cur];
+    double (*T)[PR + 1] = Gb[cur ^ 1];
+    {
+        double acc[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) acc[t] = 0.0;
+        for (int k = 0; k < PR; ++k) {
+            const double qky = Q[k][y];
+#pragma unroll
+            for (int t = 0; t < 16; ++t) acc[t] += Q[k][xh + 2 * t] * qky;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 16; ++t) S[xh + 2 * t][y] = acc[t];
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 16; ++t) acc[t] = 0.0;
+        for (int k = 0; k < PR; ++k) {
+            const double sky = S[k][y];
+#pragma unroll
+            for (int t = 0; t < 16; ++t) acc[t] += Q[xh + 2 * t][k] * sky;
+        }
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const int x = xh + 2 * t;
+            T[x][y] = 1.5 * Q[x][y] - 0.5 * acc[t];
+        }
     }
     __syncthreads();
     double* out = rot + (long)P * PR * PR;
-    for (int e = l; e < PR * PR; e += 64) out[e] = T[e / PR][e % PR];
-    if (l == 0) rotated[P] = any_rot;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int x = xh + 2 * t;
+        out[x * PR + y] = T[x][y];
+    }
+    if (l == 0) rotated[P] = any_rot ? 1 : 0;
 }
 
-__global__ __launch_bounds__(RW) void rotate_kernel(double* __restrict__ Z, int p, int ld, int r,
-                                                    int nb, const double* __restrict__ rot,
-                                                    const int* __restrict__ rotated) {
+// Z_pair <- Q^T Z_pair on a chunk of RCOLS columns with FP64 MFMA: the pair's
+// 32 rows of the chunk and Q are staged in LDS; wavefront w computes the
+// output tiles of columns 32 w .. 32 w + 31 for both 16-row halves.
+constexpr int RCOLS = 128;
+
+__global__ __launch_bounds__(256) void rotate_kernel(double* __restrict__ Z, int p, int ld, int r,
+                                                     int nb, const double* __restrict__ rot,
+                                                     const int* __restrict__ rotated) {
     const int P = blockIdx.y;
     if (!rotated[P]) return;
-    __shared__ double Q[PR * PR];
+    __shared__ double Qs[PR][PR + 1];        // Q[k][m]
+    __shared__ double Zs[PR][RCOLS + 1];     // pair rows of the chunk
     const double* src = rot + (long)P * PR * PR;
-    for (int e = threadIdx.x; e < PR * PR; e += RW) Q[e] = src[e];
-    __syncthreads();
-    const int c = blockIdx.x * RW + threadIdx.x;
-    if (c >= ld) return;
-    double x[PR];
-    long off[PR];
-#pragma unroll
-    for (int lr = 0; lr < PR; ++lr) {
+    const int t = threadIdx.x;
+    for (int e = t; e < PR * PR; e += 256) Qs[e / PR][e % PR] = src[e];
+    const int c0 = blockIdx.x * RCOLS;
+    for (int e = 0; e < PR / 2; ++e) {
+        const int lr = 2 * e + (t >> 7);
+        const int c = c0 + (t & 127);
         const int row = pair_row(P, lr, r, nb);
-        off[lr] = row < p ? (long)row * ld + c : -1;
-        x[lr] = off[lr] >= 0 ? Z[off[lr]] : 0.0;
+        Zs[lr][t & 127] = (row < p && c < ld) ? Z[(long)row * ld + c] : 0.0;
+    }
+    __syncthreads();
+    const int lane = t & 63, w = t >> 6;
+    const int l16 = lane & 15, kg = lane >> 4;
+    // 2 row tiles x 8 column tiles; wave w owns column tiles 2w, 2w+1 for both row tiles
+    d4_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = d4_t{0, 0, 0, 0};
+#pragma unroll
+    for (int k0 = 0; k0 < PR; k0 += 4) {
+        const int k = k0 + kg;
+        const double a0 = Qs[k][l16], a1 = Qs[k][16 + l16];          // A[m][k] = Q[k][m]
+        const double b0 = Zs[k][(2 * w) * 16 + l16], b1 = Zs[k][(2 * w + 1) * 16 + l16];
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
     }
 #pragma unroll
-    for (int i = 0; i < PR; ++i) {
-        double s = 0.0;
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int k = 0; k < PR; ++k) s += Q[k * PR + i] * x[k];
-        if (off[i] >= 0) Z[off[i]] = s;
-    }
+        for (int j = 0; j < 2; ++j) {
+            const int c = c0 + (2 * w + j) * 16 + l16;
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int m = i * 16 + 4 * rr + kg;      // FP64 MFMA accumulator row
+                const int row = pair_row(P, m, r, nb);
+                if (row < p && c < ld) Z[(long)row * ld + c] = acc[i][j][rr];
+            }
+        }
 }
 
 __global__ __launch_bounds__(256) void row_norms_kernel(const double* __restrict__ Z, int q, int ld,
@@ -299,6 +405,16 @@ void jacobi_input(const double* theta, int m, int n, int dir, double* Z, hipStre
     HIP_CHECK(hipGetLastError());
 }
 
+void jacobi_workspace(int p, int q, size_t* gram, size_t* rot, size_t* off) {
+    int nb = (p + RB - 1) / RB;
+    if (nb < 2) nb = 2;
+    if (nb & 1) ++nb;
+    const size_t npairs = nb / 2, nchunks = std::max(1, (q + GW - 1) / GW);
+    *gram = npairs * nchunks * PR * PR;
+    *rot = npairs * PR * PR;
+    *off = npairs + 16;
+}
+
 JacobiResult jacobi_rows(double* Z, int p, int q, int ld, double tol, int max_sweeps,
                          double* gram_ws, double* rot_ws, double* off_ws, double* host_off,
                          hipStream_t s) {
@@ -309,22 +425,26 @@ JacobiResult jacobi_rows(double* Z, int p, int q, int ld, double tol, int max_sw
     if (nb & 1) ++nb;
     const int npairs = nb / 2;
     const int nchunks = std::max(1, (q + GW - 1) / GW);
-    const int nrot = (ld + RW - 1) / RW;
-    int* rotated = reinterpret_cast<int*>(off_ws + 1);
-    double prev = 1e300;
+    const int nrot = (ld + RCOLS - 1) / RCOLS;
+    // off_ws[0]: largest off-diagonal measure of the sweep, off_ws[1]: largest
+    // row norm squared seen in it, then one int per pair (rotated flag)
+    int* rotated = reinterpret_cast<int*>(off_ws + 2);
+    constexpr double kappa = 1e-3;
+    double prev = 1e300, sigma1sq = 0.0;
     for (int sw = 0; sw < max_sweeps; ++sw) {
-        fill(off_ws, 0.0, 1, s);
+        fill(off_ws, 0.0, 2, s);
         for (int r = 0; r < nb - 1; ++r) {
             hipLaunchKernelGGL(gram_kernel, dim3(nchunks, npairs), dim3(256), 0, s, Z, p, q, ld, r, nb,
                                nchunks, gram_ws);
             hipLaunchKernelGGL(inner_kernel, dim3(npairs), dim3(64), 0, s, gram_ws, nchunks, p, r, nb, tol,
-                               8, rot_ws, rotated, off_ws);
-            hipLaunchKernelGGL(rotate_kernel, dim3(nrot, npairs), dim3(RW), 0, s, Z, p, ld, r, nb, rot_ws,
+                               kappa, sigma1sq, 1, rot_ws, rotated, off_ws);
+            hipLaunchKernelGGL(rotate_kernel, dim3(nrot, npairs), dim3(256), 0, s, Z, p, ld, r, nb, rot_ws,
                                rotated);
         }
         HIP_CHECK(hipGetLastError());
-        HIP_CHECK(hipMemcpyAsync(host_off, off_ws, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipMemcpyAsync(host_off, off_ws, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
+        sigma1sq = host_off[1];
         res.sweeps = sw + 1;
         res.last_off = *host_off;
         if (*host_off <= tol) break;
