@@ -9,16 +9,18 @@
 // of one run and the rotation part is a complete orthonormal basis even when
 // some sigma_i are zero.
 //
-// Rows are grouped in blocks of 16; a round-robin (circle) schedule pairs the
-// blocks so that every pair meets once per sweep.  For each pair of blocks
-// (32 rows):
+// Rows are grouped in blocks of RB (16, or 32 for large p); a round-robin
+// (circle) schedule pairs the blocks so that every pair meets once per sweep.
+// For each pair of blocks (PR = 2 RB rows):
 //   1. gram:   G = X_pair X_pair^T, summed over column chunks with FP64 MFMA;
-//   2. inner:  G = Q diag Q^T by cyclic two-sided Jacobi on the 32 x 32
-//              matrix in LDS (one wavefront); Q accumulates the rotations;
-//   3. rotate: Z_pair <- Q^T Z_pair over all ld columns.
+//   2. inner:  one cyclic sweep of two-sided Jacobi rotations on the PR x PR
+//              matrix in LDS; Q accumulates the rotations;
+//   3. rotate: Z_pair <- Q^T Z_pair over all ld columns (FP64 MFMA).
 // Pairs whose rows are already orthogonal to the working tolerance produce no
 // rotation and skip step 3.  A sweep ends with one host read of the largest
-// relative off-diagonal |G_ij| / sqrt(G_ii G_jj) seen in it.
+// off-diagonal measure seen in it.  Larger blocks halve the number of rounds
+// per sweep, and with it the traffic over the whole work matrix, at the price
+// of a longer inner sweep.
 #include "internal.h"
 
 #include <algorithm>
@@ -29,9 +31,14 @@ namespace {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
-constexpr int RB = 16;       // rows per block
-constexpr int PR = 2 * RB;   // rows per pair
-constexpr int GW = 256;      // columns per gram chunk
+constexpr int RCOLS = 128;   // columns per rotate block
+
+template <int RB> struct Blk {
+    static constexpr int PR = 2 * RB;              // rows per pair
+    static constexpr int NT = PR * PR / 16;        // inner threads: 16 entries each
+    static constexpr int XS = NT / PR;             // row stride of a thread's entries
+    static constexpr int GW = RB == 16 ? 256 : 128;   // columns per gram chunk
+};
 
 // Block index at position `pos` of the circle schedule in round r
 // (nb blocks, nb even; position 0 is fixed).
@@ -39,9 +46,10 @@ __device__ inline int circle_block(int pos, int r, int nb) {
     return pos == 0 ? 0 : ((pos - 1 + r) % (nb - 1)) + 1;
 }
 
-// Local row lr of pair P in round r; the first 16 local rows always belong to
+// Local row lr of pair P in round r; the first RB local rows always belong to
 // the block with the lower index, so that the sorting rotations below move
 // larger rows towards lower global indices.
+template <int RB>
 __device__ inline int pair_row(int P, int lr, int r, int nb) {
     const int b0 = circle_block(P, r, nb);
     const int b1 = circle_block(nb - 1 - P, r, nb);
@@ -49,9 +57,10 @@ __device__ inline int pair_row(int P, int lr, int r, int nb) {
     return lr < RB ? bi * RB + lr : bj * RB + (lr - RB);
 }
 
-__global__ __launch_bounds__(256) void gram_kernel(const double* __restrict__ Z, int p, int q,
-                                                   int ld, int r, int nb, int nchunks,
-                                                   double* __restrict__ gram) {
+template <int RB>
+__global__ __launch_bounds__(256) void gram_kernel(const double* __restrict__ Z, int p, int q, int ld, int r,
+                                                   int nb, int nchunks, double* __restrict__ gram) {
+    constexpr int PR = Blk<RB>::PR, GW = Blk<RB>::GW;
     __shared__ double Xs[PR][GW + 1];
     const int P = blockIdx.y, chunk = blockIdx.x;
     const int c0 = chunk * GW;
@@ -59,21 +68,24 @@ __global__ __launch_bounds__(256) void gram_kernel(const double* __restrict__ Z,
     for (int e = t; e < PR * GW; e += 256) {
         const int lr = e / GW, cc = e % GW;
         const int c = c0 + cc;
-        const int row = pair_row(P, lr, r, nb);
+        const int row = pair_row<RB>(P, lr, r, nb);
         Xs[lr][cc] = (row < p && c < q) ? Z[(long)row * ld + c] : 0.0;
     }
     __syncthreads();
     const int lane = t & 63, w = t >> 6;
-    const int I = w >> 1, J = w & 1;
     const int l16 = lane & 15, kg = lane >> 4;
-    d4_t acc = {0, 0, 0, 0};
-    for (int k0 = 0; k0 < GW; k0 += 4)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Xs[I * 16 + l16][k0 + kg], Xs[J * 16 + l16][k0 + kg],
-                                                   acc, 0, 0, 0);
+    constexpr int NTL = PR / 16;                  // tiles per side
     double* out = gram + ((long)P * nchunks + chunk) * (PR * PR);
-    // FP64 MFMA accumulator element rr of lane group kg is tile row 4 rr + kg
+    for (int tile = w; tile < NTL * NTL; tile += 4) {
+        const int I = tile / NTL, J = tile % NTL;
+        d4_t acc = {0, 0, 0, 0};
+        for (int k0 = 0; k0 < GW; k0 += 4)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Xs[I * 16 + l16][k0 + kg], Xs[J * 16 + l16][k0 + kg],
+                                                       acc, 0, 0, 0);
+        // FP64 MFMA accumulator element rr of lane group kg is tile row 4 rr + kg
 #pragma unroll
-    for (int rr = 0; rr < 4; ++rr) out[(I * 16 + 4 * rr + kg) * PR + J * 16 + l16] = acc[rr];
+        for (int rr = 0; rr < 4; ++rr) out[(I * 16 + 4 * rr + kg) * PR + J * 16 + l16] = acc[rr];
+    }
 }
 
 __device__ inline void atomic_max_pos(double* addr, double v) {
@@ -93,56 +105,62 @@ __device__ inline double off_den(double gi, double gj, double kappa_s1) {
     return di * dj + kappa_s1 * (di + dj);
 }
 
-// One wavefront per pair: sum the chunk partials, then one cyclic sweep of
-// two-sided Jacobi rotations on the 32 x 32 Gram matrix (each rotation the
+// One workgroup per pair: sum the chunk partials, then one cyclic sweep of
+// two-sided Jacobi rotations on the PR x PR Gram matrix (each rotation the
 // one of the two diagonalising angles that keeps the larger row at the lower
 // index), then a Newton-Schulz step on the accumulated Q; writes Q and
 // whether any rotation was applied.  sigma1sq: largest row norm squared seen
 // in the previous sweep (0: use this pair's own).
 //
-// The 16 disjoint rotations of a round act as new_i = al_i old_i + be_i
+// The PR/2 disjoint rotations of a round act as new_i = al_i old_i + be_i
 // old_partner(i) on rows and columns, so every entry of G' = J^T G J and of
 // Q' = Q J is an independent combination of at most four old entries: one
-// double-buffered update per round with all LDS loads of a lane in flight
-// together.
-__global__ __launch_bounds__(64) void inner_kernel(const double* __restrict__ gram, int nchunks,
-                                                   int p, int r, int nb, double tol, double kappa,
-                                                   double sigma1sq, int inner_sweeps,
-                                                   double* __restrict__ rot, int* __restrict__ rotated,
-                                                   double* __restrict__ sweep_off) {
+// double-buffered update per round with all LDS loads of a thread in flight
+// together.  Thread t owns column t % PR and rows t / PR + XS u, u < 16.
+template <int RB>
+__global__ __launch_bounds__(Blk<RB>::NT) void inner_kernel(const double* __restrict__ gram, int nchunks, int p,
+                                                            int r, int nb, double tol, double kappa,
+                                                            double sigma1sq, double* __restrict__ rot,
+                                                            int* __restrict__ rotated,
+                                                            double* __restrict__ sweep_off) {
+    constexpr int PR = Blk<RB>::PR, NT = Blk<RB>::NT, XS = Blk<RB>::XS;
     __shared__ double Gb[2][PR][PR + 1];
     __shared__ double Qb[2][PR][PR + 1];
     __shared__ double al[PR], be[PR];
     __shared__ int part[PR];
+    __shared__ double red[NT / 64];
+    // one slot per round parity: a wave that skips a round without rotations
+    // must not overwrite the flag another wave is still reading
+    __shared__ int flag[2];
     const int P = blockIdx.x;
-    const int l = threadIdx.x;
-    const int y = l & 31, xh = l >> 5;   // this lane's column and half
+    const int t = threadIdx.x;
+    const int y = t % PR, xh = t / PR;
     const double* src = gram + (long)P * nchunks * (PR * PR);
     {
         // chunk-outer so that the 16 loads of a chunk are in flight together
         double s[16];
 #pragma unroll
-        for (int t = 0; t < 16; ++t) s[t] = 0.0;
+        for (int u = 0; u < 16; ++u) s[u] = 0.0;
         for (int c = 0; c < nchunks; ++c) {
             const double* g = src + (long)c * PR * PR + y;
             double v[16];
 #pragma unroll
-            for (int t = 0; t < 16; ++t) v[t] = g[(xh + 2 * t) * PR];
+            for (int u = 0; u < 16; ++u) v[u] = g[(xh + XS * u) * PR];
 #pragma unroll
-            for (int t = 0; t < 16; ++t) s[t] += v[t];
+            for (int u = 0; u < 16; ++u) s[u] += v[u];
         }
 #pragma unroll
-        for (int t = 0; t < 16; ++t) {
-            const int x = xh + 2 * t;
-            Gb[0][x][y] = s[t];
+        for (int u = 0; u < 16; ++u) {
+            const int x = xh + XS * u;
+            Gb[0][x][y] = s[u];
             Qb[0][x][y] = (x == y) ? 1.0 : 0.0;
         }
     }
     __syncthreads();
     // symmetrise (the two triangles come from different MFMA tiles)
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-        const int x = xh + 2 * t;
+    for (int u = 0; u < 16; ++u) {
+        const int x = xh + XS * u;
         if (x < y) {
             const double v = 0.5 * (Gb[0][x][y] + Gb[0][y][x]);
             Gb[0][x][y] = v;
@@ -158,8 +176,8 @@ __global__ __launch_bounds__(64) void inner_kernel(const double* __restrict__ gr
     {
         const double gyy = Gb[0][y][y];
 #pragma unroll
-        for (int t = 0; t < 16; ++t) {
-            const int x = xh + 2 * t;
+        for (int u = 0; u < 16; ++u) {
+            const int x = xh + XS * u;
             if (x < y) {
                 const double den = off_den(Gb[0][x][x], gyy, kappa_s1);
                 if (den > 0.0) off = fmax(off, fabs(Gb[0][x][y]) / den);
@@ -167,23 +185,26 @@ __global__ __launch_bounds__(64) void inner_kernel(const double* __restrict__ gr
         }
     }
     for (int o = 32; o > 0; o >>= 1) off = fmax(off, __shfl_xor(off, o, 64));
-    if (l == 0) {
+    if ((t & 63) == 0) red[t >> 6] = off;
+    __syncthreads();
+    off = red[0];
+    for (int i = 1; i < NT / 64; ++i) off = fmax(off, red[i]);
+    if (t == 0) {
         atomic_max_pos(sweep_off, off);
         atomic_max_pos(sweep_off + 1, gmax_local);
     }
     if (off <= tol) {
-        if (l == 0) rotated[P] = 0;
+        if (t == 0) rotated[P] = 0;
         return;
     }
     int cur = 0;
-    bool any_rot = false;
-    for (int sw = 0; sw < inner_sweeps; ++sw) {
-        bool swept = false;
-        for (int rr = 0; rr < PR - 1; ++rr) {
+    bool swept = false;
+    for (int rr = 0; rr < PR - 1; ++rr) {
+        if (t < 64) {
             bool mine = false;
-            if (l < PR / 2) {
-                const int a0 = l == 0 ? 0 : ((l - 1 + rr) % (PR - 1)) + 1;
-                const int b0 = ((PR - 1 - l - 1 + rr) % (PR - 1)) + 1;
+            if (t < PR / 2) {
+                const int a0 = t == 0 ? 0 : ((t - 1 + rr) % (PR - 1)) + 1;
+                const int b0 = ((PR - 1 - t - 1 + rr) % (PR - 1)) + 1;
                 const int a = a0 < b0 ? a0 : b0, b = a0 < b0 ? b0 : a0;
                 const double gaa = Gb[cur][a][a], gbb = Gb[cur][b][b], gab = Gb[cur][a][b];
                 double c = 1.0, s = 0.0;
@@ -213,34 +234,32 @@ __global__ __launch_bounds__(64) void inner_kernel(const double* __restrict__ gr
                 part[a] = b;
                 part[b] = a;
             }
-            const bool round_rot = __any(mine);
-            __syncthreads();
-            if (!round_rot) continue;
-            swept = true;
-            const int nxt = cur ^ 1;
-            const int yp = part[y];
-            const double ay = al[y], by = be[y];
-            double gv[16], qv[16];
-#pragma unroll
-            for (int t = 0; t < 16; ++t) {
-                const int x = xh + 2 * t;
-                const int xp = part[x];
-                const double ax = al[x], bx = be[x];
-                gv[t] = ax * (ay * Gb[cur][x][y] + by * Gb[cur][x][yp]) +
-                        bx * (ay * Gb[cur][xp][y] + by * Gb[cur][xp][yp]);
-                qv[t] = ay * Qb[cur][x][y] + by * Qb[cur][x][yp];
-            }
-#pragma unroll
-            for (int t = 0; t < 16; ++t) {
-                const int x = xh + 2 * t;
-                Gb[nxt][x][y] = gv[t];
-                Qb[nxt][x][y] = qv[t];
-            }
-            __syncthreads();
-            cur = nxt;
+            const bool any = __any(mine);
+            if (t == 0) flag[rr & 1] = any ? 1 : 0;
         }
-        any_rot = any_rot || swept;
-        if (!swept) break;
+        __syncthreads();
+        if (!flag[rr & 1]) continue;   // uniform: every thread reads the flag after the barrier
+        swept = true;
+        const int nxt = cur ^ 1;
+        const int yp = part[y];
+        const double ay = al[y], by = be[y];
+        double gv[16], qv[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int x = xh + XS * u;
+            const int xp = part[x];
+            const double ax = al[x], bx = be[x];
+            gv[u] = ax * (ay * Gb[cur][x][y] + by * Gb[cur][x][yp]) + bx * (ay * Gb[cur][xp][y] + by * Gb[cur][xp][yp]);
+            qv[u] = ay * Qb[cur][x][y] + by * Qb[cur][x][yp];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int x = xh + XS * u;
+            Gb[nxt][x][y] = gv[u];
+            Qb[nxt][x][y] = qv[u];
+        }
+        __syncthreads();
+        cur = nxt;
     }
     // One Newton-Schulz step towards the nearest orthogonal matrix,
     // Q <- Q (3 I - Q^T Q) / 2: the product of Givens rotations is orthogonal
@@ -252,47 +271,48 @@ __global__ __launch_bounds__(64) void inner_kernel(const double* __restrict__ gr
     {
         double acc[16];
 #pragma unroll
-        for (int t = 0; t < 16; ++t) acc[t] = 0.0;
+        for (int u = 0; u < 16; ++u) acc[u] = 0.0;
         for (int k = 0; k < PR; ++k) {
             const double qky = Q[k][y];
 #pragma unroll
-            for (int t = 0; t < 16; ++t) acc[t] += Q[k][xh + 2 * t] * qky;
+            for (int u = 0; u < 16; ++u) acc[u] += Q[k][xh + XS * u] * qky;
         }
         __syncthreads();
 #pragma unroll
-        for (int t = 0; t < 16; ++t) S[xh + 2 * t][y] = acc[t];
+        for (int u = 0; u < 16; ++u) S[xh + XS * u][y] = acc[u];
         __syncthreads();
 #pragma unroll
-        for (int t = 0; t < 16; ++t) acc[t] = 0.0;
+        for (int u = 0; u < 16; ++u) acc[u] = 0.0;
         for (int k = 0; k < PR; ++k) {
             const double sky = S[k][y];
 #pragma unroll
-            for (int t = 0; t < 16; ++t) acc[t] += Q[xh + 2 * t][k] * sky;
+            for (int u = 0; u < 16; ++u) acc[u] += Q[xh + XS * u][k] * sky;
         }
 #pragma unroll
-        for (int t = 0; t < 16; ++t) {
-            const int x = xh + 2 * t;
-            T[x][y] = 1.5 * Q[x][y] - 0.5 * acc[t];
+        for (int u = 0; u < 16; ++u) {
+            const int x = xh + XS * u;
+            T[x][y] = 1.5 * Q[x][y] - 0.5 * acc[u];
         }
     }
     __syncthreads();
     double* out = rot + (long)P * PR * PR;
 #pragma unroll
-    for (int t = 0; t < 16; ++t) {
-        const int x = xh + 2 * t;
+    for (int u = 0; u < 16; ++u) {
+        const int x = xh + XS * u;
         out[x * PR + y] = T[x][y];
     }
-    if (l == 0) rotated[P] = any_rot ? 1 : 0;
+    if (t == 0) rotated[P] = swept ? 1 : 0;
 }
 
 // Z_pair <- Q^T Z_pair on a chunk of RCOLS columns with FP64 MFMA: the pair's
-// 32 rows of the chunk and Q are staged in LDS; wavefront w computes the
-// output tiles of columns 32 w .. 32 w + 31 for both 16-row halves.
-constexpr int RCOLS = 128;
-
-__global__ __launch_bounds__(256) void rotate_kernel(double* __restrict__ Z, int p, int ld, int r,
-                                                     int nb, const double* __restrict__ rot,
+// rows of the chunk and Q are staged in LDS; the (PR/16) x (RCOLS/16) output
+// tiles are dealt round-robin to the four wavefronts.
+template <int RB>
+__global__ __launch_bounds__(256) void rotate_kernel(double* __restrict__ Z, int p, int ld, int r, int nb,
+                                                     const double* __restrict__ rot,
                                                      const int* __restrict__ rotated) {
+    constexpr int PR = Blk<RB>::PR;
+    constexpr int NTR = PR / 16, NTC = RCOLS / 16, TPW = NTR * NTC / 4;
     const int P = blockIdx.y;
     if (!rotated[P]) return;
     __shared__ double Qs[PR][PR + 1];        // Q[k][m]
@@ -301,43 +321,41 @@ __global__ __launch_bounds__(256) void rotate_kernel(double* __restrict__ Z, int
     const int t = threadIdx.x;
     for (int e = t; e < PR * PR; e += 256) Qs[e / PR][e % PR] = src[e];
     const int c0 = blockIdx.x * RCOLS;
-    for (int e = 0; e < PR / 2; ++e) {
-        const int lr = 2 * e + (t >> 7);
-        const int c = c0 + (t & 127);
-        const int row = pair_row(P, lr, r, nb);
-        Zs[lr][t & 127] = (row < p && c < ld) ? Z[(long)row * ld + c] : 0.0;
+    for (int e = t; e < PR * RCOLS; e += 256) {
+        const int lr = e / RCOLS, cc = e % RCOLS;
+        const int c = c0 + cc;
+        const int row = pair_row<RB>(P, lr, r, nb);
+        Zs[lr][cc] = (row < p && c < ld) ? Z[(long)row * ld + c] : 0.0;
     }
     __syncthreads();
     const int lane = t & 63, w = t >> 6;
     const int l16 = lane & 15, kg = lane >> 4;
-    // 2 row tiles x 8 column tiles; wave w owns column tiles 2w, 2w+1 for both row tiles
-    d4_t acc[2][2];
+    d4_t acc[TPW];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = d4_t{0, 0, 0, 0};
+    for (int i = 0; i < TPW; ++i) acc[i] = d4_t{0, 0, 0, 0};
 #pragma unroll
     for (int k0 = 0; k0 < PR; k0 += 4) {
         const int k = k0 + kg;
-        const double a0 = Qs[k][l16], a1 = Qs[k][16 + l16];          // A[m][k] = Q[k][m]
-        const double b0 = Zs[k][(2 * w) * 16 + l16], b1 = Zs[k][(2 * w + 1) * 16 + l16];
-        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < TPW; ++i) {
+            const int tile = w + 4 * i;
+            const int tm = tile % NTR, tn = tile / NTR;
+            acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(Qs[k][tm * 16 + l16], Zs[k][tn * 16 + l16], acc[i], 0, 0,
+                                                          0);
+        }
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TPW; ++i) {
+        const int tile = w + 4 * i;
+        const int tm = tile % NTR, tn = tile / NTR;
+        const int c = c0 + tn * 16 + l16;
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            const int c = c0 + (2 * w + j) * 16 + l16;
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
-                const int m = i * 16 + 4 * rr + kg;      // FP64 MFMA accumulator row
-                const int row = pair_row(P, m, r, nb);
-                if (row < p && c < ld) Z[(long)row * ld + c] = acc[i][j][rr];
-            }
+        for (int rr = 0; rr < 4; ++rr) {
+            const int m = tm * 16 + 4 * rr + kg;      // FP64 MFMA accumulator row
+            const int row = pair_row<RB>(P, m, r, nb);
+            if (row < p && c < ld) Z[(long)row * ld + c] = acc[i][rr];
         }
+    }
 }
 
 __global__ __launch_bounds__(256) void row_norms_kernel(const double* __restrict__ Z, int q, int ld,
@@ -405,7 +423,14 @@ void jacobi_input(const double* theta, int m, int n, int dir, double* Z, hipStre
     HIP_CHECK(hipGetLastError());
 }
 
-void jacobi_workspace(int p, int q, size_t* gram, size_t* rot, size_t* off) {
+namespace {
+
+// Rows per block: 16 for small matrices, 32 from p = 256 on (fewer rounds).
+inline int block_rows(int p) { return p >= 256 ? 32 : 16; }
+
+template <int RB>
+void ws_sizes(int p, int q, size_t* gram, size_t* rot, size_t* off) {
+    constexpr int PR = Blk<RB>::PR, GW = Blk<RB>::GW;
     int nb = (p + RB - 1) / RB;
     if (nb < 2) nb = 2;
     if (nb & 1) ++nb;
@@ -415,11 +440,11 @@ void jacobi_workspace(int p, int q, size_t* gram, size_t* rot, size_t* off) {
     *off = npairs + 16;
 }
 
-JacobiResult jacobi_rows(double* Z, int p, int q, int ld, double tol, int max_sweeps,
-                         double* gram_ws, double* rot_ws, double* off_ws, double* host_off,
-                         hipStream_t s) {
+template <int RB>
+JacobiResult run_jacobi(double* Z, int p, int q, int ld, double tol, int max_sweeps, double* gram_ws,
+                        double* rot_ws, double* off_ws, double* host_off, hipStream_t s) {
+    constexpr int GW = Blk<RB>::GW, NT = Blk<RB>::NT;
     JacobiResult res;
-    if (p <= 1) return res;
     int nb = (p + RB - 1) / RB;
     if (nb < 2) nb = 2;
     if (nb & 1) ++nb;
@@ -434,11 +459,11 @@ JacobiResult jacobi_rows(double* Z, int p, int q, int ld, double tol, int max_sw
     for (int sw = 0; sw < max_sweeps; ++sw) {
         fill(off_ws, 0.0, 2, s);
         for (int r = 0; r < nb - 1; ++r) {
-            hipLaunchKernelGGL(gram_kernel, dim3(nchunks, npairs), dim3(256), 0, s, Z, p, q, ld, r, nb,
+            hipLaunchKernelGGL((gram_kernel<RB>), dim3(nchunks, npairs), dim3(256), 0, s, Z, p, q, ld, r, nb,
                                nchunks, gram_ws);
-            hipLaunchKernelGGL(inner_kernel, dim3(npairs), dim3(64), 0, s, gram_ws, nchunks, p, r, nb, tol,
-                               kappa, sigma1sq, 1, rot_ws, rotated, off_ws);
-            hipLaunchKernelGGL(rotate_kernel, dim3(nrot, npairs), dim3(256), 0, s, Z, p, ld, r, nb, rot_ws,
+            hipLaunchKernelGGL((inner_kernel<RB>), dim3(npairs), dim3(NT), 0, s, gram_ws, nchunks, p, r, nb, tol,
+                               kappa, sigma1sq, rot_ws, rotated, off_ws);
+            hipLaunchKernelGGL((rotate_kernel<RB>), dim3(nrot, npairs), dim3(256), 0, s, Z, p, ld, r, nb, rot_ws,
                                rotated);
         }
         HIP_CHECK(hipGetLastError());
@@ -453,6 +478,20 @@ JacobiResult jacobi_rows(double* Z, int p, int q, int ld, double tol, int max_sw
         prev = *host_off;
     }
     return res;
+}
+
+}  // namespace
+
+void jacobi_workspace(int p, int q, size_t* gram, size_t* rot, size_t* off) {
+    if (block_rows(p) == 32) ws_sizes<32>(p, q, gram, rot, off);
+    else ws_sizes<16>(p, q, gram, rot, off);
+}
+
+JacobiResult jacobi_rows(double* Z, int p, int q, int ld, double tol, int max_sweeps, double* gram_ws,
+                         double* rot_ws, double* off_ws, double* host_off, hipStream_t s) {
+    if (p <= 1) return JacobiResult{};
+    if (block_rows(p) == 32) return run_jacobi<32>(Z, p, q, ld, tol, max_sweeps, gram_ws, rot_ws, off_ws, host_off, s);
+    return run_jacobi<16>(Z, p, q, ld, tol, max_sweeps, gram_ws, rot_ws, off_ws, host_off, s);
 }
 
 void row_norms(const double* Z, int p, int q, int ld, double* norms, hipStream_t s) {
