@@ -157,11 +157,60 @@ void two_site(ite_ctx* c, int Dl, int d1, int Dm, int d2, int Dr, const double* 
 //   X1[(a' w), (s t c)]   = L[(a' w), a] theta[a, (s t c)]           GEMM
 //   X3[a'][(p q u)][c]    = WW[(p q u), (w s t)] X1[a'][(w s t)][c]  sparse MPO stage
 //   y[(a' p q), c']       = X3[(a' p q), (u c)] R[c', (u c)]^T        GEMM (+ alpha Cadd)
+static size_t lo_bytes(Prec p) { return p == Prec::F32 ? 4 : 2; }
+
+// Round n FP64 values to the operand precision into dst.
+static void to_lo(ite_ctx* c, Prec p, const double* x, void* dst, size_t n) {
+    if (p == Prec::F32) convert_f32(x, static_cast<float*>(dst), n, c->stream);
+    else convert_bf16(x, static_cast<uint16_t*>(dst), n, c->stream);
+}
+
+static void gemm_lo(ite_ctx* c, Prec p, bool tA, bool tB, int M, int N, int K, double alpha, const void* A,
+                    long lda, const void* B, long ldb, double beta, const double* C, long ldc, double* D, long ldd) {
+    Gemm g;
+    g.M = M; g.N = N; g.K = K; g.tA = tA; g.tB = tB;
+    g.alpha = alpha; g.beta = beta;
+    g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc; g.D = D; g.ldd = ldd;
+    if (p == Prec::F32) gemm_f32(g, c->stream);
+    else gemm_bf16(g, c->stream);
+}
+
 void heff_apply(ite_ctx* c, const HeffShape& s, const double* L, const CsrDev& ww, const double* R,
-                const double* theta, double beta, double alpha, const double* Cadd, double* y, Prec prec) {
-    (void)prec;
+                const double* theta, double beta, double alpha, const double* Cadd, double* y, Prec prec,
+                const void* Llo, const void* Rlo) {
     const int I = s.w0 * s.d1 * s.d2, O = s.d1 * s.d2 * s.w2;
     const size_t nx = (size_t)s.Dxl * std::max(I, O) * s.Dyr;
+    if (prec != Prec::F64) {
+        // operands rounded to FP32 / BF16, FP32 accumulation in the matrix
+        // cores, FP64 intermediates and output
+        const size_t eb = lo_bytes(prec);
+        if (!Llo || !Rlo) {
+            const size_t nl = (size_t)s.Dxl * s.w0 * s.Dyl, nr = (size_t)s.Dxr * s.w2 * s.Dyr;
+            void* l = slot(c, SL_LO_L, nl * eb);
+            void* r = slot(c, SL_LO_R, nr * eb);
+            to_lo(c, prec, L, l, nl);
+            to_lo(c, prec, R, r, nr);
+            Llo = l;
+            Rlo = r;
+        }
+        const size_t nth = (size_t)s.Dyl * s.d1 * s.d2 * s.Dyr;
+        void* tlo = slot(c, SL_LO_T, nth * eb);
+        void* x3lo = slot(c, SL_LO_X, nx * eb);
+        double* X1 = slot_t<double>(c, SL_X1, nx);
+        to_lo(c, prec, theta, tlo, nth);
+        gemm_lo(c, prec, false, false, s.Dxl * s.w0, s.d1 * s.d2 * s.Dyr, s.Dyl, 1.0, Llo, s.Dyl, tlo,
+                (long)s.d1 * s.d2 * s.Dyr, 0.0, nullptr, 0, X1, (long)s.d1 * s.d2 * s.Dyr);
+        Stage st;
+        st.G = s.Dxl; st.C = s.Dyr;
+        st.in = X1; st.in_gs = (long)I * s.Dyr; st.in_s1 = s.Dyr;
+        st.out_gs = (long)O * s.Dyr; st.out_s1 = s.Dyr;
+        st.out_prec = prec == Prec::F32 ? 1 : 2;
+        st.out_lo = x3lo;
+        stage(c, ww, st);
+        gemm_lo(c, prec, false, true, s.Dxl * s.d1 * s.d2, s.Dxr, s.w2 * s.Dyr, beta, x3lo, (long)s.w2 * s.Dyr,
+                Rlo, (long)s.w2 * s.Dyr, alpha, Cadd, s.Dxr, y, s.Dxr);
+        return;
+    }
     double* X1 = slot_t<double>(c, SL_X1, nx);
     double* X3 = slot_t<double>(c, SL_X3, nx);
     gemm(c, false, false, s.Dxl * s.w0, s.d1 * s.d2 * s.Dyr, s.Dyl, 1.0, L, s.Dyl, theta,
@@ -344,15 +393,19 @@ SplitResult split(ite_ctx* c, int dir, int Dl, int d1, int d2, int Dr, const dou
 // ---------------------------------------------------------------------------
 
 static void op_apply(ite_ctx* c, const LocalOp& op, const double* v, double* y) {
-    heff_apply(c, op.s, op.L, *op.ww, op.R, v, op.beta, op.alpha, v, y, Prec::F64);
+    heff_apply(c, op.s, op.L, *op.ww, op.R, v, op.beta, op.alpha, v, y, op.prec, op.Llo, op.Rlo);
 }
 
 // GMRES(m) (Saad and Schultz) with classical Gram-Schmidt applied twice; the
 // Hessenberg column comes to the host once per Arnoldi step, where Givens
-// rotations keep the least-squares residual.
-static SolveStats gmres64(ite_ctx* c, const LocalOp& op, const double* b, double* x, int m, int max_cycles,
-                          double tol) {
+// rotations keep the least-squares residual.  Vectors, Gram-Schmidt and the
+// Hessenberg problem are FP64 whatever the precision of the products.  With
+// x_is_zero the first residual is b itself (no product).
+static SolveStats gmres(ite_ctx* c, const LocalOp& op, const double* b, double* x, int m, int max_cycles,
+                        double tol, bool x_is_zero = false) {
     SolveStats st;
+    const bool lo = op.prec != Prec::F64;
+    int& mv = lo ? st.matvecs_lo : st.matvecs64;
     const size_t n = op.n();
     const int mm = (int)std::min<size_t>((size_t)m, n);
     double* V = slot_t<double>(c, SL_V, (size_t)(mm + 1) * n);
@@ -365,9 +418,13 @@ static SolveStats gmres64(ite_ctx* c, const LocalOp& op, const double* b, double
     std::vector<double> H((size_t)(mm + 1) * mm), cs(mm), sn(mm), g(mm + 1), y(mm);
     for (int cyc = 0; cyc < max_cycles; ++cyc) {
         // r0 = b - A x
-        op_apply(c, op, x, V);
-        st.matvecs64++;
-        axpby(n, 1.0, b, -1.0, V, V, c->stream);
+        if (x_is_zero && cyc == 0) {
+            d2d(c, V, b, n);
+        } else {
+            op_apply(c, op, x, V);
+            mv++;
+            axpby(n, 1.0, b, -1.0, V, V, c->stream);
+        }
         dot_partials(V, V, n, part, c->stream);
         finish_partials(part, 1, nb, sm + 128, 2, c->stream);
         d2h(c, host, sm + 128, 1);
@@ -383,7 +440,7 @@ static SolveStats gmres64(ite_ctx* c, const LocalOp& op, const double* b, double
         bool converged = false;
         for (int k = 0; k < mm; ++k) {
             op_apply(c, op, V + (size_t)k * n, w);
-            st.matvecs64++;
+            mv++;
             mdot_partials(V, (long)n, k + 1, w, n, part, c->stream);
             finish_partials(part, k + 1, nb, sm, 0, c->stream);
             gemv_sub(V, (long)n, k + 1, sm, w, n, c->stream);
@@ -444,10 +501,49 @@ static SolveStats gmres64(ite_ctx* c, const LocalOp& op, const double* b, double
     return st;
 }
 
+// Local solve.  FP64: GMRES on the FP64 operator.  FP32_IR / BF16_IR: mixed
+// precision iterative refinement -- the residual r = b - A x is formed with
+// the FP64 operator, the correction solves A d = r by GMRES whose products use
+// FP32 or BF16 operands with FP32 accumulation, then x += d; max_refine
+// corrections, stopping early once ||r|| <= tol_refine ||b||.  The reported
+// residual is the last FP64 one.
 SolveStats local_solve(ite_ctx* c, const LocalOp& op, const double* b, double* x, int m, int max_cycles,
                        double tol, int precision, int max_refine, double tol_refine) {
-    (void)precision; (void)max_refine; (void)tol_refine;
-    return gmres64(c, op, b, x, m, max_cycles, tol);
+    if (precision == ITE_PREC_FP64) return gmres(c, op, b, x, m, max_cycles, tol);
+    const Prec p = precision == ITE_PREC_FP32_IR ? Prec::F32 : Prec::BF16;
+    const size_t n = op.n();
+    const size_t eb = lo_bytes(p);
+    const size_t nl = (size_t)op.s.Dxl * op.s.w0 * op.s.Dyl, nr = (size_t)op.s.Dxr * op.s.w2 * op.s.Dyr;
+    void* Llo = slot(c, SL_LO_L, nl * eb);
+    void* Rlo = slot(c, SL_LO_R, nr * eb);
+    to_lo(c, p, op.L, Llo, nl);
+    to_lo(c, p, op.R, Rlo, nr);
+    LocalOp lop = op;
+    lop.prec = p;
+    lop.Llo = Llo;
+    lop.Rlo = Rlo;
+    double* r = slot_t<double>(c, SL_R64, n);
+    double* d = slot_t<double>(c, SL_D64, n);
+    const double bnorm = std::sqrt(std::max(0.0, dot(c, b, b, n)));
+    SolveStats st;
+    for (int it = 0;; ++it) {
+        op_apply(c, op, x, r);
+        st.matvecs64++;
+        axpby(n, 1.0, b, -1.0, r, r, c->stream);
+        const double rn = std::sqrt(std::max(0.0, dot(c, r, r, n)));
+        st.res_rel = bnorm > 0 ? rn / bnorm : 0.0;
+        if (!(rn > 0.0) || (tol_refine > 0 && rn <= tol_refine * bnorm)) break;
+        if (it == max_refine) {
+            if (tol_refine > 0) st.flags |= ITE_FLAG_REFINE_LIMIT;
+            break;
+        }
+        fill(d, 0.0, n, c->stream);
+        SolveStats in = gmres(c, lop, r, d, m, max_cycles, tol, true);
+        st.matvecs_lo += in.matvecs_lo;
+        st.flags |= in.flags & ~ITE_FLAG_BUDGET_EXHAUSTED;
+        axpby(n, 1.0, d, 1.0, x, x, c->stream);
+    }
+    return st;
 }
 
 // ---------------------------------------------------------------------------

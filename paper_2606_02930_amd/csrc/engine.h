@@ -106,10 +106,12 @@ void prof_collect(ite_ctx* c);
 struct HeffShape {
     int Dxl, Dyl, Dxr, Dyr, d1, d2, w0, w2;
 };
-// y = beta * H_eff theta + alpha * Cadd (Cadd may be null; y may alias Cadd)
+// y = beta * H_eff theta + alpha * Cadd (Cadd may be null; y may alias Cadd).
+// prec F32 / BF16: operands rounded to that precision (Llo / Rlo: environments
+// already rounded, else rounded here), FP32 accumulation, FP64 output.
 void heff_apply(ite_ctx* c, const HeffShape& s, const double* L, const CsrDev& ww, const double* R,
                 const double* theta, double beta, double alpha, const double* Cadd, double* y,
-                Prec prec);
+                Prec prec, const void* Llo = nullptr, const void* Rlo = nullptr);
 // y = alpha * Lo theta Ro^T with Lo [Dxl][Dyl], Ro [Dxr][Dyr] (null = identity)
 void overlap_apply(ite_ctx* c, int Dxl, int Dyl, int Dxr, int Dyr, int d1, int d2, const double* Lo,
                    const double* Ro, const double* theta, double alpha, double* y);
@@ -148,6 +150,10 @@ struct LocalOp {
     const double* R;
     const CsrDev* ww;
     double alpha, beta;
+    // low-precision products: environments rounded once per local solve
+    Prec prec = Prec::F64;
+    const void* Llo = nullptr;
+    const void* Rlo = nullptr;
     size_t n() const { return (size_t)s.Dxl * s.d1 * s.d2 * s.Dxr; }
 };
 SolveStats local_solve(ite_ctx* c, const LocalOp& op, const double* b, double* x, int m, int max_cycles,

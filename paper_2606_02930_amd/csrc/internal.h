@@ -71,6 +71,8 @@ struct Stage {
     double* out = nullptr;
     long out_gs = 0, out_s1 = 0, out_s2 = 0, out_cs = 1; int out_div = 1;
     const int* rowptr = nullptr; const int* col = nullptr; const double* val = nullptr;
+    int out_prec = 0;           // 0: FP64 into out; 1: FP32, 2: BF16 into out_lo
+    void* out_lo = nullptr;
 };
 void stage_f64(const Stage& st, hipStream_t s);
 

@@ -197,6 +197,9 @@ __global__ void transpose_kernel(const double* __restrict__ in, int rows, int co
 // ---------------------------------------------------------------------------
 constexpr int SC = 128;
 
+// OUT: 0 writes FP64 to st.out, 1 rounds to FP32 and 2 to BF16 into st.out_lo
+// (the operand of a following low-precision contraction).
+template <int OUT>
 __global__ __launch_bounds__(SC) void stage_kernel(Stage st) {
     extern __shared__ double xin[];   // [I][SC]
     const int g = blockIdx.y;
@@ -208,12 +211,15 @@ __global__ __launch_bounds__(SC) void stage_kernel(Stage st) {
     }
     __syncthreads();
     if (c >= st.C) return;
-    double* __restrict__ out = st.out + (long)g * st.out_gs + (long)c * st.out_cs;
+    const long base = (long)g * st.out_gs + (long)c * st.out_cs;
     for (int o = 0; o < st.O; ++o) {
         double acc = 0.0;
         const int e1 = st.rowptr[o + 1];
         for (int e = st.rowptr[o]; e < e1; ++e) acc += st.val[e] * xin[st.col[e] * SC + threadIdx.x];
-        out[(long)(o / st.out_div) * st.out_s1 + (long)(o % st.out_div) * st.out_s2] = acc;
+        const long at = base + (long)(o / st.out_div) * st.out_s1 + (long)(o % st.out_div) * st.out_s2;
+        if (OUT == 0) st.out[at] = acc;
+        else if (OUT == 1) static_cast<float*>(st.out_lo)[at] = (float)acc;
+        else static_cast<uint16_t*>(st.out_lo)[at] = to_bf16(acc);
     }
 }
 
@@ -348,7 +354,9 @@ void stage_f64(const Stage& st, hipStream_t s) {
     if (st.I > 128) ITE_FAIL(ITE_EINVAL, "MPO stage: more than 128 inputs per column");
     dim3 grid((st.C + SC - 1) / SC, st.G);
     const size_t lds = (size_t)st.I * SC * sizeof(double);
-    hipLaunchKernelGGL(stage_kernel, grid, dim3(SC), lds, s, st);
+    if (st.out_prec == 0) hipLaunchKernelGGL((stage_kernel<0>), grid, dim3(SC), lds, s, st);
+    else if (st.out_prec == 1) hipLaunchKernelGGL((stage_kernel<1>), grid, dim3(SC), lds, s, st);
+    else hipLaunchKernelGGL((stage_kernel<2>), grid, dim3(SC), lds, s, st);
     HIP_CHECK(hipGetLastError());
 }
 

@@ -268,3 +268,76 @@ def test_local_solve_matches_oracle(env, budget):
                                 b.reshape(-1)).reshape(b.shape)
         assert rel_err(got, exact) < 1e-11
         assert res <= 1e-13
+
+
+@pytest.mark.parametrize("prec,bound", [(1, 2e-6), (2, 3e-2)])
+@pytest.mark.parametrize("dims", [(3, 5, 4, 2), (37, 29, 70, 130), (130, 130, 64, 64)])
+def test_heff_apply_low_precision(env, prec, bound, dims):
+    # FP32 / BF16 operands with FP32 accumulation: error of the order of the
+    # operand rounding (2^-24 resp. 2^-9 relative per operand, three roundings)
+    torch, ctx = env
+    Dxl, Dyl, Dxr, Dyr = dims
+    rng = np.random.default_rng(100 + sum(dims))
+    W = ompo.heisenberg_mpo(4, Jz=0.9)
+    Lm, Rm, th = _heff_case(rng, Dxl, Dyl, Dxr, Dyr, 2, W[1], W[2])
+    want = omps.heff_apply(Lm, W[1], W[2], Rm, th)
+    y = torch.zeros((Dxl, 2, 2, Dxr), dtype=torch.float64, device="cuda")
+    ite.ite_debug_heff_apply(ctx, dev(torch, Lm), W[1], W[2], dev(torch, Rm), dev(torch, th), 0.0, 1.0, y, prec=prec)
+    err = rel_err(host(y), want)
+    assert err < bound
+    assert err > 0.0    # the products really ran in the lower precision
+    if Dxl == Dyl and Dxr == Dyr:
+        ite.ite_debug_heff_apply(ctx, dev(torch, Lm), W[1], W[2], dev(torch, Rm), dev(torch, th), 0.3, -0.25, y,
+                                 prec=prec)
+        assert rel_err(host(y), 0.3 * th - 0.25 * want) < bound
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_local_solve_refinement_reaches_fp64(env, prec):
+    # mixed precision refinement: FP64 residuals, low-precision GMRES
+    # corrections; the refined solution meets an FP64 residual target
+    torch, ctx = env
+    rng = np.random.default_rng(19)
+    Lm, Rm, W1, W2 = _symmetric_envs(rng, 8, None, None)
+    h, s = 0.3, -1.0
+    alpha, beta = 1.0 - h * s, h
+    b = rng.standard_normal((Lm.shape[0], 2, 2, Rm.shape[0]))
+    x0 = np.zeros_like(b)
+    op = lambda v: alpha * v + beta * omps.heff_apply(Lm, W1, W2, Rm, v)
+    A = np.column_stack([op(e.reshape(b.shape)).reshape(-1) for e in np.eye(b.size)])
+    exact = np.linalg.solve(A, b.reshape(-1)).reshape(b.shape)
+    x = torch.zeros(b.shape, dtype=torch.float64, device="cuda")
+    mv, res = ite.ite_debug_local_solve(ctx, dev(torch, Lm), W1, W2, dev(torch, Rm), alpha, beta, dev(torch, b),
+                                        dev(torch, x0), x, krylov_dim=8, max_cycles=4, tol=1e-6, precision=prec,
+                                        max_refine=20, tol_refine=1e-12)
+    assert res <= 1e-12
+    assert rel_err(host(x), exact) < 1e-11
+    r = b - op(host(x))
+    assert np.linalg.norm(r) <= 2e-12 * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_local_solve_refinement_fixed_rounds(env, prec):
+    # tol_refine = 0: exactly max_refine corrections of one GMRES(m) cycle each;
+    # products: (max_refine + 1) FP64 residuals + max_refine * m low precision
+    # (the first Krylov vector of a correction is the residual itself)
+    torch, ctx = env
+    rng = np.random.default_rng(23)
+    Lm, Rm, W1, W2 = _symmetric_envs(rng, 4, None, None)
+    h, s = 0.3, -1.0
+    alpha, beta = 1.0 - h * s, h
+    b = rng.standard_normal((Lm.shape[0], 2, 2, Rm.shape[0]))
+    x0 = rng.standard_normal(b.shape)
+    op = lambda v: alpha * v + beta * omps.heff_apply(Lm, W1, W2, Rm, v)
+    res_prev = None
+    for rounds in (1, 2, 3):
+        x = torch.zeros(b.shape, dtype=torch.float64, device="cuda")
+        mv, res = ite.ite_debug_local_solve(ctx, dev(torch, Lm), W1, W2, dev(torch, Rm), alpha, beta,
+                                            dev(torch, b), dev(torch, x0), x, krylov_dim=6, max_cycles=1, tol=0.0,
+                                            precision=prec, max_refine=rounds, tol_refine=0.0)
+        assert mv == (rounds + 1) + rounds * 6
+        r = b - op(host(x))
+        assert abs(np.linalg.norm(r) / np.linalg.norm(b) - res) <= 1e-12 + 1e-9 * res
+        if res_prev is not None:
+            assert res < res_prev
+        res_prev = res

@@ -238,3 +238,32 @@ def test_boundary_error_paths(ctx):
         ite.ite_mps_destroy(psi)
         ite.ite_mpo_destroy(H)
         ite.ite_mpo_destroy(H8)
+
+
+@pytest.mark.parametrize("prec", [ite.PREC_FP32_IR, ite.PREC_BF16_IR])
+def test_mixed_precision_step_matches_oracle(ctx, prec):
+    # FP32 / BF16 inner GMRES refined against FP64 residuals to the same local
+    # target (1e-12) as the FP64 oracle: energies agree to 1e-10 relative
+    L, chi = 10, 32
+    sp = random_spinors(rng_for(0, 2), L, 2)
+    grid = ed.loggrid(0.01, 50.0, 1.5)
+    Wp, Wo = hamiltonians.heisenberg(L), ompo.heisenberg_mpo(L)
+    psi = ite.ite_mps_create(ctx, sp, chi, pad_full=True)
+    H = ite.ite_mpo_load(ctx, Wp)
+    try:
+        opts = _opts(scheme="trap", shift_mode="track", chi_max=chi, cutoff=0.0, krylov_dim=10, max_cycles=20,
+                     tol_loc=1e-5, precision=prec, max_refine=40, tol_refine=1e-12)
+        reps = ite.ite_evolve_grid(ctx, psi, H, grid, opts)
+        out = ite.ite_mps_export(ctx, psi, [2] * L)
+    finally:
+        ite.ite_mps_destroy(psi)
+        ite.ite_mpo_destroy(H)
+    o_out, o_reps = omps.evolve_grid(omps.product_state(sp, chi, pad_full=True), Wo, grid,
+                                     _oracle_opts(scheme="trap", shift_mode="track", chi_max=chi, cutoff=0.0,
+                                                  krylov_dim=10, max_cycles=100, tol_loc=1e-12))
+    for r, orr in zip(reps, o_reps):
+        assert r["matvecs_lo"] > 0
+        assert r["flags"] & ite.FLAG_REFINE_LIMIT == 0
+        assert r["max_res_rel"] <= 1e-12
+        assert abs(r["energy"] - orr.energy) <= 1e-10 * abs(orr.energy)
+    assert 1 - abs(mps_vector(out) @ mps_vector(o_out)) <= 1e-8
