@@ -78,7 +78,9 @@ typedef struct ite_allocator {
 
 /* Options of one implicit step.  ite_default_opts() fills the paper's budget:
  * trapezoid, shift tracking, Krylov dimension 10, one GMRES cycle, one sweep
- * (Appendix D), cutoff 1e-10 (Heisenberg chain section). */
+ * (Appendix D), cutoff 1e-10 (Heisenberg chain section); FP64 products, and
+ * for the mixed precisions one correction (max_refine 1, tol_refine 0), which
+ * spends the same single GMRES cycle on the FP64 residual of x0. */
 typedef struct ite_step_opts {
     int    scheme;       /* ITE_SCHEME_TRAP or ITE_SCHEME_BE */
     int    shift_mode;   /* ITE_SHIFT_FIXED (use `shift`) or ITE_SHIFT_TRACK (s = energy of psi) */
@@ -92,7 +94,9 @@ typedef struct ite_step_opts {
     int    nsweeps;      /* full (left-right-left) sweeps per step, >= 1 */
     int    precision;    /* ITE_PREC_*: inner matvec precision of the local solves */
     int    max_refine;   /* mixed precision: refinement rounds per local solve */
-    double tol_refine;   /* mixed precision: FP64 relative residual target (0: run max_refine rounds) */
+    double tol_refine;   /* mixed precision: FP64 relative residual target; 0: exactly max_refine
+                          * corrections, no FP64 residual after the last one (the reported
+                          * residual is then the inner GMRES estimate) */
 } ite_step_opts;
 
 /* Per-step report. */
@@ -275,7 +279,9 @@ int ite_debug_svd_split(ite_ctx* ctx, int dir, int Dl, int d1, int d2, int Dr,
 
 /* One local solve: GMRES on (alpha I + beta H_eff) x = b with x0 as the
  * initial guess (shapes as ite_debug_heff_apply with Dyl = Dxl, Dyr = Dxr).
- * Writes x, the matvec count and the final relative residual estimate. */
+ * precision, max_refine, tol_refine as in ite_step_opts (mixed precision:
+ * FP64 residuals, FP32 / BF16 GMRES corrections).  Writes x, the matvec count
+ * (all precisions) and the final relative residual estimate. */
 int ite_debug_local_solve(ite_ctx* ctx, int Dl, int Dr, int d1, int d2, int w0, int w1, int w2,
                           const double* L, const double* W1h, const double* W2h, const double* R,
                           double alpha, double beta, const double* b, const double* x0,

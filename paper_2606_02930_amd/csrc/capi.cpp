@@ -114,7 +114,7 @@ void ite_default_opts(ite_step_opts* o) {
     o->tol_loc = 0.0;
     o->nsweeps = 1;
     o->precision = ITE_PREC_FP64;
-    o->max_refine = 3;
+    o->max_refine = 1;
     o->tol_refine = 0.0;
 }
 

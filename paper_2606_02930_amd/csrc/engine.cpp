@@ -505,8 +505,11 @@ static SolveStats gmres(ite_ctx* c, const LocalOp& op, const double* b, double* 
 // precision iterative refinement -- the residual r = b - A x is formed with
 // the FP64 operator, the correction solves A d = r by GMRES whose products use
 // FP32 or BF16 operands with FP32 accumulation, then x += d; max_refine
-// corrections, stopping early once ||r|| <= tol_refine ||b||.  The reported
-// residual is the last FP64 one.
+// corrections, stopping early once ||r|| <= tol_refine ||b||.  With a
+// residual target the reported residual is the last FP64 one; without one
+// (tol_refine = 0: a fixed number of corrections, the analogue of the fixed
+// GMRES budget) the residual after the last correction is not formed and the
+// inner GMRES estimate, scaled by ||r|| / ||b||, is reported instead.
 SolveStats local_solve(ite_ctx* c, const LocalOp& op, const double* b, double* x, int m, int max_cycles,
                        double tol, int precision, int max_refine, double tol_refine) {
     if (precision == ITE_PREC_FP64) return gmres(c, op, b, x, m, max_cycles, tol);
@@ -534,7 +537,7 @@ SolveStats local_solve(ite_ctx* c, const LocalOp& op, const double* b, double* x
         st.res_rel = bnorm > 0 ? rn / bnorm : 0.0;
         if (!(rn > 0.0) || (tol_refine > 0 && rn <= tol_refine * bnorm)) break;
         if (it == max_refine) {
-            if (tol_refine > 0) st.flags |= ITE_FLAG_REFINE_LIMIT;
+            st.flags |= ITE_FLAG_REFINE_LIMIT;
             break;
         }
         fill(d, 0.0, n, c->stream);
@@ -542,6 +545,10 @@ SolveStats local_solve(ite_ctx* c, const LocalOp& op, const double* b, double* x
         st.matvecs_lo += in.matvecs_lo;
         st.flags |= in.flags & ~ITE_FLAG_BUDGET_EXHAUSTED;
         axpby(n, 1.0, d, 1.0, x, x, c->stream);
+        if (tol_refine <= 0 && it + 1 == max_refine) {
+            st.res_rel = in.res_rel * st.res_rel;
+            break;
+        }
     }
     return st;
 }
@@ -867,6 +874,8 @@ void imag_step(ite_mps* psi, const ite_mpo* H, double h, const ite_step_opts& o,
     ITE_REQUIRE(o.tol_loc >= 0.0, "imag_step: tol_loc must be >= 0");
     ITE_REQUIRE(o.nsweeps >= 1, "imag_step: nsweeps must be >= 1");
     ITE_REQUIRE(o.precision >= 0 && o.precision <= 2, "imag_step: unknown precision");
+    ITE_REQUIRE(o.precision == ITE_PREC_FP64 || (o.max_refine >= 1 && o.tol_refine >= 0.0),
+                "imag_step: mixed precision needs max_refine >= 1 and tol_refine >= 0");
     ensure_evolution(psi, H);
 
     Timer tm(c);

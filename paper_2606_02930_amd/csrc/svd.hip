@@ -35,7 +35,7 @@ constexpr int RCOLS = 128;   // columns per rotate block
 
 template <int RB> struct Blk {
     static constexpr int PR = 2 * RB;              // rows per pair
-    static constexpr int NT = PR * PR / 16;        // inner threads: 16 entries each
+    static constexpr int NT = PR * PR / 8;         // inner threads: 8 entries of a PR x PR matrix each
     static constexpr int XS = NT / PR;             // row stride of a thread's entries
     static constexpr int GW = RB == 16 ? 256 : 128;   // columns per gram chunk
 };
@@ -105,61 +105,102 @@ __device__ inline double off_den(double gi, double gj, double kappa_s1) {
     return di * dj + kappa_s1 * (di + dj);
 }
 
+// Round-robin order inside a pair, kept in position space: in every round
+// the rows at positions i and i + RB are rotated together (i < RB), then the
+// rows move one step along the ring 1 -> 2 -> ... -> RB-1 -> PR-1 -> PR-2
+// -> ... -> RB -> 1 (position 0 stays).  After PR - 1 rounds every two rows
+// have met once and every row is back at its starting position.  Keeping
+// the partners at a fixed distance makes every update a 2 x 2 block update
+// with regular LDS addresses.
+template <int PR>
+__device__ inline int ring_next(int pos) {
+    constexpr int H = PR / 2;
+    if (pos == 0) return 0;
+    if (pos < H - 1) return pos + 1;
+    if (pos == H - 1) return PR - 1;
+    if (pos == H) return 1;
+    return pos - 1;
+}
+
+// Local row held at position `pos` in round k (0 <= k < PR - 1).
+template <int PR>
+__device__ inline int ring_row(int pos, int k) {
+    constexpr int H = PR / 2, M = PR - 1;
+    if (pos == 0) return 0;
+    const int rg = pos < H ? pos - 1 : PR - 2 - (pos - H);
+    int r0 = rg - k;
+    if (r0 < 0) r0 += M;
+    return r0 <= H - 2 ? r0 + 1 : H + (PR - 2 - r0);
+}
+
 // One workgroup per pair: sum the chunk partials, then one cyclic sweep of
 // two-sided Jacobi rotations on the PR x PR Gram matrix (each rotation the
 // one of the two diagonalising angles that keeps the larger row at the lower
-// index), then a Newton-Schulz step on the accumulated Q; writes Q and
-// whether any rotation was applied.  sigma1sq: largest row norm squared seen
-// in the previous sweep (0: use this pair's own).
+// local index), then a Newton-Schulz step on the accumulated rotation; writes
+// Q (new row m = sum_k Q[k][m] old row k) and whether any rotation was
+// applied.  sigma1sq: largest row norm squared seen in the previous sweep
+// (0: use this pair's own).
 //
-// The PR/2 disjoint rotations of a round act as new_i = al_i old_i + be_i
-// old_partner(i) on rows and columns, so every entry of G' = J^T G J and of
-// Q' = Q J is an independent combination of at most four old entries: one
-// double-buffered update per round with all LDS loads of a thread in flight
-// together.  Thread t owns column t % PR and rows t / PR + XS u, u < 16.
+// Per round the RB rotation angles are computed by RB lanes; then G' = J G J^T
+// is formed as RB x RB independent 2 x 2 block updates (rows and columns
+// {i, i + RB} x {j, j + RB}) and the accumulated rotation A' = J A as row-pair
+// updates, both written straight to the next round's positions in the other
+// LDS buffer.  A holds the new rows (positions) against the original local
+// rows (columns); Q = A^T.
 template <int RB>
 __global__ __launch_bounds__(Blk<RB>::NT) void inner_kernel(const double* __restrict__ gram, int nchunks, int p,
                                                             int r, int nb, double tol, double kappa,
                                                             double sigma1sq, double* __restrict__ rot,
                                                             int* __restrict__ rotated,
                                                             double* __restrict__ sweep_off) {
-    constexpr int PR = Blk<RB>::PR, NT = Blk<RB>::NT, XS = Blk<RB>::XS;
+    constexpr int PR = Blk<RB>::PR, NT = Blk<RB>::NT, XS = Blk<RB>::XS, EPT = PR / XS;
+    constexpr int QPT = RB * RB / NT, IS = NT / RB;     // 2 x 2 blocks per thread, their row stride
+    constexpr int JPT = RB * PR / NT, JS = NT / PR;     // row-pair entries of A per thread, their stride
+    constexpr int NW = NT / 64, NTL = PR / 16;          // wavefronts, 16 x 16 tiles per side
+    static_assert(QPT * NT == RB * RB && JPT * NT == RB * PR && EPT * NT == PR * PR, "thread layout");
+    static_assert((NTL * NTL) % NW == 0, "tiles per wavefront");
     __shared__ double Gb[2][PR][PR + 1];
-    __shared__ double Qb[2][PR][PR + 1];
-    __shared__ double al[PR], be[PR];
-    __shared__ int part[PR];
-    __shared__ double red[NT / 64];
-    // one slot per round parity: a wave that skips a round without rotations
-    // must not overwrite the flag another wave is still reading
-    __shared__ int flag[2];
+    __shared__ double Ab[2][PR][PR + 1];
+    __shared__ double cc[RB], ss[RB];
+    __shared__ double red[NW];
+    __shared__ int anyrot;
     const int P = blockIdx.x;
     const int t = threadIdx.x;
     const int y = t % PR, xh = t / PR;
     const double* src = gram + (long)P * nchunks * (PR * PR);
     {
-        // chunk-outer so that the 16 loads of a chunk are in flight together
-        double s[16];
+        // two chunks per step so that 2 EPT loads are in flight together
+        double s[EPT];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) s[u] = 0.0;
-        for (int c = 0; c < nchunks; ++c) {
+        for (int u = 0; u < EPT; ++u) s[u] = 0.0;
+        int c = 0;
+        for (; c + 1 < nchunks; c += 2) {
             const double* g = src + (long)c * PR * PR + y;
-            double v[16];
+            double v[2][EPT];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) v[u] = g[(xh + XS * u) * PR];
+            for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int u = 0; u < 16; ++u) s[u] += v[u];
+                for (int u = 0; u < EPT; ++u) v[h][u] = g[(long)h * PR * PR + (xh + XS * u) * PR];
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) s[u] += v[0][u] + v[1][u];
+        }
+        if (c < nchunks) {
+            const double* g = src + (long)c * PR * PR + y;
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) s[u] += g[(xh + XS * u) * PR];
         }
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
+        for (int u = 0; u < EPT; ++u) {
             const int x = xh + XS * u;
             Gb[0][x][y] = s[u];
-            Qb[0][x][y] = (x == y) ? 1.0 : 0.0;
+            Ab[0][x][y] = (x == y) ? 1.0 : 0.0;
         }
     }
+    if (t == 0) anyrot = 0;
     __syncthreads();
     // symmetrise (the two triangles come from different MFMA tiles)
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
+    for (int u = 0; u < EPT; ++u) {
         const int x = xh + XS * u;
         if (x < y) {
             const double v = 0.5 * (Gb[0][x][y] + Gb[0][y][x]);
@@ -176,7 +217,7 @@ __global__ __launch_bounds__(Blk<RB>::NT) void inner_kernel(const double* __rest
     {
         const double gyy = Gb[0][y][y];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
+        for (int u = 0; u < EPT; ++u) {
             const int x = xh + XS * u;
             if (x < y) {
                 const double den = off_den(Gb[0][x][x], gyy, kappa_s1);
@@ -188,7 +229,7 @@ __global__ __launch_bounds__(Blk<RB>::NT) void inner_kernel(const double* __rest
     if ((t & 63) == 0) red[t >> 6] = off;
     __syncthreads();
     off = red[0];
-    for (int i = 1; i < NT / 64; ++i) off = fmax(off, red[i]);
+    for (int i = 1; i < NW; ++i) off = fmax(off, red[i]);
     if (t == 0) {
         atomic_max_pos(sweep_off, off);
         atomic_max_pos(sweep_off + 1, gmax_local);
@@ -197,163 +238,193 @@ __global__ __launch_bounds__(Blk<RB>::NT) void inner_kernel(const double* __rest
         if (t == 0) rotated[P] = 0;
         return;
     }
+    // fixed per thread: the column pair j of its 2 x 2 blocks, the column l of
+    // its entries of A
+    const int jq = t % RB;
+    const int pj0 = ring_next<PR>(jq), pj1 = ring_next<PR>(jq + RB);
+    const int la = t % PR;
     int cur = 0;
-    bool swept = false;
-    for (int rr = 0; rr < PR - 1; ++rr) {
-        if (t < 64) {
-            bool mine = false;
-            if (t < PR / 2) {
-                const int a0 = t == 0 ? 0 : ((t - 1 + rr) % (PR - 1)) + 1;
-                const int b0 = ((PR - 1 - t - 1 + rr) % (PR - 1)) + 1;
-                const int a = a0 < b0 ? a0 : b0, b = a0 < b0 ? b0 : a0;
-                const double gaa = Gb[cur][a][a], gbb = Gb[cur][b][b], gab = Gb[cur][a][b];
-                double c = 1.0, s = 0.0;
-                if (gab != 0.0 && fabs(gab) > 0.25 * tol * off_den(gaa, gbb, kappa_s1)) {
-                    const double tau = (gbb - gaa) / (2.0 * gab);
-                    double tt;
-                    if (fabs(tau) > 1e150) tt = 0.5 / tau;
-                    else tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                    c = 1.0 / sqrt(1.0 + tt * tt);
-                    s = tt * c;
-                    // the other diagonalising angle if this one leaves the
-                    // smaller row at the lower index
-                    const double naa = c * c * gaa - 2.0 * c * s * gab + s * s * gbb;
-                    const double nbb = s * s * gaa + 2.0 * c * s * gab + c * c * gbb;
-                    if (naa < nbb) {
-                        const double c0 = c;
-                        c = -s;
-                        s = c0;
-                    }
-                    mine = true;
+    for (int k = 0; k < PR - 1; ++k) {
+        if (t < RB) {
+            // Jacobi angle of the pair (a, b) = positions (i, i + RB):
+            // tan(theta) = sign(x) y / (|x| + hypot(x, y)), x = g_bb - g_aa,
+            // y = 2 g_ab; new_a = c a - s b, new_b = s a + c b
+            const int i = t;
+            const double gaa = Gb[cur][i][i], gbb = Gb[cur][i + RB][i + RB], gab = Gb[cur][i][i + RB];
+            double c = 1.0, s = 0.0;
+            if (gab != 0.0) {
+                const double x = gbb - gaa, yy = 2.0 * gab;
+                const double tt = (x >= 0.0 ? yy : -yy) / (fabs(x) + sqrt(x * x + yy * yy));
+                c = rsqrt(1.0 + tt * tt);
+                s = tt * c;
+                // take the other diagonalising angle if this one leaves the
+                // larger row at the higher local index
+                const double naa = c * c * gaa - 2.0 * c * s * gab + s * s * gbb;
+                const double nbb = s * s * gaa + 2.0 * c * s * gab + c * c * gbb;
+                const bool a_low = ring_row<PR>(i, k) < ring_row<PR>(i + RB, k);
+                if (a_low ? (naa < nbb) : (naa > nbb)) {
+                    const double c0 = c;
+                    c = -s;
+                    s = c0;
                 }
-                // new_a = c a - s b, new_b = s a + c b
-                al[a] = c;
-                be[a] = -s;
-                al[b] = c;
-                be[b] = s;
-                part[a] = b;
-                part[b] = a;
+                anyrot = 1;
             }
-            const bool any = __any(mine);
-            if (t == 0) flag[rr & 1] = any ? 1 : 0;
+            cc[i] = c;
+            ss[i] = s;
         }
         __syncthreads();
-        if (!flag[rr & 1]) continue;   // uniform: every thread reads the flag after the barrier
-        swept = true;
         const int nxt = cur ^ 1;
-        const int yp = part[y];
-        const double ay = al[y], by = be[y];
-        double gv[16], qv[16];
+        {
+            const double cj = cc[jq], sj = ss[jq];
+            double nv[QPT][4];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int x = xh + XS * u;
-            const int xp = part[x];
-            const double ax = al[x], bx = be[x];
-            gv[u] = ax * (ay * Gb[cur][x][y] + by * Gb[cur][x][yp]) + bx * (ay * Gb[cur][xp][y] + by * Gb[cur][xp][yp]);
-            qv[u] = ay * Qb[cur][x][y] + by * Qb[cur][x][yp];
-        }
+            for (int u = 0; u < QPT; ++u) {
+                const int i = t / RB + IS * u;
+                const double ci = cc[i], si = ss[i];
+                const double g00 = Gb[cur][i][jq], g01 = Gb[cur][i][jq + RB];
+                const double g10 = Gb[cur][i + RB][jq], g11 = Gb[cur][i + RB][jq + RB];
+                const double t00 = ci * g00 - si * g10, t01 = ci * g01 - si * g11;
+                const double t10 = si * g00 + ci * g10, t11 = si * g01 + ci * g11;
+                nv[u][0] = t00 * cj - t01 * sj;
+                nv[u][1] = t00 * sj + t01 * cj;
+                nv[u][2] = t10 * cj - t11 * sj;
+                nv[u][3] = t10 * sj + t11 * cj;
+            }
+            double na[JPT][2];
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int x = xh + XS * u;
-            Gb[nxt][x][y] = gv[u];
-            Qb[nxt][x][y] = qv[u];
+            for (int u = 0; u < JPT; ++u) {
+                const int i = t / PR + JS * u;
+                const double ci = cc[i], si = ss[i];
+                const double a0 = Ab[cur][i][la], a1 = Ab[cur][i + RB][la];
+                na[u][0] = ci * a0 - si * a1;
+                na[u][1] = si * a0 + ci * a1;
+            }
+#pragma unroll
+            for (int u = 0; u < QPT; ++u) {
+                const int i = t / RB + IS * u;
+                const int pi0 = ring_next<PR>(i), pi1 = ring_next<PR>(i + RB);
+                Gb[nxt][pi0][pj0] = nv[u][0];
+                Gb[nxt][pi0][pj1] = nv[u][1];
+                Gb[nxt][pi1][pj0] = nv[u][2];
+                Gb[nxt][pi1][pj1] = nv[u][3];
+            }
+#pragma unroll
+            for (int u = 0; u < JPT; ++u) {
+                const int i = t / PR + JS * u;
+                Ab[nxt][ring_next<PR>(i)][la] = na[u][0];
+                Ab[nxt][ring_next<PR>(i + RB)][la] = na[u][1];
+            }
         }
         __syncthreads();
         cur = nxt;
     }
-    // One Newton-Schulz step towards the nearest orthogonal matrix,
-    // Q <- Q (3 I - Q^T Q) / 2: the product of Givens rotations is orthogonal
-    // only to a few hundred ulps, and every row meets such a rotation in each
-    // round of every sweep, so the defect would otherwise accumulate.
-    double (*Q)[PR + 1] = Qb[cur];
+    // Every row is back at its starting position.  One Newton-Schulz step
+    // towards the nearest orthogonal matrix, A <- (3 I - A A^T) A / 2, with
+    // FP64 MFMA: the product of Givens rotations is orthogonal only to a few
+    // hundred ulps, and every row meets such a rotation in each round of every
+    // sweep, so the defect would otherwise accumulate.
+    double (*A)[PR + 1] = Ab[cur];
     double (*S)[PR + 1] = Gb[cur];
     double (*T)[PR + 1] = Gb[cur ^ 1];
-    {
-        double acc[16];
+    const int lane = t & 63, w = t >> 6;
+    const int l16 = lane & 15, kg = lane >> 4;
+    constexpr int TPW = NTL * NTL / NW;
+    // S = A A^T
 #pragma unroll
-        for (int u = 0; u < 16; ++u) acc[u] = 0.0;
-        for (int k = 0; k < PR; ++k) {
-            const double qky = Q[k][y];
+    for (int i = 0; i < TPW; ++i) {
+        const int tile = w + NW * i;
+        const int tm = tile / NTL, tn = tile % NTL;
+        d4_t acc = {0, 0, 0, 0};
 #pragma unroll
-            for (int u = 0; u < 16; ++u) acc[u] += Q[k][xh + XS * u] * qky;
-        }
-        __syncthreads();
+        for (int k0 = 0; k0 < PR; k0 += 4)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[tm * 16 + l16][k0 + kg], A[tn * 16 + l16][k0 + kg], acc,
+                                                       0, 0, 0);
 #pragma unroll
-        for (int u = 0; u < 16; ++u) S[xh + XS * u][y] = acc[u];
-        __syncthreads();
+        for (int rr = 0; rr < 4; ++rr) S[tm * 16 + 4 * rr + kg][tn * 16 + l16] = acc[rr];
+    }
+    __syncthreads();
+    // A_new = 1.5 A - 0.5 S A, stored transposed: T[k][m] = A_new[m][k] = Q[k][m]
 #pragma unroll
-        for (int u = 0; u < 16; ++u) acc[u] = 0.0;
-        for (int k = 0; k < PR; ++k) {
-            const double sky = S[k][y];
+    for (int i = 0; i < TPW; ++i) {
+        const int tile = w + NW * i;
+        const int tm = tile / NTL, tn = tile % NTL;
+        d4_t acc = {0, 0, 0, 0};
 #pragma unroll
-            for (int u = 0; u < 16; ++u) acc[u] += Q[xh + XS * u][k] * sky;
-        }
+        for (int k0 = 0; k0 < PR; k0 += 4)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(S[tm * 16 + l16][k0 + kg], A[k0 + kg][tn * 16 + l16], acc,
+                                                       0, 0, 0);
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int x = xh + XS * u;
-            T[x][y] = 1.5 * Q[x][y] - 0.5 * acc[u];
+        for (int rr = 0; rr < 4; ++rr) {
+            const int m = tm * 16 + 4 * rr + kg, kk = tn * 16 + l16;
+            T[kk][m] = 1.5 * A[m][kk] - 0.5 * acc[rr];
         }
     }
     __syncthreads();
     double* out = rot + (long)P * PR * PR;
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
+    for (int u = 0; u < EPT; ++u) {
         const int x = xh + XS * u;
         out[x * PR + y] = T[x][y];
     }
-    if (t == 0) rotated[P] = swept ? 1 : 0;
+    if (t == 0) rotated[P] = anyrot;
 }
 
-// Z_pair <- Q^T Z_pair on a chunk of RCOLS columns with FP64 MFMA: the pair's
-// rows of the chunk and Q are staged in LDS; the (PR/16) x (RCOLS/16) output
-// tiles are dealt round-robin to the four wavefronts.
+// Z_pair <- Q^T Z_pair with FP64 MFMA on a chunk of RCOLS columns: Q is staged
+// in LDS; each wavefront streams its own 32 columns of the pair's rows from
+// memory straight into MFMA operands and writes the rotated values back
+// (wavefronts own disjoint columns, so the update is in place).
 template <int RB>
 __global__ __launch_bounds__(256) void rotate_kernel(double* __restrict__ Z, int p, int ld, int r, int nb,
                                                      const double* __restrict__ rot,
                                                      const int* __restrict__ rotated) {
     constexpr int PR = Blk<RB>::PR;
-    constexpr int NTR = PR / 16, NTC = RCOLS / 16, TPW = NTR * NTC / 4;
+    constexpr int NTM = PR / 16, KS = PR / 4, CT = RCOLS / 64;   // row tiles, k steps, column tiles per wave
     const int P = blockIdx.y;
     if (!rotated[P]) return;
     __shared__ double Qs[PR][PR + 1];        // Q[k][m]
-    __shared__ double Zs[PR][RCOLS + 1];     // pair rows of the chunk
     const double* src = rot + (long)P * PR * PR;
     const int t = threadIdx.x;
     for (int e = t; e < PR * PR; e += 256) Qs[e / PR][e % PR] = src[e];
-    const int c0 = blockIdx.x * RCOLS;
-    for (int e = t; e < PR * RCOLS; e += 256) {
-        const int lr = e / RCOLS, cc = e % RCOLS;
-        const int c = c0 + cc;
-        const int row = pair_row<RB>(P, lr, r, nb);
-        Zs[lr][cc] = (row < p && c < ld) ? Z[(long)row * ld + c] : 0.0;
-    }
-    __syncthreads();
     const int lane = t & 63, w = t >> 6;
     const int l16 = lane & 15, kg = lane >> 4;
-    d4_t acc[TPW];
+    const int cw = blockIdx.x * RCOLS + w * (16 * CT);
+    double b[CT][KS];
 #pragma unroll
-    for (int i = 0; i < TPW; ++i) acc[i] = d4_t{0, 0, 0, 0};
+    for (int ks = 0; ks < KS; ++ks) {
+        const int row = pair_row<RB>(P, 4 * ks + kg, r, nb);
 #pragma unroll
-    for (int k0 = 0; k0 < PR; k0 += 4) {
-        const int k = k0 + kg;
+        for (int ct = 0; ct < CT; ++ct) {
+            const int c = cw + ct * 16 + l16;
+            b[ct][ks] = (row < p && c < ld) ? Z[(long)row * ld + c] : 0.0;
+        }
+    }
+    __syncthreads();
+    d4_t acc[CT][NTM];
 #pragma unroll
-        for (int i = 0; i < TPW; ++i) {
-            const int tile = w + 4 * i;
-            const int tm = tile % NTR, tn = tile / NTR;
-            acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(Qs[k][tm * 16 + l16], Zs[k][tn * 16 + l16], acc[i], 0, 0,
-                                                          0);
+    for (int ct = 0; ct < CT; ++ct)
+#pragma unroll
+        for (int tm = 0; tm < NTM; ++tm) acc[ct][tm] = d4_t{0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+#pragma unroll
+        for (int tm = 0; tm < NTM; ++tm) {
+            const double a = Qs[4 * ks + kg][tm * 16 + l16];
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct)
+                acc[ct][tm] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[ct][ks], acc[ct][tm], 0, 0, 0);
         }
     }
 #pragma unroll
-    for (int i = 0; i < TPW; ++i) {
-        const int tile = w + 4 * i;
-        const int tm = tile % NTR, tn = tile / NTR;
-        const int c = c0 + tn * 16 + l16;
+    for (int tm = 0; tm < NTM; ++tm) {
 #pragma unroll
         for (int rr = 0; rr < 4; ++rr) {
             const int m = tm * 16 + 4 * rr + kg;      // FP64 MFMA accumulator row
             const int row = pair_row<RB>(P, m, r, nb);
-            if (row < p && c < ld) Z[(long)row * ld + c] = acc[i][rr];
+#pragma unroll
+            for (int ct = 0; ct < CT; ++ct) {
+                const int c = cw + ct * 16 + l16;
+                if (row < p && c < ld) Z[(long)row * ld + c] = acc[ct][tm][rr];
+            }
         }
     }
 }

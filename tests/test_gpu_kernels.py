@@ -318,9 +318,10 @@ def test_local_solve_refinement_reaches_fp64(env, prec):
 
 @pytest.mark.parametrize("prec", [1, 2])
 def test_local_solve_refinement_fixed_rounds(env, prec):
-    # tol_refine = 0: exactly max_refine corrections of one GMRES(m) cycle each;
-    # products: (max_refine + 1) FP64 residuals + max_refine * m low precision
-    # (the first Krylov vector of a correction is the residual itself)
+    # tol_refine = 0: exactly max_refine corrections of one GMRES(m) cycle
+    # each; products: one FP64 residual before each correction and m - 1 + 1
+    # = m low-precision products per correction (its first Krylov vector is
+    # the residual itself); no FP64 residual after the last correction
     torch, ctx = env
     rng = np.random.default_rng(23)
     Lm, Rm, W1, W2 = _symmetric_envs(rng, 4, None, None)
@@ -329,15 +330,18 @@ def test_local_solve_refinement_fixed_rounds(env, prec):
     b = rng.standard_normal((Lm.shape[0], 2, 2, Rm.shape[0]))
     x0 = rng.standard_normal(b.shape)
     op = lambda v: alpha * v + beta * omps.heff_apply(Lm, W1, W2, Rm, v)
-    res_prev = None
+    true_prev = None
     for rounds in (1, 2, 3):
         x = torch.zeros(b.shape, dtype=torch.float64, device="cuda")
         mv, res = ite.ite_debug_local_solve(ctx, dev(torch, Lm), W1, W2, dev(torch, Rm), alpha, beta,
                                             dev(torch, b), dev(torch, x0), x, krylov_dim=6, max_cycles=1, tol=0.0,
                                             precision=prec, max_refine=rounds, tol_refine=0.0)
-        assert mv == (rounds + 1) + rounds * 6
-        r = b - op(host(x))
-        assert abs(np.linalg.norm(r) / np.linalg.norm(b) - res) <= 1e-12 + 1e-9 * res
-        if res_prev is not None:
-            assert res < res_prev
-        res_prev = res
+        assert mv == rounds + rounds * 6
+        true = np.linalg.norm(b - op(host(x))) / np.linalg.norm(b)
+        if prec == 1 and rounds == 1:
+            # the estimate is the FP32 system's residual: close to the true one
+            # while it is far above the FP32 rounding level
+            assert abs(res - true) <= 0.1 * true
+        if true_prev is not None:
+            assert true < true_prev
+        true_prev = true
