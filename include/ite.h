@@ -65,6 +65,7 @@ enum { ITE_PREC_FP64 = 0, ITE_PREC_FP32_IR = 1, ITE_PREC_BF16_IR = 2 };
 typedef struct ite_ctx ite_ctx;
 typedef struct ite_mpo ite_mpo;
 typedef struct ite_mps ite_mps;
+typedef struct ite_server ite_server;
 
 /* Device allocator supplied by the caller (e.g. a framework's caching
  * allocator).  alloc returns device memory of at least `bytes` bytes usable on
@@ -232,6 +233,89 @@ int ite_loggrid(double tau0, double tau1, double ratio, double* out, int cap, in
 /* Panel grid (Method): P panels with endpoints {0, tau_max / 2^(P-j)},
  * j = 1..P, and n uniform steps per panel: P*n + 1 points. */
 int ite_panel_grid(double tau_max, int P, int n, double* out, int cap, int* npts);
+
+/* ---- serving: many independent evolutions at once ----------------------
+ * A request is one whole evolution as ite_evolve_loggrid runs it: a product
+ * state (ite_mps_create), a Hamiltonian (ite_mpo_load), the geometric grid
+ * tau0, tau1, ratio and the step options (Method; Appendix D for the
+ * budget).  Requests are independent, as the METTS evolutions of the impurity
+ * application are.  The server keeps `workers` host threads, each with its
+ * own context on its own non-blocking HIP stream of device `device`, so the
+ * steps of different requests run on the GPU at the same time.  Continuous
+ * batching: a request waits in FIFO order until the summed footprint
+ * estimate of the active requests plus its own fits `mem_cap` bytes and a
+ * worker has fewer than `max_active` active requests; it then stays on that
+ * worker, which advances its active requests one time step each in turn, and
+ * leaves as soon as its grid is done, making room for the next.  All device
+ * memory comes from a pool owned by the server (no hipFree while the server
+ * runs).  A request's arithmetic does not depend on what else is running:
+ * its results are bitwise those of the same evolution run alone. */
+
+typedef struct ite_server_opts {
+    int    device;
+    int    workers;      /* host threads = concurrent device streams, 1..64 */
+    int    max_active;   /* active requests per worker, >= 1 */
+    double mem_cap;      /* bytes; admission cap on the summed footprint estimates */
+} ite_server_opts;
+
+typedef struct ite_request {
+    int L;
+    const int* d;                    /* [L] local dimensions */
+    const int* w;                    /* [L+1] MPO bond dimensions */
+    const double* const* W;          /* [L] MPO tensors as ite_mpo_load (host) */
+    const double* const* spinors;    /* [L] product state as ite_mps_create (host) */
+    int chi_max;
+    int pad_full;
+    double tau0, tau1, ratio;        /* geometric grid as ite_evolve_loggrid */
+    ite_step_opts opts;
+} ite_request;
+
+/* Request states */
+#define ITE_REQ_PENDING  0
+#define ITE_REQ_ACTIVE   1
+#define ITE_REQ_DONE     2
+#define ITE_REQ_FAILED   3
+
+typedef struct ite_request_info {
+    int status;          /* ITE_REQ_* */
+    int error;           /* status code of the failure (ITE_REQ_FAILED) */
+    int worker;          /* worker that ran it (-1 before admission) */
+    int n_steps;         /* steps done so far */
+    int n_grid;          /* steps of its grid */
+    double tau, energy;  /* after the last step done */
+    double footprint;    /* bytes, the admission estimate */
+    double t_submit, t_admit, t_done;   /* seconds on the server clock (0 = not yet) */
+} ite_request_info;
+
+/* Create / destroy a server.  Destroy waits for the running steps, drops
+ * pending requests and frees everything.  Errors: EINVAL, EDEVICE, ENOMEM. */
+int ite_server_create(const ite_server_opts* o, ite_server** out);
+int ite_server_destroy(ite_server* srv);
+/* Queue a request (all arrays are copied before return) and return its id.
+ * EINVAL for inconsistent inputs; ENOMEM when its footprint alone exceeds
+ * mem_cap. */
+int ite_server_submit(ite_server* srv, const ite_request* req, long long* id);
+/* Wait until request `id` is DONE or FAILED, at most timeout_s seconds
+ * (< 0: no limit); fills *info either way.  Returns OK when finished,
+ * ESTATE on time-out, EINVAL for an unknown id. */
+int ite_server_wait(ite_server* srv, long long id, double timeout_s, ite_request_info* info);
+/* Current state of a request without waiting. */
+int ite_server_info(ite_server* srv, long long id, ite_request_info* info);
+/* Per-step reports of a finished request: up to cap reports to out, their
+ * number to *n. */
+int ite_server_reports(ite_server* srv, long long id, ite_step_report* out, int cap, int* n);
+/* Final state of a finished request: bond dimensions to chi [L+1] and, when A
+ * is not NULL, the site tensors to A[i] (host, chi[i] d[i] chi[i+1] each). */
+int ite_server_state(ite_server* srv, long long id, int* chi, double* const* A);
+/* Forget a finished request (its reports and state). */
+int ite_server_release(ite_server* srv, long long id);
+/* Server clock (seconds since creation) and the text of the last error of
+ * a failed request (empty when none). */
+double ite_server_clock(const ite_server* srv);
+int ite_server_error(ite_server* srv, long long id, char* buf, int cap);
+/* Footprint estimate (bytes) the server uses for admission: MPS and working
+ * copy, environments, Krylov basis and the largest split workspace. */
+double ite_request_footprint(int L, const int* d, const int* w, int chi_max, int krylov_dim);
 
 /* ---- building blocks exposed for parity tests ---------------------------
  * Each operates on caller device memory on the context's stream and returns

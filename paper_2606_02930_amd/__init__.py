@@ -57,6 +57,29 @@ class ite_step_report(C.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class ite_server_opts(C.Structure):
+    _fields_ = [("device", C.c_int), ("workers", C.c_int), ("max_active", C.c_int), ("mem_cap", C.c_double)]
+
+
+class ite_request(C.Structure):
+    _fields_ = [("L", C.c_int), ("d", C.POINTER(C.c_int)), ("w", C.POINTER(C.c_int)),
+                ("W", C.POINTER(C.POINTER(C.c_double))), ("spinors", C.POINTER(C.POINTER(C.c_double))),
+                ("chi_max", C.c_int), ("pad_full", C.c_int),
+                ("tau0", C.c_double), ("tau1", C.c_double), ("ratio", C.c_double),
+                ("opts", ite_step_opts)]
+
+
+class ite_request_info(C.Structure):
+    _fields_ = [("status", C.c_int), ("error", C.c_int), ("worker", C.c_int), ("n_steps", C.c_int),
+                ("n_grid", C.c_int), ("tau", C.c_double), ("energy", C.c_double), ("footprint", C.c_double),
+                ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+REQ_PENDING, REQ_ACTIVE, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
+
 _P = C.c_void_p
 _I = C.c_int
 _D = C.c_double
@@ -99,6 +122,17 @@ _SIGNATURES = {
     "ite_debug_local_solve": (_I, [_P, _I, _I, _I, _I, _I, _I, _I, _P, _PD, _PD, _P, _D, _D, _P, _P,
                                    _I, _I, _D, _I, _I, _D, _P, _PI, _PD]),
     "ite_debug_mfma_probe": (_I, [_P, _I, _PD]),
+    "ite_server_create": (_I, [C.POINTER(ite_server_opts), C.POINTER(_P)]),
+    "ite_server_destroy": (_I, [_P]),
+    "ite_server_submit": (_I, [_P, C.POINTER(ite_request), C.POINTER(C.c_longlong)]),
+    "ite_server_wait": (_I, [_P, C.c_longlong, _D, C.POINTER(ite_request_info)]),
+    "ite_server_info": (_I, [_P, C.c_longlong, C.POINTER(ite_request_info)]),
+    "ite_server_reports": (_I, [_P, C.c_longlong, C.POINTER(ite_step_report), _I, _PI]),
+    "ite_server_state": (_I, [_P, C.c_longlong, _PI, _PPD]),
+    "ite_server_release": (_I, [_P, C.c_longlong]),
+    "ite_server_clock": (_D, [_P]),
+    "ite_server_error": (_I, [_P, C.c_longlong, C.c_char_p, _I]),
+    "ite_request_footprint": (_D, [_I, _PI, _PI, _I, _I]),
 }
 
 _lib = None
@@ -431,3 +465,87 @@ def ite_debug_mfma_probe(ctx: Ctx, kind: int = 0) -> np.ndarray:
     out = np.zeros(256)
     _check(load_library().ite_debug_mfma_probe(ctx.handle, int(kind), _dptr(out)), ctx.handle)
     return out
+
+
+# ---------------------------------------------------------------------------
+# Serving: many independent evolutions on one device
+# ---------------------------------------------------------------------------
+
+def ite_server_create(device: int = 0, workers: int = 4, max_active: int = 2, mem_cap: float = 200e9) -> int:
+    """A server with ``workers`` host threads / streams; ``mem_cap`` bytes of
+    admission budget."""
+    o = ite_server_opts(int(device), int(workers), int(max_active), float(mem_cap))
+    h = _P()
+    _check(load_library().ite_server_create(C.byref(o), C.byref(h)))
+    return h.value
+
+
+def ite_server_destroy(srv: int) -> None:
+    _check(load_library().ite_server_destroy(srv))
+
+
+def ite_server_submit(srv: int, Ws, spinors, chi_max: int, tau0: float, tau1: float, ratio: float,
+                      opts: ite_step_opts, pad_full: bool = False) -> int:
+    """Queue one evolution (MPO tensors Ws as ite_mpo_load, product state as
+    ite_mps_create, geometric grid as ite_evolve_loggrid); returns its id."""
+    Ws = [np.ascontiguousarray(W, dtype=np.float64) for W in Ws]
+    sp = [np.ascontiguousarray(x, dtype=np.float64) for x in spinors]
+    L = len(Ws)
+    d = _ints([W.shape[2] for W in Ws])
+    w = _ints([Ws[0].shape[0]] + [W.shape[1] for W in Ws])
+    req = ite_request(L, d, w, _ptr_array(Ws), _ptr_array(sp), int(chi_max), int(bool(pad_full)),
+                      float(tau0), float(tau1), float(ratio), opts)
+    rid = C.c_longlong()
+    _check(load_library().ite_server_submit(srv, C.byref(req), C.byref(rid)))
+    return rid.value
+
+
+def ite_server_wait(srv: int, rid: int, timeout: float = -1.0) -> dict:
+    info = ite_request_info()
+    rc = load_library().ite_server_wait(srv, C.c_longlong(rid), float(timeout), C.byref(info))
+    if rc not in (ITE_OK, ITE_ESTATE):
+        _check(rc)
+    return info.as_dict()
+
+
+def ite_server_info(srv: int, rid: int) -> dict:
+    info = ite_request_info()
+    _check(load_library().ite_server_info(srv, C.c_longlong(rid), C.byref(info)))
+    return info.as_dict()
+
+
+def ite_server_reports(srv: int, rid: int) -> list[dict]:
+    lib = load_library()
+    n = C.c_int()
+    _check(lib.ite_server_reports(srv, C.c_longlong(rid), None, 0, C.byref(n)))
+    out = (ite_step_report * max(1, n.value))()
+    _check(lib.ite_server_reports(srv, C.c_longlong(rid), out, n.value, C.byref(n)))
+    return [out[i].as_dict() for i in range(n.value)]
+
+
+def ite_server_state(srv: int, rid: int, d) -> list[np.ndarray]:
+    L = len(d)
+    chi = (C.c_int * (L + 1))()
+    lib = load_library()
+    _check(lib.ite_server_state(srv, C.c_longlong(rid), chi, None))
+    out = [np.empty((chi[i], d[i], chi[i + 1])) for i in range(L)]
+    _check(lib.ite_server_state(srv, C.c_longlong(rid), chi, _ptr_array(out)))
+    return out
+
+
+def ite_server_release(srv: int, rid: int) -> None:
+    _check(load_library().ite_server_release(srv, C.c_longlong(rid)))
+
+
+def ite_server_clock(srv: int) -> float:
+    return load_library().ite_server_clock(srv)
+
+
+def ite_server_error(srv: int, rid: int) -> str:
+    buf = C.create_string_buffer(1024)
+    _check(load_library().ite_server_error(srv, C.c_longlong(rid), buf, 1024))
+    return buf.value.decode()
+
+
+def ite_request_footprint(d, w, chi_max: int, krylov_dim: int = 10) -> float:
+    return load_library().ite_request_footprint(len(d), _ints(d), _ints(w), int(chi_max), int(krylov_dim))

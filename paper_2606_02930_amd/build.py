@@ -24,6 +24,7 @@ FLAGS = [
     "-O3",
     "-std=c++17",
     "-fPIC",
+    "-pthread",
     "-Wall",
     "-Wno-unused-result",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -31,7 +32,7 @@ FLAGS = [
     f"-I{CSRC}",
 ]
 
-SOURCES = ["gemm.hip", "vec.hip", "svd.hip", "engine.cpp", "capi.cpp"]
+SOURCES = ["gemm.hip", "vec.hip", "svd.hip", "engine.cpp", "capi.cpp", "server.cpp"]
 
 
 def _compile(src: str, build_dir: str) -> str:
@@ -49,7 +50,7 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(lambda s: _compile(s, build_dir), SOURCES))
     tmp = OUT + ".tmp"
-    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stderr}")

@@ -1,0 +1,139 @@
+"""GPU tests of the serving loop (continuous batching of independent
+evolutions), through the C ABI.
+
+* Every request's per-step energies and final tensors are bitwise those of
+  the same evolution run alone with the plain entry points (FP64 and mixed
+  precision requests, Heisenberg and Anderson-impurity chains, several
+  workers and several active requests per worker).
+* Admission by footprint: with room for one request only they run one after
+  the other.
+* Continuous batching: a short request that arrives behind a long one
+  finishes first when a second worker is free.
+* A request that fails on the device is reported as failed with its message
+  and leaves the server usable.
+"""
+import numpy as np
+import pytest
+
+import paper_2606_02930_amd as ite
+from paper_2606_02930_amd import hamiltonians
+from workload import rng_for, random_spinors, aim_bath
+from tests.gpu_util import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _requests():
+    reqs = []
+    for k, (L, chi, tau1, prec) in enumerate([(6, 8, 1.0, 0), (8, 16, 2.0, 0), (10, 16, 4.0, 0),
+                                              (8, 8, 3.0, 1), (10, 12, 1.5, 2), (7, 16, 2.5, 0)]):
+        sp = random_spinors(rng_for(5, k), L, 2)
+        o = dict(chi_max=chi, cutoff=1e-10, precision=prec)
+        reqs.append((hamiltonians.heisenberg(L), sp, chi, 0.01, tau1, 1.3, o))
+    eps, V = aim_bath(3, 0.1)
+    sp = random_spinors(rng_for(5, 99), 4, 4)
+    reqs.append((hamiltonians.anderson_star(4.0, -2.0, eps, V), sp, 16, 0.01, 2.0, 1.3, dict(chi_max=16, cutoff=1e-9)))
+    return reqs
+
+
+def _alone(ctx, W, sp, chi, tau0, tau1, ratio, o):
+    psi = ite.ite_mps_create(ctx, sp, chi)
+    H = ite.ite_mpo_load(ctx, W)
+    try:
+        reps = ite.ite_evolve_loggrid(ctx, psi, H, tau0, tau1, ratio, ite.ite_default_opts(**o))
+        out = ite.ite_mps_export(ctx, psi, [len(s) for s in sp])
+    finally:
+        ite.ite_mps_destroy(psi)
+        ite.ite_mpo_destroy(H)
+    return reps, out
+
+
+def test_results_are_the_same_alone_and_in_the_mix():
+    torch = require_gpu()
+    reqs = _requests()
+    srv = ite.ite_server_create(0, workers=3, max_active=2, mem_cap=50e9)
+    try:
+        ids = [ite.ite_server_submit(srv, W, sp, chi, t0, t1, r, ite.ite_default_opts(**o))
+               for (W, sp, chi, t0, t1, r, o) in reqs]
+        infos = [ite.ite_server_wait(srv, i, 120.0) for i in ids]
+        for info in infos:
+            assert info["status"] == ite.REQ_DONE, info
+            assert info["n_steps"] == info["n_grid"]
+        assert len({info["worker"] for info in infos}) > 1      # the work was spread over workers
+        mixed = [(ite.ite_server_reports(srv, i), ite.ite_server_state(srv, i, [len(s) for s in q[1]]))
+                 for i, q in zip(ids, reqs)]
+    finally:
+        ite.ite_server_destroy(srv)
+    ctx = ite.ite_ctx_create(0)
+    try:
+        for (W, sp, chi, t0, t1, r, o), (reps_m, state_m) in zip(reqs, mixed):
+            reps_a, state_a = _alone(ctx, W, sp, chi, t0, t1, r, o)
+            assert len(reps_a) == len(reps_m)
+            for a, m in zip(reps_a, reps_m):
+                assert a["energy"] == m["energy"] and a["tau"] == m["tau"]
+                assert a["matvecs_fp64"] == m["matvecs_fp64"] and a["matvecs_lo"] == m["matvecs_lo"]
+            for x, y in zip(state_a, state_m):
+                assert x.shape == y.shape and np.array_equal(x, y)
+    finally:
+        torch.cuda.synchronize()
+        ite.ite_ctx_destroy(ctx)
+
+
+def test_admission_by_footprint_serialises_when_only_one_fits():
+    require_gpu()
+    W = hamiltonians.heisenberg(8)
+    fp = ite.ite_request_footprint([2] * 8, [1] + [5] * 7 + [1], 16)
+    srv = ite.ite_server_create(0, workers=3, max_active=2, mem_cap=1.5 * fp)
+    try:
+        ids = [ite.ite_server_submit(srv, W, random_spinors(rng_for(6, k), 8, 2), 16, 0.01, 1.0, 1.3,
+                                     ite.ite_default_opts(chi_max=16)) for k in range(3)]
+        infos = [ite.ite_server_wait(srv, i, 120.0) for i in ids]
+    finally:
+        ite.ite_server_destroy(srv)
+    for info in infos:
+        assert info["status"] == ite.REQ_DONE
+        assert abs(info["footprint"] - fp) <= 1e-6 * fp
+    for a, b in zip(infos, infos[1:]):
+        assert b["t_admit"] >= a["t_done"]
+
+
+def test_short_request_overtakes_a_long_one():
+    require_gpu()
+    srv = ite.ite_server_create(0, workers=2, max_active=1, mem_cap=50e9)
+    try:
+        long_id = ite.ite_server_submit(srv, hamiltonians.heisenberg(16), random_spinors(rng_for(7, 0), 16, 2),
+                                        32, 0.01, 200.0, 1.3, ite.ite_default_opts(chi_max=32))
+        short_id = ite.ite_server_submit(srv, hamiltonians.heisenberg(6), random_spinors(rng_for(7, 1), 6, 2),
+                                         8, 0.01, 0.5, 1.3, ite.ite_default_opts(chi_max=8))
+        s = ite.ite_server_wait(srv, short_id, 120.0)
+        lg = ite.ite_server_info(srv, long_id)
+        assert s["status"] == ite.REQ_DONE
+        assert lg["status"] == ite.REQ_ACTIVE      # still running while the short one is done
+        lg = ite.ite_server_wait(srv, long_id, 300.0)
+        assert lg["status"] == ite.REQ_DONE and lg["t_done"] > s["t_done"]
+    finally:
+        ite.ite_server_destroy(srv)
+
+
+def test_failed_request_is_reported_and_server_goes_on():
+    require_gpu()
+    srv = ite.ite_server_create(0, workers=2, max_active=2, mem_cap=50e9)
+    try:
+        W = hamiltonians.heisenberg(6)
+        bad = ite.ite_default_opts(chi_max=8)
+        bad.krylov_dim = 0                      # rejected by the first step on the device side
+        bad_id = ite.ite_server_submit(srv, W, random_spinors(rng_for(8, 0), 6, 2), 8, 0.01, 1.0, 1.3, bad)
+        good_id = ite.ite_server_submit(srv, W, random_spinors(rng_for(8, 1), 6, 2), 8, 0.01, 1.0, 1.3,
+                                        ite.ite_default_opts(chi_max=8))
+        b = ite.ite_server_wait(srv, bad_id, 60.0)
+        g = ite.ite_server_wait(srv, good_id, 60.0)
+        assert b["status"] == ite.REQ_FAILED and b["error"] == ite.ITE_EINVAL
+        assert "krylov_dim" in ite.ite_server_error(srv, bad_id)
+        assert g["status"] == ite.REQ_DONE
+        with pytest.raises(ite.IteError):
+            ite.ite_server_state(srv, bad_id, [2] * 6)
+        ite.ite_server_release(srv, bad_id)
+        with pytest.raises(ite.IteError):
+            ite.ite_server_info(srv, bad_id)
+    finally:
+        ite.ite_server_destroy(srv)

@@ -108,3 +108,29 @@ def test_bath_grid():
     eb, V = aim_bath(59, 0.1)
     assert len(eb) == 59 and abs(eb[29]) < 1e-15 and np.allclose(eb, -eb[::-1])
     assert np.allclose(V ** 2 * np.pi / (2 / 59), 0.1)
+
+
+def test_request_footprint_estimate():
+    # host-only admission estimate of the serving loop: grows with chi, L and
+    # the Krylov dimension, and is bounded by the structurally full bonds
+    d8, w8 = [2] * 8, [1] + [5] * 7 + [1]
+    f = [ite.ite_request_footprint(d8, w8, chi) for chi in (2, 4, 8, 16)]
+    assert all(b > a for a, b in zip(f, f[1:]))
+    # L=8 bonds saturate at 2^4 = 16
+    assert f[-1] == ite.ite_request_footprint(d8, w8, 32) == ite.ite_request_footprint(d8, w8, 1000)
+    assert ite.ite_request_footprint([2] * 64, [1] + [5] * 63 + [1], 256) > \
+        ite.ite_request_footprint([2] * 32, [1] + [5] * 31 + [1], 256)
+    assert ite.ite_request_footprint(d8, w8, 16, 20) > ite.ite_request_footprint(d8, w8, 16, 10)
+    # the c4 maximum (L=128, chi=512) stays within a few GB
+    big = ite.ite_request_footprint([2] * 128, [1] + [5] * 127 + [1], 512)
+    assert 1e9 < big < 8e9
+    assert ite.ite_request_footprint([2], [1, 1], 4) < 0
+
+
+def test_server_create_validates_options():
+    lib = ite.load_library()
+    h = ctypes.c_void_p()
+    for o in (ite.ite_server_opts(0, 0, 1, 1e9), ite.ite_server_opts(0, 2, 0, 1e9),
+              ite.ite_server_opts(0, 2, 1, 0.0)):
+        assert lib.ite_server_create(ctypes.byref(o), ctypes.byref(h)) == ite.ITE_EINVAL
+    assert lib.ite_server_create(None, ctypes.byref(h)) == ite.ITE_EINVAL

@@ -150,19 +150,23 @@ WORKLOADS: dict[str, Workload] = {
 }
 
 
-def serving_requests(n: int = 256, rate: float = 20.0, seed: int = 4000):
+def serving_requests(n: int = 256, rate: float = 20.0, seed: int = 4000, Ls=(32, 48, 64, 96, 128),
+                     chis=(64, 128, 256, 512), tau_range=(1.0, 1000.0)):
     """Request stream: (arrival_s, L, chi_max, tau_final, seed) tuples.
 
-    L uniform in {32,48,64,96,128}, chi_max uniform in {64,128,256,512},
-    tau_final = beta/2 log-uniform in [1, 1000], Poisson arrivals at ``rate``/s.
+    Defaults: L uniform in {32,48,64,96,128}, chi_max uniform in
+    {64,128,256,512}, tau_final = beta/2 log-uniform in [1, 1000], Poisson
+    arrivals at ``rate``/s.  Ls, chis and tau_range give scaled-down streams of
+    the same structure.
     """
     rng = np.random.default_rng(seed)
     t = 0.0
     out = []
+    lo, hi = math.log10(tau_range[0]), math.log10(tau_range[1])
     for i in range(n):
         t += rng.exponential(1.0 / rate)
-        L = int(rng.choice([32, 48, 64, 96, 128]))
-        chi = int(rng.choice([64, 128, 256, 512]))
-        tau = float(10 ** rng.uniform(0.0, 3.0))
+        L = int(rng.choice(list(Ls)))
+        chi = int(rng.choice(list(chis)))
+        tau = float(10 ** rng.uniform(lo, hi))
         out.append((t, L, chi, tau, seed + 1 + i))
     return out
