@@ -358,9 +358,17 @@ SplitResult split(ite_ctx* c, int dir, int Dl, int d1, int d2, int Dr, const dou
     double* norms = slot_t<double>(c, SL_NORM, (size_t)p + 16);
     int* perm = slot_t<int>(c, SL_PERM, (size_t)p + 16);
     jacobi_input(theta, m, n, dir, Z, c->stream);
+    // Householder preconditioning: the Jacobi then works on the rows of R,
+    // of which only the first min(p, q) can be non-zero
+    int pj = p;
+    if (householder_applies(p, q)) {
+        double* qws = slot_t<double>(c, SL_QR, householder_workspace(p, q, ld));
+        householder_rows(Z, p, q, ld, qws, c->stream);
+        pj = std::min(p, q);
+    }
     double* host = pinned(c, (size_t)p + 64);
     const double tol = 8.0 * std::sqrt((double)std::max(q, 1)) * 2.220446049250313e-16;
-    JacobiResult jr = jacobi_rows(Z, p, q, ld, tol, 60, gram, rot, off, host, c->stream);
+    JacobiResult jr = jacobi_rows(Z, pj, q, ld, tol, 60, gram, rot, off, host, c->stream);
     row_norms(Z, p, q, ld, norms, c->stream);
     d2h(c, host, norms, p);
     sync(c);

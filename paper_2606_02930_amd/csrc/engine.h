@@ -16,6 +16,7 @@ enum SlotId {
     SL_V, SL_W,                    // Krylov basis, work vector
     SL_PART, SL_SMALL,             // reduction partials, small device scalars
     SL_Z, SL_GRAM, SL_ROT, SL_OFF, SL_NORM, SL_PERM,   // Jacobi split
+    SL_QR,                         // Householder preconditioning
     SL_TMPA, SL_TMPB,              // scratch environments (overlap, energy)
     SL_LO_L, SL_LO_R, SL_LO_T, SL_LO_X,   // low-precision shadows (mixed precision)
     SL_R64, SL_D64,                // refinement residual and correction

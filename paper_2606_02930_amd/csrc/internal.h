@@ -132,6 +132,14 @@ void row_norms(const double* Z, int p, int q, int ld, double* norms, hipStream_t
 void gather_split(const double* Z, int ld, const int* perm, int k, int roff, int nr,
                   double* rowdst, int coff, int nc, double* coldst, hipStream_t s);
 
+// Householder QR preconditioning of the Jacobi work matrix: Z <- Q^T Z with
+// X = Q R the QR of the first q columns (p rows, leading dimension ld); the
+// rows q..p-1 of the first part become zero when p > q.  Applies to
+// 256 <= p <= 2048 and q >= 16; ws holds householder_workspace doubles.
+bool householder_applies(int p, int q);
+size_t householder_workspace(int p, int q, int ld);
+void householder_rows(double* Z, int p, int q, int ld, double* ws, hipStream_t s);
+
 // MFMA lane-layout probe (tests only).
 void mfma_probe_f64(double* out, hipStream_t s);
 

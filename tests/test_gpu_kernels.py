@@ -164,8 +164,11 @@ def test_env_update_matches_oracle(env, with_mpo, direction, dims):
     assert rel_err(host(out), want) < 1e-13
 
 
+# from p >= 256 rows the Jacobi runs on the Householder R factor: square,
+# more rows than columns (rows of R beyond q vanish) and fewer rows
 SPLIT_SHAPES = [(1, 2, 2, 1), (1, 2, 2, 2), (3, 2, 2, 5), (8, 2, 2, 3), (16, 2, 2, 16), (33, 2, 2, 17),
-                (64, 4, 4, 64), (256, 2, 2, 256)]
+                (64, 4, 4, 64), (256, 2, 2, 256), (200, 2, 2, 64), (64, 2, 2, 300), (130, 2, 2, 150),
+                (512, 2, 2, 512)]
 
 
 @pytest.mark.parametrize("direction", [0, 1])
@@ -202,22 +205,24 @@ def test_svd_split_matches_numpy(env, direction, shape):
 
 
 @pytest.mark.parametrize("direction", [0, 1])
-def test_svd_split_keeps_complete_basis_with_zeros(env, direction):
+@pytest.mark.parametrize("D", [4, 128])
+def test_svd_split_keeps_complete_basis_with_zeros(env, direction, D):
     # cutoff 0 keeps min(rows, cols, chi) values including exact zeros; the
     # factor that becomes the canonical tensor must still be orthonormal
+    # (D = 128: 256 rows, through the Householder-preconditioned path)
     torch, ctx = env
     rng = np.random.default_rng(77)
-    Dl, d, Dr = 4, 2, 4
+    Dl, d, Dr = D, 2, D
     m = Dl * d
     u = rng.standard_normal((m, 2))
     v = rng.standard_normal((2, d * Dr))
     theta = (u @ v).reshape(Dl, d, d, Dr)       # rank 2
-    A1 = torch.zeros((Dl, d, 8), dtype=torch.float64, device="cuda")
-    A2 = torch.zeros((8, d, Dr), dtype=torch.float64, device="cuda")
-    k, sig, disc = ite.ite_debug_svd_split(ctx, direction, dev(torch, theta), 8, 0.0, 1e-13, A1, A2)
-    assert k == 8 and np.all(sig[2:] < 1e-13 * sig[0])
-    a1 = host(A1).reshape(Dl, d, 8)
-    a2 = host(A2).reshape(8, d, Dr)
+    A1 = torch.zeros((Dl, d, m), dtype=torch.float64, device="cuda")
+    A2 = torch.zeros((m, d, Dr), dtype=torch.float64, device="cuda")
+    k, sig, disc = ite.ite_debug_svd_split(ctx, direction, dev(torch, theta), m, 0.0, 1e-13, A1, A2)
+    assert k == m and np.all(sig[2:] < 1e-13 * sig[0])
+    a1 = host(A1).reshape(Dl, d, m)
+    a2 = host(A2).reshape(m, d, Dr)
     assert rel_err(omps.two_site(a1, a2), theta) < 1e-13
     if direction == 0:
         assert omps.left_orthonormality_error(a1) < 1e-13
