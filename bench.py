@@ -1,20 +1,31 @@
 #!/usr/bin/env python3
 """Benchmark of the implicit imaginary-time step on one MI355X.
 
-A step is one implicit trapezoid step (I + h (H - s)) x = (I - h (H - s)) psi
-of the Heisenberg S=1/2 open chain, L=100, MPS bond dimension 1024, MPO bond
-dimension 5, with the paper's budget (GMRES Krylov 10, one cycle, one sweep),
-shift tracking the energy, from a steady-state MPS at full bonds (random
-right-orthonormal tensors, chi = 1024 in the interior).  h cycles through the
-trapezoid half-steps of grid steps 26-28 of the geometric grid 0.01 -> 1000,
-ratio 1.3.  Inputs are resident in HBM before the timed region.
+Default workload (heis100): one implicit trapezoid step
+(I + h (H - s)) x = (I - h (H - s)) psi of the Heisenberg S=1/2 open chain,
+L=100, MPS bond dimension 1024, MPO bond dimension 5, with the paper's budget
+(GMRES Krylov 10, one cycle, one sweep), shift tracking the energy, from a
+steady-state MPS at full bonds (random right-orthonormal tensors, chi = 1024
+in the interior).  h cycles through the trapezoid half-steps of grid steps
+26-28 of the geometric grid 0.01 -> 1000, ratio 1.3.  Inputs are resident in
+HBM before the timed region.
 
 Prints one JSON line with tau-steps/s, the H_eff matvec TFLOP/s at the
-1024-bond block shape, the roofline of the dominant kernel (FP64 MFMA GEMM),
-and the CPU oracle timed on a bounded sample.
+1024-bond block shape, the per-kernel profile of the timed steps with the
+roofline of the kernel that takes the most device time, and the CPU oracle
+timed on a bounded sample.
+
+Other workloads (own JSON line each):
+  --workload aim60   the same steady-state step for the Anderson impurity chain
+                     (59 bath sites, d=4, MPO w=6, chi=512, U=4)
+  --workload heis64  a whole evolution of the L=64 chain (chi <= 256, cutoff
+                     1e-10, 45 steps from a random product state), in the
+                     chosen precision and in FP64, with the energy differences
+  --mode serve       the serving loop on a scaled-down request stream
+  --mode matvec      the H_eff product alone
 
     python bench.py [--steps K] [--warmup W] [--precision fp64|fp32|bf16]
-                    [--mode step|matvec|parts] [--no-cpu]
+                    [--workload heis100|aim60|heis64] [--mode step|matvec|serve] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -31,6 +42,14 @@ METRIC = "H_eff matvec TFLOP/s + tau-steps/s at L=100 chi=1024; p50/p99 solve la
 FP64_PEAK = 78.6      # TFLOP/s, MI355X dense FP64 (MFMA and vector)
 FP32_PEAK = 157.3
 BF16_PEAK = 2500.0
+HBM_PEAK = 8000.0     # GB/s
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
+DTYPE = {"fp64": "f64", "fp32": "f64+f32", "bf16": "f64+bf16"}
+# kernel kinds of the context's launch profile
+KERNELS = {0: ("gemm_kernel<double> (FP64 MFMA contraction)", "mfma"),
+           1: ("gram_kernel (Jacobi pair Gram, FP64 MFMA)", "hbm"),
+           2: ("inner_kernel (Jacobi inner sweep, FP64 vector, LDS)", "alu"),
+           3: ("rotate_kernel (Jacobi row rotation, FP64 MFMA)", "hbm")}
 
 
 def log(msg):
@@ -57,16 +76,38 @@ def block_equivalents(dims, d, w):
     return 2.0 * tot
 
 
-def steady_state(L=100, chi=1024, seed=2002):
-    from workload import random_isometry_mps, rng_for
-    rng = rng_for(2, 2)
-    return random_isometry_mps(rng, L, 2, chi, distinct=2)
-
-
-def h_values():
+def h_values(tau1):
     from paper_2606_02930_amd import ite_loggrid
-    g = ite_loggrid(0.01, 1000.0, 1.3)
+    g = ite_loggrid(0.01, tau1, 1.3)
     return [0.5 * (g[k] - g[k - 1]) for k in (26, 27, 28)]
+
+
+def steady_workload(name, chi_arg):
+    """(label, MPO tensors, steady-state MPS tensors, d, w, chi, tau1)."""
+    from paper_2606_02930_amd import hamiltonians
+    from workload import random_isometry_mps, rng_for, aim_bath
+    if name == "heis100":
+        L, d, chi = 100, 2, chi_arg or 1024
+        W = hamiltonians.heisenberg(L)
+        tensors = random_isometry_mps(rng_for(2, 2), L, d, chi, distinct=2)
+        label = (f"Heisenberg S=1/2 open chain L={L}, J=1, MPO w=5, MPS chi={chi} (steady state, random "
+                 f"right-orthonormal full bonds), trapezoid step with the paper's budget (GMRES Krylov 10, one "
+                 f"cycle, one sweep), shift = energy, cutoff 0 + tie rule, h of grid steps 26-28 "
+                 f"(tau 0.01->1000, ratio 1.3)")
+        return label, W, tensors, d, 5, chi, 1000.0
+    if name == "aim60":
+        d, chi = 4, chi_arg or 512
+        eps, V = aim_bath(59, 0.1)
+        U = 4.0
+        W = hamiltonians.anderson_star(U, -U / 2, eps, V)
+        L = len(W)
+        tensors = random_isometry_mps(rng_for(3, 2), L, d, chi, distinct=2)
+        label = (f"Anderson impurity, 59-site metallic bath (uniform grid in [-1,1], Gamma=0.1), U={U}, "
+                 f"eps_d=-U/2, L={L} spinful sites (d=4, Jordan-Wigner), MPO w=6, MPS chi={chi} (steady state, "
+                 f"random right-orthonormal full bonds), trapezoid step with the paper's budget, shift = "
+                 f"energy, cutoff 0 + tie rule, h of grid steps 26-28 (tau 0.01->1e4, ratio 1.3)")
+        return label, W, tensors, d, 6, chi, 1e4
+    raise ValueError(name)
 
 
 def run_matvec(ite, ctx, torch, reps=10, prec=0):
@@ -89,76 +130,80 @@ def run_matvec(ite, ctx, torch, reps=10, prec=0):
     return heff_flops(D, d, 5) / dt / 1e12, dt
 
 
-def cpu_baseline(dims, budget_s=30.0):
+def cpu_baseline(dims, d, W, budget_s=30.0):
     """The oracle on one full-size block of the same workload (right-hand side,
     GMRES(10) one cycle, SVD split, environment updates), extrapolated to a
     step by the block-cost equivalents of the steady-state bond dimensions."""
-    from oracle import mps as omps, mpo as ompo
+    from oracle import mps as omps
     try:
         from threadpoolctl import threadpool_info
         threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
     except Exception:
         threads = 1
     rng = np.random.default_rng(99)
-    D, d, w = max(dims), 2, 5
-    W = ompo.heisenberg_mpo(4)
-    Lm = rng.standard_normal((D, w, D)) / D
-    Rm = rng.standard_normal((D, w, D)) / D
+    D = max(dims)
+    W1, W2 = W[len(W) // 2], W[len(W) // 2 + 1]
+    w = W1.shape[1]
+    Lm = rng.standard_normal((D, W1.shape[0], D)) / D
+    Rm = rng.standard_normal((D, W2.shape[1], D)) / D
     A1 = rng.standard_normal((D, d, D)) / math.sqrt(D)
     A2 = rng.standard_normal((D, d, D)) / math.sqrt(D)
     h, s = 0.5, -1.0
     t0 = time.perf_counter()
     th_psi = omps.two_site(A1, A2)
-    b = (1 + h * s) * th_psi - h * omps.heff_apply(Lm, W[1], W[2], Rm, th_psi)
-    op = lambda v: (1 - h * s) * v + h * omps.heff_apply(Lm, W[1], W[2], Rm, v)
+    b = (1 + h * s) * th_psi - h * omps.heff_apply(Lm, W1, W2, Rm, th_psi)
+    op = lambda v: (1 - h * s) * v + h * omps.heff_apply(Lm, W1, W2, Rm, v)
     x, _ = omps.gmres(op, b, th_psi, 10, 1, 0.0)
     a, bb, _ = omps.split_two_site(x, "lr", 0.0, D, 1e-13)
-    omps.env_left_h(Lm, a, W[1], a)
-    omps.env_left_h(Lm, a, W[1], A1)
+    omps.env_left_h(Lm, a, W1, a)
+    omps.env_left_h(Lm, a, W1, A1)
     omps.env_left_o(np.eye(D), a, A1)
     t_block = time.perf_counter() - t0
     eq = block_equivalents(dims, d, w)
     return {"value": 1.0 / (t_block * eq), "unit": "tau-steps/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"one full-size block (chi=1024: rhs, GMRES(10) one cycle, SVD split, 3 env updates) "
+            "sample": f"one full-size block (chi={D}: rhs, GMRES(10) one cycle, SVD split, 3 env updates) "
                       f"took {t_block:.1f} s; step = {eq:.1f} full-block equivalents (sum over the 2(L-1) blocks "
                       f"of D_l D_r (D_l+D_r) / (2 chi^3) at the steady-state bonds)",
             "host_cpus": len(os.sched_getaffinity(0))}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
-    ap.add_argument("--mode", default="step", choices=["step", "matvec", "parts"])
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--chi", type=int, default=1024)
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding of this path is a "
-              f"design note, not an implementation", file=sys.stderr)
-        sys.exit(2)
-    import torch
-    import paper_2606_02930_amd as ite
-    from paper_2606_02930_amd import hamiltonians
-    prec = {"fp64": 0, "fp32": 1, "bf16": 2}[args.precision]
+def kernel_profile(ite, ctx, precision):
+    """Per-kernel device time of the profiled region (sampled launches scaled
+    to all launches) and the roofline of each kind; returns (table, dominant)."""
+    table = {}
+    for kind, (name, bound) in KERNELS.items():
+        p = ite.ite_ctx_profile_kernel(ctx, kind)
+        if p["launches"] == 0 or p["timed"] == 0:
+            continue
+        avg_ms = p["ms_timed"] / p["timed"]
+        total_s = avg_ms * p["launches"] * 1e-3
+        row = {"kernel": name, "bound": bound, "launches": p["launches"], "timed": p["timed"],
+               "avg_launch_ms": avg_ms, "est_total_s": total_s,
+               "flops_per_launch": p["flops"] / p["launches"], "bytes_per_launch": p["bytes"] / p["launches"]}
+        if bound == "hbm":
+            row.update(achieved=p["bytes"] / total_s / 1e9, peak=HBM_PEAK, unit="GB/s")
+        else:
+            row.update(achieved=p["flops"] / total_s / 1e12, peak=FP64_PEAK, unit="TFLOP/s")
+        row["frac"] = row["achieved"] / row["peak"]
+        table[kind] = row
+    dom = max(table.values(), key=lambda r: r["est_total_s"]) if table else None
+    return table, dom
+
+
+def run_steady(ite, torch, args):
+    label, W, tensors, d, w, chi, tau1 = steady_workload(args.workload, args.chi)
+    prec = PREC[args.precision]
     ctx = ite.ite_ctx_create(0)
     log("context ready")
     mv_tflops, mv_s = run_matvec(ite, ctx, torch, prec=0)
     log(f"matvec 1024-bond block: {mv_tflops:.2f} TFLOP/s ({mv_s * 1e3:.2f} ms)")
-    if args.mode == "matvec":
-        print(json.dumps({"metric": "H_eff matvec TFLOP/s at chi=1024 d=2 w=5", "value": mv_tflops,
-                          "unit": "TFLOP/s", "ms": mv_s * 1e3}))
-        return
-    L, chi = 100, args.chi
-    tensors = steady_state(L, chi)
+    L = len(tensors)
     dims = [tensors[0].shape[0]] + [a.shape[2] for a in tensors]
-    H = ite.ite_mpo_load(ctx, hamiltonians.heisenberg(L))
+    H = ite.ite_mpo_load(ctx, W)
     psi = ite.ite_mps_load(ctx, tensors, chi)
-    log(f"steady-state MPS loaded: L={L}, max bond {max(dims)}")
+    log(f"steady-state MPS loaded: L={L}, d={d}, max bond {max(dims)}")
     o = ite.ite_default_opts(chi_max=chi, cutoff=0.0, precision=prec)
-    hs = h_values()
+    hs = h_values(tau1)
     reps = []
     for k in range(args.warmup):
         r = ite.ite_imag_step(ctx, psi, H, hs[k % 3], o)
@@ -174,9 +219,14 @@ def main():
             f"split {r['ms_split']:.0f}, env {r['ms_env']:.0f}) E={r['energy']:.10f} maxchi={r['max_chi']}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    launches, gemm_ms, gemm_flops = ite.ite_ctx_profile_read(ctx)
+    table, dom = kernel_profile(ite, ctx, args.precision)
     ite.ite_ctx_profile(ctx, False)
-    achieved = gemm_flops / (gemm_ms * 1e-3) / 1e12 if gemm_ms > 0 else 0.0
+    roof = None
+    if dom is not None:
+        roof = {"bound": dom["bound"], "achieved": dom["achieved"], "peak": dom["peak"], "unit": dom["unit"],
+                "frac": dom["frac"], "traffic": None, "kernel": dom["kernel"],
+                "avg_launch_ms": dom["avg_launch_ms"], "launches": dom["launches"],
+                "share_of_step_device_time": dom["est_total_s"] / (elapsed)}
     out = {
         "metric": METRIC,
         "value": args.steps / elapsed,
@@ -188,31 +238,179 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f64+f32", "bf16": "f64+bf16"}[args.precision],
+        "dtype": DTYPE[args.precision],
         "data": "synthetic",
-        "config": {"workload": f"Heisenberg S=1/2 open chain L={L}, J=1, MPO w=5, MPS chi={chi} (steady state, "
-                               f"random right-orthonormal full bonds), trapezoid step with the paper's budget "
-                               f"(GMRES Krylov 10, one cycle, one sweep), shift = energy, cutoff 0 + tie rule, "
-                               f"h of grid steps 26-28 (tau 0.01->1000, ratio 1.3)",
-                   "precision": args.precision},
+        "config": {"workload": label, "precision": args.precision},
         "matvec_tflops": mv_tflops,
         "matvec_ms": mv_s * 1e3,
         "phase_ms": {k: float(np.mean([r[k] for r in reps])) for k in
                      ("ms_total", "ms_rhs", "ms_solve", "ms_split", "ms_env")},
+        "matvecs_per_step": {"fp64": int(np.mean([r["matvecs_fp64"] for r in reps])),
+                             "low": int(np.mean([r["matvecs_lo"] for r in reps]))},
         "energy": reps[-1]["energy"],
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_PEAK, "traffic": None,
-                     "kernel": "gemm_kernel<double> (FP64 MFMA 16x16x4)", "launches": launches,
-                     "avg_launch_ms": gemm_ms / max(launches, 1),
-                     "flops_per_launch": gemm_flops / max(launches, 1)},
+        "roofline": roof,
+        "kernels": {KERNELS[k][0].split(" ")[0]: v for k, v in table.items()},
     }
     if not args.no_cpu:
         log("timing the CPU oracle on one full-size block ...")
-        out["cpu_baseline"] = cpu_baseline(dims)
-    print(json.dumps(out), flush=True)
+        out["cpu_baseline"] = cpu_baseline(dims, d, W)
     ite.ite_mps_destroy(psi)
     ite.ite_mpo_destroy(H)
     ite.ite_ctx_destroy(ctx)
+    return out
+
+
+def run_heis64(ite, torch, args):
+    """A whole evolution of the L=64 chain (chi <= 256, cutoff 1e-10, trapezoid,
+    shift tracking, paper budget, tau 0.01 -> 1000 ratio 1.3) from a seeded
+    random product state, in FP64 and (if asked) in a mixed precision, with the
+    per-step relative energy differences."""
+    from paper_2606_02930_amd import hamiltonians
+    from workload import rng_for, random_spinors
+    L, chi = 64, 256
+    W = hamiltonians.heisenberg(L)
+    sp = random_spinors(rng_for(1), L, 2)
+    ctx = ite.ite_ctx_create(0)
+    H = ite.ite_mpo_load(ctx, W)
+    res = {}
+    for pname in (["fp64"] + ([args.precision] if args.precision != "fp64" else [])):
+        psi = ite.ite_mps_create(ctx, sp, chi)
+        o = ite.ite_default_opts(chi_max=chi, cutoff=1e-10, precision=PREC[pname])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = ite.ite_evolve_loggrid(ctx, psi, H, 0.01, 1000.0, 1.3, o)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ite.ite_mps_destroy(psi)
+        res[pname] = (reps, dt)
+        log(f"{pname}: {len(reps)} steps in {dt:.1f} s, final E = {reps[-1]['energy']:.12f}, "
+            f"max chi {max(r['max_chi'] for r in reps)}")
+    ite.ite_mpo_destroy(H)
+    ite.ite_ctx_destroy(ctx)
+    reps64, t64 = res["fp64"]
+    out = {"metric": "tau-steps/s, whole evolution", "unit": "tau-steps/s", "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": f"Heisenberg S=1/2 open chain L={L}, chi<={chi}, cutoff 1e-10, trapezoid, shift "
+                                  f"= energy, paper budget, tau 0.01->1000 ratio 1.3, random product state"},
+           "fp64": {"value": len(reps64) / t64, "seconds": t64, "steps": len(reps64),
+                    "final_energy": reps64[-1]["energy"], "max_chi": max(r["max_chi"] for r in reps64)}}
+    if args.precision != "fp64":
+        repl, tl = res[args.precision]
+        e64 = np.array([r["energy"] for r in reps64])
+        el = np.array([r["energy"] for r in repl])
+        rel = np.abs(el - e64) / np.abs(e64)
+        out[args.precision] = {"value": len(repl) / tl, "seconds": tl, "steps": len(repl),
+                               "final_energy": repl[-1]["energy"], "max_rel_energy_diff_vs_fp64": float(rel.max()),
+                               "final_rel_energy_diff_vs_fp64": float(rel[-1]),
+                               "solve_ms_per_step": float(np.mean([r["ms_solve"] for r in repl])),
+                               "fp64_solve_ms_per_step": float(np.mean([r["ms_solve"] for r in reps64]))}
+    return out
+
+
+SERVE_LS = (12, 16, 24)
+SERVE_CHIS = (16, 32)
+SERVE_TAU = (1.0, 100.0)
+
+
+def _serve_once(ite, hamiltonians, stream, workers, max_active, precision):
+    """Submit the stream at its arrival times to a fresh server; return the
+    per-request latencies, the steps, the makespan and the final energies."""
+    from workload import random_spinors
+    srv = ite.ite_server_create(0, workers=workers, max_active=max_active, mem_cap=200e9)
+    try:
+        t_start = ite.ite_server_clock(srv)
+        ids = []
+        for (t_arr, L, chi, tau1, seed) in stream:
+            while ite.ite_server_clock(srv) - t_start < t_arr:
+                time.sleep(0.001)
+            sp = random_spinors(np.random.default_rng(seed), L, 2)
+            o = ite.ite_default_opts(chi_max=chi, cutoff=1e-10, precision=precision)
+            ids.append(ite.ite_server_submit(srv, hamiltonians.heisenberg(L), sp, chi, 0.01, tau1, 1.3, o))
+        infos = []
+        for i in ids:
+            infos.append(ite.ite_server_wait(srv, i))
+            log(f"  request {len(infos)}/{len(ids)} done at {infos[-1]['t_done'] - t_start:.2f} s")
+        energies = [ite.ite_server_reports(srv, i)[-1]["energy"] for i in ids]
+    finally:
+        ite.ite_server_destroy(srv)
+    for info in infos:
+        if info["status"] != ite.REQ_DONE:
+            raise RuntimeError(f"request failed: {info}")
+    lat = np.array([i["t_done"] - i["t_submit"] for i in infos])
+    steps = sum(i["n_steps"] for i in infos)
+    makespan = max(i["t_done"] for i in infos) - min(i["t_submit"] for i in infos)
+    return lat, steps, makespan, np.array(energies)
+
+
+def run_serve(ite, args):
+    """Serving: a scaled-down stream of the 256-request stream (same
+    structure: Poisson arrivals at 20/s, random product states, L and chi
+    drawn uniformly, tau_final log-uniform), served with continuous batching
+    in mixed precision (FP32 products, FP64 refinement) on `workers`
+    streams, against the same stream served serially in plain FP64 (one
+    worker, one active request, FIFO)."""
+    from paper_2606_02930_amd import hamiltonians
+    from workload import serving_requests
+    stream = serving_requests(n=args.requests, rate=20.0, seed=4000, Ls=SERVE_LS, chis=SERVE_CHIS,
+                              tau_range=SERVE_TAU)
+    log(f"serving {len(stream)} requests, continuous batching on {args.workers} workers (FP32-IR)")
+    lat, steps, span, e_mix = _serve_once(ite, hamiltonians, stream, args.workers, 2, ite.PREC_FP32_IR)
+    log("same stream, serial plain FP64 (1 worker, FIFO)")
+    lat0, steps0, span0, e_64 = _serve_once(ite, hamiltonians, stream, 1, 1, ite.PREC_FP64)
+    rel = np.abs(e_mix - e_64) / np.abs(e_64)
+    pct = lambda a, q: float(np.percentile(a, q))
+    return {
+        "metric": "serving latency p50/p99 (s) and aggregate tau-steps/s",
+        "unit": "s",
+        "n_gpus": 1,
+        "data": "synthetic",
+        "config": {"workload": f"{len(stream)} Heisenberg open-chain evolutions, L in {list(SERVE_LS)}, chi_max in "
+                               f"{list(SERVE_CHIS)}, tau_final log-uniform in {list(SERVE_TAU)}, grid 0.01 ratio 1.3, "
+                               f"random product states, Poisson arrivals 20/s, cutoff 1e-10, paper budget",
+                   "workers": args.workers, "max_active": 2},
+        "served": {"precision": "fp32-ir", "p50_s": pct(lat, 50), "p99_s": pct(lat, 99), "makespan_s": span,
+                   "tau_steps": int(steps), "tau_steps_per_s": steps / span},
+        "serial_fp64": {"p50_s": pct(lat0, 50), "p99_s": pct(lat0, 99), "makespan_s": span0,
+                        "tau_steps": int(steps0), "tau_steps_per_s": steps0 / span0},
+        "throughput_ratio": (steps / span) / (steps0 / span0),
+        "final_energy_rel_diff_vs_fp64": {"max": float(rel.max()), "median": float(np.median(rel))},
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--precision", default="fp64", choices=list(PREC))
+    ap.add_argument("--workload", default="heis100", choices=["heis100", "aim60", "heis64"])
+    ap.add_argument("--mode", default="step", choices=["step", "matvec", "serve"])
+    ap.add_argument("--requests", type=int, default=32, help="serve mode: number of requests")
+    ap.add_argument("--workers", type=int, default=8, help="serve mode: server worker threads")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--chi", type=int, default=0, help="bond dimension (default: the workload's)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); multi-GPU sharding of this path is a "
+              f"design note, not an implementation", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2606_02930_amd as ite
+    if args.mode == "serve":
+        out = run_serve(ite, args)
+    elif args.mode == "matvec":
+        ctx = ite.ite_ctx_create(0)
+        res = {}
+        for pname in PREC:
+            tf, s = run_matvec(ite, ctx, torch, prec=PREC[pname])
+            res[pname] = {"tflops": tf, "ms": s * 1e3}
+        ite.ite_ctx_destroy(ctx)
+        out = {"metric": "H_eff matvec TFLOP/s at chi=1024 d=2 w=5", "value": res["fp64"]["tflops"],
+               "unit": "TFLOP/s", "by_precision": res}
+    elif args.workload == "heis64":
+        out = run_heis64(ite, torch, args)
+    else:
+        out = run_steady(ite, torch, args)
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

@@ -132,14 +132,23 @@ const char* ite_last_error(const ite_ctx* ctx);
 /* Library version string. */
 const char* ite_version(void);
 
-/* GEMM launch profiler (observability, used by the benchmark): with enable =
- * 1 the context brackets every FP64 contraction launch with HIP events on its
- * stream and counts its algorithmic work 2 M N K; enabling resets the totals,
- * enable = 0 stops recording.  ite_ctx_profile_read synchronises the stream
- * and returns the launch count, the summed device time (ms) and the summed
- * algorithmic flops since the last enable. */
+/* Launch profiler (observability, used by the benchmark): with enable = 1
+ * the context brackets FP64 contraction launches (all) and Jacobi launches
+ * (a sample) with HIP events on its stream and counts their algorithmic work;
+ * enabling resets the totals, enable = 0 stops recording.
+ * ite_ctx_profile_read synchronises the stream and returns, for the FP64
+ * contraction GEMMs, the launch count, the summed device time (ms) and the
+ * summed algorithmic flops 2 M N K since the last enable. */
 int ite_ctx_profile(ite_ctx* ctx, int enable);
 int ite_ctx_profile_read(ite_ctx* ctx, long long* launches, double* ms, double* flops);
+/* Per-kernel launch profile since the last enable, by kind: 0 FP64
+ * contraction GEMMs (every launch timed), 1 Jacobi Gram, 2 Jacobi inner
+ * sweep, 3 Jacobi rotation (every 8th launch of a kind timed).  launches: all
+ * launches; timed, ms_timed: the timed ones and their summed device time;
+ * flops, bytes: the algorithmic work of all launches (Jacobi: of the pairs
+ * and column chunks the kernels actually processed). */
+int ite_ctx_profile_kernel(ite_ctx* ctx, int kind, long long* launches, long long* timed,
+                           double* ms_timed, double* flops, double* bytes);
 
 /* Fill `o` with the defaults described at ite_step_opts. */
 void ite_default_opts(ite_step_opts* o);

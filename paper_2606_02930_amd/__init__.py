@@ -96,6 +96,7 @@ _SIGNATURES = {
     "ite_last_error": (C.c_char_p, [_P]),
     "ite_ctx_profile": (_I, [_P, _I]),
     "ite_ctx_profile_read": (_I, [_P, C.POINTER(C.c_longlong), _PD, _PD]),
+    "ite_ctx_profile_kernel": (_I, [_P, _I, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong), _PD, _PD, _PD]),
     "ite_mpo_load": (_I, [_P, _I, _PI, _PI, _PPD, C.POINTER(_P)]),
     "ite_mpo_destroy": (_I, [_P]),
     "ite_mps_create": (_I, [_P, _I, _PI, _PPD, _I, _I, C.POINTER(_P)]),
@@ -257,6 +258,20 @@ def ite_ctx_profile_read(ctx: Ctx) -> tuple[int, float, float]:
     fl = C.c_double()
     _check(load_library().ite_ctx_profile_read(ctx.handle, C.byref(n), C.byref(ms), C.byref(fl)), ctx.handle)
     return n.value, ms.value, fl.value
+
+
+PROBE_GEMM, PROBE_GRAM, PROBE_INNER, PROBE_ROTATE = 0, 1, 2, 3
+
+
+def ite_ctx_profile_kernel(ctx: Ctx, kind: int) -> dict:
+    """Launch profile of one kernel kind since the last enable: launches,
+    timed launches, their summed device ms, algorithmic flops and bytes of all
+    launches."""
+    n, t = C.c_longlong(), C.c_longlong()
+    ms, fl, by = C.c_double(), C.c_double(), C.c_double()
+    _check(load_library().ite_ctx_profile_kernel(ctx.handle, int(kind), C.byref(n), C.byref(t), C.byref(ms),
+                                                 C.byref(fl), C.byref(by)), ctx.handle)
+    return {"launches": n.value, "timed": t.value, "ms_timed": ms.value, "flops": fl.value, "bytes": by.value}
 
 
 # ---------------------------------------------------------------------------

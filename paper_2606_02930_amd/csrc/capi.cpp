@@ -155,11 +155,14 @@ int ite_ctx_profile(ite_ctx* c, int enable) {
         set_device(c);
         prof_collect(c);
         c->prof_on = enable != 0;
-        if (c->prof_on) {
-            c->prof_launches = 0;
-            c->prof_ms = 0.0;
-            c->prof_total_flops = 0.0;
-        }
+        if (c->prof_on)
+            for (int k = 0; k < PK_COUNT; ++k) {
+                c->prof_launches[k] = 0;
+                c->prof_timed[k] = 0;
+                c->prof_ms[k] = 0.0;
+                c->prof_flops[k] = 0.0;
+                c->prof_bytes[k] = 0.0;
+            }
     });
 }
 
@@ -168,9 +171,24 @@ int ite_ctx_profile_read(ite_ctx* c, long long* launches, double* ms, double* fl
     return guarded(c, [&] {
         set_device(c);
         prof_collect(c);
-        *launches = c->prof_launches;
-        *ms = c->prof_ms;
-        *flops = c->prof_total_flops;
+        *launches = c->prof_launches[PK_GEMM];
+        *ms = c->prof_ms[PK_GEMM];
+        *flops = c->prof_flops[PK_GEMM];
+    });
+}
+
+int ite_ctx_profile_kernel(ite_ctx* c, int kind, long long* launches, long long* timed, double* ms_timed,
+                           double* flops, double* bytes) {
+    if (!c || !launches || !timed || !ms_timed || !flops || !bytes || kind < 0 || kind >= PK_COUNT)
+        return ITE_EINVAL;
+    return guarded(c, [&] {
+        set_device(c);
+        prof_collect(c);
+        *launches = c->prof_launches[kind];
+        *timed = c->prof_timed[kind];
+        *ms_timed = c->prof_ms[kind];
+        *flops = c->prof_flops[kind];
+        *bytes = c->prof_bytes[kind];
     });
 }
 

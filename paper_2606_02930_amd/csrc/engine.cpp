@@ -108,18 +108,43 @@ static hipEvent_t prof_event(ite_ctx* c) {
 
 // Fold the recorded launch spans into the totals (synchronises the stream).
 void prof_collect(ite_ctx* c) {
-    if (c->prof_flops.empty()) return;
+    if (c->prof_kind.empty()) return;
     HIP_CHECK(hipStreamSynchronize(c->stream));
-    for (size_t i = 0; i < c->prof_flops.size(); ++i) {
+    for (size_t i = 0; i < c->prof_kind.size(); ++i) {
         float ms = 0.f;
         HIP_CHECK(hipEventElapsedTime(&ms, c->prof_events[2 * i], c->prof_events[2 * i + 1]));
-        c->prof_ms += ms;
-        c->prof_total_flops += c->prof_flops[i];
-        c->prof_launches++;
+        c->prof_ms[c->prof_kind[i]] += ms;
+        c->prof_timed[c->prof_kind[i]]++;
     }
-    c->prof_flops.clear();
+    c->prof_kind.clear();
     c->prof_used = 0;
 }
+
+namespace {
+
+// The context's LaunchProbe: counts launches, times every launch of an FP64
+// GEMM and every jac_period-th launch of each Jacobi kernel.
+struct CtxProbe final : LaunchProbe {
+    ite_ctx* c;
+    explicit CtxProbe(ite_ctx* cc) : c(cc) {}
+    bool begin(int kind, hipStream_t s) override {
+        const long long n = c->prof_launches[kind]++;
+        if (kind != PK_GEMM && n % c->jac_period != 0) return false;
+        if (c->prof_kind.size() >= 4096) prof_collect(c);
+        HIP_CHECK(hipEventRecord(prof_event(c), s));
+        return true;
+    }
+    void end(int kind, hipStream_t s) override {
+        HIP_CHECK(hipEventRecord(prof_event(c), s));
+        c->prof_kind.push_back(kind);
+    }
+    void work(int kind, double flops, double bytes) override {
+        c->prof_flops[kind] += flops;
+        c->prof_bytes[kind] += bytes;
+    }
+};
+
+}  // namespace
 
 static void gemm(ite_ctx* c, bool tA, bool tB, int M, int N, int K, double alpha, const double* A, long lda,
                  const double* B, long ldb, double beta, const double* C, long ldc, double* D, long ldd) {
@@ -128,11 +153,12 @@ static void gemm(ite_ctx* c, bool tA, bool tB, int M, int N, int K, double alpha
     g.alpha = alpha; g.beta = beta;
     g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc; g.D = D; g.ldd = ldd;
     if (c->prof_on && M > 0 && N > 0) {
-        if (c->prof_flops.size() >= 4096) prof_collect(c);
-        HIP_CHECK(hipEventRecord(prof_event(c), c->stream));
+        CtxProbe pr(c);
+        pr.begin(PK_GEMM, c->stream);
         gemm_f64(g, c->stream);
-        HIP_CHECK(hipEventRecord(prof_event(c), c->stream));
-        c->prof_flops.push_back(2.0 * M * N * (double)K);
+        pr.end(PK_GEMM, c->stream);
+        pr.work(PK_GEMM, 2.0 * M * N * (double)K,
+                8.0 * ((double)M * K + (double)K * N + (C && beta != 0.0 ? 2.0 : 1.0) * (double)M * N));
         return;
     }
     gemm_f64(g, c->stream);
@@ -368,7 +394,9 @@ SplitResult split(ite_ctx* c, int dir, int Dl, int d1, int d2, int Dr, const dou
     }
     double* host = pinned(c, (size_t)p + 64);
     const double tol = 8.0 * std::sqrt((double)std::max(q, 1)) * 2.220446049250313e-16;
-    JacobiResult jr = jacobi_rows(Z, pj, q, ld, tol, 60, gram, rot, off, host, c->stream);
+    CtxProbe probe(c);
+    JacobiResult jr = jacobi_rows(Z, pj, q, ld, tol, 60, gram, rot, off, host, c->stream,
+                                  c->prof_on ? &probe : nullptr);
     row_norms(Z, p, q, ld, norms, c->stream);
     d2h(c, host, norms, p);
     sync(c);

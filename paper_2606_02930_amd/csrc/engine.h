@@ -35,13 +35,17 @@ struct ite_ctx {
     size_t pinned_bytes = 0;
     std::vector<hipEvent_t> events;
     size_t events_used = 0;
-    // GEMM launch profiler: event pairs around each GEMM launch
+    // launch profiler (observability): FP64 GEMM launches are all timed,
+    // Jacobi launches every `jac_period`-th of a kind; see LaunchProbe
     bool prof_on = false;
+    int jac_period = 8;
     std::vector<hipEvent_t> prof_events;
     size_t prof_used = 0;
-    std::vector<double> prof_flops;    // algorithmic flops (2 M N K) per recorded launch
-    long long prof_launches = 0;
-    double prof_ms = 0.0, prof_total_flops = 0.0;
+    std::vector<int> prof_kind;                 // kind of each recorded event pair
+    long long prof_launches[ite::PK_COUNT] = {};
+    long long prof_timed[ite::PK_COUNT] = {};
+    double prof_ms[ite::PK_COUNT] = {};
+    double prof_flops[ite::PK_COUNT] = {}, prof_bytes[ite::PK_COUNT] = {};
 };
 
 // Sparse small matrix in CSR form on the device.

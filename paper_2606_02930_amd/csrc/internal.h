@@ -112,13 +112,24 @@ void nonfinite_any(const double* x, size_t n, int* flag, hipStream_t s);
 // out[j][i] = in[i][j]  (rows x cols -> cols x rows)
 void transpose(const double* in, int rows, int cols, double* out, hipStream_t s);
 
+// Observability of kernel launches: every launch of a kind is counted, some
+// are bracketed by events (begin returns true for those), and the
+// algorithmic work actually done is added once it is known.
+enum ProbeKind { PK_GEMM = 0, PK_GRAM = 1, PK_INNER = 2, PK_ROTATE = 3, PK_COUNT = 4 };
+struct LaunchProbe {
+    virtual ~LaunchProbe() = default;
+    virtual bool begin(int kind, hipStream_t s) = 0;
+    virtual void end(int kind, hipStream_t s) = 0;
+    virtual void work(int kind, double flops, double bytes) = 0;
+};
+
 // One-sided Jacobi on the rows of Z[p][ld] (the first q columns are the
-// matrix whose rows are orthogonalised; all ld columns are rotated).
-struct JacobiWork;
+// matrix whose rows are orthogonalised; all ld columns are rotated).  probe
+// may be null.
 struct JacobiResult { int sweeps = 0; double last_off = 0.0; };
 JacobiResult jacobi_rows(double* Z, int p, int q, int ld, double tol, int max_sweeps,
                          double* gram_ws, double* rot_ws, double* off_ws, double* host_off,
-                         hipStream_t s);
+                         hipStream_t s, LaunchProbe* probe = nullptr);
 // Build the Jacobi work matrix [theta | I_m] (dir 0) or [theta^T | I_n]
 // (dir 1) for theta m x n; leading dimension m + n.
 void jacobi_input(const double* theta, int m, int n, int dir, double* Z, hipStream_t s);

@@ -59,18 +59,28 @@ __device__ inline int pair_row(int P, int lr, int r, int nb) {
 
 template <int RB>
 __global__ __launch_bounds__(256) void gram_kernel(const double* __restrict__ Z, int p, int q, int ld, int r,
-                                                   int nb, int nchunks, double* __restrict__ gram) {
+                                                   int nb, int nchunks, double* __restrict__ gram,
+                                                   unsigned long long* __restrict__ work) {
     constexpr int PR = Blk<RB>::PR, GW = Blk<RB>::GW;
     __shared__ double Xs[PR][GW + 1];
     const int P = blockIdx.y, chunk = blockIdx.x;
     const int c0 = chunk * GW;
     const int t = threadIdx.x;
-    for (int e = t; e < PR * GW; e += 256) {
-        const int lr = e / GW, cc = e % GW;
+    {
+        // all PR * GW / 256 loads of a thread in flight together
+        constexpr int RPP = 256 / GW, NPASS = PR / RPP;
+        const int cc = t % GW, lr0 = t / GW;
         const int c = c0 + cc;
-        const int row = pair_row<RB>(P, lr, r, nb);
-        Xs[lr][cc] = (row < p && c < q) ? Z[(long)row * ld + c] : 0.0;
+        double v[NPASS];
+#pragma unroll
+        for (int u = 0; u < NPASS; ++u) {
+            const int row = pair_row<RB>(P, lr0 + RPP * u, r, nb);
+            v[u] = (row < p && c < q) ? Z[(long)row * ld + c] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < NPASS; ++u) Xs[lr0 + RPP * u][cc] = v[u];
     }
+    if (t == 0) atomicAdd(work, 1ull);
     __syncthreads();
     const int lane = t & 63, w = t >> 6;
     const int l16 = lane & 15, kg = lane >> 4;
@@ -152,7 +162,8 @@ __global__ __launch_bounds__(Blk<RB>::NT) void inner_kernel(const double* __rest
                                                             int r, int nb, double tol, double kappa,
                                                             double sigma1sq, double* __restrict__ rot,
                                                             int* __restrict__ rotated,
-                                                            double* __restrict__ sweep_off) {
+                                                            double* __restrict__ sweep_off,
+                                                            unsigned long long* __restrict__ work) {
     constexpr int PR = Blk<RB>::PR, NT = Blk<RB>::NT, XS = Blk<RB>::XS, EPT = PR / XS;
     constexpr int QPT = RB * RB / NT, IS = NT / RB;     // 2 x 2 blocks per thread, their row stride
     constexpr int JPT = RB * PR / NT, JS = NT / PR;     // row-pair entries of A per thread, their stride
@@ -169,22 +180,23 @@ __global__ __launch_bounds__(Blk<RB>::NT) void inner_kernel(const double* __rest
     const int y = t % PR, xh = t / PR;
     const double* src = gram + (long)P * nchunks * (PR * PR);
     {
-        // two chunks per step so that 2 EPT loads are in flight together
+        // four chunks per step so that 4 EPT loads are in flight together
+        // (the summation order is fixed: results do not depend on timing)
         double s[EPT];
 #pragma unroll
         for (int u = 0; u < EPT; ++u) s[u] = 0.0;
         int c = 0;
-        for (; c + 1 < nchunks; c += 2) {
+        for (; c + 3 < nchunks; c += 4) {
             const double* g = src + (long)c * PR * PR + y;
-            double v[2][EPT];
+            double v[4][EPT];
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
+            for (int h = 0; h < 4; ++h)
 #pragma unroll
                 for (int u = 0; u < EPT; ++u) v[h][u] = g[(long)h * PR * PR + (xh + XS * u) * PR];
 #pragma unroll
-            for (int u = 0; u < EPT; ++u) s[u] += v[0][u] + v[1][u];
+            for (int u = 0; u < EPT; ++u) s[u] += (v[0][u] + v[1][u]) + (v[2][u] + v[3][u]);
         }
-        if (c < nchunks) {
+        for (; c < nchunks; ++c) {
             const double* g = src + (long)c * PR * PR + y;
 #pragma unroll
             for (int u = 0; u < EPT; ++u) s[u] += g[(xh + XS * u) * PR];
@@ -238,6 +250,7 @@ __global__ __launch_bounds__(Blk<RB>::NT) void inner_kernel(const double* __rest
         if (t == 0) rotated[P] = 0;
         return;
     }
+    if (t == 0) atomicAdd(work, 1ull);
     // fixed per thread: the column pair j of its 2 x 2 blocks, the column l of
     // its entries of A
     const int jq = t % RB;
@@ -376,11 +389,13 @@ __global__ __launch_bounds__(Blk<RB>::NT) void inner_kernel(const double* __rest
 template <int RB>
 __global__ __launch_bounds__(256) void rotate_kernel(double* __restrict__ Z, int p, int ld, int r, int nb,
                                                      const double* __restrict__ rot,
-                                                     const int* __restrict__ rotated) {
+                                                     const int* __restrict__ rotated,
+                                                     unsigned long long* __restrict__ work) {
     constexpr int PR = Blk<RB>::PR;
     constexpr int NTM = PR / 16, KS = PR / 4, CT = RCOLS / 64;   // row tiles, k steps, column tiles per wave
     const int P = blockIdx.y;
     if (!rotated[P]) return;
+    if (threadIdx.x == 0) atomicAdd(work, 1ull);
     __shared__ double Qs[PR][PR + 1];        // Q[k][m]
     const double* src = rot + (long)P * PR * PR;
     const int t = threadIdx.x;
@@ -508,13 +523,13 @@ void ws_sizes(int p, int q, size_t* gram, size_t* rot, size_t* off) {
     const size_t npairs = nb / 2, nchunks = std::max(1, (q + GW - 1) / GW);
     *gram = npairs * nchunks * PR * PR;
     *rot = npairs * PR * PR;
-    *off = npairs + 16;
+    *off = npairs + 24;
 }
 
 template <int RB>
 JacobiResult run_jacobi(double* Z, int p, int q, int ld, double tol, int max_sweeps, double* gram_ws,
-                        double* rot_ws, double* off_ws, double* host_off, hipStream_t s) {
-    constexpr int GW = Blk<RB>::GW, NT = Blk<RB>::NT;
+                        double* rot_ws, double* off_ws, double* host_off, hipStream_t s, LaunchProbe* probe) {
+    constexpr int GW = Blk<RB>::GW, NT = Blk<RB>::NT, PR = Blk<RB>::PR;
     JacobiResult res;
     int nb = (p + RB - 1) / RB;
     if (nb < 2) nb = 2;
@@ -523,19 +538,28 @@ JacobiResult run_jacobi(double* Z, int p, int q, int ld, double tol, int max_swe
     const int nchunks = std::max(1, (q + GW - 1) / GW);
     const int nrot = (ld + RCOLS - 1) / RCOLS;
     // off_ws[0]: largest off-diagonal measure of the sweep, off_ws[1]: largest
-    // row norm squared seen in it, then one int per pair (rotated flag)
+    // row norm squared seen in it, then one int per pair (rotated flag), then
+    // three work counters (gram chunks, inner pairs, rotated chunks)
     int* rotated = reinterpret_cast<int*>(off_ws + 2);
+    unsigned long long* work = reinterpret_cast<unsigned long long*>(off_ws + 2 + npairs);
+    if (probe) fill(off_ws + 2 + npairs, 0.0, 3, s);
     constexpr double kappa = 1e-3;
     double prev = 1e300, sigma1sq = 0.0;
     for (int sw = 0; sw < max_sweeps; ++sw) {
         fill(off_ws, 0.0, 2, s);
         for (int r = 0; r < nb - 1; ++r) {
+            bool timed = probe && probe->begin(PK_GRAM, s);
             hipLaunchKernelGGL((gram_kernel<RB>), dim3(nchunks, npairs), dim3(256), 0, s, Z, p, q, ld, r, nb,
-                               nchunks, gram_ws);
+                               nchunks, gram_ws, work);
+            if (timed) probe->end(PK_GRAM, s);
+            timed = probe && probe->begin(PK_INNER, s);
             hipLaunchKernelGGL((inner_kernel<RB>), dim3(npairs), dim3(NT), 0, s, gram_ws, nchunks, p, r, nb, tol,
-                               kappa, sigma1sq, rot_ws, rotated, off_ws);
+                               kappa, sigma1sq, rot_ws, rotated, off_ws, work + 1);
+            if (timed) probe->end(PK_INNER, s);
+            timed = probe && probe->begin(PK_ROTATE, s);
             hipLaunchKernelGGL((rotate_kernel<RB>), dim3(nrot, npairs), dim3(256), 0, s, Z, p, ld, r, nb, rot_ws,
-                               rotated);
+                               rotated, work + 2);
+            if (timed) probe->end(PK_ROTATE, s);
         }
         HIP_CHECK(hipGetLastError());
         HIP_CHECK(hipMemcpyAsync(host_off, off_ws, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -548,6 +572,20 @@ JacobiResult run_jacobi(double* Z, int p, int q, int ld, double tol, int max_swe
         if (sw >= 3 && *host_off > 0.5 * prev && *host_off < 1e3 * tol) break;
         prev = *host_off;
     }
+    if (probe) {
+        // algorithmic work actually done: a chunk Gram is 2 PR^2 GW flops over
+        // PR GW doubles read; a pair's inner sweep applies PR (PR - 1) / 2
+        // rotations to two rows and two columns of G and two rows of Q
+        // (18 PR flops each) plus the Newton-Schulz step (4 PR^3); a rotated
+        // chunk is 2 PR^2 RCOLS flops over 2 PR RCOLS doubles read and written
+        unsigned long long cnt[3];
+        HIP_CHECK(hipMemcpyAsync(cnt, work, sizeof(cnt), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        const double pr = PR;
+        probe->work(PK_GRAM, cnt[0] * 2.0 * pr * pr * GW, cnt[0] * 8.0 * pr * GW);
+        probe->work(PK_INNER, cnt[1] * (9.0 * pr * pr * (pr - 1) + 4.0 * pr * pr * pr), cnt[1] * 8.0 * 2 * pr * pr);
+        probe->work(PK_ROTATE, cnt[2] * 2.0 * pr * pr * RCOLS, cnt[2] * 16.0 * pr * RCOLS);
+    }
     return res;
 }
 
@@ -559,10 +597,11 @@ void jacobi_workspace(int p, int q, size_t* gram, size_t* rot, size_t* off) {
 }
 
 JacobiResult jacobi_rows(double* Z, int p, int q, int ld, double tol, int max_sweeps, double* gram_ws,
-                         double* rot_ws, double* off_ws, double* host_off, hipStream_t s) {
+                         double* rot_ws, double* off_ws, double* host_off, hipStream_t s, LaunchProbe* probe) {
     if (p <= 1) return JacobiResult{};
-    if (block_rows(p) == 32) return run_jacobi<32>(Z, p, q, ld, tol, max_sweeps, gram_ws, rot_ws, off_ws, host_off, s);
-    return run_jacobi<16>(Z, p, q, ld, tol, max_sweeps, gram_ws, rot_ws, off_ws, host_off, s);
+    if (block_rows(p) == 32)
+        return run_jacobi<32>(Z, p, q, ld, tol, max_sweeps, gram_ws, rot_ws, off_ws, host_off, s, probe);
+    return run_jacobi<16>(Z, p, q, ld, tol, max_sweeps, gram_ws, rot_ws, off_ws, host_off, s, probe);
 }
 
 void row_norms(const double* Z, int p, int q, int ld, double* norms, hipStream_t s) {
