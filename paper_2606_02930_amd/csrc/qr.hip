@@ -15,6 +15,8 @@
 // column j, each lane 32 of its rows), writes the reflectors V and the
 // triangular factor T with H_1 ... H_QB = I - V T V^T, and the trailing
 // columns are updated as Z_t <- Z_t - V (T^T (V^T Z_t)) with FP64 MFMA GEMMs.
+// The reflectors are kept transposed (one row per reflector) so that they are
+// written and read in whole rows.
 #include "internal.h"
 
 #include <algorithm>
@@ -35,10 +37,14 @@ __device__ inline double wave_sum(double v) {
 
 // Factor the m x nbw panel at P (leading dimension ld), nbw <= QB, m <= 2048.
 // Writes R (upper triangle) and zeros below it into the panel, the reflectors
-// to V [vrows][QB] (row-major, unit diagonal, zero above the diagonal and in
-// rows m..vrows-1 and columns nbw..QB-1) and T [QB][QB] (upper triangular).
-__global__ __launch_bounds__(1024) void qr_panel_kernel(double* __restrict__ P, int ld, int m, int nbw, int vrows,
-                                                        double* __restrict__ V, double* __restrict__ T) {
+// transposed to VT [QB][m] (row j = reflector j: zero above row j, one at row
+// j; rows nbw..QB-1 zero) and T [QB][QB] (upper triangular).  The panel moves
+// between memory and the wavefronts' registers through LDS in chunks of
+// QCH rows, so that every global access reads or writes whole rows.
+constexpr int QCH = 512;
+__global__ __launch_bounds__(1024) void qr_panel_kernel(double* __restrict__ P, int ld, int m, int nbw,
+                                                        double* __restrict__ VT, double* __restrict__ T) {
+    __shared__ double Pc[QCH][QB + 1];
     __shared__ double vs[64 * QRPL];
     __shared__ double tau_s[QB];
     __shared__ double Sp[16][QB][QB + 1];
@@ -48,9 +54,23 @@ __global__ __launch_bounds__(1024) void qr_panel_kernel(double* __restrict__ P, 
     const bool own = w < nbw;
     double a[QRPL];
 #pragma unroll
-    for (int i = 0; i < QRPL; ++i) {
-        const int row = lane + 64 * i;
-        a[i] = (own && row < m) ? P[(long)row * ld + w] : 0.0;
+    for (int i = 0; i < QRPL; ++i) a[i] = 0.0;
+    // coalesced load: thread t moves 8 consecutive entries of row t / 2
+    for (int c0 = 0; c0 < 64 * QRPL; c0 += QCH) {
+        {
+            const int rr = t >> 1, h = (t & 1) * 8;
+            const int row = c0 + rr;
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                Pc[rr][h + e] = (row < m && h + e < nbw) ? P[(long)row * ld + h + e] : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < QRPL; ++i) {
+            const int row = lane + 64 * i;
+            if (row >= c0 && row < c0 + QCH) a[i] = Pc[row - c0][w];
+        }
+        __syncthreads();
     }
     for (int j = 0; j < nbw; ++j) {
         if (w == j) {
@@ -82,7 +102,7 @@ __global__ __launch_bounds__(1024) void qr_panel_kernel(double* __restrict__ P, 
             if (lane == 0) tau_s[j] = tau;
         }
         __syncthreads();
-        for (int row = t; row < vrows; row += 1024) V[(long)row * QB + j] = vs[row];
+        for (int row = t; row < m; row += 1024) VT[(long)j * m + row] = vs[row];
         if (own && w > j) {
             const double tau = tau_s[j];
             double dot = 0.0;
@@ -96,16 +116,25 @@ __global__ __launch_bounds__(1024) void qr_panel_kernel(double* __restrict__ P, 
         }
         __syncthreads();
     }
+    // coalesced write-back of R and the zeros below it
+    for (int c0 = 0; c0 < 64 * QRPL; c0 += QCH) {
 #pragma unroll
-    for (int i = 0; i < QRPL; ++i) {
-        const int row = lane + 64 * i;
-        if (own && row < m) P[(long)row * ld + w] = a[i];
+        for (int i = 0; i < QRPL; ++i) {
+            const int row = lane + 64 * i;
+            if (row >= c0 && row < c0 + QCH) Pc[row - c0][w] = a[i];
+        }
+        __syncthreads();
+        {
+            const int rr = t >> 1, h = (t & 1) * 8;
+            const int row = c0 + rr;
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                if (row < m && h + e < nbw) P[(long)row * ld + h + e] = Pc[rr][h + e];
+        }
+        __syncthreads();
     }
-    // unused columns of V and rows m..vrows-1
-    for (int e = t; e < vrows * QB; e += 1024) {
-        const int row = e / QB, col = e % QB;
-        if (col >= nbw || row >= m) V[e] = 0.0;
-    }
+    // reflector rows nbw..QB-1 are zero
+    for (int e = t; e < (QB - nbw) * m; e += 1024) VT[(long)nbw * m + e] = 0.0;
     if (t < QB && t >= nbw) tau_s[t] = 0.0;
     __syncthreads();
     // S = V^T V with FP64 MFMA, the rows split over the 16 wavefronts
@@ -116,7 +145,7 @@ __global__ __launch_bounds__(1024) void qr_panel_kernel(double* __restrict__ P, 
         const int r0 = w * rows_per_wave, r1 = min(m, r0 + rows_per_wave);
         for (int k0 = r0; k0 < r1; k0 += 4) {
             const int row = k0 + kg;
-            const double v = (row < r1) ? V[(long)row * QB + l16] : 0.0;
+            const double v = (row < r1) ? VT[(long)l16 * m + row] : 0.0;
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v, v, acc, 0, 0, 0);
         }
 #pragma unroll
@@ -184,8 +213,8 @@ size_t householder_workspace(int p, int q, int ld) {
 
 void householder_rows(double* Z, int p, int q, int ld, double* ws, hipStream_t s) {
     const int kmax = std::min(p, q);
-    double* V = ws;
-    double* T = V + (size_t)p * QB;
+    double* VT = ws;
+    double* T = VT + (size_t)p * QB;
     double* Wp = T + QB * QB;
     const int nchunk_max = (p + QKC - 1) / QKC;
     double* W2 = Wp + (size_t)nchunk_max * QB * ld;
@@ -193,7 +222,7 @@ void householder_rows(double* Z, int p, int q, int ld, double* ws, hipStream_t s
         const int nbw = std::min(QB, kmax - c0);
         const int m = p - c0;
         double* P = Z + (long)c0 * ld + c0;
-        hipLaunchKernelGGL(qr_panel_kernel, dim3(1), dim3(1024), 0, s, P, ld, m, nbw, m, V, T);
+        hipLaunchKernelGGL(qr_panel_kernel, dim3(1), dim3(1024), 0, s, P, ld, m, nbw, VT, T);
         const int nt = ld - (c0 + nbw);
         if (nt <= 0) continue;
         double* Zt = P + nbw;
@@ -202,8 +231,8 @@ void householder_rows(double* Z, int p, int q, int ld, double* ws, hipStream_t s
         const int nfull = m / QKC, rem = m % QKC;
         if (nfull > 0) {
             Gemm g;
-            g.M = QB; g.N = nt; g.K = QKC; g.tA = true; g.tB = false;
-            g.A = V; g.lda = QB; g.sA = (long)QKC * QB;
+            g.M = QB; g.N = nt; g.K = QKC;
+            g.A = VT; g.lda = m; g.sA = QKC;
             g.B = Zt; g.ldb = ld; g.sB = (long)QKC * ld;
             g.D = Wp; g.ldd = nt; g.sD = (long)QB * nt;
             g.batch = nfull;
@@ -211,18 +240,18 @@ void householder_rows(double* Z, int p, int q, int ld, double* ws, hipStream_t s
         }
         if (rem > 0) {
             Gemm g;
-            g.M = QB; g.N = nt; g.K = rem; g.tA = true; g.tB = false;
-            g.A = V + (long)nfull * QKC * QB; g.lda = QB;
+            g.M = QB; g.N = nt; g.K = rem;
+            g.A = VT + (long)nfull * QKC; g.lda = m;
             g.B = Zt + (long)nfull * QKC * ld; g.ldb = ld;
             g.D = Wp + (long)nfull * QB * nt; g.ldd = nt;
             gemm_f64(g, s);
         }
         const int nchunk = nfull + (rem > 0 ? 1 : 0);
         hipLaunchKernelGGL(qr_reduce_t_kernel, dim3((nt + 63) / 64), dim3(1024), 0, s, Wp, nchunk, nt, T, W2);
-        // Zt -= V W2
+        // Zt -= V W2 (V = VT^T)
         Gemm u;
-        u.M = m; u.N = nt; u.K = QB; u.alpha = -1.0; u.beta = 1.0;
-        u.A = V; u.lda = QB;
+        u.M = m; u.N = nt; u.K = QB; u.tA = true; u.alpha = -1.0; u.beta = 1.0;
+        u.A = VT; u.lda = m;
         u.B = W2; u.ldb = nt;
         u.C = Zt; u.ldc = ld;
         u.D = Zt; u.ldd = ld;

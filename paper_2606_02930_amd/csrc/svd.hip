@@ -37,6 +37,7 @@ template <int RB> struct Blk {
     static constexpr int PR = 2 * RB;              // rows per pair
     static constexpr int NT = PR * PR / 8;         // inner threads: 8 entries of a PR x PR matrix each
     static constexpr int XS = NT / PR;             // row stride of a thread's entries
+    static constexpr int NTI = NT + 64;            // inner kernel: NT update threads + one angle wavefront
     static constexpr int GW = RB == 16 ? 256 : 128;   // columns per gram chunk
 };
 
@@ -132,6 +133,17 @@ __device__ inline int ring_next(int pos) {
     return pos - 1;
 }
 
+// Position in round k of the row that is at `pos` in round k + 1.
+template <int PR>
+__device__ inline int ring_prev(int pos) {
+    constexpr int H = PR / 2;
+    if (pos == 0) return 0;
+    if (pos == 1) return H;
+    if (pos < H) return pos - 1;
+    if (pos == PR - 1) return H - 1;
+    return pos + 1;
+}
+
 // Local row held at position `pos` in round k (0 <= k < PR - 1).
 template <int PR>
 __device__ inline int ring_row(int pos, int k) {
@@ -143,6 +155,44 @@ __device__ inline int ring_row(int pos, int k) {
     return r0 <= H - 2 ? r0 + 1 : H + (PR - 2 - r0);
 }
 
+// Jacobi angle of the pair (a, b) with Gram entries g_aa, g_bb, g_ab:
+// tan(theta) = sign(x) y / (|x| + hypot(x, y)), x = g_bb - g_aa, y = 2 g_ab;
+// new_a = c a - s b, new_b = s a + c b.  Of the two diagonalising angles the
+// one that leaves the larger row at the lower local index (a_low: a has the
+// lower index) is taken.  Returns whether the pair rotates.
+__device__ inline bool jacobi_angle(double gaa, double gbb, double gab, bool a_low, double& c, double& s) {
+    c = 1.0;
+    s = 0.0;
+    if (gab == 0.0) return false;
+    const double x = gbb - gaa, yy = 2.0 * gab;
+    const double tt = (x >= 0.0 ? yy : -yy) / (fabs(x) + sqrt(x * x + yy * yy));
+    c = rsqrt(1.0 + tt * tt);
+    s = tt * c;
+    const double naa = c * c * gaa - 2.0 * c * s * gab + s * s * gbb;
+    const double nbb = s * s * gaa + 2.0 * c * s * gab + c * c * gbb;
+    if (a_low ? (naa < nbb) : (naa > nbb)) {
+        const double c0 = c;
+        c = -s;
+        s = c0;
+    }
+    return true;
+}
+
+// Entry (x, y) of G' = J G J^T for positions x, y of the current round, J the
+// round's rotations (cc, ss by pair index): the same expressions as the 2 x 2
+// block updates of inner_kernel.
+template <int RB>
+__device__ inline double rotated_entry(const double (*G)[2 * RB + 1], const double* cc, const double* ss, int x,
+                                       int y) {
+    const bool rx = x >= RB, ry = y >= RB;
+    const int i = rx ? x - RB : x, j = ry ? y - RB : y;
+    const double ci = cc[i], si = ss[i], cj = cc[j], sj = ss[j];
+    const double g00 = G[i][j], g01 = G[i][j + RB], g10 = G[i + RB][j], g11 = G[i + RB][j + RB];
+    const double t0 = rx ? si * g00 + ci * g10 : ci * g00 - si * g10;
+    const double t1 = rx ? si * g01 + ci * g11 : ci * g01 - si * g11;
+    return ry ? t0 * sj + t1 * cj : t0 * cj - t1 * sj;
+}
+
 // One workgroup per pair: sum the chunk partials, then one cyclic sweep of
 // two-sided Jacobi rotations on the PR x PR Gram matrix (each rotation the
 // one of the two diagonalising angles that keeps the larger row at the lower
@@ -151,35 +201,40 @@ __device__ inline int ring_row(int pos, int k) {
 // applied.  sigma1sq: largest row norm squared seen in the previous sweep
 // (0: use this pair's own).
 //
-// Per round the RB rotation angles are computed by RB lanes; then G' = J G J^T
-// is formed as RB x RB independent 2 x 2 block updates (rows and columns
-// {i, i + RB} x {j, j + RB}) and the accumulated rotation A' = J A as row-pair
-// updates, both written straight to the next round's positions in the other
-// LDS buffer.  A holds the new rows (positions) against the original local
-// rows (columns); Q = A^T.
+// NT threads form G' = J G J^T of each round as RB x RB independent 2 x 2
+// block updates (rows and columns {i, i + RB} x {j, j + RB}) and the
+// accumulated rotation A' = J A as row-pair updates, both written straight to
+// the next round's positions in the other LDS buffer.  A holds the new rows
+// (positions) against the original local rows (columns); Q = A^T.  One more
+// wavefront computes the angles one round ahead: from G and the angles of
+// round k it forms the three entries of G' each pair of round k + 1 needs and
+// that pair's angle, while the update of round k runs, so a round costs one
+// barrier.
 template <int RB>
-__global__ __launch_bounds__(Blk<RB>::NT) void inner_kernel(const double* __restrict__ gram, int nchunks, int p,
-                                                            int r, int nb, double tol, double kappa,
-                                                            double sigma1sq, double* __restrict__ rot,
-                                                            int* __restrict__ rotated,
-                                                            double* __restrict__ sweep_off,
-                                                            unsigned long long* __restrict__ work) {
+__global__ __launch_bounds__(Blk<RB>::NTI) void inner_kernel(const double* __restrict__ gram, int nchunks, int p,
+                                                             int r, int nb, double tol, double kappa,
+                                                             double sigma1sq, double* __restrict__ rot,
+                                                             int* __restrict__ rotated,
+                                                             double* __restrict__ sweep_off,
+                                                             unsigned long long* __restrict__ work) {
     constexpr int PR = Blk<RB>::PR, NT = Blk<RB>::NT, XS = Blk<RB>::XS, EPT = PR / XS;
     constexpr int QPT = RB * RB / NT, IS = NT / RB;     // 2 x 2 blocks per thread, their row stride
     constexpr int JPT = RB * PR / NT, JS = NT / PR;     // row-pair entries of A per thread, their stride
-    constexpr int NW = NT / 64, NTL = PR / 16;          // wavefronts, 16 x 16 tiles per side
+    constexpr int NW = NT / 64, NTL = PR / 16;          // update wavefronts, 16 x 16 tiles per side
     static_assert(QPT * NT == RB * RB && JPT * NT == RB * PR && EPT * NT == PR * PR, "thread layout");
     static_assert((NTL * NTL) % NW == 0, "tiles per wavefront");
     __shared__ double Gb[2][PR][PR + 1];
     __shared__ double Ab[2][PR][PR + 1];
-    __shared__ double cc[RB], ss[RB];
+    __shared__ double cc[2][RB], ss[2][RB];
     __shared__ double red[NW];
     __shared__ int anyrot;
     const int P = blockIdx.x;
     const int t = threadIdx.x;
+    const bool upd = t < NT;                      // update thread (else: the angle wavefront)
+    const int al = t - NT;                        // lane of the angle wavefront
     const int y = t % PR, xh = t / PR;
     const double* src = gram + (long)P * nchunks * (PR * PR);
-    {
+    if (upd) {
         // four chunks per step so that 4 EPT loads are in flight together
         // (the summation order is fixed: results do not depend on timing)
         double s[EPT];
@@ -211,13 +266,15 @@ __global__ __launch_bounds__(Blk<RB>::NT) void inner_kernel(const double* __rest
     if (t == 0) anyrot = 0;
     __syncthreads();
     // symmetrise (the two triangles come from different MFMA tiles)
+    if (upd) {
 #pragma unroll
-    for (int u = 0; u < EPT; ++u) {
-        const int x = xh + XS * u;
-        if (x < y) {
-            const double v = 0.5 * (Gb[0][x][y] + Gb[0][y][x]);
-            Gb[0][x][y] = v;
-            Gb[0][y][x] = v;
+        for (int u = 0; u < EPT; ++u) {
+            const int x = xh + XS * u;
+            if (x < y) {
+                const double v = 0.5 * (Gb[0][x][y] + Gb[0][y][x]);
+                Gb[0][x][y] = v;
+                Gb[0][y][x] = v;
+            }
         }
     }
     __syncthreads();
@@ -226,7 +283,7 @@ __global__ __launch_bounds__(Blk<RB>::NT) void inner_kernel(const double* __rest
     for (int i = 0; i < PR; ++i) gmax_local = fmax(gmax_local, Gb[0][i][i]);
     const double kappa_s1 = kappa * sqrt(fmax(sigma1sq, gmax_local));
     double off = 0.0;
-    {
+    if (upd) {
         const double gyy = Gb[0][y][y];
 #pragma unroll
         for (int u = 0; u < EPT; ++u) {
@@ -238,7 +295,7 @@ __global__ __launch_bounds__(Blk<RB>::NT) void inner_kernel(const double* __rest
         }
     }
     for (int o = 32; o > 0; o >>= 1) off = fmax(off, __shfl_xor(off, o, 64));
-    if ((t & 63) == 0) red[t >> 6] = off;
+    if (upd && (t & 63) == 0) red[t >> 6] = off;
     __syncthreads();
     off = red[0];
     for (int i = 1; i < NW; ++i) off = fmax(off, red[i]);
@@ -251,49 +308,31 @@ __global__ __launch_bounds__(Blk<RB>::NT) void inner_kernel(const double* __rest
         return;
     }
     if (t == 0) atomicAdd(work, 1ull);
-    // fixed per thread: the column pair j of its 2 x 2 blocks, the column l of
-    // its entries of A
+    // angles of round 0
+    if (!upd && al < RB) {
+        double c, s;
+        if (jacobi_angle(Gb[0][al][al], Gb[0][al + RB][al + RB], Gb[0][al][al + RB],
+                         ring_row<PR>(al, 0) < ring_row<PR>(al + RB, 0), c, s))
+            anyrot = 1;
+        cc[0][al] = c;
+        ss[0][al] = s;
+    }
+    __syncthreads();
+    // fixed per update thread: the column pair j of its 2 x 2 blocks, the
+    // column l of its entries of A
     const int jq = t % RB;
     const int pj0 = ring_next<PR>(jq), pj1 = ring_next<PR>(jq + RB);
     const int la = t % PR;
     int cur = 0;
     for (int k = 0; k < PR - 1; ++k) {
-        if (t < RB) {
-            // Jacobi angle of the pair (a, b) = positions (i, i + RB):
-            // tan(theta) = sign(x) y / (|x| + hypot(x, y)), x = g_bb - g_aa,
-            // y = 2 g_ab; new_a = c a - s b, new_b = s a + c b
-            const int i = t;
-            const double gaa = Gb[cur][i][i], gbb = Gb[cur][i + RB][i + RB], gab = Gb[cur][i][i + RB];
-            double c = 1.0, s = 0.0;
-            if (gab != 0.0) {
-                const double x = gbb - gaa, yy = 2.0 * gab;
-                const double tt = (x >= 0.0 ? yy : -yy) / (fabs(x) + sqrt(x * x + yy * yy));
-                c = rsqrt(1.0 + tt * tt);
-                s = tt * c;
-                // take the other diagonalising angle if this one leaves the
-                // larger row at the higher local index
-                const double naa = c * c * gaa - 2.0 * c * s * gab + s * s * gbb;
-                const double nbb = s * s * gaa + 2.0 * c * s * gab + c * c * gbb;
-                const bool a_low = ring_row<PR>(i, k) < ring_row<PR>(i + RB, k);
-                if (a_low ? (naa < nbb) : (naa > nbb)) {
-                    const double c0 = c;
-                    c = -s;
-                    s = c0;
-                }
-                anyrot = 1;
-            }
-            cc[i] = c;
-            ss[i] = s;
-        }
-        __syncthreads();
-        const int nxt = cur ^ 1;
-        {
-            const double cj = cc[jq], sj = ss[jq];
+        const int pb = k & 1, nxt = cur ^ 1;
+        if (upd) {
+            const double cj = cc[pb][jq], sj = ss[pb][jq];
             double nv[QPT][4];
 #pragma unroll
             for (int u = 0; u < QPT; ++u) {
                 const int i = t / RB + IS * u;
-                const double ci = cc[i], si = ss[i];
+                const double ci = cc[pb][i], si = ss[pb][i];
                 const double g00 = Gb[cur][i][jq], g01 = Gb[cur][i][jq + RB];
                 const double g10 = Gb[cur][i + RB][jq], g11 = Gb[cur][i + RB][jq + RB];
                 const double t00 = ci * g00 - si * g10, t01 = ci * g01 - si * g11;
@@ -307,7 +346,7 @@ __global__ __launch_bounds__(Blk<RB>::NT) void inner_kernel(const double* __rest
 #pragma unroll
             for (int u = 0; u < JPT; ++u) {
                 const int i = t / PR + JS * u;
-                const double ci = cc[i], si = ss[i];
+                const double ci = cc[pb][i], si = ss[pb][i];
                 const double a0 = Ab[cur][i][la], a1 = Ab[cur][i + RB][la];
                 na[u][0] = ci * a0 - si * a1;
                 na[u][1] = si * a0 + ci * a1;
@@ -327,6 +366,18 @@ __global__ __launch_bounds__(Blk<RB>::NT) void inner_kernel(const double* __rest
                 Ab[nxt][ring_next<PR>(i)][la] = na[u][0];
                 Ab[nxt][ring_next<PR>(i + RB)][la] = na[u][1];
             }
+        } else if (al < RB && k + 1 < PR - 1) {
+            // pair al of round k + 1 sits at positions (al, al + RB) then,
+            // i.e. at (a, b) now
+            const int a = ring_prev<PR>(al), b = ring_prev<PR>(al + RB);
+            const double gaa = rotated_entry<RB>(Gb[cur], cc[pb], ss[pb], a, a);
+            const double gbb = rotated_entry<RB>(Gb[cur], cc[pb], ss[pb], b, b);
+            const double gab = rotated_entry<RB>(Gb[cur], cc[pb], ss[pb], a, b);
+            double c, s;
+            if (jacobi_angle(gaa, gbb, gab, ring_row<PR>(al, k + 1) < ring_row<PR>(al + RB, k + 1), c, s))
+                anyrot = 1;
+            cc[pb ^ 1][al] = c;
+            ss[pb ^ 1][al] = s;
         }
         __syncthreads();
         cur = nxt;
@@ -343,41 +394,47 @@ __global__ __launch_bounds__(Blk<RB>::NT) void inner_kernel(const double* __rest
     const int l16 = lane & 15, kg = lane >> 4;
     constexpr int TPW = NTL * NTL / NW;
     // S = A A^T
+    if (upd) {
 #pragma unroll
-    for (int i = 0; i < TPW; ++i) {
-        const int tile = w + NW * i;
-        const int tm = tile / NTL, tn = tile % NTL;
-        d4_t acc = {0, 0, 0, 0};
+        for (int i = 0; i < TPW; ++i) {
+            const int tile = w + NW * i;
+            const int tm = tile / NTL, tn = tile % NTL;
+            d4_t acc = {0, 0, 0, 0};
 #pragma unroll
-        for (int k0 = 0; k0 < PR; k0 += 4)
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[tm * 16 + l16][k0 + kg], A[tn * 16 + l16][k0 + kg], acc,
-                                                       0, 0, 0);
+            for (int k0 = 0; k0 < PR; k0 += 4)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[tm * 16 + l16][k0 + kg], A[tn * 16 + l16][k0 + kg],
+                                                           acc, 0, 0, 0);
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) S[tm * 16 + 4 * rr + kg][tn * 16 + l16] = acc[rr];
-    }
-    __syncthreads();
-    // A_new = 1.5 A - 0.5 S A, stored transposed: T[k][m] = A_new[m][k] = Q[k][m]
-#pragma unroll
-    for (int i = 0; i < TPW; ++i) {
-        const int tile = w + NW * i;
-        const int tm = tile / NTL, tn = tile % NTL;
-        d4_t acc = {0, 0, 0, 0};
-#pragma unroll
-        for (int k0 = 0; k0 < PR; k0 += 4)
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(S[tm * 16 + l16][k0 + kg], A[k0 + kg][tn * 16 + l16], acc,
-                                                       0, 0, 0);
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-            const int m = tm * 16 + 4 * rr + kg, kk = tn * 16 + l16;
-            T[kk][m] = 1.5 * A[m][kk] - 0.5 * acc[rr];
+            for (int rr = 0; rr < 4; ++rr) S[tm * 16 + 4 * rr + kg][tn * 16 + l16] = acc[rr];
         }
     }
     __syncthreads();
-    double* out = rot + (long)P * PR * PR;
+    // A_new = 1.5 A - 0.5 S A, stored transposed: T[k][m] = A_new[m][k] = Q[k][m]
+    if (upd) {
 #pragma unroll
-    for (int u = 0; u < EPT; ++u) {
-        const int x = xh + XS * u;
-        out[x * PR + y] = T[x][y];
+        for (int i = 0; i < TPW; ++i) {
+            const int tile = w + NW * i;
+            const int tm = tile / NTL, tn = tile % NTL;
+            d4_t acc = {0, 0, 0, 0};
+#pragma unroll
+            for (int k0 = 0; k0 < PR; k0 += 4)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(S[tm * 16 + l16][k0 + kg], A[k0 + kg][tn * 16 + l16],
+                                                           acc, 0, 0, 0);
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int m = tm * 16 + 4 * rr + kg, kk = tn * 16 + l16;
+                T[kk][m] = 1.5 * A[m][kk] - 0.5 * acc[rr];
+            }
+        }
+    }
+    __syncthreads();
+    if (upd) {
+        double* out = rot + (long)P * PR * PR;
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) {
+            const int x = xh + XS * u;
+            out[x * PR + y] = T[x][y];
+        }
     }
     if (t == 0) rotated[P] = anyrot;
 }
@@ -553,7 +610,7 @@ JacobiResult run_jacobi(double* Z, int p, int q, int ld, double tol, int max_swe
                                nchunks, gram_ws, work);
             if (timed) probe->end(PK_GRAM, s);
             timed = probe && probe->begin(PK_INNER, s);
-            hipLaunchKernelGGL((inner_kernel<RB>), dim3(npairs), dim3(NT), 0, s, gram_ws, nchunks, p, r, nb, tol,
+            hipLaunchKernelGGL((inner_kernel<RB>), dim3(npairs), dim3(Blk<RB>::NTI), 0, s, gram_ws, nchunks, p, r, nb, tol,
                                kappa, sigma1sq, rot_ws, rotated, off_ws, work + 1);
             if (timed) probe->end(PK_INNER, s);
             timed = probe && probe->begin(PK_ROTATE, s);
