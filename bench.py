@@ -23,6 +23,9 @@ Other workloads (own JSON line each):
                      chosen precision and in FP64, with the energy differences
   --mode serve       the serving loop on a scaled-down request stream
   --mode matvec      the H_eff product alone
+  --mode split       the bond split alone on a full-size 2048 x 2048 theta, and
+                     a plain 256 MiB device copy (the reference of the HBM
+                     traffic counters)
 
     python bench.py [--steps K] [--warmup W] [--precision fp64|fp32|bf16]
                     [--workload heis100|aim60|heis64] [--mode step|matvec|serve] [--no-cpu]
@@ -167,6 +170,23 @@ def cpu_baseline(dims, d, W, budget_s=30.0):
             "host_cpus": len(os.sched_getaffinity(0))}
 
 
+def measured_traffic(kernel_short):
+    """HBM bytes per launch of a kernel from the committed counter summary
+    (profiles/traffic.json: FETCH_SIZE and WRITE_SIZE per dispatch, scaled by
+    the same counters on a plain copy of known size), or None when the kernel
+    source has changed since the counters were taken."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    try:
+        rec = json.load(open(os.path.join(here, "profiles", "traffic.json")))[kernel_short]
+        src = open(os.path.join(here, rec["source"]), "rb").read()
+    except (OSError, KeyError, ValueError):
+        return None
+    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["bytes_per_launch"]
+
+
 def kernel_profile(ite, ctx, precision):
     """Per-kernel device time of the profiled region (sampled launches scaled
     to all launches) and the roofline of each kind; returns (table, dominant)."""
@@ -185,6 +205,7 @@ def kernel_profile(ite, ctx, precision):
         else:
             row.update(achieved=p["flops"] / total_s / 1e12, peak=FP64_PEAK, unit="TFLOP/s")
         row["frac"] = row["achieved"] / row["peak"]
+        row["traffic"] = measured_traffic(name.split(" ")[0])
         table[kind] = row
     dom = max(table.values(), key=lambda r: r["est_total_s"]) if table else None
     return table, dom
@@ -224,7 +245,8 @@ def run_steady(ite, torch, args):
     roof = None
     if dom is not None:
         roof = {"bound": dom["bound"], "achieved": dom["achieved"], "peak": dom["peak"], "unit": dom["unit"],
-                "frac": dom["frac"], "traffic": None, "kernel": dom["kernel"],
+                "frac": dom["frac"], "traffic": measured_traffic(dom["kernel"].split(" ")[0]),
+                "algorithmic_bytes_per_launch": dom["bytes_per_launch"], "kernel": dom["kernel"],
                 "avg_launch_ms": dom["avg_launch_ms"], "launches": dom["launches"],
                 "share_of_step_device_time": dom["est_total_s"] / (elapsed)}
     out = {
@@ -376,6 +398,35 @@ def run_serve(ite, args):
     }
 
 
+def run_split(ite, torch, args, reps=3):
+    """The Jacobi bond split of one full-size block (theta 2048 x 2048, seeded
+    Gaussian, left-to-right: A1 = U, A2 = S V^T, chi 1024, cutoff 0), timed,
+    then a plain device copy of 256 MiB: the reference kernel for scaling the
+    HBM traffic counters (its algorithmic traffic is 256 MiB read and 256 MiB
+    written)."""
+    D = 1024
+    rng = np.random.default_rng(5)
+    th = torch.from_numpy(rng.standard_normal((2 * D, 2 * D)).reshape(D, 2, 2, D)).cuda()
+    A1 = torch.zeros((D, 2, D), dtype=torch.float64, device="cuda")
+    A2 = torch.zeros((D, 2, D), dtype=torch.float64, device="cuda")
+    ctx = ite.ite_ctx_create(0)
+    ite.ite_debug_svd_split(ctx, 0, th, D, 0.0, 1e-13, A1, A2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        k, sig, disc = ite.ite_debug_svd_split(ctx, 0, th, D, 0.0, 1e-13, A1, A2)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    a = torch.empty(32 << 20, dtype=torch.float64, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    ite.ite_ctx_destroy(ctx)
+    return {"metric": "bond split ms (theta 2048 x 2048, Gaussian, chi 1024)", "value": dt * 1e3, "unit": "ms",
+            "kept": int(k), "discarded_weight": float(disc), "copy_reference_bytes": 2 * (32 << 20) * 8}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -383,7 +434,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="fp64", choices=list(PREC))
     ap.add_argument("--workload", default="heis100", choices=["heis100", "aim60", "heis64"])
-    ap.add_argument("--mode", default="step", choices=["step", "matvec", "serve"])
+    ap.add_argument("--mode", default="step", choices=["step", "matvec", "serve", "split"])
     ap.add_argument("--requests", type=int, default=32, help="serve mode: number of requests")
     ap.add_argument("--workers", type=int, default=8, help="serve mode: server worker threads")
     ap.add_argument("--no-cpu", action="store_true")
@@ -397,6 +448,8 @@ def main():
     import paper_2606_02930_amd as ite
     if args.mode == "serve":
         out = run_serve(ite, args)
+    elif args.mode == "split":
+        out = run_split(ite, torch, args)
     elif args.mode == "matvec":
         ctx = ite.ite_ctx_create(0)
         res = {}
