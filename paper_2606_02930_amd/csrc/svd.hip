@@ -87,8 +87,14 @@ __global__ __launch_bounds__(256) void gram_kernel(const double* __restrict__ Z,
     const int l16 = lane & 15, kg = lane >> 4;
     constexpr int NTL = PR / 16;                  // tiles per side
     double* out = gram + ((long)P * nchunks + chunk) * (PR * PR);
-    for (int tile = w; tile < NTL * NTL; tile += 4) {
-        const int I = tile / NTL, J = tile % NTL;
+    // the Gram is symmetric: only the tiles I <= J are formed and stored
+    for (int tile = w; tile < NTL * (NTL + 1) / 2; tile += 4) {
+        int I = 0, J = tile;
+        while (J >= NTL - I) {
+            J -= NTL - I;
+            ++I;
+        }
+        J += I;
         d4_t acc = {0, 0, 0, 0};
         for (int k0 = 0; k0 < GW; k0 += 4)
             acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Xs[I * 16 + l16][k0 + kg], Xs[J * 16 + l16][k0 + kg],
@@ -179,14 +185,14 @@ __device__ inline bool jacobi_angle(double gaa, double gbb, double gab, bool a_l
 }
 
 // Entry (x, y) of G' = J G J^T for positions x, y of the current round, J the
-// round's rotations (cc, ss by pair index): the same expressions as the 2 x 2
-// block updates of inner_kernel.
+// round's rotations ((cos, sin) by pair index): the same expressions as the
+// 2 x 2 block updates of inner_kernel.
 template <int RB>
-__device__ inline double rotated_entry(const double (*G)[2 * RB + 1], const double* cc, const double* ss, int x,
-                                       int y) {
+__device__ inline double rotated_entry(const double (*G)[2 * RB + 1], const double2* cs, int x, int y) {
     const bool rx = x >= RB, ry = y >= RB;
     const int i = rx ? x - RB : x, j = ry ? y - RB : y;
-    const double ci = cc[i], si = ss[i], cj = cc[j], sj = ss[j];
+    const double2 pi = cs[i], pj = cs[j];
+    const double ci = pi.x, si = pi.y, cj = pj.x, sj = pj.y;
     const double g00 = G[i][j], g01 = G[i][j + RB], g10 = G[i + RB][j], g11 = G[i + RB][j + RB];
     const double t0 = rx ? si * g00 + ci * g10 : ci * g00 - si * g10;
     const double t1 = rx ? si * g01 + ci * g11 : ci * g01 - si * g11;
@@ -225,7 +231,7 @@ __global__ __launch_bounds__(Blk<RB>::NTI) void inner_kernel(const double* __res
     static_assert((NTL * NTL) % NW == 0, "tiles per wavefront");
     __shared__ double Gb[2][PR][PR + 1];
     __shared__ double Ab[2][PR][PR + 1];
-    __shared__ double cc[2][RB], ss[2][RB];
+    __shared__ double2 cs[2][RB];               // (cos, sin) of each pair's rotation, by round parity
     __shared__ double red[NW];
     __shared__ int anyrot;
     const int P = blockIdx.x;
@@ -247,14 +253,16 @@ __global__ __launch_bounds__(Blk<RB>::NTI) void inner_kernel(const double* __res
 #pragma unroll
             for (int h = 0; h < 4; ++h)
 #pragma unroll
-                for (int u = 0; u < EPT; ++u) v[h][u] = g[(long)h * PR * PR + (xh + XS * u) * PR];
+                for (int u = 0; u < EPT; ++u)
+                    v[h][u] = ((xh + XS * u) >> 4) <= (y >> 4) ? g[(long)h * PR * PR + (xh + XS * u) * PR] : 0.0;
 #pragma unroll
             for (int u = 0; u < EPT; ++u) s[u] += (v[0][u] + v[1][u]) + (v[2][u] + v[3][u]);
         }
         for (; c < nchunks; ++c) {
             const double* g = src + (long)c * PR * PR + y;
 #pragma unroll
-            for (int u = 0; u < EPT; ++u) s[u] += g[(xh + XS * u) * PR];
+            for (int u = 0; u < EPT; ++u)
+                if (((xh + XS * u) >> 4) <= (y >> 4)) s[u] += g[(xh + XS * u) * PR];
         }
 #pragma unroll
         for (int u = 0; u < EPT; ++u) {
@@ -265,12 +273,16 @@ __global__ __launch_bounds__(Blk<RB>::NTI) void inner_kernel(const double* __res
     }
     if (t == 0) anyrot = 0;
     __syncthreads();
-    // symmetrise (the two triangles come from different MFMA tiles)
+    // symmetrise: tiles below the diagonal were not formed and take the
+    // transpose; inside a diagonal tile the two triangles come from different
+    // MFMA lanes and are averaged
     if (upd) {
 #pragma unroll
         for (int u = 0; u < EPT; ++u) {
             const int x = xh + XS * u;
-            if (x < y) {
+            if ((x >> 4) > (y >> 4)) {
+                Gb[0][x][y] = Gb[0][y][x];
+            } else if ((x >> 4) == (y >> 4) && x < y) {
                 const double v = 0.5 * (Gb[0][x][y] + Gb[0][y][x]);
                 Gb[0][x][y] = v;
                 Gb[0][y][x] = v;
@@ -314,8 +326,7 @@ __global__ __launch_bounds__(Blk<RB>::NTI) void inner_kernel(const double* __res
         if (jacobi_angle(Gb[0][al][al], Gb[0][al + RB][al + RB], Gb[0][al][al + RB],
                          ring_row<PR>(al, 0) < ring_row<PR>(al + RB, 0), c, s))
             anyrot = 1;
-        cc[0][al] = c;
-        ss[0][al] = s;
+        cs[0][al] = make_double2(c, s);
     }
     __syncthreads();
     // fixed per update thread: the column pair j of its 2 x 2 blocks, the
@@ -327,12 +338,14 @@ __global__ __launch_bounds__(Blk<RB>::NTI) void inner_kernel(const double* __res
     for (int k = 0; k < PR - 1; ++k) {
         const int pb = k & 1, nxt = cur ^ 1;
         if (upd) {
-            const double cj = cc[pb][jq], sj = ss[pb][jq];
+            const double2 pj = cs[pb][jq];
+            const double cj = pj.x, sj = pj.y;
             double nv[QPT][4];
 #pragma unroll
             for (int u = 0; u < QPT; ++u) {
                 const int i = t / RB + IS * u;
-                const double ci = cc[pb][i], si = ss[pb][i];
+                const double2 pi = cs[pb][i];
+                const double ci = pi.x, si = pi.y;
                 const double g00 = Gb[cur][i][jq], g01 = Gb[cur][i][jq + RB];
                 const double g10 = Gb[cur][i + RB][jq], g11 = Gb[cur][i + RB][jq + RB];
                 const double t00 = ci * g00 - si * g10, t01 = ci * g01 - si * g11;
@@ -346,7 +359,8 @@ __global__ __launch_bounds__(Blk<RB>::NTI) void inner_kernel(const double* __res
 #pragma unroll
             for (int u = 0; u < JPT; ++u) {
                 const int i = t / PR + JS * u;
-                const double ci = cc[pb][i], si = ss[pb][i];
+                const double2 pi = cs[pb][i];
+                const double ci = pi.x, si = pi.y;
                 const double a0 = Ab[cur][i][la], a1 = Ab[cur][i + RB][la];
                 na[u][0] = ci * a0 - si * a1;
                 na[u][1] = si * a0 + ci * a1;
@@ -370,14 +384,13 @@ __global__ __launch_bounds__(Blk<RB>::NTI) void inner_kernel(const double* __res
             // pair al of round k + 1 sits at positions (al, al + RB) then,
             // i.e. at (a, b) now
             const int a = ring_prev<PR>(al), b = ring_prev<PR>(al + RB);
-            const double gaa = rotated_entry<RB>(Gb[cur], cc[pb], ss[pb], a, a);
-            const double gbb = rotated_entry<RB>(Gb[cur], cc[pb], ss[pb], b, b);
-            const double gab = rotated_entry<RB>(Gb[cur], cc[pb], ss[pb], a, b);
+            const double gaa = rotated_entry<RB>(Gb[cur], cs[pb], a, a);
+            const double gbb = rotated_entry<RB>(Gb[cur], cs[pb], b, b);
+            const double gab = rotated_entry<RB>(Gb[cur], cs[pb], a, b);
             double c, s;
             if (jacobi_angle(gaa, gbb, gab, ring_row<PR>(al, k + 1) < ring_row<PR>(al + RB, k + 1), c, s))
                 anyrot = 1;
-            cc[pb ^ 1][al] = c;
-            ss[pb ^ 1][al] = s;
+            cs[pb ^ 1][al] = make_double2(c, s);
         }
         __syncthreads();
         cur = nxt;
