@@ -225,12 +225,11 @@ __global__ __launch_bounds__(Blk<RB>::NTI) void inner_kernel(const double* __res
                                                              unsigned long long* __restrict__ work) {
     constexpr int PR = Blk<RB>::PR, NT = Blk<RB>::NT, XS = Blk<RB>::XS, EPT = PR / XS;
     constexpr int QPT = RB * RB / NT, IS = NT / RB;     // 2 x 2 blocks per thread, their row stride
-    constexpr int JPT = RB * PR / NT, JS = NT / PR;     // row-pair entries of A per thread, their stride
     constexpr int NW = NT / 64, NTL = PR / 16;          // update wavefronts, 16 x 16 tiles per side
-    static_assert(QPT * NT == RB * RB && JPT * NT == RB * PR && EPT * NT == PR * PR, "thread layout");
+    static_assert(QPT * NT == RB * RB && EPT * NT == PR * PR && (RB * PR / 2) % NT == 0, "thread layout");
     static_assert((NTL * NTL) % NW == 0, "tiles per wavefront");
     __shared__ double Gb[2][PR][PR + 1];
-    __shared__ double Ab[2][PR][PR + 1];
+    __shared__ __align__(16) double Ab[2][PR][PR + 2];
     __shared__ double2 cs[2][RB];               // (cos, sin) of each pair's rotation, by round parity
     __shared__ double red[NW];
     __shared__ int anyrot;
@@ -333,7 +332,22 @@ __global__ __launch_bounds__(Blk<RB>::NTI) void inner_kernel(const double* __res
     // column l of its entries of A
     const int jq = t % RB;
     const int pj0 = ring_next<PR>(jq), pj1 = ring_next<PR>(jq + RB);
-    const int la = t % PR;
+    // entries of A per thread: columns (ca, ca + 1) of rows i and i + RB for
+    // JC row pairs i (16-byte LDS accesses; rows padded to an even length);
+    // the next-round positions of a thread's rows are fixed, computed once
+    constexpr int JC = RB * (PR / 2) / NT, JCS = NT / (PR / 2);
+    const int ca = 2 * (t % (PR / 2));
+    int pa0[JC], pa1[JC], pq0[QPT], pq1[QPT];
+#pragma unroll
+    for (int u = 0; u < JC; ++u) {
+        pa0[u] = ring_next<PR>(t / (PR / 2) + JCS * u);
+        pa1[u] = ring_next<PR>(t / (PR / 2) + JCS * u + RB);
+    }
+#pragma unroll
+    for (int u = 0; u < QPT; ++u) {
+        pq0[u] = ring_next<PR>(t / RB + IS * u);
+        pq1[u] = ring_next<PR>(t / RB + IS * u + RB);
+    }
     int cur = 0;
     for (int k = 0; k < PR - 1; ++k) {
         const int pb = k & 1, nxt = cur ^ 1;
@@ -355,30 +369,29 @@ __global__ __launch_bounds__(Blk<RB>::NTI) void inner_kernel(const double* __res
                 nv[u][2] = t10 * cj - t11 * sj;
                 nv[u][3] = t10 * sj + t11 * cj;
             }
-            double na[JPT][2];
+            double2 na[JC][2];
 #pragma unroll
-            for (int u = 0; u < JPT; ++u) {
-                const int i = t / PR + JS * u;
+            for (int u = 0; u < JC; ++u) {
+                const int i = t / (PR / 2) + JCS * u;
                 const double2 pi = cs[pb][i];
                 const double ci = pi.x, si = pi.y;
-                const double a0 = Ab[cur][i][la], a1 = Ab[cur][i + RB][la];
-                na[u][0] = ci * a0 - si * a1;
-                na[u][1] = si * a0 + ci * a1;
+                const double2 a0 = *reinterpret_cast<const double2*>(&Ab[cur][i][ca]);
+                const double2 a1 = *reinterpret_cast<const double2*>(&Ab[cur][i + RB][ca]);
+                na[u][0] = make_double2(ci * a0.x - si * a1.x, ci * a0.y - si * a1.y);
+                na[u][1] = make_double2(si * a0.x + ci * a1.x, si * a0.y + ci * a1.y);
             }
 #pragma unroll
             for (int u = 0; u < QPT; ++u) {
-                const int i = t / RB + IS * u;
-                const int pi0 = ring_next<PR>(i), pi1 = ring_next<PR>(i + RB);
+                const int pi0 = pq0[u], pi1 = pq1[u];
                 Gb[nxt][pi0][pj0] = nv[u][0];
                 Gb[nxt][pi0][pj1] = nv[u][1];
                 Gb[nxt][pi1][pj0] = nv[u][2];
                 Gb[nxt][pi1][pj1] = nv[u][3];
             }
 #pragma unroll
-            for (int u = 0; u < JPT; ++u) {
-                const int i = t / PR + JS * u;
-                Ab[nxt][ring_next<PR>(i)][la] = na[u][0];
-                Ab[nxt][ring_next<PR>(i + RB)][la] = na[u][1];
+            for (int u = 0; u < JC; ++u) {
+                *reinterpret_cast<double2*>(&Ab[nxt][pa0[u]][ca]) = na[u][0];
+                *reinterpret_cast<double2*>(&Ab[nxt][pa1[u]][ca]) = na[u][1];
             }
         } else if (al < RB && k + 1 < PR - 1) {
             // pair al of round k + 1 sits at positions (al, al + RB) then,
@@ -400,7 +413,7 @@ __global__ __launch_bounds__(Blk<RB>::NTI) void inner_kernel(const double* __res
     // FP64 MFMA: the product of Givens rotations is orthogonal only to a few
     // hundred ulps, and every row meets such a rotation in each round of every
     // sweep, so the defect would otherwise accumulate.
-    double (*A)[PR + 1] = Ab[cur];
+    double (*A)[PR + 2] = Ab[cur];
     double (*S)[PR + 1] = Gb[cur];
     double (*T)[PR + 1] = Gb[cur ^ 1];
     const int lane = t & 63, w = t >> 6;
