@@ -5,7 +5,9 @@
 //
 // Tile: 128 x 128 output per workgroup of 256 threads (four 64-wide
 // wavefronts in a 2 x 2 arrangement, each owning 64 x 64 = 4 x 4 MFMA tiles of
-// 16 x 16).  K advances in slices of 16 staged through LDS with double
+// 16 x 16).  Registers are kept within 256 per lane (operands of two MFMA
+// sub-steps live at a time) so that two workgroups share a CU and one's
+// barrier and LDS traffic overlap the other's matrix-core work.  K advances in slices of 16 staged through LDS with double
 // buffering: the next slice is fetched into registers while the current one
 // feeds the matrix cores.  Both operands are stored in LDS "K-contiguous"
 // (row = output row or column, 16 K values per row, padded) so that each lane
@@ -110,7 +112,7 @@ __device__ inline void store_slice(T* __restrict__ lds, int t, const T (&r)[8]) 
 }
 
 template <typename T, bool TA, bool TB>
-__global__ __launch_bounds__(NTHREADS) void gemm_kernel(Params p) {
+__global__ __launch_bounds__(NTHREADS, 2) void gemm_kernel(Params p) {
     typedef typename MfmaOp<T>::acc_t acc_t;
     constexpr int LDK = MfmaOp<T>::LDK;
     __shared__ T As[2][BM * LDK];
@@ -152,25 +154,30 @@ __global__ __launch_bounds__(NTHREADS) void gemm_kernel(Params p) {
             fetch_slice<T, !TA>(A, p.lda, m0, p.M, (kt + 1) * BK, p.K, t, ra);
             fetch_slice<T, TB>(B, p.ldb, n0, p.N, (kt + 1) * BK, p.K, t, rb);
         }
-        T a[4][4], b[4][4];
+        // two sub-steps of the slice at a time: 16 operand values live
+        // instead of 32, which leaves room for two workgroups per CU
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const T* src = &As[cur][(wm * 64 + i * 16 + l16) * LDK + 4 * kg];
+        for (int s2 = 0; s2 < 4; s2 += 2) {
+            T a[4][2], b[4][2];
 #pragma unroll
-            for (int s = 0; s < 4; ++s) a[i][s] = src[s];
+            for (int i = 0; i < 4; ++i) {
+                const T* src = &As[cur][(wm * 64 + i * 16 + l16) * LDK + 4 * kg + s2];
+                a[i][0] = src[0];
+                a[i][1] = src[1];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const T* src = &Bs[cur][(wn * 64 + j * 16 + l16) * LDK + 4 * kg + s2];
+                b[j][0] = src[0];
+                b[j][1] = src[1];
+            }
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) acc[i][j] = MfmaOp<T>::mma(a[i][s], b[j][s], acc[i][j]);
         }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const T* src = &Bs[cur][(wn * 64 + j * 16 + l16) * LDK + 4 * kg];
-#pragma unroll
-            for (int s = 0; s < 4; ++s) b[j][s] = src[s];
-        }
-#pragma unroll
-        for (int s = 0; s < 4; ++s)
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-#pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = MfmaOp<T>::mma(a[i][s], b[j][s], acc[i][j]);
         if (more) {
             store_slice<T, !TA>(As[cur ^ 1], t, ra);
             store_slice<T, TB>(Bs[cur ^ 1], t, rb);
