@@ -31,7 +31,7 @@ namespace {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
-constexpr int RCOLS = 128;   // columns per rotate block
+constexpr int RCOLS = 512;   // columns per rotate block (8 slices of 64)
 
 template <int RB> struct Blk {
     static constexpr int PR = 2 * RB;              // rows per pair
@@ -466,8 +466,9 @@ __global__ __launch_bounds__(Blk<RB>::NTI) void inner_kernel(const double* __res
 }
 
 // Z_pair <- Q^T Z_pair with FP64 MFMA on a chunk of RCOLS columns: Q is staged
-// in LDS; each wavefront streams its own 32 columns of the pair's rows from
-// memory straight into MFMA operands and writes the rotated values back
+// in LDS; each wavefront streams 16-column slices of the pair's rows from
+// memory straight into MFMA operands, fetching the next slice while the
+// matrix cores work on the current one, and writes the rotated values back
 // (wavefronts own disjoint columns, so the update is in place).
 template <int RB>
 __global__ __launch_bounds__(256) void rotate_kernel(double* __restrict__ Z, int p, int ld, int r, int nb,
@@ -475,7 +476,7 @@ __global__ __launch_bounds__(256) void rotate_kernel(double* __restrict__ Z, int
                                                      const int* __restrict__ rotated,
                                                      unsigned long long* __restrict__ work) {
     constexpr int PR = Blk<RB>::PR;
-    constexpr int NTM = PR / 16, KS = PR / 4, CT = RCOLS / 64;   // row tiles, k steps, column tiles per wave
+    constexpr int NTM = PR / 16, KS = PR / 4, NIT = RCOLS / 64;   // row tiles, k steps, slices per wavefront
     const int P = blockIdx.y;
     if (!rotated[P]) return;
     if (threadIdx.x == 0) atomicAdd(work, 1ull);
@@ -485,45 +486,43 @@ __global__ __launch_bounds__(256) void rotate_kernel(double* __restrict__ Z, int
     for (int e = t; e < PR * PR; e += 256) Qs[e / PR][e % PR] = src[e];
     const int lane = t & 63, w = t >> 6;
     const int l16 = lane & 15, kg = lane >> 4;
-    const int cw = blockIdx.x * RCOLS + w * (16 * CT);
-    double b[CT][KS];
+    // row offsets of the operand rows this lane reads (-1: past the matrix)
+    long rk[KS];
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
         const int row = pair_row<RB>(P, 4 * ks + kg, r, nb);
-#pragma unroll
-        for (int ct = 0; ct < CT; ++ct) {
-            const int c = cw + ct * 16 + l16;
-            b[ct][ks] = (row < p && c < ld) ? Z[(long)row * ld + c] : 0.0;
-        }
+        rk[ks] = row < p ? (long)row * ld : -1;
     }
+    const int c0 = blockIdx.x * RCOLS + w * 16 + l16;
+    double b[KS], bn[KS];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) b[ks] = (rk[ks] >= 0 && c0 < ld) ? Z[rk[ks] + c0] : 0.0;
     __syncthreads();
-    d4_t acc[CT][NTM];
+    for (int it = 0; it < NIT; ++it) {
+        const int c = c0 + it * 64, cn = c + 64;
+        if (it + 1 < NIT) {
 #pragma unroll
-    for (int ct = 0; ct < CT; ++ct)
-#pragma unroll
-        for (int tm = 0; tm < NTM; ++tm) acc[ct][tm] = d4_t{0, 0, 0, 0};
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-#pragma unroll
-        for (int tm = 0; tm < NTM; ++tm) {
-            const double a = Qs[4 * ks + kg][tm * 16 + l16];
-#pragma unroll
-            for (int ct = 0; ct < CT; ++ct)
-                acc[ct][tm] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[ct][ks], acc[ct][tm], 0, 0, 0);
+            for (int ks = 0; ks < KS; ++ks) bn[ks] = (rk[ks] >= 0 && cn < ld) ? Z[rk[ks] + cn] : 0.0;
         }
-    }
+        d4_t acc[NTM];
 #pragma unroll
-    for (int tm = 0; tm < NTM; ++tm) {
+        for (int tm = 0; tm < NTM; ++tm) acc[tm] = d4_t{0, 0, 0, 0};
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) {
-            const int m = tm * 16 + 4 * rr + kg;      // FP64 MFMA accumulator row
-            const int row = pair_row<RB>(P, m, r, nb);
+        for (int ks = 0; ks < KS; ++ks)
 #pragma unroll
-            for (int ct = 0; ct < CT; ++ct) {
-                const int c = cw + ct * 16 + l16;
-                if (row < p && c < ld) Z[(long)row * ld + c] = acc[ct][tm][rr];
+            for (int tm = 0; tm < NTM; ++tm)
+                acc[tm] = __builtin_amdgcn_mfma_f64_16x16x4f64(Qs[4 * ks + kg][tm * 16 + l16], b[ks], acc[tm],
+                                                               0, 0, 0);
+#pragma unroll
+        for (int tm = 0; tm < NTM; ++tm)
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int m = tm * 16 + 4 * rr + kg;      // FP64 MFMA accumulator row
+                const int row = pair_row<RB>(P, m, r, nb);
+                if (row < p && c < ld) Z[(long)row * ld + c] = acc[tm][rr];
             }
-        }
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) b[ks] = bn[ks];
     }
 }
 
