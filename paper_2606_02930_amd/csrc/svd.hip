@@ -31,14 +31,15 @@ namespace {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
-constexpr int RCOLS = 512;   // columns per rotate block (8 slices of 64)
-
 template <int RB> struct Blk {
     static constexpr int PR = 2 * RB;              // rows per pair
     static constexpr int NT = PR * PR / 8;         // inner threads: 8 entries of a PR x PR matrix each
     static constexpr int XS = NT / PR;             // row stride of a thread's entries
     static constexpr int NTI = NT + 64;            // inner kernel: NT update threads + one angle wavefront
-    static constexpr int GW = RB == 16 ? 256 : 128;   // columns per gram chunk
+    static constexpr int GW = RB == 16 ? 256 : 128;   // columns per LDS stage of the gram kernel
+    static constexpr int GS = 2;                   // stages per gram chunk
+    static constexpr int GC = GW * GS;             // columns per gram chunk
+    static constexpr int UW = 16 * (NT / 64) * 4;  // identity-part columns per rotating inner workgroup
 };
 
 // Block index at position `pos` of the circle schedule in round r
@@ -62,46 +63,72 @@ template <int RB>
 __global__ __launch_bounds__(256) void gram_kernel(const double* __restrict__ Z, int p, int q, int ld, int r,
                                                    int nb, int nchunks, double* __restrict__ gram,
                                                    unsigned long long* __restrict__ work) {
-    constexpr int PR = Blk<RB>::PR, GW = Blk<RB>::GW;
+    constexpr int PR = Blk<RB>::PR, GW = Blk<RB>::GW, GS = Blk<RB>::GS;
+    constexpr int NTL = PR / 16, NTILE = NTL * (NTL + 1) / 2, TPW = (NTILE + 3) / 4;
+    constexpr int RPP = 256 / GW, NPASS = PR / RPP;
     __shared__ double Xs[PR][GW + 1];
     const int P = blockIdx.y, chunk = blockIdx.x;
-    const int c0 = chunk * GW;
     const int t = threadIdx.x;
+    const int cc = t % GW, lr0 = t / GW;
+    long ro[NPASS];
+#pragma unroll
+    for (int u = 0; u < NPASS; ++u) {
+        const int row = pair_row<RB>(P, lr0 + RPP * u, r, nb);
+        ro[u] = row < p ? (long)row * ld : -1;
+    }
+    // all PR * GW / 256 loads of a stage in flight together; the next
+    // stage is fetched while the matrix cores work on the current one
+    double v[NPASS];
     {
-        // all PR * GW / 256 loads of a thread in flight together
-        constexpr int RPP = 256 / GW, NPASS = PR / RPP;
-        const int cc = t % GW, lr0 = t / GW;
-        const int c = c0 + cc;
-        double v[NPASS];
+        const int c = chunk * Blk<RB>::GC + cc;
 #pragma unroll
-        for (int u = 0; u < NPASS; ++u) {
-            const int row = pair_row<RB>(P, lr0 + RPP * u, r, nb);
-            v[u] = (row < p && c < q) ? Z[(long)row * ld + c] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < NPASS; ++u) Xs[lr0 + RPP * u][cc] = v[u];
+        for (int u = 0; u < NPASS; ++u) v[u] = (ro[u] >= 0 && c < q) ? Z[ro[u] + c] : 0.0;
     }
     if (t == 0) atomicAdd(work, 1ull);
-    __syncthreads();
     const int lane = t & 63, w = t >> 6;
     const int l16 = lane & 15, kg = lane >> 4;
-    constexpr int NTL = PR / 16;                  // tiles per side
-    double* out = gram + ((long)P * nchunks + chunk) * (PR * PR);
-    // the Gram is symmetric: only the tiles I <= J are formed and stored
-    for (int tile = w; tile < NTL * (NTL + 1) / 2; tile += 4) {
-        int I = 0, J = tile;
-        while (J >= NTL - I) {
+    // the Gram is symmetric: only the tiles I <= J are formed and stored;
+    // wavefront w owns tiles w, w + 4, ...
+    int ti[TPW], tj[TPW];
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+        int I = 0, J = w + 4 * i;
+        while (J >= NTL - I && I < NTL) {
             J -= NTL - I;
             ++I;
         }
-        J += I;
-        d4_t acc = {0, 0, 0, 0};
-        for (int k0 = 0; k0 < GW; k0 += 4)
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Xs[I * 16 + l16][k0 + kg], Xs[J * 16 + l16][k0 + kg],
-                                                       acc, 0, 0, 0);
+        ti[i] = I;
+        tj[i] = J + I;
+    }
+    d4_t acc[TPW];
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) acc[i] = d4_t{0, 0, 0, 0};
+    for (int st = 0; st < GS; ++st) {
+        if (st > 0) __syncthreads();
+#pragma unroll
+        for (int u = 0; u < NPASS; ++u) Xs[lr0 + RPP * u][cc] = v[u];
+        __syncthreads();
+        if (st + 1 < GS) {
+            const int c = chunk * Blk<RB>::GC + (st + 1) * GW + cc;
+#pragma unroll
+            for (int u = 0; u < NPASS; ++u) v[u] = (ro[u] >= 0 && c < q) ? Z[ro[u] + c] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < TPW; ++i) {
+            if (w + 4 * i >= NTILE) break;
+            const int I = ti[i], J = tj[i];
+            for (int k0 = 0; k0 < GW; k0 += 4)
+                acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(Xs[I * 16 + l16][k0 + kg], Xs[J * 16 + l16][k0 + kg],
+                                                              acc[i], 0, 0, 0);
+        }
+    }
+    double* out = gram + ((long)P * nchunks + chunk) * (PR * PR);
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) {
+        if (w + 4 * i >= NTILE) break;
         // FP64 MFMA accumulator element rr of lane group kg is tile row 4 rr + kg
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) out[(I * 16 + 4 * rr + kg) * PR + J * 16 + l16] = acc[rr];
+        for (int rr = 0; rr < 4; ++rr) out[(ti[i] * 16 + 4 * rr + kg) * PR + tj[i] * 16 + l16] = acc[i][rr];
     }
 }
 
@@ -162,21 +189,29 @@ __device__ inline int ring_row(int pos, int k) {
 }
 
 // Jacobi angle of the pair (a, b) with Gram entries g_aa, g_bb, g_ab:
-// tan(theta) = sign(x) y / (|x| + hypot(x, y)), x = g_bb - g_aa, y = 2 g_ab;
-// new_a = c a - s b, new_b = s a + c b.  Of the two diagonalising angles the
-// one that leaves the larger row at the lower local index (a_low: a has the
-// lower index) is taken.  Returns whether the pair rotates.
+// tan(theta) = sign(x) y / (|x| + r), x = g_bb - g_aa, y = 2 g_ab,
+// r = hypot(x, y); new_a = c a - s b, new_b = s a + c b.  Written without a
+// division: with d = |x| + r, cos = d / sqrt(2 r d) and
+// sin = sign(x) y / sqrt(2 r d) (x and y first scaled by a power of two, so
+// that nothing overflows or underflows).  This rotation keeps the order of
+// the two diagonal entries (b ends larger when x >= 0); of the two
+// diagonalising angles the one that leaves the larger row at the lower local
+// index (a_low: a has the lower index) is taken, by swapping (c, s) to
+// (-s, c) when needed.  Returns whether the pair rotates.
 __device__ inline bool jacobi_angle(double gaa, double gbb, double gab, bool a_low, double& c, double& s) {
     c = 1.0;
     s = 0.0;
     if (gab == 0.0) return false;
     const double x = gbb - gaa, yy = 2.0 * gab;
-    const double tt = (x >= 0.0 ? yy : -yy) / (fabs(x) + sqrt(x * x + yy * yy));
-    c = rsqrt(1.0 + tt * tt);
-    s = tt * c;
-    const double naa = c * c * gaa - 2.0 * c * s * gab + s * s * gbb;
-    const double nbb = s * s * gaa + 2.0 * c * s * gab + c * c * gbb;
-    if (a_low ? (naa < nbb) : (naa > nbb)) {
+    int e;
+    (void)frexp(fmax(fabs(x), fabs(yy)), &e);
+    const double xs = ldexp(x, -e), ys = ldexp(yy, -e);
+    const double r = sqrt(xs * xs + ys * ys);
+    const double d = fabs(xs) + r;
+    const double iw = rsqrt(2.0 * r * d);
+    c = d * iw;
+    s = (x >= 0.0 ? ys : -ys) * iw;
+    if (a_low == (x >= 0.0)) {
         const double c0 = c;
         c = -s;
         s = c0;
@@ -199,6 +234,77 @@ __device__ inline double rotated_entry(const double (*G)[2 * RB + 1], const doub
     return ry ? t0 * sj + t1 * cj : t0 * cj - t1 * sj;
 }
 
+// Z_pair <- Q^T Z_pair with FP64 MFMA on columns [cb, ce) of the pair's rows
+// for the pair of round r, Q (Q[k][m]) staged in LDS.  NWV wavefronts stream
+// 16-column slices of the pair's rows from memory straight into MFMA
+// operands, fetching the next slice while the matrix cores work on the
+// current one, and write the rotated values back (wavefronts own disjoint
+// columns, so the update is in place).  Every thread of the workgroup calls
+// this (it holds one barrier: Q must be complete in LDS after it); threads
+// with `active` false only take part in the barrier.  PF: fetch one slice
+// ahead (twice the operand registers) and keep Q in registers across
+// slices; otherwise Q is read from LDS for every slice.
+template <int RB, int NWV, bool PF>
+__device__ inline void rotate_cols(double* __restrict__ Z, int p, int ld, int P, int r, int nb,
+                                   const double (*Qs)[2 * RB + 1], int cb, int ce, int t, bool active) {
+    constexpr int PR = 2 * RB;
+    constexpr int NTM = PR / 16, KS = PR / 4, STRIDE = 16 * NWV;   // row tiles, k steps, slice stride
+    const int lane = t & 63, w = t >> 6;
+    const int l16 = lane & 15, kg = lane >> 4;
+    // element offsets of the operand rows this lane reads and of the rows it
+    // writes (-1: past the matrix; p ld < 2^31 is checked by the caller)
+    int rk[KS], ro[NTM * 4];
+    double b[KS], bn[PF ? KS : 1];
+    const int c0 = cb + w * 16 + l16;
+    if (active) {
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const int row = pair_row<RB>(P, 4 * ks + kg, r, nb);
+            rk[ks] = row < p ? row * ld : -1;
+        }
+#pragma unroll
+        for (int m4 = 0; m4 < NTM * 4; ++m4) {
+            const int row = pair_row<RB>(P, 4 * m4 + kg, r, nb);    // FP64 MFMA accumulator row
+            ro[m4] = row < p ? row * ld : -1;
+        }
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) b[ks] = (rk[ks] >= 0 && c0 < ce) ? Z[rk[ks] + c0] : 0.0;
+    }
+    __syncthreads();
+    if (!active) return;
+    const int nit = (ce - cb + STRIDE - 1) / STRIDE;
+    for (int it = 0; it < nit; ++it) {
+        const int c = c0 + it * STRIDE, cn = c + STRIDE;
+        if (!PF) asm volatile("" ::: "memory");   // keeps the Q operand loads inside the loop
+        if (PF && it + 1 < nit) {
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) bn[PF ? ks : 0] = (rk[ks] >= 0 && cn < ce) ? Z[rk[ks] + cn] : 0.0;
+        }
+        if (!PF && it > 0) {
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) b[ks] = (rk[ks] >= 0 && c < ce) ? Z[rk[ks] + c] : 0.0;
+        }
+        d4_t acc[NTM];
+#pragma unroll
+        for (int tm = 0; tm < NTM; ++tm) acc[tm] = d4_t{0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+            for (int tm = 0; tm < NTM; ++tm)
+                acc[tm] = __builtin_amdgcn_mfma_f64_16x16x4f64(Qs[4 * ks + kg][tm * 16 + l16], b[ks], acc[tm],
+                                                               0, 0, 0);
+#pragma unroll
+        for (int tm = 0; tm < NTM; ++tm)
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr)
+                if (ro[4 * tm + rr] >= 0 && c < ce) Z[ro[4 * tm + rr] + c] = acc[tm][rr];
+        if (PF) {
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) b[ks] = bn[PF ? ks : 0];
+        }
+    }
+}
+
 // One workgroup per pair: sum the chunk partials, then one cyclic sweep of
 // two-sided Jacobi rotations on the PR x PR Gram matrix (each rotation the
 // one of the two diagonalising angles that keeps the larger row at the lower
@@ -216,23 +322,43 @@ __device__ inline double rotated_entry(const double (*G)[2 * RB + 1], const doub
 // round k it forms the three entries of G' each pair of round k + 1 needs and
 // that pair's angle, while the update of round k runs, so a round costs one
 // barrier.
+//
+// Workgroups npairs and up rotate the identity part (columns q .. ld) of
+// the rows of the previous round's pairs (round rprev, rotations rot_prev),
+// UW columns each: that work is off the critical path of the sweep and
+// fills the compute units the pairs leave idle.  work[1] counts the pairs
+// rotated, work[3] the identity-part columns rotated here.
 template <int RB>
 __global__ __launch_bounds__(Blk<RB>::NTI) void inner_kernel(const double* __restrict__ gram, int nchunks, int p,
                                                              int r, int nb, double tol, double kappa,
                                                              double sigma1sq, double* __restrict__ rot,
                                                              int* __restrict__ rotated,
                                                              double* __restrict__ sweep_off,
-                                                             unsigned long long* __restrict__ work) {
+                                                             unsigned long long* __restrict__ work,
+                                                             double* __restrict__ Z, int ld, int q, int npairs,
+                                                             int rprev, const double* __restrict__ rot_prev,
+                                                             const int* __restrict__ rotated_prev, int nuch) {
     constexpr int PR = Blk<RB>::PR, NT = Blk<RB>::NT, XS = Blk<RB>::XS, EPT = PR / XS;
     constexpr int QPT = RB * RB / NT, IS = NT / RB;     // 2 x 2 blocks per thread, their row stride
     constexpr int NW = NT / 64, NTL = PR / 16;          // update wavefronts, 16 x 16 tiles per side
+    constexpr int NTI = Blk<RB>::NTI, UW = Blk<RB>::UW;
     static_assert(QPT * NT == RB * RB && EPT * NT == PR * PR && (RB * PR / 2) % NT == 0, "thread layout");
     static_assert((NTL * NTL) % NW == 0, "tiles per wavefront");
     __shared__ double Gb[2][PR][PR + 1];
     __shared__ __align__(16) double Ab[2][PR][PR + 2];
     __shared__ double2 cs[2][RB];               // (cos, sin) of each pair's rotation, by round parity
-    __shared__ double red[NW];
+    __shared__ double red[NW], gred[NW];
     __shared__ int anyrot;
+    if ((int)blockIdx.x >= npairs) {
+        const int u = blockIdx.x - npairs, Pu = u / nuch, ch = u % nuch;
+        if (!rotated_prev[Pu]) return;
+        const int cb = q + ch * UW, ce = min(cb + UW, ld);
+        if (threadIdx.x == 0) atomicAdd(work + 3, (unsigned long long)(ce - cb));
+        const double* qsrc = rot_prev + (long)Pu * PR * PR;
+        for (int e = threadIdx.x; e < PR * PR; e += NTI) Gb[0][e / PR][e % PR] = qsrc[e];
+        rotate_cols<RB, NW, false>(Z, p, ld, Pu, rprev, nb, Gb[0], cb, ce, threadIdx.x, threadIdx.x < NT);
+        return;
+    }
     const int P = blockIdx.x;
     const int t = threadIdx.x;
     const bool upd = t < NT;                      // update thread (else: the angle wavefront)
@@ -263,12 +389,16 @@ __global__ __launch_bounds__(Blk<RB>::NTI) void inner_kernel(const double* __res
             for (int u = 0; u < EPT; ++u)
                 if (((xh + XS * u) >> 4) <= (y >> 4)) s[u] += g[(xh + XS * u) * PR];
         }
+        double dm = 0.0;
 #pragma unroll
         for (int u = 0; u < EPT; ++u) {
             const int x = xh + XS * u;
             Gb[0][x][y] = s[u];
             Ab[0][x][y] = (x == y) ? 1.0 : 0.0;
+            if (x == y) dm = fmax(dm, s[u]);
         }
+        for (int o = 32; o > 0; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o, 64));
+        if ((t & 63) == 0) gred[t >> 6] = dm;
     }
     if (t == 0) anyrot = 0;
     __syncthreads();
@@ -290,8 +420,8 @@ __global__ __launch_bounds__(Blk<RB>::NTI) void inner_kernel(const double* __res
     }
     __syncthreads();
     // off-diagonal measure before rotating; largest diagonal for the next sweep
-    double gmax_local = 0.0;
-    for (int i = 0; i < PR; ++i) gmax_local = fmax(gmax_local, Gb[0][i][i]);
+    double gmax_local = gred[0];
+    for (int i = 1; i < NW; ++i) gmax_local = fmax(gmax_local, gred[i]);
     const double kappa_s1 = kappa * sqrt(fmax(sigma1sq, gmax_local));
     double off = 0.0;
     if (upd) {
@@ -318,7 +448,7 @@ __global__ __launch_bounds__(Blk<RB>::NTI) void inner_kernel(const double* __res
         if (t == 0) rotated[P] = 0;
         return;
     }
-    if (t == 0) atomicAdd(work, 1ull);
+    if (t == 0) atomicAdd(work + 1, 1ull);
     // angles of round 0
     if (!upd && al < RB) {
         double c, s;
@@ -465,65 +595,23 @@ __global__ __launch_bounds__(Blk<RB>::NTI) void inner_kernel(const double* __res
     if (t == 0) rotated[P] = anyrot;
 }
 
-// Z_pair <- Q^T Z_pair with FP64 MFMA on a chunk of RCOLS columns: Q is staged
-// in LDS; each wavefront streams 16-column slices of the pair's rows from
-// memory straight into MFMA operands, fetching the next slice while the
-// matrix cores work on the current one, and writes the rotated values back
-// (wavefronts own disjoint columns, so the update is in place).
+// Rotation of columns [cb, ce) for the pairs of round r, cw columns per
+// workgroup (grid: column chunks x pairs).  Pairs without rotation skip.
+// work counts the columns rotated.
 template <int RB>
 __global__ __launch_bounds__(256) void rotate_kernel(double* __restrict__ Z, int p, int ld, int r, int nb,
                                                      const double* __restrict__ rot,
-                                                     const int* __restrict__ rotated,
+                                                     const int* __restrict__ rotated, int cb, int ce, int cw,
                                                      unsigned long long* __restrict__ work) {
     constexpr int PR = Blk<RB>::PR;
-    constexpr int NTM = PR / 16, KS = PR / 4, NIT = RCOLS / 64;   // row tiles, k steps, slices per wavefront
     const int P = blockIdx.y;
     if (!rotated[P]) return;
-    if (threadIdx.x == 0) atomicAdd(work, 1ull);
+    const int c0 = cb + blockIdx.x * cw, c1 = min(c0 + cw, ce);
+    if (threadIdx.x == 0) atomicAdd(work, (unsigned long long)(c1 - c0));
     __shared__ double Qs[PR][PR + 1];        // Q[k][m]
     const double* src = rot + (long)P * PR * PR;
-    const int t = threadIdx.x;
-    for (int e = t; e < PR * PR; e += 256) Qs[e / PR][e % PR] = src[e];
-    const int lane = t & 63, w = t >> 6;
-    const int l16 = lane & 15, kg = lane >> 4;
-    // row offsets of the operand rows this lane reads (-1: past the matrix)
-    long rk[KS];
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-        const int row = pair_row<RB>(P, 4 * ks + kg, r, nb);
-        rk[ks] = row < p ? (long)row * ld : -1;
-    }
-    const int c0 = blockIdx.x * RCOLS + w * 16 + l16;
-    double b[KS], bn[KS];
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) b[ks] = (rk[ks] >= 0 && c0 < ld) ? Z[rk[ks] + c0] : 0.0;
-    __syncthreads();
-    for (int it = 0; it < NIT; ++it) {
-        const int c = c0 + it * 64, cn = c + 64;
-        if (it + 1 < NIT) {
-#pragma unroll
-            for (int ks = 0; ks < KS; ++ks) bn[ks] = (rk[ks] >= 0 && cn < ld) ? Z[rk[ks] + cn] : 0.0;
-        }
-        d4_t acc[NTM];
-#pragma unroll
-        for (int tm = 0; tm < NTM; ++tm) acc[tm] = d4_t{0, 0, 0, 0};
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-            for (int tm = 0; tm < NTM; ++tm)
-                acc[tm] = __builtin_amdgcn_mfma_f64_16x16x4f64(Qs[4 * ks + kg][tm * 16 + l16], b[ks], acc[tm],
-                                                               0, 0, 0);
-#pragma unroll
-        for (int tm = 0; tm < NTM; ++tm)
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
-                const int m = tm * 16 + 4 * rr + kg;      // FP64 MFMA accumulator row
-                const int row = pair_row<RB>(P, m, r, nb);
-                if (row < p && c < ld) Z[(long)row * ld + c] = acc[tm][rr];
-            }
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) b[ks] = bn[ks];
-    }
+    for (int e = threadIdx.x; e < PR * PR; e += 256) Qs[e / PR][e % PR] = src[e];
+    rotate_cols<RB, 4, true>(Z, p, ld, P, r, nb, Qs, c0, c1, threadIdx.x, true);
 }
 
 __global__ __launch_bounds__(256) void row_norms_kernel(const double* __restrict__ Z, int q, int ld,
@@ -598,50 +686,75 @@ inline int block_rows(int p) { return p >= 256 ? 32 : 16; }
 
 template <int RB>
 void ws_sizes(int p, int q, size_t* gram, size_t* rot, size_t* off) {
-    constexpr int PR = Blk<RB>::PR, GW = Blk<RB>::GW;
+    constexpr int PR = Blk<RB>::PR, GC = Blk<RB>::GC;
     int nb = (p + RB - 1) / RB;
     if (nb < 2) nb = 2;
     if (nb & 1) ++nb;
-    const size_t npairs = nb / 2, nchunks = std::max(1, (q + GW - 1) / GW);
+    const size_t npairs = nb / 2, nchunks = std::max(1, (q + GC - 1) / GC);
     *gram = npairs * nchunks * PR * PR;
-    *rot = npairs * PR * PR;
+    *rot = 2 * npairs * PR * PR;     // rotations of two consecutive rounds
     *off = npairs + 24;
+}
+
+// Columns per rotate workgroup: wide chunks amortise the load of Q, narrow
+// ones give the launch enough workgroups to fill the chip.
+inline int rotate_width(int npairs, int ncols) {
+    int cw = 512;
+    while (cw > 128 && (long)npairs * ((ncols + cw - 1) / cw) < 256) cw /= 2;
+    return cw;
 }
 
 template <int RB>
 JacobiResult run_jacobi(double* Z, int p, int q, int ld, double tol, int max_sweeps, double* gram_ws,
                         double* rot_ws, double* off_ws, double* host_off, hipStream_t s, LaunchProbe* probe) {
-    constexpr int GW = Blk<RB>::GW, NT = Blk<RB>::NT, PR = Blk<RB>::PR;
+    constexpr int GC = Blk<RB>::GC, NT = Blk<RB>::NT, PR = Blk<RB>::PR, UW = Blk<RB>::UW;
     JacobiResult res;
     int nb = (p + RB - 1) / RB;
     if (nb < 2) nb = 2;
     if (nb & 1) ++nb;
     const int npairs = nb / 2;
-    const int nchunks = std::max(1, (q + GW - 1) / GW);
-    const int nrot = (ld + RCOLS - 1) / RCOLS;
+    const int nchunks = std::max(1, (q + GC - 1) / GC);
+    const int xw = rotate_width(npairs, q), nxr = std::max(1, (q + xw - 1) / xw);
+    const int nu = ld - q;                         // identity-part columns
+    const int nuch = (nu + UW - 1) / UW;
     // off_ws[0]: largest off-diagonal measure of the sweep, off_ws[1]: largest
-    // row norm squared seen in it, then one int per pair (rotated flag), then
-    // three work counters (gram chunks, inner pairs, rotated chunks)
+    // row norm squared seen in it, then the rotated flags of two consecutive
+    // rounds (npairs ints each), then four work counters (gram chunks, inner
+    // pairs, columns rotated by rotate launches, identity-part columns
+    // rotated by inner launches)
     int* rotated = reinterpret_cast<int*>(off_ws + 2);
     unsigned long long* work = reinterpret_cast<unsigned long long*>(off_ws + 2 + npairs);
-    if (probe) fill(off_ws + 2 + npairs, 0.0, 3, s);
+    if (probe) fill(off_ws + 2 + npairs, 0.0, 4, s);
     constexpr double kappa = 1e-3;
     double prev = 1e300, sigma1sq = 0.0;
+    // The identity part of round g's rotations is applied during round
+    // g + 1 (by the extra workgroups of its inner launch) and after the last
+    // round; rotations and flags alternate between two buffers.
+    long g = 0;
+    int rprev = -1;
     for (int sw = 0; sw < max_sweeps; ++sw) {
         fill(off_ws, 0.0, 2, s);
-        for (int r = 0; r < nb - 1; ++r) {
+        for (int r = 0; r < nb - 1; ++r, ++g) {
+            const int cur = (int)(g & 1);
+            double* rcur = rot_ws + (long)cur * npairs * PR * PR;
+            const double* rold = rot_ws + (long)(cur ^ 1) * npairs * PR * PR;
+            int* fcur = rotated + cur * npairs;
+            const int* fold = rotated + (cur ^ 1) * npairs;
             bool timed = probe && probe->begin(PK_GRAM, s);
             hipLaunchKernelGGL((gram_kernel<RB>), dim3(nchunks, npairs), dim3(256), 0, s, Z, p, q, ld, r, nb,
                                nchunks, gram_ws, work);
             if (timed) probe->end(PK_GRAM, s);
             timed = probe && probe->begin(PK_INNER, s);
-            hipLaunchKernelGGL((inner_kernel<RB>), dim3(npairs), dim3(Blk<RB>::NTI), 0, s, gram_ws, nchunks, p, r, nb, tol,
-                               kappa, sigma1sq, rot_ws, rotated, off_ws, work + 1);
+            const int ublocks = (rprev >= 0 && nu > 0) ? npairs * nuch : 0;
+            hipLaunchKernelGGL((inner_kernel<RB>), dim3(npairs + ublocks), dim3(Blk<RB>::NTI), 0, s, gram_ws,
+                               nchunks, p, r, nb, tol, kappa, sigma1sq, rcur, fcur, off_ws, work, Z, ld, q, npairs,
+                               rprev, rold, fold, nuch);
             if (timed) probe->end(PK_INNER, s);
             timed = probe && probe->begin(PK_ROTATE, s);
-            hipLaunchKernelGGL((rotate_kernel<RB>), dim3(nrot, npairs), dim3(256), 0, s, Z, p, ld, r, nb, rot_ws,
-                               rotated, work + 2);
+            hipLaunchKernelGGL((rotate_kernel<RB>), dim3(nxr, npairs), dim3(256), 0, s, Z, p, ld, r, nb, rcur,
+                               fcur, 0, q, xw, work + 2);
             if (timed) probe->end(PK_ROTATE, s);
+            rprev = r;
         }
         HIP_CHECK(hipGetLastError());
         HIP_CHECK(hipMemcpyAsync(host_off, off_ws, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -654,19 +767,32 @@ JacobiResult run_jacobi(double* Z, int p, int q, int ld, double tol, int max_swe
         if (sw >= 3 && *host_off > 0.5 * prev && *host_off < 1e3 * tol) break;
         prev = *host_off;
     }
+    if (rprev >= 0 && nu > 0) {
+        // identity part of the last round
+        const int cur = (int)((g - 1) & 1);
+        const int uw = rotate_width(npairs, nu);
+        bool timed = probe && probe->begin(PK_ROTATE, s);
+        hipLaunchKernelGGL((rotate_kernel<RB>), dim3((nu + uw - 1) / uw, npairs), dim3(256), 0, s, Z, p, ld, rprev,
+                           nb, rot_ws + (long)cur * npairs * PR * PR, rotated + cur * npairs, q, ld, uw, work + 2);
+        if (timed) probe->end(PK_ROTATE, s);
+        HIP_CHECK(hipGetLastError());
+    }
     if (probe) {
-        // algorithmic work actually done: a chunk Gram is 2 PR^2 GW flops over
-        // PR GW doubles read; a pair's inner sweep applies PR (PR - 1) / 2
+        // algorithmic work actually done: a chunk Gram is 2 PR^2 GC flops over
+        // PR GC doubles read; a pair's inner sweep applies PR (PR - 1) / 2
         // rotations to two rows and two columns of G and two rows of Q
         // (18 PR flops each) plus the Newton-Schulz step (4 PR^3); a rotated
-        // chunk is 2 PR^2 RCOLS flops over 2 PR RCOLS doubles read and written
-        unsigned long long cnt[3];
+        // column is 2 PR^2 flops over 2 PR doubles read and written (the
+        // identity-part columns rotated inside inner launches count there)
+        unsigned long long cnt[4];
         HIP_CHECK(hipMemcpyAsync(cnt, work, sizeof(cnt), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
         const double pr = PR;
-        probe->work(PK_GRAM, cnt[0] * 2.0 * pr * pr * GW, cnt[0] * 8.0 * pr * GW);
-        probe->work(PK_INNER, cnt[1] * (9.0 * pr * pr * (pr - 1) + 4.0 * pr * pr * pr), cnt[1] * 8.0 * 2 * pr * pr);
-        probe->work(PK_ROTATE, cnt[2] * 2.0 * pr * pr * RCOLS, cnt[2] * 16.0 * pr * RCOLS);
+        (void)NT;
+        probe->work(PK_GRAM, cnt[0] * 2.0 * pr * pr * GC, cnt[0] * 8.0 * pr * GC);
+        probe->work(PK_INNER, cnt[1] * (9.0 * pr * pr * (pr - 1) + 4.0 * pr * pr * pr) + cnt[3] * 2.0 * pr * pr,
+                    cnt[1] * 8.0 * 2 * pr * pr + cnt[3] * 16.0 * pr);
+        probe->work(PK_ROTATE, cnt[2] * 2.0 * pr * pr, cnt[2] * 16.0 * pr);
     }
     return res;
 }
@@ -681,6 +807,7 @@ void jacobi_workspace(int p, int q, size_t* gram, size_t* rot, size_t* off) {
 JacobiResult jacobi_rows(double* Z, int p, int q, int ld, double tol, int max_sweeps, double* gram_ws,
                          double* rot_ws, double* off_ws, double* host_off, hipStream_t s, LaunchProbe* probe) {
     if (p <= 1) return JacobiResult{};
+    ITE_REQUIRE((long)p * ld < 2147483647L, "svd: work matrix too large for 32-bit element offsets");
     if (block_rows(p) == 32)
         return run_jacobi<32>(Z, p, q, ld, tol, max_sweeps, gram_ws, rot_ws, off_ws, host_off, s, probe);
     return run_jacobi<16>(Z, p, q, ld, tol, max_sweeps, gram_ws, rot_ws, off_ws, host_off, s, probe);
