@@ -14,7 +14,8 @@
 // per panel of QB columns, one workgroup factors the panel (wavefront j owns
 // column j, each lane 32 of its rows), writes the reflectors V and the
 // triangular factor T with H_1 ... H_QB = I - V T V^T, and the trailing
-// columns are updated as Z_t <- Z_t - V (T^T (V^T Z_t)) with FP64 MFMA GEMMs.
+// columns are updated as Z_t <- Z_t - V (T^T (V^T Z_t)) by one launch whose
+// workgroups own 16-column blocks (FP64 MFMA).
 // The reflectors are kept transposed (one row per reflector) so that they are
 // written and read in whole rows.
 #include "internal.h"
@@ -26,8 +27,6 @@ namespace {
 
 constexpr int QB = 16;        // panel width
 constexpr int QRPL = 32;      // panel rows per lane: panels of up to 64 * 32 = 2048 rows
-constexpr int QKC = 128;      // rows per K chunk of V^T Z_t
-typedef double d4_t __attribute__((ext_vector_type(4)));
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -40,37 +39,50 @@ __device__ inline double wave_sum(double v) {
 // transposed to VT [QB][m] (row j = reflector j: zero above row j, one at row
 // j; rows nbw..QB-1 zero) and T [QB][QB] (upper triangular).  The panel moves
 // between memory and the wavefronts' registers through LDS in chunks of
-// QCH rows, so that every global access reads or writes whole rows.
+// QCH rows, so that every global access reads or writes whole rows; all
+// loads of the panel are in flight together.  A wavefront keeps its
+// reflector in its registers below the diagonal (where R is zero), and while
+// the wavefronts right of column j apply reflector j, those left of it form
+// their entries v_i . v_j of S = V^T V, which the recursion for T needs.
 constexpr int QCH = 512;
+constexpr int QNC = 64 * QRPL / QCH;    // LDS chunks per panel
 __global__ __launch_bounds__(1024) void qr_panel_kernel(double* __restrict__ P, int ld, int m, int nbw,
                                                         double* __restrict__ VT, double* __restrict__ T) {
     __shared__ double Pc[QCH][QB + 1];
     __shared__ double vs[64 * QRPL];
     __shared__ double tau_s[QB];
-    __shared__ double Sp[16][QB][QB + 1];
     __shared__ double S[QB][QB + 1];
     __shared__ double Ts[QB][QB + 1];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     const bool own = w < nbw;
+    if (t < QB * (QB + 1)) S[t / (QB + 1)][t % (QB + 1)] = 0.0;
     double a[QRPL];
 #pragma unroll
     for (int i = 0; i < QRPL; ++i) a[i] = 0.0;
-    // coalesced load: thread t moves 8 consecutive entries of row t / 2
-    for (int c0 = 0; c0 < 64 * QRPL; c0 += QCH) {
-        {
-            const int rr = t >> 1, h = (t & 1) * 8;
-            const int row = c0 + rr;
+    // coalesced load: thread t moves 8 consecutive entries of row t / 2 of
+    // every chunk
+    {
+        const int rr = t >> 1, h = (t & 1) * 8;
+        double ldv[QNC][8];
+#pragma unroll
+        for (int c = 0; c < QNC; ++c) {
+            const int row = c * QCH + rr;
 #pragma unroll
             for (int e = 0; e < 8; ++e)
-                Pc[rr][h + e] = (row < m && h + e < nbw) ? P[(long)row * ld + h + e] : 0.0;
+                ldv[c][e] = (row < m && h + e < nbw) ? P[(long)row * ld + h + e] : 0.0;
         }
-        __syncthreads();
 #pragma unroll
-        for (int i = 0; i < QRPL; ++i) {
-            const int row = lane + 64 * i;
-            if (row >= c0 && row < c0 + QCH) a[i] = Pc[row - c0][w];
+        for (int c = 0; c < QNC; ++c) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) Pc[rr][h + e] = ldv[c][e];
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < QRPL; ++i) {
+                const int row = lane + 64 * i;
+                if (row >= c * QCH && row < (c + 1) * QCH) a[i] = Pc[row - c * QCH][w];
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
     for (int j = 0; j < nbw; ++j) {
         if (w == j) {
@@ -97,31 +109,44 @@ __global__ __launch_bounds__(1024) void qr_panel_kernel(double* __restrict__ P, 
                 const int row = lane + 64 * i;
                 const double v = row == j ? 1.0 : ((row > j && row < m) ? a[i] * scale : 0.0);
                 vs[row] = v;
-                a[i] = row < j ? a[i] : (row == j ? beta : 0.0);
+                a[i] = row < j ? a[i] : (row == j ? beta : v);
             }
-            if (lane == 0) tau_s[j] = tau;
+            if (lane == 0) {
+                tau_s[j] = tau;
+                S[j][j] = 1.0 + sg * scale * scale;    // v . v
+            }
         }
         __syncthreads();
         for (int row = t; row < m; row += 1024) VT[(long)j * m + row] = vs[row];
-        if (own && w > j) {
-            const double tau = tau_s[j];
+        if (own && w != j) {
+            // w > j: apply reflector j to column w; w < j: S[w][j] = v_w . v_j
             double dot = 0.0;
 #pragma unroll
-            for (int i = 0; i < QRPL; ++i) dot += vs[lane + 64 * i] * a[i];
-            const double f = tau * wave_sum(dot);
-            // reload v from LDS below rather than keeping 32 more values live
-            asm volatile("" ::: "memory");
+            for (int i = 0; i < QRPL; ++i) {
+                const int row = lane + 64 * i;
+                const double x = w > j ? a[i] : (row == w ? 1.0 : (row > w ? a[i] : 0.0));
+                dot += vs[row] * x;
+            }
+            dot = wave_sum(dot);
+            if (w > j) {
+                const double f = tau_s[j] * dot;
+                // reload v from LDS below rather than keeping 32 more values live
+                asm volatile("" ::: "memory");
 #pragma unroll
-            for (int i = 0; i < QRPL; ++i) a[i] -= f * vs[lane + 64 * i];
+                for (int i = 0; i < QRPL; ++i) a[i] -= f * vs[lane + 64 * i];
+            } else if (lane == 0) {
+                S[w][j] = dot;
+            }
         }
         __syncthreads();
     }
-    // coalesced write-back of R and the zeros below it
+    // coalesced write-back of R and the zeros below it (the reflectors held
+    // below the diagonal are not part of R)
     for (int c0 = 0; c0 < 64 * QRPL; c0 += QCH) {
 #pragma unroll
         for (int i = 0; i < QRPL; ++i) {
             const int row = lane + 64 * i;
-            if (row >= c0 && row < c0 + QCH) Pc[row - c0][w] = a[i];
+            if (row >= c0 && row < c0 + QCH) Pc[row - c0][w] = row > w ? 0.0 : a[i];
         }
         __syncthreads();
         {
@@ -136,28 +161,6 @@ __global__ __launch_bounds__(1024) void qr_panel_kernel(double* __restrict__ P, 
     // reflector rows nbw..QB-1 are zero
     for (int e = t; e < (QB - nbw) * m; e += 1024) VT[(long)nbw * m + e] = 0.0;
     if (t < QB && t >= nbw) tau_s[t] = 0.0;
-    __syncthreads();
-    // S = V^T V with FP64 MFMA, the rows split over the 16 wavefronts
-    {
-        const int l16 = lane & 15, kg = lane >> 4;
-        d4_t acc = {0, 0, 0, 0};
-        const int rows_per_wave = (m + 15) / 16;
-        const int r0 = w * rows_per_wave, r1 = min(m, r0 + rows_per_wave);
-        for (int k0 = r0; k0 < r1; k0 += 4) {
-            const int row = k0 + kg;
-            const double v = (row < r1) ? VT[(long)l16 * m + row] : 0.0;
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v, v, acc, 0, 0, 0);
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) Sp[w][4 * r + kg][l16] = acc[r];
-    }
-    __syncthreads();
-    if (t < QB * QB) {
-        const int i = t / QB, k = t % QB;
-        double s = 0.0;
-        for (int ww = 0; ww < 16; ++ww) s += Sp[ww][i][k];
-        S[i][k] = s;
-    }
     __syncthreads();
     // T: T_jj = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] S[0:j, j]; column j by
     // lanes i < j of the first wavefront, one column after the other
@@ -181,43 +184,118 @@ __global__ __launch_bounds__(1024) void qr_panel_kernel(double* __restrict__ P, 
     if (t < QB * QB) T[t] = Ts[t / QB][t % QB];
 }
 
-// W2[r][c] = sum_k T[k][r] W[k][c] with W = sum over nchunk partials
-// Wp[b][k][c] (b < nchunk, k < QB, c < n).  Block: 16 rows x 64 columns.
-__global__ __launch_bounds__(1024) void qr_reduce_t_kernel(const double* __restrict__ Wp, int nchunk, int n,
-                                                           const double* __restrict__ T, double* __restrict__ W2) {
-    __shared__ double Ws[QB][64 + 1];
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+// Zt[:, cbeg:cbeg + 16 NCT] <- (I - V T V^T)^T Zt = Zt - V (T^T (V^T Zt)) for
+// the reflectors VT [QB][m] and T [QB][QB], by one workgroup of 16
+// wavefronts, in one pass over the rows for W = V^T Zt (FP64 MFMA, the rows
+// split over the wavefronts, partials summed in LDS) and one for the update
+// (FP64 MFMA, K = QB).  Columns at and past cend are left alone.
+template <int NCT>
+__global__ __launch_bounds__(1024) void qr_apply_kernel(double* __restrict__ Zt, int ld, int m, int nt,
+                                                        const double* __restrict__ VT,
+                                                        const double* __restrict__ T) {
+    constexpr int CW = 16 * NCT;
+    __shared__ double Wp[16][QB][CW + 1];
+    __shared__ double W2[QB][CW + 1];
     __shared__ double Ts[QB][QB + 1];
-    const int t = threadIdx.x, r = t / 64, cl = t % 64;
-    const int c = blockIdx.x * 64 + cl;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int l16 = lane & 15, kg = lane >> 4;
+    const int cbeg = blockIdx.x * CW, cend = min(nt, cbeg + CW);
     if (t < QB * QB) Ts[t / QB][t % QB] = T[t];
-    double s = 0.0;
-    if (c < n)
-        for (int b = 0; b < nchunk; ++b) s += Wp[((long)b * QB + r) * n + c];
-    Ws[r][cl] = s;
-    __syncthreads();
-    double acc = 0.0;
+    // W partials: wavefront w sums over its slice of rows
+    {
+        const int rw = ((m + 15) / 16 + 3) & ~3;
+        const int r0 = w * rw, r1 = min(m, r0 + rw);
+        d4_t acc[NCT];
 #pragma unroll
-    for (int k = 0; k < QB; ++k) acc += Ts[k][r] * Ws[k][cl];
-    if (c < n) W2[(long)r * n + c] = acc;
+        for (int ct = 0; ct < NCT; ++ct) acc[ct] = d4_t{0, 0, 0, 0};
+        // four k steps per iteration, their loads issued together
+        for (int k0 = r0; k0 < r1; k0 += 16) {
+            double av[4], bv[4][NCT];
+#pragma unroll
+            for (int st = 0; st < 4; ++st) {
+                const int row = k0 + 4 * st + kg;
+                av[st] = row < r1 ? VT[(long)l16 * m + row] : 0.0;
+#pragma unroll
+                for (int ct = 0; ct < NCT; ++ct) {
+                    const int col = cbeg + ct * 16 + l16;
+                    bv[st][ct] = (row < r1 && col < cend) ? Zt[(long)row * ld + col] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int st = 0; st < 4; ++st)
+#pragma unroll
+                for (int ct = 0; ct < NCT; ++ct)
+                    acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[st], bv[st][ct], acc[ct], 0, 0, 0);
+        }
+        // FP64 MFMA accumulator element rr of lane group kg is row 4 rr + kg
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) Wp[w][4 * rr + kg][ct * 16 + l16] = acc[ct][rr];
+    }
+    __syncthreads();
+    // W2 = T^T W, negated for the update below
+    if (t < QB * CW) {
+        const int i = t / CW, c = t % CW;
+        double sw = 0.0;
+        for (int ww = 0; ww < 16; ++ww) sw += Wp[ww][i][c];
+        Wp[0][i][c] = sw;     // row i of W; only this thread reads it back
+    }
+    __syncthreads();
+    if (t < QB * CW) {
+        const int r = t / CW, c = t % CW;
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < QB; ++k) acc += Ts[k][r] * Wp[0][k][c];
+        W2[r][c] = -acc;
+    }
+    __syncthreads();
+    // Zt -= V W2: 16-row tiles over the wavefronts
+    const int nrt = (m + 15) / 16;
+    for (int rt = w; rt < nrt; rt += 16) {
+        const int rowa = rt * 16 + l16;            // A operand row (V row)
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct) {
+            const int col = cbeg + ct * 16 + l16;
+            d4_t acc;
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int row = rt * 16 + 4 * rr + kg;
+                acc[rr] = (row < m && col < cend) ? Zt[(long)row * ld + col] : 0.0;
+            }
+#pragma unroll
+            for (int ks = 0; ks < QB / 4; ++ks) {
+                const int k = 4 * ks + kg;
+                const double a = rowa < m ? VT[(long)k * m + rowa] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, W2[k][ct * 16 + l16], acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int row = rt * 16 + 4 * rr + kg;
+                if (row < m && col < cend) Zt[(long)row * ld + col] = acc[rr];
+            }
+        }
+    }
 }
+
+constexpr int QNCT = 1;       // column tiles per apply workgroup
 
 }  // namespace
 
 bool householder_applies(int p, int q) { return p >= 256 && p <= 64 * QRPL && q >= QB; }
 
 size_t householder_workspace(int p, int q, int ld) {
-    const int nt = ld;   // trailing columns are at most ld
-    const int nchunk = (p + QKC - 1) / QKC;
-    return (size_t)p * QB + QB * QB + (size_t)nchunk * QB * nt + (size_t)QB * nt + 256;
+    (void)q;
+    (void)ld;
+    return (size_t)p * QB + QB * QB + 256;
 }
 
 void householder_rows(double* Z, int p, int q, int ld, double* ws, hipStream_t s) {
     const int kmax = std::min(p, q);
     double* VT = ws;
     double* T = VT + (size_t)p * QB;
-    double* Wp = T + QB * QB;
-    const int nchunk_max = (p + QKC - 1) / QKC;
-    double* W2 = Wp + (size_t)nchunk_max * QB * ld;
     for (int c0 = 0; c0 < kmax; c0 += QB) {
         const int nbw = std::min(QB, kmax - c0);
         const int m = p - c0;
@@ -225,37 +303,9 @@ void householder_rows(double* Z, int p, int q, int ld, double* ws, hipStream_t s
         hipLaunchKernelGGL(qr_panel_kernel, dim3(1), dim3(1024), 0, s, P, ld, m, nbw, VT, T);
         const int nt = ld - (c0 + nbw);
         if (nt <= 0) continue;
-        double* Zt = P + nbw;
-        // Wp[b] = V[b-th chunk]^T Zt[b-th chunk]: full chunks in one batched
-        // launch, the remainder in a second
-        const int nfull = m / QKC, rem = m % QKC;
-        if (nfull > 0) {
-            Gemm g;
-            g.M = QB; g.N = nt; g.K = QKC;
-            g.A = VT; g.lda = m; g.sA = QKC;
-            g.B = Zt; g.ldb = ld; g.sB = (long)QKC * ld;
-            g.D = Wp; g.ldd = nt; g.sD = (long)QB * nt;
-            g.batch = nfull;
-            gemm_f64(g, s);
-        }
-        if (rem > 0) {
-            Gemm g;
-            g.M = QB; g.N = nt; g.K = rem;
-            g.A = VT + (long)nfull * QKC; g.lda = m;
-            g.B = Zt + (long)nfull * QKC * ld; g.ldb = ld;
-            g.D = Wp + (long)nfull * QB * nt; g.ldd = nt;
-            gemm_f64(g, s);
-        }
-        const int nchunk = nfull + (rem > 0 ? 1 : 0);
-        hipLaunchKernelGGL(qr_reduce_t_kernel, dim3((nt + 63) / 64), dim3(1024), 0, s, Wp, nchunk, nt, T, W2);
-        // Zt -= V W2 (V = VT^T)
-        Gemm u;
-        u.M = m; u.N = nt; u.K = QB; u.tA = true; u.alpha = -1.0; u.beta = 1.0;
-        u.A = VT; u.lda = m;
-        u.B = W2; u.ldb = nt;
-        u.C = Zt; u.ldc = ld;
-        u.D = Zt; u.ldd = ld;
-        gemm_f64(u, s);
+        constexpr int CW = 16 * QNCT;
+        hipLaunchKernelGGL((qr_apply_kernel<QNCT>), dim3((nt + CW - 1) / CW), dim3(1024), 0, s, P + nbw, ld, m, nt,
+                           VT, T);
     }
     HIP_CHECK(hipGetLastError());
 }
