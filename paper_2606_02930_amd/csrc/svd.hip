@@ -59,13 +59,17 @@ __device__ inline int pair_row(int P, int lr, int r, int nb) {
     return lr < RB ? bi * RB + lr : bj * RB + (lr - RB);
 }
 
+// 4 GRAM_KS wavefronts: wavefront w forms tiles (w mod 4), (w mod 4) + 4, ...
+// over the part w / 4 of each stage's columns; the parts are summed in LDS.
+constexpr int GRAM_KS = 2, GRAM_NT = 256 * GRAM_KS;
 template <int RB>
-__global__ __launch_bounds__(256) void gram_kernel(const double* __restrict__ Z, int p, int q, int ld, int r,
-                                                   int nb, int nchunks, double* __restrict__ gram,
-                                                   unsigned long long* __restrict__ work) {
+__global__ __launch_bounds__(GRAM_NT) void gram_kernel(const double* __restrict__ Z, int p, int q, int ld, int r,
+                                                       int nb, int nchunks, double* __restrict__ gram,
+                                                       unsigned long long* __restrict__ work) {
     constexpr int PR = Blk<RB>::PR, GW = Blk<RB>::GW, GS = Blk<RB>::GS;
     constexpr int NTL = PR / 16, NTILE = NTL * (NTL + 1) / 2, TPW = (NTILE + 3) / 4;
-    constexpr int RPP = 256 / GW, NPASS = PR / RPP;
+    constexpr int RPP = GRAM_NT / GW, NPASS = PR / RPP, KH = GW / GRAM_KS;
+    static_assert(NPASS * RPP == PR && (GRAM_KS - 1) * 4 * TPW * 256 <= PR * (GW + 1), "gram layout");
     __shared__ double Xs[PR][GW + 1];
     const int P = blockIdx.y, chunk = blockIdx.x;
     const int t = threadIdx.x;
@@ -76,7 +80,7 @@ __global__ __launch_bounds__(256) void gram_kernel(const double* __restrict__ Z,
         const int row = pair_row<RB>(P, lr0 + RPP * u, r, nb);
         ro[u] = row < p ? (long)row * ld : -1;
     }
-    // all PR * GW / 256 loads of a stage in flight together; the next
+    // all PR * GW / GRAM_NT loads of a stage in flight together; the next
     // stage is fetched while the matrix cores work on the current one
     double v[NPASS];
     {
@@ -85,14 +89,13 @@ __global__ __launch_bounds__(256) void gram_kernel(const double* __restrict__ Z,
         for (int u = 0; u < NPASS; ++u) v[u] = (ro[u] >= 0 && c < q) ? Z[ro[u] + c] : 0.0;
     }
     if (t == 0) atomicAdd(work, 1ull);
-    const int lane = t & 63, w = t >> 6;
+    const int lane = t & 63, w = t >> 6, wt = w & 3, kh = w >> 2;
     const int l16 = lane & 15, kg = lane >> 4;
-    // the Gram is symmetric: only the tiles I <= J are formed and stored;
-    // wavefront w owns tiles w, w + 4, ...
+    // the Gram is symmetric: only the tiles I <= J are formed and stored
     int ti[TPW], tj[TPW];
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
-        int I = 0, J = w + 4 * i;
+        int I = 0, J = wt + 4 * i;
         while (J >= NTL - I && I < NTL) {
             J -= NTL - I;
             ++I;
@@ -115,20 +118,39 @@ __global__ __launch_bounds__(256) void gram_kernel(const double* __restrict__ Z,
         }
 #pragma unroll
         for (int i = 0; i < TPW; ++i) {
-            if (w + 4 * i >= NTILE) break;
+            if (wt + 4 * i >= NTILE) break;
             const int I = ti[i], J = tj[i];
-            for (int k0 = 0; k0 < GW; k0 += 4)
+            for (int k0 = kh * KH; k0 < (kh + 1) * KH; k0 += 4)
                 acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(Xs[I * 16 + l16][k0 + kg], Xs[J * 16 + l16][k0 + kg],
                                                               acc[i], 0, 0, 0);
         }
     }
-    double* out = gram + ((long)P * nchunks + chunk) * (PR * PR);
+    // column parts 1.. into LDS, summed by part 0 in a fixed order
+    __syncthreads();
+    double* red = &Xs[0][0];
+    if (kh > 0) {
 #pragma unroll
-    for (int i = 0; i < TPW; ++i) {
-        if (w + 4 * i >= NTILE) break;
-        // FP64 MFMA accumulator element rr of lane group kg is tile row 4 rr + kg
+        for (int i = 0; i < TPW; ++i) {
+            if (wt + 4 * i >= NTILE) break;
 #pragma unroll
-        for (int rr = 0; rr < 4; ++rr) out[(ti[i] * 16 + 4 * rr + kg) * PR + tj[i] * 16 + l16] = acc[i][rr];
+            for (int rr = 0; rr < 4; ++rr)
+                red[((((kh - 1) * 4 + wt) * TPW + i) * 4 + rr) * 64 + lane] = acc[i][rr];
+        }
+    }
+    __syncthreads();
+    if (kh == 0) {
+        double* out = gram + ((long)P * nchunks + chunk) * (PR * PR);
+#pragma unroll
+        for (int i = 0; i < TPW; ++i) {
+            if (wt + 4 * i >= NTILE) break;
+            // FP64 MFMA accumulator element rr of lane group kg is tile row 4 rr + kg
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                double sum = acc[i][rr];
+                for (int k = 1; k < GRAM_KS; ++k) sum += red[((((k - 1) * 4 + wt) * TPW + i) * 4 + rr) * 64 + lane];
+                out[(ti[i] * 16 + 4 * rr + kg) * PR + tj[i] * 16 + l16] = sum;
+            }
+        }
     }
 }
 
@@ -242,9 +264,9 @@ __device__ inline double rotated_entry(const double (*G)[2 * RB + 1], const doub
 // columns, so the update is in place).  Every thread of the workgroup calls
 // this (it holds one barrier: Q must be complete in LDS after it); threads
 // with `active` false only take part in the barrier.  PF: fetch one slice
-// ahead (twice the operand registers) and keep Q in registers across
-// slices; otherwise Q is read from LDS for every slice.
-template <int RB, int NWV, bool PF>
+// ahead (twice the operand registers); QREG: keep Q in registers across
+// slices (otherwise Q is read from LDS for every slice).
+template <int RB, int NWV, bool PF, bool QREG>
 __device__ inline void rotate_cols(double* __restrict__ Z, int p, int ld, int P, int r, int nb,
                                    const double (*Qs)[2 * RB + 1], int cb, int ce, int t, bool active) {
     constexpr int PR = 2 * RB;
@@ -275,7 +297,7 @@ __device__ inline void rotate_cols(double* __restrict__ Z, int p, int ld, int P,
     const int nit = (ce - cb + STRIDE - 1) / STRIDE;
     for (int it = 0; it < nit; ++it) {
         const int c = c0 + it * STRIDE, cn = c + STRIDE;
-        if (!PF) asm volatile("" ::: "memory");   // keeps the Q operand loads inside the loop
+        if (!QREG) asm volatile("" ::: "memory");   // keeps the Q operand loads inside the loop
         if (PF && it + 1 < nit) {
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) bn[PF ? ks : 0] = (rk[ks] >= 0 && cn < ce) ? Z[rk[ks] + cn] : 0.0;
@@ -356,7 +378,7 @@ __global__ __launch_bounds__(Blk<RB>::NTI) void inner_kernel(const double* __res
         if (threadIdx.x == 0) atomicAdd(work + 3, (unsigned long long)(ce - cb));
         const double* qsrc = rot_prev + (long)Pu * PR * PR;
         for (int e = threadIdx.x; e < PR * PR; e += NTI) Gb[0][e / PR][e % PR] = qsrc[e];
-        rotate_cols<RB, NW, false>(Z, p, ld, Pu, rprev, nb, Gb[0], cb, ce, threadIdx.x, threadIdx.x < NT);
+        rotate_cols<RB, NW, false, false>(Z, p, ld, Pu, rprev, nb, Gb[0], cb, ce, threadIdx.x, threadIdx.x < NT);
         return;
     }
     const int P = blockIdx.x;
@@ -598,8 +620,11 @@ __global__ __launch_bounds__(Blk<RB>::NTI) void inner_kernel(const double* __res
 // Rotation of columns [cb, ce) for the pairs of round r, cw columns per
 // workgroup (grid: column chunks x pairs).  Pairs without rotation skip.
 // work counts the columns rotated.
+// Eight wavefronts per workgroup with Q read from LDS for every slice (two
+// wavefronts per SIMD) measured faster than four holding Q in registers.
+constexpr int ROT_WAVES = 8;
 template <int RB>
-__global__ __launch_bounds__(256) void rotate_kernel(double* __restrict__ Z, int p, int ld, int r, int nb,
+__global__ __launch_bounds__(64 * ROT_WAVES) void rotate_kernel(double* __restrict__ Z, int p, int ld, int r, int nb,
                                                      const double* __restrict__ rot,
                                                      const int* __restrict__ rotated, int cb, int ce, int cw,
                                                      unsigned long long* __restrict__ work) {
@@ -610,8 +635,8 @@ __global__ __launch_bounds__(256) void rotate_kernel(double* __restrict__ Z, int
     if (threadIdx.x == 0) atomicAdd(work, (unsigned long long)(c1 - c0));
     __shared__ double Qs[PR][PR + 1];        // Q[k][m]
     const double* src = rot + (long)P * PR * PR;
-    for (int e = threadIdx.x; e < PR * PR; e += 256) Qs[e / PR][e % PR] = src[e];
-    rotate_cols<RB, 4, true>(Z, p, ld, P, r, nb, Qs, c0, c1, threadIdx.x, true);
+    for (int e = threadIdx.x; e < PR * PR; e += 64 * ROT_WAVES) Qs[e / PR][e % PR] = src[e];
+    rotate_cols<RB, ROT_WAVES, true, false>(Z, p, ld, P, r, nb, Qs, c0, c1, threadIdx.x, true);
 }
 
 __global__ __launch_bounds__(256) void row_norms_kernel(const double* __restrict__ Z, int q, int ld,
@@ -741,7 +766,7 @@ JacobiResult run_jacobi(double* Z, int p, int q, int ld, double tol, int max_swe
             int* fcur = rotated + cur * npairs;
             const int* fold = rotated + (cur ^ 1) * npairs;
             bool timed = probe && probe->begin(PK_GRAM, s);
-            hipLaunchKernelGGL((gram_kernel<RB>), dim3(nchunks, npairs), dim3(256), 0, s, Z, p, q, ld, r, nb,
+            hipLaunchKernelGGL((gram_kernel<RB>), dim3(nchunks, npairs), dim3(GRAM_NT), 0, s, Z, p, q, ld, r, nb,
                                nchunks, gram_ws, work);
             if (timed) probe->end(PK_GRAM, s);
             timed = probe && probe->begin(PK_INNER, s);
@@ -751,7 +776,7 @@ JacobiResult run_jacobi(double* Z, int p, int q, int ld, double tol, int max_swe
                                rprev, rold, fold, nuch);
             if (timed) probe->end(PK_INNER, s);
             timed = probe && probe->begin(PK_ROTATE, s);
-            hipLaunchKernelGGL((rotate_kernel<RB>), dim3(nxr, npairs), dim3(256), 0, s, Z, p, ld, r, nb, rcur,
+            hipLaunchKernelGGL((rotate_kernel<RB>), dim3(nxr, npairs), dim3(64 * ROT_WAVES), 0, s, Z, p, ld, r, nb, rcur,
                                fcur, 0, q, xw, work + 2);
             if (timed) probe->end(PK_ROTATE, s);
             rprev = r;
@@ -772,7 +797,7 @@ JacobiResult run_jacobi(double* Z, int p, int q, int ld, double tol, int max_swe
         const int cur = (int)((g - 1) & 1);
         const int uw = rotate_width(npairs, nu);
         bool timed = probe && probe->begin(PK_ROTATE, s);
-        hipLaunchKernelGGL((rotate_kernel<RB>), dim3((nu + uw - 1) / uw, npairs), dim3(256), 0, s, Z, p, ld, rprev,
+        hipLaunchKernelGGL((rotate_kernel<RB>), dim3((nu + uw - 1) / uw, npairs), dim3(64 * ROT_WAVES), 0, s, Z, p, ld, rprev,
                            nb, rot_ws + (long)cur * npairs * PR * PR, rotated + cur * npairs, q, ld, uw, work + 2);
         if (timed) probe->end(PK_ROTATE, s);
         HIP_CHECK(hipGetLastError());
