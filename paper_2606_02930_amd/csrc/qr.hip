@@ -28,10 +28,34 @@ namespace {
 constexpr int QB = 16;        // panel width
 constexpr int QRPL = 32;      // panel rows per lane: panels of up to 64 * 32 = 2048 rows
 
+// One DPP data movement on both halves of a double; lanes of rows outside
+// ROWS receive 0.
+template <int CTRL, int ROWS>
+__device__ inline double dpp_move(double v) {
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)bits, CTRL, ROWS, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), CTRL, ROWS, 0xf, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+__device__ inline double lane_value(double v, int lane) {
+    const long long bits = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)bits, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over the 64 lanes, returned to every lane: sums within quads, half
+// rows and rows by DPP lane permutations, then across the four rows by the
+// row broadcasts (lane 63 ends with the total).
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    v += dpp_move<0xB1, 0xf>(v);     // quad_perm [1, 0, 3, 2]
+    v += dpp_move<0x4E, 0xf>(v);     // quad_perm [2, 3, 0, 1]
+    v += dpp_move<0x141, 0xf>(v);    // row_half_mirror
+    v += dpp_move<0x140, 0xf>(v);    // row_mirror
+    v += dpp_move<0x142, 0xa>(v);    // row_bcast:15 into rows 1 and 3
+    v += dpp_move<0x143, 0xc>(v);    // row_bcast:31 into rows 2 and 3
+    return lane_value(v, 63);
 }
 
 // Factor the m x nbw panel at P (leading dimension ld), nbw <= QB, m <= 2048.
@@ -89,7 +113,7 @@ __global__ __launch_bounds__(1024) void qr_panel_kernel(double* __restrict__ P, 
             // reflector of column j over rows j..m-1 (LAPACK's convention:
             // beta = -sign(alpha) ||x||, tau = (beta - alpha) / beta,
             // v = x / (alpha - beta) with v_j = 1; tau = 0 when x_(j+1..) = 0)
-            const double alpha = __shfl(a[0], j, 64);     // row j < QB lies in a[0] of lane j
+            const double alpha = lane_value(a[0], j);     // row j < QB lies in a[0] of lane j
             double sg = 0.0;
 #pragma unroll
             for (int i = 0; i < QRPL; ++i) {
