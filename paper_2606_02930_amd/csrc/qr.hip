@@ -19,6 +19,7 @@
 // The reflectors are kept transposed (one row per reflector) so that they are
 // written and read in whole rows.
 #include "internal.h"
+#include "wave.h"
 
 #include <algorithm>
 
@@ -27,36 +28,6 @@ namespace {
 
 constexpr int QB = 16;        // panel width
 constexpr int QRPL = 32;      // panel rows per lane: panels of up to 64 * 32 = 2048 rows
-
-// One DPP data movement on both halves of a double; lanes of rows outside
-// ROWS receive 0.
-template <int CTRL, int ROWS>
-__device__ inline double dpp_move(double v) {
-    const long long bits = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)bits, CTRL, ROWS, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(bits >> 32), CTRL, ROWS, 0xf, false);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-
-__device__ inline double lane_value(double v, int lane) {
-    const long long bits = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)bits, lane);
-    const int hi = __builtin_amdgcn_readlane((int)(bits >> 32), lane);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-
-// Sum over the 64 lanes, returned to every lane: sums within quads, half
-// rows and rows by DPP lane permutations, then across the four rows by the
-// row broadcasts (lane 63 ends with the total).
-__device__ inline double wave_sum(double v) {
-    v += dpp_move<0xB1, 0xf>(v);     // quad_perm [1, 0, 3, 2]
-    v += dpp_move<0x4E, 0xf>(v);     // quad_perm [2, 3, 0, 1]
-    v += dpp_move<0x141, 0xf>(v);    // row_half_mirror
-    v += dpp_move<0x140, 0xf>(v);    // row_mirror
-    v += dpp_move<0x142, 0xa>(v);    // row_bcast:15 into rows 1 and 3
-    v += dpp_move<0x143, 0xc>(v);    // row_bcast:31 into rows 2 and 3
-    return lane_value(v, 63);
-}
 
 // Factor the m x nbw panel at P (leading dimension ld), nbw <= QB, m <= 2048.
 // Writes R (upper triangle) and zeros below it into the panel, the reflectors

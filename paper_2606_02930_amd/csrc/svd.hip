@@ -22,6 +22,7 @@
 // per sweep, and with it the traffic over the whole work matrix, at the price
 // of a longer inner sweep.
 #include "internal.h"
+#include "wave.h"
 
 #include <algorithm>
 #include <cmath>
@@ -388,22 +389,28 @@ __global__ __launch_bounds__(Blk<RB>::NTI) void inner_kernel(const double* __res
     const int y = t % PR, xh = t / PR;
     const double* src = gram + (long)P * nchunks * (PR * PR);
     if (upd) {
-        // four chunks per step so that 4 EPT loads are in flight together
+        // LB chunks per step so that LB EPT loads are in flight together
         // (the summation order is fixed: results do not depend on timing)
+        constexpr int LB = 4;
         double s[EPT];
 #pragma unroll
         for (int u = 0; u < EPT; ++u) s[u] = 0.0;
         int c = 0;
-        for (; c + 3 < nchunks; c += 4) {
+        for (; c + LB - 1 < nchunks; c += LB) {
             const double* g = src + (long)c * PR * PR + y;
-            double v[4][EPT];
+            double v[LB][EPT];
 #pragma unroll
-            for (int h = 0; h < 4; ++h)
+            for (int h = 0; h < LB; ++h)
 #pragma unroll
                 for (int u = 0; u < EPT; ++u)
                     v[h][u] = ((xh + XS * u) >> 4) <= (y >> 4) ? g[(long)h * PR * PR + (xh + XS * u) * PR] : 0.0;
 #pragma unroll
-            for (int u = 0; u < EPT; ++u) s[u] += (v[0][u] + v[1][u]) + (v[2][u] + v[3][u]);
+            for (int u = 0; u < EPT; ++u) {
+                double t4 = 0.0;
+#pragma unroll
+                for (int h = 0; h < LB; h += 4) t4 += (v[h][u] + v[h + 1][u]) + (v[h + 2][u] + v[h + 3][u]);
+                s[u] += t4;
+            }
         }
         for (; c < nchunks; ++c) {
             const double* g = src + (long)c * PR * PR + y;
@@ -419,7 +426,7 @@ __global__ __launch_bounds__(Blk<RB>::NTI) void inner_kernel(const double* __res
             Ab[0][x][y] = (x == y) ? 1.0 : 0.0;
             if (x == y) dm = fmax(dm, s[u]);
         }
-        for (int o = 32; o > 0; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o, 64));
+        dm = wave_max_nonneg(dm);
         if ((t & 63) == 0) gred[t >> 6] = dm;
     }
     if (t == 0) anyrot = 0;
@@ -457,7 +464,7 @@ __global__ __launch_bounds__(Blk<RB>::NTI) void inner_kernel(const double* __res
             }
         }
     }
-    for (int o = 32; o > 0; o >>= 1) off = fmax(off, __shfl_xor(off, o, 64));
+    off = wave_max_nonneg(off);
     if (upd && (t & 63) == 0) red[t >> 6] = off;
     __syncthreads();
     off = red[0];
