@@ -268,7 +268,7 @@ __device__ inline double rotated_entry(const double (*G)[2 * RB + 1], const doub
 // ahead (twice the operand registers); QREG: keep Q in registers across
 // slices (otherwise Q is read from LDS for every slice).
 template <int RB, int NWV, bool PF, bool QREG>
-__device__ inline void rotate_cols(double* __restrict__ Z, int p, int ld, int P, int r, int nb,
+__device__ __forceinline__ void rotate_cols(double* __restrict__ Z, int p, int ld, int P, int r, int nb,
                                    const double (*Qs)[2 * RB + 1], int cb, int ce, int t, bool active) {
     constexpr int PR = 2 * RB;
     constexpr int NTM = PR / 16, KS = PR / 4, STRIDE = 16 * NWV;   // row tiles, k steps, slice stride
@@ -328,13 +328,32 @@ __device__ inline void rotate_cols(double* __restrict__ Z, int p, int ld, int P,
     }
 }
 
-// One workgroup per pair: sum the chunk partials, then one cyclic sweep of
-// two-sided Jacobi rotations on the PR x PR Gram matrix (each rotation the
-// one of the two diagonalising angles that keeps the larger row at the lower
-// local index), then a Newton-Schulz step on the accumulated rotation; writes
-// Q (new row m = sum_k Q[k][m] old row k) and whether any rotation was
-// applied.  sigma1sq: largest row norm squared seen in the previous sweep
-// (0: use this pair's own).
+// Shared memory of one block pair's inner sweep: the Gram (two buffers, by
+// round parity), the accumulated rotation (two buffers), the angles of a
+// round and of the next, reduction slots.
+template <int RB> struct PairLDS {
+    static constexpr int PR = 2 * RB, NW = Blk<RB>::NT / 64;
+    double Gb[2][PR][PR + 1];
+    __align__(16) double Ab[2][PR][PR + 2];
+    double2 cs[2][RB];               // (cos, sin) of each pair's rotation, by round parity
+    double red[NW], gred[NW];
+    int anyrot;
+};
+
+// Buffer of PairLDS::Gb that holds Q after pair_sweep.
+template <int RB> constexpr int q_buffer() { return ((2 * RB - 1) & 1) ^ 1; }
+
+// One cyclic sweep of two-sided Jacobi rotations on the PR x PR Gram of a
+// block pair (each rotation the one of the two diagonalising angles that
+// keeps the larger row at the lower local index), then a Newton-Schulz step
+// on the accumulated rotation.  On entry Gb[0] holds the Gram's 16 x 16
+// tiles on and above the diagonal and Ab[0] the identity (written by the
+// caller; this function begins with a barrier).  sigma1sq: largest row norm
+// squared seen in the previous sweep (0: use this pair's own).  sweep_off
+// (may be null) receives, by atomic maximum, the off-diagonal measure and the
+// largest diagonal entry.  Returns 0 when the rows are already orthogonal to
+// the tolerance (nothing done), else 1 + whether any rotation was applied;
+// then Q (new row m = sum_k Q[k][m] old row k) is in Gb[q_buffer<RB>()].
 //
 // NT threads form G' = J G J^T of each round as RB x RB independent 2 x 2
 // block updates (rows and columns {i, i + RB} x {j, j + RB}) and the
@@ -345,96 +364,31 @@ __device__ inline void rotate_cols(double* __restrict__ Z, int p, int ld, int P,
 // round k it forms the three entries of G' each pair of round k + 1 needs and
 // that pair's angle, while the update of round k runs, so a round costs one
 // barrier.
-//
-// Workgroups npairs and up rotate the identity part (columns q .. ld) of
-// the rows of the previous round's pairs (round rprev, rotations rot_prev),
-// UW columns each: that work is off the critical path of the sweep and
-// fills the compute units the pairs leave idle.  work[1] counts the pairs
-// rotated, work[3] the identity-part columns rotated here.
 template <int RB>
-__global__ __launch_bounds__(Blk<RB>::NTI) void inner_kernel(const double* __restrict__ gram, int nchunks, int p,
-                                                             int r, int nb, double tol, double kappa,
-                                                             double sigma1sq, double* __restrict__ rot,
-                                                             int* __restrict__ rotated,
-                                                             double* __restrict__ sweep_off,
-                                                             unsigned long long* __restrict__ work,
-                                                             double* __restrict__ Z, int ld, int q, int npairs,
-                                                             int rprev, const double* __restrict__ rot_prev,
-                                                             const int* __restrict__ rotated_prev, int nuch) {
+__device__ __forceinline__ int pair_sweep(PairLDS<RB>& sh, double tol, double kappa, double sigma1sq, double* sweep_off,
+                          double& off_out) {
     constexpr int PR = Blk<RB>::PR, NT = Blk<RB>::NT, XS = Blk<RB>::XS, EPT = PR / XS;
     constexpr int QPT = RB * RB / NT, IS = NT / RB;     // 2 x 2 blocks per thread, their row stride
     constexpr int NW = NT / 64, NTL = PR / 16;          // update wavefronts, 16 x 16 tiles per side
-    constexpr int NTI = Blk<RB>::NTI, UW = Blk<RB>::UW;
     static_assert(QPT * NT == RB * RB && EPT * NT == PR * PR && (RB * PR / 2) % NT == 0, "thread layout");
     static_assert((NTL * NTL) % NW == 0, "tiles per wavefront");
-    __shared__ double Gb[2][PR][PR + 1];
-    __shared__ __align__(16) double Ab[2][PR][PR + 2];
-    __shared__ double2 cs[2][RB];               // (cos, sin) of each pair's rotation, by round parity
-    __shared__ double red[NW], gred[NW];
-    __shared__ int anyrot;
-    if ((int)blockIdx.x >= npairs) {
-        const int u = blockIdx.x - npairs, Pu = u / nuch, ch = u % nuch;
-        if (!rotated_prev[Pu]) return;
-        const int cb = q + ch * UW, ce = min(cb + UW, ld);
-        if (threadIdx.x == 0) atomicAdd(work + 3, (unsigned long long)(ce - cb));
-        const double* qsrc = rot_prev + (long)Pu * PR * PR;
-        for (int e = threadIdx.x; e < PR * PR; e += NTI) Gb[0][e / PR][e % PR] = qsrc[e];
-        rotate_cols<RB, NW, false, false>(Z, p, ld, Pu, rprev, nb, Gb[0], cb, ce, threadIdx.x, threadIdx.x < NT);
-        return;
-    }
-    const int P = blockIdx.x;
+    auto& Gb = sh.Gb;
+    auto& Ab = sh.Ab;
+    auto& cs = sh.cs;
+    auto& red = sh.red;
+    auto& gred = sh.gred;
+    int& anyrot = sh.anyrot;
     const int t = threadIdx.x;
     const bool upd = t < NT;                      // update thread (else: the angle wavefront)
     const int al = t - NT;                        // lane of the angle wavefront
     const int y = t % PR, xh = t / PR;
-    const double* src = gram + (long)P * nchunks * (PR * PR);
-    if (upd) {
-        // LB chunks per step so that LB EPT loads are in flight together
-        // (the summation order is fixed: results do not depend on timing)
-        constexpr int LB = 4;
-        double s[EPT];
-#pragma unroll
-        for (int u = 0; u < EPT; ++u) s[u] = 0.0;
-        int c = 0;
-        for (; c + LB - 1 < nchunks; c += LB) {
-            const double* g = src + (long)c * PR * PR + y;
-            double v[LB][EPT];
-#pragma unroll
-            for (int h = 0; h < LB; ++h)
-#pragma unroll
-                for (int u = 0; u < EPT; ++u)
-                    v[h][u] = ((xh + XS * u) >> 4) <= (y >> 4) ? g[(long)h * PR * PR + (xh + XS * u) * PR] : 0.0;
-#pragma unroll
-            for (int u = 0; u < EPT; ++u) {
-                double t4 = 0.0;
-#pragma unroll
-                for (int h = 0; h < LB; h += 4) t4 += (v[h][u] + v[h + 1][u]) + (v[h + 2][u] + v[h + 3][u]);
-                s[u] += t4;
-            }
-        }
-        for (; c < nchunks; ++c) {
-            const double* g = src + (long)c * PR * PR + y;
-#pragma unroll
-            for (int u = 0; u < EPT; ++u)
-                if (((xh + XS * u) >> 4) <= (y >> 4)) s[u] += g[(xh + XS * u) * PR];
-        }
-        double dm = 0.0;
-#pragma unroll
-        for (int u = 0; u < EPT; ++u) {
-            const int x = xh + XS * u;
-            Gb[0][x][y] = s[u];
-            Ab[0][x][y] = (x == y) ? 1.0 : 0.0;
-            if (x == y) dm = fmax(dm, s[u]);
-        }
-        dm = wave_max_nonneg(dm);
-        if ((t & 63) == 0) gred[t >> 6] = dm;
-    }
     if (t == 0) anyrot = 0;
     __syncthreads();
     // symmetrise: tiles below the diagonal were not formed and take the
     // transpose; inside a diagonal tile the two triangles come from different
     // MFMA lanes and are averaged
     if (upd) {
+        double dm = 0.0;
 #pragma unroll
         for (int u = 0; u < EPT; ++u) {
             const int x = xh + XS * u;
@@ -444,8 +398,12 @@ __global__ __launch_bounds__(Blk<RB>::NTI) void inner_kernel(const double* __res
                 const double v = 0.5 * (Gb[0][x][y] + Gb[0][y][x]);
                 Gb[0][x][y] = v;
                 Gb[0][y][x] = v;
+            } else if (x == y) {
+                dm = fmax(dm, Gb[0][x][y]);
             }
         }
+        dm = wave_max_nonneg(dm);
+        if ((t & 63) == 0) gred[t >> 6] = dm;
     }
     __syncthreads();
     // off-diagonal measure before rotating; largest diagonal for the next sweep
@@ -469,15 +427,12 @@ __global__ __launch_bounds__(Blk<RB>::NTI) void inner_kernel(const double* __res
     __syncthreads();
     off = red[0];
     for (int i = 1; i < NW; ++i) off = fmax(off, red[i]);
-    if (t == 0) {
+    off_out = off;
+    if (t == 0 && sweep_off) {
         atomic_max_pos(sweep_off, off);
         atomic_max_pos(sweep_off + 1, gmax_local);
     }
-    if (off <= tol) {
-        if (t == 0) rotated[P] = 0;
-        return;
-    }
-    if (t == 0) atomicAdd(work + 1, 1ull);
+    if (off <= tol) return 0;
     // angles of round 0
     if (!upd && al < RB) {
         double c, s;
@@ -613,7 +568,93 @@ __global__ __launch_bounds__(Blk<RB>::NTI) void inner_kernel(const double* __res
         }
     }
     __syncthreads();
+    return anyrot ? 2 : 1;
+}
+
+// One workgroup per pair: sum the chunk partials of the pair's Gram (tiles on
+// and above the diagonal) and run pair_sweep; writes Q and whether any
+// rotation was applied.
+//
+// Workgroups npairs and up rotate the identity part (columns q .. ld) of
+// the rows of the previous round's pairs (round rprev, rotations rot_prev),
+// UW columns each: that work is off the critical path of the sweep and
+// fills the compute units the pairs leave idle.  work[1] counts the pairs
+// swept, work[3] the identity-part columns rotated here.
+template <int RB>
+__global__ __launch_bounds__(Blk<RB>::NTI) void inner_kernel(const double* __restrict__ gram, int nchunks, int p,
+                                                             int r, int nb, double tol, double kappa,
+                                                             double sigma1sq, double* __restrict__ rot,
+                                                             int* __restrict__ rotated,
+                                                             double* __restrict__ sweep_off,
+                                                             unsigned long long* __restrict__ work,
+                                                             double* __restrict__ Z, int ld, int q, int npairs,
+                                                             int rprev, const double* __restrict__ rot_prev,
+                                                             const int* __restrict__ rotated_prev, int nuch) {
+    constexpr int PR = Blk<RB>::PR, NT = Blk<RB>::NT, XS = Blk<RB>::XS, EPT = PR / XS;
+    constexpr int NW = NT / 64;
+    constexpr int NTI = Blk<RB>::NTI, UW = Blk<RB>::UW;
+    __shared__ PairLDS<RB> sh;
+    if ((int)blockIdx.x >= npairs) {
+        const int u = blockIdx.x - npairs, Pu = u / nuch, ch = u % nuch;
+        if (!rotated_prev[Pu]) return;
+        const int cb = q + ch * UW, ce = min(cb + UW, ld);
+        if (threadIdx.x == 0) atomicAdd(work + 3, (unsigned long long)(ce - cb));
+        const double* qsrc = rot_prev + (long)Pu * PR * PR;
+        for (int e = threadIdx.x; e < PR * PR; e += NTI) sh.Gb[0][e / PR][e % PR] = qsrc[e];
+        rotate_cols<RB, NW, false, false>(Z, p, ld, Pu, rprev, nb, sh.Gb[0], cb, ce, threadIdx.x, threadIdx.x < NT);
+        return;
+    }
+    const int P = blockIdx.x;
+    const int t = threadIdx.x;
+    const bool upd = t < NT;
+    const int y = t % PR, xh = t / PR;
+    const double* src = gram + (long)P * nchunks * (PR * PR);
     if (upd) {
+        // LB chunks per step so that LB EPT loads are in flight together
+        // (the summation order is fixed: results do not depend on timing)
+        constexpr int LB = 4;
+        double s[EPT];
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) s[u] = 0.0;
+        int c = 0;
+        for (; c + LB - 1 < nchunks; c += LB) {
+            const double* g = src + (long)c * PR * PR + y;
+            double v[LB][EPT];
+#pragma unroll
+            for (int h = 0; h < LB; ++h)
+#pragma unroll
+                for (int u = 0; u < EPT; ++u)
+                    v[h][u] = ((xh + XS * u) >> 4) <= (y >> 4) ? g[(long)h * PR * PR + (xh + XS * u) * PR] : 0.0;
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) {
+                double t4 = 0.0;
+#pragma unroll
+                for (int h = 0; h < LB; h += 4) t4 += (v[h][u] + v[h + 1][u]) + (v[h + 2][u] + v[h + 3][u]);
+                s[u] += t4;
+            }
+        }
+        for (; c < nchunks; ++c) {
+            const double* g = src + (long)c * PR * PR + y;
+#pragma unroll
+            for (int u = 0; u < EPT; ++u)
+                if (((xh + XS * u) >> 4) <= (y >> 4)) s[u] += g[(xh + XS * u) * PR];
+        }
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) {
+            const int x = xh + XS * u;
+            sh.Gb[0][x][y] = s[u];
+            sh.Ab[0][x][y] = (x == y) ? 1.0 : 0.0;
+        }
+    }
+    double off;
+    const int res = pair_sweep<RB>(sh, tol, kappa, sigma1sq, sweep_off, off);
+    if (res == 0) {
+        if (t == 0) rotated[P] = 0;
+        return;
+    }
+    if (t == 0) atomicAdd(work + 1, 1ull);
+    if (upd) {
+        const auto& T = sh.Gb[q_buffer<RB>()];
         double* out = rot + (long)P * PR * PR;
 #pragma unroll
         for (int u = 0; u < EPT; ++u) {
@@ -621,7 +662,67 @@ __global__ __launch_bounds__(Blk<RB>::NTI) void inner_kernel(const double* __res
             out[x * PR + y] = T[x][y];
         }
     }
-    if (t == 0) rotated[P] = anyrot;
+    if (t == 0) rotated[P] = res == 2;
+}
+
+// The whole one-sided Jacobi of p <= PR rows (a single block pair) in one
+// workgroup, for small splits where launches and host round trips would
+// dominate: per sweep the Gram of the rows over the first q columns (FP64
+// MFMA straight from memory, tiles on and above the diagonal), pair_sweep,
+// and the rotation of the rows over all ld columns; until the rows are
+// orthogonal to the tolerance, the measure stagnates at the rounding floor
+// (as in the multi-pair driver), or max_sweeps.  res[0]: the last measure,
+// res[1]: the number of sweeps.
+template <int RB>
+__global__ __launch_bounds__(Blk<RB>::NTI) void single_pair_jacobi_kernel(double* __restrict__ Z, int p, int q,
+                                                                          int ld, double tol, double kappa,
+                                                                          int max_sweeps, double* __restrict__ res) {
+    constexpr int PR = Blk<RB>::PR, NT = Blk<RB>::NT, NW = NT / 64;
+    constexpr int NTL = PR / 16, NTILE = NTL * (NTL + 1) / 2;
+    __shared__ PairLDS<RB> sh;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int l16 = lane & 15, kg = lane >> 4;
+    double prev = 1e300, off = 0.0;
+    int sweeps = 0;
+    for (int sw = 0; sw < max_sweeps; ++sw) {
+        sweeps = sw + 1;
+        if (t < NT) {
+            for (int tile = w; tile < NTILE; tile += NW) {
+                int I = 0, J = tile;
+                while (J >= NTL - I) {
+                    J -= NTL - I;
+                    ++I;
+                }
+                J += I;
+                const int ra = I * 16 + l16, rb = J * 16 + l16;
+                const double* za = Z + (long)ra * ld;
+                const double* zb = Z + (long)rb * ld;
+                d4_t acc = {0, 0, 0, 0};
+                for (int k0 = 0; k0 < q; k0 += 4) {
+                    const int c = k0 + kg;
+                    const double a = (ra < p && c < q) ? za[c] : 0.0;
+                    const double b = (rb < p && c < q) ? zb[c] : 0.0;
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+                }
+                // FP64 MFMA accumulator element rr of lane group kg is tile row 4 rr + kg
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) sh.Gb[0][I * 16 + 4 * rr + kg][J * 16 + l16] = acc[rr];
+            }
+            for (int e = t; e < PR * PR; e += NT) sh.Ab[0][e / PR][e % PR] = (e / PR == e % PR) ? 1.0 : 0.0;
+        }
+        if (pair_sweep<RB>(sh, tol, kappa, 0.0, nullptr, off) == 0) break;
+        rotate_cols<RB, NW, false, false>(Z, p, ld, 0, 0, 2, sh.Gb[q_buffer<RB>()], 0, ld, t, t < NT);
+        // the next sweep's Gram reads the rotated rows: wait for the stores
+        // and drop stale lines of the vector cache
+        __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "agent");
+        if (sw >= 3 && off > 0.5 * prev && off < 1e3 * tol) break;
+        prev = off;
+    }
+    if (t == 0) {
+        res[0] = off;
+        res[1] = sweeps;
+    }
 }
 
 // Rotation of columns [cb, ce) for the pairs of round r, cw columns per
@@ -840,6 +941,31 @@ JacobiResult jacobi_rows(double* Z, int p, int q, int ld, double tol, int max_sw
                          double* rot_ws, double* off_ws, double* host_off, hipStream_t s, LaunchProbe* probe) {
     if (p <= 1) return JacobiResult{};
     ITE_REQUIRE((long)p * ld < 2147483647L, "svd: work matrix too large for 32-bit element offsets");
+    if (p <= Blk<32>::PR) {
+        // one block pair: the whole Jacobi in one launch and one host read
+        bool timed = probe && probe->begin(PK_INNER, s);
+        if (p <= Blk<16>::PR)
+            hipLaunchKernelGGL((single_pair_jacobi_kernel<16>), dim3(1), dim3(Blk<16>::NTI), 0, s, Z, p, q, ld, tol,
+                               1e-3, max_sweeps, off_ws);
+        else
+            hipLaunchKernelGGL((single_pair_jacobi_kernel<32>), dim3(1), dim3(Blk<32>::NTI), 0, s, Z, p, q, ld, tol,
+                               1e-3, max_sweeps, off_ws);
+        if (timed) probe->end(PK_INNER, s);
+        HIP_CHECK(hipGetLastError());
+        HIP_CHECK(hipMemcpyAsync(host_off, off_ws, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_CHECK(hipStreamSynchronize(s));
+        JacobiResult res;
+        res.last_off = host_off[0];
+        res.sweeps = (int)host_off[1];
+        if (probe) {
+            // per sweep: the Gram (p^2 q flops), the inner sweep of the pair and the
+            // rotation of p rows over ld columns
+            const double pr = p <= Blk<16>::PR ? Blk<16>::PR : Blk<32>::PR, sw = res.sweeps;
+            probe->work(PK_INNER, sw * (2.0 * p * p * q + 9.0 * pr * pr * (pr - 1) + 4.0 * pr * pr * pr + 2.0 * p * p * ld),
+                        sw * 8.0 * (double)p * (q + 2.0 * ld));
+        }
+        return res;
+    }
     if (block_rows(p) == 32)
         return run_jacobi<32>(Z, p, q, ld, tol, max_sweeps, gram_ws, rot_ws, off_ws, host_off, s, probe);
     return run_jacobi<16>(Z, p, q, ld, tol, max_sweeps, gram_ws, rot_ws, off_ws, host_off, s, probe);
