@@ -432,6 +432,115 @@ static void op_apply(ite_ctx* c, const LocalOp& op, const double* v, double* y) 
     heff_apply(c, op.s, op.L, *op.ww, op.R, v, op.beta, op.alpha, v, y, op.prec, op.Llo, op.Rlo);
 }
 
+// GMRES(m) with the fixed budget (no tolerance: m Arnoldi steps per cycle,
+// fewer only at an invariant subspace).  The Arnoldi steps are issued without
+// waiting for the host: the Hessenberg columns and the norms of b and of the
+// first residual stay on the device and come to the host once per cycle,
+// where the Givens rotations, the breakdown test and the least-squares solve
+// run.  Steps after a breakdown (the next basis vector divides by a
+// vanishing norm) are computed and discarded; the counts report the products
+// whose results enter the solution.  Same kernels in the same order as the
+// tolerance-driven loop below, so the results are the same.
+static SolveStats gmres_budget(ite_ctx* c, const LocalOp& op, const double* b, double* x, int m, int max_cycles,
+                               bool x_is_zero) {
+    SolveStats st;
+    const bool lo = op.prec != Prec::F64;
+    int& mv = lo ? st.matvecs_lo : st.matvecs64;
+    const size_t n = op.n();
+    const int mm = (int)std::min<size_t>((size_t)m, n);
+    constexpr int HC = 192;   // per column: [0,64) first-pass coefficients, [64,128) second pass, 128 norm
+    double* V = slot_t<double>(c, SL_V, (size_t)(mm + 1) * n);
+    double* w = slot_t<double>(c, SL_W, n);
+    const int nb = reduce_blocks(n);
+    double* part = slot_t<double>(c, SL_PART, (size_t)nb * 64 + 64);
+    double* hd = slot_t<double>(c, SL_HESS, (size_t)mm * HC + 8);
+    double* bnorm_d = hd + (size_t)mm * HC;       // ||b||
+    double* beta_d = bnorm_d + 1;                 // ||r0||
+    double* host = pinned(c, (size_t)mm * HC + 8 + 64);
+    dot_partials(b, b, n, part, c->stream);
+    finish_partials(part, 1, nb, bnorm_d, 2, c->stream);
+    std::vector<double> H((size_t)(mm + 1) * mm), cs(mm), sn(mm), g(mm + 1), y(mm);
+    for (int cyc = 0; cyc < max_cycles; ++cyc) {
+        // r0 = b - A x
+        bool r_product = false;
+        if (x_is_zero && cyc == 0) {
+            d2d(c, V, b, n);
+        } else {
+            op_apply(c, op, x, V);
+            r_product = true;
+            axpby(n, 1.0, b, -1.0, V, V, c->stream);
+        }
+        dot_partials(V, V, n, part, c->stream);
+        finish_partials(part, 1, nb, beta_d, 2, c->stream);
+        scale_inv(V, beta_d, V, n, c->stream);
+        for (int k = 0; k < mm; ++k) {
+            double* col = hd + (size_t)k * HC;
+            op_apply(c, op, V + (size_t)k * n, w);
+            mdot_partials(V, (long)n, k + 1, w, n, part, c->stream);
+            finish_partials(part, k + 1, nb, col, 0, c->stream);
+            gemv_sub(V, (long)n, k + 1, col, w, n, c->stream);
+            mdot_partials(V, (long)n, k + 1, w, n, part, c->stream);
+            finish_partials(part, k + 1, nb, col + 64, 0, c->stream);
+            gemv_sub(V, (long)n, k + 1, col + 64, w, n, c->stream);
+            dot_partials(w, w, n, part, c->stream);
+            finish_partials(part, 1, nb, col + 128, 2, c->stream);
+            if (k + 1 < mm) scale_inv(w, col + 128, V + (size_t)(k + 1) * n, n, c->stream);
+        }
+        d2h(c, host, hd, (size_t)mm * HC + 2);
+        sync(c);
+        if (r_product) mv++;
+        const double bnorm = host[(size_t)mm * HC], beta = host[(size_t)mm * HC + 1];
+        st.res_rel = bnorm > 0 ? beta / bnorm : 0.0;
+        if (!(beta > 0.0)) return st;
+        std::fill(H.begin(), H.end(), 0.0);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int kused = 0;
+        bool breakdown = false;
+        for (int k = 0; k < mm; ++k) {
+            const double* col = host + (size_t)k * HC;
+            for (int i = 0; i <= k; ++i) H[(size_t)i * mm + k] = col[i] + col[64 + i];
+            const double hnext = col[128];
+            for (int i = 0; i < k; ++i) {
+                const double a = H[(size_t)i * mm + k], bb = H[(size_t)(i + 1) * mm + k];
+                H[(size_t)i * mm + k] = cs[i] * a + sn[i] * bb;
+                H[(size_t)(i + 1) * mm + k] = -sn[i] * a + cs[i] * bb;
+            }
+            const double a = H[(size_t)k * mm + k];
+            const double rr = std::hypot(a, hnext);
+            cs[k] = rr > 0 ? a / rr : 1.0;
+            sn[k] = rr > 0 ? hnext / rr : 0.0;
+            H[(size_t)k * mm + k] = rr;
+            g[k + 1] = -sn[k] * g[k];
+            g[k] = cs[k] * g[k];
+            kused = k + 1;
+            st.res_rel = bnorm > 0 ? std::fabs(g[k + 1]) / bnorm : 0.0;
+            if (hnext <= 1e-14 * beta) {
+                st.flags |= ITE_FLAG_BREAKDOWN;
+                breakdown = true;
+                break;
+            }
+        }
+        mv += kused;
+        // back substitution R y = g
+        for (int i = kused - 1; i >= 0; --i) {
+            double s = g[i];
+            for (int j = i + 1; j < kused; ++j) s -= H[(size_t)i * mm + j] * y[j];
+            const double dgn = H[(size_t)i * mm + i];
+            y[i] = dgn != 0.0 ? s / dgn : 0.0;
+        }
+        double* ys = host + (size_t)mm * HC + 8;
+        for (int i = 0; i < kused; ++i) ys[i] = y[i];
+        double* ydev = slot_t<double>(c, SL_SMALL, 512) + 192;
+        h2d(c, ydev, ys, sizeof(double) * kused);
+        gemv_add(V, (long)n, kused, ydev, x, n, c->stream);
+        sync(c);
+        if (breakdown) return st;
+        if (cyc + 1 == max_cycles) st.flags |= ITE_FLAG_BUDGET_EXHAUSTED;
+    }
+    return st;
+}
+
 // GMRES(m) (Saad and Schultz) with classical Gram-Schmidt applied twice; the
 // Hessenberg column comes to the host once per Arnoldi step, where Givens
 // rotations keep the least-squares residual.  Vectors, Gram-Schmidt and the
@@ -439,6 +548,7 @@ static void op_apply(ite_ctx* c, const LocalOp& op, const double* v, double* y) 
 // x_is_zero the first residual is b itself (no product).
 static SolveStats gmres(ite_ctx* c, const LocalOp& op, const double* b, double* x, int m, int max_cycles,
                         double tol, bool x_is_zero = false) {
+    if (tol <= 0) return gmres_budget(c, op, b, x, m, max_cycles, x_is_zero);
     SolveStats st;
     const bool lo = op.prec != Prec::F64;
     int& mv = lo ? st.matvecs_lo : st.matvecs64;

@@ -20,6 +20,7 @@ enum SlotId {
     SL_TMPA, SL_TMPB,              // scratch environments (overlap, energy)
     SL_LO_L, SL_LO_R, SL_LO_T, SL_LO_X,   // low-precision shadows (mixed precision)
     SL_R64, SL_D64,                // refinement residual and correction
+    SL_HESS,                       // Hessenberg columns of a fixed-budget GMRES cycle
     SL_NSLOTS
 };
 
