@@ -475,7 +475,9 @@ static SolveStats gmres_budget(ite_ctx* c, const LocalOp& op, const double* b, d
         scale_inv(V, beta_d, V, n, c->stream);
         for (int k = 0; k < mm; ++k) {
             double* col = hd + (size_t)k * HC;
+            double* vnext = k + 1 < mm ? V + (size_t)(k + 1) * n : nullptr;
             op_apply(c, op, V + (size_t)k * n, w);
+            if (cgs2_small(V, (long)n, k + 1, w, n, col, vnext, c->stream)) continue;
             mdot_partials(V, (long)n, k + 1, w, n, part, c->stream);
             finish_partials(part, k + 1, nb, col, 0, c->stream);
             gemv_sub(V, (long)n, k + 1, col, w, n, c->stream);
@@ -484,7 +486,7 @@ static SolveStats gmres_budget(ite_ctx* c, const LocalOp& op, const double* b, d
             gemv_sub(V, (long)n, k + 1, col + 64, w, n, c->stream);
             dot_partials(w, w, n, part, c->stream);
             finish_partials(part, 1, nb, col + 128, 2, c->stream);
-            if (k + 1 < mm) scale_inv(w, col + 128, V + (size_t)(k + 1) * n, n, c->stream);
+            if (vnext) scale_inv(w, col + 128, vnext, n, c->stream);
         }
         d2h(c, host, hd, (size_t)mm * HC + 2);
         sync(c);
@@ -587,14 +589,16 @@ static SolveStats gmres(ite_ctx* c, const LocalOp& op, const double* b, double* 
         for (int k = 0; k < mm; ++k) {
             op_apply(c, op, V + (size_t)k * n, w);
             mv++;
-            mdot_partials(V, (long)n, k + 1, w, n, part, c->stream);
-            finish_partials(part, k + 1, nb, sm, 0, c->stream);
-            gemv_sub(V, (long)n, k + 1, sm, w, n, c->stream);
-            mdot_partials(V, (long)n, k + 1, w, n, part, c->stream);
-            finish_partials(part, k + 1, nb, sm + 64, 0, c->stream);
-            gemv_sub(V, (long)n, k + 1, sm + 64, w, n, c->stream);
-            dot_partials(w, w, n, part, c->stream);
-            finish_partials(part, 1, nb, sm + 128, 2, c->stream);
+            if (!cgs2_small(V, (long)n, k + 1, w, n, sm, nullptr, c->stream)) {
+                mdot_partials(V, (long)n, k + 1, w, n, part, c->stream);
+                finish_partials(part, k + 1, nb, sm, 0, c->stream);
+                gemv_sub(V, (long)n, k + 1, sm, w, n, c->stream);
+                mdot_partials(V, (long)n, k + 1, w, n, part, c->stream);
+                finish_partials(part, k + 1, nb, sm + 64, 0, c->stream);
+                gemv_sub(V, (long)n, k + 1, sm + 64, w, n, c->stream);
+                dot_partials(w, w, n, part, c->stream);
+                finish_partials(part, 1, nb, sm + 128, 2, c->stream);
+            }
             d2h(c, host, sm, 129);
             sync(c);
             for (int i = 0; i <= k; ++i) H[(size_t)i * mm + k] = host[i] + host[64 + i];

@@ -101,6 +101,11 @@ void axpby(size_t n, double a, const double* x, double b, const double* y, doubl
            hipStream_t s);
 // out = x / *den (device scalar); writes zeros when *den <= thresh
 void scale_inv(const double* x, const double* den, double* out, size_t n, hipStream_t s);
+// Both classical Gram-Schmidt passes of one Arnoldi step in a single
+// workgroup for n <= 8192 (k1 <= 64 basis vectors): coefficients to
+// col[0..k1) and col[64..64+k1), ||w|| to col[128], vnext = w / ||w|| when
+// not null.  Returns false (and does nothing) for longer vectors.
+bool cgs2_small(const double* V, long ldv, int k1, double* w, size_t n, double* col, double* vnext, hipStream_t s);
 // x *= a
 void scale(double* x, double a, size_t n, hipStream_t s);
 // y[i] = x[i*inc] for i < n (strided gather)

@@ -6,6 +6,7 @@
 // only), a fixed per-block order (wavefront shuffles, then LDS), and a second
 // pass that sums the block partials in index order.
 #include "internal.h"
+#include "wave.h"
 
 #include <cmath>
 
@@ -105,6 +106,75 @@ __global__ void axpby_kernel(size_t n, double a, const double* __restrict__ x, d
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
         out[i] = y ? a * x[i] + b * y[i] : a * x[i];
+}
+
+// Both Gram-Schmidt passes of one Arnoldi step for short vectors, in one
+// workgroup: w <- w - V (V^T w) twice (V: k1 vectors of length n, leading
+// dimension ldv), the coefficients of the passes to col[0..k1) and
+// col[64..64+k1), ||w|| to col[128] and, when vnext is given,
+// vnext = w / ||w|| (0 for a zero norm, as scale_inv).  Thread t owns the
+// entries t, t + CGS_T, ... of w, kept in LDS between the passes; fixed
+// reduction order.
+constexpr int CGS_T = 256, CGS_E = 32;
+template <int KMAX>
+__global__ __launch_bounds__(CGS_T) void cgs2_small_kernel(const double* __restrict__ V, long ldv, int k1,
+                                                           double* __restrict__ w, int n, double* __restrict__ col,
+                                                           double* __restrict__ vnext) {
+    __shared__ double xs[CGS_T * CGS_E];
+    __shared__ double part[CGS_T / 64][KMAX];
+    __shared__ double coef[KMAX];
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    for (int i = t; i < n; i += CGS_T) xs[i] = w[i];
+    for (int pass = 0; pass < 2; ++pass) {
+        double acc[KMAX];
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j) acc[j] = 0.0;
+        for (int i = t; i < n; i += CGS_T) {
+            const double xi = xs[i];
+#pragma unroll
+            for (int j = 0; j < KMAX; ++j)
+                if (j < k1) acc[j] += V[j * ldv + i] * xi;
+        }
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j) {
+            if (j < k1) {
+                const double sj = wave_sum(acc[j]);
+                if (lane == 0) part[wv][j] = sj;
+            }
+        }
+        __syncthreads();
+        if (t < k1) {
+            double sj = 0.0;
+#pragma unroll
+            for (int ww = 0; ww < CGS_T / 64; ++ww) sj += part[ww][t];
+            coef[t] = sj;
+            col[64 * pass + t] = sj;
+        }
+        __syncthreads();
+        for (int i = t; i < n; i += CGS_T) {
+            double xi = xs[i];
+#pragma unroll
+            for (int j = 0; j < KMAX; ++j)
+                if (j < k1) xi -= coef[j] * V[j * ldv + i];
+            xs[i] = xi;
+        }
+        __syncthreads();
+    }
+    double ss = 0.0;
+    for (int i = t; i < n; i += CGS_T) ss += xs[i] * xs[i];
+    ss = wave_sum(ss);
+    if (lane == 0) part[wv][0] = ss;
+    __syncthreads();
+    double tot = 0.0;
+#pragma unroll
+    for (int ww = 0; ww < CGS_T / 64; ++ww) tot += part[ww][0];
+    const double nrm = sqrt(fmax(tot, 0.0));
+    if (t == 0) col[128] = nrm;
+    const double inv = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    for (int i = t; i < n; i += CGS_T) {
+        w[i] = xs[i];
+        if (vnext) vnext[i] = xs[i] * inv;
+    }
 }
 
 __global__ void scale_inv_kernel(const double* __restrict__ x, const double* __restrict__ den,
@@ -299,6 +369,21 @@ void axpby(size_t n, double a, const double* x, double b, const double* y, doubl
     if (n == 0) return;
     hipLaunchKernelGGL(axpby_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, n, a, x, b, y, out);
     HIP_CHECK(hipGetLastError());
+}
+
+bool cgs2_small(const double* V, long ldv, int k1, double* w, size_t n, double* col, double* vnext, hipStream_t s) {
+    if (n == 0 || n > (size_t)CGS_T * CGS_E || k1 < 1 || k1 > 64) return false;
+    const int nn = (int)n;
+    if (k1 <= 8)
+        hipLaunchKernelGGL((cgs2_small_kernel<8>), dim3(1), dim3(CGS_T), 0, s, V, ldv, k1, w, nn, col, vnext);
+    else if (k1 <= 16)
+        hipLaunchKernelGGL((cgs2_small_kernel<16>), dim3(1), dim3(CGS_T), 0, s, V, ldv, k1, w, nn, col, vnext);
+    else if (k1 <= 32)
+        hipLaunchKernelGGL((cgs2_small_kernel<32>), dim3(1), dim3(CGS_T), 0, s, V, ldv, k1, w, nn, col, vnext);
+    else
+        hipLaunchKernelGGL((cgs2_small_kernel<64>), dim3(1), dim3(CGS_T), 0, s, V, ldv, k1, w, nn, col, vnext);
+    HIP_CHECK(hipGetLastError());
+    return true;
 }
 
 void scale_inv(const double* x, const double* den, double* out, size_t n, hipStream_t s) {
