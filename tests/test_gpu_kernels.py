@@ -166,9 +166,12 @@ def test_env_update_matches_oracle(env, with_mpo, direction, dims):
 
 # from p >= 256 rows the Jacobi runs on the Householder R factor: square,
 # more rows than columns (rows of R beyond q vanish) and fewer rows
-SPLIT_SHAPES = [(1, 2, 2, 1), (1, 2, 2, 2), (3, 2, 2, 5), (8, 2, 2, 3), (16, 2, 2, 16), (33, 2, 2, 17),
-                (64, 4, 4, 64), (256, 2, 2, 256), (200, 2, 2, 64), (64, 2, 2, 300), (130, 2, 2, 150),
-                (512, 2, 2, 512)]
+# up to 64 rows the whole Jacobi runs in one launch (16-row blocks up to 32
+# rows, 32-row blocks up to 64); from 256 rows on with Householder
+# preconditioning
+SPLIT_SHAPES = [(1, 2, 2, 1), (1, 2, 2, 2), (3, 2, 2, 5), (8, 2, 2, 3), (16, 2, 2, 16), (24, 2, 2, 20),
+                (32, 2, 2, 32), (33, 2, 2, 17), (64, 4, 4, 64), (256, 2, 2, 256), (200, 2, 2, 64),
+                (64, 2, 2, 300), (130, 2, 2, 150), (512, 2, 2, 512)]
 
 
 @pytest.mark.parametrize("direction", [0, 1])
@@ -273,6 +276,27 @@ def test_local_solve_matches_oracle(env, budget):
                                 b.reshape(-1)).reshape(b.shape)
         assert rel_err(got, exact) < 1e-11
         assert res <= 1e-13
+
+
+@pytest.mark.parametrize("D", [40, 48])
+def test_local_solve_paper_budget_longer_vectors(env, D):
+    # n = 6400 (both Gram-Schmidt passes in one launch) and n = 9216 (the
+    # multi-workgroup reductions): the same GMRES iterate as the oracle's
+    torch, ctx = env
+    rng = np.random.default_rng(90 + D)
+    Lm, Rm, W1, W2 = _symmetric_envs(rng, D, None, None)
+    Dl, Dr = Lm.shape[0], Rm.shape[0]
+    h, s = 0.2, -1.5
+    alpha, beta = 1.0 - h * s, h
+    b = rng.standard_normal((Dl, 2, 2, Dr))
+    x0 = rng.standard_normal((Dl, 2, 2, Dr))
+    op = lambda v: alpha * v + beta * omps.heff_apply(Lm, W1, W2, Rm, v)
+    want, info = omps.gmres(op, b, x0, 10, 1, 0.0)
+    x = torch.zeros(b.shape, dtype=torch.float64, device="cuda")
+    mv, res = ite.ite_debug_local_solve(ctx, dev(torch, Lm), W1, W2, dev(torch, Rm), alpha, beta, dev(torch, b),
+                                        dev(torch, x0), x, krylov_dim=10, max_cycles=1, tol=0.0)
+    assert mv == info["matvecs"] == 11
+    assert rel_err(host(x), want) < 1e-10
 
 
 @pytest.mark.parametrize("prec,bound", [(1, 2e-6), (2, 3e-2)])
