@@ -268,9 +268,10 @@ double ite_request_footprint(int L, const int* d, const int* w, int chi_max, int
         zmax = std::max(zmax, p * ((double)D[i] * d[i] + (double)d[i + 1] * D[i + 2]));
     }
     // psi and its working copy, three environment kinds, Krylov basis and
-    // solve vectors, the two contraction intermediates, the split work matrix
-    // and its Gram partials, low-precision shadows (at most half of FP64)
-    const double doubles = 2.0 * mps + envs + (krylov_dim + 8.0) * nmax + 2.0 * xmax + 2.0 * zmax +
+    // solve vectors, the two contraction intermediates, the split work matrix,
+    // its Gram partials and the second buffer of its data columns,
+    // low-precision shadows (at most half of FP64)
+    const double doubles = 2.0 * mps + envs + (krylov_dim + 8.0) * nmax + 2.0 * xmax + 3.0 * zmax +
                            0.5 * (envs + xmax + nmax);
     return 8.0 * doubles + (double)(64 << 20);
 }

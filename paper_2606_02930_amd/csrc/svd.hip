@@ -725,6 +725,148 @@ __global__ __launch_bounds__(Blk<RB>::NTI) void single_pair_jacobi_kernel(double
     }
 }
 
+// Position-to-pair bookkeeping of the circle schedule: the pair of round r
+// that holds block b, and whether b is that pair's higher-indexed block.
+__device__ inline void block_pair(int b, int r, int nb, int& P, int& side) {
+    const int m = nb - 1;
+    const int pos = b == 0 ? 0 : ((b - 1 - r) % m + m) % m + 1;
+    P = pos < nb / 2 ? pos : nb - 1 - pos;
+    const int b0 = circle_block(P, r, nb), b1 = circle_block(nb - 1 - P, r, nb);
+    side = b == (b0 < b1 ? b0 : b1) ? 0 : 1;
+}
+
+// Round r's rotation of the data columns fused with round r + 1's Gram: one
+// workgroup per pair P' of round r + 1 and column chunk (GC columns).  Its
+// two blocks come from two different pairs of round r; for each, the block's
+// new rows are formed from that pair's 2 RB old rows and the block's half of
+// Q (FP64 MFMA, operands streamed from memory one slice ahead), written to
+// the other data buffer (Xd: the old rows are read by two workgroups, so the
+// update cannot be in place), and kept in LDS for the Gram partial of P'
+// (tiles on and above the diagonal).  Pairs of round r without rotation
+// take Q = I (their rows are copied).  Eight wavefronts: wavefront w rotates
+// the 16-column slab w mod 4 of half w / 4 of every 64-column slice.
+template <int RB>
+__global__ __launch_bounds__(512) void rotate_gram_kernel(const double* __restrict__ Xs, int lds,
+                                                          double* __restrict__ Xd, int ldd, int p, int q, int r,
+                                                          int nb, int nchunks, const double* __restrict__ rot,
+                                                          const int* __restrict__ rotated,
+                                                          double* __restrict__ gram,
+                                                          unsigned long long* __restrict__ work) {
+    constexpr int PR = Blk<RB>::PR, GC = Blk<RB>::GC, KS = PR / 4, SW = 64;   // slice width
+    constexpr int NTL = PR / 16, NTILE = NTL * (NTL + 1) / 2, GTW = (NTILE + 7) / 8;
+    static_assert(RB == 32, "two 16-row tiles per half");
+    __shared__ double Qh[2][PR][RB + 1];     // Q[k][side RB + i] of each half's round-r pair
+    __shared__ double Ys[2][PR][SW + 1];     // new rows of P' over a slice (two slices in flight)
+    const int Pn = blockIdx.y, chunk = blockIdx.x;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int l16 = lane & 15, kg = lane >> 4;
+    const int rn = r + 1;
+    const int bn0 = circle_block(Pn, rn, nb), bn1 = circle_block(nb - 1 - Pn, rn, nb);
+    const int blk[2] = {bn0 < bn1 ? bn0 : bn1, bn0 < bn1 ? bn1 : bn0};
+    int Ph[2], sh[2];
+    block_pair(blk[0], r, nb, Ph[0], sh[0]);
+    block_pair(blk[1], r, nb, Ph[1], sh[1]);
+    for (int e = t; e < 2 * PR * RB; e += 512) {
+        const int h = e / (PR * RB), k = (e / RB) % PR, i = e % RB;
+        Qh[h][k][i] = rotated[Ph[h]] ? rot[(long)Ph[h] * PR * PR + k * PR + sh[h] * RB + i]
+                                     : (k == sh[h] * RB + i ? 1.0 : 0.0);
+    }
+    if (t == 0) atomicAdd(work, (unsigned long long)min(GC, q - chunk * GC));
+    // this wavefront: half hw, 16-column slab cs of each slice
+    const int hw = w >> 2, csl = w & 3;
+    int rk[KS], ro[2][4];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        const int row = pair_row<RB>(Ph[hw], 4 * ks + kg, r, nb);
+        rk[ks] = row < p ? row * lds : -1;
+    }
+#pragma unroll
+    for (int tm = 0; tm < 2; ++tm)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+            const int row = blk[hw] * RB + tm * 16 + 4 * rr + kg;   // FP64 MFMA accumulator row
+            ro[tm][rr] = row < p ? row * ldd : -1;
+        }
+    const int cb = chunk * GC, ce = min(q, cb + GC);
+    const int nsl = (ce - cb + SW - 1) / SW;
+    // Gram tiles of this wavefront: w, w + 8 (of the NTILE tiles I <= J)
+    int ti[GTW], tj[GTW];
+#pragma unroll
+    for (int i = 0; i < GTW; ++i) {
+        int I = 0, J = w + 8 * i;
+        while (J >= NTL - I && I < NTL) {
+            J -= NTL - I;
+            ++I;
+        }
+        ti[i] = I;
+        tj[i] = J + I;
+    }
+    d4_t gacc[GTW];
+#pragma unroll
+    for (int i = 0; i < GTW; ++i) gacc[i] = d4_t{0, 0, 0, 0};
+    double b[KS], bn[KS];
+    {
+        const int c = cb + csl * 16 + l16;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) b[ks] = (rk[ks] >= 0 && c < ce) ? Xs[rk[ks] + c] : 0.0;
+    }
+    __syncthreads();
+    for (int sl = 0; sl < nsl; ++sl) {
+        const int c = cb + sl * SW + csl * 16 + l16;
+        if (sl + 1 < nsl) {
+            const int cn = c + SW;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) bn[ks] = (rk[ks] >= 0 && cn < ce) ? Xs[rk[ks] + cn] : 0.0;
+        }
+        d4_t acc[2] = {d4_t{0, 0, 0, 0}, d4_t{0, 0, 0, 0}};
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+            for (int tm = 0; tm < 2; ++tm)
+                acc[tm] = __builtin_amdgcn_mfma_f64_16x16x4f64(Qh[hw][4 * ks + kg][tm * 16 + l16], b[ks], acc[tm],
+                                                               0, 0, 0);
+#pragma unroll
+        for (int tm = 0; tm < 2; ++tm)
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const bool in = ro[tm][rr] >= 0 && c < ce;
+                if (in) Xd[ro[tm][rr] + c] = acc[tm][rr];
+                Ys[sl & 1][hw * RB + tm * 16 + 4 * rr + kg][csl * 16 + l16] = in ? acc[tm][rr] : 0.0;
+            }
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) b[ks] = bn[ks];
+        // one barrier per slice: a wavefront writes the other buffer next,
+        // which every wavefront finished reading before reaching this barrier
+        __syncthreads();
+        const auto& Y = Ys[sl & 1];
+#pragma unroll
+        for (int i = 0; i < GTW; ++i) {
+            if (w + 8 * i >= NTILE) break;
+#pragma unroll
+            for (int k0 = 0; k0 < SW; k0 += 4)
+                gacc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(Y[ti[i] * 16 + l16][k0 + kg],
+                                                               Y[tj[i] * 16 + l16][k0 + kg], gacc[i], 0, 0, 0);
+        }
+    }
+    double* out = gram + ((long)Pn * nchunks + chunk) * (PR * PR);
+#pragma unroll
+    for (int i = 0; i < GTW; ++i) {
+        if (w + 8 * i >= NTILE) break;
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) out[(ti[i] * 16 + 4 * rr + kg) * PR + tj[i] * 16 + l16] = gacc[i][rr];
+    }
+}
+
+// Dst[i][c] = Src[i][c] for i < p, c < q (data columns back to the work matrix).
+__global__ void copy_cols_kernel(const double* __restrict__ src, int lds, double* __restrict__ dst, int ldd, int p,
+                                 int q) {
+    const long total = (long)p * q;
+    for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long)gridDim.x * blockDim.x) {
+        const int i = (int)(e / q), c = (int)(e % q);
+        dst[(long)i * ldd + c] = src[(long)i * lds + c];
+    }
+}
+
 // Rotation of columns [cb, ce) for the pairs of round r, cw columns per
 // workgroup (grid: column chunks x pairs).  Pairs without rotation skip.
 // work counts the columns rotated.
@@ -824,7 +966,8 @@ void ws_sizes(int p, int q, size_t* gram, size_t* rot, size_t* off) {
     if (nb < 2) nb = 2;
     if (nb & 1) ++nb;
     const size_t npairs = nb / 2, nchunks = std::max(1, (q + GC - 1) / GC);
-    *gram = npairs * nchunks * PR * PR;
+    // Gram partials, then (32-row blocks) the second buffer of the data columns
+    *gram = npairs * nchunks * PR * PR + (RB == 32 ? (size_t)p * q : 0);
     *rot = 2 * npairs * PR * PR;     // rotations of two consecutive rounds
     *off = npairs + 24;
 }
@@ -852,12 +995,23 @@ JacobiResult run_jacobi(double* Z, int p, int q, int ld, double tol, int max_swe
     const int nuch = (nu + UW - 1) / UW;
     // off_ws[0]: largest off-diagonal measure of the sweep, off_ws[1]: largest
     // row norm squared seen in it, then the rotated flags of two consecutive
-    // rounds (npairs ints each), then four work counters (gram chunks, inner
+    // rounds (npairs ints each), then five work counters (gram chunks, inner
     // pairs, columns rotated by rotate launches, identity-part columns
-    // rotated by inner launches)
+    // rotated by inner launches, data columns rotated by fused launches)
     int* rotated = reinterpret_cast<int*>(off_ws + 2);
     unsigned long long* work = reinterpret_cast<unsigned long long*>(off_ws + 2 + npairs);
-    if (probe) fill(off_ws + 2 + npairs, 0.0, 4, s);
+    if (probe) fill(off_ws + 2 + npairs, 0.0, 5, s);
+    // 32-row blocks: the rotation of round r and the Gram of round r + 1 are
+    // one launch, whose new data rows go to the other of two buffers (the Z
+    // columns 0..q and Xb); round g reads buffer g mod 2
+    constexpr bool fused = RB == 32;
+    double* Xb = gram_ws + (size_t)npairs * nchunks * PR * PR;
+    if (fused) {
+        bool timed = probe && probe->begin(PK_GRAM, s);
+        hipLaunchKernelGGL((gram_kernel<RB>), dim3(nchunks, npairs), dim3(GRAM_NT), 0, s, Z, p, q, ld, 0, nb,
+                           nchunks, gram_ws, work);
+        if (timed) probe->end(PK_GRAM, s);
+    }
     constexpr double kappa = 1e-3;
     double prev = 1e300, sigma1sq = 0.0;
     // The identity part of round g's rotations is applied during round
@@ -873,10 +1027,13 @@ JacobiResult run_jacobi(double* Z, int p, int q, int ld, double tol, int max_swe
             const double* rold = rot_ws + (long)(cur ^ 1) * npairs * PR * PR;
             int* fcur = rotated + cur * npairs;
             const int* fold = rotated + (cur ^ 1) * npairs;
-            bool timed = probe && probe->begin(PK_GRAM, s);
-            hipLaunchKernelGGL((gram_kernel<RB>), dim3(nchunks, npairs), dim3(GRAM_NT), 0, s, Z, p, q, ld, r, nb,
-                               nchunks, gram_ws, work);
-            if (timed) probe->end(PK_GRAM, s);
+            bool timed;
+            if (!fused) {
+                timed = probe && probe->begin(PK_GRAM, s);
+                hipLaunchKernelGGL((gram_kernel<RB>), dim3(nchunks, npairs), dim3(GRAM_NT), 0, s, Z, p, q, ld, r, nb,
+                                   nchunks, gram_ws, work);
+                if (timed) probe->end(PK_GRAM, s);
+            }
             timed = probe && probe->begin(PK_INNER, s);
             const int ublocks = (rprev >= 0 && nu > 0) ? npairs * nuch : 0;
             hipLaunchKernelGGL((inner_kernel<RB>), dim3(npairs + ublocks), dim3(Blk<RB>::NTI), 0, s, gram_ws,
@@ -884,8 +1041,15 @@ JacobiResult run_jacobi(double* Z, int p, int q, int ld, double tol, int max_swe
                                rprev, rold, fold, nuch);
             if (timed) probe->end(PK_INNER, s);
             timed = probe && probe->begin(PK_ROTATE, s);
-            hipLaunchKernelGGL((rotate_kernel<RB>), dim3(nxr, npairs), dim3(64 * ROT_WAVES), 0, s, Z, p, ld, r, nb, rcur,
-                               fcur, 0, q, xw, work + 2);
+            if constexpr (fused) {
+                const bool odd = g & 1;
+                hipLaunchKernelGGL((rotate_gram_kernel<RB>), dim3(nchunks, npairs), dim3(512), 0, s,
+                                   odd ? Xb : Z, odd ? q : ld, odd ? Z : Xb, odd ? ld : q, p, q, r, nb, nchunks, rcur,
+                                   fcur, gram_ws, work + 4);
+            } else {
+                hipLaunchKernelGGL((rotate_kernel<RB>), dim3(nxr, npairs), dim3(64 * ROT_WAVES), 0, s, Z, p, ld, r, nb,
+                                   rcur, fcur, 0, q, xw, work + 2);
+            }
             if (timed) probe->end(PK_ROTATE, s);
             rprev = r;
         }
@@ -899,6 +1063,13 @@ JacobiResult run_jacobi(double* Z, int p, int q, int ld, double tol, int max_swe
         // stagnation at the rounding floor: stop once the measure no longer drops
         if (sw >= 3 && *host_off > 0.5 * prev && *host_off < 1e3 * tol) break;
         prev = *host_off;
+    }
+    if (fused && (g & 1)) {
+        // the final data rows are in Xb
+        const long total = (long)p * q;
+        hipLaunchKernelGGL(copy_cols_kernel, dim3((int)std::min<long>(4096, (total + 255) / 256)), dim3(256), 0, s, Xb,
+                           q, Z, ld, p, q);
+        HIP_CHECK(hipGetLastError());
     }
     if (rprev >= 0 && nu > 0) {
         // identity part of the last round
@@ -916,8 +1087,10 @@ JacobiResult run_jacobi(double* Z, int p, int q, int ld, double tol, int max_swe
         // rotations to two rows and two columns of G and two rows of Q
         // (18 PR flops each) plus the Newton-Schulz step (4 PR^3); a rotated
         // column is 2 PR^2 flops over 2 PR doubles read and written (the
-        // identity-part columns rotated inside inner launches count there)
-        unsigned long long cnt[4];
+        // identity-part columns rotated inside inner launches count there);
+        // a fused column also forms the next round's Gram tiles (1.25 PR^2
+        // flops) and reads the 2 PR rows of both source pairs
+        unsigned long long cnt[5];
         HIP_CHECK(hipMemcpyAsync(cnt, work, sizeof(cnt), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
         const double pr = PR;
@@ -925,7 +1098,8 @@ JacobiResult run_jacobi(double* Z, int p, int q, int ld, double tol, int max_swe
         probe->work(PK_GRAM, cnt[0] * 2.0 * pr * pr * GC, cnt[0] * 8.0 * pr * GC);
         probe->work(PK_INNER, cnt[1] * (9.0 * pr * pr * (pr - 1) + 4.0 * pr * pr * pr) + cnt[3] * 2.0 * pr * pr,
                     cnt[1] * 8.0 * 2 * pr * pr + cnt[3] * 16.0 * pr);
-        probe->work(PK_ROTATE, cnt[2] * 2.0 * pr * pr, cnt[2] * 16.0 * pr);
+        probe->work(PK_ROTATE, cnt[2] * 2.0 * pr * pr + cnt[4] * 3.25 * pr * pr,
+                    cnt[2] * 16.0 * pr + cnt[4] * 24.0 * pr);
     }
     return res;
 }
