@@ -50,9 +50,10 @@ PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 DTYPE = {"fp64": "f64", "fp32": "f64+f32", "bf16": "f64+bf16"}
 # kernel kinds of the context's launch profile
 KERNELS = {0: ("gemm_kernel<double> (FP64 MFMA contraction)", "mfma"),
-           1: ("gram_kernel (Jacobi pair Gram, FP64 MFMA)", "hbm"),
+           1: ("gram_kernel (Jacobi pair Gram of a split's first round, FP64 MFMA)", "hbm"),
            2: ("inner_kernel (Jacobi inner sweep, FP64 vector, LDS)", "alu"),
-           3: ("rotate_kernel (Jacobi row rotation, FP64 MFMA)", "hbm")}
+           3: ("rotate_gram_kernel (Jacobi row rotation fused with the next round's pair Gram, FP64 MFMA; "
+               "rotate_kernel for 16-row blocks and the last identity-part rotation)", "hbm")}
 
 
 def log(msg):

@@ -648,18 +648,16 @@ __global__ __launch_bounds__(Blk<RB>::NTI) void inner_kernel(const double* __res
     }
     double off;
     const int res = pair_sweep<RB>(sh, tol, kappa, sigma1sq, sweep_off, off);
-    if (res == 0) {
-        if (t == 0) rotated[P] = 0;
-        return;
-    }
-    if (t == 0) atomicAdd(work + 1, 1ull);
+    if (res != 0 && t == 0) atomicAdd(work + 1, 1ull);
+    // Q of every pair is written (the identity when the rows are already
+    // orthogonal), so that the fused rotation reads it unconditionally
     if (upd) {
         const auto& T = sh.Gb[q_buffer<RB>()];
         double* out = rot + (long)P * PR * PR;
 #pragma unroll
         for (int u = 0; u < EPT; ++u) {
             const int x = xh + XS * u;
-            out[x * PR + y] = T[x][y];
+            out[x * PR + y] = res == 0 ? (x == y ? 1.0 : 0.0) : T[x][y];
         }
     }
     if (t == 0) rotated[P] = res == 2;
@@ -739,17 +737,18 @@ __device__ inline void block_pair(int b, int r, int nb, int& P, int& side) {
 // workgroup per pair P' of round r + 1 and column chunk (GC columns).  Its
 // two blocks come from two different pairs of round r; for each, the block's
 // new rows are formed from that pair's 2 RB old rows and the block's half of
-// Q (FP64 MFMA, operands streamed from memory one slice ahead), written to
+// Q (FP64 MFMA, all operand loads of the chunk issued up front), written to
 // the other data buffer (Xd: the old rows are read by two workgroups, so the
 // update cannot be in place), and kept in LDS for the Gram partial of P'
 // (tiles on and above the diagonal).  Pairs of round r without rotation
-// take Q = I (their rows are copied).  Eight wavefronts: wavefront w rotates
-// the 16-column slab w mod 4 of half w / 4 of every 64-column slice.
+// carry Q = I (written by the inner launch), so their rows are copied.
+// Eight wavefronts: wavefront w rotates the 16-column slab w mod 4 of half
+// w / 4 of every 64-column slice.  Xs is not declared __restrict__: its loads
+// must stay above the compiler barrier that keeps them in flight together.
 template <int RB>
-__global__ __launch_bounds__(512) void rotate_gram_kernel(const double* __restrict__ Xs, int lds,
+__global__ __launch_bounds__(512) void rotate_gram_kernel(const double* Xs, int lds,
                                                           double* __restrict__ Xd, int ldd, int p, int q, int r,
                                                           int nb, int nchunks, const double* __restrict__ rot,
-                                                          const int* __restrict__ rotated,
                                                           double* __restrict__ gram,
                                                           unsigned long long* __restrict__ work) {
     constexpr int PR = Blk<RB>::PR, GC = Blk<RB>::GC, KS = PR / 4, SW = 64;   // slice width
@@ -766,10 +765,16 @@ __global__ __launch_bounds__(512) void rotate_gram_kernel(const double* __restri
     int Ph[2], sh[2];
     block_pair(blk[0], r, nb, Ph[0], sh[0]);
     block_pair(blk[1], r, nb, Ph[1], sh[1]);
-    for (int e = t; e < 2 * PR * RB; e += 512) {
+    // Q of both round-r pairs (the identity for pairs without rotation is
+    // written by the inner launch), loaded before the data so that waiting
+    // for it leaves the data loads in flight
+    constexpr int QPT = 2 * PR * RB / 512;
+    double qv[QPT];
+#pragma unroll
+    for (int u = 0; u < QPT; ++u) {
+        const int e = t + 512 * u;
         const int h = e / (PR * RB), k = (e / RB) % PR, i = e % RB;
-        Qh[h][k][i] = rotated[Ph[h]] ? rot[(long)Ph[h] * PR * PR + k * PR + sh[h] * RB + i]
-                                     : (k == sh[h] * RB + i ? 1.0 : 0.0);
+        qv[u] = rot[(long)Ph[h] * PR * PR + k * PR + sh[h] * RB + i];
     }
     if (t == 0) atomicAdd(work, (unsigned long long)min(GC, q - chunk * GC));
     // this wavefront: half hw, 16-column slab cs of each slice
@@ -804,27 +809,39 @@ __global__ __launch_bounds__(512) void rotate_gram_kernel(const double* __restri
     d4_t gacc[GTW];
 #pragma unroll
     for (int i = 0; i < GTW; ++i) gacc[i] = d4_t{0, 0, 0, 0};
-    double b[KS], bn[KS];
-    {
-        const int c = cb + csl * 16 + l16;
+    // every data load of the chunk is issued before the first product (the
+    // launch has one workgroup per compute unit, so the loads in flight set
+    // the bandwidth); loads are unconditional (an out-of-range operand reads
+    // element 0 and is replaced by zero where it is used), which keeps the
+    // wait before each slice's products to that slice's loads
+    constexpr int NSL = GC / SW;
+    double b[NSL][KS];
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks) b[ks] = (rk[ks] >= 0 && c < ce) ? Xs[rk[ks] + c] : 0.0;
+    for (int sl = 0; sl < NSL; ++sl) {
+        const int c = cb + sl * SW + csl * 16 + l16;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) b[sl][ks] = Xs[(rk[ks] >= 0 && c < ce) ? rk[ks] + c : 0];
+    }
+    asm volatile("" ::: "memory");   // keeps the loads above from being moved down to their uses
+#pragma unroll
+    for (int u = 0; u < QPT; ++u) {
+        const int e = t + 512 * u;
+        Qh[e / (PR * RB)][(e / RB) % PR][e % RB] = qv[u];
     }
     __syncthreads();
-    for (int sl = 0; sl < nsl; ++sl) {
-        const int c = cb + sl * SW + csl * 16 + l16;
-        if (sl + 1 < nsl) {
-            const int cn = c + SW;
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks) bn[ks] = (rk[ks] >= 0 && cn < ce) ? Xs[rk[ks] + cn] : 0.0;
-        }
+    for (int sl = 0; sl < NSL; ++sl) {
+        if (sl >= nsl) break;
+        const int c = cb + sl * SW + csl * 16 + l16;
         d4_t acc[2] = {d4_t{0, 0, 0, 0}, d4_t{0, 0, 0, 0}};
 #pragma unroll
-        for (int ks = 0; ks < KS; ++ks)
+        for (int ks = 0; ks < KS; ++ks) {
+            const double bv = (rk[ks] >= 0 && c < ce) ? b[sl][ks] : 0.0;
 #pragma unroll
             for (int tm = 0; tm < 2; ++tm)
-                acc[tm] = __builtin_amdgcn_mfma_f64_16x16x4f64(Qh[hw][4 * ks + kg][tm * 16 + l16], b[ks], acc[tm],
-                                                               0, 0, 0);
+                acc[tm] = __builtin_amdgcn_mfma_f64_16x16x4f64(Qh[hw][4 * ks + kg][tm * 16 + l16], bv, acc[tm], 0,
+                                                               0, 0);
+        }
 #pragma unroll
         for (int tm = 0; tm < 2; ++tm)
 #pragma unroll
@@ -833,8 +850,6 @@ __global__ __launch_bounds__(512) void rotate_gram_kernel(const double* __restri
                 if (in) Xd[ro[tm][rr] + c] = acc[tm][rr];
                 Ys[sl & 1][hw * RB + tm * 16 + 4 * rr + kg][csl * 16 + l16] = in ? acc[tm][rr] : 0.0;
             }
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) b[ks] = bn[ks];
         // one barrier per slice: a wavefront writes the other buffer next,
         // which every wavefront finished reading before reaching this barrier
         __syncthreads();
@@ -1045,7 +1060,7 @@ JacobiResult run_jacobi(double* Z, int p, int q, int ld, double tol, int max_swe
                 const bool odd = g & 1;
                 hipLaunchKernelGGL((rotate_gram_kernel<RB>), dim3(nchunks, npairs), dim3(512), 0, s,
                                    odd ? Xb : Z, odd ? q : ld, odd ? Z : Xb, odd ? ld : q, p, q, r, nb, nchunks, rcur,
-                                   fcur, gram_ws, work + 4);
+                                   gram_ws, work + 4);
             } else {
                 hipLaunchKernelGGL((rotate_kernel<RB>), dim3(nxr, npairs), dim3(64 * ROT_WAVES), 0, s, Z, p, ld, r, nb,
                                    rcur, fcur, 0, q, xw, work + 2);
