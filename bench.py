@@ -53,7 +53,7 @@ KERNELS = {0: ("gemm_kernel<double> (FP64 MFMA contraction)", "mfma"),
            1: ("gram_kernel (Jacobi pair Gram of a split's first round, FP64 MFMA)", "hbm"),
            2: ("inner_kernel (Jacobi inner sweep, FP64 vector, LDS)", "alu"),
            3: ("rotate_gram_kernel (Jacobi row rotation fused with the next round's pair Gram, FP64 MFMA; "
-               "rotate_kernel for 16-row blocks and the last identity-part rotation)", "hbm")}
+               "rotate_kernel for 16-row blocks and the last identity-part rotation)", "mfma")}
 
 
 def log(msg):

@@ -872,6 +872,42 @@ __global__ __launch_bounds__(512) void rotate_gram_kernel(const double* Xs, int 
     }
 }
 
+// Convergence check over all row pairs at once, in place of a sweep that
+// would only confirm convergence: with G = X X^T (n x n, leading dimension
+// ldg) of the current rows, the largest orthogonality measure over i < j
+// (the measure and rounding floor of pair_sweep, sigma1^2 = the larger of
+// sigma1sq and the largest diagonal entry).  out[0]: the measure (atomic
+// maximum, cleared by the caller), out[1]: the largest diagonal entry.
+__global__ __launch_bounds__(256) void gram_diag_kernel(const double* __restrict__ G, int n, long ldg,
+                                                        double* __restrict__ diag, double* __restrict__ out) {
+    __shared__ double red[4];
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    const double v = j < n ? fmax(G[(long)j * ldg + j], 0.0) : 0.0;
+    if (j < n) diag[j] = v;
+    const double m = wave_max_nonneg(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) atomic_max_pos(out + 1, fmax(fmax(red[0], red[1]), fmax(red[2], red[3])));
+}
+
+__global__ __launch_bounds__(256) void gram_off_kernel(const double* __restrict__ G, int n, long ldg,
+                                                       const double* __restrict__ diag, double kappa,
+                                                       double sigma1sq, double* __restrict__ out) {
+    __shared__ double red[4];
+    const int i = blockIdx.x, t = threadIdx.x;
+    const double kappa_s1 = kappa * sqrt(fmax(sigma1sq, out[1]));
+    const double gii = diag[i];
+    double off = 0.0;
+    for (int j = i + 1 + t; j < n; j += 256) {
+        const double den = off_den(gii, diag[j], kappa_s1);
+        if (den > 0.0) off = fmax(off, fabs(G[(long)i * ldg + j]) / den);
+    }
+    off = wave_max_nonneg(off);
+    if ((t & 63) == 0) red[t >> 6] = off;
+    __syncthreads();
+    if (t == 0) atomic_max_pos(out, fmax(fmax(red[0], red[1]), fmax(red[2], red[3])));
+}
+
 // Dst[i][c] = Src[i][c] for i < p, c < q (data columns back to the work matrix).
 __global__ void copy_cols_kernel(const double* __restrict__ src, int lds, double* __restrict__ dst, int ldd, int p,
                                  int q) {
@@ -984,7 +1020,7 @@ void ws_sizes(int p, int q, size_t* gram, size_t* rot, size_t* off) {
     // Gram partials, then (32-row blocks) the second buffer of the data columns
     *gram = npairs * nchunks * PR * PR + (RB == 32 ? (size_t)p * q : 0);
     *rot = 2 * npairs * PR * PR;     // rotations of two consecutive rounds
-    *off = npairs + 24;
+    *off = npairs + 24 + (size_t)p;     // flags, counters, check result, Gram diagonal
 }
 
 // Columns per rotate workgroup: wide chunks amortise the load of Q, narrow
@@ -1029,6 +1065,7 @@ JacobiResult run_jacobi(double* Z, int p, int q, int ld, double tol, int max_swe
     }
     constexpr double kappa = 1e-3;
     double prev = 1e300, sigma1sq = 0.0;
+    int checks = 0;
     // The identity part of round g's rotations is applied during round
     // g + 1 (by the extra workgroups of its inner launch) and after the last
     // round; rotations and flags alternate between two buffers.
@@ -1071,13 +1108,52 @@ JacobiResult run_jacobi(double* Z, int p, int q, int ld, double tol, int max_swe
         HIP_CHECK(hipGetLastError());
         HIP_CHECK(hipMemcpyAsync(host_off, off_ws, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
+        const double soff = host_off[0];
         sigma1sq = host_off[1];
         res.sweeps = sw + 1;
-        res.last_off = *host_off;
-        if (*host_off <= tol) break;
+        res.last_off = soff;
+        if (soff <= tol) break;
+        // In the quadratic phase the next sweep would most likely only
+        // confirm convergence: check all row pairs at once instead, with the
+        // Gram of the current rows formed in the free data buffer (at most
+        // two checks per split)
+        if (fused && p <= q && soff < 1e-5 && checks < 2) {
+            ++checks;
+            const bool odd = g & 1;                    // the rows are in Xb when odd
+            const double* X = odd ? Xb : Z;
+            const long ldx = odd ? q : ld;
+            double* G = odd ? Z : Xb;
+            const long ldg = odd ? ld : p;
+            double* chk = off_ws + 2 + npairs + 8;
+            double* diag = chk + 8;
+            const bool timed = probe && probe->begin(PK_GRAM, s);
+            Gemm gm;
+            gm.M = p;
+            gm.N = p;
+            gm.K = q;
+            gm.tB = true;
+            gm.A = X;
+            gm.lda = ldx;
+            gm.B = X;
+            gm.ldb = ldx;
+            gm.D = G;
+            gm.ldd = ldg;
+            gemm_f64(gm, s);
+            fill(chk, 0.0, 2, s);
+            hipLaunchKernelGGL(gram_diag_kernel, dim3((p + 255) / 256), dim3(256), 0, s, G, p, ldg, diag, chk);
+            hipLaunchKernelGGL(gram_off_kernel, dim3(p), dim3(256), 0, s, G, p, ldg, diag, kappa, sigma1sq, chk);
+            if (timed) probe->end(PK_GRAM, s);
+            HIP_CHECK(hipGetLastError());
+            HIP_CHECK(hipMemcpyAsync(host_off, chk, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIP_CHECK(hipStreamSynchronize(s));
+            if (*host_off <= tol) {
+                res.last_off = *host_off;
+                break;
+            }
+        }
         // stagnation at the rounding floor: stop once the measure no longer drops
-        if (sw >= 3 && *host_off > 0.5 * prev && *host_off < 1e3 * tol) break;
-        prev = *host_off;
+        if (sw >= 3 && soff > 0.5 * prev && soff < 1e3 * tol) break;
+        prev = soff;
     }
     if (fused && (g & 1)) {
         // the final data rows are in Xb
@@ -1104,17 +1180,19 @@ JacobiResult run_jacobi(double* Z, int p, int q, int ld, double tol, int max_swe
         // column is 2 PR^2 flops over 2 PR doubles read and written (the
         // identity-part columns rotated inside inner launches count there);
         // a fused column also forms the next round's Gram tiles (1.25 PR^2
-        // flops) and reads the 2 PR rows of both source pairs
+        // flops, 10 tiles of 256 doubles written per GC columns); the check
+        // of all row pairs is one p x p x q product over the rows read once
         unsigned long long cnt[5];
         HIP_CHECK(hipMemcpyAsync(cnt, work, sizeof(cnt), hipMemcpyDeviceToHost, s));
         HIP_CHECK(hipStreamSynchronize(s));
         const double pr = PR;
         (void)NT;
-        probe->work(PK_GRAM, cnt[0] * 2.0 * pr * pr * GC, cnt[0] * 8.0 * pr * GC);
+        probe->work(PK_GRAM, cnt[0] * 2.0 * pr * pr * GC + checks * 2.0 * p * p * q,
+                    cnt[0] * 8.0 * pr * GC + checks * 8.0 * ((double)p * q + (double)p * p));
         probe->work(PK_INNER, cnt[1] * (9.0 * pr * pr * (pr - 1) + 4.0 * pr * pr * pr) + cnt[3] * 2.0 * pr * pr,
                     cnt[1] * 8.0 * 2 * pr * pr + cnt[3] * 16.0 * pr);
         probe->work(PK_ROTATE, cnt[2] * 2.0 * pr * pr + cnt[4] * 3.25 * pr * pr,
-                    cnt[2] * 16.0 * pr + cnt[4] * 24.0 * pr);
+                    cnt[2] * 16.0 * pr + cnt[4] * (16.0 * pr + 8.0 * 10 * 256 / GC));
     }
     return res;
 }
