@@ -1117,7 +1117,7 @@ JacobiResult run_jacobi(double* Z, int p, int q, int ld, double tol, int max_swe
         // confirm convergence: check all row pairs at once instead, with the
         // Gram of the current rows formed in the free data buffer (at most
         // two checks per split)
-        if (fused && p <= q && soff < 1e-5 && checks < 2) {
+        if (fused && p <= q && soff < 1e-6 && checks < 2) {
             ++checks;
             const bool odd = g & 1;                    // the rows are in Xb when odd
             const double* X = odd ? Xb : Z;
