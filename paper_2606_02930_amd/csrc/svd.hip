@@ -757,7 +757,8 @@ __global__ __launch_bounds__(512) void rotate_gram_kernel(const double* Xs, int 
     __shared__ double Qh[2][PR][RB + 1];     // Q[k][side RB + i] of each half's round-r pair
     __shared__ double Ys[2][PR][SW + 1];     // new rows of P' over a slice (two slices in flight)
     const int Pn = blockIdx.y, chunk = blockIdx.x;
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int t = threadIdx.x, lane = t & 63;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);   // wavefront-uniform: schedule arithmetic stays scalar
     const int l16 = lane & 15, kg = lane >> 4;
     const int rn = r + 1;
     const int bn0 = circle_block(Pn, rn, nb), bn1 = circle_block(nb - 1 - Pn, rn, nb);
@@ -780,10 +781,16 @@ __global__ __launch_bounds__(512) void rotate_gram_kernel(const double* Xs, int 
     // this wavefront: half hw, 16-column slab cs of each slice
     const int hw = w >> 2, csl = w & 3;
     int rk[KS], ro[2][4];
+    {
+        // local rows 0..RB-1 of the round-r pair are its lower-indexed block
+        const int s0 = circle_block(Ph[hw], r, nb), s1 = circle_block(nb - 1 - Ph[hw], r, nb);
+        const int bi = s0 < s1 ? s0 : s1, bj = s0 < s1 ? s1 : s0;
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-        const int row = pair_row<RB>(Ph[hw], 4 * ks + kg, r, nb);
-        rk[ks] = row < p ? row * lds : -1;
+        for (int ks = 0; ks < KS; ++ks) {
+            const int lr = 4 * ks + kg;
+            const int row = ks < KS / 2 ? bi * RB + lr : bj * RB + (lr - RB);
+            rk[ks] = row < p ? row * lds : -1;
+        }
     }
 #pragma unroll
     for (int tm = 0; tm < 2; ++tm)
@@ -809,18 +816,17 @@ __global__ __launch_bounds__(512) void rotate_gram_kernel(const double* Xs, int 
     d4_t gacc[GTW];
 #pragma unroll
     for (int i = 0; i < GTW; ++i) gacc[i] = d4_t{0, 0, 0, 0};
-    // every data load of the chunk is issued before the first product (the
-    // launch has one workgroup per compute unit, so the loads in flight set
-    // the bandwidth); loads are unconditional (an out-of-range operand reads
-    // element 0 and is replaced by zero where it is used), which keeps the
-    // wait before each slice's products to that slice's loads
-    constexpr int NSL = GC / SW;
-    double b[NSL][KS];
+    // Data operands one slice ahead: the loads of slice sl + 1 are issued
+    // right after the products of slice sl, into the registers those
+    // products consumed, and unconditionally (an out-of-range operand reads
+    // element 0 and is replaced by zero where it is used; past the last slice
+    // they reread element 0), so that the wait before each slice's products
+    // covers exactly that slice's loads.
+    double b[KS];
+    {
+        const int c = cb + csl * 16 + l16;
 #pragma unroll
-    for (int sl = 0; sl < NSL; ++sl) {
-        const int c = cb + sl * SW + csl * 16 + l16;
-#pragma unroll
-        for (int ks = 0; ks < KS; ++ks) b[sl][ks] = Xs[(rk[ks] >= 0 && c < ce) ? rk[ks] + c : 0];
+        for (int ks = 0; ks < KS; ++ks) b[ks] = Xs[(rk[ks] >= 0 && c < ce) ? rk[ks] + c : 0];
     }
     asm volatile("" ::: "memory");   // keeps the loads above from being moved down to their uses
 #pragma unroll
@@ -829,18 +835,29 @@ __global__ __launch_bounds__(512) void rotate_gram_kernel(const double* Xs, int 
         Qh[e / (PR * RB)][(e / RB) % PR][e % RB] = qv[u];
     }
     __syncthreads();
+    // this wavefront's Q operands stay in registers for every slice
+    double qa[KS][2];
 #pragma unroll
-    for (int sl = 0; sl < NSL; ++sl) {
-        if (sl >= nsl) break;
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int tm = 0; tm < 2; ++tm) {
+            qa[ks][tm] = Qh[hw][4 * ks + kg][tm * 16 + l16];
+            asm volatile("" : "+v"(qa[ks][tm]));   // held in registers, not reread from LDS per slice
+        }
+    for (int sl = 0; sl < nsl; ++sl) {
         const int c = cb + sl * SW + csl * 16 + l16;
         d4_t acc[2] = {d4_t{0, 0, 0, 0}, d4_t{0, 0, 0, 0}};
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            const double bv = (rk[ks] >= 0 && c < ce) ? b[sl][ks] : 0.0;
+            const double bv = (rk[ks] >= 0 && c < ce) ? b[ks] : 0.0;
 #pragma unroll
             for (int tm = 0; tm < 2; ++tm)
-                acc[tm] = __builtin_amdgcn_mfma_f64_16x16x4f64(Qh[hw][4 * ks + kg][tm * 16 + l16], bv, acc[tm], 0,
-                                                               0, 0);
+                acc[tm] = __builtin_amdgcn_mfma_f64_16x16x4f64(qa[ks][tm], bv, acc[tm], 0, 0, 0);
+        }
+        {
+            const int cn = c + SW;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) b[ks] = Xs[(rk[ks] >= 0 && cn < ce) ? rk[ks] + cn : 0];
         }
 #pragma unroll
         for (int tm = 0; tm < 2; ++tm)
@@ -854,13 +871,21 @@ __global__ __launch_bounds__(512) void rotate_gram_kernel(const double* Xs, int 
         // which every wavefront finished reading before reaching this barrier
         __syncthreads();
         const auto& Y = Ys[sl & 1];
+        // per tile: all operands read from LDS first, then two independent
+        // accumulation chains (even and odd k steps)
 #pragma unroll
         for (int i = 0; i < GTW; ++i) {
             if (w + 8 * i >= NTILE) break;
+            double ya[SW / 4], yb[SW / 4];
 #pragma unroll
-            for (int k0 = 0; k0 < SW; k0 += 4)
-                gacc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(Y[ti[i] * 16 + l16][k0 + kg],
-                                                               Y[tj[i] * 16 + l16][k0 + kg], gacc[i], 0, 0, 0);
+            for (int k = 0; k < SW / 4; ++k) {
+                ya[k] = Y[ti[i] * 16 + l16][4 * k + kg];
+                yb[k] = Y[tj[i] * 16 + l16][4 * k + kg];
+            }
+            d4_t g2[2] = {d4_t{0, 0, 0, 0}, d4_t{0, 0, 0, 0}};
+#pragma unroll
+            for (int k = 0; k < SW / 4; ++k) g2[k & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(ya[k], yb[k], g2[k & 1], 0, 0, 0);
+            gacc[i] += g2[0] + g2[1];
         }
     }
     double* out = gram + ((long)Pn * nchunks + chunk) * (PR * PR);
