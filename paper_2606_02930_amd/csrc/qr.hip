@@ -34,127 +34,145 @@ constexpr int QRPL = 32;      // panel rows per lane: panels of up to 64 * 32 = 
 // transposed to VT [QB][m] (row j = reflector j: zero above row j, one at row
 // j; rows nbw..QB-1 zero) and T [QB][QB] (upper triangular).  The panel moves
 // between memory and the wavefronts' registers through LDS in chunks of
-// QCH rows, so that every global access reads or writes whole rows; all
-// loads of the panel are in flight together.  A wavefront keeps its
-// reflector in its registers below the diagonal (where R is zero), and while
-// the wavefronts right of column j apply reflector j, those left of it form
-// their entries v_i . v_j of S = V^T V, which the recursion for T needs.
+// QCH rows, so that every global access reads or writes whole rows.  Eight
+// wavefronts, wavefront w owning columns w and w + 8 (each lane 32 rows of
+// both); a column keeps its reflector in its registers below the diagonal
+// (where R is zero).  Per reflector the owning wavefront writes it to LDS
+// once and every wavefront reads it once into registers, then applies it to
+// its columns right of j or, left of j, forms their entries v_i . v_j of
+// S = V^T V, which the recursion for T needs.
 constexpr int QCH = 512;
 constexpr int QNC = 64 * QRPL / QCH;    // LDS chunks per panel
-__global__ __launch_bounds__(1024) void qr_panel_kernel(double* __restrict__ P, int ld, int m, int nbw,
-                                                        double* __restrict__ VT, double* __restrict__ T) {
+constexpr int QPW = 8;                  // wavefronts of the panel kernel
+
+// Reflector j from the column held in a (LAPACK's convention:
+// beta = -sign(alpha) ||x||, tau = (beta - alpha) / beta,
+// v = x / (alpha - beta) with v_j = 1; tau = 0 when x_(j+1..) = 0); v goes
+// to vs (all 64 QRPL rows), beta and v replace the column from row j on.
+// Rows at and past m hold zeros, and j < QB <= 64: only the rows of a[0]
+// need comparing with j.
+__device__ __forceinline__ void qr_reflector(double (&a)[QRPL], int j, int lane, double* vs, double* tau_s,
+                                             double (*S)[QB + 1]) {
+    const double alpha = lane_value(a[0], j);     // row j < QB lies in a[0] of lane j
+    double sg = lane > j ? a[0] * a[0] : 0.0;
+#pragma unroll
+    for (int i = 1; i < QRPL; ++i) sg += a[i] * a[i];
+    sg = wave_sum(sg);
+    double tau = 0.0, beta = alpha, scale = 0.0;
+    if (sg > 0.0) {
+        const double nrm = sqrt(alpha * alpha + sg);
+        beta = alpha >= 0.0 ? -nrm : nrm;
+        tau = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+    }
+    {
+        const double v = lane == j ? 1.0 : (lane > j ? a[0] * scale : 0.0);
+        vs[lane] = v;
+        a[0] = lane < j ? a[0] : (lane == j ? beta : v);
+    }
+#pragma unroll
+    for (int i = 1; i < QRPL; ++i) {
+        a[i] *= scale;
+        vs[lane + 64 * i] = a[i];
+    }
+    if (lane == 0) {
+        tau_s[j] = tau;
+        S[j][j] = 1.0 + sg * scale * scale;    // v . v
+    }
+}
+
+// Reflector j (v, in registers) on column c held in a: for c > j the
+// update a -= tau v (v . a); for c < j the entry S[c][j] = v_c . v_j.
+__device__ __forceinline__ void qr_column_step(double (&a)[QRPL], const double (&v)[QRPL], int c, int j, int nbw,
+                                               int lane, double tau, double (*S)[QB + 1]) {
+    if (c >= nbw || c == j) return;
+    // column c's values (c > j) or its reflector (c < j: one at row c, zero
+    // above it) against v; rows of a[1..] lie below every row < QB
+    double dot = v[0] * (c > j ? a[0] : (lane == c ? 1.0 : (lane > c ? a[0] : 0.0)));
+#pragma unroll
+    for (int i = 1; i < QRPL; ++i) dot += v[i] * a[i];
+    dot = wave_sum(dot);
+    if (c > j) {
+        const double f = tau * dot;
+#pragma unroll
+        for (int i = 0; i < QRPL; ++i) a[i] -= f * v[i];
+    } else if (lane == 0) {
+        S[c][j] = dot;
+    }
+}
+
+__global__ __launch_bounds__(64 * QPW) void qr_panel_kernel(double* __restrict__ P, int ld, int m, int nbw,
+                                                            double* __restrict__ VT, double* __restrict__ T) {
+    constexpr int NT = 64 * QPW;
     __shared__ double Pc[QCH][QB + 1];
     __shared__ double vs[64 * QRPL];
     __shared__ double tau_s[QB];
     __shared__ double S[QB][QB + 1];
     __shared__ double Ts[QB][QB + 1];
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    const bool own = w < nbw;
+    const int c0 = w, c1 = w + QPW;               // this wavefront's columns
     if (t < QB * (QB + 1)) S[t / (QB + 1)][t % (QB + 1)] = 0.0;
-    double a[QRPL];
+    double a0[QRPL], a1[QRPL];
+    // coalesced load: thread t moves row t of a chunk
 #pragma unroll
-    for (int i = 0; i < QRPL; ++i) a[i] = 0.0;
-    // coalesced load: thread t moves 8 consecutive entries of row t / 2 of
-    // every chunk
-    {
-        const int rr = t >> 1, h = (t & 1) * 8;
-        double ldv[QNC][8];
+    for (int c = 0; c < QNC; ++c) {
+        {
+            const int row = c * QCH + t;
+            double ldv[QB];
 #pragma unroll
-        for (int c = 0; c < QNC; ++c) {
-            const int row = c * QCH + rr;
+            for (int e = 0; e < QB; ++e) ldv[e] = (row < m && e < nbw) ? P[(long)row * ld + e] : 0.0;
 #pragma unroll
-            for (int e = 0; e < 8; ++e)
-                ldv[c][e] = (row < m && h + e < nbw) ? P[(long)row * ld + h + e] : 0.0;
-        }
-#pragma unroll
-        for (int c = 0; c < QNC; ++c) {
-#pragma unroll
-            for (int e = 0; e < 8; ++e) Pc[rr][h + e] = ldv[c][e];
-            __syncthreads();
-#pragma unroll
-            for (int i = 0; i < QRPL; ++i) {
-                const int row = lane + 64 * i;
-                if (row >= c * QCH && row < (c + 1) * QCH) a[i] = Pc[row - c * QCH][w];
-            }
-            __syncthreads();
-        }
-    }
-    for (int j = 0; j < nbw; ++j) {
-        if (w == j) {
-            // reflector of column j over rows j..m-1 (LAPACK's convention:
-            // beta = -sign(alpha) ||x||, tau = (beta - alpha) / beta,
-            // v = x / (alpha - beta) with v_j = 1; tau = 0 when x_(j+1..) = 0)
-            const double alpha = lane_value(a[0], j);     // row j < QB lies in a[0] of lane j
-            double sg = 0.0;
-#pragma unroll
-            for (int i = 0; i < QRPL; ++i) {
-                const int row = lane + 64 * i;
-                if (row > j && row < m) sg += a[i] * a[i];
-            }
-            sg = wave_sum(sg);
-            double tau = 0.0, beta = alpha, scale = 0.0;
-            if (sg > 0.0) {
-                const double nrm = sqrt(alpha * alpha + sg);
-                beta = alpha >= 0.0 ? -nrm : nrm;
-                tau = (beta - alpha) / beta;
-                scale = 1.0 / (alpha - beta);
-            }
-#pragma unroll
-            for (int i = 0; i < QRPL; ++i) {
-                const int row = lane + 64 * i;
-                const double v = row == j ? 1.0 : ((row > j && row < m) ? a[i] * scale : 0.0);
-                vs[row] = v;
-                a[i] = row < j ? a[i] : (row == j ? beta : v);
-            }
-            if (lane == 0) {
-                tau_s[j] = tau;
-                S[j][j] = 1.0 + sg * scale * scale;    // v . v
-            }
+            for (int e = 0; e < QB; ++e) Pc[t][e] = ldv[e];
         }
         __syncthreads();
-        for (int row = t; row < m; row += 1024) VT[(long)j * m + row] = vs[row];
-        if (own && w != j) {
-            // w > j: apply reflector j to column w; w < j: S[w][j] = v_w . v_j
-            double dot = 0.0;
 #pragma unroll
-            for (int i = 0; i < QRPL; ++i) {
-                const int row = lane + 64 * i;
-                const double x = w > j ? a[i] : (row == w ? 1.0 : (row > w ? a[i] : 0.0));
-                dot += vs[row] * x;
-            }
-            dot = wave_sum(dot);
-            if (w > j) {
-                const double f = tau_s[j] * dot;
-                // reload v from LDS below rather than keeping 32 more values live
-                asm volatile("" ::: "memory");
-#pragma unroll
-                for (int i = 0; i < QRPL; ++i) a[i] -= f * vs[lane + 64 * i];
-            } else if (lane == 0) {
-                S[w][j] = dot;
-            }
+        for (int i = 0; i < QRPL; ++i) {
+            if (64 * i < c * QCH || 64 * i >= (c + 1) * QCH) continue;
+            const int r = lane + 64 * i - c * QCH;
+            a0[i] = Pc[r][c0];
+            a1[i] = Pc[r][c1];
         }
+        __syncthreads();
+    }
+    for (int j = 0; j < nbw; ++j) {
+        if (w == (j & (QPW - 1))) {
+            if (j < QPW)
+                qr_reflector(a0, j, lane, vs, tau_s, S);
+            else
+                qr_reflector(a1, j, lane, vs, tau_s, S);
+        }
+        __syncthreads();
+        for (int row = t; row < m; row += NT) VT[(long)j * m + row] = vs[row];
+        double v[QRPL];
+#pragma unroll
+        for (int i = 0; i < QRPL; ++i) v[i] = vs[lane + 64 * i];
+        const double tau = tau_s[j];
+        qr_column_step(a0, v, c0, j, nbw, lane, tau, S);
+        qr_column_step(a1, v, c1, j, nbw, lane, tau, S);
         __syncthreads();
     }
     // coalesced write-back of R and the zeros below it (the reflectors held
     // below the diagonal are not part of R)
-    for (int c0 = 0; c0 < 64 * QRPL; c0 += QCH) {
+#pragma unroll
+    for (int c = 0; c < QNC; ++c) {
 #pragma unroll
         for (int i = 0; i < QRPL; ++i) {
+            if (64 * i < c * QCH || 64 * i >= (c + 1) * QCH) continue;
             const int row = lane + 64 * i;
-            if (row >= c0 && row < c0 + QCH) Pc[row - c0][w] = row > w ? 0.0 : a[i];
+            Pc[row - c * QCH][c0] = row > c0 ? 0.0 : a0[i];
+            Pc[row - c * QCH][c1] = row > c1 ? 0.0 : a1[i];
         }
         __syncthreads();
         {
-            const int rr = t >> 1, h = (t & 1) * 8;
-            const int row = c0 + rr;
+            const int row = c * QCH + t;
 #pragma unroll
-            for (int e = 0; e < 8; ++e)
-                if (row < m && h + e < nbw) P[(long)row * ld + h + e] = Pc[rr][h + e];
+            for (int e = 0; e < QB; ++e)
+                if (row < m && e < nbw) P[(long)row * ld + e] = Pc[t][e];
         }
         __syncthreads();
     }
     // reflector rows nbw..QB-1 are zero
-    for (int e = t; e < (QB - nbw) * m; e += 1024) VT[(long)nbw * m + e] = 0.0;
+    for (int e = t; e < (QB - nbw) * m; e += NT) VT[(long)nbw * m + e] = 0.0;
     if (t < QB && t >= nbw) tau_s[t] = 0.0;
     __syncthreads();
     // T: T_jj = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] S[0:j, j]; column j by
@@ -295,7 +313,7 @@ void householder_rows(double* Z, int p, int q, int ld, double* ws, hipStream_t s
         const int nbw = std::min(QB, kmax - c0);
         const int m = p - c0;
         double* P = Z + (long)c0 * ld + c0;
-        hipLaunchKernelGGL(qr_panel_kernel, dim3(1), dim3(1024), 0, s, P, ld, m, nbw, VT, T);
+        hipLaunchKernelGGL(qr_panel_kernel, dim3(1), dim3(64 * QPW), 0, s, P, ld, m, nbw, VT, T);
         const int nt = ld - (c0 + nbw);
         if (nt <= 0) continue;
         constexpr int CW = 16 * QNCT;
