@@ -26,6 +26,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 namespace ite {
 namespace {
@@ -221,39 +222,60 @@ __device__ inline int ring_row(int pos, int k) {
 // diagonalising angles the one that leaves the larger row at the lower local
 // index (a_low: a has the lower index) is taken, by swapping (c, s) to
 // (-s, c) when needed.  Returns whether the pair rotates.
-__device__ inline bool jacobi_angle(double gaa, double gbb, double gab, bool a_low, double& c, double& s) {
-    c = 1.0;
-    s = 0.0;
-    if (gab == 0.0) return false;
-    const double x = gbb - gaa, yy = 2.0 * gab;
+template <typename T>
+__device__ inline bool jacobi_angle(T gaa, T gbb, T gab, bool a_low, T& c, T& s) {
+    c = T(1);
+    s = T(0);
+    if (gab == T(0)) return false;
+    const T x = gbb - gaa, yy = T(2) * gab;
     int e;
     (void)frexp(fmax(fabs(x), fabs(yy)), &e);
-    const double xs = ldexp(x, -e), ys = ldexp(yy, -e);
-    const double r = sqrt(xs * xs + ys * ys);
-    const double d = fabs(xs) + r;
-    const double iw = rsqrt(2.0 * r * d);
+    const T xs = ldexp(x, -e), ys = ldexp(yy, -e);
+    const T r = sqrt(xs * xs + ys * ys);
+    const T d = fabs(xs) + r;
+    T iw;
+    if constexpr (std::is_same<T, float>::value)
+        iw = rsqrtf(T(2) * r * d);
+    else
+        iw = rsqrt(T(2) * r * d);
     c = d * iw;
-    s = (x >= 0.0 ? ys : -ys) * iw;
-    if (a_low == (x >= 0.0)) {
-        const double c0 = c;
+    s = (x >= T(0) ? ys : -ys) * iw;
+    if (a_low == (x >= T(0))) {
+        const T c0 = c;
         c = -s;
         s = c0;
     }
     return true;
 }
 
+// (cos, sin) as stored for a round: the accumulated rotation is FP64, so an
+// angle formed in single precision is normalised to cos^2 + sin^2 = 1 in
+// double (with e = c^2 + s^2 - 1 ~ 1e-7, the factor 1 - e/2 + 3e^2/8 is
+// 1/sqrt(1 + e) to O(e^3)): the rotation is then orthogonal to FP64
+// rounding, only its angle carries the single-precision error.
+template <typename T> __device__ inline double2 stored_angle(T c, T s) {
+    if constexpr (std::is_same<T, double>::value) {
+        return make_double2(c, s);
+    } else {
+        const double cd = c, sd = s;
+        const double e = fma(cd, cd, sd * sd) - 1.0;
+        const double f = 1.0 + e * (-0.5 + 0.375 * e);
+        return make_double2(cd * f, sd * f);
+    }
+}
+
 // Entry (x, y) of G' = J G J^T for positions x, y of the current round, J the
 // round's rotations ((cos, sin) by pair index): the same expressions as the
 // 2 x 2 block updates of inner_kernel.
-template <int RB>
-__device__ inline double rotated_entry(const double (*G)[2 * RB + 1], const double2* cs, int x, int y) {
+template <int RB, typename T>
+__device__ inline T rotated_entry(const T (*G)[2 * RB + 1], const double2* cs, int x, int y) {
     const bool rx = x >= RB, ry = y >= RB;
     const int i = rx ? x - RB : x, j = ry ? y - RB : y;
     const double2 pi = cs[i], pj = cs[j];
-    const double ci = pi.x, si = pi.y, cj = pj.x, sj = pj.y;
-    const double g00 = G[i][j], g01 = G[i][j + RB], g10 = G[i + RB][j], g11 = G[i + RB][j + RB];
-    const double t0 = rx ? si * g00 + ci * g10 : ci * g00 - si * g10;
-    const double t1 = rx ? si * g01 + ci * g11 : ci * g01 - si * g11;
+    const T ci = pi.x, si = pi.y, cj = pj.x, sj = pj.y;
+    const T g00 = G[i][j], g01 = G[i][j + RB], g10 = G[i + RB][j], g11 = G[i + RB][j + RB];
+    const T t0 = rx ? si * g00 + ci * g10 : ci * g00 - si * g10;
+    const T t1 = rx ? si * g01 + ci * g11 : ci * g01 - si * g11;
     return ry ? t0 * sj + t1 * cj : t0 * cj - t1 * sj;
 }
 
@@ -364,7 +386,7 @@ template <int RB> constexpr int q_buffer() { return ((2 * RB - 1) & 1) ^ 1; }
 // round k it forms the three entries of G' each pair of round k + 1 needs and
 // that pair's angle, while the update of round k runs, so a round costs one
 // barrier.
-template <int RB>
+template <int RB, typename GT = double>
 __device__ __forceinline__ int pair_sweep(PairLDS<RB>& sh, double tol, double kappa, double sigma1sq, double* sweep_off,
                           double& off_out) {
     constexpr int PR = Blk<RB>::PR, NT = Blk<RB>::NT, XS = Blk<RB>::XS, EPT = PR / XS;
@@ -433,13 +455,28 @@ __device__ __forceinline__ int pair_sweep(PairLDS<RB>& sh, double tol, double ka
         atomic_max_pos(sweep_off + 1, gmax_local);
     }
     if (off <= tol) return 0;
+    // the sweep's copies of G, in GT: for single precision they take the
+    // space of Gb[0] (two float matrices), converted after the measure above
+    GT(&Gw)[2][PR][PR + 1] = *reinterpret_cast<GT(*)[2][PR][PR + 1]>(&Gb[0][0][0]);
+    static_assert(sizeof(GT) == sizeof(double) || 2 * sizeof(GT) * PR * (PR + 1) <= sizeof(Gb[0]), "G fits");
+    if constexpr (!std::is_same<GT, double>::value) {
+        double gv[EPT];
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) gv[u] = upd ? Gb[0][xh + XS * u][y] : 0.0;
+        __syncthreads();
+        if (upd) {
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) Gw[0][xh + XS * u][y] = GT(gv[u]);
+        }
+        __syncthreads();
+    }
     // angles of round 0
     if (!upd && al < RB) {
-        double c, s;
-        if (jacobi_angle(Gb[0][al][al], Gb[0][al + RB][al + RB], Gb[0][al][al + RB],
-                         ring_row<PR>(al, 0) < ring_row<PR>(al + RB, 0), c, s))
+        GT c, s;
+        if (jacobi_angle<GT>(Gw[0][al][al], Gw[0][al + RB][al + RB], Gw[0][al][al + RB],
+                             ring_row<PR>(al, 0) < ring_row<PR>(al + RB, 0), c, s))
             anyrot = 1;
-        cs[0][al] = make_double2(c, s);
+        cs[0][al] = stored_angle(c, s);
     }
     __syncthreads();
     // fixed per update thread: the column pair j of its 2 x 2 blocks, the
@@ -467,17 +504,17 @@ __device__ __forceinline__ int pair_sweep(PairLDS<RB>& sh, double tol, double ka
         const int pb = k & 1, nxt = cur ^ 1;
         if (upd) {
             const double2 pj = cs[pb][jq];
-            const double cj = pj.x, sj = pj.y;
-            double nv[QPT][4];
+            const GT cj = pj.x, sj = pj.y;
+            GT nv[QPT][4];
 #pragma unroll
             for (int u = 0; u < QPT; ++u) {
                 const int i = t / RB + IS * u;
                 const double2 pi = cs[pb][i];
-                const double ci = pi.x, si = pi.y;
-                const double g00 = Gb[cur][i][jq], g01 = Gb[cur][i][jq + RB];
-                const double g10 = Gb[cur][i + RB][jq], g11 = Gb[cur][i + RB][jq + RB];
-                const double t00 = ci * g00 - si * g10, t01 = ci * g01 - si * g11;
-                const double t10 = si * g00 + ci * g10, t11 = si * g01 + ci * g11;
+                const GT ci = pi.x, si = pi.y;
+                const GT g00 = Gw[cur][i][jq], g01 = Gw[cur][i][jq + RB];
+                const GT g10 = Gw[cur][i + RB][jq], g11 = Gw[cur][i + RB][jq + RB];
+                const GT t00 = ci * g00 - si * g10, t01 = ci * g01 - si * g11;
+                const GT t10 = si * g00 + ci * g10, t11 = si * g01 + ci * g11;
                 nv[u][0] = t00 * cj - t01 * sj;
                 nv[u][1] = t00 * sj + t01 * cj;
                 nv[u][2] = t10 * cj - t11 * sj;
@@ -497,10 +534,10 @@ __device__ __forceinline__ int pair_sweep(PairLDS<RB>& sh, double tol, double ka
 #pragma unroll
             for (int u = 0; u < QPT; ++u) {
                 const int pi0 = pq0[u], pi1 = pq1[u];
-                Gb[nxt][pi0][pj0] = nv[u][0];
-                Gb[nxt][pi0][pj1] = nv[u][1];
-                Gb[nxt][pi1][pj0] = nv[u][2];
-                Gb[nxt][pi1][pj1] = nv[u][3];
+                Gw[nxt][pi0][pj0] = nv[u][0];
+                Gw[nxt][pi0][pj1] = nv[u][1];
+                Gw[nxt][pi1][pj0] = nv[u][2];
+                Gw[nxt][pi1][pj1] = nv[u][3];
             }
 #pragma unroll
             for (int u = 0; u < JC; ++u) {
@@ -511,13 +548,13 @@ __device__ __forceinline__ int pair_sweep(PairLDS<RB>& sh, double tol, double ka
             // pair al of round k + 1 sits at positions (al, al + RB) then,
             // i.e. at (a, b) now
             const int a = ring_prev<PR>(al), b = ring_prev<PR>(al + RB);
-            const double gaa = rotated_entry<RB>(Gb[cur], cs[pb], a, a);
-            const double gbb = rotated_entry<RB>(Gb[cur], cs[pb], b, b);
-            const double gab = rotated_entry<RB>(Gb[cur], cs[pb], a, b);
-            double c, s;
-            if (jacobi_angle(gaa, gbb, gab, ring_row<PR>(al, k + 1) < ring_row<PR>(al + RB, k + 1), c, s))
+            const GT gaa = rotated_entry<RB, GT>(Gw[cur], cs[pb], a, a);
+            const GT gbb = rotated_entry<RB, GT>(Gw[cur], cs[pb], b, b);
+            const GT gab = rotated_entry<RB, GT>(Gw[cur], cs[pb], a, b);
+            GT c, s;
+            if (jacobi_angle<GT>(gaa, gbb, gab, ring_row<PR>(al, k + 1) < ring_row<PR>(al + RB, k + 1), c, s))
                 anyrot = 1;
-            cs[pb ^ 1][al] = make_double2(c, s);
+            cs[pb ^ 1][al] = stored_angle(c, s);
         }
         __syncthreads();
         cur = nxt;
@@ -580,7 +617,7 @@ __device__ __forceinline__ int pair_sweep(PairLDS<RB>& sh, double tol, double ka
 // UW columns each: that work is off the critical path of the sweep and
 // fills the compute units the pairs leave idle.  work[1] counts the pairs
 // swept, work[3] the identity-part columns rotated here.
-template <int RB>
+template <int RB, typename GT>
 __global__ __launch_bounds__(Blk<RB>::NTI) void inner_kernel(const double* __restrict__ gram, int nchunks, int p,
                                                              int r, int nb, double tol, double kappa,
                                                              double sigma1sq, double* __restrict__ rot,
@@ -647,7 +684,7 @@ __global__ __launch_bounds__(Blk<RB>::NTI) void inner_kernel(const double* __res
         }
     }
     double off;
-    const int res = pair_sweep<RB>(sh, tol, kappa, sigma1sq, sweep_off, off);
+    const int res = pair_sweep<RB, GT>(sh, tol, kappa, sigma1sq, sweep_off, off);
     if (res != 0 && t == 0) atomicAdd(work + 1, 1ull);
     // Q of every pair is written (the identity when the rows are already
     // orthogonal), so that the fused rotation reads it unconditionally
@@ -1098,6 +1135,11 @@ JacobiResult run_jacobi(double* Z, int p, int q, int ld, double tol, int max_swe
     int rprev = -1;
     for (int sw = 0; sw < max_sweeps; ++sw) {
         fill(off_ws, 0.0, 2, s);
+        // far from convergence the pair sweeps rotate a single-precision copy
+        // of the Gram (the measure and the accumulated rotation stay FP64):
+        // their angles only need to be roughly right while the measure is
+        // large, and the sweeps that reach the tolerance run in FP64
+        const bool lowg = prev > 1e-3;
         for (int r = 0; r < nb - 1; ++r, ++g) {
             const int cur = (int)(g & 1);
             double* rcur = rot_ws + (long)cur * npairs * PR * PR;
@@ -1113,9 +1155,14 @@ JacobiResult run_jacobi(double* Z, int p, int q, int ld, double tol, int max_swe
             }
             timed = probe && probe->begin(PK_INNER, s);
             const int ublocks = (rprev >= 0 && nu > 0) ? npairs * nuch : 0;
-            hipLaunchKernelGGL((inner_kernel<RB>), dim3(npairs + ublocks), dim3(Blk<RB>::NTI), 0, s, gram_ws,
-                               nchunks, p, r, nb, tol, kappa, sigma1sq, rcur, fcur, off_ws, work, Z, ld, q, npairs,
-                               rprev, rold, fold, nuch);
+            if (lowg)
+                hipLaunchKernelGGL((inner_kernel<RB, float>), dim3(npairs + ublocks), dim3(Blk<RB>::NTI), 0, s,
+                                   gram_ws, nchunks, p, r, nb, tol, kappa, sigma1sq, rcur, fcur, off_ws, work, Z, ld,
+                                   q, npairs, rprev, rold, fold, nuch);
+            else
+                hipLaunchKernelGGL((inner_kernel<RB, double>), dim3(npairs + ublocks), dim3(Blk<RB>::NTI), 0, s,
+                                   gram_ws, nchunks, p, r, nb, tol, kappa, sigma1sq, rcur, fcur, off_ws, work, Z, ld,
+                                   q, npairs, rprev, rold, fold, nuch);
             if (timed) probe->end(PK_INNER, s);
             timed = probe && probe->begin(PK_ROTATE, s);
             if constexpr (fused) {
