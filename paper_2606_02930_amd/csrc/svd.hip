@@ -459,6 +459,9 @@ __device__ __forceinline__ int pair_sweep(PairLDS<RB>& sh, double tol, double ka
     // space of Gb[0] (two float matrices), converted after the measure above
     GT(&Gw)[2][PR][PR + 1] = *reinterpret_cast<GT(*)[2][PR][PR + 1]>(&Gb[0][0][0]);
     static_assert(sizeof(GT) == sizeof(double) || 2 * sizeof(GT) * PR * (PR + 1) <= sizeof(Gb[0]), "G fits");
+    // likewise the accumulated rotation: in GT, over Ab[0] for single
+    // precision (started at the identity here)
+    GT(&Aw)[2][PR][PR + 2] = *reinterpret_cast<GT(*)[2][PR][PR + 2]>(&Ab[0][0][0]);
     if constexpr (!std::is_same<GT, double>::value) {
         double gv[EPT];
 #pragma unroll
@@ -466,7 +469,11 @@ __device__ __forceinline__ int pair_sweep(PairLDS<RB>& sh, double tol, double ka
         __syncthreads();
         if (upd) {
 #pragma unroll
-            for (int u = 0; u < EPT; ++u) Gw[0][xh + XS * u][y] = GT(gv[u]);
+            for (int u = 0; u < EPT; ++u) {
+                const int x = xh + XS * u;
+                Gw[0][x][y] = GT(gv[u]);
+                Aw[0][x][y] = x == y ? GT(1) : GT(0);
+            }
         }
         __syncthreads();
     }
@@ -520,16 +527,19 @@ __device__ __forceinline__ int pair_sweep(PairLDS<RB>& sh, double tol, double ka
                 nv[u][2] = t10 * cj - t11 * sj;
                 nv[u][3] = t10 * sj + t11 * cj;
             }
-            double2 na[JC][2];
+            using GT2 = typename std::conditional<std::is_same<GT, double>::value, double2, float2>::type;
+            GT2 na[JC][2];
 #pragma unroll
             for (int u = 0; u < JC; ++u) {
                 const int i = t / (PR / 2) + JCS * u;
                 const double2 pi = cs[pb][i];
-                const double ci = pi.x, si = pi.y;
-                const double2 a0 = *reinterpret_cast<const double2*>(&Ab[cur][i][ca]);
-                const double2 a1 = *reinterpret_cast<const double2*>(&Ab[cur][i + RB][ca]);
-                na[u][0] = make_double2(ci * a0.x - si * a1.x, ci * a0.y - si * a1.y);
-                na[u][1] = make_double2(si * a0.x + ci * a1.x, si * a0.y + ci * a1.y);
+                const GT ci = pi.x, si = pi.y;
+                const GT2 a0 = *reinterpret_cast<const GT2*>(&Aw[cur][i][ca]);
+                const GT2 a1 = *reinterpret_cast<const GT2*>(&Aw[cur][i + RB][ca]);
+                na[u][0].x = ci * a0.x - si * a1.x;
+                na[u][0].y = ci * a0.y - si * a1.y;
+                na[u][1].x = si * a0.x + ci * a1.x;
+                na[u][1].y = si * a0.y + ci * a1.y;
             }
 #pragma unroll
             for (int u = 0; u < QPT; ++u) {
@@ -541,8 +551,8 @@ __device__ __forceinline__ int pair_sweep(PairLDS<RB>& sh, double tol, double ka
             }
 #pragma unroll
             for (int u = 0; u < JC; ++u) {
-                *reinterpret_cast<double2*>(&Ab[nxt][pa0[u]][ca]) = na[u][0];
-                *reinterpret_cast<double2*>(&Ab[nxt][pa1[u]][ca]) = na[u][1];
+                *reinterpret_cast<GT2*>(&Aw[nxt][pa0[u]][ca]) = na[u][0];
+                *reinterpret_cast<GT2*>(&Aw[nxt][pa1[u]][ca]) = na[u][1];
             }
         } else if (al < RB && k + 1 < PR - 1) {
             // pair al of round k + 1 sits at positions (al, al + RB) then,
@@ -559,52 +569,75 @@ __device__ __forceinline__ int pair_sweep(PairLDS<RB>& sh, double tol, double ka
         __syncthreads();
         cur = nxt;
     }
-    // Every row is back at its starting position.  One Newton-Schulz step
+    // Every row is back at its starting position.  Newton-Schulz steps
     // towards the nearest orthogonal matrix, A <- (3 I - A A^T) A / 2, with
     // FP64 MFMA: the product of Givens rotations is orthogonal only to a few
-    // hundred ulps, and every row meets such a rotation in each round of every
-    // sweep, so the defect would otherwise accumulate.
-    double (*A)[PR + 2] = Ab[cur];
-    double (*S)[PR + 1] = Gb[cur];
-    double (*T)[PR + 1] = Gb[cur ^ 1];
+    // hundred ulps (a few million for the single-precision accumulation),
+    // and every row meets such a rotation in each round of every sweep, so
+    // the defect would otherwise accumulate.  The step squares the defect:
+    // one suffices from FP64, two from FP32 (held in double in Ab[cur]).
     const int lane = t & 63, w = t >> 6;
     const int l16 = lane & 15, kg = lane >> 4;
     constexpr int TPW = NTL * NTL / NW;
-    // S = A A^T
-    if (upd) {
+    double (*S)[PR + 1] = Gb[cur];
+    // out = 1.5 A - 0.5 (A A^T) A: transposed into Gb[cur ^ 1] (the final Q)
+    // or, for a first step, into Ab[cur ^ 1]
+    auto ns_step = [&](double (*A)[PR + 2], bool last) {
+        if (upd) {
 #pragma unroll
-        for (int i = 0; i < TPW; ++i) {
-            const int tile = w + NW * i;
-            const int tm = tile / NTL, tn = tile % NTL;
-            d4_t acc = {0, 0, 0, 0};
+            for (int i = 0; i < TPW; ++i) {
+                const int tile = w + NW * i;
+                const int tm = tile / NTL, tn = tile % NTL;
+                d4_t acc = {0, 0, 0, 0};
 #pragma unroll
-            for (int k0 = 0; k0 < PR; k0 += 4)
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[tm * 16 + l16][k0 + kg], A[tn * 16 + l16][k0 + kg],
-                                                           acc, 0, 0, 0);
+                for (int k0 = 0; k0 < PR; k0 += 4)
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[tm * 16 + l16][k0 + kg], A[tn * 16 + l16][k0 + kg],
+                                                               acc, 0, 0, 0);
 #pragma unroll
-            for (int rr = 0; rr < 4; ++rr) S[tm * 16 + 4 * rr + kg][tn * 16 + l16] = acc[rr];
-        }
-    }
-    __syncthreads();
-    // A_new = 1.5 A - 0.5 S A, stored transposed: T[k][m] = A_new[m][k] = Q[k][m]
-    if (upd) {
-#pragma unroll
-        for (int i = 0; i < TPW; ++i) {
-            const int tile = w + NW * i;
-            const int tm = tile / NTL, tn = tile % NTL;
-            d4_t acc = {0, 0, 0, 0};
-#pragma unroll
-            for (int k0 = 0; k0 < PR; k0 += 4)
-                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(S[tm * 16 + l16][k0 + kg], A[k0 + kg][tn * 16 + l16],
-                                                           acc, 0, 0, 0);
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
-                const int m = tm * 16 + 4 * rr + kg, kk = tn * 16 + l16;
-                T[kk][m] = 1.5 * A[m][kk] - 0.5 * acc[rr];
+                for (int rr = 0; rr < 4; ++rr) S[tm * 16 + 4 * rr + kg][tn * 16 + l16] = acc[rr];
             }
         }
+        __syncthreads();
+        if (upd) {
+#pragma unroll
+            for (int i = 0; i < TPW; ++i) {
+                const int tile = w + NW * i;
+                const int tm = tile / NTL, tn = tile % NTL;
+                d4_t acc = {0, 0, 0, 0};
+#pragma unroll
+                for (int k0 = 0; k0 < PR; k0 += 4)
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(S[tm * 16 + l16][k0 + kg], A[k0 + kg][tn * 16 + l16],
+                                                               acc, 0, 0, 0);
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) {
+                    const int m = tm * 16 + 4 * rr + kg, kk = tn * 16 + l16;
+                    const double v = 1.5 * A[m][kk] - 0.5 * acc[rr];
+                    if (last)
+                        Gb[cur ^ 1][kk][m] = v;
+                    else
+                        Ab[cur ^ 1][m][kk] = v;
+                }
+            }
+        }
+        __syncthreads();
+    };
+    if constexpr (std::is_same<GT, double>::value) {
+        ns_step(Ab[cur], true);
+    } else {
+        // the FP32 rotation (over Ab[0]) to double in Ab[cur]: cur is odd
+        // after the PR - 1 rounds, so Ab[cur] does not overlap it
+        static_assert(((PR - 1) & 1) == 1, "odd number of rounds");
+        if (upd) {
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) {
+                const int x = xh + XS * u;
+                Ab[cur][x][y] = double(Aw[cur][x][y]);
+            }
+        }
+        __syncthreads();
+        ns_step(Ab[cur], false);
+        ns_step(Ab[cur ^ 1], true);
     }
-    __syncthreads();
     return anyrot ? 2 : 1;
 }
 
