@@ -207,6 +207,35 @@ def test_svd_split_matches_numpy(env, direction, shape):
     assert diag["orth"] < 5e-13, diag
 
 
+@pytest.mark.parametrize("shape", [(256, 2, 2, 256), (1024, 2, 2, 1024)])
+def test_svd_split_wide_dynamic_range(env, shape):
+    # singular values from 1 down to 1e-30: the pair Grams span 60 decades,
+    # beyond single precision, which the first Jacobi sweeps use for their
+    # rotation angles; the result must still be FP64-accurate (2048 x 2048:
+    # the full-size bond split of the benchmark)
+    torch, ctx = env
+    Dl, d1, d2, Dr = shape
+    m, n = Dl * d1, d2 * Dr
+    rng = np.random.default_rng(m + 5)
+    r = min(m, n)
+    U, _ = np.linalg.qr(rng.standard_normal((m, r)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, r)))
+    s_true = np.logspace(0, -30, r)
+    theta = ((U * s_true) @ V.T).reshape(Dl, d1, d2, Dr)
+    chi = r
+    A1o, A2o, info = omps.split_two_site(theta, "lr", 1e-14, chi, 1e-13)
+    A1 = torch.zeros((Dl, d1, r), dtype=torch.float64, device="cuda")
+    A2 = torch.zeros((r, d2, Dr), dtype=torch.float64, device="cuda")
+    k, sig, disc = ite.ite_debug_svd_split(ctx, 0, dev(torch, theta), chi, 1e-14, 1e-13, A1, A2)
+    a1 = host(A1).reshape(-1)[: Dl * d1 * k].reshape(Dl, d1, k)
+    a2 = host(A2).reshape(-1)[: k * d2 * Dr].reshape(k, d2, Dr)
+    diag = dict(k=k, k_o=info["k"], sig_err=float(np.abs(sig - info["sigma"]).max()))
+    assert k == info["k"], diag
+    assert np.allclose(sig, info["sigma"], rtol=0, atol=1e-13), diag
+    assert rel_err(omps.two_site(a1, a2), omps.two_site(A1o, A2o)) < 1e-12, diag
+    assert omps.left_orthonormality_error(a1) < 5e-13, diag
+
+
 @pytest.mark.parametrize("direction", [0, 1])
 @pytest.mark.parametrize("D", [4, 128])
 def test_svd_split_keeps_complete_basis_with_zeros(env, direction, D):
