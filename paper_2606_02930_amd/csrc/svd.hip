@@ -248,30 +248,25 @@ __device__ inline bool jacobi_angle(T gaa, T gbb, T gab, bool a_low, T& c, T& s)
     return true;
 }
 
-// (cos, sin) as stored for a round: the accumulated rotation is FP64, so an
-// angle formed in single precision is normalised to cos^2 + sin^2 = 1 in
-// double (with e = c^2 + s^2 - 1 ~ 1e-7, the factor 1 - e/2 + 3e^2/8 is
-// 1/sqrt(1 + e) to O(e^3)): the rotation is then orthogonal to FP64
-// rounding, only its angle carries the single-precision error.
-template <typename T> __device__ inline double2 stored_angle(T c, T s) {
-    if constexpr (std::is_same<T, double>::value) {
-        return make_double2(c, s);
-    } else {
-        const double cd = c, sd = s;
-        const double e = fma(cd, cd, sd * sd) - 1.0;
-        const double f = 1.0 + e * (-0.5 + 0.375 * e);
-        return make_double2(cd * f, sd * f);
-    }
-}
+// (cos, sin) of a round's rotations in the sweep's precision.
+template <typename T> struct CosSin;
+template <> struct CosSin<double> {
+    typedef double2 type;
+    static __device__ type make(double c, double s) { return make_double2(c, s); }
+};
+template <> struct CosSin<float> {
+    typedef float2 type;
+    static __device__ type make(float c, float s) { return make_float2(c, s); }
+};
 
 // Entry (x, y) of G' = J G J^T for positions x, y of the current round, J the
 // round's rotations ((cos, sin) by pair index): the same expressions as the
 // 2 x 2 block updates of inner_kernel.
 template <int RB, typename T>
-__device__ inline T rotated_entry(const T (*G)[2 * RB + 1], const double2* cs, int x, int y) {
+__device__ inline T rotated_entry(const T (*G)[2 * RB + 1], const typename CosSin<T>::type* cs, int x, int y) {
     const bool rx = x >= RB, ry = y >= RB;
     const int i = rx ? x - RB : x, j = ry ? y - RB : y;
-    const double2 pi = cs[i], pj = cs[j];
+    const auto pi = cs[i], pj = cs[j];
     const T ci = pi.x, si = pi.y, cj = pj.x, sj = pj.y;
     const T g00 = G[i][j], g01 = G[i][j + RB], g10 = G[i + RB][j], g11 = G[i + RB][j + RB];
     const T t0 = rx ? si * g00 + ci * g10 : ci * g00 - si * g10;
@@ -396,7 +391,9 @@ __device__ __forceinline__ int pair_sweep(PairLDS<RB>& sh, double tol, double ka
     static_assert((NTL * NTL) % NW == 0, "tiles per wavefront");
     auto& Gb = sh.Gb;
     auto& Ab = sh.Ab;
-    auto& cs = sh.cs;
+    // angles in the sweep's precision, over sh.cs
+    typedef typename CosSin<GT>::type CS2;
+    CS2(&cs)[2][RB] = *reinterpret_cast<CS2(*)[2][RB]>(&sh.cs[0][0]);
     auto& red = sh.red;
     auto& gred = sh.gred;
     int& anyrot = sh.anyrot;
@@ -483,7 +480,7 @@ __device__ __forceinline__ int pair_sweep(PairLDS<RB>& sh, double tol, double ka
         if (jacobi_angle<GT>(Gw[0][al][al], Gw[0][al + RB][al + RB], Gw[0][al][al + RB],
                              ring_row<PR>(al, 0) < ring_row<PR>(al + RB, 0), c, s))
             anyrot = 1;
-        cs[0][al] = stored_angle(c, s);
+        cs[0][al] = CosSin<GT>::make(c, s);
     }
     __syncthreads();
     // fixed per update thread: the column pair j of its 2 x 2 blocks, the
@@ -510,13 +507,13 @@ __device__ __forceinline__ int pair_sweep(PairLDS<RB>& sh, double tol, double ka
     for (int k = 0; k < PR - 1; ++k) {
         const int pb = k & 1, nxt = cur ^ 1;
         if (upd) {
-            const double2 pj = cs[pb][jq];
+            const CS2 pj = cs[pb][jq];
             const GT cj = pj.x, sj = pj.y;
             GT nv[QPT][4];
 #pragma unroll
             for (int u = 0; u < QPT; ++u) {
                 const int i = t / RB + IS * u;
-                const double2 pi = cs[pb][i];
+                const CS2 pi = cs[pb][i];
                 const GT ci = pi.x, si = pi.y;
                 const GT g00 = Gw[cur][i][jq], g01 = Gw[cur][i][jq + RB];
                 const GT g10 = Gw[cur][i + RB][jq], g11 = Gw[cur][i + RB][jq + RB];
@@ -532,7 +529,7 @@ __device__ __forceinline__ int pair_sweep(PairLDS<RB>& sh, double tol, double ka
 #pragma unroll
             for (int u = 0; u < JC; ++u) {
                 const int i = t / (PR / 2) + JCS * u;
-                const double2 pi = cs[pb][i];
+                const CS2 pi = cs[pb][i];
                 const GT ci = pi.x, si = pi.y;
                 const GT2 a0 = *reinterpret_cast<const GT2*>(&Aw[cur][i][ca]);
                 const GT2 a1 = *reinterpret_cast<const GT2*>(&Aw[cur][i + RB][ca]);
@@ -564,7 +561,7 @@ __device__ __forceinline__ int pair_sweep(PairLDS<RB>& sh, double tol, double ka
             GT c, s;
             if (jacobi_angle<GT>(gaa, gbb, gab, ring_row<PR>(al, k + 1) < ring_row<PR>(al + RB, k + 1), c, s))
                 anyrot = 1;
-            cs[pb ^ 1][al] = stored_angle(c, s);
+            cs[pb ^ 1][al] = CosSin<GT>::make(c, s);
         }
         __syncthreads();
         cur = nxt;
@@ -572,10 +569,11 @@ __device__ __forceinline__ int pair_sweep(PairLDS<RB>& sh, double tol, double ka
     // Every row is back at its starting position.  Newton-Schulz steps
     // towards the nearest orthogonal matrix, A <- (3 I - A A^T) A / 2, with
     // FP64 MFMA: the product of Givens rotations is orthogonal only to a few
-    // hundred ulps (a few million for the single-precision accumulation),
-    // and every row meets such a rotation in each round of every sweep, so
-    // the defect would otherwise accumulate.  The step squares the defect:
-    // one suffices from FP64, two from FP32 (held in double in Ab[cur]).
+    // hundred ulps (to about 1e-5 for the single-precision sweep, whose
+    // rotations are FP32 pairs (cos, sin) applied in FP32), and every row
+    // meets such a rotation in each round of every sweep, so the defect
+    // would otherwise accumulate.  The step squares the defect: one suffices
+    // from FP64, two from FP32 (held in double in Ab[cur]).
     const int lane = t & 63, w = t >> 6;
     const int l16 = lane & 15, kg = lane >> 4;
     constexpr int TPW = NTL * NTL / NW;
