@@ -51,7 +51,8 @@ DTYPE = {"fp64": "f64", "fp32": "f64+f32", "bf16": "f64+bf16"}
 # kernel kinds of the context's launch profile
 KERNELS = {0: ("gemm_kernel<double> (FP64 MFMA contraction)", "mfma"),
            1: ("gram_kernel (Jacobi pair Gram of a split's first round, FP64 MFMA)", "hbm"),
-           2: ("inner_kernel (Jacobi inner sweep, FP64 vector, LDS)", "alu"),
+           2: ("inner_kernel (Jacobi inner sweep, LDS; FP32 vector arithmetic in the sweeps far from "
+               "convergence, FP64 in the last ones, priced at the FP32 vector peak)", "alu"),
            3: ("rotate_gram_kernel (Jacobi row rotation fused with the next round's pair Gram, FP64 MFMA; "
                "rotate_kernel for 16-row blocks and the last identity-part rotation)", "mfma")}
 
@@ -204,7 +205,8 @@ def kernel_profile(ite, ctx, precision):
         if bound == "hbm":
             row.update(achieved=p["bytes"] / total_s / 1e9, peak=HBM_PEAK, unit="GB/s")
         else:
-            row.update(achieved=p["flops"] / total_s / 1e12, peak=FP64_PEAK, unit="TFLOP/s")
+            peak = FP32_PEAK if kind == 2 else FP64_PEAK
+            row.update(achieved=p["flops"] / total_s / 1e12, peak=peak, unit="TFLOP/s")
         row["frac"] = row["achieved"] / row["peak"]
         row["traffic"] = measured_traffic(name.split(" ")[0])
         table[kind] = row

@@ -147,6 +147,9 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     if not os.path.exists(path):
         raise RuntimeError(f"HIP library not built: {path} is missing "
                            "(run python -m paper_2606_02930_amd.build)")
+    # torch first: its HIP runtime is then the one the library binds to, so
+    # that a process holds one runtime whichever of the two is used first
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     for name, (res, args) in _SIGNATURES.items():
         fn = getattr(lib, name)
