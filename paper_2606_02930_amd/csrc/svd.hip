@@ -14,13 +14,20 @@
 // For each pair of blocks (PR = 2 RB rows):
 //   1. gram:   G = X_pair X_pair^T, summed over column chunks with FP64 MFMA;
 //   2. inner:  one cyclic sweep of two-sided Jacobi rotations on the PR x PR
-//              matrix in LDS; Q accumulates the rotations;
+//              matrix in LDS (in FP32 while the previous sweep's measure is
+//              above 1e-3, the measure itself always FP64); Q accumulates
+//              the rotations and is made orthogonal to FP64 rounding by
+//              Newton-Schulz steps;
 //   3. rotate: Z_pair <- Q^T Z_pair over all ld columns (FP64 MFMA).
-// Pairs whose rows are already orthogonal to the working tolerance produce no
-// rotation and skip step 3.  A sweep ends with one host read of the largest
-// off-diagonal measure seen in it.  Larger blocks halve the number of rounds
-// per sweep, and with it the traffic over the whole work matrix, at the price
-// of a longer inner sweep.
+// For 32-row blocks step 3 of a round and step 1 of the next are one launch
+// (the data columns alternate between Z and a second buffer), and the
+// identity part of step 3 runs inside the next round's inner launch.  Pairs
+// whose rows are already orthogonal to the working tolerance produce no
+// rotation.  A sweep ends with one host read of the largest off-diagonal
+// measure seen in it; in the quadratic phase one product X X^T checks all row
+// pairs at once instead of a sweep that would only confirm convergence.
+// Larger blocks halve the number of rounds per sweep, and with it the traffic
+// over the whole work matrix, at the price of a longer inner sweep.
 #include "internal.h"
 #include "wave.h"
 
