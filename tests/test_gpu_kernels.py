@@ -207,12 +207,14 @@ def test_svd_split_matches_numpy(env, direction, shape):
     assert diag["orth"] < 5e-13, diag
 
 
-@pytest.mark.parametrize("shape", [(256, 2, 2, 256), (1024, 2, 2, 1024)])
+@pytest.mark.parametrize("shape", [(64, 2, 2, 64), (100, 2, 2, 100), (256, 2, 2, 256), (1024, 2, 2, 1024)])
 def test_svd_split_wide_dynamic_range(env, shape):
     # singular values from 1 down to 1e-30: the pair Grams span 60 decades,
     # beyond single precision, which the first Jacobi sweeps use for their
-    # rotation angles; the result must still be FP64-accurate (2048 x 2048:
-    # the full-size bond split of the benchmark)
+    # rotation angles; the result must still be FP64-accurate (128 and 200
+    # rows: 16-row blocks without preconditioning; 512 rows: Householder and
+    # the fused rotation; 2048 x 2048: the full-size bond split of the
+    # benchmark)
     torch, ctx = env
     Dl, d1, d2, Dr = shape
     m, n = Dl * d1, d2 * Dr
