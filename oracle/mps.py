@@ -26,7 +26,7 @@ Appendix D for the budget and the shift):
   4. Right-to-left half sweep, mirrored (A_j = U S, A_(j+1) = V^T).
   5. Normalise x, measure E = <x|H|x>, psi <- x.
 
-Readings where the paper is silent (each also listed in the design doc):
+Readings where the paper is silent:
   * b is projected exactly through mixed environments rather than first formed
     as an MPS by the density-matrix MPO-MPS product;
   * the initial guess is x = psi (for backward Euler this is b itself);
