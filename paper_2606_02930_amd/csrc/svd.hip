@@ -238,13 +238,18 @@ __device__ inline bool jacobi_angle(T gaa, T gbb, T gab, bool a_low, T& c, T& s)
     int e;
     (void)frexp(fmax(fabs(x), fabs(yy)), &e);
     const T xs = ldexp(x, -e), ys = ldexp(yy, -e);
-    const T r = sqrt(xs * xs + ys * ys);
+    // xs, ys are scaled so that xs^2 + ys^2 lies in [1/4, 2) and 2 r d in
+    // [1/2, 8): in single precision the hardware square root and reciprocal
+    // square root (no range reduction needed) are used directly
+    T r, iw;
+    if constexpr (std::is_same<T, float>::value) {
+        r = __builtin_amdgcn_sqrtf(xs * xs + ys * ys);
+        iw = __builtin_amdgcn_rsqf(T(2) * r * (fabs(xs) + r));
+    } else {
+        r = sqrt(xs * xs + ys * ys);
+        iw = rsqrt(T(2) * r * (fabs(xs) + r));
+    }
     const T d = fabs(xs) + r;
-    T iw;
-    if constexpr (std::is_same<T, float>::value)
-        iw = rsqrtf(T(2) * r * d);
-    else
-        iw = rsqrt(T(2) * r * d);
     c = d * iw;
     s = (x >= T(0) ? ys : -ys) * iw;
     if (a_low == (x >= T(0))) {
