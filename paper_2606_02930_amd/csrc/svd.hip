@@ -592,19 +592,32 @@ __device__ __forceinline__ int pair_sweep(PairLDS<RB>& sh, double tol, double ka
     double (*S)[PR + 1] = Gb[cur];
     // out = 1.5 A - 0.5 (A A^T) A: transposed into Gb[cur ^ 1] (the final Q)
     // or, for a first step, into Ab[cur ^ 1]
+    // S = A A^T is symmetric: only its tiles on and above the diagonal are
+    // formed, each written to both of its places
+    constexpr int NUT = NTL * (NTL + 1) / 2, UPW = (NUT + NW - 1) / NW;
+    const int wu = __builtin_amdgcn_readfirstlane(w);
     auto ns_step = [&](double (*A)[PR + 2], bool last) {
         if (upd) {
 #pragma unroll
-            for (int i = 0; i < TPW; ++i) {
-                const int tile = w + NW * i;
-                const int tm = tile / NTL, tn = tile % NTL;
+            for (int i = 0; i < UPW; ++i) {
+                const int tile = wu + NW * i;
+                if (tile >= NUT) break;
+                int tm = 0, tn = tile;
+                while (tn >= NTL - tm) {
+                    tn -= NTL - tm;
+                    ++tm;
+                }
+                tn += tm;
                 d4_t acc = {0, 0, 0, 0};
 #pragma unroll
                 for (int k0 = 0; k0 < PR; k0 += 4)
                     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[tm * 16 + l16][k0 + kg], A[tn * 16 + l16][k0 + kg],
                                                                acc, 0, 0, 0);
 #pragma unroll
-                for (int rr = 0; rr < 4; ++rr) S[tm * 16 + 4 * rr + kg][tn * 16 + l16] = acc[rr];
+                for (int rr = 0; rr < 4; ++rr) {
+                    S[tm * 16 + 4 * rr + kg][tn * 16 + l16] = acc[rr];
+                    if (tm != tn) S[tn * 16 + l16][tm * 16 + 4 * rr + kg] = acc[rr];
+                }
             }
         }
         __syncthreads();
