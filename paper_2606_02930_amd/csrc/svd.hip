@@ -442,14 +442,16 @@ __device__ __forceinline__ int pair_sweep(PairLDS<RB>& sh, double tol, double ka
     for (int i = 1; i < NW; ++i) gmax_local = fmax(gmax_local, gred[i]);
     const double kappa_s1 = kappa * sqrt(fmax(sigma1sq, gmax_local));
     double off = 0.0;
+    double gv[EPT];     // this thread's entries, kept for the single-precision copy
     if (upd) {
         const double gyy = Gb[0][y][y];
 #pragma unroll
         for (int u = 0; u < EPT; ++u) {
             const int x = xh + XS * u;
+            gv[u] = Gb[0][x][y];
             if (x < y) {
                 const double den = off_den(Gb[0][x][x], gyy, kappa_s1);
-                if (den > 0.0) off = fmax(off, fabs(Gb[0][x][y]) / den);
+                if (den > 0.0) off = fmax(off, fabs(gv[u]) / den);
             }
         }
     }
@@ -472,10 +474,7 @@ __device__ __forceinline__ int pair_sweep(PairLDS<RB>& sh, double tol, double ka
     // precision (started at the identity here)
     GT(&Aw)[2][PR][PR + 2] = *reinterpret_cast<GT(*)[2][PR][PR + 2]>(&Ab[0][0][0]);
     if constexpr (!std::is_same<GT, double>::value) {
-        double gv[EPT];
-#pragma unroll
-        for (int u = 0; u < EPT; ++u) gv[u] = upd ? Gb[0][xh + XS * u][y] : 0.0;
-        __syncthreads();
+        // every read of the FP64 Gram happened before the barrier above
         if (upd) {
 #pragma unroll
             for (int u = 0; u < EPT; ++u) {
