@@ -589,13 +589,13 @@ __device__ __forceinline__ int pair_sweep(PairLDS<RB>& sh, double tol, double ka
     const int l16 = lane & 15, kg = lane >> 4;
     constexpr int TPW = NTL * NTL / NW;
     double (*S)[PR + 1] = Gb[cur];
-    // out = 1.5 A - 0.5 (A A^T) A: transposed into Gb[cur ^ 1] (the final Q)
-    // or, for a first step, into Ab[cur ^ 1]
+    // 1.5 A - 0.5 (A A^T) A: transposed into Gb[cur ^ 1] (the final Q) or,
+    // for a first step, into out; A is read as double whatever it is stored in
     // S = A A^T is symmetric: only its tiles on and above the diagonal are
     // formed, each written to both of its places
     constexpr int NUT = NTL * (NTL + 1) / 2, UPW = (NUT + NW - 1) / NW;
     const int wu = __builtin_amdgcn_readfirstlane(w);
-    auto ns_step = [&](double (*A)[PR + 2], bool last) {
+    auto ns_step = [&](auto A, double (*out)[PR + 2], bool last) {
         if (upd) {
 #pragma unroll
             for (int i = 0; i < UPW; ++i) {
@@ -610,8 +610,8 @@ __device__ __forceinline__ int pair_sweep(PairLDS<RB>& sh, double tol, double ka
                 d4_t acc = {0, 0, 0, 0};
 #pragma unroll
                 for (int k0 = 0; k0 < PR; k0 += 4)
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[tm * 16 + l16][k0 + kg], A[tn * 16 + l16][k0 + kg],
-                                                               acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(double(A[tm * 16 + l16][k0 + kg]),
+                                                               double(A[tn * 16 + l16][k0 + kg]), acc, 0, 0, 0);
 #pragma unroll
                 for (int rr = 0; rr < 4; ++rr) {
                     S[tm * 16 + 4 * rr + kg][tn * 16 + l16] = acc[rr];
@@ -628,37 +628,29 @@ __device__ __forceinline__ int pair_sweep(PairLDS<RB>& sh, double tol, double ka
                 d4_t acc = {0, 0, 0, 0};
 #pragma unroll
                 for (int k0 = 0; k0 < PR; k0 += 4)
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(S[tm * 16 + l16][k0 + kg], A[k0 + kg][tn * 16 + l16],
-                                                               acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(S[tm * 16 + l16][k0 + kg],
+                                                               double(A[k0 + kg][tn * 16 + l16]), acc, 0, 0, 0);
 #pragma unroll
                 for (int rr = 0; rr < 4; ++rr) {
                     const int m = tm * 16 + 4 * rr + kg, kk = tn * 16 + l16;
-                    const double v = 1.5 * A[m][kk] - 0.5 * acc[rr];
+                    const double v = 1.5 * double(A[m][kk]) - 0.5 * acc[rr];
                     if (last)
                         Gb[cur ^ 1][kk][m] = v;
                     else
-                        Ab[cur ^ 1][m][kk] = v;
+                        out[m][kk] = v;
                 }
             }
         }
         __syncthreads();
     };
     if constexpr (std::is_same<GT, double>::value) {
-        ns_step(Ab[cur], true);
+        ns_step(Ab[cur], nullptr, true);
     } else {
-        // the FP32 rotation (over Ab[0]) to double in Ab[cur]: cur is odd
-        // after the PR - 1 rounds, so Ab[cur] does not overlap it
+        // first step straight from the FP32 rotation (over Ab[0]) into Ab[cur]:
+        // cur is odd after the PR - 1 rounds, so Ab[cur] does not overlap it
         static_assert(((PR - 1) & 1) == 1, "odd number of rounds");
-        if (upd) {
-#pragma unroll
-            for (int u = 0; u < EPT; ++u) {
-                const int x = xh + XS * u;
-                Ab[cur][x][y] = double(Aw[cur][x][y]);
-            }
-        }
-        __syncthreads();
-        ns_step(Ab[cur], false);
-        ns_step(Ab[cur ^ 1], true);
+        ns_step(Aw[cur], Ab[cur], false);
+        ns_step(Ab[cur], nullptr, true);
     }
     return anyrot ? 2 : 1;
 }
