@@ -113,16 +113,22 @@ __global__ __launch_bounds__(64 * QPW) void qr_panel_kernel(double* __restrict__
     const int c0 = w, c1 = w + QPW;               // this wavefront's columns
     if (t < QB * (QB + 1)) S[t / (QB + 1)][t % (QB + 1)] = 0.0;
     double a0[QRPL], a1[QRPL];
-    // coalesced load: thread t moves row t of a chunk
+    // coalesced load through LDS: QB consecutive lanes move one row of the
+    // chunk (one load touches NT / QB rows, not one row per lane)
+    static_assert((QCH * QB) % NT == 0 && NT % QB == 0, "chunk layout");
+    constexpr int LPT = QCH * QB / NT;
+    const int er = t % QB, rr0 = t / QB;
 #pragma unroll
     for (int c = 0; c < QNC; ++c) {
         {
-            const int row = c * QCH + t;
-            double ldv[QB];
+            double ldv[LPT];
 #pragma unroll
-            for (int e = 0; e < QB; ++e) ldv[e] = (row < m && e < nbw) ? P[(long)row * ld + e] : 0.0;
+            for (int h = 0; h < LPT; ++h) {
+                const int row = c * QCH + rr0 + h * (NT / QB);
+                ldv[h] = (row < m && er < nbw) ? P[(long)row * ld + er] : 0.0;
+            }
 #pragma unroll
-            for (int e = 0; e < QB; ++e) Pc[t][e] = ldv[e];
+            for (int h = 0; h < LPT; ++h) Pc[rr0 + h * (NT / QB)][er] = ldv[h];
         }
         __syncthreads();
 #pragma unroll
@@ -163,11 +169,10 @@ __global__ __launch_bounds__(64 * QPW) void qr_panel_kernel(double* __restrict__
             Pc[row - c * QCH][c1] = row > c1 ? 0.0 : a1[i];
         }
         __syncthreads();
-        {
-            const int row = c * QCH + t;
 #pragma unroll
-            for (int e = 0; e < QB; ++e)
-                if (row < m && e < nbw) P[(long)row * ld + e] = Pc[t][e];
+        for (int h = 0; h < LPT; ++h) {
+            const int row = c * QCH + rr0 + h * (NT / QB);
+            if (row < m && er < nbw) P[(long)row * ld + er] = Pc[rr0 + h * (NT / QB)][er];
         }
         __syncthreads();
     }
@@ -175,22 +180,22 @@ __global__ __launch_bounds__(64 * QPW) void qr_panel_kernel(double* __restrict__
     for (int e = t; e < (QB - nbw) * m; e += NT) VT[(long)nbw * m + e] = 0.0;
     if (t < QB && t >= nbw) tau_s[t] = 0.0;
     __syncthreads();
-    // T: T_jj = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] S[0:j, j]; column j by
-    // lanes i < j of the first wavefront, one column after the other
+    // T: T_jj = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] S[0:j, j]; lane i of
+    // the first wavefront holds row i of T in registers (entries left of the
+    // diagonal are zero, so the sum over k < j equals the one over i <= k < j)
     if (t < 64) {
         const int i = t;
+        double trow[QB];
+#pragma unroll
         for (int j = 0; j < QB; ++j) {
-            double tij = 0.0;
-            if (i < j) {
-                double acc = 0.0;
-                for (int k = i; k < j; ++k) acc += Ts[i][k] * S[k][j];
-                tij = -tau_s[j] * acc;
-            } else if (i == j) {
-                tij = tau_s[j];
-            }
-            if (i < QB) Ts[i][j] = tij;
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            double acc = 0.0;
+#pragma unroll
+            for (int k = 0; k < j; ++k) acc += trow[k] * S[k][j];
+            trow[j] = i < j ? -tau_s[j] * acc : (i == j ? tau_s[j] : 0.0);
+        }
+        if (i < QB) {
+#pragma unroll
+            for (int j = 0; j < QB; ++j) Ts[i][j] = trow[j];
         }
     }
     __syncthreads();
