@@ -39,6 +39,7 @@ namespace ite {
 namespace {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
 
 template <int RB> struct Blk {
     static constexpr int PR = 2 * RB;              // rows per pair
@@ -578,20 +579,28 @@ __device__ __forceinline__ int pair_sweep(PairLDS<RB>& sh, double tol, double ka
         cur = nxt;
     }
     // Every row is back at its starting position.  Newton-Schulz steps
-    // towards the nearest orthogonal matrix, A <- (3 I - A A^T) A / 2, with
-    // FP64 MFMA: the product of Givens rotations is orthogonal only to a few
-    // hundred ulps (to about 1e-5 for the single-precision sweep, whose
-    // rotations are FP32 pairs (cos, sin) applied in FP32), and every row
-    // meets such a rotation in each round of every sweep, so the defect
-    // would otherwise accumulate.  The step squares the defect: one suffices
-    // from FP64, two from FP32 (held in double in Ab[cur]).
+    // towards the nearest orthogonal matrix, A <- (3 I - A A^T) A / 2 =
+    // A - E A / 2 with E = A A^T - I: the product of Givens rotations is
+    // orthogonal only to a few hundred ulps (to about 1e-5 for the
+    // single-precision sweep, whose rotations are FP32 pairs (cos, sin)
+    // applied in FP32), and every row meets such a rotation in each round of
+    // every sweep, so the defect would otherwise accumulate.  The step
+    // squares the defect: one suffices from FP64, two from FP32 (held in
+    // double in Ab[cur]).  A A^T is formed with FP64 MFMA (E must be exact to
+    // the defect the step leaves); E A with FP32 MFMA from E and A rounded to
+    // FP32: E is at most about 1e-5, so the product's error (a few 1e-7 of
+    // E A) stays below the squared defect, and A - E A / 2 is formed in FP64.
     const int lane = t & 63, w = t >> 6;
     const int l16 = lane & 15, kg = lane >> 4;
     constexpr int TPW = NTL * NTL / NW;
-    double (*S)[PR + 1] = Gb[cur];
-    // 1.5 A - 0.5 (A A^T) A: transposed into Gb[cur ^ 1] (the final Q) or,
-    // for a first step, into out; A is read as double whatever it is stored in
-    // S = A A^T is symmetric: only its tiles on and above the diagonal are
+    // E in FP32 over Gb[cur] (rows of PR + 4 floats: the operand reads of
+    // a 16 x 4 block fall in distinct banks)
+    constexpr int LE = PR + 4;
+    static_assert(PR * LE * sizeof(float) <= sizeof(Gb[0]), "E fits");
+    float (*E)[LE] = reinterpret_cast<float (*)[LE]>(&Gb[cur][0][0]);
+    // A - E A / 2: transposed into Gb[cur ^ 1] (the final Q) or, for a first
+    // step, into out; A is read as double whatever it is stored in.
+    // A A^T is symmetric: only its tiles on and above the diagonal are
     // formed, each written to both of its places
     constexpr int NUT = NTL * (NTL + 1) / 2, UPW = (NUT + NW - 1) / NW;
     const int wu = __builtin_amdgcn_readfirstlane(w);
@@ -614,8 +623,11 @@ __device__ __forceinline__ int pair_sweep(PairLDS<RB>& sh, double tol, double ka
                                                                double(A[tn * 16 + l16][k0 + kg]), acc, 0, 0, 0);
 #pragma unroll
                 for (int rr = 0; rr < 4; ++rr) {
-                    S[tm * 16 + 4 * rr + kg][tn * 16 + l16] = acc[rr];
-                    if (tm != tn) S[tn * 16 + l16][tm * 16 + 4 * rr + kg] = acc[rr];
+                    // FP64 MFMA: element rr of lane group kg is tile row 4 rr + kg
+                    const int m = tm * 16 + 4 * rr + kg, n = tn * 16 + l16;
+                    const float e = float(acc[rr] - (m == n ? 1.0 : 0.0));
+                    E[m][n] = e;
+                    if (tm != tn) E[n][m] = e;
                 }
             }
         }
@@ -625,15 +637,16 @@ __device__ __forceinline__ int pair_sweep(PairLDS<RB>& sh, double tol, double ka
             for (int i = 0; i < TPW; ++i) {
                 const int tile = w + NW * i;
                 const int tm = tile / NTL, tn = tile % NTL;
-                d4_t acc = {0, 0, 0, 0};
+                f4_t acc = {0, 0, 0, 0};
 #pragma unroll
                 for (int k0 = 0; k0 < PR; k0 += 4)
-                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(S[tm * 16 + l16][k0 + kg],
-                                                               double(A[k0 + kg][tn * 16 + l16]), acc, 0, 0, 0);
+                    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(E[tm * 16 + l16][k0 + kg],
+                                                               float(A[k0 + kg][tn * 16 + l16]), acc, 0, 0, 0);
 #pragma unroll
                 for (int rr = 0; rr < 4; ++rr) {
-                    const int m = tm * 16 + 4 * rr + kg, kk = tn * 16 + l16;
-                    const double v = 1.5 * double(A[m][kk]) - 0.5 * acc[rr];
+                    // FP32 MFMA: element rr of lane group kg is tile row 4 kg + rr
+                    const int m = tm * 16 + 4 * kg + rr, kk = tn * 16 + l16;
+                    const double v = double(A[m][kk]) - 0.5 * double(acc[rr]);
                     if (last)
                         Gb[cur ^ 1][kk][m] = v;
                     else
