@@ -210,6 +210,29 @@ int ite_mps_set_tau(ite_mps* psi, double tau);
 int ite_imag_step(ite_mps* psi, const ite_mpo* H, double h,
                   const ite_step_opts* opts, ite_step_report* rep);
 
+/* Two-site DMRG ground-state sweeps (the ground state of the impurity model
+ * that seeds the METTS chains and gives the zero-temperature double
+ * occupancy, Appendix D), on the same blocks, environments and SVD split as
+ * ite_imag_step: per block the lowest eigenpair of the two-site effective
+ * Hamiltonian by Lanczos (Arnoldi steps with classical Gram-Schmidt twice,
+ * at most krylov_dim vectors per cycle, restarted from the Ritz vector for
+ * at most max_cycles cycles, or until ||H x - theta x|| <= tol |theta|;
+ * tol = 0: the full budget), then the split (chi_max capped by psi's own
+ * maximum, cutoff and tie_rel as in ite_step_opts).  One sweep is a
+ * left-to-right plus a right-to-left half sweep; psi (any normalised state
+ * with the centre on site 1, as left by the constructors and ite_imag_step)
+ * is replaced by the result, normalised, centre on site 1; its tau is
+ * unchanged.  Outputs (each nullable): *energy = <psi|H|psi> of the result,
+ * *max_res_rel the largest relative residual estimate of a local problem,
+ * *max_disc the largest discarded weight, *matvecs the effective-Hamiltonian
+ * products.  Errors: EINVAL (nsweeps or max_cycles < 1, krylov_dim outside
+ * 1..64, chi_max < 1, cutoff outside [0, 1), tie_rel or tol < 0), ESTATE (L
+ * or d of psi and H differ), ENOMEM, EDEVICE, ENONFINITE (psi left
+ * unchanged). */
+int ite_dmrg_sweeps(ite_mps* psi, const ite_mpo* H, int nsweeps, int chi_max, double cutoff,
+                    double tie_rel, int krylov_dim, int max_cycles, double tol, double* energy,
+                    double* max_res_rel, double* max_disc, long long* matvecs);
+
 /* Evolve along the geometric grid 0, tau0, tau0 r, tau0 r^2, ... clamped to
  * end at tau1 (Method: logarithmic grids), starting at the first grid point
  * after psi's current tau.  per_step (nullable) receives up to max_steps

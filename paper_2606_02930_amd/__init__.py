@@ -111,6 +111,7 @@ _SIGNATURES = {
     "ite_evolve_grid": (_I, [_P, _P, _PD, _I, C.POINTER(ite_step_opts),
                              C.POINTER(ite_step_report), _I, _PI]),
     "ite_measure_energy": (_I, [_P, _P, _PD]),
+    "ite_dmrg_sweeps": (_I, [_P, _P, _I, _I, _D, _D, _I, _I, _D, _PD, _PD, _PD, C.POINTER(C.c_longlong)]),
     "ite_mps_overlap": (_I, [_P, _P, _PD]),
     "ite_mps_norm": (_I, [_P, _PD]),
     "ite_loggrid": (_I, [_D, _D, _D, _PD, _I, _PI]),
@@ -369,6 +370,15 @@ def ite_evolve_grid(ctx: Ctx, psi: int, mpo: int, taus, opts: ite_step_opts) -> 
     _check(load_library().ite_evolve_grid(psi, mpo, _dptr(t), len(t), C.byref(opts), reps, cap, C.byref(n)),
            ctx.handle)
     return [reps[i].as_dict() for i in range(n.value)]
+
+
+def ite_dmrg_sweeps(ctx: Ctx, psi: int, mpo: int, nsweeps: int, chi_max: int, cutoff: float = 0.0,
+                    tie_rel: float = 1e-10, krylov_dim: int = 10, max_cycles: int = 1, tol: float = 0.0) -> dict:
+    e, res, disc, mv = C.c_double(), C.c_double(), C.c_double(), C.c_longlong()
+    _check(load_library().ite_dmrg_sweeps(psi, mpo, int(nsweeps), int(chi_max), float(cutoff), float(tie_rel),
+                                          int(krylov_dim), int(max_cycles), float(tol), C.byref(e), C.byref(res),
+                                          C.byref(disc), C.byref(mv)), ctx.handle)
+    return {"energy": e.value, "max_res_rel": res.value, "max_disc": disc.value, "matvecs": mv.value}
 
 
 def ite_measure_energy(ctx: Ctx, psi: int, mpo: int) -> float:

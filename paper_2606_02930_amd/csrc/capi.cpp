@@ -326,6 +326,32 @@ int ite_imag_step(ite_mps* psi, const ite_mpo* H, double h, const ite_step_opts*
     });
 }
 
+int ite_dmrg_sweeps(ite_mps* psi, const ite_mpo* H, int nsweeps, int chi_max, double cutoff, double tie_rel,
+                    int krylov_dim, int max_cycles, double tol, double* energy, double* max_res_rel,
+                    double* max_disc, long long* matvecs) {
+    if (!psi || !H) return ITE_EINVAL;
+    if (psi->ctx != H->ctx) return ITE_ESTATE;
+    if (nsweeps < 1 || max_cycles < 1 || krylov_dim < 1 || krylov_dim > 64 || chi_max < 1) return ITE_EINVAL;
+    if (!(cutoff >= 0.0 && cutoff < 1.0) || !(tie_rel >= 0.0) || !(tol >= 0.0)) return ITE_EINVAL;
+    return guarded(psi->ctx, [&] {
+        set_device(psi->ctx);
+        DmrgOpts o;
+        o.nsweeps = nsweeps;
+        o.chi_max = chi_max;
+        o.cutoff = cutoff;
+        o.tie_rel = tie_rel;
+        o.krylov_dim = krylov_dim;
+        o.max_cycles = max_cycles;
+        o.tol = tol;
+        DmrgReport r;
+        dmrg_sweeps(psi, H, o, &r);
+        if (energy) *energy = r.energy;
+        if (max_res_rel) *max_res_rel = r.max_res_rel;
+        if (max_disc) *max_disc = r.max_disc;
+        if (matvecs) *matvecs = r.matvecs;
+    });
+}
+
 int ite_loggrid(double tau0, double tau1, double ratio, double* out, int cap, int* n) {
     if (!n) return ITE_EINVAL;
     *n = 0;

@@ -1197,4 +1197,224 @@ void imag_step(ite_mps* psi, const ite_mpo* H, double h, const ite_step_opts& o,
     if (rep) *rep = r;
 }
 
+// ---------------------------------------------------------------------------
+// DMRG ground-state sweeps
+// ---------------------------------------------------------------------------
+
+// Eigenvalues w and eigenvectors (columns of Z, row-major k x k) of the
+// symmetric k x k matrix A by cyclic Jacobi rotations (Jacobi's method; each
+// rotation J in the (p, q) plane with tan = t the smaller root of
+// t^2 + 2 tau t - 1 = 0, tau = (a_qq - a_pp) / (2 a_pq), zeroes a_pq of J^T A J).
+static void sym_eig_small(int k, std::vector<double> A, std::vector<double>& w, std::vector<double>& Z) {
+    Z.assign((size_t)k * k, 0.0);
+    for (int i = 0; i < k; ++i) Z[(size_t)i * k + i] = 1.0;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < k; ++i)
+            for (int j = 0; j < k; ++j) {
+                const double v = A[(size_t)i * k + j] * A[(size_t)i * k + j];
+                tot += v;
+                if (i != j) off += v;
+            }
+        if (!(off > 1e-32 * tot)) break;
+        for (int p = 0; p < k; ++p)
+            for (int q = p + 1; q < k; ++q) {
+                const double apq = A[(size_t)p * k + q];
+                if (apq == 0.0) continue;
+                const double tau = (A[(size_t)q * k + q] - A[(size_t)p * k + p]) / (2.0 * apq);
+                const double t = (tau >= 0.0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
+                const double cc = 1.0 / std::sqrt(1.0 + t * t), ss = t * cc;
+                for (int r = 0; r < k; ++r) {   // columns p, q of A J
+                    const double arp = A[(size_t)r * k + p], arq = A[(size_t)r * k + q];
+                    A[(size_t)r * k + p] = cc * arp - ss * arq;
+                    A[(size_t)r * k + q] = ss * arp + cc * arq;
+                }
+                for (int r = 0; r < k; ++r) {   // rows p, q of J^T (A J)
+                    const double apr = A[(size_t)p * k + r], aqr = A[(size_t)q * k + r];
+                    A[(size_t)p * k + r] = cc * apr - ss * aqr;
+                    A[(size_t)q * k + r] = ss * apr + cc * aqr;
+                }
+                for (int r = 0; r < k; ++r) {   // Z J
+                    const double zrp = Z[(size_t)r * k + p], zrq = Z[(size_t)r * k + q];
+                    Z[(size_t)r * k + p] = cc * zrp - ss * zrq;
+                    Z[(size_t)r * k + q] = ss * zrp + cc * zrq;
+                }
+            }
+    }
+    w.resize(k);
+    for (int i = 0; i < k; ++i) w[i] = A[(size_t)i * k + i];
+}
+
+struct EigStats {
+    double theta = 0.0, res_rel = 0.0;
+    long long matvecs = 0;
+};
+
+// Lowest eigenpair of the symmetric operator op by the Lanczos method with
+// full reorthogonalisation: the Arnoldi steps of the GMRES solver (classical
+// Gram-Schmidt twice, the projected column kept on the device and brought to
+// the host once per cycle), the symmetric part of the projected matrix
+// diagonalised on the host, and a restart from the Ritz vector, for at most
+// max_cycles cycles of m steps or until ||op x - theta x|| <= tol |theta|
+// (estimated as |h_(k+1,k) y_k|).  x: the start vector on entry (any norm),
+// the normalised Ritz vector on return.
+static EigStats lanczos_lowest(ite_ctx* c, const LocalOp& op, double* x, int m, int max_cycles, double tol) {
+    EigStats st;
+    const size_t n = op.n();
+    const int mm = (int)std::min<size_t>((size_t)m, n);
+    constexpr int HC = 192;   // per column: [0,64) first-pass coefficients, [64,128) second pass, 128 norm
+    double* V = slot_t<double>(c, SL_V, (size_t)(mm + 1) * n);
+    double* w = slot_t<double>(c, SL_W, n);
+    const int nb = reduce_blocks(n);
+    double* part = slot_t<double>(c, SL_PART, (size_t)nb * 64 + 64);
+    double* hd = slot_t<double>(c, SL_HESS, (size_t)mm * HC + 8);
+    double* xnorm_d = hd + (size_t)mm * HC;
+    double* host = pinned(c, (size_t)mm * HC + 8 + 64);
+    std::vector<double> T, ev, Z;
+    for (int cyc = 0; cyc < max_cycles; ++cyc) {
+        dot_partials(x, x, n, part, c->stream);
+        finish_partials(part, 1, nb, xnorm_d, 2, c->stream);
+        scale_inv(x, xnorm_d, V, n, c->stream);
+        for (int k = 0; k < mm; ++k) {
+            double* col = hd + (size_t)k * HC;
+            double* vnext = k + 1 < mm ? V + (size_t)(k + 1) * n : nullptr;
+            op_apply(c, op, V + (size_t)k * n, w);
+            if (cgs2_small(V, (long)n, k + 1, w, n, col, vnext, c->stream)) continue;
+            mdot_partials(V, (long)n, k + 1, w, n, part, c->stream);
+            finish_partials(part, k + 1, nb, col, 0, c->stream);
+            gemv_sub(V, (long)n, k + 1, col, w, n, c->stream);
+            mdot_partials(V, (long)n, k + 1, w, n, part, c->stream);
+            finish_partials(part, k + 1, nb, col + 64, 0, c->stream);
+            gemv_sub(V, (long)n, k + 1, col + 64, w, n, c->stream);
+            dot_partials(w, w, n, part, c->stream);
+            finish_partials(part, 1, nb, col + 128, 2, c->stream);
+            if (vnext) scale_inv(w, col + 128, vnext, n, c->stream);
+        }
+        d2h(c, host, hd, (size_t)mm * HC + 1);
+        sync(c);
+        if (!(host[(size_t)mm * HC] > 0.0) || !std::isfinite(host[(size_t)mm * HC]))
+            ITE_FAIL(ITE_ENONFINITE, "dmrg: zero or non-finite start vector of a local problem");
+        // projected matrix (upper triangle from the Gram-Schmidt coefficients)
+        // up to the first breakdown
+        int kused = mm;
+        double scale_h = 0.0;
+        for (int k = 0; k < mm; ++k) {
+            const double* col = host + (size_t)k * HC;
+            scale_h = std::max(scale_h, std::fabs(col[k] + col[64 + k]));
+            if (k + 1 < mm && !(col[128] > 1e-14 * std::max(scale_h, 1e-300))) {
+                kused = k + 1;
+                break;
+            }
+        }
+        T.assign((size_t)kused * kused, 0.0);
+        for (int k = 0; k < kused; ++k) {
+            const double* col = host + (size_t)k * HC;
+            for (int i = 0; i <= k; ++i) {
+                const double v = col[i] + col[64 + i];
+                T[(size_t)i * kused + k] = v;
+                T[(size_t)k * kused + i] = v;
+            }
+        }
+        sym_eig_small(kused, T, ev, Z);
+        const int imin = (int)(std::min_element(ev.begin(), ev.end()) - ev.begin());
+        st.theta = ev[imin];
+        const double hlast = kused == mm ? host[(size_t)(mm - 1) * HC + 128] : 0.0;
+        const double res = std::fabs(hlast * Z[(size_t)(kused - 1) * kused + imin]);
+        st.res_rel = st.theta != 0.0 ? res / std::fabs(st.theta) : res;
+        st.matvecs += kused;
+        double* ys = host + (size_t)mm * HC + 8;
+        for (int i = 0; i < kused; ++i) ys[i] = Z[(size_t)i * kused + imin];
+        double* ydev = slot_t<double>(c, SL_SMALL, 512) + 192;
+        h2d(c, ydev, ys, sizeof(double) * kused);
+        fill(x, 0.0, n, c->stream);
+        gemv_add(V, (long)n, kused, ydev, x, n, c->stream);
+        sync(c);
+        if (!std::isfinite(st.theta)) ITE_FAIL(ITE_ENONFINITE, "dmrg: non-finite Ritz value");
+        if (kused < mm || res <= tol * std::fabs(st.theta)) break;
+    }
+    return st;
+}
+
+void dmrg_sweeps(ite_mps* psi, const ite_mpo* H, const DmrgOpts& o, DmrgReport* rep) {
+    ite_ctx* c = psi->ctx;
+    const int L = psi->L;
+    if (H->L != L) ITE_FAIL(ITE_ESTATE, "dmrg: MPS and MPO lengths differ");
+    for (int i = 0; i < L; ++i)
+        if (H->d[i] != psi->d[i]) ITE_FAIL(ITE_ESTATE, "dmrg: local dimensions of MPS and MPO differ");
+    ITE_REQUIRE(o.nsweeps >= 1, "dmrg: nsweeps must be >= 1");
+    ITE_REQUIRE(o.chi_max >= 1, "dmrg: chi_max must be >= 1");
+    ITE_REQUIRE(o.cutoff >= 0.0 && o.cutoff < 1.0, "dmrg: cutoff must be in [0, 1)");
+    ITE_REQUIRE(o.tie_rel >= 0.0, "dmrg: tie_rel must be >= 0");
+    ITE_REQUIRE(o.krylov_dim >= 1 && o.krylov_dim <= 64, "dmrg: krylov_dim must be in 1..64");
+    ITE_REQUIRE(o.max_cycles >= 1, "dmrg: max_cycles must be >= 1");
+    ITE_REQUIRE(o.tol >= 0.0, "dmrg: tol must be >= 0");
+    ensure_evolution(psi, H);
+    const int chi = std::min(o.chi_max, psi->chi_max);
+    auto& env = psi->env;
+    auto& X = psi->X;
+    auto& XD = psi->XD;
+    XD = psi->D;
+    for (int i = 0; i < L; ++i) d2d(c, X[i], psi->A[i], (size_t)psi->D[i] * psi->d[i] * psi->D[i + 1]);
+    fill(env[0].H, 1.0, 1, c->stream);
+    fill(env[L].H, 1.0, 1, c->stream);
+    for (int b = L - 1; b >= 2; --b)
+        env_right(c, XD[b + 1], XD[b + 1], XD[b], XD[b], psi->d[b], H->w[b], H->w[b + 1], env[b + 1].H, X[b],
+                  &H->right[b], X[b], env[b].H);
+    DmrgReport r{};
+    auto block = [&](int i, int dir) {
+        const int d1 = psi->d[i], d2 = psi->d[i + 1];
+        const int Dl = XD[i], Dr = XD[i + 2];
+        double* th = slot_t<double>(c, SL_TH, (size_t)Dl * d1 * d2 * Dr);
+        two_site(c, Dl, d1, XD[i + 1], d2, Dr, X[i], X[i + 1], th);
+        LocalOp op;
+        op.s = HeffShape{Dl, Dl, Dr, Dr, d1, d2, H->w[i], H->w[i + 2]};
+        op.L = env[i].H;
+        op.R = env[i + 2].H;
+        op.ww = &H->pair[i];
+        op.alpha = 0.0;
+        op.beta = 1.0;
+        const EigStats es = lanczos_lowest(c, op, th, o.krylov_dim, o.max_cycles, o.tol);
+        r.energy = es.theta;
+        r.matvecs += es.matvecs;
+        r.max_res_rel = std::max(r.max_res_rel, es.res_rel);
+        const SplitResult sp = split(c, dir, Dl, d1, d2, Dr, th, chi, o.cutoff, o.tie_rel, X[i], X[i + 1], nullptr);
+        XD[i + 1] = sp.k;
+        r.max_disc = std::max(r.max_disc, sp.disc);
+    };
+    for (int sw = 0; sw < o.nsweeps; ++sw) {
+        for (int i = 0; i + 1 < L; ++i) {
+            block(i, 0);
+            if (i + 2 < L)
+                env_left(c, XD[i], XD[i], XD[i + 1], XD[i + 1], psi->d[i], H->w[i], H->w[i + 1], env[i].H, X[i],
+                         &H->left[i], X[i], env[i + 1].H);
+        }
+        for (int i = L - 2; i >= 0; --i) {
+            block(i, 1);
+            if (i > 0)
+                env_right(c, XD[i + 2], XD[i + 2], XD[i + 1], XD[i + 1], psi->d[i + 1], H->w[i + 1], H->w[i + 2],
+                          env[i + 2].H, X[i + 1], &H->right[i + 1], X[i + 1], env[i + 1].H);
+        }
+    }
+    // the mixed environments of the evolution describe the previous state
+    for (int b = 2; b < L; ++b) {
+        env[b].hp_alias = true;
+        env[b].o_ident = true;
+    }
+    // normalise the centre (site 1; the last eigenvector is normalised, the
+    // truncation of its split may not be) and measure
+    const size_t n0 = (size_t)XD[0] * psi->d[0] * XD[1];
+    const double nrm = std::sqrt(std::max(dot(c, X[0], X[0], n0), 0.0));
+    if (!(std::isfinite(nrm) && nrm > 0.0)) ITE_FAIL(ITE_ENONFINITE, "dmrg: non-finite state; psi left unchanged");
+    scale(X[0], 1.0 / nrm, n0, c->stream);
+    const double E = centre_energy(c, H, X, XD, env[2].H);
+    if (!std::isfinite(E)) ITE_FAIL(ITE_ENONFINITE, "dmrg: non-finite energy; psi left unchanged");
+    std::swap(psi->A, psi->X);
+    std::swap(psi->D, psi->XD);
+    psi->energy = E;
+    psi->e_valid = true;
+    r.energy = E;
+    r.max_chi = *std::max_element(psi->D.begin(), psi->D.end());
+    if (rep) *rep = r;
+}
+
 }  // namespace ite

@@ -176,4 +176,17 @@ void imag_step(ite_mps* psi, const ite_mpo* H, double h, const ite_step_opts& o,
 double measure_energy(ite_mps* psi, const ite_mpo* H);
 double overlap(ite_mps* a, ite_mps* b);
 
+// Two-site DMRG ground-state sweeps (local problems: lowest eigenpair by
+// Lanczos); see ite_dmrg_sweeps.
+struct DmrgOpts {
+    int nsweeps = 1, chi_max = 1, krylov_dim = 10, max_cycles = 1;
+    double cutoff = 0.0, tie_rel = 1e-10, tol = 0.0;
+};
+struct DmrgReport {
+    double energy = 0.0, max_res_rel = 0.0, max_disc = 0.0;
+    long long matvecs = 0;
+    int max_chi = 0;
+};
+void dmrg_sweeps(ite_mps* psi, const ite_mpo* H, const DmrgOpts& o, DmrgReport* rep);
+
 }  // namespace ite
