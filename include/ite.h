@@ -233,6 +233,19 @@ int ite_dmrg_sweeps(ite_mps* psi, const ite_mpo* H, int nsweeps, int chi_max, do
                     double tie_rel, int krylov_dim, int max_cycles, double tol, double* energy,
                     double* max_res_rel, double* max_disc, long long* matvecs);
 
+/* Product-basis samples of psi, the collapse step of a METTS chain (the
+ * chains of Appendix D start from product states sampled from the ground
+ * state): site by site from the left, s_i drawn from its conditional
+ * probability given s_1..s_(i-1), exact because psi is right-orthonormal
+ * with the centre on site 1 (as every call of this library leaves it; the
+ * norm cancels).  Sample k takes the first s with P(s' <= s) > u and
+ * P(s) > 0, u = uniforms[i * nsamples + k] (host array, L * nsamples values
+ * in [0, 1), drawn by the caller); configs (host, nsamples * L ints) gets
+ * s_i of sample k at configs[k * L + i].  Local dimensions up to 16.
+ * Errors: EINVAL (nsamples < 1, null arrays, a uniform outside [0, 1), a
+ * local dimension above 16), ENOMEM, EDEVICE. */
+int ite_mps_sample(ite_mps* psi, int nsamples, const double* uniforms, int* configs);
+
 /* Evolve along the geometric grid 0, tau0, tau0 r, tau0 r^2, ... clamped to
  * end at tau1 (Method: logarithmic grids), starting at the first grid point
  * after psi's current tau.  per_step (nullable) receives up to max_steps

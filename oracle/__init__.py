@@ -22,6 +22,8 @@ Logarithmic Grids" (Zima, Stoudenmire, White, Parcollet, Kaye) by eye:
   linear solve of (I + h (H - s)) x = b with b projected into x's basis, GMRES
   local solves, SVD truncation by discarded weight, normalisation and energy
   shift after every step (Method; Appendices B and D).
+* ``oracle.sampling`` -- product-basis sampling of a right-orthonormal MPS by
+  conditional probabilities (the METTS collapse, Appendix D).
 * ``oracle.dmrg`` -- two-site DMRG ground-state sweeps on the same blocks and
   split, the local problem diagonalised exactly (the ground state that seeds
   the METTS chains and gives the zero-temperature double occupancy,

@@ -111,6 +111,7 @@ _SIGNATURES = {
     "ite_evolve_grid": (_I, [_P, _P, _PD, _I, C.POINTER(ite_step_opts),
                              C.POINTER(ite_step_report), _I, _PI]),
     "ite_measure_energy": (_I, [_P, _P, _PD]),
+    "ite_mps_sample": (_I, [_P, _I, _PD, _PI]),
     "ite_dmrg_sweeps": (_I, [_P, _P, _I, _I, _D, _D, _I, _I, _D, _PD, _PD, _PD, C.POINTER(C.c_longlong)]),
     "ite_mps_overlap": (_I, [_P, _P, _PD]),
     "ite_mps_norm": (_I, [_P, _PD]),
@@ -379,6 +380,15 @@ def ite_dmrg_sweeps(ctx: Ctx, psi: int, mpo: int, nsweeps: int, chi_max: int, cu
                                           int(krylov_dim), int(max_cycles), float(tol), C.byref(e), C.byref(res),
                                           C.byref(disc), C.byref(mv)), ctx.handle)
     return {"energy": e.value, "max_res_rel": res.value, "max_disc": disc.value, "matvecs": mv.value}
+
+
+def ite_mps_sample(ctx: Ctx, psi: int, uniforms) -> np.ndarray:
+    """uniforms [L][nsamples] in [0, 1); returns configs [nsamples][L]."""
+    u = np.ascontiguousarray(uniforms, dtype=np.float64)
+    L, S = u.shape
+    cfg = np.zeros((S, L), dtype=np.int32)
+    _check(load_library().ite_mps_sample(psi, S, _dptr(u), cfg.ctypes.data_as(_PI)), ctx.handle)
+    return cfg
 
 
 def ite_measure_energy(ctx: Ctx, psi: int, mpo: int) -> float:

@@ -352,6 +352,14 @@ int ite_dmrg_sweeps(ite_mps* psi, const ite_mpo* H, int nsweeps, int chi_max, do
     });
 }
 
+int ite_mps_sample(ite_mps* psi, int nsamples, const double* uniforms, int* configs) {
+    if (!psi || !uniforms || !configs || nsamples < 1) return ITE_EINVAL;
+    return guarded(psi->ctx, [&] {
+        set_device(psi->ctx);
+        mps_sample(psi, nsamples, uniforms, configs);
+    });
+}
+
 int ite_loggrid(double tau0, double tau1, double ratio, double* out, int cap, int* n) {
     if (!n) return ITE_EINVAL;
     *n = 0;

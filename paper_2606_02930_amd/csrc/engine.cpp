@@ -1417,4 +1417,42 @@ void dmrg_sweeps(ite_mps* psi, const ite_mpo* H, const DmrgOpts& o, DmrgReport* 
     if (rep) *rep = r;
 }
 
+// ---------------------------------------------------------------------------
+// Product-basis sampling (METTS collapse)
+// ---------------------------------------------------------------------------
+
+// Site by site from the left, all samples at once: T = V A_i (FP64 GEMM,
+// V [S][D_i] the samples' normalised left vectors), then one workgroup per
+// sample picks s_i from the conditional probabilities ||T[smp][s]||^2 (exact
+// because the sites right of i are right-orthonormal) and forms the next V.
+void mps_sample(ite_mps* psi, int S, const double* uniforms, int* configs) {
+    ite_ctx* c = psi->ctx;
+    const int L = psi->L;
+    ITE_REQUIRE(S >= 1, "mps_sample: nsamples must be >= 1");
+    int Dmax = 1, dmax = 1;
+    for (int i = 0; i < L; ++i) {
+        ITE_REQUIRE(psi->d[i] >= 1 && psi->d[i] <= SAMPLE_DMAX, "mps_sample: local dimension above 16");
+        Dmax = std::max(Dmax, psi->D[i + 1]);
+        dmax = std::max(dmax, psi->d[i]);
+    }
+    for (size_t k = 0; k < (size_t)S * L; ++k)
+        ITE_REQUIRE(uniforms[k] >= 0.0 && uniforms[k] < 1.0, "mps_sample: uniforms must lie in [0, 1)");
+    double* u = slot_t<double>(c, SL_PART, (size_t)S * L);
+    int* cfg = slot_t<int>(c, SL_PERM, (size_t)S * L);
+    double* V0 = slot_t<double>(c, SL_V, (size_t)S * Dmax);
+    double* V1 = slot_t<double>(c, SL_W, (size_t)S * Dmax);
+    double* T = slot_t<double>(c, SL_X1, (size_t)S * dmax * Dmax);
+    h2d(c, u, uniforms, sizeof(double) * S * L);
+    fill(V0, 1.0, (size_t)S, c->stream);
+    for (int i = 0; i < L; ++i) {
+        const int Dl = psi->D[i], Dr = psi->D[i + 1], d = psi->d[i];
+        gemm(c, false, false, S, d * Dr, Dl, 1.0, V0, Dl, psi->A[i], (long)d * Dr, 0.0, nullptr, 0, T,
+             (long)d * Dr);
+        sample_site(T, S, d, Dr, u + (size_t)i * S, V1, cfg, L, i, c->stream);
+        std::swap(V0, V1);
+    }
+    HIP_CHECK(hipMemcpyAsync(configs, cfg, sizeof(int) * S * L, hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+}
+
 }  // namespace ite

@@ -188,5 +188,7 @@ struct DmrgReport {
     int max_chi = 0;
 };
 void dmrg_sweeps(ite_mps* psi, const ite_mpo* H, const DmrgOpts& o, DmrgReport* rep);
+// Product-basis samples of psi (see ite_mps_sample); host arrays.
+void mps_sample(ite_mps* psi, int nsamples, const double* uniforms, int* configs);
 
 }  // namespace ite

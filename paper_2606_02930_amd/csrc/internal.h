@@ -101,6 +101,11 @@ void axpby(size_t n, double a, const double* x, double b, const double* y, doubl
            hipStream_t s);
 // out = x / *den (device scalar); writes zeros when *den <= thresh
 void scale_inv(const double* x, const double* den, double* out, size_t n, hipStream_t s);
+// One site of product-basis sampling (see sample_site_kernel): T [nsamples][d][Dr],
+// u [nsamples], vnext [nsamples][Dr], cfg [nsamples][L]; d <= SAMPLE_DMAX.
+constexpr int SAMPLE_DMAX = 16;
+void sample_site(const double* T, int nsamples, int d, int Dr, const double* u, double* vnext, int* cfg, int L,
+                 int site, hipStream_t s);
 // Both classical Gram-Schmidt passes of one Arnoldi step in a single
 // workgroup for n <= 8192 (k1 <= 64 basis vectors): coefficients to
 // col[0..k1) and col[64..64+k1), ||w|| to col[128], vnext = w / ||w|| when

@@ -9,6 +9,7 @@
 #include "wave.h"
 
 #include <cmath>
+#include <stdexcept>
 
 namespace ite {
 namespace {
@@ -384,6 +385,68 @@ bool cgs2_small(const double* V, long ldv, int k1, double* w, size_t n, double* 
         hipLaunchKernelGGL((cgs2_small_kernel<64>), dim3(1), dim3(CGS_T), 0, s, V, ldv, k1, w, nn, col, vnext);
     HIP_CHECK(hipGetLastError());
     return true;
+}
+
+// One site of the conditional sampling of an MPS in the product basis, one
+// workgroup per sample: T[smp] ([d][Dr]) = v A_site for that sample's
+// normalised left vector v; p_s = ||T[smp][s]||^2 (fixed reduction order);
+// the site takes the first s with p_0 + .. + p_s > u[smp] (p_0 + .. + p_(d-1))
+// and p_s > 0 (else the last s with p_s > 0, else 0), written to
+// cfg[smp * L + site]; vnext[smp] = T[smp][s] / ||T[smp][s]||.
+constexpr int SMP_T = 256;
+__global__ __launch_bounds__(SMP_T) void sample_site_kernel(const double* __restrict__ T, int d, int Dr,
+                                                            const double* __restrict__ u,
+                                                            double* __restrict__ vnext, int* __restrict__ cfg,
+                                                            int L, int site) {
+    __shared__ double part[SMP_T / 64][SAMPLE_DMAX];
+    __shared__ double pw[SAMPLE_DMAX];
+    __shared__ int chosen;
+    const int smp = blockIdx.x, t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const double* row = T + (size_t)smp * d * Dr;
+    for (int q = 0; q < d; ++q) {
+        double acc = 0.0;
+        for (int j = t; j < Dr; j += SMP_T) {
+            const double x = row[(size_t)q * Dr + j];
+            acc += x * x;
+        }
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);   // butterfly: fixed order
+        if (lane == 0) part[wv][q] = acc;
+    }
+    __syncthreads();
+    if (t == 0) {
+        double tot = 0.0;
+        for (int q = 0; q < d; ++q) {
+            double pq = 0.0;
+            for (int w = 0; w < SMP_T / 64; ++w) pq += part[w][q];
+            pw[q] = pq;
+            tot += pq;
+        }
+        const double thr = u[smp] * tot;
+        int pick = -1;
+        double cum = 0.0;
+        for (int q = 0; q < d; ++q) {
+            cum += pw[q];
+            if (pick < 0 && cum > thr && pw[q] > 0.0) pick = q;
+        }
+        for (int q = d - 1; q >= 0 && pick < 0; --q)
+            if (pw[q] > 0.0) pick = q;
+        if (pick < 0) pick = 0;
+        chosen = pick;
+        cfg[(size_t)smp * L + site] = pick;
+    }
+    __syncthreads();
+    const int q = chosen;
+    const double nq = pw[q];
+    const double inv = nq > 0.0 ? 1.0 / sqrt(nq) : 0.0;
+    for (int j = t; j < Dr; j += SMP_T) vnext[(size_t)smp * Dr + j] = row[(size_t)q * Dr + j] * inv;
+}
+
+void sample_site(const double* T, int nsamples, int d, int Dr, const double* u, double* vnext, int* cfg, int L,
+                 int site, hipStream_t s) {
+    if (nsamples <= 0) return;
+    if (d < 1 || d > SAMPLE_DMAX || Dr < 1) throw std::invalid_argument("sample_site: bad dimensions");
+    hipLaunchKernelGGL(sample_site_kernel, dim3(nsamples), dim3(SMP_T), 0, s, T, d, Dr, u, vnext, cfg, L, site);
+    HIP_CHECK(hipGetLastError());
 }
 
 void scale_inv(const double* x, const double* den, double* out, size_t n, hipStream_t s) {
