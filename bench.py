@@ -445,6 +445,57 @@ def run_dmrg(ite, torch, args):
             "roofline": roof, "kernels": {KERNELS[k][0].split(" ")[0]: v for k, v in table.items()}}
 
 
+def run_sample(ite, torch, args, nsamples=1024):
+    """Product-basis samples (the METTS collapse) of the steady-state MPS:
+    nsamples per call, site by site (one FP64 GEMM of the samples' left
+    vectors with the site tensor, then one workgroup per sample)."""
+    label, W, tensors, d, w, chi, tau1 = steady_workload(args.workload, args.chi)
+    L = len(tensors)
+    ctx = ite.ite_ctx_create(0)
+    psi = ite.ite_mps_load(ctx, tensors, chi)
+    rng = np.random.default_rng(2024)
+    u = [rng.random((L, nsamples)) for _ in range(args.warmup + args.steps)]
+    for k in range(args.warmup):
+        ite.ite_mps_sample(ctx, psi, u[k])
+    torch.cuda.synchronize()
+    ite.ite_ctx_profile(ctx, True)
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        cfg = ite.ite_mps_sample(ctx, psi, u[args.warmup + k])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    table, dom = kernel_profile(ite, ctx, "fp64")
+    ite.ite_ctx_profile(ctx, False)
+    ite.ite_mps_destroy(psi)
+    ite.ite_ctx_destroy(ctx)
+    log(f"{args.steps} x {nsamples} samples in {elapsed:.3f} s; mean magnetisation {(2 * cfg - 1).mean():.4f}")
+    roof = None
+    if dom is not None:
+        roof = {"bound": dom["bound"], "achieved": dom["achieved"], "peak": dom["peak"], "unit": dom["unit"],
+                "frac": dom["frac"], "traffic": None, "kernel": dom["kernel"],
+                "avg_launch_ms": dom["avg_launch_ms"], "launches": dom["launches"]}
+    out = {"metric": "METTS collapse samples/s (product basis) at L=100 chi=1024", "value": args.steps * nsamples / elapsed,
+           "unit": "samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": label.split(", trapezoid")[0] + f"; {nsamples} product-basis samples per call"},
+           "roofline": roof, "kernels": {KERNELS[k][0].split(" ")[0]: v for k, v in table.items()}}
+    if not args.no_cpu:
+        from oracle import sampling as osmp
+        ns = 8
+        t0 = time.perf_counter()
+        osmp.sample(tensors, u[0][:, :ns])
+        dt = time.perf_counter() - t0
+        try:
+            from threadpoolctl import threadpool_info
+            threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+        except Exception:
+            threads = 1
+        out["cpu_baseline"] = {"value": ns / dt, "unit": "samples/s", "cores": int(threads), "kind": "oracle",
+                               "sample": f"{ns} samples of the same MPS by the oracle ({dt:.1f} s)"}
+    return out
+
+
 def run_split(ite, torch, args, reps=3):
     """The Jacobi bond split of one full-size block (theta 2048 x 2048, seeded
     Gaussian, left-to-right: A1 = U, A2 = S V^T, chi 1024, cutoff 0), timed,
@@ -481,7 +532,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="fp64", choices=list(PREC))
     ap.add_argument("--workload", default="heis100", choices=["heis100", "aim60", "heis64"])
-    ap.add_argument("--mode", default="step", choices=["step", "matvec", "serve", "split", "dmrg"])
+    ap.add_argument("--mode", default="step", choices=["step", "matvec", "serve", "split", "dmrg", "sample"])
     ap.add_argument("--requests", type=int, default=32, help="serve mode: number of requests")
     ap.add_argument("--workers", type=int, default=8, help="serve mode: server worker threads")
     ap.add_argument("--no-cpu", action="store_true")
@@ -499,6 +550,8 @@ def main():
         out = run_split(ite, torch, args)
     elif args.mode == "dmrg":
         out = run_dmrg(ite, torch, args)
+    elif args.mode == "sample":
+        out = run_sample(ite, torch, args)
     elif args.mode == "matvec":
         ctx = ite.ite_ctx_create(0)
         res = {}
