@@ -535,6 +535,7 @@ def main():
     ap.add_argument("--mode", default="step", choices=["step", "matvec", "serve", "split", "dmrg", "sample"])
     ap.add_argument("--requests", type=int, default=32, help="serve mode: number of requests")
     ap.add_argument("--workers", type=int, default=8, help="serve mode: server worker threads")
+    ap.add_argument("--samples", type=int, default=1024, help="sample mode: samples per call")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--chi", type=int, default=0, help="bond dimension (default: the workload's)")
     args = ap.parse_args()
@@ -551,7 +552,7 @@ def main():
     elif args.mode == "dmrg":
         out = run_dmrg(ite, torch, args)
     elif args.mode == "sample":
-        out = run_sample(ite, torch, args)
+        out = run_sample(ite, torch, args, nsamples=args.samples)
     elif args.mode == "matvec":
         ctx = ite.ite_ctx_create(0)
         res = {}
