@@ -20,7 +20,9 @@ Appendix D for the budget and the shift):
        b  = (1 + h s) P^T psi - h P^T H psi          (trapezoid)
          -- the right-hand side projected into x's basis, computed exactly
             through the mixed environments;
-       theta0 = x_j x_(j+1)  (initial guess);
+       theta0 = b on the first block of the step (the right-hand side is the
+         initial guess, Appendix B), x_j x_(j+1) on every later block
+         (or x_j x_(j+1) throughout with init_guess = "psi");
        GMRES on (1 - h s) v + h H_eff v = b;
        SVD split, A_j = U, A_(j+1) = S V^T; update the left environments.
   4. Right-to-left half sweep, mirrored (A_j = U S, A_(j+1) = V^T).
@@ -29,10 +31,15 @@ Appendix D for the budget and the shift):
 Readings where the paper is silent:
   * b is projected exactly through mixed environments rather than first formed
     as an MPS by the density-matrix MPO-MPS product;
-  * the initial guess is x = psi (for backward Euler this is b itself);
-  * "single GMRES restart with a Krylov subspace of size 10" = one cycle of at
-    most 10 Arnoldi steps; "single DMRG-style sweep" = one left-to-right plus
-    one right-to-left half sweep;
+  * the initial guess: Appendix B starts the solve from b itself.  x starts
+    as a copy of psi (its basis is the one b is projected into), and the
+    local guess of the step's first block is b projected into that basis,
+    which is what x = b would give there; later blocks start from the
+    current x_j x_(j+1), as a sweep does.  For backward Euler b = psi, so both
+    choices coincide.  init_guess = "psi" uses x_j x_(j+1) on every block;
+  * the budget of Appendix D is one GMRES cycle of at most 10 Arnoldi steps
+    per local solve and one sweep per step, a sweep being a left-to-right
+    plus a right-to-left half sweep;
   * truncation: keep the smallest k with sum_(i>=k) s_i^2 <= cutoff sum s_i^2,
     1 <= k <= chi_max; with cutoff 0 keep min(rows, cols, chi_max) values,
     zeros included; a cut inside a group of (numerically) equal non-zero
@@ -323,6 +330,7 @@ class StepOptions:
     max_cycles: int = 1
     tol_loc: float = 0.0
     nsweeps: int = 1
+    init_guess: str = "b"          # "b" (Appendix B) or "psi"
 
 
 @dataclass
@@ -367,7 +375,7 @@ def imag_step(psi, W, h: float, opts: StepOptions):
     rep = StepReport(h=h, shift=s)
     a_coef = 1.0 - h * s
 
-    def solve_block(i):
+    def solve_block(i, first):
         theta_psi = two_site(psi[i], psi[i + 1])
         ov = overlap_project(LO[i], RO[i + 2], theta_psi)
         if opts.scheme == "be":
@@ -376,16 +384,21 @@ def imag_step(psi, W, h: float, opts: StepOptions):
             b = (1.0 + h * s) * ov - h * heff_apply(LHp[i], W[i], W[i + 1], RHp[i + 2], theta_psi)
         else:
             raise ValueError(opts.scheme)
-        theta0 = two_site(x[i], x[i + 1])
+        if opts.init_guess == "b" and first:
+            theta0 = b.copy()
+        elif opts.init_guess in ("b", "psi"):
+            theta0 = two_site(x[i], x[i + 1])
+        else:
+            raise ValueError(opts.init_guess)
         op = lambda v: a_coef * v + h * heff_apply(LH[i], W[i], W[i + 1], RH[i + 2], v)
         theta, info = gmres(op, b, theta0, opts.krylov_dim, opts.max_cycles, opts.tol_loc)
         rep.matvecs += info["matvecs"]
         rep.max_res_rel = max(rep.max_res_rel, info["res_rel"])
         return theta
 
-    for _sweep in range(opts.nsweeps):
+    for sweep in range(opts.nsweeps):
         for i in range(0, L - 1):
-            theta = solve_block(i)
+            theta = solve_block(i, sweep == 0 and i == 0)
             x[i], x[i + 1], sp = split_two_site(theta, "lr", opts.cutoff, opts.chi_max, opts.tie_rel)
             rep.max_disc = max(rep.max_disc, sp["disc"])
             rep.sum_disc += sp["disc"]
@@ -394,7 +407,7 @@ def imag_step(psi, W, h: float, opts: StepOptions):
                 LHp[i + 1] = env_left_h(LHp[i], x[i], W[i], psi[i])
                 LO[i + 1] = env_left_o(LO[i], x[i], psi[i])
         for i in range(L - 2, -1, -1):
-            theta = solve_block(i)
+            theta = solve_block(i, False)
             x[i], x[i + 1], sp = split_two_site(theta, "rl", opts.cutoff, opts.chi_max, opts.tie_rel)
             rep.max_disc = max(rep.max_disc, sp["disc"])
             rep.sum_disc += sp["disc"]

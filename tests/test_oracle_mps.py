@@ -288,3 +288,63 @@ def test_paper_budget_counts_matvecs():
         expect += 1 + min(10, n)
     assert rep.matvecs <= expect
     assert rep.matvecs >= expect - 2 * (L - 1) * 2      # early invariant-space stops only
+
+
+def _krylov_minimiser(A, b, x0, m):
+    """Brute-force GMRES(m) cycle: x0 + argmin over span{r0, A r0, .., A^(m-1) r0}
+    of ||b - A x||, from the explicit Krylov matrix (no Arnoldi)."""
+    r0 = b - A @ x0
+    K = np.stack([np.linalg.matrix_power(A, j) @ r0 for j in range(m)], axis=1)
+    y = np.linalg.lstsq(A @ K, r0, rcond=None)[0]
+    return x0 + K @ y
+
+
+@pytest.mark.parametrize("init_guess", ["b", "psi"])
+@pytest.mark.parametrize("m", [1, 2])
+def test_initial_guess_on_a_single_block_by_brute_force(init_guess, m):
+    # L = 2: the sweep is the block (1, 2) solved twice (left-to-right, then
+    # right-to-left) with complete bonds, so the step is two GMRES(m) cycles on
+    # the dense 4 x 4 problem.  Appendix B starts the first from b, the "psi"
+    # reading from psi; the second starts from the first's result.
+    H = ed.heisenberg_dense(2, Jz=0.6)
+    sp = random_spinors(rng_for(4, 1), 2, 2)
+    psi = mps.product_state(sp)
+    v = mps.to_vector(psi)
+    v = v / np.linalg.norm(v)
+    h = 0.7
+    s = float(v @ H @ v)
+    A = (1 - h * s) * np.eye(4) + h * H
+    b = (1 + h * s) * v - h * (H @ v)
+    x = _krylov_minimiser(A, b, b if init_guess == "b" else v, m)
+    x = _krylov_minimiser(A, b, x, m)
+    x = x / np.linalg.norm(x)
+    opts = mps.StepOptions(scheme="trap", shift_mode="track", chi_max=4, cutoff=0.0, krylov_dim=m,
+                           init_guess=init_guess)
+    out, rep = mps.imag_step(psi, mpo.heisenberg_mpo(2, Jz=0.6), h, opts)
+    got = mps.to_vector(out)
+    assert abs(abs(got @ x) - 1) < 1e-13
+    assert abs(rep.energy - x @ H @ x) < 1e-13
+    # the two guesses give different steps with this budget
+    other = _krylov_minimiser(A, b, v if init_guess == "b" else b, m)
+    other = _krylov_minimiser(A, b, other, m)
+    other = other / np.linalg.norm(other)
+    assert abs(abs(got @ other) - 1) > 1e-11
+
+
+def test_initial_guess_is_irrelevant_for_backward_euler_and_converged_solves():
+    # backward Euler: b = psi, so both guesses are the same step (bitwise);
+    # tolerance-driven solves reach the same step from either guess
+    L = 8
+    W = mpo.heisenberg_mpo(L)
+    psi = mps.product_state(random_spinors(rng_for(4, 2), L, 2), 16, pad_full=True)
+    for kw, tol in ((dict(scheme="be"), None), (dict(scheme="trap", max_cycles=200, tol_loc=1e-13), 1e-10)):
+        outs = []
+        for g in ("b", "psi"):
+            o = mps.StepOptions(shift_mode="track", chi_max=16, cutoff=0.0, init_guess=g, **kw)
+            outs.append(mps.imag_step(psi, W, 0.4, o))
+        (a, ra), (b_, rb) = outs
+        if tol is None:
+            assert all(np.array_equal(x, y) for x, y in zip(a, b_))
+        else:
+            assert abs(ra.energy - rb.energy) < tol * abs(ra.energy)
+            assert 1 - abs(mps.overlap(a, b_)) < 1e-10
