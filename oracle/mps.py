@@ -118,10 +118,13 @@ def to_vector(A) -> np.ndarray:
 
 
 def overlap(A, B) -> float:
-    """<A|B> by transfer matrices from the left."""
+    """<A|B> by transfer matrices from the left:
+    E'[j, b] = sum E[i, a] A[i, s, j] B[a, s, b], one pairwise contraction at
+    a time."""
     E = np.ones((1, 1))
     for a, b in zip(A, B):
-        E = np.einsum("ia,isj,asb->jb", E, a, b)
+        t = np.tensordot(E, b, axes=([1], [0]))                # [i, s, b]
+        E = np.tensordot(a, t, axes=([0, 1], [0, 1]))          # [j, b]
     return float(E[0, 0])
 
 
