@@ -55,6 +55,7 @@ extern "C" {
 enum { ITE_SCHEME_TRAP = 0, ITE_SCHEME_BE = 1 };
 enum { ITE_SHIFT_FIXED = 0, ITE_SHIFT_TRACK = 1 };
 enum { ITE_PREC_FP64 = 0, ITE_PREC_FP32_IR = 1, ITE_PREC_BF16_IR = 2 };
+enum { ITE_GUESS_PSI = 0, ITE_GUESS_B = 1 };
 
 /* report flags */
 #define ITE_FLAG_BUDGET_EXHAUSTED 1  /* a local solve ended on its Krylov budget above tol_loc (normal in budget mode) */
@@ -79,7 +80,8 @@ typedef struct ite_allocator {
 
 /* Options of one implicit step.  ite_default_opts() fills the paper's budget:
  * trapezoid, shift tracking, Krylov dimension 10, one GMRES cycle, one sweep
- * (Appendix D), cutoff 1e-10 (Heisenberg chain section); FP64 products, and
+ * (Appendix D), cutoff 1e-10 (Heisenberg chain section), the right-hand side as
+ * the first local solve's initial guess (Appendix B); FP64 products, and
  * for the mixed precisions one correction (max_refine 1, tol_refine 0), which
  * spends the same single GMRES cycle on the FP64 residual of x0. */
 typedef struct ite_step_opts {
@@ -98,6 +100,10 @@ typedef struct ite_step_opts {
     double tol_refine;   /* mixed precision: FP64 relative residual target; 0: exactly max_refine
                           * corrections, no FP64 residual after the last one (the reported
                           * residual is then the inner GMRES estimate) */
+    int    init_guess;   /* ITE_GUESS_B: the step's first local solve starts from b projected
+                          * into x's basis (Appendix B uses the right-hand side as the initial
+                          * guess), later ones from the current x_j x_(j+1); ITE_GUESS_PSI:
+                          * x_j x_(j+1) throughout.  Identical for backward Euler (b = psi). */
 } ite_step_opts;
 
 /* Per-step report. */
@@ -155,9 +161,12 @@ void ite_default_opts(ite_step_opts* o);
 
 /* ---- Hamiltonian ------------------------------------------------------- */
 
-/* Load an MPO (Method: H represented as an MPO).  d[L] local dimensions,
- * w[L+1] MPO bond dimensions with w[0] = w[L] = 1, W[i] points to
- * w[i]*w[i+1]*d[i]*d[i] doubles in [wl][wr][out][in] order (host memory).
+/* Load an MPO (Method: the Hamiltonian is represented as an MPO; Appendix B:
+ * the Heisenberg and impurity MPOs are exact sums of local terms with modest
+ * bond dimension).  d[L] local dimensions, w[L+1] MPO bond dimensions with
+ * w[0] = w[L] = 1, W[i] points to w[i]*w[i+1]*d[i]*d[i] doubles in
+ * [wl][wr][out][in] order (host memory).  Every MPO within these limits runs
+ * (the two-site stage has at most 16 * 8 * 8 = 1024 inputs per column).
  * Errors: EINVAL (L < 2, d < 1, w[0] != 1, w[L] != 1, w > 16, d > 8,
  * non-finite entries, NULL pointers), ENOMEM, EDEVICE. */
 int ite_mpo_load(ite_ctx* ctx, int L, const int* d, const int* w,
@@ -166,7 +175,9 @@ int ite_mpo_destroy(ite_mpo* mpo);
 
 /* ---- states ------------------------------------------------------------ */
 
-/* Product state from L normalised real spinors (spinors[i] has d[i] entries,
+/* Product state (the initial states of the paper are product states: the
+ * Neel state of the Heisenberg chain section, the METTS product states of
+ * Appendix D) from L normalised real spinors (spinors[i] has d[i] entries,
  * host memory; each is normalised again on entry).  chi_max bounds every
  * bond of the state for its lifetime.  pad_full = 0: all bonds have dimension
  * 1.  pad_full = 1: the state is embedded in bonds of dimension
@@ -179,7 +190,8 @@ int ite_mpo_destroy(ite_mpo* mpo);
 int ite_mps_create(ite_ctx* ctx, int L, const int* d, const double* const* spinors,
                    int chi_max, int pad_full, ite_mps** out);
 
-/* Load site tensors (host memory, A[i] has chi[i]*d[i]*chi[i+1] doubles).  The
+/* Load an MPS (Method: the state is represented as an MPS) from site tensors
+ * (host memory, A[i] has chi[i]*d[i]*chi[i+1] doubles).  The
  * tensors must be right-orthonormal (each A_i as a chi[i] x (d_i chi[i+1])
  * matrix has orthonormal rows for i >= 2) with the norm on site 1 -- the form
  * every step leaves behind; this is not checked beyond finiteness.  chi[0] =
@@ -187,9 +199,11 @@ int ite_mps_create(ite_ctx* ctx, int L, const int* d, const double* const* spino
 int ite_mps_load(ite_ctx* ctx, int L, const int* d, const int* chi,
                  const double* const* A, int chi_max, ite_mps** out);
 
-/* Export bond dimensions (chi[L+1], required) and, when A is not NULL, the
- * site tensors into caller buffers A[i] of at least chi[i]*d[i]*chi[i+1]
- * doubles (call first with A = NULL to learn the sizes). */
+/* Export the MPS (Method: the state as an MPS) -- bond dimensions (chi[L+1],
+ * required) and, when A is not NULL, the site tensors into caller buffers A[i]
+ * of at least chi[i]*d[i]*chi[i+1] doubles (call first with A = NULL to learn
+ * the sizes).  Right-orthonormal with the norm on site 1.  Errors: EINVAL
+ * (NULL psi or chi), EDEVICE. */
 int ite_mps_export(ite_mps* psi, int* chi, double* const* A);
 int ite_mps_destroy(ite_mps* psi);
 
@@ -233,18 +247,22 @@ int ite_dmrg_sweeps(ite_mps* psi, const ite_mpo* H, int nsweeps, int chi_max, do
                     double tie_rel, int krylov_dim, int max_cycles, double tol, double* energy,
                     double* max_res_rel, double* max_disc, long long* matvecs);
 
-/* Product-basis samples of psi, the collapse step of a METTS chain (the
- * chains of Appendix D start from product states sampled from the ground
- * state): site by site from the left, s_i drawn from its conditional
- * probability given s_1..s_(i-1), exact because psi is right-orthonormal
- * with the centre on site 1 (as every call of this library leaves it; the
- * norm cancels).  Sample k takes the first s with P(s' <= s) > u and
- * P(s) > 0, u = uniforms[i * nsamples + k] (host array, L * nsamples values
- * in [0, 1), drawn by the caller); configs (host, nsamples * L ints) gets
- * s_i of sample k at configs[k * L + i].  Local dimensions up to 16.
- * Errors: EINVAL (nsamples < 1, null arrays, a uniform outside [0, 1), a
- * local dimension above 16), ENOMEM, EDEVICE. */
-int ite_mps_sample(ite_mps* psi, int nsamples, const double* uniforms, int* configs);
+/* Product-basis samples of psi, the collapse step of a METTS chain
+ * (Appendix D: a METTS |psi_i> is measured in a product basis, giving |j>
+ * with probability |<j|psi_i>|^2; the chains start from product states
+ * sampled from the ground state): site by site from the left, s_i drawn from
+ * its conditional probability given s_1..s_(i-1), exact because psi is
+ * right-orthonormal with the centre on site 1 (as every call of this library
+ * leaves it; the norm cancels).  Sample k takes the first s with
+ * P(s' <= s) > u and P(s) > 0, u = uniforms[i * nsamples + k] (host array,
+ * L * nsamples values in [0, 1), drawn by the caller); configs (host,
+ * nsamples * L ints) gets s_i of sample k at configs[k * L + i].  L must equal
+ * psi's length: it states the size of both host buffers.
+ * Errors: EINVAL (nsamples < 1, null arrays, L not psi's length, a uniform
+ * outside [0, 1)), ENONFINITE (a conditional distribution with a zero or
+ * non-finite total: psi is zero or not finite; configs are then meaningless),
+ * ENOMEM, EDEVICE. */
+int ite_mps_sample(ite_mps* psi, int nsamples, int L, const double* uniforms, int* configs);
 
 /* Evolve along the geometric grid 0, tau0, tau0 r, tau0 r^2, ... clamped to
  * end at tau1 (Method: logarithmic grids), starting at the first grid point
@@ -262,11 +280,20 @@ int ite_evolve_grid(ite_mps* psi, const ite_mpo* H, const double* taus, int n_ta
                     const ite_step_opts* opts, ite_step_report* per_step, int max_steps,
                     int* n_steps);
 
-/* <psi|H|psi> / <psi|psi> by a transfer contraction from the right. */
+/* Energy <psi|H|psi> / <psi|psi> (the quantity the trapezoid step's shift
+ * tracks, Appendix D: the spectrum is shifted by the energy of the new state
+ * each step; Method: the shift that puts the ground state energy at 0), by a
+ * transfer contraction from the right with the MPO.  Also caches the value as
+ * the shift of a following TRACK step.  Errors: EINVAL (NULL arguments),
+ * ESTATE (different contexts or lengths), EDEVICE. */
 int ite_measure_energy(ite_mps* psi, const ite_mpo* H, double* energy);
-/* <a|b> (same L and local dimensions, same context). */
+/* <a|b> by transfer matrices (the overlap of the Heisenberg chain section's
+ * error measure, sqrt(1 - <psi|psi_ref>) for normalised states).  Same L and
+ * local dimensions, same context; errors: EINVAL, ESTATE, EDEVICE. */
 int ite_mps_overlap(ite_mps* a, ite_mps* b, double* out);
-/* ||psi|| (the norm of the centre tensor on site 1). */
+/* ||psi||, the norm of the centre tensor on site 1 (Appendix D: the state is
+ * normalised after each step, so this is 1 after every step).  Errors:
+ * EINVAL, EDEVICE. */
 int ite_mps_norm(ite_mps* psi, double* out);
 
 /* ---- grids (host only; no device work) ---------------------------------- */

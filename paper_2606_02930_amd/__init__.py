@@ -21,6 +21,7 @@ ITE_OK, ITE_EINVAL, ITE_ENOMEM, ITE_EDEVICE, ITE_ESTATE, ITE_ENONFINITE = 0, -1,
 SCHEME_TRAP, SCHEME_BE = 0, 1
 SHIFT_FIXED, SHIFT_TRACK = 0, 1
 PREC_FP64, PREC_FP32_IR, PREC_BF16_IR = 0, 1, 2
+GUESS_PSI, GUESS_B = 0, 1
 FLAG_BUDGET_EXHAUSTED, FLAG_BREAKDOWN, FLAG_REFINE_LIMIT = 1, 2, 4
 
 
@@ -41,7 +42,7 @@ class ite_step_opts(C.Structure):
                 ("chi_max", C.c_int), ("cutoff", C.c_double), ("tie_rel", C.c_double),
                 ("krylov_dim", C.c_int), ("max_cycles", C.c_int), ("tol_loc", C.c_double),
                 ("nsweeps", C.c_int), ("precision", C.c_int), ("max_refine", C.c_int),
-                ("tol_refine", C.c_double)]
+                ("tol_refine", C.c_double), ("init_guess", C.c_int)]
 
 
 class ite_step_report(C.Structure):
@@ -111,7 +112,7 @@ _SIGNATURES = {
     "ite_evolve_grid": (_I, [_P, _P, _PD, _I, C.POINTER(ite_step_opts),
                              C.POINTER(ite_step_report), _I, _PI]),
     "ite_measure_energy": (_I, [_P, _P, _PD]),
-    "ite_mps_sample": (_I, [_P, _I, _PD, _PI]),
+    "ite_mps_sample": (_I, [_P, _I, _I, _PD, _PI]),
     "ite_dmrg_sweeps": (_I, [_P, _P, _I, _I, _D, _D, _I, _I, _D, _PD, _PD, _PD, C.POINTER(C.c_longlong)]),
     "ite_mps_overlap": (_I, [_P, _P, _PD]),
     "ite_mps_norm": (_I, [_P, _PD]),
@@ -385,9 +386,11 @@ def ite_dmrg_sweeps(ctx: Ctx, psi: int, mpo: int, nsweeps: int, chi_max: int, cu
 def ite_mps_sample(ctx: Ctx, psi: int, uniforms) -> np.ndarray:
     """uniforms [L][nsamples] in [0, 1); returns configs [nsamples][L]."""
     u = np.ascontiguousarray(uniforms, dtype=np.float64)
+    if u.ndim != 2:
+        raise ValueError("uniforms must be a [L][nsamples] array")
     L, S = u.shape
     cfg = np.zeros((S, L), dtype=np.int32)
-    _check(load_library().ite_mps_sample(psi, S, _dptr(u), cfg.ctypes.data_as(_PI)), ctx.handle)
+    _check(load_library().ite_mps_sample(psi, S, L, _dptr(u), cfg.ctypes.data_as(_PI)), ctx.handle)
     return cfg
 
 

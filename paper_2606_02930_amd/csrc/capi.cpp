@@ -116,6 +116,7 @@ void ite_default_opts(ite_step_opts* o) {
     o->precision = ITE_PREC_FP64;
     o->max_refine = 1;
     o->tol_refine = 0.0;
+    o->init_guess = ITE_GUESS_B;
 }
 
 int ite_ctx_create(int device, void* hip_stream, const ite_allocator* alloc, ite_ctx** out) {
@@ -352,10 +353,11 @@ int ite_dmrg_sweeps(ite_mps* psi, const ite_mpo* H, int nsweeps, int chi_max, do
     });
 }
 
-int ite_mps_sample(ite_mps* psi, int nsamples, const double* uniforms, int* configs) {
+int ite_mps_sample(ite_mps* psi, int nsamples, int L, const double* uniforms, int* configs) {
     if (!psi || !uniforms || !configs || nsamples < 1) return ITE_EINVAL;
     return guarded(psi->ctx, [&] {
         set_device(psi->ctx);
+        ITE_REQUIRE(L == psi->L, "mps_sample: L differs from the state's length (buffers of nsamples * L entries)");
         mps_sample(psi, nsamples, uniforms, configs);
     });
 }

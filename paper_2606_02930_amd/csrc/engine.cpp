@@ -1026,6 +1026,7 @@ void imag_step(ite_mps* psi, const ite_mpo* H, double h, const ite_step_opts& o,
     ITE_REQUIRE(o.precision >= 0 && o.precision <= 2, "imag_step: unknown precision");
     ITE_REQUIRE(o.precision == ITE_PREC_FP64 || (o.max_refine >= 1 && o.tol_refine >= 0.0),
                 "imag_step: mixed precision needs max_refine >= 1 and tol_refine >= 0");
+    ITE_REQUIRE(o.init_guess == ITE_GUESS_PSI || o.init_guess == ITE_GUESS_B, "imag_step: unknown init_guess");
     ensure_evolution(psi, H);
 
     Timer tm(c);
@@ -1071,6 +1072,9 @@ void imag_step(ite_mps* psi, const ite_mpo* H, double h, const ite_step_opts& o,
     const double acoef = 1.0 - h * s;
     int nres = 0;
     double sum_res = 0.0;
+    // Appendix B: the right-hand side is the initial guess of the solve; in
+    // x's (= psi's) basis that is b_loc itself on the step's first block
+    bool guess_b = o.init_guess == ITE_GUESS_B;
 
     auto block = [&](int i, int dir) {
         const int d1 = psi->d[i], d2 = psi->d[i + 1];
@@ -1092,7 +1096,9 @@ void imag_step(ite_mps* psi, const ite_mpo* H, double h, const ite_step_opts& o,
             HeffShape hs{Dl, Dpl, Dr, Dpr, d1, d2, H->w[i], H->w[i + 2]};
             heff_apply(c, hs, Lh, H->pair[i], Rh, tpsi, -h, 1.0, bvec, bvec, Prec::F64);
         }
-        two_site(c, Dl, d1, XD[i + 1], d2, Dr, X[i], X[i + 1], th);
+        if (guess_b) d2d(c, th, bvec, nx);
+        else two_site(c, Dl, d1, XD[i + 1], d2, Dr, X[i], X[i + 1], th);
+        guess_b = false;
         tm.close(t_rhs);
         const int t_solve = tm.open(PH_SOLVE);
         LocalOp op;
@@ -1431,7 +1437,6 @@ void mps_sample(ite_mps* psi, int S, const double* uniforms, int* configs) {
     ITE_REQUIRE(S >= 1, "mps_sample: nsamples must be >= 1");
     int Dmax = 1, dmax = 1;
     for (int i = 0; i < L; ++i) {
-        ITE_REQUIRE(psi->d[i] >= 1 && psi->d[i] <= SAMPLE_DMAX, "mps_sample: local dimension above 16");
         Dmax = std::max(Dmax, psi->D[i + 1]);
         dmax = std::max(dmax, psi->d[i]);
     }
@@ -1442,17 +1447,24 @@ void mps_sample(ite_mps* psi, int S, const double* uniforms, int* configs) {
     double* V0 = slot_t<double>(c, SL_V, (size_t)S * Dmax);
     double* V1 = slot_t<double>(c, SL_W, (size_t)S * Dmax);
     double* T = slot_t<double>(c, SL_X1, (size_t)S * dmax * Dmax);
+    double* flag = slot_t<double>(c, SL_SMALL, 512) + 400;   // any non-zero: a vanishing or non-finite norm
     h2d(c, u, uniforms, sizeof(double) * S * L);
     fill(V0, 1.0, (size_t)S, c->stream);
+    fill(flag, 0.0, 1, c->stream);
     for (int i = 0; i < L; ++i) {
         const int Dl = psi->D[i], Dr = psi->D[i + 1], d = psi->d[i];
         gemm(c, false, false, S, d * Dr, Dl, 1.0, V0, Dl, psi->A[i], (long)d * Dr, 0.0, nullptr, 0, T,
              (long)d * Dr);
-        sample_site(T, S, d, Dr, u + (size_t)i * S, V1, cfg, L, i, c->stream);
+        sample_site(T, S, d, Dr, u + (size_t)i * S, V1, cfg, L, i, flag, c->stream);
         std::swap(V0, V1);
     }
+    double* hflag = pinned(c, 64);
+    d2h(c, hflag, flag, 1);
     HIP_CHECK(hipMemcpyAsync(configs, cfg, sizeof(int) * S * L, hipMemcpyDeviceToHost, c->stream));
     sync(c);
+    if (hflag[0] != 0.0)
+        ITE_FAIL(ITE_ENONFINITE, "mps_sample: a conditional probability had a zero or non-finite total "
+                                 "(the state is zero or not finite)");
 }
 
 }  // namespace ite

@@ -264,13 +264,15 @@ __global__ void transpose_kernel(const double* __restrict__ in, int rows, int co
 // Sparse MPO stage.  A block handles one g and SC consecutive columns; the
 // I inputs of those columns are staged in LDS, then every thread produces the
 // O outputs of its column from the CSR rows (uniform across the block, so the
-// matrix entries come through scalar loads).
+// matrix entries come through scalar loads).  SC shrinks with I so that the
+// staged inputs stay within 128 KiB of LDS: SC = 128 up to 128 inputs, down
+// to 16 columns for the largest stage an MPO can have (w = 16, d = 8: 1024).
 // ---------------------------------------------------------------------------
-constexpr int SC = 128;
+constexpr size_t STAGE_LDS = 128 * 1024;
 
 // OUT: 0 writes FP64 to st.out, 1 rounds to FP32 and 2 to BF16 into st.out_lo
 // (the operand of a following low-precision contraction).
-template <int OUT>
+template <int OUT, int SC>
 __global__ __launch_bounds__(SC) void stage_kernel(Stage st) {
     extern __shared__ double xin[];   // [I][SC]
     const int g = blockIdx.y;
@@ -392,12 +394,13 @@ bool cgs2_small(const double* V, long ldv, int k1, double* w, size_t n, double* 
 // normalised left vector v; p_s = ||T[smp][s]||^2 (fixed reduction order);
 // the site takes the first s with p_0 + .. + p_s > u[smp] (p_0 + .. + p_(d-1))
 // and p_s > 0 (else the last s with p_s > 0, else 0), written to
-// cfg[smp * L + site]; vnext[smp] = T[smp][s] / ||T[smp][s]||.
+// cfg[smp * L + site]; vnext[smp] = T[smp][s] / ||T[smp][s]||.  A total that
+// is zero or not finite (a zero or non-finite state) sets *flag = 1.
 constexpr int SMP_T = 256;
 __global__ __launch_bounds__(SMP_T) void sample_site_kernel(const double* __restrict__ T, int d, int Dr,
                                                             const double* __restrict__ u,
                                                             double* __restrict__ vnext, int* __restrict__ cfg,
-                                                            int L, int site) {
+                                                            int L, int site, double* __restrict__ flag) {
     __shared__ double part[SMP_T / 64][SAMPLE_DMAX];
     __shared__ double pw[SAMPLE_DMAX];
     __shared__ int chosen;
@@ -421,6 +424,7 @@ __global__ __launch_bounds__(SMP_T) void sample_site_kernel(const double* __rest
             pw[q] = pq;
             tot += pq;
         }
+        if (!(tot > 0.0) || !isfinite(tot)) flag[0] = 1.0;
         const double thr = u[smp] * tot;
         int pick = -1;
         double cum = 0.0;
@@ -442,10 +446,11 @@ __global__ __launch_bounds__(SMP_T) void sample_site_kernel(const double* __rest
 }
 
 void sample_site(const double* T, int nsamples, int d, int Dr, const double* u, double* vnext, int* cfg, int L,
-                 int site, hipStream_t s) {
+                 int site, double* flag, hipStream_t s) {
     if (nsamples <= 0) return;
     if (d < 1 || d > SAMPLE_DMAX || Dr < 1) throw std::invalid_argument("sample_site: bad dimensions");
-    hipLaunchKernelGGL(sample_site_kernel, dim3(nsamples), dim3(SMP_T), 0, s, T, d, Dr, u, vnext, cfg, L, site);
+    hipLaunchKernelGGL(sample_site_kernel, dim3(nsamples), dim3(SMP_T), 0, s, T, d, Dr, u, vnext, cfg, L, site,
+                       flag);
     HIP_CHECK(hipGetLastError());
 }
 
@@ -497,15 +502,25 @@ void transpose(const double* in, int rows, int cols, double* out, hipStream_t s)
     HIP_CHECK(hipGetLastError());
 }
 
-void stage_f64(const Stage& st, hipStream_t s) {
-    if (st.G <= 0 || st.C <= 0 || st.O <= 0) return;
-    if (st.I > 128) ITE_FAIL(ITE_EINVAL, "MPO stage: more than 128 inputs per column");
+template <int SC>
+static void stage_launch(const Stage& st, hipStream_t s) {
     dim3 grid((st.C + SC - 1) / SC, st.G);
     const size_t lds = (size_t)st.I * SC * sizeof(double);
-    if (st.out_prec == 0) hipLaunchKernelGGL((stage_kernel<0>), grid, dim3(SC), lds, s, st);
-    else if (st.out_prec == 1) hipLaunchKernelGGL((stage_kernel<1>), grid, dim3(SC), lds, s, st);
-    else hipLaunchKernelGGL((stage_kernel<2>), grid, dim3(SC), lds, s, st);
+    if (st.out_prec == 0) hipLaunchKernelGGL((stage_kernel<0, SC>), grid, dim3(SC), lds, s, st);
+    else if (st.out_prec == 1) hipLaunchKernelGGL((stage_kernel<1, SC>), grid, dim3(SC), lds, s, st);
+    else hipLaunchKernelGGL((stage_kernel<2, SC>), grid, dim3(SC), lds, s, st);
     HIP_CHECK(hipGetLastError());
+}
+
+void stage_f64(const Stage& st, hipStream_t s) {
+    if (st.G <= 0 || st.C <= 0 || st.O <= 0) return;
+    if (st.I < 1 || (size_t)st.I * 16 * sizeof(double) > STAGE_LDS)
+        ITE_FAIL(ITE_EINVAL, "MPO stage: more than 1024 inputs per column");
+    const size_t per_col = (size_t)st.I * sizeof(double);
+    if (per_col * 128 <= STAGE_LDS) stage_launch<128>(st, s);
+    else if (per_col * 64 <= STAGE_LDS) stage_launch<64>(st, s);
+    else if (per_col * 32 <= STAGE_LDS) stage_launch<32>(st, s);
+    else stage_launch<16>(st, s);
 }
 
 }  // namespace ite

@@ -123,6 +123,21 @@ def test_heff_apply_fermionic_boundary_blocks(env):
         assert rel_err(host(y), want) < 1e-13
 
 
+@pytest.mark.parametrize("w,d", [(10, 4), (16, 8)])
+def test_heff_apply_wide_mpo(env, w, d):
+    # MPO bond dimension up to the loader's limits: the two-site stage then has
+    # w d^2 = 160 (the impurity model's allowed w = 10 at d = 4) and 1024 inputs
+    torch, ctx = env
+    rng = np.random.default_rng(w * d)
+    W1 = rng.standard_normal((w, w, d, d))
+    W2 = rng.standard_normal((w, w, d, d))
+    Lm, Rm, th = _heff_case(rng, 9, 7, 11, 6, d, W1, W2)
+    want = omps.heff_apply(Lm, W1, W2, Rm, th)
+    y = torch.zeros((9, d, d, 11), dtype=torch.float64, device="cuda")
+    ite.ite_debug_heff_apply(ctx, dev(torch, Lm), W1, W2, dev(torch, Rm), dev(torch, th), 0.0, 1.0, y)
+    assert rel_err(host(y), want) < 1e-13
+
+
 def test_heff_apply_full_block_shape(env):
     # the L=100, chi=1024 Heisenberg block: L, R [1024][5][1024], theta [1024][2][2][1024]
     torch, ctx = env
@@ -328,6 +343,28 @@ def test_local_solve_paper_budget_longer_vectors(env, D):
                                         dev(torch, x0), x, krylov_dim=10, max_cycles=1, tol=0.0)
     assert mv == info["matvecs"] == 11
     assert rel_err(host(x), want) < 1e-10
+
+
+def test_local_solve_paper_budget_full_block(env):
+    # the L=100, chi=1024 block: n = 4 194 304 (the reductions run on their
+    # capped grid of 1024 workgroups), paper budget, against the oracle's GMRES
+    torch, ctx = env
+    D = 1024
+    rng = np.random.default_rng(1024)
+    W = ompo.heisenberg_mpo(4)
+    Lm = rng.standard_normal((D, 5, D)) / np.sqrt(D)
+    Rm = rng.standard_normal((D, 5, D)) / np.sqrt(D)
+    b = rng.standard_normal((D, 2, 2, D))
+    x0 = b + 0.1 * rng.standard_normal((D, 2, 2, D))
+    alpha, beta = 2.5, 0.3
+    op = lambda v: alpha * v + beta * omps.heff_apply(Lm, W[1], W[2], Rm, v)
+    want, info = omps.gmres(op, b, x0, 10, 1, 0.0)
+    x = torch.zeros(b.shape, dtype=torch.float64, device="cuda")
+    mv, res = ite.ite_debug_local_solve(ctx, dev(torch, Lm), W[1], W[2], dev(torch, Rm), alpha, beta,
+                                        dev(torch, b), dev(torch, x0), x, krylov_dim=10, max_cycles=1, tol=0.0)
+    assert mv == info["matvecs"] == 11
+    assert rel_err(host(x), want) < 1e-10
+    assert abs(res - info["res_rel"]) <= 1e-8 * info["res_rel"]
 
 
 @pytest.mark.parametrize("prec,bound", [(1, 2e-6), (2, 3e-2)])

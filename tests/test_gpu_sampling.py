@@ -71,5 +71,18 @@ def test_basis_state_and_errors(ctx):
         with pytest.raises(ite.IteError) as e:
             ite.ite_mps_sample(ctx, psi, bad)
         assert e.value.code == ite.ITE_EINVAL
+        # uniforms of the wrong orientation: L (rows) differs from the state's
+        with pytest.raises(ite.IteError) as e:
+            ite.ite_mps_sample(ctx, psi, rng_for(82).random((64, 5)))
+        assert e.value.code == ite.ITE_EINVAL
+        assert "length" in ite.ite_last_error(ctx)
     finally:
         ite.ite_mps_destroy(psi)
+    # a zero state has no distribution to sample
+    zero = ite.ite_mps_load(ctx, [np.zeros((1, 2, 1))] * 4, 4)
+    try:
+        with pytest.raises(ite.IteError) as e:
+            ite.ite_mps_sample(ctx, zero, rng_for(83).random((4, 8)))
+        assert e.value.code == ite.ITE_ENONFINITE
+    finally:
+        ite.ite_mps_destroy(zero)

@@ -34,7 +34,8 @@ def ctx():
 def _opts(**kw):
     o = ite.ite_default_opts()
     conv = {"scheme": {"trap": ite.SCHEME_TRAP, "be": ite.SCHEME_BE},
-            "shift_mode": {"fixed": ite.SHIFT_FIXED, "track": ite.SHIFT_TRACK}}
+            "shift_mode": {"fixed": ite.SHIFT_FIXED, "track": ite.SHIFT_TRACK},
+            "init_guess": {"b": ite.GUESS_B, "psi": ite.GUESS_PSI}}
     for k, v in kw.items():
         setattr(o, k, conv[k][v] if k in conv and isinstance(v, str) else v)
     return o
@@ -100,12 +101,15 @@ def test_heis10_trapezoid_matches_oracle_and_ed(ctx):
     assert 1 - abs(mps_vector(out) @ mps_vector(o_out)) <= 1e-8
 
 
-def test_paper_budget_with_truncation_matches_oracle(ctx):
-    # the paper's budget: Krylov 10, one cycle, one sweep; cutoff 1e-10, chi <= 16
+@pytest.mark.parametrize("init_guess", ["b", "psi"])
+def test_paper_budget_with_truncation_matches_oracle(ctx, init_guess):
+    # the paper's budget: Krylov 10, one cycle, one sweep; cutoff 1e-10, chi <= 16;
+    # the first local solve starts from b (Appendix B) or from psi
     L, chi = 14, 16
     sp = random_spinors(rng_for(1), L, 2)
     grid = ed.loggrid(0.01, 20.0, 1.3)
-    kw = dict(scheme="trap", shift_mode="track", cutoff=1e-10, krylov_dim=10, max_cycles=1, tol_loc=0.0)
+    kw = dict(scheme="trap", shift_mode="track", cutoff=1e-10, krylov_dim=10, max_cycles=1, tol_loc=0.0,
+              init_guess=init_guess)
     reps, out, o_reps, o_out = _run_both(ctx, L, 2, hamiltonians.heisenberg(L), ompo.heisenberg_mpo(L), sp, chi,
                                          False, grid, **kw)
     for r, orr in zip(reps, o_reps):
@@ -114,6 +118,29 @@ def test_paper_budget_with_truncation_matches_oracle(ctx):
         assert r["matvecs_fp64"] == orr.matvecs
     ov = mps_overlap(out, o_out)
     assert 1 - abs(ov) <= 1e-8
+
+
+@pytest.mark.parametrize("L,chi,cutoff", [(16, 256, 0.0), (16, 256, 1e-10), (18, 512, 0.0)])
+def test_full_size_splits_inside_steps_match_oracle(ctx, L, chi, cutoff):
+    # Complete bonds up to 256 / 512: the central blocks split 256 x 256 and
+    # 512 x 512 matrices, so the steps run the Householder preconditioning,
+    # the multi-pair Jacobi rounds (fused rotation + Gram, single-precision
+    # pair sweeps far from convergence, the X X^T convergence check) and the
+    # bond bookkeeping around them; paper budget, three trapezoid steps on the
+    # 0.01 -> 1000, ratio 1.3 grid
+    sp = random_spinors(rng_for(1, 30 + L), L, 2)
+    grid = ed.loggrid(0.01, 1000.0, 1.3)[:4]
+    kw = dict(scheme="trap", shift_mode="track", cutoff=cutoff, krylov_dim=10, max_cycles=1, tol_loc=0.0)
+    reps, out, o_reps, o_out = _run_both(ctx, L, 2, hamiltonians.heisenberg(L), ompo.heisenberg_mpo(L), sp, chi,
+                                         True, grid, **kw)
+    assert len(reps) == 3
+    if cutoff == 0.0:
+        assert max(omps.bond_dims(o_out)) == chi
+    for r, orr in zip(reps, o_reps):
+        assert r["max_chi"] == orr.max_chi
+        assert abs(r["energy"] - orr.energy) <= 1e-10 * abs(orr.energy)
+        assert abs(r["norm_before"] - orr.norm_before) <= 1e-10 * orr.norm_before
+    assert 1 - abs(mps_overlap(out, o_out)) <= 1e-8
 
 
 def test_anderson_impurity_matches_oracle(ctx):

@@ -39,6 +39,7 @@ def test_version_and_default_options():
     o = ite.ite_default_opts()
     assert o.scheme == ite.SCHEME_TRAP and o.krylov_dim == 10 and o.max_cycles == 1 and o.nsweeps == 1
     assert o.shift_mode == ite.SHIFT_TRACK and o.cutoff == 1e-10
+    assert o.init_guess == ite.GUESS_B      # Appendix B: b is the initial guess
 
 
 @pytest.mark.parametrize("args", [(0.01, 100.0, 1.5), (0.01, 1000.0, 1.3), (0.01, 1e4, 1.3), (0.3, 0.5, 7.0)])
@@ -76,6 +77,10 @@ def test_null_handles_are_rejected():
     h = ctypes.c_void_p()
     assert lib.ite_ctx_create(-1, None, None, ctypes.byref(h)) == ite.ITE_EINVAL
     assert lib.ite_last_error(None) == b"NULL context"
+    assert lib.ite_mps_sample(None, 4, 3, None, None) == ite.ITE_EINVAL
+    # the binding refuses uniforms that are not a [L][nsamples] table before any call
+    with pytest.raises(ValueError):
+        ite.ite_mps_sample(None, 0, np.zeros(5))
 
 
 @pytest.mark.parametrize("L", [2, 3, 6])
