@@ -82,8 +82,9 @@ typedef struct ite_allocator {
  * trapezoid, shift tracking, Krylov dimension 10, one GMRES cycle, one sweep
  * (Appendix D), cutoff 1e-10 (Heisenberg chain section), the right-hand side as
  * the first local solve's initial guess (Appendix B); FP64 products, and
- * for the mixed precisions one correction (max_refine 1, tol_refine 0), which
- * spends the same single GMRES cycle on the FP64 residual of x0. */
+ * for the mixed precisions max_refine 0 (one correction for FP32-IR, which
+ * spends the same single GMRES cycle on the FP64 residual of x0, two for
+ * BF16-IR) with tol_refine 0. */
 typedef struct ite_step_opts {
     int    scheme;       /* ITE_SCHEME_TRAP or ITE_SCHEME_BE */
     int    shift_mode;   /* ITE_SHIFT_FIXED (use `shift`) or ITE_SHIFT_TRACK (s = energy of psi) */
@@ -96,7 +97,10 @@ typedef struct ite_step_opts {
     double tol_loc;      /* relative residual target; 0 = fixed budget (no early exit) */
     int    nsweeps;      /* full (left-right-left) sweeps per step, >= 1 */
     int    precision;    /* ITE_PREC_*: inner matvec precision of the local solves */
-    int    max_refine;   /* mixed precision: refinement rounds per local solve */
+    int    max_refine;   /* mixed precision: refinement rounds (corrections) per local solve;
+                          * 0 = the cheapest count that keeps the fixed-budget step within
+                          * 1e-8 relative energy of the FP64 step: 1 for FP32-IR, 2 for
+                          * BF16-IR */
     double tol_refine;   /* mixed precision: FP64 relative residual target; 0: exactly max_refine
                           * corrections, no FP64 residual after the last one (the reported
                           * residual is then the inner GMRES estimate) */

@@ -114,7 +114,7 @@ void ite_default_opts(ite_step_opts* o) {
     o->tol_loc = 0.0;
     o->nsweeps = 1;
     o->precision = ITE_PREC_FP64;
-    o->max_refine = 1;
+    o->max_refine = 0;   // per precision: 1 correction for FP32-IR, 2 for BF16-IR
     o->tol_refine = 0.0;
     o->init_guess = ITE_GUESS_B;
 }

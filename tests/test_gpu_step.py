@@ -268,6 +268,39 @@ def test_boundary_error_paths(ctx):
 
 
 @pytest.mark.parametrize("prec", [ite.PREC_FP32_IR, ite.PREC_BF16_IR])
+@pytest.mark.parametrize("L,chi,cutoff,pad", [(24, 32, 1e-10, False), (12, 64, 0.0, True), (32, 64, 0.0, False)])
+def test_mixed_precision_default_budget_within_1e8_of_fp64(ctx, prec, L, chi, cutoff, pad):
+    # The default mixed-precision configuration at the paper's budget (one
+    # GMRES cycle of 10 low-precision products per correction; one correction
+    # for FP32 operands, two for BF16) against the FP64 path: every step's
+    # energy within 1e-8 relative; the FP64 path itself against the oracle
+    sp = random_spinors(rng_for(5, L), L, 2)
+    Wp = hamiltonians.heisenberg(L)
+    runs = {}
+    for p in (ite.PREC_FP64, prec):
+        psi = ite.ite_mps_create(ctx, sp, chi, pad_full=pad)
+        H = ite.ite_mpo_load(ctx, Wp)
+        try:
+            runs[p] = ite.ite_evolve_loggrid(ctx, psi, H, 0.01, 20.0, 1.3, _opts(chi_max=chi, cutoff=cutoff,
+                                                                                  precision=p))
+        finally:
+            ite.ite_mps_destroy(psi)
+            ite.ite_mpo_destroy(H)
+    e64 = np.array([r["energy"] for r in runs[ite.PREC_FP64]])
+    elo = np.array([r["energy"] for r in runs[prec]])
+    dev = np.abs(elo - e64) / np.abs(e64)
+    print(f"prec {prec} L={L} chi={chi} cutoff={cutoff}: largest per-step relative energy deviation "
+          f"from FP64 {dev.max():.2e} (final {dev[-1]:.2e}) over {len(dev)} steps")
+    assert all(r["matvecs_lo"] > 0 for r in runs[prec])
+    assert dev.max() <= 1e-8
+    if L <= 24:
+        o_out, o_reps = omps.evolve_loggrid(omps.product_state(sp, chi, pad_full=pad), ompo.heisenberg_mpo(L),
+                                            0.01, 20.0, 1.3, _oracle_opts(chi_max=chi, cutoff=cutoff))
+        for r, orr in zip(runs[ite.PREC_FP64], o_reps):
+            assert abs(r["energy"] - orr.energy) <= 1e-10 * abs(orr.energy)
+
+
+@pytest.mark.parametrize("prec", [ite.PREC_FP32_IR, ite.PREC_BF16_IR])
 def test_mixed_precision_step_matches_oracle(ctx, prec):
     # FP32 / BF16 inner GMRES refined against FP64 residuals to the same local
     # target (1e-12) as the FP64 oracle: energies agree to 1e-10 relative
