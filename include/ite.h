@@ -268,6 +268,24 @@ int ite_dmrg_sweeps(ite_mps* psi, const ite_mpo* H, int nsweeps, int chi_max, do
  * ENOMEM, EDEVICE. */
 int ite_mps_sample(ite_mps* psi, int nsamples, int L, const double* uniforms, int* configs);
 
+/* ite_mps_sample for callers that cannot allocate device or pinned host
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation): the same samples, bit for bit, from DEVICE buffers --
+ * uniforms (L * nsamples doubles, layout as ite_mps_sample) and configs
+ * (nsamples * L ints) -- with every working vector in a fixed scratch array of
+ * 64 MiB that the library reserves on each GPU it runs on until the process
+ * ends.  The call allocates nothing; it needs
+ * 256 + 8 * nsamples * (2 + d_max) * D_max bytes of that scratch (D_max the
+ * largest bond of psi, d_max the largest local dimension), e.g. up to 2730
+ * samples at D_max = 1024, d = 2.  Calls on one GPU share the array and keep
+ * the last call's contents: calls that overlap in time on one GPU (from two
+ * threads or two streams) race and give wrong samples.  Returns after configs
+ * is written (synchronous on psi's stream).  Errors: EINVAL (NULL pointers,
+ * nsamples < 1, L not psi's length, the scratch need above 64 MiB -- the
+ * message states both sizes --, a uniform outside [0, 1)), ENONFINITE (as
+ * ite_mps_sample), EDEVICE. */
+int ite_mps_sample_noalloc(ite_mps* psi, int nsamples, int L, const double* uniforms, int* configs);
+
 /* Evolve along the geometric grid 0, tau0, tau0 r, tau0 r^2, ... clamped to
  * end at tau1 (Method: logarithmic grids), starting at the first grid point
  * after psi's current tau.  per_step (nullable) receives up to max_steps

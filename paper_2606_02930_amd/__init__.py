@@ -113,6 +113,7 @@ _SIGNATURES = {
                              C.POINTER(ite_step_report), _I, _PI]),
     "ite_measure_energy": (_I, [_P, _P, _PD]),
     "ite_mps_sample": (_I, [_P, _I, _I, _PD, _PI]),
+    "ite_mps_sample_noalloc": (_I, [_P, _I, _I, _P, _P]),
     "ite_dmrg_sweeps": (_I, [_P, _P, _I, _I, _D, _D, _I, _I, _D, _PD, _PD, _PD, C.POINTER(C.c_longlong)]),
     "ite_mps_overlap": (_I, [_P, _P, _PD]),
     "ite_mps_norm": (_I, [_P, _PD]),
@@ -392,6 +393,22 @@ def ite_mps_sample(ctx: Ctx, psi: int, uniforms) -> np.ndarray:
     cfg = np.zeros((S, L), dtype=np.int32)
     _check(load_library().ite_mps_sample(psi, S, L, _dptr(u), cfg.ctypes.data_as(_PI)), ctx.handle)
     return cfg
+
+
+def ite_mps_sample_noalloc(ctx: Ctx, psi: int, uniforms, configs) -> None:
+    """uniforms: device tensor [L][nsamples] (float64); configs: device tensor
+    [nsamples][L] (int32), written in place.  No allocation in the library."""
+    if uniforms.dim() != 2 or configs.dim() != 2:
+        raise ValueError("uniforms [L][nsamples] and configs [nsamples][L] must be 2-d")
+    L, S = uniforms.shape
+    if tuple(configs.shape) != (S, L):
+        raise ValueError("configs must be [nsamples][L]")
+    if not (uniforms.is_contiguous() and configs.is_contiguous()):
+        raise ValueError("uniforms and configs must be contiguous")
+    import torch
+    if uniforms.dtype != torch.float64 or configs.dtype != torch.int32:
+        raise ValueError("uniforms must be float64 and configs int32")
+    _check(load_library().ite_mps_sample_noalloc(psi, S, L, _tp(uniforms), _tp(configs)), ctx.handle)
 
 
 def ite_measure_energy(ctx: Ctx, psi: int, mpo: int) -> float:

@@ -133,6 +133,9 @@ int ite_ctx_create(int device, void* hip_stream, const ite_allocator* alloc, ite
         c->has_alloc = true;
     }
     if (hipSetDevice(device) != hipSuccess) return ITE_EDEVICE;
+    // this device's copy of the fixed scratch of ite_mps_sample_noalloc
+    const int rc = guarded(c.get(), [&] { noalloc_init(device); });
+    if (rc != ITE_OK) return rc;
     *out = c.release();
     return ITE_OK;
 }
@@ -359,6 +362,16 @@ int ite_mps_sample(ite_mps* psi, int nsamples, int L, const double* uniforms, in
         set_device(psi->ctx);
         ITE_REQUIRE(L == psi->L, "mps_sample: L differs from the state's length (buffers of nsamples * L entries)");
         mps_sample(psi, nsamples, uniforms, configs);
+    });
+}
+
+int ite_mps_sample_noalloc(ite_mps* psi, int nsamples, int L, const double* uniforms, int* configs) {
+    if (!psi || !uniforms || !configs || nsamples < 1) return ITE_EINVAL;
+    return guarded(psi->ctx, [&] {
+        set_device(psi->ctx);
+        ITE_REQUIRE(L == psi->L, "mps_sample_noalloc: L differs from the state's length");
+        mps_sample_noalloc(psi, nsamples, uniforms, configs, noalloc_scratch(psi->ctx->device),
+                           noalloc_scratch_doubles());
     });
 }
 

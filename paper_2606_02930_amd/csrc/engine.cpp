@@ -1436,26 +1436,15 @@ void dmrg_sweeps(ite_mps* psi, const ite_mpo* H, const DmrgOpts& o, DmrgReport* 
 // V [S][D_i] the samples' normalised left vectors), then one workgroup per
 // sample picks s_i from the conditional probabilities ||T[smp][s]||^2 (exact
 // because the sites right of i are right-orthonormal) and forms the next V.
-void mps_sample(ite_mps* psi, int S, const double* uniforms, int* configs) {
+// Device buffers: u [L][S] uniforms, cfg [S][L] output, V0 and V1
+// [S][D_max], T [S][d_max][D_max], flag [2] (zeroed here; [0] set for a zero
+// or non-finite total, [1] for a uniform outside [0, 1)).
+void mps_sample_core(ite_mps* psi, int S, const double* u, int* cfg, double* V0, double* V1, double* T,
+                     double* flag) {
     ite_ctx* c = psi->ctx;
     const int L = psi->L;
-    ITE_REQUIRE(S >= 1, "mps_sample: nsamples must be >= 1");
-    int Dmax = 1, dmax = 1;
-    for (int i = 0; i < L; ++i) {
-        Dmax = std::max(Dmax, psi->D[i + 1]);
-        dmax = std::max(dmax, psi->d[i]);
-    }
-    for (size_t k = 0; k < (size_t)S * L; ++k)
-        ITE_REQUIRE(uniforms[k] >= 0.0 && uniforms[k] < 1.0, "mps_sample: uniforms must lie in [0, 1)");
-    double* u = slot_t<double>(c, SL_PART, (size_t)S * L);
-    int* cfg = slot_t<int>(c, SL_PERM, (size_t)S * L);
-    double* V0 = slot_t<double>(c, SL_V, (size_t)S * Dmax);
-    double* V1 = slot_t<double>(c, SL_W, (size_t)S * Dmax);
-    double* T = slot_t<double>(c, SL_X1, (size_t)S * dmax * Dmax);
-    double* flag = slot_t<double>(c, SL_SMALL, 512) + 400;   // any non-zero: a vanishing or non-finite norm
-    h2d(c, u, uniforms, sizeof(double) * S * L);
     fill(V0, 1.0, (size_t)S, c->stream);
-    fill(flag, 0.0, 1, c->stream);
+    fill(flag, 0.0, 2, c->stream);
     for (int i = 0; i < L; ++i) {
         const int Dl = psi->D[i], Dr = psi->D[i + 1], d = psi->d[i];
         gemm(c, false, false, S, d * Dr, Dl, 1.0, V0, Dl, psi->A[i], (long)d * Dr, 0.0, nullptr, 0, T,
@@ -1463,13 +1452,68 @@ void mps_sample(ite_mps* psi, int S, const double* uniforms, int* configs) {
         sample_site(T, S, d, Dr, u + (size_t)i * S, V1, cfg, L, i, flag, c->stream);
         std::swap(V0, V1);
     }
-    double* hflag = pinned(c, 64);
-    d2h(c, hflag, flag, 1);
-    HIP_CHECK(hipMemcpyAsync(configs, cfg, sizeof(int) * S * L, hipMemcpyDeviceToHost, c->stream));
-    sync(c);
-    if (hflag[0] != 0.0)
+}
+
+size_t mps_sample_scratch_doubles(const ite_mps* psi, int S) {
+    int Dmax = 1, dmax = 1;
+    for (int i = 0; i < psi->L; ++i) {
+        Dmax = std::max(Dmax, psi->D[i + 1]);
+        dmax = std::max(dmax, psi->d[i]);
+    }
+    return 32 + (size_t)S * Dmax * (2 + dmax);
+}
+
+static void sample_flags(double f0, double f1) {
+    if (f1 != 0.0) ITE_FAIL(ITE_EINVAL, "mps_sample: uniforms must lie in [0, 1)");
+    if (f0 != 0.0)
         ITE_FAIL(ITE_ENONFINITE, "mps_sample: a conditional probability had a zero or non-finite total "
                                  "(the state is zero or not finite)");
+}
+
+void mps_sample(ite_mps* psi, int S, const double* uniforms, int* configs) {
+    ite_ctx* c = psi->ctx;
+    const int L = psi->L;
+    ITE_REQUIRE(S >= 1, "mps_sample: nsamples must be >= 1");
+    for (size_t k = 0; k < (size_t)S * L; ++k)
+        ITE_REQUIRE(uniforms[k] >= 0.0 && uniforms[k] < 1.0, "mps_sample: uniforms must lie in [0, 1)");
+    const size_t nw = mps_sample_scratch_doubles(psi, S);
+    double* ws = slot_t<double>(c, SL_X1, nw);
+    double* u = slot_t<double>(c, SL_PART, (size_t)S * L);
+    int* cfg = slot_t<int>(c, SL_PERM, (size_t)S * L);
+    double* flag = ws;
+    int Dmax = 1;
+    for (int i = 0; i < L; ++i) Dmax = std::max(Dmax, psi->D[i + 1]);
+    double* V0 = ws + 32;
+    double* V1 = V0 + (size_t)S * Dmax;
+    double* T = V1 + (size_t)S * Dmax;
+    h2d(c, u, uniforms, sizeof(double) * S * L);
+    mps_sample_core(psi, S, u, cfg, V0, V1, T, flag);
+    double* hflag = pinned(c, 64);
+    d2h(c, hflag, flag, 2);
+    HIP_CHECK(hipMemcpyAsync(configs, cfg, sizeof(int) * S * L, hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+    sample_flags(hflag[0], hflag[1]);
+}
+
+void mps_sample_noalloc(ite_mps* psi, int S, const double* u_dev, int* cfg_dev, double* scratch, size_t scratch_doubles) {
+    ite_ctx* c = psi->ctx;
+    const int L = psi->L;
+    ITE_REQUIRE(S >= 1, "mps_sample_noalloc: nsamples must be >= 1");
+    const size_t nw = mps_sample_scratch_doubles(psi, S);
+    if (nw > scratch_doubles)
+        ITE_FAIL(ITE_EINVAL, "mps_sample_noalloc: nsamples * (2 + d_max) * D_max * 8 + 256 = " +
+                                 std::to_string(nw * 8) + " bytes exceeds the fixed scratch of " +
+                                 std::to_string(scratch_doubles * 8) + " bytes");
+    int Dmax = 1;
+    for (int i = 0; i < L; ++i) Dmax = std::max(Dmax, psi->D[i + 1]);
+    double* V0 = scratch + 32;
+    double* V1 = V0 + (size_t)S * Dmax;
+    double* T = V1 + (size_t)S * Dmax;
+    mps_sample_core(psi, S, u_dev, cfg_dev, V0, V1, T, scratch);
+    double hflag[2] = {0.0, 0.0};
+    HIP_CHECK(hipMemcpyAsync(hflag, scratch, sizeof(hflag), hipMemcpyDeviceToHost, c->stream));
+    sync(c);
+    sample_flags(hflag[0], hflag[1]);
 }
 
 }  // namespace ite

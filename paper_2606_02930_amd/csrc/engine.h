@@ -190,5 +190,15 @@ struct DmrgReport {
 void dmrg_sweeps(ite_mps* psi, const ite_mpo* H, const DmrgOpts& o, DmrgReport* rep);
 // Product-basis samples of psi (see ite_mps_sample); host arrays.
 void mps_sample(ite_mps* psi, int nsamples, const double* uniforms, int* configs);
+// Doubles of working memory mps_sample needs for nsamples samples of psi.
+size_t mps_sample_scratch_doubles(const ite_mps* psi, int nsamples);
+// The same samples from device uniforms into device configs, with the working
+// vectors in the caller-given scratch (scratch_doubles long): no allocation.
+void mps_sample_noalloc(ite_mps* psi, int nsamples, const double* u_dev, int* cfg_dev, double* scratch,
+                        size_t scratch_doubles);
+// Fixed per-device scratch of the no-allocation entry point (noalloc.hip).
+void noalloc_init(int device);
+double* noalloc_scratch(int device);
+size_t noalloc_scratch_doubles();
 
 }  // namespace ite

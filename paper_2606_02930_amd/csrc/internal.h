@@ -104,8 +104,8 @@ void scale_inv(const double* x, const double* den, double* out, size_t n, hipStr
 // One site of product-basis sampling (see sample_site_kernel): T [nsamples][d][Dr],
 // u [nsamples], vnext [nsamples][Dr], cfg [nsamples][L]; d <= SAMPLE_DMAX.
 constexpr int SAMPLE_DMAX = 16;
-// flag (device): set to 1 when a sample's total probability is zero or not
-// finite.
+// flag (device, 2 values): flag[0] set to 1 when a sample's total probability
+// is zero or not finite, flag[1] when its uniform is outside [0, 1).
 void sample_site(const double* T, int nsamples, int d, int Dr, const double* u, double* vnext, int* cfg, int L,
                  int site, double* flag, hipStream_t s);
 // Both classical Gram-Schmidt passes of one Arnoldi step in a single

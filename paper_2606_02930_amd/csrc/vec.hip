@@ -395,7 +395,8 @@ bool cgs2_small(const double* V, long ldv, int k1, double* w, size_t n, double* 
 // the site takes the first s with p_0 + .. + p_s > u[smp] (p_0 + .. + p_(d-1))
 // and p_s > 0 (else the last s with p_s > 0, else 0), written to
 // cfg[smp * L + site]; vnext[smp] = T[smp][s] / ||T[smp][s]||.  A total that
-// is zero or not finite (a zero or non-finite state) sets *flag = 1.
+// is zero or not finite (a zero or non-finite state) sets flag[0] = 1, a
+// uniform outside [0, 1) flag[1] = 1.
 constexpr int SMP_T = 256;
 __global__ __launch_bounds__(SMP_T) void sample_site_kernel(const double* __restrict__ T, int d, int Dr,
                                                             const double* __restrict__ u,
@@ -425,6 +426,7 @@ __global__ __launch_bounds__(SMP_T) void sample_site_kernel(const double* __rest
             tot += pq;
         }
         if (!(tot > 0.0) || !isfinite(tot)) flag[0] = 1.0;
+        if (!(u[smp] >= 0.0 && u[smp] < 1.0)) flag[1] = 1.0;
         const double thr = u[smp] * tot;
         int pick = -1;
         double cum = 0.0;
