@@ -28,6 +28,9 @@ Logarithmic Grids" (Zima, Stoudenmire, White, Parcollet, Kaye) by eye:
   split, the local problem diagonalised exactly (the ground state that seeds
   the METTS chains and gives the zero-temperature double occupancy,
   Appendix D).
+* ``oracle.metts`` -- one-site expectation values and METTS chains
+  (evolution, measurement, collapse; Appendix D), with their exact dense
+  counterparts used to pin them.
 
 Parity status of every function is stated in its module header; the pins live
 in ``tests/test_oracle_*.py``.
