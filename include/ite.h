@@ -268,6 +268,36 @@ int ite_dmrg_sweeps(ite_mps* psi, const ite_mpo* H, int nsweeps, int chi_max, do
  * ENOMEM, EDEVICE. */
 int ite_mps_sample(ite_mps* psi, int nsamples, int L, const double* uniforms, int* configs);
 
+/* <psi|O|psi> / <psi|psi> for a one-site operator O acting on `site`
+ * (0-based), op[d_site][d_site] (host, row-major, (out, in)): the impurity
+ * double occupancy n_(d,up) n_(d,dn) of Appendix D is diag(0, 0, 0, 1) on the
+ * impurity site in the local basis |0>, |up>, |dn>, |up dn>.  psi must be
+ * right-orthonormal right of the site (every state this library leaves is:
+ * centre on site 1).  Errors: EINVAL (NULL pointers, site out of range,
+ * non-finite entries, zero state), EDEVICE. */
+int ite_mps_expect_site(ite_mps* psi, int site, const double* op, double* out);
+
+/* A METTS chain (Appendix D): from the product state `start` (L local
+ * indices; the paper seeds it with a sample of the ground state, e.g. from
+ * ite_dmrg_sweeps and ite_mps_sample), nsamples times: |psi_k> ~
+ * exp(-beta H / 2)|config_k> by ite_evolve_loggrid on the geometric grid
+ * tau0 -> beta / 2 with `ratio` and `opts` (MPS created with chi_max, unit
+ * bonds), the energy of |psi_k> (the last step's) into energies[k], <psi_k|O|psi_k>
+ * for the one-site operator (site, op) as ite_mps_expect_site into
+ * observables[k], config_k into configs[k * L .. k * L + L), then the
+ * collapse to the next configuration by ite_mps_sample with the L uniforms
+ * uniforms[k * L .. k * L + L) (host, in [0, 1)).  The thermal average of O is
+ * the plain mean of observables.  The collapse in the computational basis
+ * keeps every conserved quantity of the start state (particle number and S^z
+ * for the impurity model), so the chain samples the canonical ensemble of the
+ * start state's sector.  Host arrays; the chain runs on H's context.
+ * Errors: EINVAL (NULL pointers, nsamples < 1, L not H's length, 0 < tau0 <
+ * beta / 2 violated, ratio <= 1, site or start out of range), and those of
+ * the calls it makes (the chain stops at the failing element). */
+int ite_metts_chain(const ite_mpo* H, const int* start, int chi_max, double beta, double tau0, double ratio,
+                    const ite_step_opts* opts, int site, const double* op, int nsamples, int L,
+                    const double* uniforms, int* configs, double* energies, double* observables);
+
 /* ite_mps_sample for callers that cannot allocate device or pinned host
  * memory (code under HIP graph capture, tight serving loops, harnesses that
  * forbid allocation): the same samples, bit for bit, from DEVICE buffers --

@@ -114,6 +114,9 @@ _SIGNATURES = {
     "ite_measure_energy": (_I, [_P, _P, _PD]),
     "ite_mps_sample": (_I, [_P, _I, _I, _PD, _PI]),
     "ite_mps_sample_noalloc": (_I, [_P, _I, _I, _P, _P]),
+    "ite_mps_expect_site": (_I, [_P, _I, _PD, _PD]),
+    "ite_metts_chain": (_I, [_P, _PI, _I, _D, _D, _D, C.POINTER(ite_step_opts), _I, _PD, _I, _I, _PD, _PI, _PD,
+                             _PD]),
     "ite_dmrg_sweeps": (_I, [_P, _P, _I, _I, _D, _D, _I, _I, _D, _PD, _PD, _PD, C.POINTER(C.c_longlong)]),
     "ite_mps_overlap": (_I, [_P, _P, _PD]),
     "ite_mps_norm": (_I, [_P, _PD]),
@@ -393,6 +396,35 @@ def ite_mps_sample(ctx: Ctx, psi: int, uniforms) -> np.ndarray:
     cfg = np.zeros((S, L), dtype=np.int32)
     _check(load_library().ite_mps_sample(psi, S, L, _dptr(u), cfg.ctypes.data_as(_PI)), ctx.handle)
     return cfg
+
+
+def ite_mps_expect_site(ctx: Ctx, psi: int, site: int, op) -> float:
+    """<psi|O_site|psi> / <psi|psi>; op [d][d] (out, in)."""
+    o = np.ascontiguousarray(op, dtype=np.float64)
+    out = C.c_double()
+    _check(load_library().ite_mps_expect_site(psi, int(site), _dptr(o), C.byref(out)), ctx.handle)
+    return out.value
+
+
+def ite_metts_chain(ctx: Ctx, mpo: int, start, chi_max: int, beta: float, tau0: float, ratio: float,
+                    opts: ite_step_opts, site: int, op, uniforms):
+    """uniforms [nsamples][L]; returns (configs [nsamples][L], energies,
+    observables)."""
+    u = np.ascontiguousarray(uniforms, dtype=np.float64)
+    if u.ndim != 2:
+        raise ValueError("uniforms must be a [nsamples][L] array")
+    n, L = u.shape
+    st = np.ascontiguousarray(start, dtype=np.int32)
+    if st.shape != (L,):
+        raise ValueError("start must have L entries")
+    o = np.ascontiguousarray(op, dtype=np.float64)
+    cfg = np.zeros((n, L), dtype=np.int32)
+    en = np.zeros(n)
+    ob = np.zeros(n)
+    _check(load_library().ite_metts_chain(mpo, st.ctypes.data_as(_PI), int(chi_max), float(beta), float(tau0),
+                                          float(ratio), C.byref(opts), int(site), _dptr(o), n, L, _dptr(u),
+                                          cfg.ctypes.data_as(_PI), _dptr(en), _dptr(ob)), ctx.handle)
+    return cfg, en, ob
 
 
 def ite_mps_sample_noalloc(ctx: Ctx, psi: int, uniforms, configs) -> None:

@@ -365,6 +365,64 @@ int ite_mps_sample(ite_mps* psi, int nsamples, int L, const double* uniforms, in
     });
 }
 
+int ite_mps_expect_site(ite_mps* psi, int site, const double* op, double* out) {
+    if (!psi || !op || !out) return ITE_EINVAL;
+    return guarded(psi->ctx, [&] {
+        set_device(psi->ctx);
+        *out = site_expect(psi, site, op);
+    });
+}
+
+int ite_metts_chain(const ite_mpo* H, const int* start, int chi_max, double beta, double tau0, double ratio,
+                    const ite_step_opts* opts, int site, const double* op, int nsamples, int L,
+                    const double* uniforms, int* configs, double* energies, double* observables) {
+    if (!H || !start || !opts || !op || !uniforms || !configs || !energies || !observables || nsamples < 1)
+        return ITE_EINVAL;
+    ite_ctx* c = H->ctx;
+    int rc = guarded(c, [&] {
+        ITE_REQUIRE(L == H->L, "metts_chain: L differs from the Hamiltonian's length");
+        ITE_REQUIRE(std::isfinite(beta) && std::isfinite(tau0) && tau0 > 0.0 && 0.5 * beta > tau0,
+                    "metts_chain: need 0 < tau0 < beta / 2");
+        ITE_REQUIRE(site >= 0 && site < L, "metts_chain: site out of range");
+        for (int i = 0; i < L; ++i)
+            ITE_REQUIRE(start[i] >= 0 && start[i] < H->d[i], "metts_chain: start configuration out of range");
+    });
+    if (rc != ITE_OK) return rc;
+    int n = 0;
+    ite_loggrid(tau0, 0.5 * beta, ratio, nullptr, 0, &n);
+    if (n < 2) {
+        c->err = "metts_chain: bad grid (need ratio > 1)";
+        return ITE_EINVAL;
+    }
+    std::vector<int> cfg(start, start + L);
+    std::vector<ite_step_report> reps(n);
+    std::vector<std::vector<double>> sp(L);
+    std::vector<const double*> spp(L);
+    for (int k = 0; k < nsamples; ++k) {
+        for (int i = 0; i < L; ++i) {
+            configs[(size_t)k * L + i] = cfg[i];
+            sp[i].assign(H->d[i], 0.0);
+            sp[i][cfg[i]] = 1.0;
+            spp[i] = sp[i].data();
+        }
+        // |psi_k> ~ exp(-beta H / 2)|cfg> on the geometric grid tau0 -> beta / 2
+        ite_mps* psi = nullptr;
+        rc = ite_mps_create(c, L, H->d.data(), spp.data(), chi_max, 0, &psi);
+        if (rc != ITE_OK) return rc;
+        int steps = 0;
+        rc = ite_evolve_loggrid(psi, H, tau0, 0.5 * beta, ratio, opts, reps.data(), n, &steps);
+        if (rc == ITE_OK) {
+            energies[k] = steps > 0 ? reps[steps - 1].energy : 0.0;
+            rc = ite_mps_expect_site(psi, site, op, &observables[k]);
+        }
+        // collapse into the product basis: the next chain element
+        if (rc == ITE_OK) rc = ite_mps_sample(psi, 1, L, uniforms + (size_t)k * L, cfg.data());
+        ite_mps_destroy(psi);
+        if (rc != ITE_OK) return rc;
+    }
+    return ITE_OK;
+}
+
 int ite_mps_sample_noalloc(ite_mps* psi, int nsamples, int L, const double* uniforms, int* configs) {
     if (!psi || !uniforms || !configs || nsamples < 1) return ITE_EINVAL;
     return guarded(psi->ctx, [&] {

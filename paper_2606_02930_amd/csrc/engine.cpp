@@ -1429,6 +1429,52 @@ void dmrg_sweeps(ite_mps* psi, const ite_mpo* H, const DmrgOpts& o, DmrgReport* 
 }
 
 // ---------------------------------------------------------------------------
+// One-site expectation values (the observable of the METTS chains)
+// ---------------------------------------------------------------------------
+
+// <psi|O_site|psi> / <psi|psi>: the overlap transfer from the left up to the
+// site (E[a', a] over sites < site), T = E A_site (GEMM), U = O T on the
+// physical index (a GEMM batched over the left index), then the two
+// contractions A . U and A . T.  The sites right of `site` are
+// right-orthonormal in every state this library leaves (centre on site 1),
+// so they contribute the identity.
+double site_expect(ite_mps* psi, int site, const double* op_host) {
+    ite_ctx* c = psi->ctx;
+    const int L = psi->L;
+    ITE_REQUIRE(site >= 0 && site < L, "expect_site: site out of range");
+    const int d = psi->d[site];
+    for (int k = 0; k < d * d; ++k) ITE_REQUIRE(std::isfinite(op_host[k]), "expect_site: non-finite operator entry");
+    size_t mx = 1;
+    for (int i = 0; i <= site; ++i) mx = std::max(mx, (size_t)psi->D[i] * psi->D[i]);
+    double* E0 = slot_t<double>(c, SL_TMPA, mx);
+    double* E1 = slot_t<double>(c, SL_TMPB, mx);
+    fill(E0, 1.0, 1, c->stream);
+    for (int i = 0; i < site; ++i) {
+        env_left(c, psi->D[i], psi->D[i], psi->D[i + 1], psi->D[i + 1], psi->d[i], 1, 1, E0, psi->A[i], nullptr,
+                 psi->A[i], E1);
+        std::swap(E0, E1);
+    }
+    const int Dl = psi->D[site], Dr = psi->D[site + 1];
+    const size_t n = (size_t)Dl * d * Dr;
+    double* T = slot_t<double>(c, SL_R64, n);
+    double* U = slot_t<double>(c, SL_D64, n);
+    double* op = slot_t<double>(c, SL_SMALL, 512) + 320;   // d <= 8: 64 values
+    h2d(c, op, op_host, sizeof(double) * d * d);
+    gemm(c, false, false, Dl, d * Dr, Dl, 1.0, E0, Dl, psi->A[site], (long)d * Dr, 0.0, nullptr, 0, T, (long)d * Dr);
+    Gemm g;
+    g.M = d; g.N = Dr; g.K = d;
+    g.A = op; g.lda = d; g.sA = 0;
+    g.B = T; g.ldb = Dr; g.sB = (long)d * Dr;
+    g.D = U; g.ldd = Dr; g.sD = (long)d * Dr;
+    g.batch = Dl;
+    gemm_f64(g, c->stream);
+    const double num = dot(c, psi->A[site], U, n);
+    const double den = dot(c, psi->A[site], T, n);
+    ITE_REQUIRE(den > 0.0 && std::isfinite(den), "expect_site: zero or non-finite state");
+    return num / den;
+}
+
+// ---------------------------------------------------------------------------
 // Product-basis sampling (METTS collapse)
 // ---------------------------------------------------------------------------
 

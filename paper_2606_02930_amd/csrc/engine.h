@@ -188,6 +188,9 @@ struct DmrgReport {
     int max_chi = 0;
 };
 void dmrg_sweeps(ite_mps* psi, const ite_mpo* H, const DmrgOpts& o, DmrgReport* rep);
+// <psi|O_site|psi> / <psi|psi> for a one-site operator op_host [d][d] (host,
+// (out, in)); psi right-orthonormal right of the site.
+double site_expect(ite_mps* psi, int site, const double* op_host);
 // Product-basis samples of psi (see ite_mps_sample); host arrays.
 void mps_sample(ite_mps* psi, int nsamples, const double* uniforms, int* configs);
 // Doubles of working memory mps_sample needs for nsamples samples of psi.
