@@ -428,38 +428,49 @@ SplitResult split(ite_ctx* c, int dir, int Dl, int d1, int d2, int Dr, const dou
 // GMRES local solve
 // ---------------------------------------------------------------------------
 
+// SolveStats of a device record (see hess_solve): [0] residual, [1] products,
+// [2] flags.
+static SolveStats stats_from(const double* rec, bool low) {
+    SolveStats st;
+    st.res_rel = rec[0];
+    (low ? st.matvecs_lo : st.matvecs64) = (int)rec[1];
+    st.flags = (int)rec[2];
+    return st;
+}
+
 static void op_apply(ite_ctx* c, const LocalOp& op, const double* v, double* y) {
     heff_apply(c, op.s, op.L, *op.ww, op.R, v, op.beta, op.alpha, v, y, op.prec, op.Llo, op.Rlo);
 }
 
 // GMRES(m) with the fixed budget (no tolerance: m Arnoldi steps per cycle,
-// fewer only at an invariant subspace).  The Arnoldi steps are issued without
-// waiting for the host: the Hessenberg columns and the norms of b and of the
-// first residual stay on the device and come to the host once per cycle,
-// where the Givens rotations, the breakdown test and the least-squares solve
-// run.  Steps after a breakdown (the next basis vector divides by a
-// vanishing norm) are computed and discarded; the counts report the products
-// whose results enter the solution.  Same kernels in the same order as the
-// tolerance-driven loop below, so the results are the same.
+// fewer only at an invariant subspace), entirely on the device: the Arnoldi
+// steps, then the cycle's least-squares problem (Givens rotations, the
+// breakdown test, back substitution: hess_solve) and x += V y, with no wait
+// for the host.  The residual estimate, the product count and the flags are
+// accumulated in the device record `stats` (8 doubles); when it is null a
+// context slot is used and read back once at the end.  Steps after a
+// breakdown (the next basis vector divides by a vanishing norm) are computed
+// and discarded; the counts report the products whose results enter the
+// solution.  Same kernels in the same order as the tolerance-driven loop
+// below.
 static SolveStats gmres_budget(ite_ctx* c, const LocalOp& op, const double* b, double* x, int m, int max_cycles,
-                               bool x_is_zero) {
-    SolveStats st;
-    const bool lo = op.prec != Prec::F64;
-    int& mv = lo ? st.matvecs_lo : st.matvecs64;
+                               bool x_is_zero, double* stats = nullptr) {
     const size_t n = op.n();
     const int mm = (int)std::min<size_t>((size_t)m, n);
-    constexpr int HC = 192;   // per column: [0,64) first-pass coefficients, [64,128) second pass, 128 norm
+    constexpr int HC = HESS_HC;   // per column: [0,64) first-pass coefficients, [64,128) second pass, 128 norm
     double* V = slot_t<double>(c, SL_V, (size_t)(mm + 1) * n);
     double* w = slot_t<double>(c, SL_W, n);
     const int nb = reduce_blocks(n);
     double* part = slot_t<double>(c, SL_PART, (size_t)nb * 64 + 64);
-    double* hd = slot_t<double>(c, SL_HESS, (size_t)mm * HC + 8);
+    double* hd = slot_t<double>(c, SL_HESS, (size_t)mm * HC + 8 + 64 + 8);
     double* bnorm_d = hd + (size_t)mm * HC;       // ||b||
     double* beta_d = bnorm_d + 1;                 // ||r0||
-    double* host = pinned(c, (size_t)mm * HC + 8 + 64);
+    double* ydev = hd + (size_t)mm * HC + 8;      // combination coefficients (64)
+    const bool own_stats = stats == nullptr;
+    if (own_stats) stats = hd + (size_t)mm * HC + 8 + 64;
+    fill(stats, 0.0, 8, c->stream);
     dot_partials(b, b, n, part, c->stream);
     finish_partials(part, 1, nb, bnorm_d, 2, c->stream);
-    std::vector<double> H((size_t)(mm + 1) * mm), cs(mm), sn(mm), g(mm + 1), y(mm);
     for (int cyc = 0; cyc < max_cycles; ++cyc) {
         // r0 = b - A x
         bool r_product = false;
@@ -488,57 +499,15 @@ static SolveStats gmres_budget(ite_ctx* c, const LocalOp& op, const double* b, d
             finish_partials(part, 1, nb, col + 128, 2, c->stream);
             if (vnext) scale_inv(w, col + 128, vnext, n, c->stream);
         }
-        d2h(c, host, hd, (size_t)mm * HC + 2);
+        hess_solve(hd, mm, ydev, stats, r_product, cyc + 1 == max_cycles, c->stream);
+        gemv_add(V, (long)n, mm, ydev, x, n, c->stream);
+    }
+    SolveStats st;
+    if (own_stats) {
+        double* host = pinned(c, 64);
+        d2h(c, host, stats, 4);
         sync(c);
-        if (r_product) mv++;
-        const double bnorm = host[(size_t)mm * HC], beta = host[(size_t)mm * HC + 1];
-        st.res_rel = bnorm > 0 ? beta / bnorm : 0.0;
-        if (!(beta > 0.0)) return st;
-        std::fill(H.begin(), H.end(), 0.0);
-        std::fill(g.begin(), g.end(), 0.0);
-        g[0] = beta;
-        int kused = 0;
-        bool breakdown = false;
-        for (int k = 0; k < mm; ++k) {
-            const double* col = host + (size_t)k * HC;
-            for (int i = 0; i <= k; ++i) H[(size_t)i * mm + k] = col[i] + col[64 + i];
-            const double hnext = col[128];
-            for (int i = 0; i < k; ++i) {
-                const double a = H[(size_t)i * mm + k], bb = H[(size_t)(i + 1) * mm + k];
-                H[(size_t)i * mm + k] = cs[i] * a + sn[i] * bb;
-                H[(size_t)(i + 1) * mm + k] = -sn[i] * a + cs[i] * bb;
-            }
-            const double a = H[(size_t)k * mm + k];
-            const double rr = std::hypot(a, hnext);
-            cs[k] = rr > 0 ? a / rr : 1.0;
-            sn[k] = rr > 0 ? hnext / rr : 0.0;
-            H[(size_t)k * mm + k] = rr;
-            g[k + 1] = -sn[k] * g[k];
-            g[k] = cs[k] * g[k];
-            kused = k + 1;
-            st.res_rel = bnorm > 0 ? std::fabs(g[k + 1]) / bnorm : 0.0;
-            if (hnext <= 1e-14 * beta) {
-                st.flags |= ITE_FLAG_BREAKDOWN;
-                breakdown = true;
-                break;
-            }
-        }
-        mv += kused;
-        // back substitution R y = g
-        for (int i = kused - 1; i >= 0; --i) {
-            double s = g[i];
-            for (int j = i + 1; j < kused; ++j) s -= H[(size_t)i * mm + j] * y[j];
-            const double dgn = H[(size_t)i * mm + i];
-            y[i] = dgn != 0.0 ? s / dgn : 0.0;
-        }
-        double* ys = host + (size_t)mm * HC + 8;
-        for (int i = 0; i < kused; ++i) ys[i] = y[i];
-        double* ydev = slot_t<double>(c, SL_SMALL, 512) + 192;
-        h2d(c, ydev, ys, sizeof(double) * kused);
-        gemv_add(V, (long)n, kused, ydev, x, n, c->stream);
-        sync(c);
-        if (breakdown) return st;
-        if (cyc + 1 == max_cycles) st.flags |= ITE_FLAG_BUDGET_EXHAUSTED;
+        st = stats_from(host, op.prec != Prec::F64);
     }
     return st;
 }
@@ -661,7 +630,13 @@ static SolveStats gmres(ite_ctx* c, const LocalOp& op, const double* b, double* 
 // GMRES budget) the residual after the last correction is not formed and the
 // inner GMRES estimate, scaled by ||r|| / ||b||, is reported instead.
 SolveStats local_solve(ite_ctx* c, const LocalOp& op, const double* b, double* x, int m, int max_cycles,
-                       double tol, int precision, int max_refine, double tol_refine) {
+                       double tol, int precision, int max_refine, double tol_refine, double* stats_dev) {
+    if (precision == ITE_PREC_FP64 && tol <= 0 && stats_dev) {
+        gmres_budget(c, op, b, x, m, max_cycles, false, stats_dev);
+        SolveStats st;
+        st.deferred = true;
+        return st;
+    }
     if (precision == ITE_PREC_FP64) return gmres(c, op, b, x, m, max_cycles, tol);
     const Prec p = precision == ITE_PREC_FP32_IR ? Prec::F32 : Prec::BF16;
     const size_t n = op.n();
@@ -1072,6 +1047,12 @@ void imag_step(ite_mps* psi, const ite_mpo* H, double h, const ite_step_opts& o,
     const double acoef = 1.0 - h * s;
     int nres = 0;
     double sum_res = 0.0;
+    // device records of the local solves that report there (fixed budget,
+    // FP64): read once after the sweeps
+    const int nblocks = 2 * (L - 1) * o.nsweeps;
+    double* stats_dev = slot_t<double>(c, SL_STATS, (size_t)8 * nblocks + 8);
+    std::vector<char> deferred(nblocks, 0);
+    int blk = 0;
     // refinement rounds: 0 picks the cheapest count that keeps the step
     // within 1e-8 relative energy of the FP64 step at the fixed budget
     // (measured: FP32 operands 1e-12 after one correction; BF16 operands
@@ -1114,14 +1095,19 @@ void imag_step(ite_mps* psi, const ite_mpo* H, double h, const ite_step_opts& o,
         op.alpha = acoef;
         op.beta = h;
         SolveStats ss = local_solve(c, op, bvec, th, o.krylov_dim, o.max_cycles, o.tol_loc, o.precision,
-                                    refine, o.tol_refine);
+                                    refine, o.tol_refine, stats_dev + (size_t)8 * blk);
         tm.close(t_solve);
-        r.matvecs_fp64 += ss.matvecs64;
-        r.matvecs_lo += ss.matvecs_lo;
-        r.flags |= ss.flags;
-        r.max_res_rel = std::max(r.max_res_rel, ss.res_rel);
-        sum_res += ss.res_rel;
-        ++nres;
+        if (ss.deferred) {
+            deferred[blk] = 1;
+        } else {
+            r.matvecs_fp64 += ss.matvecs64;
+            r.matvecs_lo += ss.matvecs_lo;
+            r.flags |= ss.flags;
+            r.max_res_rel = std::max(r.max_res_rel, ss.res_rel);
+            sum_res += ss.res_rel;
+            ++nres;
+        }
+        ++blk;
         const int t_split = tm.open(PH_SPLIT);
         SplitResult sp = split(c, dir, Dl, d1, d2, Dr, th, chi, o.cutoff, o.tie_rel, X[i], X[i + 1], nullptr);
         tm.close(t_split);
@@ -1174,6 +1160,20 @@ void imag_step(ite_mps* psi, const ite_mpo* H, double h, const ite_step_opts& o,
             }
         }
     }
+    if (std::find(deferred.begin(), deferred.end(), 1) != deferred.end()) {
+        double* host = pinned(c, (size_t)8 * nblocks + 64);
+        d2h(c, host, stats_dev, (size_t)8 * nblocks);
+        sync(c);
+        for (int k = 0; k < nblocks; ++k) {
+            if (!deferred[k]) continue;
+            const SolveStats ss = stats_from(host + (size_t)8 * k, false);
+            r.matvecs_fp64 += ss.matvecs64;
+            r.flags |= ss.flags;
+            r.max_res_rel = std::max(r.max_res_rel, ss.res_rel);
+            sum_res += ss.res_rel;
+            ++nres;
+        }
+    }
     // normalise the centre (site 1) and measure
     const size_t n0 = (size_t)XD[0] * psi->d[0] * XD[1];
     const double nrm2 = dot(c, X[0], X[0], n0);
@@ -1212,76 +1212,29 @@ void imag_step(ite_mps* psi, const ite_mpo* H, double h, const ite_step_opts& o,
 // DMRG ground-state sweeps
 // ---------------------------------------------------------------------------
 
-// Eigenvalues w and eigenvectors (columns of Z, row-major k x k) of the
-// symmetric k x k matrix A by cyclic Jacobi rotations (Jacobi's method; each
-// rotation J in the (p, q) plane with tan = t the smaller root of
-// t^2 + 2 tau t - 1 = 0, tau = (a_qq - a_pp) / (2 a_pq), zeroes a_pq of J^T A J).
-static void sym_eig_small(int k, std::vector<double> A, std::vector<double>& w, std::vector<double>& Z) {
-    Z.assign((size_t)k * k, 0.0);
-    for (int i = 0; i < k; ++i) Z[(size_t)i * k + i] = 1.0;
-    for (int sweep = 0; sweep < 60; ++sweep) {
-        double off = 0.0, tot = 0.0;
-        for (int i = 0; i < k; ++i)
-            for (int j = 0; j < k; ++j) {
-                const double v = A[(size_t)i * k + j] * A[(size_t)i * k + j];
-                tot += v;
-                if (i != j) off += v;
-            }
-        if (!(off > 1e-32 * tot)) break;
-        for (int p = 0; p < k; ++p)
-            for (int q = p + 1; q < k; ++q) {
-                const double apq = A[(size_t)p * k + q];
-                if (apq == 0.0) continue;
-                const double tau = (A[(size_t)q * k + q] - A[(size_t)p * k + p]) / (2.0 * apq);
-                const double t = (tau >= 0.0 ? 1.0 : -1.0) / (std::fabs(tau) + std::sqrt(1.0 + tau * tau));
-                const double cc = 1.0 / std::sqrt(1.0 + t * t), ss = t * cc;
-                for (int r = 0; r < k; ++r) {   // columns p, q of A J
-                    const double arp = A[(size_t)r * k + p], arq = A[(size_t)r * k + q];
-                    A[(size_t)r * k + p] = cc * arp - ss * arq;
-                    A[(size_t)r * k + q] = ss * arp + cc * arq;
-                }
-                for (int r = 0; r < k; ++r) {   // rows p, q of J^T (A J)
-                    const double apr = A[(size_t)p * k + r], aqr = A[(size_t)q * k + r];
-                    A[(size_t)p * k + r] = cc * apr - ss * aqr;
-                    A[(size_t)q * k + r] = ss * apr + cc * aqr;
-                }
-                for (int r = 0; r < k; ++r) {   // Z J
-                    const double zrp = Z[(size_t)r * k + p], zrq = Z[(size_t)r * k + q];
-                    Z[(size_t)r * k + p] = cc * zrp - ss * zrq;
-                    Z[(size_t)r * k + q] = ss * zrp + cc * zrq;
-                }
-            }
-    }
-    w.resize(k);
-    for (int i = 0; i < k; ++i) w[i] = A[(size_t)i * k + i];
-}
-
-struct EigStats {
-    double theta = 0.0, res_rel = 0.0;
-    long long matvecs = 0;
-};
-
 // Lowest eigenpair of the symmetric operator op by the Lanczos method with
 // full reorthogonalisation: the Arnoldi steps of the GMRES solver (classical
-// Gram-Schmidt twice, the projected column kept on the device and brought to
-// the host once per cycle), the symmetric part of the projected matrix
-// diagonalised on the host, and a restart from the Ritz vector, for at most
+// Gram-Schmidt twice), the projected matrix diagonalised on the device
+// (lanczos_eig), x = V y, and a restart from that Ritz vector, for at most
 // max_cycles cycles of m steps or until ||op x - theta x|| <= tol |theta|
 // (estimated as |h_(k+1,k) y_k|).  x: the start vector on entry (any norm),
-// the normalised Ritz vector on return.
-static EigStats lanczos_lowest(ite_ctx* c, const LocalOp& op, double* x, int m, int max_cycles, double tol) {
-    EigStats st;
+// the normalised Ritz vector on return.  rec (device, 4 doubles, zeroed
+// here): [0] theta, [1] relative residual, [2] products, [3] steps of the
+// last cycle.  With one cycle nothing waits for the host; more cycles read
+// rec once per cycle for the stopping test.
+static void lanczos_lowest(ite_ctx* c, const LocalOp& op, double* x, int m, int max_cycles, double tol,
+                           double* rec) {
     const size_t n = op.n();
     const int mm = (int)std::min<size_t>((size_t)m, n);
-    constexpr int HC = 192;   // per column: [0,64) first-pass coefficients, [64,128) second pass, 128 norm
+    constexpr int HC = HESS_HC;   // per column: [0,64) first-pass coefficients, [64,128) second pass, 128 norm
     double* V = slot_t<double>(c, SL_V, (size_t)(mm + 1) * n);
     double* w = slot_t<double>(c, SL_W, n);
     const int nb = reduce_blocks(n);
     double* part = slot_t<double>(c, SL_PART, (size_t)nb * 64 + 64);
-    double* hd = slot_t<double>(c, SL_HESS, (size_t)mm * HC + 8);
+    double* hd = slot_t<double>(c, SL_HESS, (size_t)mm * HC + 8 + 64);
     double* xnorm_d = hd + (size_t)mm * HC;
-    double* host = pinned(c, (size_t)mm * HC + 8 + 64);
-    std::vector<double> T, ev, Z;
+    double* ydev = hd + (size_t)mm * HC + 8;
+    fill(rec, 0.0, 4, c->stream);
     for (int cyc = 0; cyc < max_cycles; ++cyc) {
         dot_partials(x, x, n, part, c->stream);
         finish_partials(part, 1, nb, xnorm_d, 2, c->stream);
@@ -1301,49 +1254,18 @@ static EigStats lanczos_lowest(ite_ctx* c, const LocalOp& op, double* x, int m, 
             finish_partials(part, 1, nb, col + 128, 2, c->stream);
             if (vnext) scale_inv(w, col + 128, vnext, n, c->stream);
         }
-        d2h(c, host, hd, (size_t)mm * HC + 1);
-        sync(c);
-        if (!(host[(size_t)mm * HC] > 0.0) || !std::isfinite(host[(size_t)mm * HC]))
-            ITE_FAIL(ITE_ENONFINITE, "dmrg: zero or non-finite start vector of a local problem");
-        // projected matrix (upper triangle from the Gram-Schmidt coefficients)
-        // up to the first breakdown
-        int kused = mm;
-        double scale_h = 0.0;
-        for (int k = 0; k < mm; ++k) {
-            const double* col = host + (size_t)k * HC;
-            scale_h = std::max(scale_h, std::fabs(col[k] + col[64 + k]));
-            if (k + 1 < mm && !(col[128] > 1e-14 * std::max(scale_h, 1e-300))) {
-                kused = k + 1;
-                break;
-            }
-        }
-        T.assign((size_t)kused * kused, 0.0);
-        for (int k = 0; k < kused; ++k) {
-            const double* col = host + (size_t)k * HC;
-            for (int i = 0; i <= k; ++i) {
-                const double v = col[i] + col[64 + i];
-                T[(size_t)i * kused + k] = v;
-                T[(size_t)k * kused + i] = v;
-            }
-        }
-        sym_eig_small(kused, T, ev, Z);
-        const int imin = (int)(std::min_element(ev.begin(), ev.end()) - ev.begin());
-        st.theta = ev[imin];
-        const double hlast = kused == mm ? host[(size_t)(mm - 1) * HC + 128] : 0.0;
-        const double res = std::fabs(hlast * Z[(size_t)(kused - 1) * kused + imin]);
-        st.res_rel = st.theta != 0.0 ? res / std::fabs(st.theta) : res;
-        st.matvecs += kused;
-        double* ys = host + (size_t)mm * HC + 8;
-        for (int i = 0; i < kused; ++i) ys[i] = Z[(size_t)i * kused + imin];
-        double* ydev = slot_t<double>(c, SL_SMALL, 512) + 192;
-        h2d(c, ydev, ys, sizeof(double) * kused);
+        lanczos_eig(hd, mm, ydev, rec, c->stream);
         fill(x, 0.0, n, c->stream);
-        gemv_add(V, (long)n, kused, ydev, x, n, c->stream);
-        sync(c);
-        if (!std::isfinite(st.theta)) ITE_FAIL(ITE_ENONFINITE, "dmrg: non-finite Ritz value");
-        if (kused < mm || res <= tol * std::fabs(st.theta)) break;
+        gemv_add(V, (long)n, mm, ydev, x, n, c->stream);
+        if (cyc + 1 < max_cycles) {
+            double* host = pinned(c, 64);
+            d2h(c, host, rec, 4);
+            sync(c);
+            if (!std::isfinite(host[0])) ITE_FAIL(ITE_ENONFINITE, "dmrg: non-finite Ritz value");
+            const bool converged = host[0] != 0.0 ? host[1] <= tol : host[1] == 0.0;
+            if ((int)host[3] < mm || converged) break;
+        }
     }
-    return st;
 }
 
 void dmrg_sweeps(ite_mps* psi, const ite_mpo* H, const DmrgOpts& o, DmrgReport* rep) {
@@ -1372,6 +1294,9 @@ void dmrg_sweeps(ite_mps* psi, const ite_mpo* H, const DmrgOpts& o, DmrgReport* 
         env_right(c, XD[b + 1], XD[b + 1], XD[b], XD[b], psi->d[b], H->w[b], H->w[b + 1], env[b + 1].H, X[b],
                   &H->right[b], X[b], env[b].H);
     DmrgReport r{};
+    const int nblocks = 2 * (L - 1) * o.nsweeps;
+    double* recs = slot_t<double>(c, SL_STATS, (size_t)4 * nblocks + 8);
+    int blk = 0;
     auto block = [&](int i, int dir) {
         const int d1 = psi->d[i], d2 = psi->d[i + 1];
         const int Dl = XD[i], Dr = XD[i + 2];
@@ -1384,10 +1309,8 @@ void dmrg_sweeps(ite_mps* psi, const ite_mpo* H, const DmrgOpts& o, DmrgReport* 
         op.ww = &H->pair[i];
         op.alpha = 0.0;
         op.beta = 1.0;
-        const EigStats es = lanczos_lowest(c, op, th, o.krylov_dim, o.max_cycles, o.tol);
-        r.energy = es.theta;
-        r.matvecs += es.matvecs;
-        r.max_res_rel = std::max(r.max_res_rel, es.res_rel);
+        lanczos_lowest(c, op, th, o.krylov_dim, o.max_cycles, o.tol, recs + (size_t)4 * blk);
+        ++blk;
         const SplitResult sp = split(c, dir, Dl, d1, d2, Dr, th, chi, o.cutoff, o.tie_rel, X[i], X[i + 1], nullptr);
         XD[i + 1] = sp.k;
         r.max_disc = std::max(r.max_disc, sp.disc);
@@ -1404,6 +1327,17 @@ void dmrg_sweeps(ite_mps* psi, const ite_mpo* H, const DmrgOpts& o, DmrgReport* 
             if (i > 0)
                 env_right(c, XD[i + 2], XD[i + 2], XD[i + 1], XD[i + 1], psi->d[i + 1], H->w[i + 1], H->w[i + 2],
                           env[i + 2].H, X[i + 1], &H->right[i + 1], X[i + 1], env[i + 1].H);
+        }
+    }
+    {
+        double* host = pinned(c, (size_t)4 * nblocks + 64);
+        d2h(c, host, recs, (size_t)4 * nblocks);
+        sync(c);
+        for (int k = 0; k < nblocks; ++k) {
+            const double* rc = host + (size_t)4 * k;
+            if (!std::isfinite(rc[0])) ITE_FAIL(ITE_ENONFINITE, "dmrg: non-finite Ritz value");
+            r.matvecs += (long long)rc[2];
+            r.max_res_rel = std::max(r.max_res_rel, rc[1]);
         }
     }
     // the mixed environments of the evolution describe the previous state

@@ -21,6 +21,7 @@ enum SlotId {
     SL_LO_L, SL_LO_R, SL_LO_T, SL_LO_X,   // low-precision shadows (mixed precision)
     SL_R64, SL_D64,                // refinement residual and correction
     SL_HESS,                       // Hessenberg columns of a fixed-budget GMRES cycle
+    SL_STATS,                      // per-block device records of the local solves of a step
     SL_NSLOTS
 };
 
@@ -148,6 +149,7 @@ struct SolveStats {
     int matvecs64 = 0, matvecs_lo = 0;
     double res_rel = 0.0;
     int flags = 0;
+    bool deferred = false;   // the figures are in the caller's device record, not here
 };
 // Linear operator of a local solve: y = alpha v + beta H_eff v.
 struct LocalOp {
@@ -162,8 +164,11 @@ struct LocalOp {
     const void* Rlo = nullptr;
     size_t n() const { return (size_t)s.Dxl * s.d1 * s.d2 * s.Dxr; }
 };
+// stats_dev (nullable): device record of 8 doubles; with it, a solve with the
+// fixed budget in FP64 runs without waiting for the host and leaves its
+// figures there (SolveStats::deferred; [0] residual, [1] products, [2] flags).
 SolveStats local_solve(ite_ctx* c, const LocalOp& op, const double* b, double* x, int m, int max_cycles,
-                       double tol, int precision, int max_refine, double tol_refine);
+                       double tol, int precision, int max_refine, double tol_refine, double* stats_dev = nullptr);
 
 double dot(ite_ctx* c, const double* x, const double* y, size_t n);
 

@@ -113,6 +113,17 @@ void sample_site(const double* T, int nsamples, int d, int Dr, const double* u, 
 // col[0..k1) and col[64..64+k1), ||w|| to col[128], vnext = w / ||w|| when
 // not null.  Returns false (and does nothing) for longer vectors.
 bool cgs2_small(const double* V, long ldv, int k1, double* w, size_t n, double* col, double* vnext, hipStream_t s);
+// Device least-squares solve of one GMRES cycle (see hess_solve_one in
+// vec.hip): hd holds the cycle's Hessenberg columns, HESS_HC doubles each,
+// then ||b|| and ||r0||; y gets the mm combination coefficients; stats (8
+// doubles per local solve, zeroed before the first cycle) accumulate the
+// residual estimate, the product count and the flags.
+constexpr int HESS_HC = 192, HESS_KMAX = 64;
+void hess_solve(const double* hd, int mm, double* y, double* stats, bool r_product, bool last_cycle, hipStream_t s);
+// Device eigensolve of a Lanczos cycle's projected matrix (lanczos_eig_kernel
+// in vec.hip): y = the eigenvector of the lowest eigenvalue; rec: [0] the
+// eigenvalue, [1] relative residual estimate, [2] += steps used, [3] steps used.
+void lanczos_eig(const double* hd, int mm, double* y, double* rec, hipStream_t s);
 // x *= a
 void scale(double* x, double a, size_t n, hipStream_t s);
 // y[i] = x[i*inc] for i < n (strided gather)

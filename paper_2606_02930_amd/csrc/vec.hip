@@ -178,6 +178,88 @@ __global__ __launch_bounds__(CGS_T) void cgs2_small_kernel(const double* __restr
     }
 }
 
+// The small least-squares problem of one GMRES cycle, on the device (one
+// thread; the Hessenberg matrix in LDS): the columns of the cycle's Arnoldi
+// steps are hd[k * HESS_HC + i] (first Gram-Schmidt pass), + 64 (second
+// pass), + 128 (the norm of the next vector); hd[mm * HESS_HC] = ||b||,
+// hd[mm * HESS_HC + 1] = beta = ||r0||.  Givens rotations reduce H to upper
+// triangular form while the residual estimate |g_(k+1)| is tracked; an
+// Arnoldi step whose next norm is <= 1e-14 beta ends the cycle (invariant
+// subspace); y solves R y = g by back substitution (zero beyond the steps
+// used).  stats (per local solve, zeroed by the caller before the first
+// cycle): [0] relative residual estimate, [1] products whose results enter
+// the solution, [2] ITE_FLAG_* bits, [3] 1 once a cycle found an invariant
+// subspace or a zero residual (later cycles then change nothing).
+// LDS of one solve: H ((KMAX + 1) x KMAX), then cos, sin and g.
+constexpr int HESS_LDS = (HESS_KMAX + 1) * HESS_KMAX + 3 * HESS_KMAX + 1;
+__device__ void hess_solve_one(const double* __restrict__ hd, int mm, double* __restrict__ y,
+                               double* __restrict__ stats, int r_product, int last_cycle, double* Hs) {
+    if (stats[3] != 0.0) {
+        for (int i = 0; i < mm; ++i) y[i] = 0.0;
+        return;
+    }
+    if (r_product) stats[1] += 1.0;
+    const double bnorm = hd[(size_t)mm * HESS_HC], beta = hd[(size_t)mm * HESS_HC + 1];
+    stats[0] = bnorm > 0.0 ? beta / bnorm : 0.0;
+    if (!(beta > 0.0)) {
+        for (int i = 0; i < mm; ++i) y[i] = 0.0;
+        stats[3] = 1.0;
+        return;
+    }
+    double* cs = Hs + (HESS_KMAX + 1) * HESS_KMAX;
+    double* sn = cs + HESS_KMAX;
+    double* g = sn + HESS_KMAX;
+    for (int i = 0; i <= mm; ++i) g[i] = 0.0;
+    g[0] = beta;
+    int kused = 0;
+    bool breakdown = false;
+    for (int k = 0; k < mm; ++k) {
+        const double* col = hd + (size_t)k * HESS_HC;
+        for (int i = 0; i <= k; ++i) Hs[i * HESS_KMAX + k] = col[i] + col[64 + i];
+        const double hnext = col[128];
+        for (int i = 0; i < k; ++i) {
+            const double a = Hs[i * HESS_KMAX + k], bb = Hs[(i + 1) * HESS_KMAX + k];
+            Hs[i * HESS_KMAX + k] = cs[i] * a + sn[i] * bb;
+            Hs[(i + 1) * HESS_KMAX + k] = -sn[i] * a + cs[i] * bb;
+        }
+        const double a = Hs[k * HESS_KMAX + k];
+        const double rr = hypot(a, hnext);
+        cs[k] = rr > 0.0 ? a / rr : 1.0;
+        sn[k] = rr > 0.0 ? hnext / rr : 0.0;
+        Hs[k * HESS_KMAX + k] = rr;
+        g[k + 1] = -sn[k] * g[k];
+        g[k] = cs[k] * g[k];
+        kused = k + 1;
+        stats[0] = bnorm > 0.0 ? fabs(g[k + 1]) / bnorm : 0.0;
+        if (hnext <= 1e-14 * beta) {
+            breakdown = true;
+            break;
+        }
+    }
+    stats[1] += kused;
+    for (int i = kused - 1; i >= 0; --i) {
+        double sum = g[i];
+        for (int j = i + 1; j < kused; ++j) sum -= Hs[i * HESS_KMAX + j] * y[j];
+        const double dgn = Hs[i * HESS_KMAX + i];
+        y[i] = dgn != 0.0 ? sum / dgn : 0.0;
+    }
+    for (int i = kused; i < mm; ++i) y[i] = 0.0;
+    int flags = (int)stats[2];
+    if (breakdown) {
+        flags |= ITE_FLAG_BREAKDOWN;
+        stats[3] = 1.0;
+    } else if (last_cycle) {
+        flags |= ITE_FLAG_BUDGET_EXHAUSTED;
+    }
+    stats[2] = (double)flags;
+}
+
+__global__ __launch_bounds__(64) void hess_solve_kernel(const double* __restrict__ hd, int mm, double* __restrict__ y,
+                                                        double* __restrict__ stats, int r_product, int last_cycle) {
+    __shared__ double Hs[HESS_LDS];
+    if (threadIdx.x == 0) hess_solve_one(hd, mm, y, stats, r_product, last_cycle, Hs);
+}
+
 __global__ void scale_inv_kernel(const double* __restrict__ x, const double* __restrict__ den,
                                  double* __restrict__ out, size_t n) {
     const double d = *den;
@@ -459,6 +541,129 @@ void sample_site(const double* T, int nsamples, int d, int Dr, const double* u, 
 void scale_inv(const double* x, const double* den, double* out, size_t n, hipStream_t s) {
     if (n == 0) return;
     hipLaunchKernelGGL(scale_inv_kernel, dim3(grid_for(n, 256)), dim3(256), 0, s, x, den, out, n);
+    HIP_CHECK(hipGetLastError());
+}
+
+// Lowest eigenpair of the Lanczos cycle's projected matrix, on the device
+// (one wavefront): T (kused x kused, symmetric) from the Gram-Schmidt
+// coefficients of the columns hd[k * HESS_HC ..] (both passes summed, the
+// upper triangle mirrored), kused the steps up to the first breakdown (a
+// next norm <= 1e-14 of the largest diagonal so far); cyclic Jacobi rotations
+// (each zeroes t_pq with tan the smaller root of t^2 + 2 tau t - 1 = 0,
+// tau = (t_qq - t_pp) / (2 t_pq)) until the off-diagonal mass is below 1e-32
+// of the total (at most 60 sweeps); y = the eigenvector of the smallest
+// eigenvalue (zero beyond kused).  rec: [0] the eigenvalue, [1] the residual
+// estimate |h_(k+1,k) y_k| / |theta| (its absolute value when theta = 0),
+// [2] += kused, [3] kused.
+__global__ __launch_bounds__(64) void lanczos_eig_kernel(const double* __restrict__ hd, int mm,
+                                                         double* __restrict__ y, double* __restrict__ rec) {
+    __shared__ double A[HESS_KMAX][HESS_KMAX + 1];
+    __shared__ double Z[HESS_KMAX][HESS_KMAX + 1];
+    __shared__ double cs[2];
+    __shared__ int ku;
+    __shared__ double red[2];
+    const int t = threadIdx.x;
+    if (t == 0) {
+        int kused = mm;
+        double scale_h = 0.0;
+        for (int k = 0; k < mm; ++k) {
+            const double* col = hd + (size_t)k * HESS_HC;
+            scale_h = fmax(scale_h, fabs(col[k] + col[64 + k]));
+            if (k + 1 < mm && !(col[128] > 1e-14 * fmax(scale_h, 1e-300))) {
+                kused = k + 1;
+                break;
+            }
+        }
+        ku = kused;
+    }
+    __syncthreads();
+    const int k = ku;
+    for (int c = 0; c < k; ++c) {
+        const double* col = hd + (size_t)c * HESS_HC;
+        if (t <= c) {
+            const double v = col[t] + col[64 + t];
+            A[t][c] = v;
+            A[c][t] = v;
+        }
+        if (t < k) Z[c][t] = c == t ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        if (t == 0) {
+            double off = 0.0, tot = 0.0;
+            for (int i = 0; i < k; ++i)
+                for (int j = 0; j < k; ++j) {
+                    const double v = A[i][j] * A[i][j];
+                    tot += v;
+                    if (i != j) off += v;
+                }
+            red[0] = off;
+            red[1] = tot;
+        }
+        __syncthreads();
+        if (!(red[0] > 1e-32 * red[1])) break;
+        for (int p = 0; p < k; ++p)
+            for (int q = p + 1; q < k; ++q) {
+                if (t == 0) {
+                    const double apq = A[p][q];
+                    double cc = 1.0, ss = 0.0;
+                    if (apq != 0.0) {
+                        const double tau = (A[q][q] - A[p][p]) / (2.0 * apq);
+                        const double tt = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                        cc = 1.0 / sqrt(1.0 + tt * tt);
+                        ss = tt * cc;
+                    }
+                    cs[0] = cc;
+                    cs[1] = ss;
+                }
+                __syncthreads();
+                const double cc = cs[0], ss = cs[1];
+                if (ss != 0.0) {
+                    if (t < k) {   // columns p, q of A J
+                        const double arp = A[t][p], arq = A[t][q];
+                        A[t][p] = cc * arp - ss * arq;
+                        A[t][q] = ss * arp + cc * arq;
+                    }
+                    __syncthreads();
+                    if (t < k) {   // rows p, q of J^T (A J); Z J
+                        const double apr = A[p][t], aqr = A[q][t];
+                        A[p][t] = cc * apr - ss * aqr;
+                        A[q][t] = ss * apr + cc * aqr;
+                        const double zrp = Z[t][p], zrq = Z[t][q];
+                        Z[t][p] = cc * zrp - ss * zrq;
+                        Z[t][q] = ss * zrp + cc * zrq;
+                    }
+                }
+                __syncthreads();
+            }
+    }
+    if (t == 0) {
+        int imin = 0;
+        for (int i = 1; i < k; ++i)
+            if (A[i][i] < A[imin][imin]) imin = i;
+        red[0] = imin;
+        const double theta = A[imin][imin];
+        const double hlast = k == mm ? hd[(size_t)(mm - 1) * HESS_HC + 128] : 0.0;
+        const double res = fabs(hlast * Z[k - 1][imin]);
+        rec[0] = theta;
+        rec[1] = theta != 0.0 ? res / fabs(theta) : res;
+        rec[2] += k;
+        rec[3] = k;
+    }
+    __syncthreads();
+    const int imin = (int)red[0];
+    if (t < mm) y[t] = t < k ? Z[t][imin] : 0.0;
+}
+
+void lanczos_eig(const double* hd, int mm, double* y, double* rec, hipStream_t s) {
+    if (mm < 1 || mm > HESS_KMAX) ITE_FAIL(ITE_EINVAL, "lanczos_eig: Krylov dimension outside 1..64");
+    hipLaunchKernelGGL(lanczos_eig_kernel, dim3(1), dim3(64), 0, s, hd, mm, y, rec);
+    HIP_CHECK(hipGetLastError());
+}
+
+void hess_solve(const double* hd, int mm, double* y, double* stats, bool r_product, bool last_cycle, hipStream_t s) {
+    if (mm < 1 || mm > HESS_KMAX) ITE_FAIL(ITE_EINVAL, "hess_solve: Krylov dimension outside 1..64");
+    hipLaunchKernelGGL(hess_solve_kernel, dim3(1), dim3(64), 0, s, hd, mm, y, stats, (int)r_product, (int)last_cycle);
     HIP_CHECK(hipGetLastError());
 }
 
