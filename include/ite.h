@@ -228,6 +228,32 @@ int ite_mps_set_tau(ite_mps* psi, double tau);
 int ite_imag_step(ite_mps* psi, const ite_mpo* H, double h,
                   const ite_step_opts* opts, ite_step_report* rep);
 
+/* One implicit step (as ite_imag_step) of each of n independent states, run
+ * as a batch: the sweeps advance in lockstep block by block, and the
+ * fixed-budget FP64 GMRES local solves of a block slot run together -- one
+ * grouped launch per contraction stage for the H_eff products of all states
+ * (uneven bond dimensions, tile size per GEMM shape from the library's
+ * autotuner), one batched launch per Krylov vector operation, the small
+ * least-squares solves on the device -- captured once as a HIP graph on a
+ * private stream (ordered after ctx's stream) and replayed while the batch
+ * keeps its size and budget.  Serving (Appendix D: many independent METTS
+ * evolutions) advances its active requests this way.  Every state must be on
+ * ctx; h[j] and opts[j] are state j's; reps (nullable) gets n reports,
+ * status (nullable) each state's status (a failed state is left unchanged).
+ * Local solves outside the batched kind (tolerance-driven, mixed precision,
+ * Krylov dimension above 16 or not below the block's length, more than 128
+ * MPO-stage inputs) run one by one within the same slots.  A state's result
+ * is bitwise the same in any batch, alone included, and equals ite_imag_step's
+ * to rounding.  Returns OK, or the first failing state's status, or EINVAL /
+ * ESTATE for bad arguments (nothing run). */
+int ite_step_batch(ite_ctx* ctx, int n, ite_mps* const* psi, const ite_mpo* const* H, const double* h,
+                   const ite_step_opts* const* opts, ite_step_report* reps, int* status);
+/* Batched solves: enable (1, default) or disable (0) the graph capture (the
+ * launches are then issued one by one on ctx's stream), and the counts of
+ * batched solves, graph captures and graph replays since creation. */
+int ite_ctx_set_graphs(ite_ctx* ctx, int enable);
+int ite_ctx_batch_stats(ite_ctx* ctx, long long* solves, long long* captures, long long* replays);
+
 /* Two-site DMRG ground-state sweeps (the ground state of the impurity model
  * that seeds the METTS chains and gives the zero-temperature double
  * occupancy, Appendix D), on the same blocks, environments and SVD split as
@@ -369,8 +395,10 @@ int ite_panel_grid(double tau_max, int P, int n, double* out, int cap, int* npts
  * batching: a request waits in FIFO order until the summed footprint
  * estimate of the active requests plus its own fits `mem_cap` bytes and a
  * worker has fewer than `max_active` active requests; it then stays on that
- * worker, which advances its active requests one time step each in turn, and
- * leaves as soon as its grid is done, making room for the next.  All device
+ * worker, which advances all its active requests by one time step at a time as
+ * one batch (ite_step_batch: grouped launches for their uneven-bond H_eff
+ * products, a captured graph for the batched local solves), and leaves as
+ * soon as its grid is done, making room for the next.  All device
  * memory comes from a pool owned by the server (no hipFree while the server
  * runs).  A request's arithmetic does not depend on what else is running:
  * its results are bitwise those of the same evolution run alone. */

@@ -115,6 +115,10 @@ _SIGNATURES = {
     "ite_mps_sample": (_I, [_P, _I, _I, _PD, _PI]),
     "ite_mps_sample_noalloc": (_I, [_P, _I, _I, _P, _P]),
     "ite_mps_expect_site": (_I, [_P, _I, _PD, _PD]),
+    "ite_step_batch": (_I, [_P, _I, C.POINTER(_P), C.POINTER(_P), _PD, C.POINTER(C.POINTER(ite_step_opts)),
+                            C.POINTER(ite_step_report), _PI]),
+    "ite_ctx_set_graphs": (_I, [_P, _I]),
+    "ite_ctx_batch_stats": (_I, [_P, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]),
     "ite_metts_chain": (_I, [_P, _PI, _I, _D, _D, _D, C.POINTER(ite_step_opts), _I, _PD, _I, _I, _PD, _PI, _PD,
                              _PD]),
     "ite_dmrg_sweeps": (_I, [_P, _P, _I, _I, _D, _D, _I, _I, _D, _PD, _PD, _PD, C.POINTER(C.c_longlong)]),
@@ -355,6 +359,34 @@ def ite_imag_step(ctx: Ctx, psi: int, mpo: int, h: float, opts: ite_step_opts) -
     rep = ite_step_report()
     _check(load_library().ite_imag_step(psi, mpo, float(h), C.byref(opts), C.byref(rep)), ctx.handle)
     return rep.as_dict()
+
+
+def ite_step_batch(ctx: Ctx, psis, mpos, hs, opts) -> tuple[list[dict], list[int]]:
+    """One implicit step of every state as a batch; opts: one ite_step_opts
+    or a list.  Returns (reports, statuses); raises on the first failure."""
+    n = len(psis)
+    if isinstance(opts, ite_step_opts):
+        opts = [opts] * n
+    P = (_P * n)(*psis)
+    Hm = (_P * n)(*mpos)
+    h = np.ascontiguousarray(hs, dtype=np.float64)
+    keep = [C.pointer(o) for o in opts]
+    O = (C.POINTER(ite_step_opts) * n)(*keep)
+    reps = (ite_step_report * n)()
+    st = (C.c_int * n)()
+    rc = load_library().ite_step_batch(ctx.handle, n, P, Hm, _dptr(h), O, reps, st)
+    _check(rc, ctx.handle)
+    return [reps[i].as_dict() for i in range(n)], list(st)
+
+
+def ite_ctx_set_graphs(ctx: Ctx, enable: bool) -> None:
+    _check(load_library().ite_ctx_set_graphs(ctx.handle, int(bool(enable))), ctx.handle)
+
+
+def ite_ctx_batch_stats(ctx: Ctx) -> dict:
+    a, b, c = C.c_longlong(), C.c_longlong(), C.c_longlong()
+    _check(load_library().ite_ctx_batch_stats(ctx.handle, C.byref(a), C.byref(b), C.byref(c)), ctx.handle)
+    return {"solves": a.value, "captures": b.value, "replays": c.value}
 
 
 def ite_evolve_loggrid(ctx: Ctx, psi: int, mpo: int, tau0: float, tau1: float, ratio: float,

@@ -1,0 +1,344 @@
+// Batched implicit steps for the serving path: several independent states
+// sweep in lockstep, block slot by block slot, and the fixed-budget GMRES
+// local solves of a slot run together -- one grouped launch per product
+// stage (the uneven-bond-dimension H_eff products of all states), one
+// batched launch per Krylov vector operation -- captured once as a HIP
+// graph and replayed while the batch keeps its size and budget (the kernels
+// read every shape and address from descriptors in device memory).  The
+// tile size of each product is picked per GEMM shape by a small autotuner;
+// both tile sizes give the same bits, and every per-state reduction has the
+// single-state partition and order, so a state's step does not depend on the
+// batch it runs in.
+#include "engine.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <tuple>
+
+namespace ite {
+
+// ---------------------------------------------------------------------------
+// Tile autotuner
+// ---------------------------------------------------------------------------
+
+namespace {
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int, int, int>, int> g_tune;   // (device, M, N, K, tA, tB) -> tile
+
+float time_variant(ite_ctx* c, void* desc, int* cnt, bool tA, bool tB, int bs) {
+    hipEvent_t a, b;
+    HIP_CHECK(hipEventCreate(&a));
+    HIP_CHECK(hipEventCreate(&b));
+    gemm_grouped_f64(desc, cnt, tA, tB, bs, 512, c->stream);   // warm-up
+    HIP_CHECK(hipEventRecord(a, c->stream));
+    for (int r = 0; r < 3; ++r) gemm_grouped_f64(desc, cnt, tA, tB, bs, 512, c->stream);
+    HIP_CHECK(hipEventRecord(b, c->stream));
+    HIP_CHECK(hipEventSynchronize(b));
+    float ms = 0.f;
+    HIP_CHECK(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return ms;
+}
+}  // namespace
+
+// On the first product of a shape the two tile sizes run three times each on
+// the real operands into a scratch output, and the faster is kept for the
+// process; results do not depend on the choice (same K order per element).
+int tuned_tile(ite_ctx* c, const Gemm& g0) {
+    const auto key = std::make_tuple(c->device, g0.M, g0.N, g0.K, (int)g0.tA, (int)g0.tB);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(key);
+        if (it != g_tune.end()) return it->second;
+    }
+    Gemm g = g0;
+    g.D = slot_t<double>(c, SL_TUNE, (size_t)g.M * g.N + 64 + grouped_desc_bytes() / 8 + 8);
+    g.ldd = g.N;
+    char* base = reinterpret_cast<char*>(g.D + (size_t)g.M * g.N + 32);
+    void* desc = base;
+    int* cnt = reinterpret_cast<int*>(base + grouped_desc_bytes());
+    float best = 0.f;
+    int pick = 128;
+    for (int bs : {128, 64}) {
+        std::vector<char> hd(grouped_desc_bytes());
+        grouped_desc_fill(g, bs, 0, hd.data());
+        const int hc[2] = {1, grouped_tiles(g, bs)};
+        HIP_CHECK(hipMemcpyAsync(desc, hd.data(), hd.size(), hipMemcpyHostToDevice, c->stream));
+        HIP_CHECK(hipMemcpyAsync(cnt, hc, sizeof(hc), hipMemcpyHostToDevice, c->stream));
+        const float ms = time_variant(c, desc, cnt, g.tA, g.tB, bs);
+        if (bs == 128 || ms < best) {
+            best = ms;
+            pick = bs;
+        }
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = pick;
+    return pick;
+}
+
+// ---------------------------------------------------------------------------
+// Batched fixed-budget GMRES
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// The products of one batch: for product p (0: the residual's product with
+// x, k + 1: the Arnoldi product with V_k) and each of the two GEMMs, the
+// descriptors by tile size; counts[p][gemm][tile] = {problems, tiles}.
+struct BatchLayout {
+    size_t vec_off = 0, tot_off = 0, desc_off = 0, cnt_off = 0, bytes = 0;
+    int G = 0, np = 0;
+};
+
+BatchLayout layout(int G, int np) {
+    BatchLayout l;
+    l.G = G;
+    l.np = np;
+    auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+    l.vec_off = 0;
+    l.tot_off = al(sizeof(BatchVec) * G);
+    l.desc_off = al(l.tot_off + sizeof(int) * BT_N);
+    l.cnt_off = al(l.desc_off + grouped_desc_bytes() * (size_t)np * 4 * G);
+    l.bytes = al(l.cnt_off + sizeof(int) * 2 * (size_t)np * 4);
+    return l;
+}
+
+// The launch sequence of the batched solve on stream s; every argument is
+// either fixed for the batch's size and budget or read from `dev`.
+void issue(char* dev, const BatchLayout& l, int mm, int max_cycles, hipStream_t s) {
+    const auto* d = reinterpret_cast<const BatchVec*>(dev + l.vec_off);
+    const int* tot = reinterpret_cast<const int*>(dev + l.tot_off);
+    const int G = l.G;
+    auto product = [&](int p) {
+        for (int gm = 0; gm < 2; ++gm) {
+            for (int t = 0; t < 2; ++t) {
+                const int q = (p * 2 + gm) * 2 + t;
+                const void* desc = dev + l.desc_off + grouped_desc_bytes() * (size_t)q * G;
+                const int* cnt = reinterpret_cast<const int*>(dev + l.cnt_off) + 2 * q;
+                gemm_grouped_f64(desc, cnt, false, gm == 1, t == 0 ? 128 : 64, 512, s);
+            }
+            if (gm == 0) batch_stage(d, G, tot, s);
+        }
+    };
+    batch_zero_stats(d, G, s);
+    batch_reduce(d, G, tot, 3, 1, s);
+    batch_finish(d, G, mm, 1, 3, s);
+    for (int cyc = 0; cyc < max_cycles; ++cyc) {
+        product(0);                              // V_0 = A x
+        batch_vec(d, G, tot, 3, 0, s);           // V_0 = b - V_0
+        batch_reduce(d, G, tot, 2, 1, s);
+        batch_finish(d, G, mm, 1, 4, s);         // ||r0||
+        batch_vec(d, G, tot, 4, mm, s);          // V_0 /= ||r0||
+        for (int k = 0; k < mm; ++k) {
+            product(k + 1);                      // w = A V_k
+            batch_cgs2_small(d, G, k, mm, s);
+            batch_reduce(d, G, tot, 0, k + 1, s);
+            batch_finish(d, G, k, k + 1, 0, s);
+            batch_vec(d, G, tot, 0, k, s);
+            batch_reduce(d, G, tot, 0, k + 1, s);
+            batch_finish(d, G, k, k + 1, 1, s);
+            batch_vec(d, G, tot, 1, k, s);
+            batch_reduce(d, G, tot, 1, 1, s);
+            batch_finish(d, G, k, 1, 2, s);
+            if (k + 1 < mm) batch_vec(d, G, tot, 2, k, s);
+        }
+        batch_hess(d, G, mm, true, cyc + 1 == max_cycles, s);
+        batch_vec(d, G, tot, 5, mm, s);          // x += V y
+    }
+}
+
+}  // namespace
+
+void gmres_batch(ite_ctx* c, const std::vector<BatchItem>& items, int m, int max_cycles) {
+    const int G = (int)items.size();
+    if (G == 0) return;
+    const int mm = m;
+    ITE_REQUIRE(mm >= 1 && mm <= 16, "gmres_batch: Krylov dimension must be in 1..16");
+    // workspaces, carved from one slot
+    auto al = [](size_t x) { return (x + 31) & ~size_t(31); };
+    std::vector<size_t> off(G);
+    size_t total = 0;
+    for (int g = 0; g < G; ++g) {
+        const LocalOp& op = items[g].op;
+        const size_t n = op.n();
+        ITE_REQUIRE((size_t)mm < n, "gmres_batch: Krylov dimension must be below the vector length");
+        const int I = op.s.w0 * op.s.d1 * op.s.d2, O = op.s.d1 * op.s.d2 * op.s.w2;
+        ITE_REQUIRE(I <= BATCH_STAGE_SC, "gmres_batch: more than 128 MPO-stage inputs");
+        const size_t nxi = (size_t)op.s.Dxl * std::max(I, O) * op.s.Dyr;
+        off[g] = total;
+        total += al((size_t)(mm + 1) * n) + al(n) + 2 * al(nxi) + al((size_t)reduce_blocks(n) * 64 + 64) +
+                 al((size_t)mm * HESS_HC + 8) + al(64);
+    }
+    double* ws = slot_t<double>(c, SL_BATCH, total);
+    const int np = mm + 1;
+    const BatchLayout lay = layout(G, np);
+    char* dev = static_cast<char*>(slot(c, SL_BDESC, lay.bytes));
+    std::vector<char>& host = c->batch_host;
+    host.assign(lay.bytes, 0);
+    auto* hv = reinterpret_cast<BatchVec*>(host.data() + lay.vec_off);
+    int* htot = reinterpret_cast<int*>(host.data() + lay.tot_off);
+    int* hcnt = reinterpret_cast<int*>(host.data() + lay.cnt_off);
+    std::vector<double*> X1(G), X3(G);
+    int red = 0, ew = 0, stg = 0;
+    for (int g = 0; g < G; ++g) {
+        const LocalOp& op = items[g].op;
+        const size_t n = op.n();
+        const int I = op.s.w0 * op.s.d1 * op.s.d2, O = op.s.d1 * op.s.d2 * op.s.w2;
+        const size_t nxi = (size_t)op.s.Dxl * std::max(I, O) * op.s.Dyr;
+        double* q = ws + off[g];
+        BatchVec& v = hv[g];
+        v = BatchVec{};   // the stage's default strides (the buffer itself is zeroed bytes)
+        v.n = (long)n;
+        v.nb = reduce_blocks(n);
+        v.small = n <= 8192;
+        v.V = q;
+        q += al((size_t)(mm + 1) * n);
+        v.w = q;
+        q += al(n);
+        X1[g] = q;
+        q += al(nxi);
+        X3[g] = q;
+        q += al(nxi);
+        v.part = q;
+        q += al((size_t)v.nb * 64 + 64);
+        v.hd = q;
+        q += al((size_t)mm * HESS_HC + 8);
+        v.y = q;
+        v.x = items[g].x;
+        v.b = items[g].b;
+        v.stats = items[g].stats;
+        Stage& st = v.st;
+        st.G = op.s.Dxl;
+        st.C = op.s.Dyr;
+        st.in = X1[g];
+        st.in_gs = (long)I * op.s.Dyr;
+        st.in_s1 = op.s.Dyr;
+        st.out = X3[g];
+        st.out_gs = (long)O * op.s.Dyr;
+        st.out_s1 = op.s.Dyr;
+        st.I = op.ww->I;
+        st.O = op.ww->O;
+        st.rowptr = op.ww->rowptr;
+        st.col = op.ww->col;
+        st.val = op.ww->val;
+        v.red_start = red;
+        v.ew_start = ew;
+        v.stage_start = stg;
+        red += v.nb;
+        ew += (int)((n + BATCH_EW - 1) / BATCH_EW);
+        stg += op.s.Dxl * ((op.s.Dyr + BATCH_STAGE_SC - 1) / BATCH_STAGE_SC);
+    }
+    htot[BT_RED] = red;
+    htot[BT_EW] = ew;
+    htot[BT_STAGE] = stg;
+    // grouped products: theta = x (p = 0) or V_(p-1), into V_0 or w
+    std::vector<int> tile1(G), tile2(G);
+    std::vector<Gemm> g1(G), g2(G);
+    for (int g = 0; g < G; ++g) {
+        const LocalOp& op = items[g].op;
+        const HeffShape& s = op.s;
+        Gemm& a = g1[g];
+        a.M = s.Dxl * s.w0;
+        a.N = s.d1 * s.d2 * s.Dyr;
+        a.K = s.Dyl;
+        a.alpha = 1.0;
+        a.beta = 0.0;
+        a.A = op.L;
+        a.lda = s.Dyl;
+        a.ldb = (long)s.d1 * s.d2 * s.Dyr;
+        a.D = X1[g];
+        a.ldd = a.ldb;
+        Gemm& b = g2[g];
+        b.M = s.Dxl * s.d1 * s.d2;
+        b.N = s.Dxr;
+        b.K = s.w2 * s.Dyr;
+        b.tB = true;
+        b.alpha = op.beta;
+        b.beta = op.alpha;
+        b.A = X3[g];
+        b.lda = (long)s.w2 * s.Dyr;
+        b.B = op.R;
+        b.ldb = b.lda;
+        b.ldc = s.Dxr;
+        b.ldd = s.Dxr;
+        a.B = items[g].x;
+        b.C = items[g].x;
+        b.D = hv[g].V;
+        tile1[g] = tuned_tile(c, a);
+        tile2[g] = tuned_tile(c, b);
+    }
+    for (int p = 0; p < np; ++p) {
+        for (int gm = 0; gm < 2; ++gm)
+            for (int t = 0; t < 2; ++t) {
+                const int q = (p * 2 + gm) * 2 + t, bs = t == 0 ? 128 : 64;
+                char* desc = host.data() + lay.desc_off + grouped_desc_bytes() * (size_t)q * G;
+                int cnt = 0, tiles = 0;
+                for (int g = 0; g < G; ++g) {
+                    if ((gm == 0 ? tile1[g] : tile2[g]) != bs) continue;
+                    Gemm e = gm == 0 ? g1[g] : g2[g];
+                    const double* theta = p == 0 ? items[g].x : hv[g].V + (size_t)(p - 1) * hv[g].n;
+                    if (gm == 0) e.B = theta;
+                    else {
+                        e.C = theta;
+                        e.D = p == 0 ? hv[g].V : hv[g].w;
+                    }
+                    grouped_desc_fill(e, bs, tiles, desc + grouped_desc_bytes() * cnt);
+                    tiles += grouped_tiles(e, bs);
+                    ++cnt;
+                }
+                hcnt[2 * q] = cnt;
+                hcnt[2 * q + 1] = tiles;
+            }
+    }
+    // upload (ordered before the solve on the context's stream), then run the
+    // sequence on the private stream, captured once per batch size and budget
+    HIP_CHECK(hipMemcpyAsync(dev, host.data(), lay.bytes, hipMemcpyHostToDevice, c->stream));
+    c->batch_solves++;
+    if (!c->use_graphs) {
+        issue(dev, lay, mm, max_cycles, c->stream);
+        return;
+    }
+    if (!c->side) {
+        HIP_CHECK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+        HIP_CHECK(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
+        HIP_CHECK(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
+    }
+    const long long key[5] = {G, mm, max_cycles, (long long)(uintptr_t)dev, (long long)lay.bytes};
+    if (!c->bgraph || std::memcmp(key, c->bgraph_key, sizeof(key)) != 0) {
+        if (c->bgraph) {
+            HIP_CHECK(hipStreamSynchronize(c->side));
+            HIP_CHECK(hipGraphExecDestroy(c->bgraph));
+            c->bgraph = nullptr;
+        }
+        hipGraph_t graph = nullptr;
+        HIP_CHECK(hipStreamBeginCapture(c->side, hipStreamCaptureModeThreadLocal));
+        try {
+            issue(dev, lay, mm, max_cycles, c->side);
+        } catch (...) {
+            (void)hipStreamEndCapture(c->side, &graph);
+            if (graph) (void)hipGraphDestroy(graph);
+            throw;
+        }
+        HIP_CHECK(hipStreamEndCapture(c->side, &graph));
+        hipGraphExec_t exec = nullptr;
+        const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIP_CHECK(e);
+        c->bgraph = exec;
+        std::memcpy(c->bgraph_key, key, sizeof(key));
+        c->graph_captures++;
+    }
+    HIP_CHECK(hipEventRecord(c->ev_in, c->stream));
+    HIP_CHECK(hipStreamWaitEvent(c->side, c->ev_in, 0));
+    HIP_CHECK(hipGraphLaunch(c->bgraph, c->side));
+    HIP_CHECK(hipEventRecord(c->ev_out, c->side));
+    HIP_CHECK(hipStreamWaitEvent(c->stream, c->ev_out, 0));
+    c->graph_replays++;
+}
+
+}  // namespace ite

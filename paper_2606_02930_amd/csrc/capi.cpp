@@ -144,9 +144,15 @@ int ite_ctx_destroy(ite_ctx* c) {
     if (!c) return ITE_EINVAL;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
+    if (c->side) (void)hipStreamSynchronize(c->side);
+    if (c->bgraph) (void)hipGraphExecDestroy(c->bgraph);
+    if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+    if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+    if (c->side) (void)hipStreamDestroy(c->side);
     for (int s = 0; s < SL_NSLOTS; ++s) dev_free(c, c->slot_ptr[s]);
     if (c->pinned) (void)hipHostFree(c->pinned);
     for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+    for (hipEvent_t e : c->prof_events) (void)hipEventDestroy(e);
     delete c;
     return ITE_OK;
 }
@@ -328,6 +334,35 @@ int ite_imag_step(ite_mps* psi, const ite_mpo* H, double h, const ite_step_opts*
         set_device(psi->ctx);
         imag_step(psi, H, h, *o, rep);
     });
+}
+
+int ite_step_batch(ite_ctx* c, int n, ite_mps* const* psi, const ite_mpo* const* H, const double* h,
+                   const ite_step_opts* const* opts, ite_step_report* reps, int* status) {
+    if (!c || n < 1 || !psi || !H || !h || !opts) return ITE_EINVAL;
+    int rc = guarded(c, [&] {
+        set_device(c);
+        for (int j = 0; j < n; ++j)
+            if (!psi[j] || psi[j]->ctx != c) ITE_FAIL(psi[j] ? ITE_ESTATE : ITE_EINVAL, "step_batch: state not on ctx");
+        step_batch(n, psi, H, h, opts, reps, status);
+    });
+    if (rc == ITE_OK && status)
+        for (int j = 0; j < n; ++j)
+            if (status[j] != ITE_OK) return status[j];
+    return rc;
+}
+
+int ite_ctx_set_graphs(ite_ctx* c, int enable) {
+    if (!c) return ITE_EINVAL;
+    c->use_graphs = enable != 0;
+    return ITE_OK;
+}
+
+int ite_ctx_batch_stats(ite_ctx* c, long long* solves, long long* captures, long long* replays) {
+    if (!c) return ITE_EINVAL;
+    if (solves) *solves = c->batch_solves;
+    if (captures) *captures = c->graph_captures;
+    if (replays) *replays = c->graph_replays;
+    return ITE_OK;
 }
 
 int ite_dmrg_sweeps(ite_mps* psi, const ite_mpo* H, int nsweeps, int chi_max, double cutoff, double tie_rel,

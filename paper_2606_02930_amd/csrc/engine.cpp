@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <numeric>
 
@@ -949,11 +950,12 @@ double overlap(ite_mps* a, ite_mps* b) {
 // ---------------------------------------------------------------------------
 
 namespace {
+// Device-time spans of a step's phases, from the context's event pool (the
+// caller resets the pool once per step or batch of steps).
 struct Timer {
     ite_ctx* c;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> spans;
-    size_t next = 0;
-    explicit Timer(ite_ctx* cc) : c(cc) { c->events_used = 0; }
+    explicit Timer(ite_ctx* cc) : c(cc) {}
     hipEvent_t ev() {
         if (c->events_used == c->events.size()) {
             hipEvent_t e;
@@ -979,10 +981,8 @@ struct Timer {
     }
 };
 enum { PH_TOTAL = 0, PH_RHS, PH_SOLVE, PH_SPLIT, PH_ENV, PH_N };
-}  // namespace
 
-void imag_step(ite_mps* psi, const ite_mpo* H, double h, const ite_step_opts& o, ite_step_report* rep) {
-    ite_ctx* c = psi->ctx;
+void check_step(const ite_mps* psi, const ite_mpo* H, double h, const ite_step_opts& o) {
     const int L = psi->L;
     ITE_REQUIRE(std::isfinite(h) && h > 0.0, "imag_step: h must be finite and > 0");
     if (H->L != L) ITE_FAIL(ITE_ESTATE, "imag_step: MPS and MPO lengths differ");
@@ -1002,74 +1002,135 @@ void imag_step(ite_mps* psi, const ite_mpo* H, double h, const ite_step_opts& o,
     ITE_REQUIRE(o.precision == ITE_PREC_FP64 || (o.max_refine >= 0 && o.tol_refine >= 0.0),
                 "imag_step: mixed precision needs max_refine >= 0 and tol_refine >= 0");
     ITE_REQUIRE(o.init_guess == ITE_GUESS_PSI || o.init_guess == ITE_GUESS_B, "imag_step: unknown init_guess");
-    ensure_evolution(psi, H);
+}
+}  // namespace
 
-    Timer tm(c);
-    const int t_all = tm.open(PH_TOTAL);
-    double s = o.shift;
-    if (o.shift_mode == ITE_SHIFT_TRACK) {
-        if (!psi->e_valid) {
-            psi->energy = measure_energy(psi, H);
-            psi->e_valid = true;
-        }
-        s = psi->energy;
-    }
-    const int chi = std::min(o.chi_max, psi->chi_max);
-    auto& env = psi->env;
-    auto& X = psi->X;
-    auto& XD = psi->XD;
-    const auto& P = psi->A;
-    const auto& PD = psi->D;
-    XD = PD;
-    for (int i = 0; i < L; ++i) d2d(c, X[i], P[i], (size_t)PD[i] * psi->d[i] * PD[i + 1]);
-    // boundary environments
-    fill(env[0].H, 1.0, 1, c->stream);
-    fill(env[0].Hp, 1.0, 1, c->stream);
-    fill(env[0].O, 1.0, 1, c->stream);
-    fill(env[L].H, 1.0, 1, c->stream);
-    fill(env[L].Hp, 1.0, 1, c->stream);
-    fill(env[L].O, 1.0, 1, c->stream);
-    env[0].hp_alias = env[0].o_ident = false;
-    env[L].hp_alias = env[L].o_ident = false;
-    for (int b = L - 1; b >= 2; --b) {
-        env_right(c, XD[b + 1], XD[b + 1], XD[b], XD[b], psi->d[b], H->w[b], H->w[b + 1], env[b + 1].H, X[b],
-                  &H->right[b], X[b], env[b].H);
-    }
-    for (int b = 2; b < L; ++b) {
-        env[b].hp_alias = true;
-        env[b].o_ident = true;
-    }
-
+// One implicit step of one state, split into the phases of a block so that a
+// batch of states can sweep in lockstep (step_batch): the constructor does
+// the step's set-up (shift, x <- psi, right environments), then for every
+// slot of the sweep rhs() forms b and the initial guess of the block,
+// solve() (or a batched solve) the local problem, split_env() the split and
+// the environment updates; finish() normalises and replaces psi.
+struct StepRun {
+    ite_mps* psi;
+    const ite_mpo* H;
+    ite_step_opts o;
+    ite_ctx* c;
+    int L, chi, refine, nblocks;
+    double h, s, acoef;
+    Timer tm;
+    int t_all = -1;
     ite_step_report r{};
-    r.h = h;
-    r.shift = s;
-    r.dtau = o.scheme == ITE_SCHEME_TRAP ? 2.0 * h : h;
-    const double acoef = 1.0 - h * s;
     int nres = 0;
     double sum_res = 0.0;
-    // device records of the local solves that report there (fixed budget,
-    // FP64): read once after the sweeps
-    const int nblocks = 2 * (L - 1) * o.nsweeps;
-    double* stats_dev = slot_t<double>(c, SL_STATS, (size_t)8 * nblocks + 8);
-    std::vector<char> deferred(nblocks, 0);
-    int blk = 0;
-    // refinement rounds: 0 picks the cheapest count that keeps the step
-    // within 1e-8 relative energy of the FP64 step at the fixed budget
-    // (measured: FP32 operands 1e-12 after one correction; BF16 operands
-    // 3e-7 after one, 1e-10 after two)
-    const int refine = o.max_refine > 0 ? o.max_refine : (o.precision == ITE_PREC_BF16_IR ? 2 : 1);
-    // Appendix B: the right-hand side is the initial guess of the solve; in
-    // x's (= psi's) basis that is b_loc itself on the step's first block
-    bool guess_b = o.init_guess == ITE_GUESS_B;
+    double* stats_dev;
+    std::vector<char> deferred;
+    bool guess_b;
+    // the block of the current slot
+    int bi = 0, bdir = 0, blk = 0;
+    double* bvec = nullptr;
+    double* th = nullptr;
+    LocalOp op;
 
-    auto block = [&](int i, int dir) {
+    StepRun(ite_mps* p, const ite_mpo* Hm, double hh, const ite_step_opts& oo, double* stats)
+        : psi(p), H(Hm), o(oo), c(p->ctx), h(hh), tm(p->ctx), stats_dev(stats) {
+        check_step(psi, H, h, o);
+        ensure_evolution(psi, H);
+        L = psi->L;
+        nblocks = 2 * (L - 1) * o.nsweeps;
+        t_all = tm.open(PH_TOTAL);
+        s = o.shift;
+        if (o.shift_mode == ITE_SHIFT_TRACK) {
+            if (!psi->e_valid) {
+                psi->energy = measure_energy(psi, H);
+                psi->e_valid = true;
+            }
+            s = psi->energy;
+        }
+        chi = std::min(o.chi_max, psi->chi_max);
+        auto& env = psi->env;
+        auto& X = psi->X;
+        auto& XD = psi->XD;
+        const auto& P = psi->A;
+        const auto& PD = psi->D;
+        XD = PD;
+        for (int i = 0; i < L; ++i) d2d(c, X[i], P[i], (size_t)PD[i] * psi->d[i] * PD[i + 1]);
+        // boundary environments
+        fill(env[0].H, 1.0, 1, c->stream);
+        fill(env[0].Hp, 1.0, 1, c->stream);
+        fill(env[0].O, 1.0, 1, c->stream);
+        fill(env[L].H, 1.0, 1, c->stream);
+        fill(env[L].Hp, 1.0, 1, c->stream);
+        fill(env[L].O, 1.0, 1, c->stream);
+        env[0].hp_alias = env[0].o_ident = false;
+        env[L].hp_alias = env[L].o_ident = false;
+        for (int b = L - 1; b >= 2; --b) {
+            env_right(c, XD[b + 1], XD[b + 1], XD[b], XD[b], psi->d[b], H->w[b], H->w[b + 1], env[b + 1].H, X[b],
+                      &H->right[b], X[b], env[b].H);
+        }
+        for (int b = 2; b < L; ++b) {
+            env[b].hp_alias = true;
+            env[b].o_ident = true;
+        }
+        r.h = h;
+        r.shift = s;
+        r.dtau = o.scheme == ITE_SCHEME_TRAP ? 2.0 * h : h;
+        acoef = 1.0 - h * s;
+        // refinement rounds: 0 picks the cheapest count that keeps the step
+        // within 1e-8 relative energy of the FP64 step at the fixed budget
+        // (measured: FP32 operands 1e-12 after one correction; BF16 operands
+        // 3e-7 after one, 1e-10 after two)
+        refine = o.max_refine > 0 ? o.max_refine : (o.precision == ITE_PREC_BF16_IR ? 2 : 1);
+        // Appendix B: the right-hand side is the initial guess of the solve; in
+        // x's (= psi's) basis that is b_loc itself on the step's first block
+        guess_b = o.init_guess == ITE_GUESS_B;
+        deferred.assign(nblocks, 0);
+    }
+
+    // Sweep order: left to right, then right to left, nsweeps times.
+    void slot_block(int slot, int& i, int& dir) const {
+        const int t = slot % (2 * (L - 1));
+        if (t < L - 1) {
+            i = t;
+            dir = 0;
+        } else {
+            i = L - 2 - (t - (L - 1));
+            dir = 1;
+        }
+    }
+    size_t block_n(int slot) const {
+        int i, dir;
+        slot_block(slot, i, dir);
+        return (size_t)psi->XD[i] * psi->d[i] * psi->d[i + 1] * psi->XD[i + 2];
+    }
+    // A local solve the batched GMRES takes: FP64, fixed budget, Krylov
+    // dimension below the vector length and at most 16.
+    bool batchable(int slot) const {
+        int i, dir;
+        slot_block(slot, i, dir);
+        const int I = H->w[i] * psi->d[i] * psi->d[i + 1];
+        return o.precision == ITE_PREC_FP64 && o.tol_loc <= 0.0 && o.krylov_dim <= 16 &&
+               (size_t)o.krylov_dim < block_n(slot) && I <= BATCH_STAGE_SC;
+    }
+
+    // b and the initial guess of the slot's block into bv and thv (length
+    // block_n); sets op.
+    void rhs(int slot, double* bv, double* thv) {
+        slot_block(slot, bi, bdir);
+        blk = slot;
+        bvec = bv;
+        th = thv;
+        const int i = bi;
+        auto& env = psi->env;
+        auto& X = psi->X;
+        auto& XD = psi->XD;
+        const auto& P = psi->A;
+        const auto& PD = psi->D;
         const int d1 = psi->d[i], d2 = psi->d[i + 1];
         const int Dl = XD[i], Dr = XD[i + 2], Dpl = PD[i], Dpr = PD[i + 2];
         const size_t npsi = (size_t)Dpl * d1 * d2 * Dpr;
         const size_t nx = (size_t)Dl * d1 * d2 * Dr;
         double* tpsi = slot_t<double>(c, SL_TPSI, npsi);
-        double* bvec = slot_t<double>(c, SL_B, nx);
-        double* th = slot_t<double>(c, SL_TH, nx);
         const int t_rhs = tm.open(PH_RHS);
         two_site(c, Dpl, d1, PD[i + 1], d2, Dpr, P[i], P[i + 1], tpsi);
         const double* Lo = env[i].o_ident ? nullptr : env[i].O;
@@ -1086,126 +1147,237 @@ void imag_step(ite_mps* psi, const ite_mpo* H, double h, const ite_step_opts& o,
         else two_site(c, Dl, d1, XD[i + 1], d2, Dr, X[i], X[i + 1], th);
         guess_b = false;
         tm.close(t_rhs);
-        const int t_solve = tm.open(PH_SOLVE);
-        LocalOp op;
         op.s = HeffShape{Dl, Dl, Dr, Dr, d1, d2, H->w[i], H->w[i + 2]};
         op.L = env[i].H;
         op.R = env[i + 2].H;
         op.ww = &H->pair[i];
         op.alpha = acoef;
         op.beta = h;
-        SolveStats ss = local_solve(c, op, bvec, th, o.krylov_dim, o.max_cycles, o.tol_loc, o.precision,
-                                    refine, o.tol_refine, stats_dev + (size_t)8 * blk);
+    }
+    double* stats_of(int slot) const { return stats_dev + (size_t)8 * slot; }
+
+    void solve() {
+        const int t_solve = tm.open(PH_SOLVE);
+        SolveStats ss = local_solve(c, op, bvec, th, o.krylov_dim, o.max_cycles, o.tol_loc, o.precision, refine,
+                                    o.tol_refine, stats_of(blk));
         tm.close(t_solve);
-        if (ss.deferred) {
-            deferred[blk] = 1;
-        } else {
-            r.matvecs_fp64 += ss.matvecs64;
-            r.matvecs_lo += ss.matvecs_lo;
-            r.flags |= ss.flags;
-            r.max_res_rel = std::max(r.max_res_rel, ss.res_rel);
-            sum_res += ss.res_rel;
-            ++nres;
-        }
-        ++blk;
+        if (ss.deferred) deferred[blk] = 1;
+        else add(ss);
+    }
+    void add(const SolveStats& ss) {
+        r.matvecs_fp64 += ss.matvecs64;
+        r.matvecs_lo += ss.matvecs_lo;
+        r.flags |= ss.flags;
+        r.max_res_rel = std::max(r.max_res_rel, ss.res_rel);
+        sum_res += ss.res_rel;
+        ++nres;
+    }
+
+    void split_env() {
+        const int i = bi;
+        auto& env = psi->env;
+        auto& X = psi->X;
+        auto& XD = psi->XD;
+        const auto& P = psi->A;
+        const auto& PD = psi->D;
+        const int d1 = psi->d[i], d2 = psi->d[i + 1];
         const int t_split = tm.open(PH_SPLIT);
-        SplitResult sp = split(c, dir, Dl, d1, d2, Dr, th, chi, o.cutoff, o.tie_rel, X[i], X[i + 1], nullptr);
+        SplitResult sp = split(c, bdir, XD[i], d1, d2, XD[i + 2], th, chi, o.cutoff, o.tie_rel, X[i], X[i + 1],
+                               nullptr);
         tm.close(t_split);
         XD[i + 1] = sp.k;
         r.max_disc = std::max(r.max_disc, sp.disc);
         r.sum_disc += sp.disc;
-    };
-
-    for (int sw = 0; sw < o.nsweeps; ++sw) {
-        for (int i = 0; i + 1 < L; ++i) {
-            block(i, 0);
-            if (i + 2 < L) {
-                const int t_env = tm.open(PH_ENV);
-                const int b = i + 1;
-                // <x|H|x>, <x|H|psi>, <x|psi> at bond i+1 from bond i
-                env_left(c, XD[i], XD[i], XD[b], XD[b], psi->d[i], H->w[i], H->w[b], env[i].H, X[i], &H->left[i],
-                         X[i], env[b].H);
-                const double* Ehp = env[i].hp_alias ? env[i].H : env[i].Hp;
-                env_left(c, XD[i], PD[i], XD[b], PD[b], psi->d[i], H->w[i], H->w[b], Ehp, X[i], &H->left[i], P[i],
-                         env[b].Hp);
-                env_left(c, XD[i], PD[i], XD[b], PD[b], psi->d[i], 1, 1, env[i].O, X[i], nullptr, P[i], env[b].O);
-                env[b].hp_alias = false;
-                env[b].o_ident = false;
-                tm.close(t_env);
-            }
-        }
-        for (int i = L - 2; i >= 0; --i) {
-            block(i, 1);
-            if (i > 0) {
-                const int t_env = tm.open(PH_ENV);
-                const int b = i + 1, a = i + 2;
-                env_right(c, XD[a], XD[a], XD[b], XD[b], psi->d[b], H->w[b], H->w[a], env[a].H, X[b],
-                          &H->right[b], X[b], env[b].H);
-                const double* Ehp = env[a].hp_alias ? env[a].H : env[a].Hp;
-                env_right(c, XD[a], PD[a], XD[b], PD[b], psi->d[b], H->w[b], H->w[a], Ehp, X[b], &H->right[b],
-                          P[b], env[b].Hp);
-                if (env[a].o_ident) {
-                    // <x|psi> with identity to the right: plain overlap of the site tensors
-                    double* Eid = slot_t<double>(c, SL_TMPA, (size_t)XD[a] * XD[a]);
-                    eye(Eid, XD[a], c->stream);
-                    env_right_overlap_pub(c, H->ident[psi->d[b]], XD[a], PD[a], XD[b], PD[b], psi->d[b], Eid, X[b], P[b],
+        if (bdir == 0 && i + 2 < L) {
+            const int t_env = tm.open(PH_ENV);
+            const int b = i + 1;
+            // <x|H|x>, <x|H|psi>, <x|psi> at bond i+1 from bond i
+            env_left(c, XD[i], XD[i], XD[b], XD[b], psi->d[i], H->w[i], H->w[b], env[i].H, X[i], &H->left[i], X[i],
+                     env[b].H);
+            const double* Ehp = env[i].hp_alias ? env[i].H : env[i].Hp;
+            env_left(c, XD[i], PD[i], XD[b], PD[b], psi->d[i], H->w[i], H->w[b], Ehp, X[i], &H->left[i], P[i],
+                     env[b].Hp);
+            env_left(c, XD[i], PD[i], XD[b], PD[b], psi->d[i], 1, 1, env[i].O, X[i], nullptr, P[i], env[b].O);
+            env[b].hp_alias = false;
+            env[b].o_ident = false;
+            tm.close(t_env);
+        } else if (bdir == 1 && i > 0) {
+            const int t_env = tm.open(PH_ENV);
+            const int b = i + 1, a = i + 2;
+            env_right(c, XD[a], XD[a], XD[b], XD[b], psi->d[b], H->w[b], H->w[a], env[a].H, X[b], &H->right[b], X[b],
+                      env[b].H);
+            const double* Ehp = env[a].hp_alias ? env[a].H : env[a].Hp;
+            env_right(c, XD[a], PD[a], XD[b], PD[b], psi->d[b], H->w[b], H->w[a], Ehp, X[b], &H->right[b], P[b],
+                      env[b].Hp);
+            if (env[a].o_ident) {
+                // <x|psi> with identity to the right: plain overlap of the site tensors
+                double* Eid = slot_t<double>(c, SL_TMPA, (size_t)XD[a] * XD[a]);
+                eye(Eid, XD[a], c->stream);
+                env_right_overlap_pub(c, H->ident[psi->d[b]], XD[a], PD[a], XD[b], PD[b], psi->d[b], Eid, X[b], P[b],
                                       env[b].O);
-                } else {
-                    env_right_overlap_pub(c, H->ident[psi->d[b]], XD[a], PD[a], XD[b], PD[b], psi->d[b], env[a].O, X[b],
+            } else {
+                env_right_overlap_pub(c, H->ident[psi->d[b]], XD[a], PD[a], XD[b], PD[b], psi->d[b], env[a].O, X[b],
                                       P[b], env[b].O);
-                }
-                env[b].hp_alias = false;
-                env[b].o_ident = false;
-                tm.close(t_env);
             }
+            env[b].hp_alias = false;
+            env[b].o_ident = false;
+            tm.close(t_env);
         }
     }
-    if (std::find(deferred.begin(), deferred.end(), 1) != deferred.end()) {
+
+    // The records of the deferred solves (read by the caller into `host`).
+    bool any_deferred() const { return std::find(deferred.begin(), deferred.end(), 1) != deferred.end(); }
+    void add_deferred(const double* host) {
+        for (int k = 0; k < nblocks; ++k)
+            if (deferred[k]) add(stats_from(host + (size_t)8 * k, false));
+    }
+
+    // Normalise the centre, measure, psi <- x.  Throws ENONFINITE (psi
+    // unchanged) for a non-finite state.
+    void finish(ite_step_report* rep) {
+        auto& X = psi->X;
+        auto& XD = psi->XD;
+        // normalise the centre (site 1) and measure
+        const size_t n0 = (size_t)XD[0] * psi->d[0] * XD[1];
+        const double nrm2 = dot(c, X[0], X[0], n0);
+        const double nrm = std::sqrt(std::max(nrm2, 0.0));
+        bool finite = std::isfinite(nrm) && nrm > 0.0;
+        double E = 0.0;
+        if (finite) {
+            scale(X[0], 1.0 / nrm, n0, c->stream);
+            E = centre_energy(c, H, X, XD, psi->env[2].H);
+            finite = std::isfinite(E);
+        }
+        tm.close(t_all);
+        double ms[PH_N] = {0, 0, 0, 0, 0};
+        tm.collect(ms);
+        if (!finite) ITE_FAIL(ITE_ENONFINITE, "imag_step: non-finite state; psi left unchanged");
+        // psi <- x
+        std::swap(psi->A, psi->X);
+        std::swap(psi->D, psi->XD);
+        psi->tau += r.dtau;
+        psi->energy = E;
+        psi->e_valid = true;
+        r.tau = psi->tau;
+        r.energy = E;
+        r.norm_before = nrm;
+        r.max_chi = *std::max_element(psi->D.begin(), psi->D.end());
+        r.mean_res_rel = nres ? sum_res / nres : 0.0;
+        r.ms_total = ms[PH_TOTAL];
+        r.ms_rhs = ms[PH_RHS];
+        r.ms_solve = ms[PH_SOLVE];
+        r.ms_split = ms[PH_SPLIT];
+        r.ms_env = ms[PH_ENV];
+        if (rep) *rep = r;
+    }
+};
+
+void imag_step(ite_mps* psi, const ite_mpo* H, double h, const ite_step_opts& o, ite_step_report* rep) {
+    ite_ctx* c = psi->ctx;
+    check_step(psi, H, h, o);
+    c->events_used = 0;
+    const int nblocks = 2 * (psi->L - 1) * o.nsweeps;
+    StepRun run(psi, H, h, o, slot_t<double>(c, SL_STATS, (size_t)8 * nblocks + 8));
+    for (int slot = 0; slot < run.nblocks; ++slot) {
+        const size_t nx = run.block_n(slot);
+        run.rhs(slot, slot_t<double>(c, SL_B, nx), slot_t<double>(c, SL_TH, nx));
+        run.solve();
+        run.split_env();
+    }
+    if (run.any_deferred()) {
         double* host = pinned(c, (size_t)8 * nblocks + 64);
-        d2h(c, host, stats_dev, (size_t)8 * nblocks);
+        d2h(c, host, run.stats_dev, (size_t)8 * nblocks);
         sync(c);
-        for (int k = 0; k < nblocks; ++k) {
-            if (!deferred[k]) continue;
-            const SolveStats ss = stats_from(host + (size_t)8 * k, false);
-            r.matvecs_fp64 += ss.matvecs64;
-            r.flags |= ss.flags;
-            r.max_res_rel = std::max(r.max_res_rel, ss.res_rel);
-            sum_res += ss.res_rel;
-            ++nres;
+        run.add_deferred(host);
+    }
+    run.finish(rep);
+}
+
+// A batch of steps in lockstep: every state's sweep advances one block slot
+// at a time; the slot's right-hand sides and guesses are formed state by
+// state, the local solves that the batched GMRES takes run together
+// (gmres_batch), the others one by one, then every state splits and updates
+// its environments.  States with shorter sweeps drop out when theirs end.
+// The per-state buffers of b and the guess persist across the phases of a
+// slot, so they are carved per state from one slot of the context.
+void step_batch(int n, ite_mps* const* psi, const ite_mpo* const* H, const double* h,
+                const ite_step_opts* const* opts, ite_step_report* reps, int* status) {
+    ITE_REQUIRE(n >= 1, "step_batch: n must be >= 1");
+    ite_ctx* c = psi[0]->ctx;
+    for (int j = 0; j < n; ++j) {
+        ITE_REQUIRE(psi[j] && H[j] && opts[j], "step_batch: NULL state, Hamiltonian or options");
+        if (psi[j]->ctx != c || H[j]->ctx != c) ITE_FAIL(ITE_ESTATE, "step_batch: every object must share one context");
+        for (int q = 0; q < j; ++q)
+            if (psi[q] == psi[j]) ITE_FAIL(ITE_EINVAL, "step_batch: a state appears twice");
+        check_step(psi[j], H[j], h[j], *opts[j]);
+    }
+    c->events_used = 0;
+    // per-state records and b / guess buffers
+    std::vector<size_t> soff(n), boff(n), bmax(n);
+    size_t stot = 0, btot = 0;
+    for (int j = 0; j < n; ++j) {
+        const ite_mps* p = psi[j];
+        size_t mx = 1;
+        for (int i = 0; i + 1 < p->L; ++i)
+            mx = std::max(mx, (size_t)p->Dcap[i] * p->d[i] * p->d[i + 1] * p->Dcap[i + 2]);
+        bmax[j] = (mx + 31) & ~size_t(31);
+        boff[j] = btot;
+        btot += 2 * bmax[j];
+        soff[j] = stot;
+        stot += (size_t)8 * 2 * (p->L - 1) * opts[j]->nsweeps + 32;
+    }
+    double* sbase = slot_t<double>(c, SL_STATS, stot);
+    double* bbase = slot_t<double>(c, SL_BATCHB, btot);
+    std::vector<std::unique_ptr<StepRun>> runs(n);
+    int maxslots = 0;
+    for (int j = 0; j < n; ++j) {
+        runs[j].reset(new StepRun(psi[j], H[j], h[j], *opts[j], sbase + soff[j]));
+        maxslots = std::max(maxslots, runs[j]->nblocks);
+    }
+    // batches by budget (Krylov dimension and cycles)
+    for (int slot = 0; slot < maxslots; ++slot) {
+        std::map<std::pair<int, int>, std::vector<int>> groups;
+        for (int j = 0; j < n; ++j) {
+            StepRun& r = *runs[j];
+            if (slot >= r.nblocks) continue;
+            double* bv = bbase + boff[j];
+            r.rhs(slot, bv, bv + bmax[j]);
+            if (r.batchable(slot)) groups[{r.o.krylov_dim, r.o.max_cycles}].push_back(j);
+            else r.solve();
+        }
+        for (auto& grp : groups) {
+            std::vector<BatchItem> items;
+            std::vector<int> spans;
+            for (int j : grp.second) {
+                StepRun& r = *runs[j];
+                items.push_back(BatchItem{r.op, r.bvec, r.th, r.stats_of(slot)});
+                r.deferred[slot] = 1;
+                spans.push_back(r.tm.open(PH_SOLVE));
+            }
+            gmres_batch(c, items, grp.first.first, grp.first.second);
+            for (size_t q = 0; q < grp.second.size(); ++q) runs[grp.second[q]]->tm.close(spans[q]);
+        }
+        for (int j = 0; j < n; ++j)
+            if (slot < runs[j]->nblocks) runs[j]->split_env();
+    }
+    bool any = false;
+    for (int j = 0; j < n; ++j) any = any || runs[j]->any_deferred();
+    if (any) {
+        double* host = pinned(c, stot + 64);
+        d2h(c, host, sbase, stot);
+        sync(c);
+        for (int j = 0; j < n; ++j) runs[j]->add_deferred(host + soff[j]);
+    }
+    for (int j = 0; j < n; ++j) {
+        try {
+            runs[j]->finish(reps ? &reps[j] : nullptr);
+            if (status) status[j] = ITE_OK;
+        } catch (const Error& e) {
+            if (!status) throw;
+            status[j] = e.code;
+            c->err = e.what();
         }
     }
-    // normalise the centre (site 1) and measure
-    const size_t n0 = (size_t)XD[0] * psi->d[0] * XD[1];
-    const double nrm2 = dot(c, X[0], X[0], n0);
-    const double nrm = std::sqrt(std::max(nrm2, 0.0));
-    bool finite = std::isfinite(nrm) && nrm > 0.0;
-    double E = 0.0;
-    if (finite) {
-        scale(X[0], 1.0 / nrm, n0, c->stream);
-        E = centre_energy(c, H, X, XD, env[2].H);
-        finite = std::isfinite(E);
-    }
-    tm.close(t_all);
-    double ms[PH_N] = {0, 0, 0, 0, 0};
-    tm.collect(ms);
-    if (!finite) ITE_FAIL(ITE_ENONFINITE, "imag_step: non-finite state; psi left unchanged");
-    // psi <- x
-    std::swap(psi->A, psi->X);
-    std::swap(psi->D, psi->XD);
-    psi->tau += r.dtau;
-    psi->energy = E;
-    psi->e_valid = true;
-    r.tau = psi->tau;
-    r.energy = E;
-    r.norm_before = nrm;
-    r.max_chi = *std::max_element(psi->D.begin(), psi->D.end());
-    r.mean_res_rel = nres ? sum_res / nres : 0.0;
-    r.ms_total = ms[PH_TOTAL];
-    r.ms_rhs = ms[PH_RHS];
-    r.ms_solve = ms[PH_SOLVE];
-    r.ms_split = ms[PH_SPLIT];
-    r.ms_env = ms[PH_ENV];
-    if (rep) *rep = r;
 }
 
 // ---------------------------------------------------------------------------

@@ -22,6 +22,8 @@ enum SlotId {
     SL_R64, SL_D64,                // refinement residual and correction
     SL_HESS,                       // Hessenberg columns of a fixed-budget GMRES cycle
     SL_STATS,                      // per-block device records of the local solves of a step
+    SL_BATCH, SL_BDESC, SL_BATCHB, // batched solves: workspaces, descriptors, per-state b and guess
+    SL_TUNE,                       // tile autotuner: trial output
     SL_NSLOTS
 };
 
@@ -48,6 +50,16 @@ struct ite_ctx {
     long long prof_timed[ite::PK_COUNT] = {};
     double prof_ms[ite::PK_COUNT] = {};
     double prof_flops[ite::PK_COUNT] = {}, prof_bytes[ite::PK_COUNT] = {};
+    // batched solves: a private stream (ordered after `stream` by events) on
+    // which the launch sequence of a batch is captured once as a graph and
+    // replayed while the batch keeps its size and budget
+    bool use_graphs = true;
+    hipStream_t side = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    hipGraphExec_t bgraph = nullptr;
+    long long bgraph_key[5] = {};
+    long long graph_captures = 0, graph_replays = 0, batch_solves = 0;
+    std::vector<char> batch_host;   // host image of the batch descriptors (kept until the next batch)
 };
 
 // Sparse small matrix in CSR form on the device.
@@ -169,6 +181,26 @@ struct LocalOp {
 // figures there (SolveStats::deferred; [0] residual, [1] products, [2] flags).
 SolveStats local_solve(ite_ctx* c, const LocalOp& op, const double* b, double* x, int m, int max_cycles,
                        double tol, int precision, int max_refine, double tol_refine, double* stats_dev = nullptr);
+
+// One local solve of a batch: the operator, the right-hand side, the
+// solution (initial guess on entry) and the device record of its figures.
+struct BatchItem {
+    LocalOp op;
+    const double* b;
+    double* x;
+    double* stats;
+};
+// Fixed-budget FP64 GMRES(m) of every item at once (grouped products and
+// batched vector kernels, captured as a graph when the context allows):
+// item by item the same arithmetic as local_solve with a device record.
+// Every item needs m < n, m <= 16 and at most 128 MPO-stage inputs.
+void gmres_batch(ite_ctx* c, const std::vector<BatchItem>& items, int m, int max_cycles);
+// Tile size (128 or 64) the autotuner picked for an FP64 GEMM shape.
+int tuned_tile(ite_ctx* c, const Gemm& g);
+// One implicit step of every state (ite_step_batch); status[j] gets each
+// state's status (a failed state is left unchanged).
+void step_batch(int n, ite_mps* const* psi, const ite_mpo* const* H, const double* h,
+                const ite_step_opts* const* opts, ite_step_report* reps, int* status);
 
 double dot(ite_ctx* c, const double* x, const double* y, size_t n);
 

@@ -22,6 +22,8 @@
 // L2.
 #include "internal.h"
 
+#include <cstring>
+
 namespace ite {
 namespace {
 
@@ -71,58 +73,59 @@ __device__ inline int xcd_band_tile(int bid, int T) {
     return base + idx;
 }
 
-// Stage one K slice of an operand into registers.  KC: the source is stored
-// with K contiguous (rows of the 128-wide tile side are strided by ld);
-// otherwise K is the slow index (rows are K, the tile side is contiguous).
-template <typename T, bool KC>
+// Stage one K slice of an operand into registers (BS = 128 or 64 rows of the
+// tile side, E = BS * 16 / 256 values per thread).  KC: the source is stored
+// with K contiguous (rows of the tile side are strided by ld); otherwise K is
+// the slow index (rows are K, the tile side is contiguous).
+template <typename T, bool KC, int BS>
 __device__ inline void fetch_slice(const T* __restrict__ src, long ld, int side0, int sideN, int k0,
-                                   int K, int t, T (&r)[8]) {
+                                   int K, int t, T (&r)[BS / 16]) {
+    constexpr int E = BS / 16;
     if (KC) {
         const int kk = t & 15;
         const int k = k0 + kk;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
+        for (int e = 0; e < E; ++e) {
             const int row = side0 + (t >> 4) + 16 * e;
             r[e] = (row < sideN && k < K) ? src[(long)row * ld + k] : T(0);
         }
     } else {
-        const int col = side0 + (t & 127);
-        const int kh = (t >> 7) * 8;
+        const int col = side0 + (t % BS);
+        const int kh = (t / BS) * E;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
+        for (int e = 0; e < E; ++e) {
             const int k = k0 + kh + e;
             r[e] = (col < sideN && k < K) ? src[(long)k * ld + col] : T(0);
         }
     }
 }
 
-template <typename T, bool KC>
-__device__ inline void store_slice(T* __restrict__ lds, int t, const T (&r)[8]) {
-    constexpr int LDK = MfmaOp<T>::LDK;
+template <typename T, bool KC, int BS>
+__device__ inline void store_slice(T* __restrict__ lds, int t, const T (&r)[BS / 16]) {
+    constexpr int LDK = MfmaOp<T>::LDK, E = BS / 16;
     if (KC) {
         const int kk = t & 15;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) lds[((t >> 4) + 16 * e) * LDK + kk] = r[e];
+        for (int e = 0; e < E; ++e) lds[((t >> 4) + 16 * e) * LDK + kk] = r[e];
     } else {
-        const int row = t & 127;
-        const int kh = (t >> 7) * 8;
+        const int row = t % BS;
+        const int kh = (t / BS) * E;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) lds[row * LDK + kh + e] = r[e];
+        for (int e = 0; e < E; ++e) lds[row * LDK + kh + e] = r[e];
     }
 }
 
-template <typename T, bool TA, bool TB>
-__global__ __launch_bounds__(NTHREADS, 2) void gemm_kernel(Params p) {
+// One BS x BS output tile at (m0, n0) of problem p (batch index bz): four
+// wavefronts in a 2 x 2 arrangement, each owning (BS / 2)^2 outputs as
+// (BS / 32)^2 MFMA tiles of 16 x 16.  The K order of every output element
+// (slices of 16, four sub-steps, lane group g supplying K index 4 g + step)
+// does not depend on BS, so the 128 and 64 tiles give the same bits.  As, Bs:
+// LDS of two slices of each operand.  Ends with a barrier after the last LDS
+// read, so the caller may start another tile.
+template <typename T, bool TA, bool TB, int BS>
+__device__ __forceinline__ void gemm_tile(const Params& p, int m0, int n0, long bz, T* As, T* Bs) {
     typedef typename MfmaOp<T>::acc_t acc_t;
-    constexpr int LDK = MfmaOp<T>::LDK;
-    __shared__ T As[2][BM * LDK];
-    __shared__ T Bs[2][BN * LDK];
-
-    const int T_tiles = p.mt * p.nt;
-    const int tile = xcd_band_tile(blockIdx.x, T_tiles);
-    const int m0 = (tile / p.nt) * BM;
-    const int n0 = (tile % p.nt) * BN;
-    const long bz = blockIdx.z;
+    constexpr int LDK = MfmaOp<T>::LDK, IT = BS / 32, E = BS / 16;
     const T* __restrict__ A = static_cast<const T*>(p.A) + bz * p.sA;
     const T* __restrict__ B = static_cast<const T*>(p.B) + bz * p.sB;
 
@@ -132,55 +135,57 @@ __global__ __launch_bounds__(NTHREADS, 2) void gemm_kernel(Params p) {
     const int wm = wave >> 1, wn = wave & 1;
     const int l16 = lane & 15, kg = lane >> 4;
 
-    acc_t acc[4][4];
+    acc_t acc[IT][IT];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < IT; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
+        for (int j = 0; j < IT; ++j) acc[i][j] = acc_t{0, 0, 0, 0};
 
     // A: K-contiguous unless transposed.  B: K-contiguous only when transposed.
-    T ra[8], rb[8];
+    T ra[E], rb[E];
     const int nk = (p.K + BK - 1) / BK;
-    fetch_slice<T, !TA>(A, p.lda, m0, p.M, 0, p.K, t, ra);
-    fetch_slice<T, TB>(B, p.ldb, n0, p.N, 0, p.K, t, rb);
-    store_slice<T, !TA>(As[0], t, ra);
-    store_slice<T, TB>(Bs[0], t, rb);
+    fetch_slice<T, !TA, BS>(A, p.lda, m0, p.M, 0, p.K, t, ra);
+    fetch_slice<T, TB, BS>(B, p.ldb, n0, p.N, 0, p.K, t, rb);
+    store_slice<T, !TA, BS>(As, t, ra);
+    store_slice<T, TB, BS>(Bs, t, rb);
     __syncthreads();
 
     for (int kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
         const bool more = kt + 1 < nk;
+        const T* Ac = As + cur * BS * LDK;
+        const T* Bc = Bs + cur * BS * LDK;
         if (more) {
-            fetch_slice<T, !TA>(A, p.lda, m0, p.M, (kt + 1) * BK, p.K, t, ra);
-            fetch_slice<T, TB>(B, p.ldb, n0, p.N, (kt + 1) * BK, p.K, t, rb);
+            fetch_slice<T, !TA, BS>(A, p.lda, m0, p.M, (kt + 1) * BK, p.K, t, ra);
+            fetch_slice<T, TB, BS>(B, p.ldb, n0, p.N, (kt + 1) * BK, p.K, t, rb);
         }
         // two sub-steps of the slice at a time: 16 operand values live
         // instead of 32, which leaves room for two workgroups per CU
 #pragma unroll
         for (int s2 = 0; s2 < 4; s2 += 2) {
-            T a[4][2], b[4][2];
+            T a[IT][2], b[IT][2];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const T* src = &As[cur][(wm * 64 + i * 16 + l16) * LDK + 4 * kg + s2];
+            for (int i = 0; i < IT; ++i) {
+                const T* src = &Ac[(wm * (BS / 2) + i * 16 + l16) * LDK + 4 * kg + s2];
                 a[i][0] = src[0];
                 a[i][1] = src[1];
             }
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const T* src = &Bs[cur][(wn * 64 + j * 16 + l16) * LDK + 4 * kg + s2];
+            for (int j = 0; j < IT; ++j) {
+                const T* src = &Bc[(wn * (BS / 2) + j * 16 + l16) * LDK + 4 * kg + s2];
                 b[j][0] = src[0];
                 b[j][1] = src[1];
             }
 #pragma unroll
             for (int s = 0; s < 2; ++s)
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
+                for (int i = 0; i < IT; ++i)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) acc[i][j] = MfmaOp<T>::mma(a[i][s], b[j][s], acc[i][j]);
+                    for (int j = 0; j < IT; ++j) acc[i][j] = MfmaOp<T>::mma(a[i][s], b[j][s], acc[i][j]);
         }
         if (more) {
-            store_slice<T, !TA>(As[cur ^ 1], t, ra);
-            store_slice<T, TB>(Bs[cur ^ 1], t, rb);
+            store_slice<T, !TA, BS>(As + (cur ^ 1) * BS * LDK, t, ra);
+            store_slice<T, TB, BS>(Bs + (cur ^ 1) * BS * LDK, t, rb);
         }
         __syncthreads();
     }
@@ -190,13 +195,13 @@ __global__ __launch_bounds__(NTHREADS, 2) void gemm_kernel(Params p) {
     const double* __restrict__ C = p.C ? p.C + bz * p.sC : nullptr;
     double* __restrict__ D = p.D + bz * p.sD;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < IT; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int col = n0 + wn * 64 + j * 16 + l16;
+        for (int j = 0; j < IT; ++j) {
+            const int col = n0 + wn * (BS / 2) + j * 16 + l16;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int row = m0 + wm * 64 + i * 16 + MfmaOp<T>::row(kg, r);
+                const int row = m0 + wm * (BS / 2) + i * 16 + MfmaOp<T>::row(kg, r);
                 if (row < p.M && col < p.N) {
                     double v = p.alpha * (double)acc[i][j][r];
                     if (C) v += p.beta * C[(long)row * p.ldc + col];
@@ -204,6 +209,45 @@ __global__ __launch_bounds__(NTHREADS, 2) void gemm_kernel(Params p) {
                 }
             }
         }
+}
+
+template <typename T, bool TA, bool TB>
+__global__ __launch_bounds__(NTHREADS, 2) void gemm_kernel(Params p) {
+    constexpr int LDK = MfmaOp<T>::LDK;
+    __shared__ T As[2 * BM * LDK];
+    __shared__ T Bs[2 * BN * LDK];
+    const int T_tiles = p.mt * p.nt;
+    const int tile = xcd_band_tile(blockIdx.x, T_tiles);
+    const int m0 = (tile / p.nt) * BM;
+    const int n0 = (tile % p.nt) * BN;
+    gemm_tile<T, TA, TB, BM>(p, m0, n0, (long)blockIdx.z, As, Bs);
+}
+
+// Many independent FP64 problems in one persistent launch (the products of
+// the requests batched by the serving path): problem g's tiles are
+// [tile_start[g], tile_start[g + 1]) of a common range, row-major over its
+// output; every workgroup walks that range with a stride of the grid, so the
+// grid can stay fixed (graph capture) while the problems change.  The
+// descriptors live in device memory; BS as gemm_tile.
+struct GroupDesc {
+    Params p;
+    int tile_start;
+};
+
+template <bool TA, bool TB, int BS>
+__global__ __launch_bounds__(NTHREADS, 2) void gemm_grouped_kernel(const GroupDesc* __restrict__ desc,
+                                                                   const int* __restrict__ count) {
+    constexpr int LDK = MfmaOp<double>::LDK;
+    __shared__ double As[2 * BS * LDK];
+    __shared__ double Bs[2 * BS * LDK];
+    const int G = count[0], ntiles = count[1];
+    int g = 0;
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        while (g + 1 < G && desc[g + 1].tile_start <= tile) ++g;
+        const Params& p = desc[g].p;
+        const int lt = tile - desc[g].tile_start;
+        gemm_tile<double, TA, TB, BS>(p, (lt / p.nt) * BS, (lt % p.nt) * BS, 0, As, Bs);
+    }
 }
 
 template <typename T>
@@ -357,6 +401,50 @@ __global__ __launch_bounds__(NTHREADS) void gemm_bf16_kernel(Params p) {
 }  // namespace
 
 void gemm_f64(const Gemm& g, hipStream_t s) { launch<double>(g, s); }
+
+size_t grouped_desc_bytes() { return sizeof(GroupDesc); }
+
+// Host side of a grouped launch: the descriptor of problem g (its tiles
+// start at tile_start) in the layout gemm_grouped_kernel reads.
+void grouped_desc_fill(const Gemm& g, int bs, int tile_start, void* out) {
+    GroupDesc d{};
+    Params& p = d.p;
+    p.M = g.M; p.N = g.N; p.K = g.K;
+    p.alpha = g.alpha; p.beta = g.beta;
+    p.A = g.A; p.lda = g.lda; p.sA = 0;
+    p.B = g.B; p.ldb = g.ldb; p.sB = 0;
+    p.C = g.C; p.ldc = g.ldc; p.sC = 0;
+    p.D = g.D; p.ldd = g.ldd; p.sD = 0;
+    p.mt = g.M > 0 ? (g.M + bs - 1) / bs : 0;
+    p.nt = g.N > 0 ? (g.N + bs - 1) / bs : 0;
+    d.tile_start = tile_start;
+    std::memcpy(out, &d, sizeof(d));
+}
+
+int grouped_tiles(const Gemm& g, int bs) {
+    if (g.M <= 0 || g.N <= 0) return 0;
+    return ((g.M + bs - 1) / bs) * ((g.N + bs - 1) / bs);
+}
+
+void gemm_grouped_f64(const void* desc, const int* count, bool tA, bool tB, int bs, int grid, hipStream_t s) {
+    if (bs != 128 && bs != 64) ITE_FAIL(ITE_EINVAL, "gemm_grouped: tile must be 128 or 64");
+    const auto* d = static_cast<const GroupDesc*>(desc);
+#define ITE_GG(TA, TB, BS) \
+    hipLaunchKernelGGL((gemm_grouped_kernel<TA, TB, BS>), dim3(grid), dim3(NTHREADS), 0, s, d, count)
+    if (bs == 128) {
+        if (!tA && !tB) ITE_GG(false, false, 128);
+        else if (!tA && tB) ITE_GG(false, true, 128);
+        else if (tA && !tB) ITE_GG(true, false, 128);
+        else ITE_GG(true, true, 128);
+    } else {
+        if (!tA && !tB) ITE_GG(false, false, 64);
+        else if (!tA && tB) ITE_GG(false, true, 64);
+        else if (tA && !tB) ITE_GG(true, false, 64);
+        else ITE_GG(true, true, 64);
+    }
+#undef ITE_GG
+    HIP_CHECK(hipGetLastError());
+}
 void gemm_f32(const Gemm& g, hipStream_t s) { launch<float>(g, s); }
 
 void gemm_bf16(const Gemm& g, hipStream_t s) {

@@ -53,6 +53,16 @@ struct Gemm {
 };
 // FP64 operands, FP64 MFMA.
 void gemm_f64(const Gemm& g, hipStream_t s);
+// Grouped FP64 GEMM: many problems (batch 1 each) in one persistent launch
+// of `grid` workgroups, with bs x bs output tiles (128 or 64; the same bits
+// either way).  The descriptors live in device memory (grouped_desc_bytes()
+// each, filled on the host by grouped_desc_fill with the running tile count
+// as tile_start); count (device) = {number of problems, their total tiles},
+// so the same launch, e.g. inside a captured graph, serves changing problems.
+size_t grouped_desc_bytes();
+void grouped_desc_fill(const Gemm& g, int bs, int tile_start, void* out);
+int grouped_tiles(const Gemm& g, int bs);
+void gemm_grouped_f64(const void* desc, const int* count, bool tA, bool tB, int bs, int grid, hipStream_t s);
 // FP32 operands (A, B are float*), FP32 MFMA, FP32 accumulation, FP64 output.
 void gemm_f32(const Gemm& g, hipStream_t s);
 // BF16 operands (A, B are uint16 bf16 bit patterns), BF16 MFMA, FP32
@@ -134,6 +144,54 @@ void eye(double* x, int D, hipStream_t s);
 void nonfinite_any(const double* x, size_t n, int* flag, hipStream_t s);
 // out[j][i] = in[i][j]  (rows x cols -> cols x rows)
 void transpose(const double* in, int rows, int cols, double* out, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Batched fixed-budget GMRES: the local solves of several independent states
+// advanced together, one launch per operation for all of them (persistent
+// kernels over a fixed grid, problems described in device memory, so the
+// same launches can be captured in a graph and replayed for other shapes).
+// Per problem the arithmetic is that of the single-problem kernels above
+// (the same reduction blocks and order), so a state's result does not depend
+// on the batch it runs in.
+// ---------------------------------------------------------------------------
+struct BatchVec {
+    long n;                 // vector length
+    int nb;                 // reduction blocks, reduce_blocks(n)
+    int small;              // Gram-Schmidt in one workgroup (cgs2_small applies)
+    double* V;              // Krylov basis, (mm + 1) vectors of n
+    double* w;              // work vector
+    double* x;              // solution (in: initial guess)
+    const double* b;        // right-hand side
+    double* part;           // reduction partials, nb * 64 + 64
+    double* hd;             // Hessenberg columns (mm x HESS_HC), ||b||, ||r0||
+    double* y;              // combination coefficients (mm)
+    double* stats;          // the solve's record (hess_solve)
+    Stage st;               // MPO stage of the operator (X1 -> X3)
+    int red_start, ew_start, stage_start;   // first unit of this problem in each unit range
+};
+// Unit totals of a batch (device ints): reductions, elementwise, stage.
+enum { BT_RED = 0, BT_EW = 1, BT_STAGE = 2, BT_N = 4 };
+constexpr int BATCH_GRID = 1024;      // workgroups of every batched vector launch
+constexpr long BATCH_EW = 4096;       // elements per elementwise unit
+// Reductions: mode 0 V_j . w (j < k1; large problems), 1 w . w (large),
+// 2 V_0 . V_0, 3 b . b (all problems).
+void batch_reduce(const BatchVec* d, int G, const int* tot, int mode, int k1, hipStream_t s);
+// Sum the partials: target 0 hd col k [j], 1 col k [64 + j], 2 col k [128]
+// (sqrt; large problems), 3 ||b|| (sqrt), 4 ||r0|| (sqrt) (all).
+void batch_finish(const BatchVec* d, int G, int k, int k1, int target, hipStream_t s);
+// Elementwise: 0 w -= sum_(j <= k) col_k[j] V_j, 1 the same with col_k[64 + j]
+// (large problems), 2 V_(k+1) = w / col_k[128] (large), 3 V_0 = b - V_0,
+// 4 V_0 /= ||r0||, 5 x += sum_(j < k) y_j V_j (all).
+void batch_vec(const BatchVec* d, int G, const int* tot, int op, int k, hipStream_t s);
+// Both Gram-Schmidt passes of Arnoldi step k of the small problems.
+void batch_cgs2_small(const BatchVec* d, int G, int k, int mm, hipStream_t s);
+// The cycle's least-squares solve of every problem.
+void batch_hess(const BatchVec* d, int G, int mm, bool r_product, bool last_cycle, hipStream_t s);
+// Zero every problem's solve record (8 doubles).
+void batch_zero_stats(const BatchVec* d, int G, hipStream_t s);
+// The MPO stage of every problem (inputs per column at most 128).
+void batch_stage(const BatchVec* d, int G, const int* tot, hipStream_t s);
+constexpr int BATCH_STAGE_SC = 128;
 
 // Observability of kernel launches: every launch of a kind is counted, some
 // are bracketed by events (begin returns true for those), and the

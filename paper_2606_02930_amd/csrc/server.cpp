@@ -3,7 +3,9 @@
 //
 // Each worker is a host thread with its own context on its own non-blocking
 // stream; a request, once admitted, stays on the worker that admitted it and
-// that worker advances its active requests one time step each in turn.  The
+// that worker advances all its active requests by one time step at a time as
+// one batch (ite_step_batch: their local solves share grouped launches and a
+// captured graph; each result is bitwise that of the request run alone).  The
 // FIFO queue admits the oldest request as soon as the summed footprint of the
 // active requests leaves room for it and a worker has a free slot, so short
 // requests that arrive while long ones run start at once instead of behind
@@ -154,7 +156,7 @@ void ite_server::worker(int wi) {
     ite_ctx* c = ctx[wi];
     for (;;) {
         std::shared_ptr<Req> r;
-        bool fresh = false;
+        std::vector<std::shared_ptr<Req>> batch;
         {
             std::unique_lock<std::mutex> lk(m);
             for (;;) {
@@ -168,17 +170,18 @@ void ite_server::worker(int wi) {
                     r->t_admit = now();
                     active_bytes += r->fp;
                     active[wi].push_back(r);
-                    fresh = true;
                     break;
                 }
                 if (!active[wi].empty()) {
-                    r = active[wi][rr[wi]++ % active[wi].size()];
+                    batch = active[wi];
                     break;
                 }
                 cv_work.wait(lk);
             }
         }
-        if (fresh) {
+        if (r) {
+            // a fresh admission: its tensors, then back to admit more before
+            // the next batched step
             std::vector<const double*> Wp(r->L), Sp(r->L);
             for (int i = 0; i < r->L; ++i) {
                 Wp[i] = r->W[i].data();
@@ -190,45 +193,64 @@ void ite_server::worker(int wi) {
             if (rc != ITE_OK) finish(r, wi, ITE_REQ_FAILED, rc, ite_last_error(c));
             continue;
         }
-        // one step of r: from grid[k] to grid[k + 1]
-        const double dtau = r->grid[r->k + 1] - r->grid[r->k];
-        const double h = r->o.scheme == ITE_SCHEME_TRAP ? 0.5 * dtau : dtau;
-        ite_step_report rep{};
-        int rc = ite_imag_step(r->psi, r->H, h, &r->o, &rep);
-        if (rc != ITE_OK) {
-            finish(r, wi, ITE_REQ_FAILED, rc, ite_last_error(c));
-            continue;
+        // one time step of every active request of this worker, as one batch:
+        // request j goes from grid[k] to grid[k + 1]
+        const int n = (int)batch.size();
+        std::vector<ite_mps*> P(n);
+        std::vector<const ite_mpo*> Hs(n);
+        std::vector<double> hs(n);
+        std::vector<const ite_step_opts*> Os(n);
+        for (int j = 0; j < n; ++j) {
+            Req& q = *batch[j];
+            const double dtau = q.grid[q.k + 1] - q.grid[q.k];
+            P[j] = q.psi;
+            Hs[j] = q.H;
+            hs[j] = q.o.scheme == ITE_SCHEME_TRAP ? 0.5 * dtau : dtau;
+            Os[j] = &q.o;
         }
-        ite_mps_set_tau(r->psi, r->grid[r->k + 1]);
-        rep.tau = r->grid[r->k + 1];
-        bool last;
-        {
-            std::lock_guard<std::mutex> lk(m);
-            r->reps.push_back(rep);
-            r->k += 1;
-            r->tau = rep.tau;
-            r->energy = rep.energy;
-            last = r->k + 1 >= (int)r->grid.size();
-        }
-        if (!last) continue;
-        std::vector<int> chi(r->L + 1);
-        rc = ite_mps_export(r->psi, chi.data(), nullptr);
-        std::vector<std::vector<double>> A(r->L);
-        std::vector<double*> Ap(r->L);
-        if (rc == ITE_OK) {
-            for (int i = 0; i < r->L; ++i) {
-                A[i].resize((size_t)chi[i] * r->d[i] * chi[i + 1]);
-                Ap[i] = A[i].data();
+        std::vector<ite_step_report> reps(n);
+        std::vector<int> st(n, ITE_OK);
+        const int brc = ite_step_batch(c, n, P.data(), Hs.data(), hs.data(), Os.data(), reps.data(), st.data());
+        const std::string bmsg = ite_last_error(c);
+        for (int j = 0; j < n; ++j) {
+            const std::shared_ptr<Req>& q = batch[j];
+            int rc = brc != ITE_OK && st[j] == ITE_OK && brc != ITE_ENONFINITE ? brc : st[j];
+            if (rc != ITE_OK) {
+                finish(q, wi, ITE_REQ_FAILED, rc, bmsg);
+                continue;
             }
-            rc = ite_mps_export(r->psi, chi.data(), Ap.data());
+            ite_step_report rep = reps[j];
+            ite_mps_set_tau(q->psi, q->grid[q->k + 1]);
+            rep.tau = q->grid[q->k + 1];
+            bool last;
+            {
+                std::lock_guard<std::mutex> lk(m);
+                q->reps.push_back(rep);
+                q->k += 1;
+                q->tau = rep.tau;
+                q->energy = rep.energy;
+                last = q->k + 1 >= (int)q->grid.size();
+            }
+            if (!last) continue;
+            std::vector<int> chi(q->L + 1);
+            rc = ite_mps_export(q->psi, chi.data(), nullptr);
+            std::vector<std::vector<double>> A(q->L);
+            std::vector<double*> Ap(q->L);
+            if (rc == ITE_OK) {
+                for (int i = 0; i < q->L; ++i) {
+                    A[i].resize((size_t)chi[i] * q->d[i] * chi[i + 1]);
+                    Ap[i] = A[i].data();
+                }
+                rc = ite_mps_export(q->psi, chi.data(), Ap.data());
+            }
+            if (rc != ITE_OK) {
+                finish(q, wi, ITE_REQ_FAILED, rc, ite_last_error(c));
+                continue;
+            }
+            q->chi = std::move(chi);
+            q->A = std::move(A);
+            finish(q, wi, ITE_REQ_DONE, ITE_OK, "");
         }
-        if (rc != ITE_OK) {
-            finish(r, wi, ITE_REQ_FAILED, rc, ite_last_error(c));
-            continue;
-        }
-        r->chi = std::move(chi);
-        r->A = std::move(A);
-        finish(r, wi, ITE_REQ_DONE, ITE_OK, "");
     }
 }
 

@@ -36,15 +36,42 @@ __device__ inline double block_sum(double v, double* sh) {
     return r;
 }
 
+// Block vb of a reduction over vg blocks (the partition depends on n only,
+// through vg = reduce_blocks(n)): *out = the block's share of x . y.
+__device__ inline void dot_block(const double* __restrict__ x, const double* __restrict__ y, size_t n, int vb, int vg,
+                                 double* __restrict__ out, double* sh) {
+    double acc = 0.0;
+    const size_t stride = (size_t)vg * RT;
+    for (size_t i = (size_t)vb * RT + threadIdx.x; i < n; i += stride) acc += x[i] * y[i];
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) *out = acc;
+}
+
 __global__ __launch_bounds__(RT) void dot_partials_kernel(const double* __restrict__ x,
                                                           const double* __restrict__ y, size_t n,
                                                           double* __restrict__ partial) {
     __shared__ double sh[RT / 64];
-    double acc = 0.0;
-    const size_t stride = (size_t)gridDim.x * RT;
-    for (size_t i = (size_t)blockIdx.x * RT + threadIdx.x; i < n; i += stride) acc += x[i] * y[i];
-    acc = block_sum(acc, sh);
-    if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+    dot_block(x, y, n, blockIdx.x, gridDim.x, partial + blockIdx.x, sh);
+}
+
+// Block vb of vg: partial[j * vg + vb] = its share of V_j . w for j < k.
+template <int KMAX>
+__device__ inline void mdot_block(const double* __restrict__ V, long ldv, int k, const double* __restrict__ w, size_t n,
+                                  int vb, int vg, double* __restrict__ partial, double* sh) {
+    double acc[KMAX];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j) acc[j] = 0.0;
+    const size_t stride = (size_t)vg * RT;
+    for (size_t i = (size_t)vb * RT + threadIdx.x; i < n; i += stride) {
+        const double wi = w[i];
+#pragma unroll
+        for (int j = 0; j < KMAX; ++j)
+            if (j < k) acc[j] += V[(size_t)j * ldv + i] * wi;
+    }
+    for (int j = 0; j < k; ++j) {
+        const double s = block_sum(acc[j], sh);
+        if (threadIdx.x == 0) partial[(size_t)j * vg + vb] = s;
+    }
 }
 
 // partial[j*nb + b]: block b's share of V_j . w for j < k (k <= 64).
@@ -53,19 +80,20 @@ __global__ __launch_bounds__(RT) void mdot_partials_kernel(const double* __restr
                                                            int k, const double* __restrict__ w,
                                                            size_t n, double* __restrict__ partial) {
     __shared__ double sh[RT / 64];
-    double acc[KMAX];
-#pragma unroll
-    for (int j = 0; j < KMAX; ++j) acc[j] = 0.0;
-    const size_t stride = (size_t)gridDim.x * RT;
-    for (size_t i = (size_t)blockIdx.x * RT + threadIdx.x; i < n; i += stride) {
-        const double wi = w[i];
-#pragma unroll
-        for (int j = 0; j < KMAX; ++j)
-            if (j < k) acc[j] += V[(size_t)j * ldv + i] * wi;
-    }
-    for (int j = 0; j < k; ++j) {
-        const double s = block_sum(acc[j], sh);
-        if (threadIdx.x == 0) partial[(size_t)j * gridDim.x + blockIdx.x] = s;
+    mdot_block<KMAX>(V, ldv, k, w, n, blockIdx.x, gridDim.x, partial, sh);
+}
+
+// *out (mode 0: =, 1: +=, 2: = sqrt) of the sum of nb partials.
+__device__ inline void finish_one(const double* __restrict__ partial, int nb, double* __restrict__ out, int mode,
+                                  double* sh) {
+    double acc = 0.0;
+    // fixed assignment of partials to threads, fixed combination order
+    for (int b = threadIdx.x; b < nb; b += RT) acc += partial[b];
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) {
+        if (mode == 0) *out = acc;
+        else if (mode == 1) *out += acc;
+        else *out = sqrt(fmax(acc, 0.0));
     }
 }
 
@@ -74,15 +102,7 @@ __global__ __launch_bounds__(RT) void finish_partials_kernel(const double* __res
                                                              int mode) {
     __shared__ double sh[RT / 64];
     const int j = blockIdx.x;
-    double acc = 0.0;
-    // fixed assignment of partials to threads, fixed combination order
-    for (int b = threadIdx.x; b < nb; b += RT) acc += partial[(size_t)j * nb + b];
-    acc = block_sum(acc, sh);
-    if (threadIdx.x == 0) {
-        if (mode == 0) out[j] = acc;
-        else if (mode == 1) out[j] += acc;
-        else out[j] = sqrt(fmax(acc, 0.0));
-    }
+    finish_one(partial + (size_t)j * nb, nb, out + j, mode, sh);
 }
 
 template <int KMAX, bool SUB>
@@ -118,12 +138,17 @@ __global__ void axpby_kernel(size_t n, double a, const double* __restrict__ x, d
 // reduction order.
 constexpr int CGS_T = 256, CGS_E = 32;
 template <int KMAX>
-__global__ __launch_bounds__(CGS_T) void cgs2_small_kernel(const double* __restrict__ V, long ldv, int k1,
-                                                           double* __restrict__ w, int n, double* __restrict__ col,
-                                                           double* __restrict__ vnext) {
-    __shared__ double xs[CGS_T * CGS_E];
-    __shared__ double part[CGS_T / 64][KMAX];
-    __shared__ double coef[KMAX];
+struct CgsLDS {
+    double xs[CGS_T * CGS_E];
+    double part[CGS_T / 64][KMAX];
+    double coef[KMAX];
+};
+template <int KMAX>
+__device__ inline void cgs2_small_body(const double* __restrict__ V, long ldv, int k1, double* __restrict__ w, int n,
+                                       double* __restrict__ col, double* __restrict__ vnext, CgsLDS<KMAX>& L) {
+    auto& xs = L.xs;
+    auto& part = L.part;
+    auto& coef = L.coef;
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     for (int i = t; i < n; i += CGS_T) xs[i] = w[i];
     for (int pass = 0; pass < 2; ++pass) {
@@ -176,6 +201,14 @@ __global__ __launch_bounds__(CGS_T) void cgs2_small_kernel(const double* __restr
         w[i] = xs[i];
         if (vnext) vnext[i] = xs[i] * inv;
     }
+}
+
+template <int KMAX>
+__global__ __launch_bounds__(CGS_T) void cgs2_small_kernel(const double* __restrict__ V, long ldv, int k1,
+                                                           double* __restrict__ w, int n, double* __restrict__ col,
+                                                           double* __restrict__ vnext) {
+    __shared__ CgsLDS<KMAX> sh;
+    cgs2_small_body<KMAX>(V, ldv, k1, w, n, col, vnext, sh);
 }
 
 // The small least-squares problem of one GMRES cycle, on the device (one
@@ -355,27 +388,33 @@ constexpr size_t STAGE_LDS = 128 * 1024;
 // OUT: 0 writes FP64 to st.out, 1 rounds to FP32 and 2 to BF16 into st.out_lo
 // (the operand of a following low-precision contraction).
 template <int OUT, int SC>
-__global__ __launch_bounds__(SC) void stage_kernel(Stage st) {
-    extern __shared__ double xin[];   // [I][SC]
-    const int g = blockIdx.y;
-    const int c = blockIdx.x * SC + threadIdx.x;
+__device__ inline void stage_unit(const Stage& st, int g, int cblk, double* xin) {
+    const int c = cblk * SC + threadIdx.x;
     const double* __restrict__ in = st.in + (long)g * st.in_gs + (long)c * st.in_cs;
     for (int i = 0; i < st.I; ++i) {
         const long off = (long)(i / st.in_div) * st.in_s1 + (long)(i % st.in_div) * st.in_s2;
         xin[i * SC + threadIdx.x] = (c < st.C) ? in[off] : 0.0;
     }
     __syncthreads();
-    if (c >= st.C) return;
-    const long base = (long)g * st.out_gs + (long)c * st.out_cs;
-    for (int o = 0; o < st.O; ++o) {
-        double acc = 0.0;
-        const int e1 = st.rowptr[o + 1];
-        for (int e = st.rowptr[o]; e < e1; ++e) acc += st.val[e] * xin[st.col[e] * SC + threadIdx.x];
-        const long at = base + (long)(o / st.out_div) * st.out_s1 + (long)(o % st.out_div) * st.out_s2;
-        if (OUT == 0) st.out[at] = acc;
-        else if (OUT == 1) static_cast<float*>(st.out_lo)[at] = (float)acc;
-        else static_cast<uint16_t*>(st.out_lo)[at] = to_bf16(acc);
+    if (c < st.C) {
+        const long base = (long)g * st.out_gs + (long)c * st.out_cs;
+        for (int o = 0; o < st.O; ++o) {
+            double acc = 0.0;
+            const int e1 = st.rowptr[o + 1];
+            for (int e = st.rowptr[o]; e < e1; ++e) acc += st.val[e] * xin[st.col[e] * SC + threadIdx.x];
+            const long at = base + (long)(o / st.out_div) * st.out_s1 + (long)(o % st.out_div) * st.out_s2;
+            if (OUT == 0) st.out[at] = acc;
+            else if (OUT == 1) static_cast<float*>(st.out_lo)[at] = (float)acc;
+            else static_cast<uint16_t*>(st.out_lo)[at] = to_bf16(acc);
+        }
     }
+    __syncthreads();   // xin may be refilled by the caller's next unit
+}
+
+template <int OUT, int SC>
+__global__ __launch_bounds__(SC) void stage_kernel(Stage st) {
+    extern __shared__ double xin[];   // [I][SC]
+    stage_unit<OUT, SC>(st, blockIdx.y, blockIdx.x, xin);
 }
 
 inline int grid_for(size_t n, int threads, int cap = 4096) {
@@ -728,6 +767,199 @@ void stage_f64(const Stage& st, hipStream_t s) {
     else if (per_col * 64 <= STAGE_LDS) stage_launch<64>(st, s);
     else if (per_col * 32 <= STAGE_LDS) stage_launch<32>(st, s);
     else stage_launch<16>(st, s);
+}
+
+// ---------------------------------------------------------------------------
+// Batched fixed-budget GMRES (see BatchVec in internal.h)
+// ---------------------------------------------------------------------------
+namespace {
+
+// Problem of unit u in a range split by the per-problem first units
+// (start(g) increasing; G small): the last g with start(g) <= u.
+template <typename F>
+__device__ inline int unit_problem(int u, int G, F start) {
+    int g = 0;
+    while (g + 1 < G && start(g + 1) <= u) ++g;
+    return g;
+}
+
+template <int KMAX>
+__global__ __launch_bounds__(RT) void batch_reduce_kernel(const BatchVec* __restrict__ d, int G,
+                                                          const int* __restrict__ tot, int mode, int k1) {
+    __shared__ double sh[RT / 64];
+    const int total = tot[BT_RED];
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {
+        const int g = unit_problem(u, G, [&](int q) { return d[q].red_start; });
+        const BatchVec& p = d[g];
+        const int vb = u - p.red_start;
+        if (vb >= p.nb) continue;
+        if (mode <= 1 && p.small) continue;
+        if (mode == 0) {
+            mdot_block<KMAX>(p.V, p.n, k1, p.w, p.n, vb, p.nb, p.part, sh);
+        } else {
+            const double* x = mode == 1 ? p.w : (mode == 2 ? p.V : p.b);
+            dot_block(x, x, p.n, vb, p.nb, p.part + vb, sh);
+        }
+    }
+}
+
+__global__ __launch_bounds__(RT) void batch_finish_kernel(const BatchVec* __restrict__ d, int G, int k, int k1,
+                                                          int target) {
+    __shared__ double sh[RT / 64];
+    const int total = G * k1;
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {
+        const int g = u / k1, j = u % k1;
+        const BatchVec& p = d[g];
+        if (target <= 2 && p.small) continue;
+        double* col = p.hd + (size_t)k * HESS_HC;
+        double* out;
+        int mode = 2;
+        if (target == 0) { out = col + j; mode = 0; }
+        else if (target == 1) { out = col + 64 + j; mode = 0; }
+        else if (target == 2) out = col + 128;
+        else out = p.hd + (size_t)k * HESS_HC + (target == 3 ? 0 : 1);   // k = mm here: ||b||, ||r0||
+        finish_one(p.part + (size_t)j * p.nb, p.nb, out, mode, sh);
+    }
+}
+
+// w -= sum_(j < k1) c_j V_j, in chunks of 16 basis vectors as gemv_launch does.
+__device__ inline double gemv_elem(const double* __restrict__ V, long ldv, int k1, const double* __restrict__ c,
+                                   double wi, size_t i, bool sub) {
+    for (int j0 = 0; j0 < k1; j0 += 16) {
+        const int kk = k1 - j0 < 16 ? k1 - j0 : 16;
+        double s = 0.0;
+        for (int j = 0; j < kk; ++j) s += c[j0 + j] * V[(size_t)(j0 + j) * ldv + i];
+        wi = sub ? wi - s : wi + s;
+    }
+    return wi;
+}
+
+__global__ __launch_bounds__(RT) void batch_vec_kernel(const BatchVec* __restrict__ d, int G,
+                                                       const int* __restrict__ tot, int op, int k) {
+    const int total = tot[BT_EW];
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {
+        const int g = unit_problem(u, G, [&](int q) { return d[q].ew_start; });
+        const BatchVec& p = d[g];
+        if (op <= 2 && p.small) continue;
+        const size_t i0 = (size_t)(u - p.ew_start) * BATCH_EW;
+        const size_t i1 = min((size_t)p.n, i0 + BATCH_EW);
+        const double* col = p.hd + (size_t)k * HESS_HC;
+        if (op == 0 || op == 1) {
+            const double* cf = op == 0 ? col : col + 64;
+            for (size_t i = i0 + threadIdx.x; i < i1; i += RT) p.w[i] = gemv_elem(p.V, p.n, k + 1, cf, p.w[i], i, true);
+        } else if (op == 2) {
+            const double dd = col[128];
+            const double inv = dd > 0.0 ? 1.0 / dd : 0.0;
+            double* vn = p.V + (size_t)(k + 1) * p.n;
+            for (size_t i = i0 + threadIdx.x; i < i1; i += RT) vn[i] = p.w[i] * inv;
+        } else if (op == 3) {
+            for (size_t i = i0 + threadIdx.x; i < i1; i += RT) p.V[i] = 1.0 * p.b[i] + -1.0 * p.V[i];
+        } else if (op == 4) {
+            const double dd = p.hd[(size_t)k * HESS_HC + 1];
+            const double inv = dd > 0.0 ? 1.0 / dd : 0.0;
+            for (size_t i = i0 + threadIdx.x; i < i1; i += RT) p.V[i] = p.V[i] * inv;
+        } else {
+            for (size_t i = i0 + threadIdx.x; i < i1; i += RT) p.x[i] = gemv_elem(p.V, p.n, k, p.y, p.x[i], i, false);
+        }
+    }
+}
+
+template <int KMAX>
+__global__ __launch_bounds__(CGS_T) void batch_cgs2_small_kernel(const BatchVec* __restrict__ d, int G, int k,
+                                                                 int mm) {
+    __shared__ CgsLDS<KMAX> sh;
+    for (int g = blockIdx.x; g < G; g += gridDim.x) {
+        const BatchVec& p = d[g];
+        if (!p.small) continue;
+        double* vnext = k + 1 < mm ? p.V + (size_t)(k + 1) * p.n : nullptr;
+        cgs2_small_body<KMAX>(p.V, p.n, k + 1, p.w, (int)p.n, p.hd + (size_t)k * HESS_HC, vnext, sh);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(64) void batch_hess_kernel(const BatchVec* __restrict__ d, int G, int mm, int r_product,
+                                                        int last_cycle) {
+    __shared__ double Hs[HESS_LDS];
+    for (int g = blockIdx.x; g < G; g += gridDim.x) {
+        const BatchVec& p = d[g];
+        if (threadIdx.x == 0) hess_solve_one(p.hd, mm, p.y, p.stats, r_product, last_cycle, Hs);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(BATCH_STAGE_SC) void batch_stage_kernel(const BatchVec* __restrict__ d, int G,
+                                                                     const int* __restrict__ tot) {
+    __shared__ double xin[BATCH_STAGE_SC * BATCH_STAGE_SC];
+    const int total = tot[BT_STAGE];
+    for (int u = blockIdx.x; u < total; u += gridDim.x) {
+        const int g = unit_problem(u, G, [&](int q) { return d[q].stage_start; });
+        const Stage& st = d[g].st;
+        const int nc = (st.C + BATCH_STAGE_SC - 1) / BATCH_STAGE_SC;
+        const int lu = u - d[g].stage_start;
+        stage_unit<0, BATCH_STAGE_SC>(st, lu / nc, lu % nc, xin);
+    }
+}
+
+__global__ __launch_bounds__(64) void batch_zero_stats_kernel(const BatchVec* __restrict__ d, int G) {
+    for (int g = blockIdx.x; g < G; g += gridDim.x)
+        if (threadIdx.x < 8) d[g].stats[threadIdx.x] = 0.0;
+}
+
+}  // namespace
+
+void batch_zero_stats(const BatchVec* d, int G, hipStream_t s) {
+    if (G <= 0) return;
+    hipLaunchKernelGGL(batch_zero_stats_kernel, dim3(std::min(G, BATCH_GRID)), dim3(64), 0, s, d, G);
+    HIP_CHECK(hipGetLastError());
+}
+
+void batch_reduce(const BatchVec* d, int G, const int* tot, int mode, int k1, hipStream_t s) {
+    if (G <= 0) return;
+    if (mode == 0 && k1 > 16) ITE_FAIL(ITE_EINVAL, "batch_reduce: at most 16 basis vectors per launch");
+    if (mode != 0 || k1 <= 4)
+        hipLaunchKernelGGL((batch_reduce_kernel<4>), dim3(BATCH_GRID), dim3(RT), 0, s, d, G, tot, mode, k1);
+    else if (k1 <= 8)
+        hipLaunchKernelGGL((batch_reduce_kernel<8>), dim3(BATCH_GRID), dim3(RT), 0, s, d, G, tot, mode, k1);
+    else
+        hipLaunchKernelGGL((batch_reduce_kernel<16>), dim3(BATCH_GRID), dim3(RT), 0, s, d, G, tot, mode, k1);
+    HIP_CHECK(hipGetLastError());
+}
+
+void batch_finish(const BatchVec* d, int G, int k, int k1, int target, hipStream_t s) {
+    if (G <= 0) return;
+    hipLaunchKernelGGL(batch_finish_kernel, dim3(std::min(BATCH_GRID, G * k1)), dim3(RT), 0, s, d, G, k, k1, target);
+    HIP_CHECK(hipGetLastError());
+}
+
+void batch_vec(const BatchVec* d, int G, const int* tot, int op, int k, hipStream_t s) {
+    if (G <= 0) return;
+    hipLaunchKernelGGL(batch_vec_kernel, dim3(BATCH_GRID), dim3(RT), 0, s, d, G, tot, op, k);
+    HIP_CHECK(hipGetLastError());
+}
+
+void batch_cgs2_small(const BatchVec* d, int G, int k, int mm, hipStream_t s) {
+    if (G <= 0) return;
+    const int k1 = k + 1;
+    const dim3 grid(std::min(G, BATCH_GRID));
+    if (k1 <= 8) hipLaunchKernelGGL((batch_cgs2_small_kernel<8>), grid, dim3(CGS_T), 0, s, d, G, k, mm);
+    else if (k1 <= 16) hipLaunchKernelGGL((batch_cgs2_small_kernel<16>), grid, dim3(CGS_T), 0, s, d, G, k, mm);
+    else if (k1 <= 32) hipLaunchKernelGGL((batch_cgs2_small_kernel<32>), grid, dim3(CGS_T), 0, s, d, G, k, mm);
+    else hipLaunchKernelGGL((batch_cgs2_small_kernel<64>), grid, dim3(CGS_T), 0, s, d, G, k, mm);
+    HIP_CHECK(hipGetLastError());
+}
+
+void batch_hess(const BatchVec* d, int G, int mm, bool r_product, bool last_cycle, hipStream_t s) {
+    if (G <= 0) return;
+    if (mm < 1 || mm > HESS_KMAX) ITE_FAIL(ITE_EINVAL, "batch_hess: Krylov dimension outside 1..64");
+    hipLaunchKernelGGL(batch_hess_kernel, dim3(std::min(G, BATCH_GRID)), dim3(64), 0, s, d, G, mm, (int)r_product,
+                       (int)last_cycle);
+    HIP_CHECK(hipGetLastError());
+}
+
+void batch_stage(const BatchVec* d, int G, const int* tot, hipStream_t s) {
+    if (G <= 0) return;
+    hipLaunchKernelGGL(batch_stage_kernel, dim3(BATCH_GRID), dim3(BATCH_STAGE_SC), 0, s, d, G, tot);
+    HIP_CHECK(hipGetLastError());
 }
 
 }  // namespace ite
