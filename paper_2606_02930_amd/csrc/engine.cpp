@@ -171,6 +171,7 @@ static void stage(ite_ctx* c, const CsrDev& m, Stage st) {
     st.rowptr = m.rowptr;
     st.col = m.col;
     st.val = m.val;
+    st.nnz = m.nnz;
     stage_f64(st, c->stream);
 }
 
@@ -193,11 +194,13 @@ static void to_lo(ite_ctx* c, Prec p, const double* x, void* dst, size_t n) {
 }
 
 static void gemm_lo(ite_ctx* c, Prec p, bool tA, bool tB, int M, int N, int K, double alpha, const void* A,
-                    long lda, const void* B, long ldb, double beta, const double* C, long ldc, double* D, long ldd) {
+                    long lda, const void* B, long ldb, double beta, const double* C, long ldc, double* D, long ldd,
+                    float* Df = nullptr) {
     Gemm g;
     g.M = M; g.N = N; g.K = K; g.tA = tA; g.tB = tB;
     g.alpha = alpha; g.beta = beta;
     g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc; g.D = D; g.ldd = ldd;
+    g.Df = Df;
     if (p == Prec::F32) gemm_f32(g, c->stream);
     else gemm_bf16(g, c->stream);
 }
@@ -209,7 +212,9 @@ void heff_apply(ite_ctx* c, const HeffShape& s, const double* L, const CsrDev& w
     const size_t nx = (size_t)s.Dxl * std::max(I, O) * s.Dyr;
     if (prec != Prec::F64) {
         // operands rounded to FP32 / BF16, FP32 accumulation in the matrix
-        // cores, FP64 intermediates and output
+        // cores; the first intermediate in FP32 (the accumulator's precision,
+        // half the traffic of FP64), the second in the operand precision, the
+        // output in FP64
         const size_t eb = lo_bytes(prec);
         if (!Llo || !Rlo) {
             const size_t nl = (size_t)s.Dxl * s.w0 * s.Dyl, nr = (size_t)s.Dxr * s.w2 * s.Dyr;
@@ -223,13 +228,13 @@ void heff_apply(ite_ctx* c, const HeffShape& s, const double* L, const CsrDev& w
         const size_t nth = (size_t)s.Dyl * s.d1 * s.d2 * s.Dyr;
         void* tlo = slot(c, SL_LO_T, nth * eb);
         void* x3lo = slot(c, SL_LO_X, nx * eb);
-        double* X1 = slot_t<double>(c, SL_X1, nx);
+        float* X1 = static_cast<float*>(slot(c, SL_X1, nx * sizeof(float)));
         to_lo(c, prec, theta, tlo, nth);
         gemm_lo(c, prec, false, false, s.Dxl * s.w0, s.d1 * s.d2 * s.Dyr, s.Dyl, 1.0, Llo, s.Dyl, tlo,
-                (long)s.d1 * s.d2 * s.Dyr, 0.0, nullptr, 0, X1, (long)s.d1 * s.d2 * s.Dyr);
+                (long)s.d1 * s.d2 * s.Dyr, 0.0, nullptr, 0, nullptr, (long)s.d1 * s.d2 * s.Dyr, X1);
         Stage st;
         st.G = s.Dxl; st.C = s.Dyr;
-        st.in = X1; st.in_gs = (long)I * s.Dyr; st.in_s1 = s.Dyr;
+        st.in_f32 = X1; st.in_gs = (long)I * s.Dyr; st.in_s1 = s.Dyr;
         st.out_gs = (long)O * s.Dyr; st.out_s1 = s.Dyr;
         st.out_prec = prec == Prec::F32 ? 1 : 2;
         st.out_lo = x3lo;

@@ -22,7 +22,9 @@
 // L2.
 #include "internal.h"
 
+#include <cstdint>
 #include <cstring>
+#include <type_traits>
 
 namespace ite {
 namespace {
@@ -62,6 +64,7 @@ struct Params {
     const double* C; long ldc, sC;
     double* D; long ldd, sD;
     int mt, nt;
+    float* Df;      // FP32 output instead of D (no C)
 };
 
 // Bijection from the hardware workgroup id to an output tile such that XCD x
@@ -115,6 +118,77 @@ __device__ inline void store_slice(T* __restrict__ lds, int t, const T (&r)[BS /
     }
 }
 
+// 16-byte loads of a 128-wide FP32 operand slice (four floats each) into
+// the same registers and LDS layout as fetch_slice / store_slice, so the
+// products are the same; chunks that cross the matrix edge are loaded
+// element by element.  Needs 16-byte aligned rows (checked by the launcher).
+template <bool KC>
+__device__ inline void fetch_slice_v4(const float* __restrict__ src, long ld, int side0, int sideN, int k0, int K,
+                                      int t, float (&r)[8]) {
+    if (KC) {
+        const int row = side0 + (t >> 1);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int k = k0 + (t & 1) * 8 + 4 * c;
+            if (row < sideN && k + 3 < K) {
+                const float4 v = *reinterpret_cast<const float4*>(src + (long)row * ld + k);
+                r[4 * c] = v.x; r[4 * c + 1] = v.y; r[4 * c + 2] = v.z; r[4 * c + 3] = v.w;
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) r[4 * c + q] = (row < sideN && k + q < K) ? src[(long)row * ld + k + q] : 0.f;
+            }
+        }
+    } else {
+        const int col = side0 + (t & 31) * 4;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int k = k0 + (t >> 5) + 8 * e;
+            if (k < K && col + 3 < sideN) {
+                const float4 v = *reinterpret_cast<const float4*>(src + (long)k * ld + col);
+                r[4 * e] = v.x; r[4 * e + 1] = v.y; r[4 * e + 2] = v.z; r[4 * e + 3] = v.w;
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) r[4 * e + q] = (k < K && col + q < sideN) ? src[(long)k * ld + col + q] : 0.f;
+            }
+        }
+    }
+}
+
+template <bool KC>
+__device__ inline void store_slice_v4(float* __restrict__ lds, int t, const float (&r)[8]) {
+    constexpr int LDK = MfmaOp<float>::LDK;
+    if (KC) {
+        const int row = t >> 1;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int kk = (t & 1) * 8 + 4 * c;
+            *reinterpret_cast<float4*>(&lds[row * LDK + kk]) = make_float4(r[4 * c], r[4 * c + 1], r[4 * c + 2], r[4 * c + 3]);
+        }
+    } else {
+        const int col = (t & 31) * 4;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int krow = (t >> 5) + 8 * e;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) lds[(col + q) * LDK + krow] = r[4 * e + q];
+        }
+    }
+}
+
+// The operand slice loaders of gemm_tile: 16-byte loads for FP32 operands
+// of the 128 tile when VEC, the element loads otherwise.
+template <typename T, bool KC, int BS, bool VEC>
+__device__ inline void fetch_op(const T* __restrict__ src, long ld, int side0, int sideN, int k0, int K, int t,
+                                T (&r)[BS / 16]) {
+    if constexpr (VEC && std::is_same<T, float>::value && BS == 128) fetch_slice_v4<KC>(src, ld, side0, sideN, k0, K, t, r);
+    else fetch_slice<T, KC, BS>(src, ld, side0, sideN, k0, K, t, r);
+}
+template <typename T, bool KC, int BS, bool VEC>
+__device__ inline void store_op(T* __restrict__ lds, int t, const T (&r)[BS / 16]) {
+    if constexpr (VEC && std::is_same<T, float>::value && BS == 128) store_slice_v4<KC>(lds, t, r);
+    else store_slice<T, KC, BS>(lds, t, r);
+}
+
 // One BS x BS output tile at (m0, n0) of problem p (batch index bz): four
 // wavefronts in a 2 x 2 arrangement, each owning (BS / 2)^2 outputs as
 // (BS / 32)^2 MFMA tiles of 16 x 16.  The K order of every output element
@@ -122,7 +196,7 @@ __device__ inline void store_slice(T* __restrict__ lds, int t, const T (&r)[BS /
 // does not depend on BS, so the 128 and 64 tiles give the same bits.  As, Bs:
 // LDS of two slices of each operand.  Ends with a barrier after the last LDS
 // read, so the caller may start another tile.
-template <typename T, bool TA, bool TB, int BS>
+template <typename T, bool TA, bool TB, int BS, bool VEC = false>
 __device__ __forceinline__ void gemm_tile(const Params& p, int m0, int n0, long bz, T* As, T* Bs) {
     typedef typename MfmaOp<T>::acc_t acc_t;
     constexpr int LDK = MfmaOp<T>::LDK, IT = BS / 32, E = BS / 16;
@@ -144,10 +218,10 @@ __device__ __forceinline__ void gemm_tile(const Params& p, int m0, int n0, long 
     // A: K-contiguous unless transposed.  B: K-contiguous only when transposed.
     T ra[E], rb[E];
     const int nk = (p.K + BK - 1) / BK;
-    fetch_slice<T, !TA, BS>(A, p.lda, m0, p.M, 0, p.K, t, ra);
-    fetch_slice<T, TB, BS>(B, p.ldb, n0, p.N, 0, p.K, t, rb);
-    store_slice<T, !TA, BS>(As, t, ra);
-    store_slice<T, TB, BS>(Bs, t, rb);
+    fetch_op<T, !TA, BS, VEC>(A, p.lda, m0, p.M, 0, p.K, t, ra);
+    fetch_op<T, TB, BS, VEC>(B, p.ldb, n0, p.N, 0, p.K, t, rb);
+    store_op<T, !TA, BS, VEC>(As, t, ra);
+    store_op<T, TB, BS, VEC>(Bs, t, rb);
     __syncthreads();
 
     for (int kt = 0; kt < nk; ++kt) {
@@ -156,8 +230,8 @@ __device__ __forceinline__ void gemm_tile(const Params& p, int m0, int n0, long 
         const T* Ac = As + cur * BS * LDK;
         const T* Bc = Bs + cur * BS * LDK;
         if (more) {
-            fetch_slice<T, !TA, BS>(A, p.lda, m0, p.M, (kt + 1) * BK, p.K, t, ra);
-            fetch_slice<T, TB, BS>(B, p.ldb, n0, p.N, (kt + 1) * BK, p.K, t, rb);
+            fetch_op<T, !TA, BS, VEC>(A, p.lda, m0, p.M, (kt + 1) * BK, p.K, t, ra);
+            fetch_op<T, TB, BS, VEC>(B, p.ldb, n0, p.N, (kt + 1) * BK, p.K, t, rb);
         }
         // two sub-steps of the slice at a time: 16 operand values live
         // instead of 32, which leaves room for two workgroups per CU
@@ -184,8 +258,8 @@ __device__ __forceinline__ void gemm_tile(const Params& p, int m0, int n0, long 
                     for (int j = 0; j < IT; ++j) acc[i][j] = MfmaOp<T>::mma(a[i][s], b[j][s], acc[i][j]);
         }
         if (more) {
-            store_slice<T, !TA, BS>(As + (cur ^ 1) * BS * LDK, t, ra);
-            store_slice<T, TB, BS>(Bs + (cur ^ 1) * BS * LDK, t, rb);
+            store_op<T, !TA, BS, VEC>(As + (cur ^ 1) * BS * LDK, t, ra);
+            store_op<T, TB, BS, VEC>(Bs + (cur ^ 1) * BS * LDK, t, rb);
         }
         __syncthreads();
     }
@@ -193,7 +267,8 @@ __device__ __forceinline__ void gemm_tile(const Params& p, int m0, int n0, long 
     // Epilogue.  Accumulator element r of lane l holds column l % 16 of its
     // 16 x 16 tile and row 4 r + l / 16 (FP64 MFMA) or 4 (l / 16) + r (FP32).
     const double* __restrict__ C = p.C ? p.C + bz * p.sC : nullptr;
-    double* __restrict__ D = p.D + bz * p.sD;
+    double* __restrict__ D = p.Df ? nullptr : p.D + bz * p.sD;
+    float* __restrict__ Df = p.Df ? p.Df + bz * p.sD : nullptr;
 #pragma unroll
     for (int i = 0; i < IT; ++i)
 #pragma unroll
@@ -204,23 +279,27 @@ __device__ __forceinline__ void gemm_tile(const Params& p, int m0, int n0, long 
                 const int row = m0 + wm * (BS / 2) + i * 16 + MfmaOp<T>::row(kg, r);
                 if (row < p.M && col < p.N) {
                     double v = p.alpha * (double)acc[i][j][r];
-                    if (C) v += p.beta * C[(long)row * p.ldc + col];
-                    D[(long)row * p.ldd + col] = v;
+                    if (Df) {
+                        Df[(long)row * p.ldd + col] = (float)v;
+                    } else {
+                        if (C) v += p.beta * C[(long)row * p.ldc + col];
+                        D[(long)row * p.ldd + col] = v;
+                    }
                 }
             }
         }
 }
 
-template <typename T, bool TA, bool TB>
+template <typename T, bool TA, bool TB, bool VEC = false>
 __global__ __launch_bounds__(NTHREADS, 2) void gemm_kernel(Params p) {
     constexpr int LDK = MfmaOp<T>::LDK;
-    __shared__ T As[2 * BM * LDK];
-    __shared__ T Bs[2 * BN * LDK];
+    __shared__ __attribute__((aligned(16))) T As[2 * BM * LDK];
+    __shared__ __attribute__((aligned(16))) T Bs[2 * BN * LDK];
     const int T_tiles = p.mt * p.nt;
     const int tile = xcd_band_tile(blockIdx.x, T_tiles);
     const int m0 = (tile / p.nt) * BM;
     const int n0 = (tile % p.nt) * BN;
-    gemm_tile<T, TA, TB, BM>(p, m0, n0, (long)blockIdx.z, As, Bs);
+    gemm_tile<T, TA, TB, BM, VEC>(p, m0, n0, (long)blockIdx.z, As, Bs);
 }
 
 // Many independent FP64 problems in one persistent launch (the products of
@@ -250,9 +329,18 @@ __global__ __launch_bounds__(NTHREADS, 2) void gemm_grouped_kernel(const GroupDe
     }
 }
 
+// Operands fit 16-byte loads: aligned bases, row strides and batch strides
+// that are multiples of 16 bytes.
+inline bool vec16(const Gemm& g, size_t esz) {
+    const size_t q = 16 / esz;
+    auto al = [](const void* p) { return ((uintptr_t)p & 15) == 0; };
+    return al(g.A) && al(g.B) && g.lda % q == 0 && g.ldb % q == 0 && g.sA % q == 0 && g.sB % q == 0;
+}
+
 template <typename T>
 void launch(const Gemm& g, hipStream_t s) {
     if (g.M <= 0 || g.N <= 0 || g.batch <= 0) return;
+    if (g.Df && g.C) ITE_FAIL(ITE_EINVAL, "gemm: an FP32 output takes no C");
     Params p;
     p.M = g.M; p.N = g.N; p.K = g.K;
     p.alpha = g.alpha; p.beta = g.beta;
@@ -260,13 +348,19 @@ void launch(const Gemm& g, hipStream_t s) {
     p.B = g.B; p.ldb = g.ldb; p.sB = g.sB;
     p.C = g.C; p.ldc = g.ldc; p.sC = g.sC;
     p.D = g.D; p.ldd = g.ldd; p.sD = g.sD;
+    p.Df = std::is_same<T, float>::value ? g.Df : nullptr;
     p.mt = (g.M + BM - 1) / BM;
     p.nt = (g.N + BN - 1) / BN;
     dim3 grid(p.mt * p.nt, 1, g.batch);
-    if (!g.tA && !g.tB) hipLaunchKernelGGL((gemm_kernel<T, false, false>), grid, dim3(NTHREADS), 0, s, p);
-    else if (!g.tA && g.tB) hipLaunchKernelGGL((gemm_kernel<T, false, true>), grid, dim3(NTHREADS), 0, s, p);
-    else if (g.tA && !g.tB) hipLaunchKernelGGL((gemm_kernel<T, true, false>), grid, dim3(NTHREADS), 0, s, p);
-    else hipLaunchKernelGGL((gemm_kernel<T, true, true>), grid, dim3(NTHREADS), 0, s, p);
+    const bool v = std::is_same<T, float>::value && vec16(g, sizeof(T));
+#define ITE_GL(TA, TB)                                                                              \
+    if (v) hipLaunchKernelGGL((gemm_kernel<T, TA, TB, true>), grid, dim3(NTHREADS), 0, s, p);       \
+    else hipLaunchKernelGGL((gemm_kernel<T, TA, TB, false>), grid, dim3(NTHREADS), 0, s, p)
+    if (!g.tA && !g.tB) { ITE_GL(false, false); }
+    else if (!g.tA && g.tB) { ITE_GL(false, true); }
+    else if (g.tA && !g.tB) { ITE_GL(true, false); }
+    else { ITE_GL(true, true); }
+#undef ITE_GL
     HIP_CHECK(hipGetLastError());
 }
 
@@ -327,7 +421,88 @@ __device__ inline void store_slice16(uint16_t* __restrict__ lds, int t, const ui
     }
 }
 
-template <bool TA, bool TB>
+// 16-byte loads (eight BF16 values) into the same registers and LDS layout
+// as fetch_slice16 / store_slice16; chunks across the matrix edge element by
+// element.
+__device__ inline void unpack8(const uint4 v, uint16_t* r) {
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        r[2 * q] = (uint16_t)(w[q] & 0xffffu);
+        r[2 * q + 1] = (uint16_t)(w[q] >> 16);
+    }
+}
+
+template <bool KC>
+__device__ inline void fetch_slice16_v(const uint16_t* __restrict__ src, long ld, int side0, int sideN, int k0, int K,
+                                       int t, uint16_t (&r)[16]) {
+    if (KC) {
+        const int row = side0 + (t >> 1);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int k = k0 + ((t & 1) * 2 + c) * 8;
+            if (row < sideN && k + 7 < K) {
+                unpack8(*reinterpret_cast<const uint4*>(src + (long)row * ld + k), &r[8 * c]);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    r[8 * c + q] = (row < sideN && k + q < K) ? src[(long)row * ld + k + q] : (uint16_t)0;
+            }
+        }
+    } else {
+        const int col = side0 + (t & 15) * 8;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int k = k0 + (t >> 4) + 16 * e;
+            if (k < K && col + 7 < sideN) {
+                unpack8(*reinterpret_cast<const uint4*>(src + (long)k * ld + col), &r[8 * e]);
+            } else {
+#pragma unroll
+                for (int q = 0; q < 8; ++q)
+                    r[8 * e + q] = (k < K && col + q < sideN) ? src[(long)k * ld + col + q] : (uint16_t)0;
+            }
+        }
+    }
+}
+
+template <bool KC>
+__device__ inline void store_slice16_v(uint16_t* __restrict__ lds, int t, const uint16_t (&r)[16]) {
+    if (KC) {
+        const int row = t >> 1;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int kk = ((t & 1) * 2 + c) * 8;
+            uint4 v;
+            v.x = (uint32_t)r[8 * c] | ((uint32_t)r[8 * c + 1] << 16);
+            v.y = (uint32_t)r[8 * c + 2] | ((uint32_t)r[8 * c + 3] << 16);
+            v.z = (uint32_t)r[8 * c + 4] | ((uint32_t)r[8 * c + 5] << 16);
+            v.w = (uint32_t)r[8 * c + 6] | ((uint32_t)r[8 * c + 7] << 16);
+            *reinterpret_cast<uint4*>(&lds[row * LDK16 + kk]) = v;
+        }
+    } else {
+        const int col = (t & 15) * 8;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int krow = (t >> 4) + 16 * e;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) lds[(col + q) * LDK16 + krow] = r[8 * e + q];
+        }
+    }
+}
+
+template <bool KC, bool VEC>
+__device__ inline void fetch16(const uint16_t* __restrict__ src, long ld, int side0, int sideN, int k0, int K, int t,
+                               uint16_t (&r)[16]) {
+    if constexpr (VEC) fetch_slice16_v<KC>(src, ld, side0, sideN, k0, K, t, r);
+    else fetch_slice16<KC>(src, ld, side0, sideN, k0, K, t, r);
+}
+template <bool KC, bool VEC>
+__device__ inline void store16(uint16_t* __restrict__ lds, int t, const uint16_t (&r)[16]) {
+    if constexpr (VEC) store_slice16_v<KC>(lds, t, r);
+    else store_slice16<KC>(lds, t, r);
+}
+
+template <bool TA, bool TB, bool VEC>
 __global__ __launch_bounds__(NTHREADS) void gemm_bf16_kernel(Params p) {
     __shared__ __attribute__((aligned(16))) uint16_t As[2][BM * LDK16];
     __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BN * LDK16];
@@ -350,17 +525,17 @@ __global__ __launch_bounds__(NTHREADS) void gemm_bf16_kernel(Params p) {
         for (int j = 0; j < 4; ++j) acc[i][j] = f4_t{0, 0, 0, 0};
     uint16_t ra[16], rb[16];
     const int nk = (p.K + BK16 - 1) / BK16;
-    fetch_slice16<!TA>(A, p.lda, m0, p.M, 0, p.K, t, ra);
-    fetch_slice16<TB>(B, p.ldb, n0, p.N, 0, p.K, t, rb);
-    store_slice16<!TA>(As[0], t, ra);
-    store_slice16<TB>(Bs[0], t, rb);
+    fetch16<!TA, VEC>(A, p.lda, m0, p.M, 0, p.K, t, ra);
+    fetch16<TB, VEC>(B, p.ldb, n0, p.N, 0, p.K, t, rb);
+    store16<!TA, VEC>(As[0], t, ra);
+    store16<TB, VEC>(Bs[0], t, rb);
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
         const bool more = kt + 1 < nk;
         if (more) {
-            fetch_slice16<!TA>(A, p.lda, m0, p.M, (kt + 1) * BK16, p.K, t, ra);
-            fetch_slice16<TB>(B, p.ldb, n0, p.N, (kt + 1) * BK16, p.K, t, rb);
+            fetch16<!TA, VEC>(A, p.lda, m0, p.M, (kt + 1) * BK16, p.K, t, ra);
+            fetch16<TB, VEC>(B, p.ldb, n0, p.N, (kt + 1) * BK16, p.K, t, rb);
         }
         bf8_t a[4], b[4];
 #pragma unroll
@@ -374,13 +549,14 @@ __global__ __launch_bounds__(NTHREADS) void gemm_bf16_kernel(Params p) {
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         if (more) {
-            store_slice16<!TA>(As[cur ^ 1], t, ra);
-            store_slice16<TB>(Bs[cur ^ 1], t, rb);
+            store16<!TA, VEC>(As[cur ^ 1], t, ra);
+            store16<TB, VEC>(Bs[cur ^ 1], t, rb);
         }
         __syncthreads();
     }
     const double* __restrict__ C = p.C ? p.C + bz * p.sC : nullptr;
-    double* __restrict__ D = p.D + bz * p.sD;
+    double* __restrict__ D = p.Df ? nullptr : p.D + bz * p.sD;
+    float* __restrict__ Df = p.Df ? p.Df + bz * p.sD : nullptr;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -391,8 +567,12 @@ __global__ __launch_bounds__(NTHREADS) void gemm_bf16_kernel(Params p) {
                 const int row = m0 + wm * 64 + i * 16 + 4 * kg + r;
                 if (row < p.M && col < p.N) {
                     double v = p.alpha * (double)acc[i][j][r];
-                    if (C) v += p.beta * C[(long)row * p.ldc + col];
-                    D[(long)row * p.ldd + col] = v;
+                    if (Df) {
+                        Df[(long)row * p.ldd + col] = (float)v;
+                    } else {
+                        if (C) v += p.beta * C[(long)row * p.ldc + col];
+                        D[(long)row * p.ldd + col] = v;
+                    }
                 }
             }
         }
@@ -456,13 +636,20 @@ void gemm_bf16(const Gemm& g, hipStream_t s) {
     p.B = g.B; p.ldb = g.ldb; p.sB = g.sB;
     p.C = g.C; p.ldc = g.ldc; p.sC = g.sC;
     p.D = g.D; p.ldd = g.ldd; p.sD = g.sD;
+    p.Df = g.Df;
+    if (g.Df && g.C) ITE_FAIL(ITE_EINVAL, "gemm: an FP32 output takes no C");
     p.mt = (g.M + BM - 1) / BM;
     p.nt = (g.N + BN - 1) / BN;
     dim3 grid(p.mt * p.nt, 1, g.batch);
-    if (!g.tA && !g.tB) hipLaunchKernelGGL((gemm_bf16_kernel<false, false>), grid, dim3(NTHREADS), 0, s, p);
-    else if (!g.tA && g.tB) hipLaunchKernelGGL((gemm_bf16_kernel<false, true>), grid, dim3(NTHREADS), 0, s, p);
-    else if (g.tA && !g.tB) hipLaunchKernelGGL((gemm_bf16_kernel<true, false>), grid, dim3(NTHREADS), 0, s, p);
-    else hipLaunchKernelGGL((gemm_bf16_kernel<true, true>), grid, dim3(NTHREADS), 0, s, p);
+    const bool v = vec16(g, sizeof(uint16_t));
+#define ITE_GB(TA, TB)                                                                               \
+    if (v) hipLaunchKernelGGL((gemm_bf16_kernel<TA, TB, true>), grid, dim3(NTHREADS), 0, s, p);      \
+    else hipLaunchKernelGGL((gemm_bf16_kernel<TA, TB, false>), grid, dim3(NTHREADS), 0, s, p)
+    if (!g.tA && !g.tB) { ITE_GB(false, false); }
+    else if (!g.tA && g.tB) { ITE_GB(false, true); }
+    else if (g.tA && !g.tB) { ITE_GB(true, false); }
+    else { ITE_GB(true, true); }
+#undef ITE_GB
     HIP_CHECK(hipGetLastError());
 }
 

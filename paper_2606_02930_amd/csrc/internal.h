@@ -50,6 +50,7 @@ struct Gemm {
     const double* C = nullptr; long ldc = 0, sC = 0;
     double* D = nullptr; long ldd = 0, sD = 0;
     int batch = 1;
+    float* Df = nullptr;        // FP32 / BF16 operand kernels: FP32 output here instead of D (C must be null)
 };
 // FP64 operands, FP64 MFMA.
 void gemm_f64(const Gemm& g, hipStream_t s);
@@ -77,10 +78,13 @@ void gemm_bf16(const Gemm& g, hipStream_t s);
 struct Stage {
     int G = 0, I = 0, O = 0, C = 0;
     const double* in = nullptr;
+    const float* in_f32 = nullptr;   // when set: FP32 input (same addressing) instead of `in`
     long in_gs = 0, in_s1 = 0, in_s2 = 0, in_cs = 1; int in_div = 1;
     double* out = nullptr;
     long out_gs = 0, out_s1 = 0, out_s2 = 0, out_cs = 1; int out_div = 1;
     const int* rowptr = nullptr; const int* col = nullptr; const double* val = nullptr;
+    int nnz = -1;               // entries of the CSR matrix (-1: unknown, no LDS copy)
+    int csr_lds = 0;            // set by the launcher: the matrix is copied to LDS
     int out_prec = 0;           // 0: FP64 into out; 1: FP32, 2: BF16 into out_lo
     void* out_lo = nullptr;
 };

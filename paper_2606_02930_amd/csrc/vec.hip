@@ -384,24 +384,53 @@ __global__ void transpose_kernel(const double* __restrict__ in, int rows, int co
 // to 16 columns for the largest stage an MPO can have (w = 16, d = 8: 1024).
 // ---------------------------------------------------------------------------
 constexpr size_t STAGE_LDS = 128 * 1024;
+// LDS of a stage workgroup: the inputs (at most STAGE_LDS) and, when it fits,
+// the CSR matrix behind them
+constexpr size_t STAGE_LDS_TOTAL = 152 * 1024;
 
 // OUT: 0 writes FP64 to st.out, 1 rounds to FP32 and 2 to BF16 into st.out_lo
 // (the operand of a following low-precision contraction).
 template <int OUT, int SC>
 __device__ inline void stage_unit(const Stage& st, int g, int cblk, double* xin) {
     const int c = cblk * SC + threadIdx.x;
-    const double* __restrict__ in = st.in + (long)g * st.in_gs + (long)c * st.in_cs;
-    for (int i = 0; i < st.I; ++i) {
-        const long off = (long)(i / st.in_div) * st.in_s1 + (long)(i % st.in_div) * st.in_s2;
-        xin[i * SC + threadIdx.x] = (c < st.C) ? in[off] : 0.0;
+    const long cin = (long)g * st.in_gs + (long)c * st.in_cs;
+    if (st.in_f32) {
+        const float* __restrict__ in = st.in_f32 + cin;
+        for (int i = 0; i < st.I; ++i) {
+            const long off = (long)(i / st.in_div) * st.in_s1 + (long)(i % st.in_div) * st.in_s2;
+            xin[i * SC + threadIdx.x] = (c < st.C) ? (double)in[off] : 0.0;
+        }
+    } else {
+        const double* __restrict__ in = st.in + cin;
+        for (int i = 0; i < st.I; ++i) {
+            const long off = (long)(i / st.in_div) * st.in_s1 + (long)(i % st.in_div) * st.in_s2;
+            xin[i * SC + threadIdx.x] = (c < st.C) ? in[off] : 0.0;
+        }
+    }
+    // the CSR matrix in LDS when it fits behind the inputs (read as
+    // broadcasts instead of a chain of dependent scalar loads)
+    const int nnz = st.nnz;
+    const bool lcsr = st.csr_lds != 0;
+    double* sval = xin + (size_t)st.I * SC;
+    int* scol = reinterpret_cast<int*>(sval + nnz);
+    int* srow = scol + nnz;
+    if (lcsr) {
+        for (int e = threadIdx.x; e < nnz; e += SC) {
+            sval[e] = st.val[e];
+            scol[e] = st.col[e];
+        }
+        for (int o = threadIdx.x; o <= st.O; o += SC) srow[o] = st.rowptr[o];
     }
     __syncthreads();
     if (c < st.C) {
         const long base = (long)g * st.out_gs + (long)c * st.out_cs;
+        const int* rp = lcsr ? srow : st.rowptr;
+        const int* cl = lcsr ? scol : st.col;
+        const double* vl = lcsr ? sval : st.val;
         for (int o = 0; o < st.O; ++o) {
             double acc = 0.0;
-            const int e1 = st.rowptr[o + 1];
-            for (int e = st.rowptr[o]; e < e1; ++e) acc += st.val[e] * xin[st.col[e] * SC + threadIdx.x];
+            const int e1 = rp[o + 1];
+            for (int e = rp[o]; e < e1; ++e) acc += vl[e] * xin[cl[e] * SC + threadIdx.x];
             const long at = base + (long)(o / st.out_div) * st.out_s1 + (long)(o % st.out_div) * st.out_s2;
             if (OUT == 0) st.out[at] = acc;
             else if (OUT == 1) static_cast<float*>(st.out_lo)[at] = (float)acc;
@@ -415,6 +444,90 @@ template <int OUT, int SC>
 __global__ __launch_bounds__(SC) void stage_kernel(Stage st) {
     extern __shared__ double xin[];   // [I][SC]
     stage_unit<OUT, SC>(st, blockIdx.y, blockIdx.x, xin);
+}
+
+// Four adjacent columns per thread (unit column strides, every stride a
+// multiple of 4, 16-byte aligned bases): 16-byte loads and stores instead of
+// one element per lane.  The inputs keep their type in LDS (an FP32 input
+// takes half the space, so twice the columns fit per compute unit), laid out
+// [I][4][SC] so that each LDS read is lane-contiguous.  Same sums in the same
+// order as stage_unit.
+template <typename TIN>
+__device__ inline void load4(const TIN* p, TIN (&v)[4]) {
+    if constexpr (sizeof(TIN) == 4) {
+        const float4 q = *reinterpret_cast<const float4*>(p);
+        v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    } else {
+        const double2 a = *reinterpret_cast<const double2*>(p);
+        const double2 b = *reinterpret_cast<const double2*>(p + 2);
+        v[0] = a.x; v[1] = a.y; v[2] = b.x; v[3] = b.y;
+    }
+}
+
+template <int OUT, int SC, typename TIN>
+__global__ __launch_bounds__(SC) void stage4_kernel(Stage st) {
+    extern __shared__ double lds_raw[];
+    TIN* xin = reinterpret_cast<TIN*>(lds_raw);   // [I][4][SC]
+    const int g = blockIdx.y;
+    const int t = threadIdx.x;
+    const int c0 = (blockIdx.x * SC + t) * 4;
+    const bool live = c0 < st.C;
+    const TIN* __restrict__ in;
+    if constexpr (sizeof(TIN) == 4) in = st.in_f32;
+    else in = st.in;
+    in += (long)g * st.in_gs + c0;
+    const bool in_flat = st.in_div == 1;   // no division in the common layout
+    for (int i = 0; i < st.I; ++i) {
+        TIN v[4] = {0, 0, 0, 0};
+        const long off = in_flat ? (long)i * st.in_s1
+                                 : (long)(i / st.in_div) * st.in_s1 + (long)(i % st.in_div) * st.in_s2;
+        if (live) load4(in + off, v);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) xin[(i * 4 + q) * SC + t] = v[q];
+    }
+    const int nnz = st.nnz;
+    const bool lcsr = st.csr_lds != 0;
+    double* sval = reinterpret_cast<double*>(xin + (size_t)st.I * 4 * SC);
+    int* scol = reinterpret_cast<int*>(sval + nnz);
+    int* srow = scol + nnz;
+    if (lcsr) {
+        for (int e = t; e < nnz; e += SC) {
+            sval[e] = st.val[e];
+            scol[e] = st.col[e];
+        }
+        for (int o = t; o <= st.O; o += SC) srow[o] = st.rowptr[o];
+    }
+    __syncthreads();
+    if (!live) return;
+    const int* rp = lcsr ? srow : st.rowptr;
+    const int* cl = lcsr ? scol : st.col;
+    const double* vl = lcsr ? sval : st.val;
+    const long base = (long)g * st.out_gs + c0;
+    const bool out_flat = st.out_div == 1;
+    for (int o = 0; o < st.O; ++o) {
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        const int e1 = rp[o + 1];
+        for (int e = rp[o]; e < e1; ++e) {
+            const double w = vl[e];
+            const TIN* x = xin + cl[e] * 4 * SC + t;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[q] += w * (double)x[q * SC];
+        }
+        const long at = base + (out_flat ? (long)o * st.out_s1
+                                         : (long)(o / st.out_div) * st.out_s1 + (long)(o % st.out_div) * st.out_s2);
+        if (OUT == 0) {
+            *reinterpret_cast<double2*>(st.out + at) = double2{acc[0], acc[1]};
+            *reinterpret_cast<double2*>(st.out + at + 2) = double2{acc[2], acc[3]};
+        } else if (OUT == 1) {
+            *reinterpret_cast<float4*>(static_cast<float*>(st.out_lo) + at) =
+                float4{(float)acc[0], (float)acc[1], (float)acc[2], (float)acc[3]};
+        } else {
+            uint2 v;
+            v.x = (uint32_t)to_bf16(acc[0]) | ((uint32_t)to_bf16(acc[1]) << 16);
+            v.y = (uint32_t)to_bf16(acc[2]) | ((uint32_t)to_bf16(acc[3]) << 16);
+            *reinterpret_cast<uint2*>(static_cast<uint16_t*>(st.out_lo) + at) = v;
+        }
+    }
 }
 
 inline int grid_for(size_t n, int threads, int cap = 4096) {
@@ -749,19 +862,63 @@ void transpose(const double* in, int rows, int cols, double* out, hipStream_t s)
 }
 
 template <int SC>
-static void stage_launch(const Stage& st, hipStream_t s) {
+static void stage_launch(Stage st, hipStream_t s) {
     dim3 grid((st.C + SC - 1) / SC, st.G);
-    const size_t lds = (size_t)st.I * SC * sizeof(double);
+    size_t lds = (size_t)st.I * SC * sizeof(double);
+    const size_t csr = (size_t)st.nnz * 12 + (size_t)(st.O + 1) * 4;
+    st.csr_lds = st.nnz >= 0 && lds + csr <= STAGE_LDS_TOTAL;
+    if (st.csr_lds) lds += csr;
     if (st.out_prec == 0) hipLaunchKernelGGL((stage_kernel<0, SC>), grid, dim3(SC), lds, s, st);
     else if (st.out_prec == 1) hipLaunchKernelGGL((stage_kernel<1, SC>), grid, dim3(SC), lds, s, st);
     else hipLaunchKernelGGL((stage_kernel<2, SC>), grid, dim3(SC), lds, s, st);
     HIP_CHECK(hipGetLastError());
 }
 
+// Whether the four-column kernel applies: unit column strides, strides and
+// the column count multiples of 4, 16-byte aligned bases.
+static bool stage4_ok(const Stage& st) {
+    auto m4 = [](long v) { return v % 4 == 0; };
+    auto al = [](const void* p, uintptr_t a) { return ((uintptr_t)p & (a - 1)) == 0; };
+    if (st.in_cs != 1 || st.out_cs != 1 || st.C % 4 != 0) return false;
+    if (!m4(st.in_gs) || !m4(st.in_s1) || (st.in_div > 1 && !m4(st.in_s2))) return false;
+    if (!m4(st.out_gs) || !m4(st.out_s1) || (st.out_div > 1 && !m4(st.out_s2))) return false;
+    const void* in = st.in_f32 ? static_cast<const void*>(st.in_f32) : static_cast<const void*>(st.in);
+    if (!al(in, 16)) return false;
+    if (st.out_prec == 0) return al(st.out, 16);
+    return al(st.out_lo, st.out_prec == 1 ? 16 : 8);
+}
+
+template <int SC, typename TIN>
+static void stage4_launch(Stage st, hipStream_t s) {
+    dim3 grid((st.C / 4 + SC - 1) / SC, st.G);
+    size_t lds = (size_t)st.I * 4 * SC * sizeof(TIN);
+    lds = (lds + 7) & ~(size_t)7;
+    const size_t csr = (size_t)st.nnz * 12 + (size_t)(st.O + 1) * 4;
+    st.csr_lds = st.nnz >= 0 && lds + csr <= STAGE_LDS_TOTAL;
+    if (st.csr_lds) lds += csr;
+    if (st.out_prec == 0) hipLaunchKernelGGL((stage4_kernel<0, SC, TIN>), grid, dim3(SC), lds, s, st);
+    else if (st.out_prec == 1) hipLaunchKernelGGL((stage4_kernel<1, SC, TIN>), grid, dim3(SC), lds, s, st);
+    else hipLaunchKernelGGL((stage4_kernel<2, SC, TIN>), grid, dim3(SC), lds, s, st);
+    HIP_CHECK(hipGetLastError());
+}
+
+template <typename TIN>
+static void stage4_pick(const Stage& st, hipStream_t s) {
+    const size_t per_col = (size_t)st.I * 4 * sizeof(TIN);
+    if (per_col * 64 <= STAGE_LDS) stage4_launch<64, TIN>(st, s);
+    else stage4_launch<32, TIN>(st, s);
+}
+
 void stage_f64(const Stage& st, hipStream_t s) {
     if (st.G <= 0 || st.C <= 0 || st.O <= 0) return;
     if (st.I < 1 || (size_t)st.I * 16 * sizeof(double) > STAGE_LDS)
         ITE_FAIL(ITE_EINVAL, "MPO stage: more than 1024 inputs per column");
+    const size_t in_bytes = st.in_f32 ? sizeof(float) : sizeof(double);
+    if (stage4_ok(st) && (size_t)st.I * 4 * 32 * in_bytes <= STAGE_LDS) {
+        if (st.in_f32) stage4_pick<float>(st, s);
+        else stage4_pick<double>(st, s);
+        return;
+    }
     const size_t per_col = (size_t)st.I * sizeof(double);
     if (per_col * 128 <= STAGE_LDS) stage_launch<128>(st, s);
     else if (per_col * 64 <= STAGE_LDS) stage_launch<64>(st, s);

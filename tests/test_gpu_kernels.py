@@ -60,9 +60,12 @@ def test_gemm_f64(env, tA, tB, shape):
 
 @pytest.mark.parametrize("prec", [1, 2])
 @pytest.mark.parametrize("tB", [0, 1])
-def test_gemm_low_precision(env, prec, tB):
+@pytest.mark.parametrize("shape", [(200, 136, 520), (37, 133, 517), (256, 128, 1024)])
+def test_gemm_low_precision(env, prec, tB, shape):
+    # aligned rows take the 16-byte operand loads (ragged edges element by
+    # element), the 517-wide shape the element loads throughout
     torch, ctx = env
-    M, N, K = 200, 136, 520
+    M, N, K = shape
     rng = np.random.default_rng(11 + prec + tB)
     A = rng.standard_normal((M, K))
     B = rng.standard_normal((N, K) if tB else (K, N))
