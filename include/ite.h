@@ -493,6 +493,16 @@ int ite_debug_heff_apply(ite_ctx* ctx, int Dxl, int Dyl, int Dxr, int Dyr, int d
                          const double* W2h, const double* R, const double* theta,
                          double alpha, double beta, double* y, int prec);
 
+/* The product of ite_debug_heff_apply as a local solve runs it (the MPO pair
+ * matrix uploaded and, for prec 1 / 2, the environments rounded once, before
+ * the timed region), repeated reps times on the context's stream; writes y
+ * and the mean device time per product in milliseconds (HIP events). */
+int ite_debug_heff_time(ite_ctx* ctx, int Dxl, int Dyl, int Dxr, int Dyr, int d1, int d2,
+                        int w0, int w1, int w2, const double* L, const double* W1h,
+                        const double* W2h, const double* R, const double* theta,
+                        double alpha, double beta, double* y, int prec, int reps,
+                        double* ms_per_product);
+
 /* Environment updates (device pointers; W host):
  * dir = 0 (left):  E'[b', v, b] = sum E[a', w, a] X[a', p, b'] W[w, v, p, s] Y[a, s, b]
  *   E [Dxa][wl][Dya], X [Dxa][d][Dxb], Y [Dya][d][Dyb] -> E' [Dxb][wr][Dyb]

@@ -129,6 +129,8 @@ _SIGNATURES = {
     "ite_debug_gemm": (_I, [_P, _I, _I, _I, _I, _I, _D, _P, _I, _P, _I, _D, _P, _I, _P, _I, _I]),
     "ite_debug_heff_apply": (_I, [_P, _I, _I, _I, _I, _I, _I, _I, _I, _I, _P, _PD, _PD, _P, _P,
                                   _D, _D, _P, _I]),
+    "ite_debug_heff_time": (_I, [_P, _I, _I, _I, _I, _I, _I, _I, _I, _I, _P, _PD, _PD, _P, _P,
+                                 _D, _D, _P, _I, _I, _PD]),
     "ite_debug_env_update": (_I, [_P, _I, _I, _I, _I, _I, _I, _I, _I, _P, _P, _PD, _P, _P]),
     "ite_debug_svd_split": (_I, [_P, _I, _I, _I, _I, _I, _P, _I, _D, _D, _P, _P, _PD, _PI, _PD]),
     "ite_debug_local_solve": (_I, [_P, _I, _I, _I, _I, _I, _I, _I, _P, _PD, _PD, _P, _D, _D, _P, _P,
@@ -537,6 +539,21 @@ def ite_debug_heff_apply(ctx: Ctx, L, W1, W2, R, theta, alpha, beta, y, prec=0):
     _check(load_library().ite_debug_heff_apply(ctx.handle, Dxl, Dyl, Dxr, Dyr, d1, d2, w0, W1.shape[1], w2,
                                                _tp(L), _dptr(W1), _dptr(W2), _tp(R), _tp(theta), float(alpha),
                                                float(beta), _tp(y), int(prec)), ctx.handle)
+
+
+def ite_debug_heff_time(ctx: Ctx, L, W1, W2, R, theta, alpha, beta, y, prec=0, reps=10):
+    """Mean device milliseconds of one H_eff product as a local solve runs it."""
+    W1 = np.ascontiguousarray(W1, dtype=np.float64)
+    W2 = np.ascontiguousarray(W2, dtype=np.float64)
+    Dxl, w0, Dyl = L.shape
+    Dxr, w2, Dyr = R.shape
+    d1, d2 = W1.shape[2], W2.shape[2]
+    ms = C.c_double(0.0)
+    _check(load_library().ite_debug_heff_time(ctx.handle, Dxl, Dyl, Dxr, Dyr, d1, d2, w0, W1.shape[1], w2,
+                                              _tp(L), _dptr(W1), _dptr(W2), _tp(R), _tp(theta), float(alpha),
+                                              float(beta), _tp(y), int(prec), int(reps), C.byref(ms)),
+           ctx.handle)
+    return ms.value
 
 
 def ite_debug_env_update(ctx: Ctx, direction, E, X, W, Y, Eout):

@@ -652,6 +652,41 @@ int ite_debug_heff_apply(ite_ctx* c, int Dxl, int Dyl, int Dxr, int Dyr, int d1,
     });
 }
 
+int ite_debug_heff_time(ite_ctx* c, int Dxl, int Dyl, int Dxr, int Dyr, int d1, int d2, int w0, int w1, int w2,
+                        const double* L, const double* W1h, const double* W2h, const double* R, const double* theta,
+                        double alpha, double beta, double* y, int prec, int reps, double* ms_per_product) {
+    if (!c) return ITE_EINVAL;
+    return guarded(c, [&] {
+        set_device(c);
+        ITE_REQUIRE(L && W1h && W2h && R && theta && y && ms_per_product, "debug_heff_time: NULL pointer");
+        ITE_REQUIRE(Dxl > 0 && Dyl > 0 && Dxr > 0 && Dyr > 0 && d1 > 0 && d2 > 0 && w0 > 0 && w1 > 0 && w2 > 0,
+                    "debug_heff_time: bad shape");
+        ITE_REQUIRE(alpha == 0.0 || (Dxl == Dyl && Dxr == Dyr), "debug_heff_time: alpha needs square shapes");
+        ITE_REQUIRE(prec >= 0 && prec <= 2, "debug_heff_time: unknown precision");
+        ITE_REQUIRE(reps >= 1, "debug_heff_time: reps must be positive");
+        TmpCsr t(c, pair_matrix(W1h, W2h, w0, w1, w2, d1, d2), d1 * d2 * w2, w0 * d1 * d2);
+        HeffShape s{Dxl, Dyl, Dxr, Dyr, d1, d2, w0, w2};
+        const Prec p = prec == 0 ? Prec::F64 : (prec == 1 ? Prec::F32 : Prec::BF16);
+        const void* Llo = nullptr;
+        const void* Rlo = nullptr;
+        if (p != Prec::F64) lo_shadows(c, s, p, L, R, &Llo, &Rlo);
+        auto once = [&] { heff_apply(c, s, L, t.cs, R, theta, beta, alpha, alpha != 0.0 ? theta : nullptr, y, p, Llo, Rlo); };
+        once();
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        HIP_CHECK(hipEventCreate(&e0));
+        HIP_CHECK(hipEventCreate(&e1));
+        HIP_CHECK(hipEventRecord(e0, c->stream));
+        for (int r = 0; r < reps; ++r) once();
+        HIP_CHECK(hipEventRecord(e1, c->stream));
+        HIP_CHECK(hipEventSynchronize(e1));
+        float ms = 0.0f;
+        HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        *ms_per_product = ms / reps;
+    });
+}
+
 int ite_debug_env_update(ite_ctx* c, int dir, int Dxa, int Dya, int Dxb, int Dyb, int d, int wl, int wr,
                          const double* E, const double* X, const double* Wh, const double* Y, double* Eout) {
     if (!c) return ITE_EINVAL;

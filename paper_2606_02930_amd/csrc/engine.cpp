@@ -205,6 +205,18 @@ static void gemm_lo(ite_ctx* c, Prec p, bool tA, bool tB, int M, int N, int K, d
     else gemm_bf16(g, c->stream);
 }
 
+void lo_shadows(ite_ctx* c, const HeffShape& s, Prec prec, const double* L, const double* R, const void** Llo,
+                const void** Rlo) {
+    const size_t eb = lo_bytes(prec);
+    const size_t nl = (size_t)s.Dxl * s.w0 * s.Dyl, nr = (size_t)s.Dxr * s.w2 * s.Dyr;
+    void* l = slot(c, SL_LO_L, nl * eb);
+    void* r = slot(c, SL_LO_R, nr * eb);
+    to_lo(c, prec, L, l, nl);
+    to_lo(c, prec, R, r, nr);
+    *Llo = l;
+    *Rlo = r;
+}
+
 void heff_apply(ite_ctx* c, const HeffShape& s, const double* L, const CsrDev& ww, const double* R,
                 const double* theta, double beta, double alpha, const double* Cadd, double* y, Prec prec,
                 const void* Llo, const void* Rlo) {
@@ -216,15 +228,7 @@ void heff_apply(ite_ctx* c, const HeffShape& s, const double* L, const CsrDev& w
         // half the traffic of FP64), the second in the operand precision, the
         // output in FP64
         const size_t eb = lo_bytes(prec);
-        if (!Llo || !Rlo) {
-            const size_t nl = (size_t)s.Dxl * s.w0 * s.Dyl, nr = (size_t)s.Dxr * s.w2 * s.Dyr;
-            void* l = slot(c, SL_LO_L, nl * eb);
-            void* r = slot(c, SL_LO_R, nr * eb);
-            to_lo(c, prec, L, l, nl);
-            to_lo(c, prec, R, r, nr);
-            Llo = l;
-            Rlo = r;
-        }
+        if (!Llo || !Rlo) lo_shadows(c, s, prec, L, R, &Llo, &Rlo);
         const size_t nth = (size_t)s.Dyl * s.d1 * s.d2 * s.Dyr;
         void* tlo = slot(c, SL_LO_T, nth * eb);
         void* x3lo = slot(c, SL_LO_X, nx * eb);

@@ -128,6 +128,10 @@ struct HeffShape {
 // y = beta * H_eff theta + alpha * Cadd (Cadd may be null; y may alias Cadd).
 // prec F32 / BF16: operands rounded to that precision (Llo / Rlo: environments
 // already rounded, else rounded here), FP32 accumulation, FP64 output.
+// FP32 / BF16 copies of the environments of a low-precision product (context
+// buffers, valid until the next call), as a local solve makes them once.
+void lo_shadows(ite_ctx* c, const HeffShape& s, Prec prec, const double* L, const double* R, const void** Llo,
+                const void** Rlo);
 void heff_apply(ite_ctx* c, const HeffShape& s, const double* L, const CsrDev& ww, const double* R,
                 const double* theta, double beta, double alpha, const double* Cadd, double* y,
                 Prec prec, const void* Llo = nullptr, const void* Rlo = nullptr);

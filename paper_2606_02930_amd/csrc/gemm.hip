@@ -378,134 +378,112 @@ __global__ void mfma_probe_kernel(double* out) {
 
 // ---------------------------------------------------------------------------
 // BF16 operands, FP32 accumulation: v_mfma_f32_16x16x32_bf16 (gfx950).  Same
-// 128 x 128 tile and wave arrangement; a K slice of 32 is one MFMA per 16 x 16
-// tile, lane group g = lane / 16 supplying K indices 8 g .. 8 g + 7.
+// 128 x 128 tile and 2 x 2 wave arrangement as above; K advances in slices of
+// 64 (two MFMA K steps per 16 x 16 tile, 32 MFMAs per wave between barriers).
+// Both operands sit in LDS as [row][64 K values] (row = output row or
+// column), in 16-byte chunks of 8 K values whose position within the row is
+// XOR-swizzled by the row index, so that the MFMA reads (16 rows, one chunk
+// each) and the transposing writes of a side-contiguous operand spread over
+// the banks without padding.  Lane group g = lane / 16 supplies K values
+// 8 g .. 8 g + 7 of each 32-wide step; A and B use the same mapping.
 // ---------------------------------------------------------------------------
 typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
-constexpr int BK16 = 32;
-constexpr int LDK16 = BK16 + 8;   // 80-byte rows, 16-byte aligned
+constexpr int BK16 = 64;
 
-template <bool KC>
-__device__ inline void fetch_slice16(const uint16_t* __restrict__ src, long ld, int side0, int sideN, int k0,
-                                     int K, int t, uint16_t (&r)[16]) {
-    if (KC) {
-        const int kk = t & 31;
-        const int k = k0 + kk;
+// u16 offset of chunk c (8 K values) of LDS row r
+__device__ inline int swz16(int r, int c) { return r * BK16 + ((c ^ (r & 7) ^ ((r >> 3) & 7)) << 3); }
+
+// Registers of one operand's K slice: four 16-byte words per thread.
+struct Slice16 {
+    uint4 v[4];
+};
+
+// K-contiguous source ([side][K]): thread t fetches chunks u = t + 256 e,
+// row u / 8, chunk u % 8 (eight threads read one row's 128 bytes).
+template <bool VEC>
+__device__ inline void fetch16_kc(const uint16_t* __restrict__ src, long ld, int side0, int sideN, int k0, int K,
+                                  int t, Slice16& r) {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int row = side0 + (t >> 5) + 8 * e;
-            r[e] = (row < sideN && k < K) ? src[(long)row * ld + k] : (uint16_t)0;
-        }
-    } else {
-        const int col = side0 + (t & 127);
-        const int kh = (t >> 7) * 16;
+    for (int e = 0; e < 4; ++e) {
+        const int u = t + 256 * e;
+        const int row = side0 + (u >> 3);
+        const int k = k0 + (u & 7) * 8;
+        if (VEC && row < sideN && k + 7 < K) {
+            r.v[e] = *reinterpret_cast<const uint4*>(src + (long)row * ld + k);
+        } else {
+            uint16_t h[8];
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int k = k0 + kh + e;
-            r[e] = (col < sideN && k < K) ? src[(long)k * ld + col] : (uint16_t)0;
+            for (int q = 0; q < 8; ++q) h[q] = (row < sideN && k + q < K) ? src[(long)row * ld + k + q] : (uint16_t)0;
+            r.v[e] = uint4{(uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16),
+                           (uint32_t)h[4] | ((uint32_t)h[5] << 16), (uint32_t)h[6] | ((uint32_t)h[7] << 16)};
         }
     }
 }
-
-template <bool KC>
-__device__ inline void store_slice16(uint16_t* __restrict__ lds, int t, const uint16_t (&r)[16]) {
-    if (KC) {
-        const int kk = t & 31;
+__device__ inline void store16_kc(uint16_t* __restrict__ lds, int t, const Slice16& r) {
 #pragma unroll
-        for (int e = 0; e < 16; ++e) lds[((t >> 5) + 8 * e) * LDK16 + kk] = r[e];
-    } else {
-        const int row = t & 127;
-        const int kh = (t >> 7) * 16;
-#pragma unroll
-        for (int e = 0; e < 16; ++e) lds[row * LDK16 + kh + e] = r[e];
+    for (int e = 0; e < 4; ++e) {
+        const int u = t + 256 * e;
+        *reinterpret_cast<uint4*>(&lds[swz16(u >> 3, u & 7)]) = r.v[e];
     }
 }
 
-// 16-byte loads (eight BF16 values) into the same registers and LDS layout
-// as fetch_slice16 / store_slice16; chunks across the matrix edge element by
-// element.
-__device__ inline void unpack8(const uint4 v, uint16_t* r) {
-    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+// Side-contiguous source ([K][side]): thread t fetches a 4 (K) x 8 (side)
+// block, K rows 4 (t / 16) .. +3 and side values 8 (t % 16) .. +7 (sixteen
+// threads read one K row's 256 bytes), and writes it transposed: eight LDS
+// rows of four K values (8 bytes each).
+template <bool VEC>
+__device__ inline void fetch16_sc(const uint16_t* __restrict__ src, long ld, int side0, int sideN, int k0, int K,
+                                  int t, Slice16& r) {
+    const int col = side0 + (t & 15) * 8;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        r[2 * q] = (uint16_t)(w[q] & 0xffffu);
-        r[2 * q + 1] = (uint16_t)(w[q] >> 16);
-    }
-}
-
-template <bool KC>
-__device__ inline void fetch_slice16_v(const uint16_t* __restrict__ src, long ld, int side0, int sideN, int k0, int K,
-                                       int t, uint16_t (&r)[16]) {
-    if (KC) {
-        const int row = side0 + (t >> 1);
+    for (int e = 0; e < 4; ++e) {
+        const int k = k0 + (t >> 4) * 4 + e;
+        if (VEC && k < K && col + 7 < sideN) {
+            r.v[e] = *reinterpret_cast<const uint4*>(src + (long)k * ld + col);
+        } else {
+            uint16_t h[8];
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const int k = k0 + ((t & 1) * 2 + c) * 8;
-            if (row < sideN && k + 7 < K) {
-                unpack8(*reinterpret_cast<const uint4*>(src + (long)row * ld + k), &r[8 * c]);
-            } else {
-#pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    r[8 * c + q] = (row < sideN && k + q < K) ? src[(long)row * ld + k + q] : (uint16_t)0;
-            }
-        }
-    } else {
-        const int col = side0 + (t & 15) * 8;
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            const int k = k0 + (t >> 4) + 16 * e;
-            if (k < K && col + 7 < sideN) {
-                unpack8(*reinterpret_cast<const uint4*>(src + (long)k * ld + col), &r[8 * e]);
-            } else {
-#pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    r[8 * e + q] = (k < K && col + q < sideN) ? src[(long)k * ld + col + q] : (uint16_t)0;
-            }
+            for (int q = 0; q < 8; ++q) h[q] = (k < K && col + q < sideN) ? src[(long)k * ld + col + q] : (uint16_t)0;
+            r.v[e] = uint4{(uint32_t)h[0] | ((uint32_t)h[1] << 16), (uint32_t)h[2] | ((uint32_t)h[3] << 16),
+                           (uint32_t)h[4] | ((uint32_t)h[5] << 16), (uint32_t)h[6] | ((uint32_t)h[7] << 16)};
         }
     }
 }
-
-template <bool KC>
-__device__ inline void store_slice16_v(uint16_t* __restrict__ lds, int t, const uint16_t (&r)[16]) {
-    if (KC) {
-        const int row = t >> 1;
+__device__ inline uint32_t word16(const uint4& v, int q) {
+    const uint32_t w = q < 2 ? (q == 0 ? v.x : v.y) : (q == 2 ? v.z : v.w);
+    return w;
+}
+__device__ inline void store16_sc(uint16_t* __restrict__ lds, int t, const Slice16& r) {
+    const int s0 = (t & 15) * 8;
+    const int kb = t >> 4;   // K values 4 kb .. 4 kb + 3: chunk kb / 2, half kb % 2
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const int kk = ((t & 1) * 2 + c) * 8;
-            uint4 v;
-            v.x = (uint32_t)r[8 * c] | ((uint32_t)r[8 * c + 1] << 16);
-            v.y = (uint32_t)r[8 * c + 2] | ((uint32_t)r[8 * c + 3] << 16);
-            v.z = (uint32_t)r[8 * c + 4] | ((uint32_t)r[8 * c + 5] << 16);
-            v.w = (uint32_t)r[8 * c + 6] | ((uint32_t)r[8 * c + 7] << 16);
-            *reinterpret_cast<uint4*>(&lds[row * LDK16 + kk]) = v;
-        }
-    } else {
-        const int col = (t & 15) * 8;
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            const int krow = (t >> 4) + 16 * e;
-#pragma unroll
-            for (int q = 0; q < 8; ++q) lds[(col + q) * LDK16 + krow] = r[8 * e + q];
-        }
+    for (int w = 0; w < 4; ++w) {
+        const uint32_t a0 = word16(r.v[0], w), a1 = word16(r.v[1], w);
+        const uint32_t a2 = word16(r.v[2], w), a3 = word16(r.v[3], w);
+        // side value 2 w (low halves) and 2 w + 1 (high halves)
+        const uint2 lo{(a0 & 0xffffu) | (a1 << 16), (a2 & 0xffffu) | (a3 << 16)};
+        const uint2 hi{(a0 >> 16) | (a1 & 0xffff0000u), (a2 >> 16) | (a3 & 0xffff0000u)};
+        *reinterpret_cast<uint2*>(&lds[swz16(s0 + 2 * w, kb >> 1) + (kb & 1) * 4]) = lo;
+        *reinterpret_cast<uint2*>(&lds[swz16(s0 + 2 * w + 1, kb >> 1) + (kb & 1) * 4]) = hi;
     }
 }
 
 template <bool KC, bool VEC>
 __device__ inline void fetch16(const uint16_t* __restrict__ src, long ld, int side0, int sideN, int k0, int K, int t,
-                               uint16_t (&r)[16]) {
-    if constexpr (VEC) fetch_slice16_v<KC>(src, ld, side0, sideN, k0, K, t, r);
-    else fetch_slice16<KC>(src, ld, side0, sideN, k0, K, t, r);
+                               Slice16& r) {
+    if constexpr (KC) fetch16_kc<VEC>(src, ld, side0, sideN, k0, K, t, r);
+    else fetch16_sc<VEC>(src, ld, side0, sideN, k0, K, t, r);
 }
-template <bool KC, bool VEC>
-__device__ inline void store16(uint16_t* __restrict__ lds, int t, const uint16_t (&r)[16]) {
-    if constexpr (VEC) store_slice16_v<KC>(lds, t, r);
-    else store_slice16<KC>(lds, t, r);
+template <bool KC>
+__device__ inline void store16(uint16_t* __restrict__ lds, int t, const Slice16& r) {
+    if constexpr (KC) store16_kc(lds, t, r);
+    else store16_sc(lds, t, r);
 }
 
 template <bool TA, bool TB, bool VEC>
 __global__ __launch_bounds__(NTHREADS) void gemm_bf16_kernel(Params p) {
-    __shared__ __attribute__((aligned(16))) uint16_t As[2][BM * LDK16];
-    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BN * LDK16];
+    __shared__ __attribute__((aligned(16))) uint16_t As[2][BM * BK16];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][BN * BK16];
     const int T_tiles = p.mt * p.nt;
     const int tile = xcd_band_tile(blockIdx.x, T_tiles);
     const int m0 = (tile / p.nt) * BM;
@@ -523,12 +501,12 @@ __global__ __launch_bounds__(NTHREADS) void gemm_bf16_kernel(Params p) {
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f4_t{0, 0, 0, 0};
-    uint16_t ra[16], rb[16];
+    Slice16 ra, rb;
     const int nk = (p.K + BK16 - 1) / BK16;
     fetch16<!TA, VEC>(A, p.lda, m0, p.M, 0, p.K, t, ra);
     fetch16<TB, VEC>(B, p.ldb, n0, p.N, 0, p.K, t, rb);
-    store16<!TA, VEC>(As[0], t, ra);
-    store16<TB, VEC>(Bs[0], t, rb);
+    store16<!TA>(As[0], t, ra);
+    store16<TB>(Bs[0], t, rb);
     __syncthreads();
     for (int kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
@@ -537,20 +515,24 @@ __global__ __launch_bounds__(NTHREADS) void gemm_bf16_kernel(Params p) {
             fetch16<!TA, VEC>(A, p.lda, m0, p.M, (kt + 1) * BK16, p.K, t, ra);
             fetch16<TB, VEC>(B, p.ldb, n0, p.N, (kt + 1) * BK16, p.K, t, rb);
         }
-        bf8_t a[4], b[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            a[i] = *reinterpret_cast<const bf8_t*>(&As[cur][(wm * 64 + i * 16 + l16) * LDK16 + 8 * kg]);
+        for (int h = 0; h < 2; ++h) {
+            bf8_t a[4], b[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-            b[j] = *reinterpret_cast<const bf8_t*>(&Bs[cur][(wn * 64 + j * 16 + l16) * LDK16 + 8 * kg]);
+            for (int i = 0; i < 4; ++i)
+                a[i] = *reinterpret_cast<const bf8_t*>(&As[cur][swz16(wm * 64 + i * 16 + l16, 4 * h + kg)]);
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j)
+                b[j] = *reinterpret_cast<const bf8_t*>(&Bs[cur][swz16(wn * 64 + j * 16 + l16, 4 * h + kg)]);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
         if (more) {
-            store16<!TA, VEC>(As[cur ^ 1], t, ra);
-            store16<TB, VEC>(Bs[cur ^ 1], t, rb);
+            store16<!TA>(As[cur ^ 1], t, ra);
+            store16<TB>(Bs[cur ^ 1], t, rb);
         }
         __syncthreads();
     }

@@ -59,14 +59,15 @@ def test_gemm_f64(env, tA, tB, shape):
 
 
 @pytest.mark.parametrize("prec", [1, 2])
-@pytest.mark.parametrize("tB", [0, 1])
-@pytest.mark.parametrize("shape", [(200, 136, 520), (37, 133, 517), (256, 128, 1024)])
-def test_gemm_low_precision(env, prec, tB, shape):
+@pytest.mark.parametrize("tA,tB", [(0, 0), (0, 1), (1, 0), (1, 1)])
+@pytest.mark.parametrize("shape", [(200, 136, 520), (37, 133, 517), (256, 128, 1024), (136, 200, 72)])
+def test_gemm_low_precision(env, prec, tA, tB, shape):
     # aligned rows take the 16-byte operand loads (ragged edges element by
-    # element), the 517-wide shape the element loads throughout
+    # element), the 517-wide shape the element loads throughout; K = 72 ends
+    # in a partial K slice
     torch, ctx = env
     M, N, K = shape
-    rng = np.random.default_rng(11 + prec + tB)
+    rng = np.random.default_rng(11 + prec + tB + 2 * tA)
     A = rng.standard_normal((M, K))
     B = rng.standard_normal((N, K) if tB else (K, N))
     # operands rounded to nearest even directly from FP64 (FP32: 24 bits,
@@ -80,8 +81,9 @@ def test_gemm_low_precision(env, prec, tB, shape):
     Ar, Br = rnd(A), rnd(B)
     want = Ar @ (Br.T if tB else Br)
     dD = torch.zeros((M, N), dtype=torch.float64, device="cuda")
-    ite.ite_debug_gemm(ctx, 0, tB, M, N, K, 1.0, dev(torch, A), K, dev(torch, B), B.shape[1], 0.0, None, N, dD, N,
-                       prec)
+    Ain = np.ascontiguousarray(A.T) if tA else A
+    ite.ite_debug_gemm(ctx, tA, tB, M, N, K, 1.0, dev(torch, Ain), Ain.shape[1], dev(torch, B), B.shape[1], 0.0, None,
+                       N, dD, N, prec)
     # FP32 accumulation of exactly rounded operands
     assert rel_err(host(dD), want) < 2e-5
     exact = A @ (B.T if tB else B)
@@ -386,6 +388,13 @@ def test_heff_apply_low_precision(env, prec, bound, dims):
     err = rel_err(host(y), want)
     assert err < bound
     assert err > 0.0    # the products really ran in the lower precision
+    # the timing entry runs the same product (environments rounded once):
+    # the same bits
+    y2 = torch.zeros_like(y)
+    ms = ite.ite_debug_heff_time(ctx, dev(torch, Lm), W[1], W[2], dev(torch, Rm), dev(torch, th), 0.0, 1.0, y2,
+                                 prec=prec, reps=2)
+    assert ms > 0.0
+    assert torch.equal(y2, y)
     if Dxl == Dyl and Dxr == Dyr:
         ite.ite_debug_heff_apply(ctx, dev(torch, Lm), W[1], W[2], dev(torch, Rm), dev(torch, th), 0.3, -0.25, y,
                                  prec=prec)
