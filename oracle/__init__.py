@@ -28,6 +28,9 @@ Logarithmic Grids" (Zima, Stoudenmire, White, Parcollet, Kaye) by eye:
   split, the local problem diagonalised exactly (the ground state that seeds
   the METTS chains and gives the zero-temperature double occupancy,
   Appendix D).
+* ``oracle.gauss`` -- the spectral variant (Method): Gauss-Legendre
+  collocation on a panel, densely and as one augmented MPS linear system
+  (an extra node site) solved by the same two-site sweep.
 * ``oracle.metts`` -- one-site expectation values and METTS chains
   (evolution, measurement, collapse; Appendix D), with their exact dense
   counterparts used to pin them.

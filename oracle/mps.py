@@ -66,11 +66,15 @@ import numpy as np
 # States
 # ----------------------------------------------------------------------------
 
-def full_dims(L: int, d: int, chi_max: int) -> list[int]:
+def full_dims(L: int, d, chi_max: int) -> list[int]:
+    """Bond dimensions min(prod of d left of the bond, prod right of it,
+    chi_max); d is one dimension for every site or a list of L."""
+    ds = [int(d)] * L if np.ndim(d) == 0 else [int(x) for x in d]
     out = []
     for i in range(L + 1):
-        e = min(i, L - i)
-        out.append(int(chi_max if e >= 62 else min(chi_max, d ** e)))
+        left = math.prod(ds[:i]) if i < 62 else chi_max
+        right = math.prod(ds[i:]) if L - i < 62 else chi_max
+        out.append(int(min(chi_max, left, right)))
     return out
 
 
@@ -86,12 +90,12 @@ def product_state(spinors, chi_max: int | None = None, pad_full: bool = False) -
     from the left, so the state is unchanged.
     """
     L = len(spinors)
-    d = len(spinors[0])
     if not pad_full:
-        return [np.asarray(s, dtype=float).reshape(1, d, 1).copy() for s in spinors]
-    dims = full_dims(L, d, chi_max)
+        return [np.asarray(s, dtype=float).reshape(1, len(s), 1).copy() for s in spinors]
+    dims = full_dims(L, [len(s) for s in spinors], chi_max)
     out = []
     for i, sp in enumerate(spinors):
+        d = len(sp)
         dl, dr = dims[i], dims[i + 1]
         u = np.zeros(d * dr)
         u[np.arange(d) * dr] = sp
