@@ -38,7 +38,13 @@ Readings (the paper leaves the details to a later publication):
     with truncation the two right-end formulas differ at the truncation
     level.)
   * the MPO of (H - s) is the direct sum of H's MPO and -s times the identity
-    (bond dimension w + 1), which needs no knowledge of H's MPO layout.
+    (bond dimension w + 1), which needs no knowledge of H's MPO layout;
+  * after the contraction the bonds near the left end can be larger than
+    the chain can need (the augmented left space is p + 1 times larger):
+    every bond up to the last one above min(prod d left, prod d right,
+    chi_max) is cut back by exact two-site splits (cutoff 0, left to right,
+    then right to left back to site 1), so that the next panel starts from a
+    right-orthonormal state with the centre on site 1 and minimal bonds.
 """
 from __future__ import annotations
 
@@ -161,6 +167,27 @@ def contract_node(aug, v):
     return [A1] + [a.copy() for a in aug[2:]]
 
 
+def recompress(A, chi_max: int, tie_rel: float):
+    """Cut bonds above min(prod d left, prod d right, chi_max) back by exact
+    splits: left to right over the bonds up to the last such bond, then
+    right to left back to site 1."""
+    L = len(A)
+    caps = omps.full_dims(L, [a.shape[1] for a in A], chi_max)
+    dims = omps.bond_dims(A)
+    over = [b for b in range(1, L) if dims[b] > caps[b]]
+    A = [a.copy() for a in A]
+    if not over:
+        return A
+    last = max(over)
+    for i in range(last):                       # blocks (i, i + 1): bond i + 1
+        A[i], A[i + 1], _ = omps.split_two_site(omps.two_site(A[i], A[i + 1]), "lr", 0.0,
+                                                min(chi_max, caps[i + 1]), tie_rel)
+    for i in range(last - 1, -1, -1):
+        A[i], A[i + 1], _ = omps.split_two_site(omps.two_site(A[i], A[i + 1]), "rl", 0.0,
+                                                min(chi_max, caps[i + 1]), tie_rel)
+    return A
+
+
 def gl_step(psi, W, dtau: float, p: int, opts):
     """One panel of p-point Gauss-Legendre collocation on an MPS; opts as for
     ``mps.imag_step`` (its scheme is ignored: the augmented system is solved
@@ -171,7 +198,7 @@ def gl_step(psi, W, dtau: float, p: int, opts):
     xa, rep = omps.imag_step(augmented_state(psi, p), Wa, dtau, replace(opts, scheme="be", shift_mode="fixed",
                                                                           shift=0.0))
     r_inf, w = end_weights(p)
-    out = contract_node(xa, np.concatenate([[r_inf], w]))
+    out = recompress(contract_node(xa, np.concatenate([[r_inf], w])), opts.chi_max, opts.tie_rel)
     nrm = float(np.linalg.norm(out[0]))
     out[0] = out[0] / nrm
     rep.norm_before = nrm

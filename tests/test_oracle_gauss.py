@@ -140,3 +140,25 @@ def test_mps_panel_equals_dense_panel_at_complete_bonds(p, shift_mode):
     assert 1.0 - abs(v @ st[-1]) < 1e-10
     for a in out[1:]:
         assert mps.right_orthonormality_error(a) < 1e-12
+    # the augmented sweep widened the left bonds; the panel's state is cut
+    # back to the chain's own bond dimensions
+    assert max(r.extra["aug_max_chi"] for r in reps) > 0
+    assert mps.bond_dims(out) == mps.full_dims(L, 2, 64)
+
+
+def test_recompress_is_exact_and_minimal():
+    # an MPS whose left bonds are padded with redundant directions
+    rng = np.random.default_rng(12)
+    L = 6
+    A = [rng.standard_normal((1, 2, 6))] + [rng.standard_normal((6, 2, 6)) for _ in range(2)] + \
+        [rng.standard_normal((6, 2, 4)), rng.standard_normal((4, 2, 2)), rng.standard_normal((2, 2, 1))]
+    v = mps.to_vector(A)
+    B = gauss.recompress(A, 64, 1e-13)
+    assert np.abs(mps.to_vector(B) - v).max() < 1e-12 * np.abs(v).max()
+    assert mps.bond_dims(B) == [1, 2, 4, 6, 4, 2, 1]
+    # the sites the two passes went over are right-orthonormal again, the
+    # others untouched
+    for a in B[1:3]:
+        assert mps.right_orthonormality_error(a) < 1e-12
+    for a, b in zip(A[3:], B[3:]):
+        assert np.array_equal(a, b)
