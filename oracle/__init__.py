@@ -28,6 +28,8 @@ Logarithmic Grids" (Zima, Stoudenmire, White, Parcollet, Kaye) by eye:
   split, the local problem diagonalised exactly (the ground state that seeds
   the METTS chains and gives the zero-temperature double occupancy,
   Appendix D).
+* ``oracle.apply`` -- the right-hand side as an MPS (Appendix B): the
+  density-matrix MPO-MPS product and the trapezoid step that starts from it.
 * ``oracle.gauss`` -- the spectral variant (Method): Gauss-Legendre
   collocation on a panel, densely and as one augmented MPS linear system
   (an extra node site) solved by the same two-site sweep.
