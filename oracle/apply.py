@@ -22,7 +22,9 @@ The result is right-orthonormal from site 2 on with the norm of phi in site
 
 Readings: the eigen-decomposition keeps eigenvectors by the same discarded
 weight rule as the splits (the eigenvalues are the squared singular values of
-phi at that bond, so they are the weights); the operator of the trapezoid
+phi at that bond, so they are the weights), at most min(prod d left, prod d
+right, chi_max) of them, the largest rank the bond can have (as for every MPS
+here); the operator of the trapezoid
 right-hand side, (1 + h s) I - h H, is the direct sum of H's MPO scaled by
 -h and the identity scaled by (1 + h s) (bond dimension w + 1).
 
@@ -93,6 +95,7 @@ def density_matrix_apply(O, psi, chi_max: int, cutoff: float, tie_rel: float):
         X = np.tensordot(X, O[j], axes=([1, 4], [0, 2]))                # [c', a, w, w', t']
         X = np.tensordot(X, psi[j], axes=([0, 4], [0, 1]))              # [a, w, w', a']
         F[j + 1] = np.ascontiguousarray(np.transpose(X, (3, 2, 0, 1)))  # [a', w', a, w]
+    caps = omps.full_dims(L, [a.shape[1] for a in psi], chi_max)
     b = [None] * L
     info = {"disc": 0.0, "k": [], "lam": []}
     C = np.ones((1, 1, 1))                                              # [a, w, k] at the right boundary
@@ -108,7 +111,7 @@ def density_matrix_apply(O, psi, chi_max: int, cutoff: float, tie_rel: float):
         Tm = T.reshape(Da * w, d * k)
         Fm = F[j].reshape(Da * w, Da * w)                               # [(a' w'), (a w)]
         rho = Tm.T @ Fm @ Tm                                            # [(s' k'), (s k)]
-        V, lam, kk = _eig_keep(rho, cutoff, chi_max, tie_rel)
+        V, lam, kk = _eig_keep(rho, cutoff, min(chi_max, caps[j]), tie_rel)
         total = float(lam.sum())
         info["disc"] = max(info["disc"], float(lam[kk:].sum()) / total if total > 0 else 0.0)
         info["k"].append(kk)
