@@ -52,10 +52,11 @@ extern "C" {
 #define ITE_ENONFINITE (-5)   /* the step produced a non-finite state; psi was left unchanged */
 
 /* ---- enumerations ------------------------------------------------------ */
-enum { ITE_SCHEME_TRAP = 0, ITE_SCHEME_BE = 1 };
+enum { ITE_SCHEME_TRAP = 0, ITE_SCHEME_BE = 1, ITE_SCHEME_GL = 2 };
 enum { ITE_SHIFT_FIXED = 0, ITE_SHIFT_TRACK = 1 };
 enum { ITE_PREC_FP64 = 0, ITE_PREC_FP32_IR = 1, ITE_PREC_BF16_IR = 2 };
 enum { ITE_GUESS_PSI = 0, ITE_GUESS_B = 1 };
+enum { ITE_RHS_PROJECT = 0, ITE_RHS_MPS = 1 };
 
 /* report flags */
 #define ITE_FLAG_BUDGET_EXHAUSTED 1  /* a local solve ended on its Krylov budget above tol_loc (normal in budget mode) */
@@ -108,6 +109,12 @@ typedef struct ite_step_opts {
                           * into x's basis (Appendix B uses the right-hand side as the initial
                           * guess), later ones from the current x_j x_(j+1); ITE_GUESS_PSI:
                           * x_j x_(j+1) throughout.  Identical for backward Euler (b = psi). */
+    int    gl_nodes;     /* ITE_SCHEME_GL: Gauss-Legendre nodes p per panel, 1..7 (default 2) */
+    int    rhs_mode;     /* trapezoid right-hand side: ITE_RHS_PROJECT (default) projects
+                          * (I - h (H - s)) psi into x's basis exactly through mixed environments;
+                          * ITE_RHS_MPS first forms it as an MPS b by the density-matrix MPO-MPS
+                          * product (Appendix B; truncated by chi_max / cutoff / tie_rel like a
+                          * split) and solves with b in place of psi, x starting as b */
 } ite_step_opts;
 
 /* Per-step report. */
@@ -127,6 +134,9 @@ typedef struct ite_step_report {
     long long matvecs_fp64;  /* effective-Hamiltonian products in FP64 */
     long long matvecs_lo;    /* ... in FP32 or BF16 */
     double ms_total, ms_rhs, ms_solve, ms_split, ms_env;   /* device time per phase */
+    double rhs_disc;     /* ITE_RHS_MPS: largest discarded-weight fraction of the density-matrix product */
+    int    aux_max_chi;  /* ITE_SCHEME_GL: largest bond of the augmented (node-site) state before it
+                          * is cut back to the chain's bonds */
 } ite_step_report;
 
 /* ---- context ----------------------------------------------------------- */
@@ -223,6 +233,25 @@ int ite_mps_set_tau(ite_mps* psi, double tau);
  * by one or more two-site sweeps of GMRES local solves with SVD truncation,
  * normalise, and replace psi by x.  s is opts->shift (FIXED) or <psi|H|psi>
  * (TRACK).  tau advances by h (BE) or 2h (TRAP).  rep may be NULL.
+ * With opts->rhs_mode = ITE_RHS_MPS the trapezoid right-hand side is first
+ * formed as an MPS by the density-matrix product (ite_mpo_apply of the MPO
+ * of (1 + h s) I - h H, truncated by chi_max, cutoff, tie_rel; Appendix B),
+ * and the solve runs as the backward-Euler form with that MPS in place of
+ * psi (x starts as b; rep->rhs_disc reports the product's truncation).
+ * ITE_SCHEME_GL (Method: the spectral variant) advances psi over one panel
+ * of length h by p = opts->gl_nodes point Gauss-Legendre collocation: the
+ * node values Y_1..Y_p of the polynomial solution satisfy the integral form
+ * of the evolution equation (Eq. 2 from the panel's start) at the nodes,
+ * (I + h A (x) (H - s)) Y = 1 (x) psi with A_ij the integral of the j-th
+ * Lagrange polynomial from 0 to node c_i.  The p node values are one MPS on
+ * L + 1 sites whose first site (dimension p + 1, entry 0 = psi itself)
+ * indexes the node, so the system is one backward-Euler-type solve of the
+ * augmented MPO (the node matrix [[0, 0], [0, A]] times the MPO of H - s)
+ * by the same sweep; the panel's end value r_inf psi + sum_j w_j Y_j (the
+ * (p, p) Pade approximant of exp(-h (H - s)) applied to psi; w = A^-T b for
+ * the Gauss weights b, r_inf = 1 - b^T A^-1 1) is the node site contracted
+ * into site 1, with the bonds cut back to the chain's own by exact two-site
+ * splits; then normalised.  tau advances by h.
  * Errors: EINVAL (h <= 0 or non-finite, bad options), ESTATE (L or d of psi
  * and H differ), ENOMEM, EDEVICE, ENONFINITE (psi left unchanged). */
 int ite_imag_step(ite_mps* psi, const ite_mpo* H, double h,
@@ -358,6 +387,26 @@ int ite_evolve_grid(ite_mps* psi, const ite_mpo* H, const double* taus, int n_ta
                     const ite_step_opts* opts, ite_step_report* per_step, int max_steps,
                     int* n_steps);
 
+/* phi = O psi by the "density matrix" algorithm for MPO-MPS products
+ * (Appendix B applies the trapezoid right-hand side this way): left
+ * environments F_j of <O psi|O psi> without truncation, then from the right
+ * end, at each site, the tensor T_j of O_j psi_j contracted with what is
+ * already kept to its right, its reduced density matrix rho_j = T^T F_j T
+ * (over the site index and the kept right index), and the eigenvectors of
+ * rho_j's largest eigenvalues (one-sided Jacobi, FP64) as the new
+ * right-orthonormal site tensor; the kept count follows the split's rule
+ * (cutoff, tie_rel) on the square roots of the eigenvalues, at most
+ * min(chi_max, the bond's largest possible rank); site 1 keeps the rest
+ * whole, so it holds the norm of phi.  O must have psi's L and local
+ * dimensions and at most 128 MPO-index x local-dimension inputs per site.
+ * *out receives a new MPS (same L, d and chi_max as psi, tau 0; destroy with
+ * ite_mps_destroy); *max_disc (nullable) the largest discarded-weight
+ * fraction.  psi is unchanged.  Errors: EINVAL (NULL pointers, chi_max < 1,
+ * cutoff outside [0, 1), tie_rel < 0), ESTATE (shapes or contexts differ),
+ * ENOMEM, EDEVICE, ENONFINITE (phi is zero or not finite; *out not set). */
+int ite_mpo_apply(const ite_mpo* O, ite_mps* psi, int chi_max, double cutoff, double tie_rel,
+                  ite_mps** out, double* max_disc);
+
 /* Energy <psi|H|psi> / <psi|psi> (the quantity the trapezoid step's shift
  * tracks, Appendix D: the spectrum is shifted by the energy of the new state
  * each step; Method: the shift that puts the ground state energy at 0), by a
@@ -380,6 +429,13 @@ int ite_mps_norm(ite_mps* psi, double* out);
  * out and their number to *n.  EINVAL for bad parameters or cap too small
  * (then *n holds the required count). */
 int ite_loggrid(double tau0, double tau1, double ratio, double* out, int cap, int* n);
+/* Coefficients of a p-node Gauss-Legendre collocation panel (Method: the
+ * spectral variant; the panel step of ITE_SCHEME_GL uses exactly these):
+ * nodes c[p] (ascending) and weights b[p] on [0, 1], A[p*p] (row-major,
+ * A_ij = integral from 0 to c_i of the Lagrange polynomial of node j), the
+ * end weights w[p] = A^-T b and *r_inf = 1 - b^T A^-1 1.  Host only.
+ * EINVAL for p outside 1..7 or NULL pointers. */
+int ite_gl_coefficients(int p, double* c, double* b, double* A, double* w, double* r_inf);
 /* Panel grid (Method): P panels with endpoints {0, tau_max / 2^(P-j)},
  * j = 1..P, and n uniform steps per panel: P*n + 1 points. */
 int ite_panel_grid(double tau_max, int P, int n, double* out, int cap, int* npts);

@@ -18,10 +18,11 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libite.so")
 
 ITE_OK, ITE_EINVAL, ITE_ENOMEM, ITE_EDEVICE, ITE_ESTATE, ITE_ENONFINITE = 0, -1, -2, -3, -4, -5
-SCHEME_TRAP, SCHEME_BE = 0, 1
+SCHEME_TRAP, SCHEME_BE, SCHEME_GL = 0, 1, 2
 SHIFT_FIXED, SHIFT_TRACK = 0, 1
 PREC_FP64, PREC_FP32_IR, PREC_BF16_IR = 0, 1, 2
 GUESS_PSI, GUESS_B = 0, 1
+RHS_PROJECT, RHS_MPS = 0, 1
 FLAG_BUDGET_EXHAUSTED, FLAG_BREAKDOWN, FLAG_REFINE_LIMIT = 1, 2, 4
 
 
@@ -42,7 +43,8 @@ class ite_step_opts(C.Structure):
                 ("chi_max", C.c_int), ("cutoff", C.c_double), ("tie_rel", C.c_double),
                 ("krylov_dim", C.c_int), ("max_cycles", C.c_int), ("tol_loc", C.c_double),
                 ("nsweeps", C.c_int), ("precision", C.c_int), ("max_refine", C.c_int),
-                ("tol_refine", C.c_double), ("init_guess", C.c_int)]
+                ("tol_refine", C.c_double), ("init_guess", C.c_int), ("gl_nodes", C.c_int),
+                ("rhs_mode", C.c_int)]
 
 
 class ite_step_report(C.Structure):
@@ -52,7 +54,8 @@ class ite_step_report(C.Structure):
                 ("max_res_rel", C.c_double), ("mean_res_rel", C.c_double),
                 ("matvecs_fp64", C.c_longlong), ("matvecs_lo", C.c_longlong),
                 ("ms_total", C.c_double), ("ms_rhs", C.c_double), ("ms_solve", C.c_double),
-                ("ms_split", C.c_double), ("ms_env", C.c_double)]
+                ("ms_split", C.c_double), ("ms_env", C.c_double), ("rhs_disc", C.c_double),
+                ("aux_max_chi", C.c_int)]
 
     def as_dict(self) -> dict:
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -112,6 +115,7 @@ _SIGNATURES = {
     "ite_evolve_grid": (_I, [_P, _P, _PD, _I, C.POINTER(ite_step_opts),
                              C.POINTER(ite_step_report), _I, _PI]),
     "ite_measure_energy": (_I, [_P, _P, _PD]),
+    "ite_mpo_apply": (_I, [_P, _P, _I, _D, _D, C.POINTER(_P), _PD]),
     "ite_mps_sample": (_I, [_P, _I, _I, _PD, _PI]),
     "ite_mps_sample_noalloc": (_I, [_P, _I, _I, _P, _P]),
     "ite_mps_expect_site": (_I, [_P, _I, _PD, _PD]),
@@ -126,6 +130,7 @@ _SIGNATURES = {
     "ite_mps_norm": (_I, [_P, _PD]),
     "ite_loggrid": (_I, [_D, _D, _D, _PD, _I, _PI]),
     "ite_panel_grid": (_I, [_D, _I, _I, _PD, _I, _PI]),
+    "ite_gl_coefficients": (_I, [_I, _PD, _PD, _PD, _PD, _PD]),
     "ite_debug_gemm": (_I, [_P, _I, _I, _I, _I, _I, _D, _P, _I, _P, _I, _D, _P, _I, _P, _I, _I]),
     "ite_debug_heff_apply": (_I, [_P, _I, _I, _I, _I, _I, _I, _I, _I, _I, _P, _PD, _PD, _P, _P,
                                   _D, _D, _P, _I]),
@@ -477,6 +482,17 @@ def ite_mps_sample_noalloc(ctx: Ctx, psi: int, uniforms, configs) -> None:
     _check(load_library().ite_mps_sample_noalloc(psi, S, L, _tp(uniforms), _tp(configs)), ctx.handle)
 
 
+def ite_mpo_apply(ctx: Ctx, mpo: int, psi: int, chi_max: int, cutoff: float = 0.0,
+                  tie_rel: float = 1e-13) -> tuple[int, float]:
+    """O psi by the density-matrix product; returns (new MPS handle, largest
+    discarded-weight fraction)."""
+    out = _P()
+    disc = C.c_double()
+    _check(load_library().ite_mpo_apply(mpo, psi, int(chi_max), float(cutoff), float(tie_rel), C.byref(out),
+                                        C.byref(disc)), ctx.handle)
+    return out.value, disc.value
+
+
 def ite_measure_energy(ctx: Ctx, psi: int, mpo: int) -> float:
     e = C.c_double()
     _check(load_library().ite_measure_energy(psi, mpo, C.byref(e)), ctx.handle)
@@ -504,6 +520,16 @@ def ite_loggrid(tau0: float, tau1: float, ratio: float) -> np.ndarray:
     out = np.empty(n.value)
     _check(lib.ite_loggrid(float(tau0), float(tau1), float(ratio), _dptr(out), n.value, C.byref(n)))
     return out
+
+
+def ite_gl_coefficients(p: int) -> dict:
+    """Nodes c, weights b, collocation matrix A, end weights w and r_inf of a
+    p-node Gauss-Legendre panel, as the library's panel step uses them."""
+    c, b, w = (np.zeros(p) for _ in range(3))
+    A = np.zeros((p, p))
+    r = C.c_double()
+    _check(load_library().ite_gl_coefficients(int(p), _dptr(c), _dptr(b), _dptr(A), _dptr(w), C.byref(r)))
+    return {"c": c, "b": b, "A": A, "w": w, "r_inf": r.value}
 
 
 def ite_panel_grid(tau_max: float, P: int, n: int) -> np.ndarray:

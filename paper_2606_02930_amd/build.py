@@ -32,7 +32,7 @@ FLAGS = [
     f"-I{CSRC}",
 ]
 
-SOURCES = ["gemm.hip", "vec.hip", "svd.hip", "qr.hip", "engine.cpp", "capi.cpp", "server.cpp", "noalloc.hip", "batch.cpp"]
+SOURCES = ["gemm.hip", "vec.hip", "svd.hip", "qr.hip", "engine.cpp", "capi.cpp", "server.cpp", "noalloc.hip", "batch.cpp", "panel.cpp"]
 
 
 def _compile(src: str, build_dir: str) -> str:

@@ -2,6 +2,7 @@
 // exception crosses the boundary), and the parity-test building blocks.
 #include "engine.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -117,6 +118,8 @@ void ite_default_opts(ite_step_opts* o) {
     o->max_refine = 0;   // per precision: 1 correction for FP32-IR, 2 for BF16-IR
     o->tol_refine = 0.0;
     o->init_guess = ITE_GUESS_B;
+    o->gl_nodes = 2;
+    o->rhs_mode = ITE_RHS_PROJECT;
 }
 
 int ite_ctx_create(int device, void* hip_stream, const ite_allocator* alloc, ite_ctx** out) {
@@ -333,6 +336,36 @@ int ite_imag_step(ite_mps* psi, const ite_mpo* H, double h, const ite_step_opts*
     return guarded(psi->ctx, [&] {
         set_device(psi->ctx);
         imag_step(psi, H, h, *o, rep);
+    });
+}
+
+int ite_gl_coefficients(int p, double* c, double* b, double* A, double* w, double* r_inf) {
+    if (p < 1 || p > 7 || !c || !b || !A || !w || !r_inf) return ITE_EINVAL;
+    try {
+        const GlCoef g = gl_coefficients(p);
+        std::copy(g.c.begin(), g.c.end(), c);
+        std::copy(g.b.begin(), g.b.end(), b);
+        std::copy(g.A.begin(), g.A.end(), A);
+        std::copy(g.w.begin(), g.w.end(), w);
+        *r_inf = g.r_inf;
+    } catch (...) {
+        return ITE_EINVAL;
+    }
+    return ITE_OK;
+}
+
+int ite_mpo_apply(const ite_mpo* O, ite_mps* psi, int chi_max, double cutoff, double tie_rel, ite_mps** out,
+                  double* max_disc) {
+    if (!O || !psi || !out) return ITE_EINVAL;
+    *out = nullptr;
+    if (psi->ctx != O->ctx) return ITE_ESTATE;
+    return guarded(psi->ctx, [&] {
+        set_device(psi->ctx);
+        std::unique_ptr<ite_mps, void (*)(ite_mps*)> r(mps_new(psi->ctx, psi->L, psi->d.data(), psi->chi_max),
+                                                      mps_destroy);
+        const double disc = mpo_apply_dm(psi, O, chi_max, cutoff, tie_rel, r.get());
+        if (max_disc) *max_disc = disc;
+        *out = r.release();
     });
 }
 

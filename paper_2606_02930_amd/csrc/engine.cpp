@@ -84,13 +84,13 @@ double* pinned(ite_ctx* c, size_t doubles) {
 
 void sync(ite_ctx* c) { HIP_CHECK(hipStreamSynchronize(c->stream)); }
 
-static void d2h(ite_ctx* c, double* host, const double* dev, size_t n) {
+void d2h(ite_ctx* c, double* host, const double* dev, size_t n) {
     HIP_CHECK(hipMemcpyAsync(host, dev, n * sizeof(double), hipMemcpyDeviceToHost, c->stream));
 }
-static void h2d(ite_ctx* c, void* dev, const void* host, size_t bytes) {
+void h2d(ite_ctx* c, void* dev, const void* host, size_t bytes) {
     HIP_CHECK(hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, c->stream));
 }
-static void d2d(ite_ctx* c, double* dst, const double* src, size_t n) {
+void d2d(ite_ctx* c, double* dst, const double* src, size_t n) {
     if (n) HIP_CHECK(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
 }
 
@@ -147,8 +147,8 @@ struct CtxProbe final : LaunchProbe {
 
 }  // namespace
 
-static void gemm(ite_ctx* c, bool tA, bool tB, int M, int N, int K, double alpha, const double* A, long lda,
-                 const double* B, long ldb, double beta, const double* C, long ldc, double* D, long ldd) {
+void gemm(ite_ctx* c, bool tA, bool tB, int M, int N, int K, double alpha, const double* A, long lda,
+          const double* B, long ldb, double beta, const double* C, long ldc, double* D, long ldd) {
     Gemm g;
     g.M = M; g.N = N; g.K = K; g.tA = tA; g.tB = tB;
     g.alpha = alpha; g.beta = beta;
@@ -165,7 +165,7 @@ static void gemm(ite_ctx* c, bool tA, bool tB, int M, int N, int K, double alpha
     gemm_f64(g, c->stream);
 }
 
-static void stage(ite_ctx* c, const CsrDev& m, Stage st) {
+void stage(ite_ctx* c, const CsrDev& m, Stage st) {
     st.I = m.I;
     st.O = m.O;
     st.rowptr = m.rowptr;
@@ -692,13 +692,6 @@ SolveStats local_solve(ite_ctx* c, const LocalOp& op, const double* b, double* x
 // MPO handle
 // ---------------------------------------------------------------------------
 
-namespace {
-struct CsrHost {
-    int I = 0, O = 0;
-    std::vector<int> rowptr, col;
-    std::vector<double> val;
-};
-
 CsrHost dense_to_csr(const std::vector<double>& M, int O, int I) {
     CsrHost h;
     h.I = I;
@@ -716,7 +709,44 @@ CsrHost dense_to_csr(const std::vector<double>& M, int O, int I) {
     }
     return h;
 }
-}  // namespace
+
+std::vector<CsrDev> upload_csr(ite_ctx* c, const std::vector<CsrHost>& hs, void** block) {
+    size_t bytes = 0;
+    for (const auto& h : hs) {
+        bytes += ((h.rowptr.size() * sizeof(int) + 255) & ~size_t(255));
+        bytes += ((h.col.size() * sizeof(int) + 255) & ~size_t(255)) + 256;
+        bytes += ((h.val.size() * sizeof(double) + 255) & ~size_t(255)) + 256;
+    }
+    *block = dev_alloc(c, bytes);
+    std::vector<char> staging(bytes, 0);
+    std::vector<CsrDev> out;
+    size_t pos = 0;
+    char* base = static_cast<char*>(*block);
+    for (const auto& h : hs) {
+        CsrDev dv;
+        dv.I = h.I;
+        dv.O = h.O;
+        dv.nnz = (int)h.val.size();
+        dv.rowptr = reinterpret_cast<int*>(base + pos);
+        std::memcpy(staging.data() + pos, h.rowptr.data(), h.rowptr.size() * sizeof(int));
+        pos += ((h.rowptr.size() * sizeof(int) + 255) & ~size_t(255));
+        dv.col = reinterpret_cast<int*>(base + pos);
+        if (!h.col.empty()) std::memcpy(staging.data() + pos, h.col.data(), h.col.size() * sizeof(int));
+        pos += ((h.col.size() * sizeof(int) + 255) & ~size_t(255)) + 256;
+        dv.val = reinterpret_cast<double*>(base + pos);
+        if (!h.val.empty()) std::memcpy(staging.data() + pos, h.val.data(), h.val.size() * sizeof(double));
+        pos += ((h.val.size() * sizeof(double) + 255) & ~size_t(255)) + 256;
+        out.push_back(dv);
+    }
+    try {
+        HIP_CHECK(hipMemcpy(*block, staging.data(), bytes, hipMemcpyHostToDevice));
+    } catch (...) {
+        dev_free(c, *block);
+        *block = nullptr;
+        throw;
+    }
+    return out;
+}
 
 ite_mpo* mpo_load(ite_ctx* c, int L, const int* d, const int* w, const double* const* W) {
     ITE_REQUIRE(L >= 2, "mpo_load: L must be >= 2");
@@ -779,41 +809,14 @@ ite_mpo* mpo_load(ite_ctx* c, int L, const int* d, const int* w, const double* c
         hi.push_back(dense_to_csr(Id, dd, dd));
     }
     // one device block for all CSR arrays
-    size_t bytes = 0;
-    auto need = [&](const CsrHost& h) {
-        bytes += ((h.rowptr.size() * sizeof(int) + 255) & ~size_t(255));
-        bytes += ((h.col.size() * sizeof(int) + 255) & ~size_t(255)) + 256;
-        bytes += ((h.val.size() * sizeof(double) + 255) & ~size_t(255)) + 256;
-    };
-    for (auto& h : hp) need(h);
-    for (auto& h : hl) need(h);
-    for (auto& h : hr) need(h);
-    for (auto& h : hi) need(h);
-    m->block = dev_alloc(c, bytes);
-    std::vector<char> staging(bytes, 0);
-    size_t pos = 0;
-    auto place = [&](const CsrHost& h) {
-        CsrDev dv;
-        dv.I = h.I;
-        dv.O = h.O;
-        dv.nnz = (int)h.val.size();
-        char* base = static_cast<char*>(m->block);
-        dv.rowptr = reinterpret_cast<int*>(base + pos);
-        std::memcpy(staging.data() + pos, h.rowptr.data(), h.rowptr.size() * sizeof(int));
-        pos += ((h.rowptr.size() * sizeof(int) + 255) & ~size_t(255));
-        dv.col = reinterpret_cast<int*>(base + pos);
-        if (!h.col.empty()) std::memcpy(staging.data() + pos, h.col.data(), h.col.size() * sizeof(int));
-        pos += ((h.col.size() * sizeof(int) + 255) & ~size_t(255)) + 256;
-        dv.val = reinterpret_cast<double*>(base + pos);
-        if (!h.val.empty()) std::memcpy(staging.data() + pos, h.val.data(), h.val.size() * sizeof(double));
-        pos += ((h.val.size() * sizeof(double) + 255) & ~size_t(255)) + 256;
-        return dv;
-    };
-    for (auto& h : hp) m->pair.push_back(place(h));
-    for (auto& h : hl) m->left.push_back(place(h));
-    for (auto& h : hr) m->right.push_back(place(h));
-    for (auto& h : hi) m->ident.push_back(place(h));
-    HIP_CHECK(hipMemcpy(m->block, staging.data(), bytes, hipMemcpyHostToDevice));
+    std::vector<CsrHost> all;
+    for (auto* v : {&hp, &hl, &hr, &hi}) all.insert(all.end(), v->begin(), v->end());
+    std::vector<CsrDev> dv = upload_csr(c, all, &m->block);
+    size_t k = 0;
+    for (size_t i = 0; i < hp.size(); ++i) m->pair.push_back(dv[k++]);
+    for (size_t i = 0; i < hl.size(); ++i) m->left.push_back(dv[k++]);
+    for (size_t i = 0; i < hr.size(); ++i) m->right.push_back(dv[k++]);
+    for (size_t i = 0; i < hi.size(); ++i) m->ident.push_back(dv[k++]);
     return m.release();
 }
 
@@ -827,7 +830,7 @@ void mpo_destroy(ite_mpo* m) {
 // MPS handle
 // ---------------------------------------------------------------------------
 
-static std::vector<int> bond_caps(int L, const std::vector<int>& d, int chi_max) {
+std::vector<int> bond_caps(int L, const std::vector<int>& d, int chi_max) {
     std::vector<int> cap(L + 1);
     for (int b = 0; b <= L; ++b) {
         double left = 1.0, right = 1.0;
@@ -877,6 +880,7 @@ static void free_evolution(ite_mps* p) {
 void mps_destroy(ite_mps* p) {
     if (!p) return;
     ite_ctx* c = p->ctx;
+    mps_destroy(p->aux);
     free_evolution(p);
     for (double* a : p->A) dev_free(c, a);
     delete p;
@@ -990,6 +994,7 @@ struct Timer {
     }
 };
 enum { PH_TOTAL = 0, PH_RHS, PH_SOLVE, PH_SPLIT, PH_ENV, PH_N };
+}  // namespace
 
 void check_step(const ite_mps* psi, const ite_mpo* H, double h, const ite_step_opts& o) {
     const int L = psi->L;
@@ -997,7 +1002,11 @@ void check_step(const ite_mps* psi, const ite_mpo* H, double h, const ite_step_o
     if (H->L != L) ITE_FAIL(ITE_ESTATE, "imag_step: MPS and MPO lengths differ");
     for (int i = 0; i < L; ++i)
         if (H->d[i] != psi->d[i]) ITE_FAIL(ITE_ESTATE, "imag_step: local dimensions of MPS and MPO differ");
-    ITE_REQUIRE(o.scheme == ITE_SCHEME_TRAP || o.scheme == ITE_SCHEME_BE, "imag_step: unknown scheme");
+    ITE_REQUIRE(o.scheme == ITE_SCHEME_TRAP || o.scheme == ITE_SCHEME_BE || o.scheme == ITE_SCHEME_GL,
+                "imag_step: unknown scheme");
+    ITE_REQUIRE(o.scheme != ITE_SCHEME_GL || (o.gl_nodes >= 1 && o.gl_nodes <= 7),
+                "imag_step: gl_nodes must be in 1..7");
+    ITE_REQUIRE(o.rhs_mode == ITE_RHS_PROJECT || o.rhs_mode == ITE_RHS_MPS, "imag_step: unknown rhs_mode");
     ITE_REQUIRE(o.shift_mode == ITE_SHIFT_FIXED || o.shift_mode == ITE_SHIFT_TRACK, "imag_step: unknown shift mode");
     ITE_REQUIRE(std::isfinite(o.shift), "imag_step: non-finite shift");
     ITE_REQUIRE(o.chi_max >= 1, "imag_step: chi_max must be >= 1");
@@ -1012,7 +1021,6 @@ void check_step(const ite_mps* psi, const ite_mpo* H, double h, const ite_step_o
                 "imag_step: mixed precision needs max_refine >= 0 and tol_refine >= 0");
     ITE_REQUIRE(o.init_guess == ITE_GUESS_PSI || o.init_guess == ITE_GUESS_B, "imag_step: unknown init_guess");
 }
-}  // namespace
 
 // One implicit step of one state, split into the phases of a block so that a
 // batch of states can sweep in lockstep (step_batch): the constructor does
@@ -1281,7 +1289,7 @@ struct StepRun {
     }
 };
 
-void imag_step(ite_mps* psi, const ite_mpo* H, double h, const ite_step_opts& o, ite_step_report* rep) {
+void imag_step_sweep(ite_mps* psi, const ite_mpo* H, double h, const ite_step_opts& o, ite_step_report* rep) {
     ite_ctx* c = psi->ctx;
     check_step(psi, H, h, o);
     c->events_used = 0;
@@ -1319,6 +1327,45 @@ void step_batch(int n, ite_mps* const* psi, const ite_mpo* const* H, const doubl
         for (int q = 0; q < j; ++q)
             if (psi[q] == psi[j]) ITE_FAIL(ITE_EINVAL, "step_batch: a state appears twice");
         check_step(psi[j], H[j], h[j], *opts[j]);
+    }
+    // panels and MPS right-hand sides are whole-state operations: one by one,
+    // the plain sweeps of the others in lockstep
+    std::vector<int> plain;
+    for (int j = 0; j < n; ++j) {
+        if (!step_is_composite(*opts[j])) {
+            plain.push_back(j);
+            continue;
+        }
+        try {
+            imag_step(psi[j], H[j], h[j], *opts[j], reps ? &reps[j] : nullptr);
+            if (status) status[j] = ITE_OK;
+        } catch (const Error& e) {
+            if (!status) throw;
+            status[j] = e.code;
+            c->err = e.what();
+        }
+    }
+    if ((int)plain.size() < n) {
+        if (plain.empty()) return;
+        const int m = (int)plain.size();
+        std::vector<ite_mps*> ps(m);
+        std::vector<const ite_mpo*> hs(m);
+        std::vector<double> hh(m);
+        std::vector<const ite_step_opts*> os(m);
+        std::vector<ite_step_report> rs(m);
+        std::vector<int> st(m, ITE_OK);
+        for (int q = 0; q < m; ++q) {
+            ps[q] = psi[plain[q]];
+            hs[q] = H[plain[q]];
+            hh[q] = h[plain[q]];
+            os[q] = opts[plain[q]];
+        }
+        step_batch(m, ps.data(), hs.data(), hh.data(), os.data(), rs.data(), status ? st.data() : nullptr);
+        for (int q = 0; q < m; ++q) {
+            if (reps) reps[plain[q]] = rs[q];
+            if (status) status[plain[q]] = st[q];
+        }
+        return;
     }
     c->events_used = 0;
     // per-state records and b / guess buffers

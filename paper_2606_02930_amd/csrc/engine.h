@@ -24,6 +24,8 @@ enum SlotId {
     SL_STATS,                      // per-block device records of the local solves of a step
     SL_BATCH, SL_BDESC, SL_BATCHB, // batched solves: workspaces, descriptors, per-state b and guess
     SL_TUNE,                       // tile autotuner: trial output
+    SL_DMF, SL_DM1, SL_DM2, SL_DM3, SL_DMC,   // density-matrix MPO-MPS product: environments,
+    SL_DMR, SL_DMV, SL_DMU,                   // intermediates, kept part, density matrix and its split
     SL_NSLOTS
 };
 
@@ -107,6 +109,9 @@ struct ite_mps {
     std::vector<int> XD;         // bond dimensions of x
     std::vector<BondEnv> env;
     int env_w = 0;               // MPO bond dimension the environments were sized for
+    // auxiliary state of the panel and MPS right-hand-side steps (the
+    // augmented node-site state, or b), kept between steps; owned
+    ite_mps* aux = nullptr;
 };
 
 namespace ite {
@@ -208,12 +213,54 @@ void step_batch(int n, ite_mps* const* psi, const ite_mpo* const* H, const doubl
 
 double dot(ite_ctx* c, const double* x, const double* y, size_t n);
 
+// Copies on the context's stream (asynchronous) and the FP64 GEMM / sparse
+// MPO stage on it (profiled like every contraction of the step).
+void d2h(ite_ctx* c, double* host, const double* dev, size_t n);
+void h2d(ite_ctx* c, void* dev, const void* host, size_t bytes);
+void d2d(ite_ctx* c, double* dst, const double* src, size_t n);
+void gemm(ite_ctx* c, bool tA, bool tB, int M, int N, int K, double alpha, const double* A, long lda,
+          const double* B, long ldb, double beta, const double* C, long ldc, double* D, long ldd);
+void stage(ite_ctx* c, const CsrDev& m, Stage st);
+
+// Sparse matrices of the MPO stages: a dense O x I matrix in CSR form, and
+// the upload of several into one device allocation (*block, freed by the
+// caller with dev_free).
+struct CsrHost {
+    int I = 0, O = 0;
+    std::vector<int> rowptr, col;
+    std::vector<double> val;
+};
+CsrHost dense_to_csr(const std::vector<double>& M, int O, int I);
+std::vector<CsrDev> upload_csr(ite_ctx* c, const std::vector<CsrHost>& hs, void** block);
+
 // Handles
 ite_mpo* mpo_load(ite_ctx* c, int L, const int* d, const int* w, const double* const* W);
 void mpo_destroy(ite_mpo* m);
 ite_mps* mps_new(ite_ctx* c, int L, const int* d, int chi_max);
 void mps_destroy(ite_mps* p);
+// One step by the options' scheme (panel.cpp dispatches): the Gauss-Legendre
+// panel and the MPS right-hand side are built on imag_step_sweep, the plain
+// two-site sweep of one implicit step.
 void imag_step(ite_mps* psi, const ite_mpo* H, double h, const ite_step_opts& o, ite_step_report* rep);
+void imag_step_sweep(ite_mps* psi, const ite_mpo* H, double h, const ite_step_opts& o, ite_step_report* rep);
+// Steps the lockstep batch cannot take (panel and MPS right-hand side).
+bool step_is_composite(const ite_step_opts& o);
+// Validation of step options (EINVAL with the reason).
+void check_step(const ite_mps* psi, const ite_mpo* H, double h, const ite_step_opts& o);
+// Bond capacities min(prod d left, prod d right, chi_max).
+std::vector<int> bond_caps(int L, const std::vector<int>& d, int chi_max);
+// Coefficients of a p-node Gauss-Legendre collocation panel: nodes c and
+// weights b on [0, 1], A (p x p, row-major, A_ij = int_0^(c_i) l_j), the end
+// weights w = A^-T b and r_inf = 1 - b^T A^-1 1.
+struct GlCoef {
+    int p = 0;
+    std::vector<double> c, b, A, w;
+    double r_inf = 0.0;
+};
+GlCoef gl_coefficients(int p);
+// Density-matrix MPO-MPS product out = O psi (see ite_mpo_apply); out has
+// psi's L, d and chi_max.  Returns the largest discarded-weight fraction.
+double mpo_apply_dm(ite_mps* psi, const ite_mpo* O, int chi_max, double cutoff, double tie_rel, ite_mps* out);
 double measure_energy(ite_mps* psi, const ite_mpo* H);
 double overlap(ite_mps* a, ite_mps* b);
 

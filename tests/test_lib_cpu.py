@@ -139,3 +139,27 @@ def test_server_create_validates_options():
               ite.ite_server_opts(0, 2, 1, 0.0)):
         assert lib.ite_server_create(ctypes.byref(o), ctypes.byref(h)) == ite.ITE_EINVAL
     assert lib.ite_server_create(None, ctypes.byref(h)) == ite.ITE_EINVAL
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6, 7])
+def test_gl_coefficients_match_oracle(p):
+    # the library's panel coefficients (Newton on the Legendre recurrence,
+    # the integrals by the same quadrature) against the oracle's (numpy's
+    # Gauss-Legendre rule, polynomial integration of the Lagrange basis)
+    from oracle import gauss
+    g = ite.ite_gl_coefficients(p)
+    c, b, A = gauss.collocation_matrix(p)
+    r_inf, w = gauss.end_weights(p)
+    assert np.abs(g["c"] - c).max() < 1e-14
+    assert np.abs(g["b"] - b).max() < 1e-14
+    assert np.abs(g["A"] - A).max() < 1e-12      # the oracle's monomial integration loses ~1e-13 at p = 7
+    assert np.abs(g["w"] - w).max() < 1e-11 * max(1.0, np.abs(w).max())
+    assert abs(g["r_inf"] - r_inf) < 1e-11 and abs(g["r_inf"] - (-1) ** p) < 1e-11
+
+
+def test_gl_coefficients_refuse_bad_node_counts():
+    lib = ite.load_library()
+    buf = (ctypes.c_double * 64)()
+    r = ctypes.c_double()
+    for p in (0, 8, -1):
+        assert lib.ite_gl_coefficients(p, buf, buf, buf, buf, ctypes.byref(r)) == ite.ITE_EINVAL
