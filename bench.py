@@ -192,6 +192,26 @@ def cpu_baseline(dims, d, W, budget_s=30.0):
             "host_cpus": len(os.sched_getaffinity(0)), "matvec_s": t_mv, "single_core": single}
 
 
+def cpu_dm_baseline(dims, d, L_sample=22, chi=1024):
+    """The oracle's density-matrix product (the MPS right-hand side of the
+    trapezoid step) timed on a bounded sample: a chain of L_sample sites at
+    bond dimension up to chi (random right-orthonormal tensors), the MPO of
+    (1 + h s) I - h H; extrapolated to the workload by the site-cost
+    equivalents sum_j D_j D_(j+1) (D_j + D_(j+1)) of the two bond profiles."""
+    from oracle import apply as oapply, mpo as ompo
+    from workload import random_isometry_mps, rng_for
+    psi = random_isometry_mps(rng_for(2, 9), L_sample, d, chi, distinct=2)
+    sdims = [psi[0].shape[0]] + [a.shape[2] for a in psi]
+    O = oapply.rhs_mpo(ompo.heisenberg_mpo(L_sample), 0.5, -1.0)
+    t0 = time.perf_counter()
+    oapply.density_matrix_apply(O, psi, chi, 0.0, 1e-13)
+    t = time.perf_counter() - t0
+    cost = lambda ds: sum(ds[j] * ds[j + 1] * (ds[j] + ds[j + 1]) for j in range(len(ds) - 1))
+    scale = cost(dims) / cost(sdims)
+    return t, scale, f"the oracle's density-matrix product on a {L_sample}-site chain at chi={chi} took {t:.1f} s, " \
+                     f"x {scale:.1f} site-cost equivalents for the workload's bonds"
+
+
 def measured_traffic(kernel_short):
     """HBM bytes per launch of a kernel from the committed counter summary
     (profiles/traffic.json: FETCH_SIZE and WRITE_SIZE per dispatch, scaled by
@@ -245,8 +265,17 @@ def run_steady(ite, torch, args):
     H = ite.ite_mpo_load(ctx, W)
     psi = ite.ite_mps_load(ctx, tensors, chi)
     log(f"steady-state MPS loaded: L={L}, d={d}, max bond {max(dims)}")
-    o = ite.ite_default_opts(chi_max=chi, cutoff=0.0, precision=prec)
-    hs = h_values(tau1)
+    scheme = {"trap": dict(scheme=ite.SCHEME_TRAP), "trap_mps": dict(scheme=ite.SCHEME_TRAP, rhs_mode=ite.RHS_MPS),
+              "gl": dict(scheme=ite.SCHEME_GL, gl_nodes=args.gl_nodes)}[args.scheme]
+    o = ite.ite_default_opts(chi_max=chi, cutoff=0.0, precision=prec, **scheme)
+    # trapezoid half steps; a panel spans the whole grid step
+    hs = [h * (2.0 if args.scheme == "gl" else 1.0) for h in h_values(tau1)]
+    if args.scheme == "gl":
+        label = label.replace("trapezoid step", f"Gauss-Legendre collocation panel ({args.gl_nodes} nodes)").replace(
+            "h of grid steps", "panel = grid steps")
+    elif args.scheme == "trap_mps":
+        label = label.replace("trapezoid step", "trapezoid step with the right-hand side formed as an MPS by the "
+                              "density-matrix MPO-MPS product (chi and cutoff of the step)")
     reps = []
     for k in range(args.warmup):
         r = ite.ite_imag_step(ctx, psi, H, hs[k % 3], o)
@@ -284,7 +313,7 @@ def run_steady(ite, torch, args):
         "vs_baseline": None,
         "dtype": DTYPE[args.precision],
         "data": "synthetic",
-        "config": {"workload": label, "precision": args.precision},
+        "config": {"workload": label, "precision": args.precision, "scheme": args.scheme},
         "matvec_tflops": mv_tflops,
         "matvec_ms": mv_s * 1e3,
         "phase_ms": {k: float(np.mean([r[k] for r in reps])) for k in
@@ -297,7 +326,23 @@ def run_steady(ite, torch, args):
     }
     if not args.no_cpu:
         log("timing the CPU oracle on one full-size block ...")
-        out["cpu_baseline"] = cpu_baseline(dims, d, W)
+        Wc = W
+        if args.scheme == "gl":
+            # the panel's interior blocks carry the MPO of H - s (bond w + 1)
+            from oracle import gauss
+            Wc = gauss.shifted_mpo(W, -1.0)
+        cb = cpu_baseline(dims, d, Wc)
+        if args.scheme == "trap_mps":
+            log("timing the CPU oracle's density-matrix product on a bounded sample ...")
+            t_dm, scale, note = cpu_dm_baseline(dims, d, chi=max(dims))
+            t_step = 1.0 / cb["value"] + t_dm * scale
+            cb["value"] = 1.0 / t_step
+            cb["sample"] += "; plus " + note
+            cb.pop("single_core", None)
+        elif args.scheme == "gl":
+            cb["sample"] += "; the blocks of a panel are those of the augmented system (node site first, MPO of " \
+                            "H - s), timed here on an interior block with that MPO"
+        out["cpu_baseline"] = cb
     ite.ite_mps_destroy(psi)
     ite.ite_mpo_destroy(H)
     ite.ite_ctx_destroy(ctx)
@@ -564,6 +609,10 @@ def main():
     ap.add_argument("--workers", type=int, default=4, help="serve mode: server worker threads")
     ap.add_argument("--max-active", type=int, default=8, help="serve mode: active requests per worker")
     ap.add_argument("--samples", type=int, default=1024, help="sample mode: samples per call")
+    ap.add_argument("--scheme", default="trap", choices=["trap", "trap_mps", "gl"],
+                    help="step mode: trapezoid (right-hand side projected), trapezoid with the right-hand side "
+                         "as an MPS (density-matrix product), or a Gauss-Legendre panel")
+    ap.add_argument("--gl-nodes", type=int, default=2, help="Gauss-Legendre nodes per panel (--scheme gl)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--chi", type=int, default=0, help="bond dimension (default: the workload's)")
     args = ap.parse_args()

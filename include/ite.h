@@ -133,7 +133,9 @@ typedef struct ite_step_report {
     double mean_res_rel;
     long long matvecs_fp64;  /* effective-Hamiltonian products in FP64 */
     long long matvecs_lo;    /* ... in FP32 or BF16 */
-    double ms_total, ms_rhs, ms_solve, ms_split, ms_env;   /* device time per phase */
+    double ms_total, ms_rhs, ms_solve, ms_split, ms_env;   /* device time per phase (the density-matrix
+                          * product of ITE_RHS_MPS counts as rhs, a panel's read-off and cut-back as
+                          * split; those two are timed on the host around a drained stream) */
     double rhs_disc;     /* ITE_RHS_MPS: largest discarded-weight fraction of the density-matrix product */
     int    aux_max_chi;  /* ITE_SCHEME_GL: largest bond of the augmented (node-site) state before it
                           * is cut back to the chain's bonds */

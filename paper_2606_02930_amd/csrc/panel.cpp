@@ -40,6 +40,7 @@
 #include "engine.h"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <memory>
 
@@ -192,6 +193,12 @@ ite_mps* ensure_aux(ite_mps* psi, int L, const std::vector<int>& d) {
     return psi->aux;
 }
 
+// Milliseconds since t0 after the context's stream has drained.
+double ms_since(ite_ctx* c, std::chrono::steady_clock::time_point t0) {
+    sync(c);
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
 double step_shift(ite_mps* psi, const ite_mpo* H, const ite_step_opts& o) {
     if (o.shift_mode != ITE_SHIFT_TRACK) return o.shift;
     if (!psi->e_valid) {
@@ -247,6 +254,7 @@ void gl_panel(ite_mps* psi, const ite_mpo* H, double dt, const ite_step_opts& o,
     ite_step_report r{};
     imag_step_sweep(aug, Ha.get(), dt, oa, &r);
     const int aux_max = *std::max_element(aug->D.begin(), aug->D.end());
+    const auto t_end = std::chrono::steady_clock::now();
     // end value: the node site contracted with (r_inf, w) into site 1
     const int D1 = aug->D[1], D2 = aug->D[2];
     double* sm = slot_t<double>(c, SL_DMC, (size_t)64 + D1 + (size_t)d[0] * D2);
@@ -302,6 +310,10 @@ void gl_panel(ite_mps* psi, const ite_mpo* H, double dt, const ite_step_opts& o,
     r.max_chi = *std::max_element(cd.begin(), cd.end());
     r.aux_max_chi = aux_max;
     r.rhs_disc = 0.0;
+    // the read-off and the cut back to the chain's bonds count as split time
+    const double ms_end = ms_since(c, t_end);
+    r.ms_split += ms_end;
+    r.ms_total += ms_end;
     if (rep) *rep = r;
 }
 
@@ -490,7 +502,10 @@ void trap_step_mps_rhs(ite_mps* psi, const ite_mpo* H, double h, const ite_step_
     direct_sum_identity(H, -h, 1.0 + h * s, T, wo);
     MpoPtr Ob = load_host_mpo(c, psi->d, wo, T);
     ite_mps* b = ensure_aux(psi, psi->L, psi->d);
+    sync(c);
+    const auto t0 = std::chrono::steady_clock::now();
     const double disc = mpo_apply_dm(psi, Ob.get(), std::min(o.chi_max, psi->chi_max), o.cutoff, o.tie_rel, b);
+    const double ms_prod = ms_since(c, t0);
     ite_step_opts ob = o;
     ob.scheme = ITE_SCHEME_BE;
     ob.shift_mode = ITE_SHIFT_FIXED;
@@ -510,6 +525,9 @@ void trap_step_mps_rhs(ite_mps* psi, const ite_mpo* H, double h, const ite_step_
     r.shift = s;
     r.rhs_disc = disc;
     r.aux_max_chi = 0;
+    // the density-matrix product is the step's right-hand side
+    r.ms_rhs += ms_prod;
+    r.ms_total += ms_prod;
     if (rep) *rep = r;
 }
 
