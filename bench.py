@@ -411,10 +411,24 @@ def _serve_once(ite, hamiltonians, stream, workers, max_active, precision, label
             sp = random_spinors(np.random.default_rng(seed), L, 2)
             o = ite.ite_default_opts(chi_max=chi, cutoff=1e-10, precision=precision)
             ids.append(ite.ite_server_submit(srv, hamiltonians.heisenberg(L), sp, chi, 0.01, tau1, 1.3, o))
-        infos = []
-        for i in ids:
-            infos.append(ite.ite_server_wait(srv, i))
-            log(f"  [{label}] request {len(infos)}/{len(ids)} done at {infos[-1]['t_done'] - t_start:.2f} s")
+        # poll: report each request as it finishes and, every 20 s, the
+        # steps done so far by the whole stream
+        done = {}
+        t_last = time.perf_counter()
+        while len(done) < len(ids):
+            for i in ids:
+                if i in done:
+                    continue
+                info = ite.ite_server_info(srv, i)
+                if info["status"] in (ite.REQ_DONE, ite.REQ_FAILED):
+                    done[i] = info
+                    log(f"  [{label}] request {len(done)}/{len(ids)} done at {info['t_done'] - t_start:.2f} s")
+            if time.perf_counter() - t_last > 20.0:
+                steps = sum(ite.ite_server_info(srv, i)["n_steps"] for i in ids)
+                log(f"  [{label}] {len(done)}/{len(ids)} requests done, {steps} steps in all so far")
+                t_last = time.perf_counter()
+            time.sleep(0.02)
+        infos = [done[i] for i in ids]
         energies = [ite.ite_server_reports(srv, i)[-1]["energy"] for i in ids]
     finally:
         ite.ite_server_destroy(srv)
