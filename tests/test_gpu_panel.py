@@ -340,3 +340,37 @@ def test_panel_option_validation(ctx):
     finally:
         ite.ite_mps_destroy(psi)
         ite.ite_mpo_destroy(Hm)
+
+
+@pytest.mark.parametrize("mode", ["gl", "mps_rhs"])
+def test_full_size_splits_inside_panels_and_mps_rhs_steps(ctx, mode):
+    # complete bonds up to 256: the central blocks (and, for the MPS
+    # right-hand side, the density matrices of the product) split 512 x 512
+    # matrices, through the Householder preconditioning and the multi-pair
+    # Jacobi rounds; paper budget, two steps of the 0.01 -> 1000, ratio 1.3
+    # grid
+    L, chi = 16, 256
+    sp = random_spinors(rng_for(1, 80), L, 2)
+    grid = ed.loggrid(0.01, 1000.0, 1.3)[:3]
+    kw = dict(shift_mode="track", chi_max=chi, cutoff=0.0, krylov_dim=10, max_cycles=1, tol_loc=0.0)
+    extra = dict(scheme="gl", gl_nodes=2) if mode == "gl" else dict(scheme="trap", rhs_mode="mps")
+    psi = ite.ite_mps_create(ctx, sp, chi, pad_full=True)
+    Hm = ite.ite_mpo_load(ctx, hamiltonians.heisenberg(L))
+    try:
+        reps = ite.ite_evolve_grid(ctx, psi, Hm, grid, _opts(**extra, **kw))
+        out = ite.ite_mps_export(ctx, psi, [2] * L)
+    finally:
+        ite.ite_mps_destroy(psi)
+        ite.ite_mpo_destroy(Hm)
+    o_psi = omps.product_state(sp, chi, pad_full=True)
+    if mode == "gl":
+        o_out, o_reps = gauss.gl_evolve(o_psi, ompo.heisenberg_mpo(L), grid, 2, omps.StepOptions(**kw))
+    else:
+        o_out, o_reps = oapply.evolve_grid_mps_rhs(o_psi, ompo.heisenberg_mpo(L), grid,
+                                                   omps.StepOptions(scheme="trap", **kw))
+    assert len(reps) == 2 and max(omps.bond_dims(o_out)) == chi
+    for r, orr in zip(reps, o_reps):
+        assert r["max_chi"] == orr.max_chi
+        assert abs(r["energy"] - orr.energy) <= 1e-10 * abs(orr.energy)
+        assert abs(r["norm_before"] - orr.norm_before) <= 1e-10 * orr.norm_before
+    assert 1 - abs(mps_overlap(out, o_out)) <= 1e-8
