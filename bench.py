@@ -21,6 +21,9 @@ Other workloads (own JSON line each):
   --workload heis64  a whole evolution of the L=64 chain (chi <= 256, cutoff
                      1e-10, 45 steps from a random product state), in the
                      chosen precision and in FP64, with the energy differences
+  --workload heis100full  a whole evolution of the L=100 chain from the
+                     perturbed Neel state (45 steps, chi_max 1024, --cutoff,
+                     --scheme), per-step log, DMRG reference at the end
   --mode serve       the serving loop on the first --requests arrivals of the
                      256-request stream (its own L / chi / beta distributions):
                      batched FP64 and FP32-IR against serial plain FP64
@@ -397,6 +400,57 @@ def run_heis64(ite, torch, args):
 
 
 
+def run_full(ite, torch, args):
+    """A whole evolution of the L=100 chain from the Neel state with a 0.1
+    random perturbation (seeded) along the geometric grid 0.01 -> 1000, ratio
+    1.3 (45 steps), in the scheme of --scheme, chi_max = --chi (default 1024)
+    and cutoff --cutoff (0: the bonds fill up to chi_max, the contraction-bound
+    workload; 1e-10: adaptive bonds as in the paper's Heisenberg run), shift
+    tracking the energy, paper budget; per-step energy, largest bond and time,
+    then two DMRG sweeps from the final state for a ground-state reference."""
+    from paper_2606_02930_amd import hamiltonians
+    from workload import rng_for, neel_spinors
+    L, chi = 100, args.chi or 1024
+    W = hamiltonians.heisenberg(L)
+    sp = neel_spinors(rng_for(2), L, 0.1)
+    ctx = ite.ite_ctx_create(0)
+    H = ite.ite_mpo_load(ctx, W)
+    psi = ite.ite_mps_create(ctx, sp, chi)
+    scheme = {"trap": dict(scheme=ite.SCHEME_TRAP), "trap_mps": dict(scheme=ite.SCHEME_TRAP, rhs_mode=ite.RHS_MPS),
+              "gl": dict(scheme=ite.SCHEME_GL, gl_nodes=args.gl_nodes)}[args.scheme]
+    o = ite.ite_default_opts(chi_max=chi, cutoff=args.cutoff, precision=PREC[args.precision], **scheme)
+    grid = ite.ite_loggrid(0.01, 1000.0, 1.3)
+    reps = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(1, len(grid)):
+        dtau = grid[k] - grid[k - 1]
+        r = ite.ite_imag_step(ctx, psi, H, dtau if args.scheme == "gl" else 0.5 * dtau, o)
+        reps.append(r)
+        log(f"step {k}: tau {grid[k]:.4g} E={r['energy']:.10f} maxchi={r['max_chi']} {r['ms_total']:.0f} ms "
+            f"(split {r['ms_split']:.0f}, solve {r['ms_solve']:.0f}) elapsed {time.perf_counter() - t0:.1f} s")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    dm = ite.ite_dmrg_sweeps(ctx, psi, H, 2, chi, cutoff=args.cutoff, krylov_dim=10, max_cycles=1)
+    log(f"DMRG from the final state: E={dm['energy']:.10f}")
+    ite.ite_mps_destroy(psi)
+    ite.ite_mpo_destroy(H)
+    ite.ite_ctx_destroy(ctx)
+    e_end = reps[-1]["energy"]
+    return {"metric": "tau-steps/s, whole evolution at L=100", "value": len(reps) / elapsed, "unit": "tau-steps/s",
+            "n_gpus": 1, "steps": len(reps), "seconds": elapsed, "higher_is_better": True, "dtype": DTYPE[args.precision],
+            "data": "synthetic",
+            "config": {"workload": f"Heisenberg S=1/2 open chain L={L}, J=1, MPO w=5, Neel + 0.1 N(0,1) perturbation "
+                                   f"(seeded), grid 0.01 -> 1000 ratio 1.3, chi_max={chi}, cutoff {args.cutoff:g} + "
+                                   f"tie rule, shift = energy, paper budget", "scheme": args.scheme,
+                       "precision": args.precision},
+            "final_energy": e_end, "dmrg_reference_energy": dm["energy"],
+            "final_minus_dmrg_rel": (e_end - dm["energy"]) / abs(dm["energy"]),
+            "max_chi": max(r["max_chi"] for r in reps),
+            "per_step": [{"tau": float(g), "energy": r["energy"], "max_chi": r["max_chi"], "ms": r["ms_total"]}
+                         for g, r in zip(grid[1:], reps)]}
+
+
 def _serve_once(ite, hamiltonians, stream, workers, max_active, precision, label):
     """Submit the stream at its arrival times to a fresh server; return the
     per-request latencies, the steps, the makespan and the final energies."""
@@ -617,7 +671,8 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="fp64", choices=list(PREC))
-    ap.add_argument("--workload", default="heis100", choices=["heis100", "aim60", "heis64"])
+    ap.add_argument("--workload", default="heis100", choices=["heis100", "aim60", "heis64", "heis100full"])
+    ap.add_argument("--cutoff", type=float, default=0.0, help="heis100full: discarded-weight cutoff of the splits")
     ap.add_argument("--mode", default="step", choices=["step", "matvec", "serve", "split", "dmrg", "sample"])
     ap.add_argument("--requests", type=int, default=8, help="serve mode: first arrivals of the request stream")
     ap.add_argument("--workers", type=int, default=4, help="serve mode: server worker threads")
@@ -655,6 +710,8 @@ def main():
                "unit": "TFLOP/s", "by_precision": res}
     elif args.workload == "heis64":
         out = run_heis64(ite, torch, args)
+    elif args.workload == "heis100full":
+        out = run_full(ite, torch, args)
     else:
         out = run_steady(ite, torch, args)
     print(json.dumps(out), flush=True)
