@@ -153,16 +153,25 @@ void gemm(ite_ctx* c, bool tA, bool tB, int M, int N, int K, double alpha, const
     g.M = M; g.N = N; g.K = K; g.tA = tA; g.tB = tB;
     g.alpha = alpha; g.beta = beta;
     g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc; g.D = D; g.ldd = ldd;
+    if (c->gemm_slots == 0) {
+        int cus = 0;
+        HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
+        c->gemm_slots = 2 * std::max(cus, 1);
+    }
+    // an output too small to fill the chip's workgroup slots but with a long
+    // K: K parts as one batch, summed in a fixed order
+    const int parts = M > 0 && N > 0 ? splitk_parts(M, N, K, c->gemm_slots) : 1;
+    double* work = parts > 1 ? slot_t<double>(c, SL_SPLITK, (size_t)parts * M * N) : nullptr;
     if (c->prof_on && M > 0 && N > 0) {
         CtxProbe pr(c);
         pr.begin(PK_GEMM, c->stream);
-        gemm_f64(g, c->stream);
+        gemm_f64_splitk(g, parts, work, c->stream);
         pr.end(PK_GEMM, c->stream);
         pr.work(PK_GEMM, 2.0 * M * N * (double)K,
                 8.0 * ((double)M * K + (double)K * N + (C && beta != 0.0 ? 2.0 : 1.0) * (double)M * N));
         return;
     }
-    gemm_f64(g, c->stream);
+    gemm_f64_splitk(g, parts, work, c->stream);
 }
 
 void stage(ite_ctx* c, const CsrDev& m, Stage st) {

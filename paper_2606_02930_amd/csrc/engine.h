@@ -26,6 +26,7 @@ enum SlotId {
     SL_TUNE,                       // tile autotuner: trial output
     SL_DMF, SL_DM1, SL_DM2, SL_DM3, SL_DMC,   // density-matrix MPO-MPS product: environments,
     SL_DMR, SL_DMV, SL_DMU,                   // intermediates, kept part, density matrix and its split
+    SL_SPLITK,                     // K parts of under-filled FP64 products
     SL_NSLOTS
 };
 
@@ -62,6 +63,7 @@ struct ite_ctx {
     long long bgraph_key[5] = {};
     long long graph_captures = 0, graph_replays = 0, batch_solves = 0;
     std::vector<char> batch_host;   // host image of the batch descriptors (kept until the next batch)
+    int gemm_slots = 0;             // concurrent GEMM workgroups (two per compute unit), queried once
 };
 
 // Sparse small matrix in CSR form on the device.

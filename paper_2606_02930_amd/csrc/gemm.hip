@@ -22,6 +22,7 @@
 // L2.
 #include "internal.h"
 
+#include <algorithm>
 #include <cstdint>
 #include <cstring>
 #include <type_traits>
@@ -563,6 +564,64 @@ __global__ __launch_bounds__(NTHREADS) void gemm_bf16_kernel(Params p) {
 }  // namespace
 
 void gemm_f64(const Gemm& g, hipStream_t s) { launch<double>(g, s); }
+
+namespace {
+// D[m][n] = alpha sum_b W[b][m][n] + beta C[m][n], the parts summed in order.
+__global__ __launch_bounds__(256) void splitk_sum_kernel(const double* __restrict__ W, int parts, int M, int N,
+                                                         double alpha, const double* C, long ldc, double beta,
+                                                         double* D, long ldd) {
+    const long n_all = (long)M * N, part = n_all;
+    for (long e = blockIdx.x * 256L + threadIdx.x; e < n_all; e += (long)gridDim.x * 256) {
+        double v = W[e];
+        for (int b = 1; b < parts; ++b) v += W[b * part + e];
+        const long m = e / N, n = e % N;
+        v *= alpha;
+        if (C) v += beta * C[m * ldc + n];
+        D[m * ldd + n] = v;
+    }
+}
+}  // namespace
+
+int splitk_parts(int M, int N, int K, int slots) {
+    const long tiles = (long)((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+    if (tiles * 2 > slots || K < 2048) return 1;
+    int s = (int)std::min<long>(slots / tiles, K / 1024);
+    while (s > 1 && K % (s * BK) != 0) --s;
+    return std::max(s, 1);
+}
+
+// The K parts of g (no C, alpha 1) as one batched launch: part k to
+// out + k part_stride with row stride ldo.
+static void gemm_f64_kparts(const Gemm& g, int parts, double* out, long ldo, long part_stride, hipStream_t s) {
+    if (g.batch != 1 || g.Df) ITE_FAIL(ITE_EINVAL, "gemm K parts: single FP64 problems only");
+    if (parts < 1 || g.K % parts != 0) ITE_FAIL(ITE_EINVAL, "gemm K parts: K must split evenly");
+    const int kp = g.K / parts;
+    Gemm h = g;
+    h.K = kp;
+    h.batch = parts;
+    h.sA = g.tA ? (long)kp * g.lda : kp;      // A stored K x M when transposed, else M x K
+    h.sB = g.tB ? kp : (long)kp * g.ldb;      // B stored N x K when transposed, else K x N
+    h.alpha = 1.0;
+    h.beta = 0.0;
+    h.C = nullptr;
+    h.D = out;
+    h.ldd = ldo;
+    h.sD = part_stride;
+    launch<double>(h, s);
+}
+
+void gemm_f64_splitk(const Gemm& g, int parts, double* work, hipStream_t s) {
+    if (parts <= 1) {
+        gemm_f64(g, s);
+        return;
+    }
+    gemm_f64_kparts(g, parts, work, g.N, (long)g.M * g.N, s);
+    const long n = (long)g.M * g.N;
+    const int grid = (int)std::min<long>(4096, (n + 255) / 256);
+    hipLaunchKernelGGL(splitk_sum_kernel, dim3(grid), dim3(256), 0, s, work, parts, g.M, g.N, g.alpha, g.C, g.ldc,
+                       g.beta, g.D, g.ldd);
+    HIP_CHECK(hipGetLastError());
+}
 
 size_t grouped_desc_bytes() { return sizeof(GroupDesc); }
 
