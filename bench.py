@@ -24,6 +24,9 @@ Other workloads (own JSON line each):
   --workload heis100full  a whole evolution of the L=100 chain from the
                      perturbed Neel state (45 steps, chi_max 1024, --cutoff,
                      --scheme), per-step log, DMRG reference at the end
+  --workload aim60full   whole impurity evolutions (54 steps, chi_max 512,
+                     cutoff 1e-9) at each --U, with the double occupancy and a
+                     DMRG reference at the end
   --mode serve       the serving loop on the first --requests arrivals of the
                      256-request stream (its own L / chi / beta distributions):
                      batched FP64 and FP32-IR against serial plain FP64
@@ -451,6 +454,51 @@ def run_full(ite, torch, args):
                          for g, r in zip(grid[1:], reps)]}
 
 
+def run_aim_full(ite, torch, args, U):
+    """A whole evolution of the Anderson impurity chain (59-site metallic
+    bath, d=4, MPO w=6) at interaction U, half filling eps_d = -U/2, from a
+    seeded random product state along the geometric grid 0.01 -> 1e4, ratio
+    1.3 (54 steps), trapezoid, shift tracking the energy (the paper's rule for
+    this model), paper budget, chi_max 512 (or --chi), cutoff --cutoff
+    (default 1e-9 for this workload); then the impurity double occupancy and
+    two DMRG sweeps from the final state for a ground-state reference."""
+    from paper_2606_02930_amd import hamiltonians
+    from workload import rng_for, random_spinors, aim_bath
+    chi = args.chi or 512
+    cutoff = args.cutoff if args.cutoff > 0 else 1e-9
+    eps, V = aim_bath(59, 0.1)
+    W = hamiltonians.anderson_star(U, -U / 2, eps, V)
+    L = len(W)
+    sp = random_spinors(rng_for(3), L, 4)
+    ctx = ite.ite_ctx_create(0)
+    H = ite.ite_mpo_load(ctx, W)
+    psi = ite.ite_mps_create(ctx, sp, chi)
+    o = ite.ite_default_opts(chi_max=chi, cutoff=cutoff, precision=PREC[args.precision])
+    grid = ite.ite_loggrid(0.01, 1e4, 1.3)
+    reps = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(1, len(grid)):
+        r = ite.ite_imag_step(ctx, psi, H, 0.5 * (grid[k] - grid[k - 1]), o)
+        reps.append(r)
+        log(f"U={U} step {k}: tau {grid[k]:.4g} E={r['energy']:.10f} maxchi={r['max_chi']} {r['ms_total']:.0f} ms "
+            f"elapsed {time.perf_counter() - t0:.1f} s")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    docc = ite.ite_mps_expect_site(ctx, psi, 0, np.diag([0.0, 0.0, 0.0, 1.0]))
+    dm = ite.ite_dmrg_sweeps(ctx, psi, H, 2, chi, cutoff=cutoff, krylov_dim=10, max_cycles=1)
+    log(f"U={U}: double occupancy {docc:.8f}; DMRG from the final state E={dm['energy']:.10f}")
+    ite.ite_mps_destroy(psi)
+    ite.ite_mpo_destroy(H)
+    ite.ite_ctx_destroy(ctx)
+    return {"U": U, "seconds": elapsed, "steps": len(reps), "value": len(reps) / elapsed,
+            "final_energy": reps[-1]["energy"], "dmrg_reference_energy": dm["energy"],
+            "final_minus_dmrg_rel": (reps[-1]["energy"] - dm["energy"]) / abs(dm["energy"]),
+            "double_occupancy": docc, "max_chi": max(r["max_chi"] for r in reps),
+            "per_step": [{"tau": float(g), "energy": r["energy"], "max_chi": r["max_chi"], "ms": r["ms_total"]}
+                         for g, r in zip(grid[1:], reps)]}
+
+
 def _serve_once(ite, hamiltonians, stream, workers, max_active, precision, label):
     """Submit the stream at its arrival times to a fresh server; return the
     per-request latencies, the steps, the makespan and the final energies."""
@@ -671,7 +719,9 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--precision", default="fp64", choices=list(PREC))
-    ap.add_argument("--workload", default="heis100", choices=["heis100", "aim60", "heis64", "heis100full"])
+    ap.add_argument("--workload", default="heis100",
+                    choices=["heis100", "aim60", "heis64", "heis100full", "aim60full"])
+    ap.add_argument("--U", type=float, nargs="+", default=[4.0], help="aim60full: impurity interactions")
     ap.add_argument("--cutoff", type=float, default=0.0, help="heis100full: discarded-weight cutoff of the splits")
     ap.add_argument("--mode", default="step", choices=["step", "matvec", "serve", "split", "dmrg", "sample"])
     ap.add_argument("--requests", type=int, default=8, help="serve mode: first arrivals of the request stream")
@@ -712,6 +762,17 @@ def main():
         out = run_heis64(ite, torch, args)
     elif args.workload == "heis100full":
         out = run_full(ite, torch, args)
+    elif args.workload == "aim60full":
+        runs = [run_aim_full(ite, torch, args, U) for U in args.U]
+        out = {"metric": "tau-steps/s, whole impurity evolutions", "unit": "tau-steps/s", "n_gpus": 1,
+               "dtype": DTYPE[args.precision], "data": "synthetic",
+               "value": sum(r["steps"] for r in runs) / sum(r["seconds"] for r in runs),
+               "config": {"workload": "Anderson impurity, 59-site metallic bath (uniform grid in [-1,1], "
+                                      "Gamma=0.1), eps_d=-U/2, L=60 (d=4), MPO w=6, random product state (seeded), "
+                                      "trapezoid, shift = energy, paper budget, grid 0.01 -> 1e4 ratio 1.3",
+                          "chi_max": args.chi or 512, "cutoff": args.cutoff if args.cutoff > 0 else 1e-9,
+                          "precision": args.precision},
+               "runs": runs}
     else:
         out = run_steady(ite, torch, args)
     print(json.dumps(out), flush=True)
