@@ -1129,8 +1129,9 @@ void jacobi_input(const double* theta, int m, int n, int dir, double* Z, hipStre
 
 namespace {
 
-// Rows per block: 16 for small matrices, 32 from p = 256 on (fewer rounds).
-inline int block_rows(int p) { return p >= 256 ? 32 : 16; }
+// Rows per block: 16 for small matrices, 32 from p = 128 on (fewer rounds, and
+// the fused rotation + Gram launch).
+inline int block_rows(int p) { return p >= 128 ? 32 : 16; }
 
 template <int RB>
 void ws_sizes(int p, int q, size_t* gram, size_t* rot, size_t* off) {
