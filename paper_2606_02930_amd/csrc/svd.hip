@@ -9,8 +9,10 @@
 // of one run and the rotation part is a complete orthonormal basis even when
 // some sigma_i are zero.
 //
-// Rows are grouped in blocks of RB (16, or 32 for large p); a round-robin
-// (circle) schedule pairs the blocks so that every pair meets once per sweep.
+// Up to 64 rows one workgroup runs the whole Jacobi (blocks of 16 rows up to
+// 32 rows, of 32 up to 64).  Beyond that the rows are grouped in blocks of
+// RB = 32; a round-robin (circle) schedule pairs the blocks so that every
+// pair meets once per sweep.
 // For each pair of blocks (PR = 2 RB rows):
 //   1. gram:   G = X_pair X_pair^T, summed over column chunks with FP64 MFMA;
 //   2. inner:  one cyclic sweep of two-sided Jacobi rotations on the PR x PR
@@ -19,7 +21,7 @@
 //              the rotations and is made orthogonal to FP64 rounding by
 //              Newton-Schulz steps;
 //   3. rotate: Z_pair <- Q^T Z_pair over all ld columns (FP64 MFMA).
-// For 32-row blocks step 3 of a round and step 1 of the next are one launch
+// Step 3 of a round and step 1 of the next are one launch
 // (the data columns alternate between Z and a second buffer), and the
 // identity part of step 3 runs inside the next round's inner launch.  Pairs
 // whose rows are already orthogonal to the working tolerance produce no
@@ -1129,10 +1131,6 @@ void jacobi_input(const double* theta, int m, int n, int dir, double* Z, hipStre
 
 namespace {
 
-// Rows per block: 16 for small matrices, 32 from p = 128 on (fewer rounds, and
-// the fused rotation + Gram launch).
-inline int block_rows(int p) { return p >= 128 ? 32 : 16; }
-
 template <int RB>
 void ws_sizes(int p, int q, size_t* gram, size_t* rot, size_t* off) {
     constexpr int PR = Blk<RB>::PR, GC = Blk<RB>::GC;
@@ -1164,7 +1162,6 @@ JacobiResult run_jacobi(double* Z, int p, int q, int ld, double tol, int max_swe
     if (nb & 1) ++nb;
     const int npairs = nb / 2;
     const int nchunks = std::max(1, (q + GC - 1) / GC);
-    const int xw = rotate_width(npairs, q), nxr = std::max(1, (q + xw - 1) / xw);
     const int nu = ld - q;                         // identity-part columns
     const int nuch = (nu + UW - 1) / UW;
     // off_ws[0]: largest off-diagonal measure of the sweep, off_ws[1]: largest
@@ -1178,9 +1175,9 @@ JacobiResult run_jacobi(double* Z, int p, int q, int ld, double tol, int max_swe
     // 32-row blocks: the rotation of round r and the Gram of round r + 1 are
     // one launch, whose new data rows go to the other of two buffers (the Z
     // columns 0..q and Xb); round g reads buffer g mod 2
-    constexpr bool fused = RB == 32;
+    static_assert(RB == 32, "the multi-pair rounds use 32-row blocks and the fused rotation + Gram");
     double* Xb = gram_ws + (size_t)npairs * nchunks * PR * PR;
-    if (fused) {
+    {
         bool timed = probe && probe->begin(PK_GRAM, s);
         hipLaunchKernelGGL((gram_kernel<RB>), dim3(nchunks, npairs), dim3(GRAM_NT), 0, s, Z, p, q, ld, 0, nb,
                            nchunks, gram_ws, work);
@@ -1207,14 +1204,7 @@ JacobiResult run_jacobi(double* Z, int p, int q, int ld, double tol, int max_swe
             const double* rold = rot_ws + (long)(cur ^ 1) * npairs * PR * PR;
             int* fcur = rotated + cur * npairs;
             const int* fold = rotated + (cur ^ 1) * npairs;
-            bool timed;
-            if (!fused) {
-                timed = probe && probe->begin(PK_GRAM, s);
-                hipLaunchKernelGGL((gram_kernel<RB>), dim3(nchunks, npairs), dim3(GRAM_NT), 0, s, Z, p, q, ld, r, nb,
-                                   nchunks, gram_ws, work);
-                if (timed) probe->end(PK_GRAM, s);
-            }
-            timed = probe && probe->begin(PK_INNER, s);
+            bool timed = probe && probe->begin(PK_INNER, s);
             const int ublocks = (rprev >= 0 && nu > 0) ? npairs * nuch : 0;
             if (lowg)
                 hipLaunchKernelGGL((inner_kernel<RB, float>), dim3(npairs + ublocks), dim3(Blk<RB>::NTI), 0, s,
@@ -1226,14 +1216,11 @@ JacobiResult run_jacobi(double* Z, int p, int q, int ld, double tol, int max_swe
                                    q, npairs, rprev, rold, fold, nuch);
             if (timed) probe->end(PK_INNER, s);
             timed = probe && probe->begin(PK_ROTATE, s);
-            if constexpr (fused) {
+            {
                 const bool odd = g & 1;
                 hipLaunchKernelGGL((rotate_gram_kernel<RB>), dim3(nchunks, npairs), dim3(512), 0, s,
                                    odd ? Xb : Z, odd ? q : ld, odd ? Z : Xb, odd ? ld : q, p, q, r, nb, nchunks, rcur,
                                    gram_ws, work + 4);
-            } else {
-                hipLaunchKernelGGL((rotate_kernel<RB>), dim3(nxr, npairs), dim3(64 * ROT_WAVES), 0, s, Z, p, ld, r, nb,
-                                   rcur, fcur, 0, q, xw, work + 2);
             }
             if (timed) probe->end(PK_ROTATE, s);
             rprev = r;
@@ -1250,7 +1237,7 @@ JacobiResult run_jacobi(double* Z, int p, int q, int ld, double tol, int max_swe
         // confirm convergence: check all row pairs at once instead, with the
         // Gram of the current rows formed in the free data buffer (at most
         // two checks per split)
-        if (fused && p <= q && soff < 1e-6 && checks < 2) {
+        if (p <= q && soff < 1e-6 && checks < 2) {
             ++checks;
             const bool odd = g & 1;                    // the rows are in Xb when odd
             const double* X = odd ? Xb : Z;
@@ -1288,7 +1275,7 @@ JacobiResult run_jacobi(double* Z, int p, int q, int ld, double tol, int max_swe
         if (sw >= 3 && soff > 0.5 * prev && soff < 1e3 * tol) break;
         prev = soff;
     }
-    if (fused && (g & 1)) {
+    if (g & 1) {
         // the final data rows are in Xb
         const long total = (long)p * q;
         hipLaunchKernelGGL(copy_cols_kernel, dim3((int)std::min<long>(4096, (total + 255) / 256)), dim3(256), 0, s, Xb,
@@ -1333,8 +1320,7 @@ JacobiResult run_jacobi(double* Z, int p, int q, int ld, double tol, int max_swe
 }  // namespace
 
 void jacobi_workspace(int p, int q, size_t* gram, size_t* rot, size_t* off) {
-    if (block_rows(p) == 32) ws_sizes<32>(p, q, gram, rot, off);
-    else ws_sizes<16>(p, q, gram, rot, off);
+    ws_sizes<32>(p, q, gram, rot, off);
 }
 
 JacobiResult jacobi_rows(double* Z, int p, int q, int ld, double tol, int max_sweeps, double* gram_ws,
@@ -1366,9 +1352,7 @@ JacobiResult jacobi_rows(double* Z, int p, int q, int ld, double tol, int max_sw
         }
         return res;
     }
-    if (block_rows(p) == 32)
-        return run_jacobi<32>(Z, p, q, ld, tol, max_sweeps, gram_ws, rot_ws, off_ws, host_off, s, probe);
-    return run_jacobi<16>(Z, p, q, ld, tol, max_sweeps, gram_ws, rot_ws, off_ws, host_off, s, probe);
+    return run_jacobi<32>(Z, p, q, ld, tol, max_sweeps, gram_ws, rot_ws, off_ws, host_off, s, probe);
 }
 
 void row_norms(const double* Z, int p, int q, int ld, double* norms, hipStream_t s) {
