@@ -2,18 +2,24 @@
 // sweep in lockstep, block slot by block slot, and the fixed-budget GMRES
 // local solves of a slot run together -- one grouped launch per product
 // stage (the uneven-bond-dimension H_eff products of all states), one
-// batched launch per Krylov vector operation -- captured once as a HIP
-// graph and replayed while the batch keeps its size and budget (the kernels
-// read every shape and address from descriptors in device memory).  The
+// batched launch per Krylov vector operation -- captured as a HIP graph per
+// batch size, budget and precision (the last few kept per context) and
+// replayed (the kernels read every shape and address from descriptors in
+// device memory); a capture that a call on another thread invalidates is
+// issued directly instead.  The
 // tile size of each product is picked per GEMM shape by a small autotuner;
 // both tile sizes give the same bits, and every per-state reduction has the
 // single-state partition and order, so a state's step does not depend on the
-// batch it runs in.
+// batch it runs in.  FP32 refinement with a fixed number of corrections runs
+// the same sequence with one cycle per correction: the residual product in
+// FP64, the Arnoldi products with FP32 operands (grouped FP32 launches and the
+// FP32 MPO stage), the Krylov basis and its reductions in FP64.
 #include "engine.h"
 
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <exception>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -90,21 +96,27 @@ namespace {
 // The products of one batch: for product p (0: the residual's product with
 // x, k + 1: the Arnoldi product with V_k) and each of the two GEMMs, the
 // descriptors by tile size; counts[p][gemm][tile] = {problems, tiles}.
+// With FP32 products (lo): for product p >= 1 and each GEMM one more
+// descriptor set (128 tiles), counts_lo[p][gemm] = {problems, tiles}.
 struct BatchLayout {
-    size_t vec_off = 0, tot_off = 0, desc_off = 0, cnt_off = 0, bytes = 0;
+    size_t vec_off = 0, tot_off = 0, desc_off = 0, cnt_off = 0, dlo_off = 0, clo_off = 0, bytes = 0;
     int G = 0, np = 0;
+    bool lo = false;
 };
 
-BatchLayout layout(int G, int np) {
+BatchLayout layout(int G, int np, bool lo) {
     BatchLayout l;
     l.G = G;
     l.np = np;
+    l.lo = lo;
     auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
     l.vec_off = 0;
     l.tot_off = al(sizeof(BatchVec) * G);
     l.desc_off = al(l.tot_off + sizeof(int) * BT_N);
     l.cnt_off = al(l.desc_off + grouped_desc_bytes() * (size_t)np * 4 * G);
-    l.bytes = al(l.cnt_off + sizeof(int) * 2 * (size_t)np * 4);
+    l.dlo_off = al(l.cnt_off + sizeof(int) * 2 * (size_t)np * 4);
+    l.clo_off = al(l.dlo_off + (lo ? grouped_desc_bytes() * (size_t)np * 2 * G : 0));
+    l.bytes = al(l.clo_off + sizeof(int) * 2 * (size_t)np * 2);
     return l;
 }
 
@@ -115,6 +127,18 @@ void issue(char* dev, const BatchLayout& l, int mm, int max_cycles, hipStream_t 
     const int* tot = reinterpret_cast<const int*>(dev + l.tot_off);
     const int G = l.G;
     auto product = [&](int p) {
+        if (l.lo && p > 0) {
+            // FP32 operands: the vector rounded, L_lo x, the FP32 stage, x3 R_lo^T
+            batch_vec(d, G, tot, 6, p - 1, s);
+            for (int gm = 0; gm < 2; ++gm) {
+                const int q = p * 2 + gm;
+                const void* desc = dev + l.dlo_off + grouped_desc_bytes() * (size_t)q * G;
+                const int* cnt = reinterpret_cast<const int*>(dev + l.clo_off) + 2 * q;
+                gemm_grouped_f32(desc, cnt, false, gm == 1, 512, s);
+                if (gm == 0) batch_stage_lo(d, G, tot, s);
+            }
+            return;
+        }
         for (int gm = 0; gm < 2; ++gm) {
             for (int t = 0; t < 2; ++t) {
                 const int q = (p * 2 + gm) * 2 + t;
@@ -147,18 +171,28 @@ void issue(char* dev, const BatchLayout& l, int mm, int max_cycles, hipStream_t 
             batch_finish(d, G, k, 1, 2, s);
             if (k + 1 < mm) batch_vec(d, G, tot, 2, k, s);
         }
-        batch_hess(d, G, mm, true, cyc + 1 == max_cycles, s);
+        // mixed precision: the budget is the number of corrections, not a
+        // GMRES budget, so its end sets no flag
+        batch_hess(d, G, mm, true, !l.lo && cyc + 1 == max_cycles, s);
         batch_vec(d, G, tot, 5, mm, s);          // x += V y
     }
 }
 
 }  // namespace
 
-void gmres_batch(ite_ctx* c, const std::vector<BatchItem>& items, int m, int max_cycles) {
+void gmres_batch(ite_ctx* c, const std::vector<BatchItem>& items, int m, int max_cycles, bool lo) {
     const int G = (int)items.size();
     if (G == 0) return;
     const int mm = m;
     ITE_REQUIRE(mm >= 1 && mm <= 16, "gmres_batch: Krylov dimension must be in 1..16");
+    // FP32 buffers of a problem, in doubles: rounded L and R, the rounded
+    // vector, the FP32 intermediates
+    auto lo_doubles = [&](const LocalOp& op, size_t n, size_t nxi) -> size_t {
+        if (!lo) return 0;
+        const size_t nl = (size_t)op.s.Dxl * op.s.w0 * op.s.Dyl, nr = (size_t)op.s.Dxr * op.s.w2 * op.s.Dyr;
+        auto h = [](size_t nf) { return ((nf + 1) / 2 + 31) & ~size_t(31); };
+        return h(nl) + h(nr) + h(n) + 2 * h(nxi);
+    };
     // workspaces, carved from one slot
     auto al = [](size_t x) { return (x + 31) & ~size_t(31); };
     std::vector<size_t> off(G);
@@ -172,11 +206,11 @@ void gmres_batch(ite_ctx* c, const std::vector<BatchItem>& items, int m, int max
         const size_t nxi = (size_t)op.s.Dxl * std::max(I, O) * op.s.Dyr;
         off[g] = total;
         total += al((size_t)(mm + 1) * n) + al(n) + 2 * al(nxi) + al((size_t)reduce_blocks(n) * 64 + 64) +
-                 al((size_t)mm * HESS_HC + 8) + al(64);
+                 al((size_t)mm * HESS_HC + 8) + al(64) + lo_doubles(op, n, nxi);
     }
     double* ws = slot_t<double>(c, SL_BATCH, total);
     const int np = mm + 1;
-    const BatchLayout lay = layout(G, np);
+    const BatchLayout lay = layout(G, np, lo);
     char* dev = static_cast<char*>(slot(c, SL_BDESC, lay.bytes));
     std::vector<char>& host = c->batch_host;
     host.assign(lay.bytes, 0);
@@ -184,6 +218,7 @@ void gmres_batch(ite_ctx* c, const std::vector<BatchItem>& items, int m, int max
     int* htot = reinterpret_cast<int*>(host.data() + lay.tot_off);
     int* hcnt = reinterpret_cast<int*>(host.data() + lay.cnt_off);
     std::vector<double*> X1(G), X3(G);
+    std::vector<float*> Llo(G), Rlo(G), X1lo(G), X3lo(G);
     int red = 0, ew = 0, stg = 0;
     for (int g = 0; g < G; ++g) {
         const LocalOp& op = items[g].op;
@@ -209,6 +244,23 @@ void gmres_batch(ite_ctx* c, const std::vector<BatchItem>& items, int m, int max
         v.hd = q;
         q += al((size_t)mm * HESS_HC + 8);
         v.y = q;
+        q += al(64);
+        if (lo) {
+            auto take = [&](size_t nf) {
+                float* f = reinterpret_cast<float*>(q);
+                q += ((nf + 1) / 2 + 31) & ~size_t(31);
+                return f;
+            };
+            const size_t nl = (size_t)op.s.Dxl * op.s.w0 * op.s.Dyl, nr = (size_t)op.s.Dxr * op.s.w2 * op.s.Dyr;
+            Llo[g] = take(nl);
+            Rlo[g] = take(nr);
+            v.tlo = take(n);
+            X1lo[g] = take(nxi);
+            X3lo[g] = take(nxi);
+            // the environments rounded once per solve, ordered before it
+            convert_f32(op.L, Llo[g], nl, c->stream);
+            convert_f32(op.R, Rlo[g], nr, c->stream);
+        }
         v.x = items[g].x;
         v.b = items[g].b;
         v.stats = items[g].stats;
@@ -226,6 +278,15 @@ void gmres_batch(ite_ctx* c, const std::vector<BatchItem>& items, int m, int max
         st.rowptr = op.ww->rowptr;
         st.col = op.ww->col;
         st.val = op.ww->val;
+        if (lo) {
+            Stage& sl = v.st_lo;
+            sl = st;
+            sl.in = nullptr;
+            sl.in_f32 = X1lo[g];
+            sl.out = nullptr;
+            sl.out_prec = 1;
+            sl.out_lo = X3lo[g];
+        }
         v.red_start = red;
         v.ew_start = ew;
         v.stage_start = stg;
@@ -295,8 +356,37 @@ void gmres_batch(ite_ctx* c, const std::vector<BatchItem>& items, int m, int max
                 hcnt[2 * q + 1] = tiles;
             }
     }
+    if (lo) {
+        // FP32 products p >= 1: L_lo tlo -> X1lo (FP32), X3lo R_lo^T + (1 - h s) V_(p-1) -> w
+        int* hclo = reinterpret_cast<int*>(host.data() + lay.clo_off);
+        for (int p = 1; p < np; ++p)
+            for (int gm = 0; gm < 2; ++gm) {
+                const int q = p * 2 + gm;
+                char* desc = host.data() + lay.dlo_off + grouped_desc_bytes() * (size_t)q * G;
+                int tiles = 0;
+                for (int g = 0; g < G; ++g) {
+                    Gemm e = gm == 0 ? g1[g] : g2[g];
+                    if (gm == 0) {
+                        e.A = Llo[g];
+                        e.B = hv[g].tlo;
+                        e.D = nullptr;
+                        e.Df = X1lo[g];
+                    } else {
+                        e.A = X3lo[g];
+                        e.B = Rlo[g];
+                        e.C = hv[g].V + (size_t)(p - 1) * hv[g].n;
+                        e.D = hv[g].w;
+                    }
+                    grouped_desc_fill(e, 128, tiles, desc + grouped_desc_bytes() * g);
+                    tiles += grouped_tiles(e, 128);
+                }
+                hclo[2 * q] = G;
+                hclo[2 * q + 1] = tiles;
+            }
+    }
     // upload (ordered before the solve on the context's stream), then run the
-    // sequence on the private stream, captured once per batch size and budget
+    // sequence on the private stream, captured once per batch size, budget and
+    // precision
     HIP_CHECK(hipMemcpyAsync(dev, host.data(), lay.bytes, hipMemcpyHostToDevice, c->stream));
     c->batch_solves++;
     if (!c->use_graphs) {
@@ -308,34 +398,58 @@ void gmres_batch(ite_ctx* c, const std::vector<BatchItem>& items, int m, int max
         HIP_CHECK(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
         HIP_CHECK(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
     }
-    const long long key[5] = {G, mm, max_cycles, (long long)(uintptr_t)dev, (long long)lay.bytes};
-    if (!c->bgraph || std::memcmp(key, c->bgraph_key, sizeof(key)) != 0) {
-        if (c->bgraph) {
+    const long long key[5] = {G, mm + (lo ? 1000 : 0), max_cycles, (long long)(uintptr_t)dev, (long long)lay.bytes};
+    auto& cache = c->bgraphs;
+    auto hit = std::find_if(cache.begin(), cache.end(),
+                            [&](const ite_ctx::BatchGraph& e) { return std::memcmp(key, e.key, sizeof(key)) == 0; });
+    hipGraphExec_t exec = nullptr;
+    if (hit != cache.end()) {
+        ite_ctx::BatchGraph e = *hit;   // most recently used to the back
+        cache.erase(hit);
+        cache.push_back(e);
+        exec = e.exec;
+    } else {
+        if ((int)cache.size() >= BGRAPH_CACHE) {
             HIP_CHECK(hipStreamSynchronize(c->side));
-            HIP_CHECK(hipGraphExecDestroy(c->bgraph));
-            c->bgraph = nullptr;
+            HIP_CHECK(hipGraphExecDestroy(cache.front().exec));
+            cache.erase(cache.begin());
         }
         hipGraph_t graph = nullptr;
         HIP_CHECK(hipStreamBeginCapture(c->side, hipStreamCaptureModeThreadLocal));
+        std::exception_ptr failed;
         try {
             issue(dev, lay, mm, max_cycles, c->side);
         } catch (...) {
-            (void)hipStreamEndCapture(c->side, &graph);
-            if (graph) (void)hipGraphDestroy(graph);
-            throw;
+            failed = std::current_exception();
         }
-        HIP_CHECK(hipStreamEndCapture(c->side, &graph));
-        hipGraphExec_t exec = nullptr;
+        const hipError_t ec = hipStreamEndCapture(c->side, &graph);
+        if (ec == hipErrorStreamCaptureInvalidated || ec == hipErrorStreamCaptureUnsupported) {
+            // a call elsewhere in the process that a capture does not allow
+            // ended it: nothing captured ran, so the same sequence is issued
+            // directly
+            if (graph) (void)hipGraphDestroy(graph);
+            (void)hipGetLastError();
+            c->graph_fallbacks++;
+            issue(dev, lay, mm, max_cycles, c->stream);
+            return;
+        }
+        if (failed) {
+            if (graph) (void)hipGraphDestroy(graph);
+            std::rethrow_exception(failed);
+        }
+        HIP_CHECK(ec);
         const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         HIP_CHECK(e);
-        c->bgraph = exec;
-        std::memcpy(c->bgraph_key, key, sizeof(key));
+        ite_ctx::BatchGraph ent;
+        std::memcpy(ent.key, key, sizeof(key));
+        ent.exec = exec;
+        cache.push_back(ent);
         c->graph_captures++;
     }
     HIP_CHECK(hipEventRecord(c->ev_in, c->stream));
     HIP_CHECK(hipStreamWaitEvent(c->side, c->ev_in, 0));
-    HIP_CHECK(hipGraphLaunch(c->bgraph, c->side));
+    HIP_CHECK(hipGraphLaunch(exec, c->side));
     HIP_CHECK(hipEventRecord(c->ev_out, c->side));
     HIP_CHECK(hipStreamWaitEvent(c->stream, c->ev_out, 0));
     c->graph_replays++;

@@ -148,7 +148,7 @@ int ite_ctx_destroy(ite_ctx* c) {
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     if (c->side) (void)hipStreamSynchronize(c->side);
-    if (c->bgraph) (void)hipGraphExecDestroy(c->bgraph);
+    for (auto& g : c->bgraphs) (void)hipGraphExecDestroy(g.exec);
     if (c->ev_in) (void)hipEventDestroy(c->ev_in);
     if (c->ev_out) (void)hipEventDestroy(c->ev_out);
     if (c->side) (void)hipStreamDestroy(c->side);

@@ -21,6 +21,7 @@
 #include <map>
 #include <memory>
 #include <numeric>
+#include <tuple>
 
 namespace ite {
 
@@ -448,11 +449,17 @@ SplitResult split(ite_ctx* c, int dir, int Dl, int d1, int d2, int Dr, const dou
 // ---------------------------------------------------------------------------
 
 // SolveStats of a device record (see hess_solve): [0] residual, [1] products,
-// [2] flags.
-static SolveStats stats_from(const double* rec, bool low) {
+// [2] flags, [4] the residual products among them.  low: every product with
+// low-precision operands; mixed: the residual products FP64, the others low.
+static SolveStats stats_from(const double* rec, bool low, bool mixed = false) {
     SolveStats st;
     st.res_rel = rec[0];
-    (low ? st.matvecs_lo : st.matvecs64) = (int)rec[1];
+    if (mixed) {
+        st.matvecs64 = (int)rec[4];
+        st.matvecs_lo = (int)rec[1] - (int)rec[4];
+    } else {
+        (low ? st.matvecs_lo : st.matvecs64) = (int)rec[1];
+    }
     st.flags = (int)rec[2];
     return st;
 }
@@ -1129,15 +1136,22 @@ struct StepRun {
         slot_block(slot, i, dir);
         return (size_t)psi->XD[i] * psi->d[i] * psi->d[i + 1] * psi->XD[i + 2];
     }
-    // A local solve the batched GMRES takes: FP64, fixed budget, Krylov
-    // dimension below the vector length and at most 16.
+    // A local solve the batched GMRES takes: fixed budget, Krylov dimension
+    // below the vector length and at most 16; FP64, or FP32 refinement with a
+    // fixed number of corrections of one GMRES cycle each (the batch then
+    // runs one cycle per correction).
     bool batchable(int slot) const {
         int i, dir;
         slot_block(slot, i, dir);
         const int I = H->w[i] * psi->d[i] * psi->d[i + 1];
-        return o.precision == ITE_PREC_FP64 && o.tol_loc <= 0.0 && o.krylov_dim <= 16 &&
-               (size_t)o.krylov_dim < block_n(slot) && I <= BATCH_STAGE_SC;
+        const bool prec_ok = o.precision == ITE_PREC_FP64 ||
+                             (o.precision == ITE_PREC_FP32_IR && o.tol_refine <= 0.0 && o.max_cycles == 1);
+        return prec_ok && o.tol_loc <= 0.0 && o.krylov_dim <= 16 && (size_t)o.krylov_dim < block_n(slot) &&
+               I <= BATCH_STAGE_SC;
     }
+    // The batch's cycles and precision for a batchable solve.
+    bool batch_lo() const { return o.precision != ITE_PREC_FP64; }
+    int batch_cycles() const { return batch_lo() ? refine : o.max_cycles; }
 
     // b and the initial guess of the slot's block into bv and thv (length
     // block_n); sets op.
@@ -1255,7 +1269,7 @@ struct StepRun {
     bool any_deferred() const { return std::find(deferred.begin(), deferred.end(), 1) != deferred.end(); }
     void add_deferred(const double* host) {
         for (int k = 0; k < nblocks; ++k)
-            if (deferred[k]) add(stats_from(host + (size_t)8 * k, false));
+            if (deferred[k]) add(stats_from(host + (size_t)8 * k, false, batch_lo()));
     }
 
     // Normalise the centre, measure, psi <- x.  Throws ENONFINITE (psi
@@ -1399,15 +1413,15 @@ void step_batch(int n, ite_mps* const* psi, const ite_mpo* const* H, const doubl
         runs[j].reset(new StepRun(psi[j], H[j], h[j], *opts[j], sbase + soff[j]));
         maxslots = std::max(maxslots, runs[j]->nblocks);
     }
-    // batches by budget (Krylov dimension and cycles)
+    // batches by budget (Krylov dimension, cycles) and precision
     for (int slot = 0; slot < maxslots; ++slot) {
-        std::map<std::pair<int, int>, std::vector<int>> groups;
+        std::map<std::tuple<int, int, bool>, std::vector<int>> groups;
         for (int j = 0; j < n; ++j) {
             StepRun& r = *runs[j];
             if (slot >= r.nblocks) continue;
             double* bv = bbase + boff[j];
             r.rhs(slot, bv, bv + bmax[j]);
-            if (r.batchable(slot)) groups[{r.o.krylov_dim, r.o.max_cycles}].push_back(j);
+            if (r.batchable(slot)) groups[std::make_tuple(r.o.krylov_dim, r.batch_cycles(), r.batch_lo())].push_back(j);
             else r.solve();
         }
         for (auto& grp : groups) {
@@ -1419,7 +1433,7 @@ void step_batch(int n, ite_mps* const* psi, const ite_mpo* const* H, const doubl
                 r.deferred[slot] = 1;
                 spans.push_back(r.tm.open(PH_SOLVE));
             }
-            gmres_batch(c, items, grp.first.first, grp.first.second);
+            gmres_batch(c, items, std::get<0>(grp.first), std::get<1>(grp.first), std::get<2>(grp.first));
             for (size_t q = 0; q < grp.second.size(); ++q) runs[grp.second[q]]->tm.close(spans[q]);
         }
         for (int j = 0; j < n; ++j)

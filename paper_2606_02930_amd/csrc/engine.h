@@ -59,9 +59,16 @@ struct ite_ctx {
     bool use_graphs = true;
     hipStream_t side = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
-    hipGraphExec_t bgraph = nullptr;
-    long long bgraph_key[5] = {};
+    // captured batched solves, keyed by (batch size, Krylov dimension and
+    // precision, cycles, descriptor address, layout bytes); least recently
+    // used first, at most BGRAPH_CACHE
+    struct BatchGraph {
+        long long key[5];
+        hipGraphExec_t exec;
+    };
+    std::vector<BatchGraph> bgraphs;
     long long graph_captures = 0, graph_replays = 0, batch_solves = 0;
+    long long graph_fallbacks = 0;   // batched solves issued directly after a capture was invalidated
     std::vector<char> batch_host;   // host image of the batch descriptors (kept until the next batch)
     int gemm_slots = 0;             // concurrent GEMM workgroups (two per compute unit), queried once
 };
@@ -204,8 +211,10 @@ struct BatchItem {
 // Fixed-budget FP64 GMRES(m) of every item at once (grouped products and
 // batched vector kernels, captured as a graph when the context allows):
 // item by item the same arithmetic as local_solve with a device record.
-// Every item needs m < n, m <= 16 and at most 128 MPO-stage inputs.
-void gmres_batch(ite_ctx* c, const std::vector<BatchItem>& items, int m, int max_cycles);
+// Every item needs m < n, m <= 16 and at most 128 MPO-stage inputs.  lo:
+// FP32 refinement, max_cycles corrections of one cycle each (the Arnoldi
+// products with FP32 operands; the residual product and the basis FP64).
+void gmres_batch(ite_ctx* c, const std::vector<BatchItem>& items, int m, int max_cycles, bool lo = false);
 // Tile size (128 or 64) the autotuner picked for an FP64 GEMM shape.
 int tuned_tile(ite_ctx* c, const Gemm& g);
 // One implicit step of every state (ite_step_batch); status[j] gets each

@@ -314,19 +314,19 @@ struct GroupDesc {
     int tile_start;
 };
 
-template <bool TA, bool TB, int BS>
+template <typename T, bool TA, bool TB, int BS>
 __global__ __launch_bounds__(NTHREADS, 2) void gemm_grouped_kernel(const GroupDesc* __restrict__ desc,
                                                                    const int* __restrict__ count) {
-    constexpr int LDK = MfmaOp<double>::LDK;
-    __shared__ double As[2 * BS * LDK];
-    __shared__ double Bs[2 * BS * LDK];
+    constexpr int LDK = MfmaOp<T>::LDK;
+    __shared__ __attribute__((aligned(16))) T As[2 * BS * LDK];
+    __shared__ __attribute__((aligned(16))) T Bs[2 * BS * LDK];
     const int G = count[0], ntiles = count[1];
     int g = 0;
     for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         while (g + 1 < G && desc[g + 1].tile_start <= tile) ++g;
         const Params& p = desc[g].p;
         const int lt = tile - desc[g].tile_start;
-        gemm_tile<double, TA, TB, BS>(p, (lt / p.nt) * BS, (lt % p.nt) * BS, 0, As, Bs);
+        gemm_tile<T, TA, TB, BS>(p, (lt / p.nt) * BS, (lt % p.nt) * BS, 0, As, Bs);
     }
 }
 
@@ -636,6 +636,7 @@ void grouped_desc_fill(const Gemm& g, int bs, int tile_start, void* out) {
     p.B = g.B; p.ldb = g.ldb; p.sB = 0;
     p.C = g.C; p.ldc = g.ldc; p.sC = 0;
     p.D = g.D; p.ldd = g.ldd; p.sD = 0;
+    p.Df = g.Df;
     p.mt = g.M > 0 ? (g.M + bs - 1) / bs : 0;
     p.nt = g.N > 0 ? (g.N + bs - 1) / bs : 0;
     d.tile_start = tile_start;
@@ -647,11 +648,22 @@ int grouped_tiles(const Gemm& g, int bs) {
     return ((g.M + bs - 1) / bs) * ((g.N + bs - 1) / bs);
 }
 
+void gemm_grouped_f32(const void* desc, const int* count, bool tA, bool tB, int grid, hipStream_t s) {
+    const auto* d = static_cast<const GroupDesc*>(desc);
+    if (!tA && !tB)
+        hipLaunchKernelGGL((gemm_grouped_kernel<float, false, false, 128>), dim3(grid), dim3(NTHREADS), 0, s, d, count);
+    else if (!tA && tB)
+        hipLaunchKernelGGL((gemm_grouped_kernel<float, false, true, 128>), dim3(grid), dim3(NTHREADS), 0, s, d, count);
+    else
+        ITE_FAIL(ITE_EINVAL, "gemm_grouped_f32: transposed A is not supported");
+    HIP_CHECK(hipGetLastError());
+}
+
 void gemm_grouped_f64(const void* desc, const int* count, bool tA, bool tB, int bs, int grid, hipStream_t s) {
     if (bs != 128 && bs != 64) ITE_FAIL(ITE_EINVAL, "gemm_grouped: tile must be 128 or 64");
     const auto* d = static_cast<const GroupDesc*>(desc);
 #define ITE_GG(TA, TB, BS) \
-    hipLaunchKernelGGL((gemm_grouped_kernel<TA, TB, BS>), dim3(grid), dim3(NTHREADS), 0, s, d, count)
+    hipLaunchKernelGGL((gemm_grouped_kernel<double, TA, TB, BS>), dim3(grid), dim3(NTHREADS), 0, s, d, count)
     if (bs == 128) {
         if (!tA && !tB) ITE_GG(false, false, 128);
         else if (!tA && tB) ITE_GG(false, true, 128);

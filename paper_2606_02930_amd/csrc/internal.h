@@ -7,6 +7,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <cstring>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -23,12 +24,18 @@ struct Error : std::runtime_error {
 #define ITE_FAIL(code, msg) throw ::ite::Error((code), (msg))
 #define ITE_REQUIRE(cond, msg) \
     do { if (!(cond)) throw ::ite::Error(ITE_EINVAL, (msg)); } while (0)
+// "file:line" of a failed call (the file's base name)
+inline std::string src_loc(const char* file, int line) {
+    const char* b = std::strrchr(file, '/');
+    return std::string(b ? b + 1 : file) + ":" + std::to_string(line);
+}
 #define HIP_CHECK(expr)                                                                 \
     do {                                                                                \
         hipError_t e_ = (expr);                                                         \
         if (e_ != hipSuccess)                                                           \
-            throw ::ite::Error(ITE_EDEVICE, std::string(#expr) + " failed: " +         \
-                                                hipGetErrorString(e_));                 \
+            throw ::ite::Error(ITE_EDEVICE, std::string(#expr) + " failed (" +         \
+                                                ::ite::src_loc(__FILE__, __LINE__) +    \
+                                                "): " + hipGetErrorString(e_));         \
     } while (0)
 
 // ---------------------------------------------------------------------------
@@ -71,6 +78,9 @@ size_t grouped_desc_bytes();
 void grouped_desc_fill(const Gemm& g, int bs, int tile_start, void* out);
 int grouped_tiles(const Gemm& g, int bs);
 void gemm_grouped_f64(const void* desc, const int* count, bool tA, bool tB, int bs, int grid, hipStream_t s);
+// The same for FP32 operands (FP32 MFMA, FP32 accumulation; output FP32 into
+// Df or FP64 into D with alpha, beta, C), 128 x 128 tiles, A not transposed.
+void gemm_grouped_f32(const void* desc, const int* count, bool tA, bool tB, int grid, hipStream_t s);
 // FP32 operands (A, B are float*), FP32 MFMA, FP32 accumulation, FP64 output.
 void gemm_f32(const Gemm& g, hipStream_t s);
 // BF16 operands (A, B are uint16 bf16 bit patterns), BF16 MFMA, FP32
@@ -178,11 +188,17 @@ struct BatchVec {
     double* y;              // combination coefficients (mm)
     double* stats;          // the solve's record (hess_solve)
     Stage st;               // MPO stage of the operator (X1 -> X3)
+    // FP32 products (the refinement corrections of mixed precision): the
+    // vector the product is applied to, rounded (n floats), and the stage
+    // from FP32 X1 to FP32 X3
+    float* tlo;
+    Stage st_lo;
     int red_start, ew_start, stage_start;   // first unit of this problem in each unit range
 };
 // Unit totals of a batch (device ints): reductions, elementwise, stage.
 enum { BT_RED = 0, BT_EW = 1, BT_STAGE = 2, BT_N = 4 };
 constexpr int BATCH_GRID = 1024;      // workgroups of every batched vector launch
+constexpr int BGRAPH_CACHE = 4;       // captured batched solves kept per context
 constexpr long BATCH_EW = 4096;       // elements per elementwise unit
 // Reductions: mode 0 V_j . w (j < k1; large problems), 1 w . w (large),
 // 2 V_0 . V_0, 3 b . b (all problems).
@@ -192,7 +208,8 @@ void batch_reduce(const BatchVec* d, int G, const int* tot, int mode, int k1, hi
 void batch_finish(const BatchVec* d, int G, int k, int k1, int target, hipStream_t s);
 // Elementwise: 0 w -= sum_(j <= k) col_k[j] V_j, 1 the same with col_k[64 + j]
 // (large problems), 2 V_(k+1) = w / col_k[128] (large), 3 V_0 = b - V_0,
-// 4 V_0 /= ||r0||, 5 x += sum_(j < k) y_j V_j (all).
+// 4 V_0 /= ||r0||, 5 x += sum_(j < k) y_j V_j, 6 tlo = V_k rounded to FP32
+// (all).
 void batch_vec(const BatchVec* d, int G, const int* tot, int op, int k, hipStream_t s);
 // Both Gram-Schmidt passes of Arnoldi step k of the small problems.
 void batch_cgs2_small(const BatchVec* d, int G, int k, int mm, hipStream_t s);
@@ -202,6 +219,8 @@ void batch_hess(const BatchVec* d, int G, int mm, bool r_product, bool last_cycl
 void batch_zero_stats(const BatchVec* d, int G, hipStream_t s);
 // The MPO stage of every problem (inputs per column at most 128).
 void batch_stage(const BatchVec* d, int G, const int* tot, hipStream_t s);
+// The FP32 stage st_lo of every problem (FP32 in, FP32 out).
+void batch_stage_lo(const BatchVec* d, int G, const int* tot, hipStream_t s);
 constexpr int BATCH_STAGE_SC = 128;
 
 // Observability of kernel launches: every launch of a kind is counted, some

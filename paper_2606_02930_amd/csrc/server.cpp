@@ -154,6 +154,10 @@ void ite_server::finish(const std::shared_ptr<Req>& r, int wi, int status, int c
 
 void ite_server::worker(int wi) {
     ite_ctx* c = ctx[wi];
+    // this thread's allocations and copies (admissions) may overlap another
+    // worker's graph capture: they do not touch its stream
+    hipStreamCaptureMode relaxed = hipStreamCaptureModeRelaxed;
+    (void)hipThreadExchangeStreamCaptureMode(&relaxed);
     for (;;) {
         std::shared_ptr<Req> r;
         std::vector<std::shared_ptr<Req>> batch;

@@ -231,7 +231,10 @@ __device__ void hess_solve_one(const double* __restrict__ hd, int mm, double* __
         for (int i = 0; i < mm; ++i) y[i] = 0.0;
         return;
     }
-    if (r_product) stats[1] += 1.0;
+    if (r_product) {
+        stats[1] += 1.0;
+        stats[4] += 1.0;   // the residual products alone (FP64 even when the others are not)
+    }
     const double bnorm = hd[(size_t)mm * HESS_HC], beta = hd[(size_t)mm * HESS_HC + 1];
     stats[0] = bnorm > 0.0 ? beta / bnorm : 0.0;
     if (!(beta > 0.0)) {
@@ -1015,6 +1018,9 @@ __global__ __launch_bounds__(RT) void batch_vec_kernel(const BatchVec* __restric
             const double dd = p.hd[(size_t)k * HESS_HC + 1];
             const double inv = dd > 0.0 ? 1.0 / dd : 0.0;
             for (size_t i = i0 + threadIdx.x; i < i1; i += RT) p.V[i] = p.V[i] * inv;
+        } else if (op == 6) {
+            const double* vk = p.V + (size_t)k * p.n;
+            for (size_t i = i0 + threadIdx.x; i < i1; i += RT) p.tlo[i] = (float)vk[i];
         } else {
             for (size_t i = i0 + threadIdx.x; i < i1; i += RT) p.x[i] = gemv_elem(p.V, p.n, k, p.y, p.x[i], i, false);
         }
@@ -1044,16 +1050,18 @@ __global__ __launch_bounds__(64) void batch_hess_kernel(const BatchVec* __restri
     }
 }
 
+// LO: the FP32 stage st_lo (FP32 output) instead of st.
+template <bool LO>
 __global__ __launch_bounds__(BATCH_STAGE_SC) void batch_stage_kernel(const BatchVec* __restrict__ d, int G,
                                                                      const int* __restrict__ tot) {
     __shared__ double xin[BATCH_STAGE_SC * BATCH_STAGE_SC];
     const int total = tot[BT_STAGE];
     for (int u = blockIdx.x; u < total; u += gridDim.x) {
         const int g = unit_problem(u, G, [&](int q) { return d[q].stage_start; });
-        const Stage& st = d[g].st;
+        const Stage& st = LO ? d[g].st_lo : d[g].st;
         const int nc = (st.C + BATCH_STAGE_SC - 1) / BATCH_STAGE_SC;
         const int lu = u - d[g].stage_start;
-        stage_unit<0, BATCH_STAGE_SC>(st, lu / nc, lu % nc, xin);
+        stage_unit<LO ? 1 : 0, BATCH_STAGE_SC>(st, lu / nc, lu % nc, xin);
     }
 }
 
@@ -1115,7 +1123,13 @@ void batch_hess(const BatchVec* d, int G, int mm, bool r_product, bool last_cycl
 
 void batch_stage(const BatchVec* d, int G, const int* tot, hipStream_t s) {
     if (G <= 0) return;
-    hipLaunchKernelGGL(batch_stage_kernel, dim3(BATCH_GRID), dim3(BATCH_STAGE_SC), 0, s, d, G, tot);
+    hipLaunchKernelGGL(batch_stage_kernel<false>, dim3(BATCH_GRID), dim3(BATCH_STAGE_SC), 0, s, d, G, tot);
+    HIP_CHECK(hipGetLastError());
+}
+
+void batch_stage_lo(const BatchVec* d, int G, const int* tot, hipStream_t s) {
+    if (G <= 0) return;
+    hipLaunchKernelGGL(batch_stage_kernel<true>, dim3(BATCH_GRID), dim3(BATCH_STAGE_SC), 0, s, d, G, tot);
     HIP_CHECK(hipGetLastError());
 }
 

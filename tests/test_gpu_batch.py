@@ -7,7 +7,11 @@ local solves.
   stepped alone (a batch of one), with the graph and without it, and equal
   ite_imag_step's step to rounding (1e-12 relative energy).
 * Each state's energies match the oracle's evolution per step (1e-10
-  relative, paper budget).
+  relative, paper budget; 1e-8 for FP32 refinement).
+* FP32 refinement (fixed corrections, one GMRES cycle each) is batched too:
+  same product counts as the unbatched refinement and the same step to
+  rounding (its FP32 products are the same tiles with the same K order; the
+  correction is added to x in one pass instead of through a separate vector).
 * The graph is captured once per batch size and budget and then replayed.
 """
 import numpy as np
@@ -42,7 +46,7 @@ def _cases():
     return out
 
 
-def _run(ctx, cases, which, steps, batched=True, graphs=True):
+def _run(ctx, cases, which, steps, batched=True, graphs=True, refine=0):
     ite.ite_ctx_set_graphs(ctx, graphs)
     grid = ed.loggrid(0.01, 20.0, 1.3)[:steps + 1]
     psis, Hs, opts = [], [], []
@@ -50,7 +54,8 @@ def _run(ctx, cases, which, steps, batched=True, graphs=True):
         cs = cases[j]
         psis.append(ite.ite_mps_create(ctx, cs["sp"], cs["chi"]))
         Hs.append(ite.ite_mpo_load(ctx, cs["W"]))
-        opts.append(ite.ite_default_opts(chi_max=cs["chi"], cutoff=1e-10, precision=cs["prec"]))
+        opts.append(ite.ite_default_opts(chi_max=cs["chi"], cutoff=1e-10, precision=cs["prec"],
+                                         max_refine=refine if cs["prec"] else 0))
     reps = {j: [] for j in which}
     try:
         for k in range(1, len(grid)):
@@ -106,8 +111,10 @@ def test_batch_matches_single_steps_and_the_oracle(ctx):
     for j in allj:
         cs = cases[j]
         for a, b in zip(reps_s[j], reps_b[j]):
-            assert abs(a["energy"] - b["energy"]) <= 1e-12 * abs(a["energy"])
+            tol = 1e-12 if cs["prec"] == 0 else 1e-10
+            assert abs(a["energy"] - b["energy"]) <= tol * abs(a["energy"]), (j, a["energy"], b["energy"])
             assert a["max_chi"] == b["max_chi"]
+            assert (a["matvecs_fp64"], a["matvecs_lo"]) == (b["matvecs_fp64"], b["matvecs_lo"]), j
         o_out, o_reps = omps.evolve_grid(omps.product_state(cs["sp"]), cs["Wo"], grid,
                                          omps.StepOptions(chi_max=cs["chi"], cutoff=1e-10))
         bound = 1e-10 if cs["prec"] == 0 else 1e-8
@@ -134,3 +141,33 @@ def test_batch_argument_errors(ctx):
     finally:
         ite.ite_mps_destroy(p)
         ite.ite_mpo_destroy(H)
+
+
+def test_batch_fp32_refinement_two_corrections(ctx):
+    """FP32 refinement with two corrections: batched (with FP64 states in the
+    same slot) bitwise equal to the state alone, equal to the unbatched
+    refinement to rounding, and close to the oracle's evolution."""
+    cases = _cases()
+    cases.append(dict(W=hamiltonians.heisenberg(14), Wo=ompo.heisenberg_mpo(14), d=2,
+                      sp=random_spinors(rng_for(70, 11), 14, 2), chi=40, prec=1))
+    fp32 = [4, len(cases) - 1]
+    allj = [0, 1] + fp32
+    before = ite.ite_ctx_batch_stats(ctx)
+    reps_b, st_b = _run(ctx, cases, allj, 5, refine=2)
+    assert ite.ite_ctx_batch_stats(ctx)["solves"] > before["solves"]
+    reps_s, _ = _run(ctx, cases, fp32, 5, batched=False, refine=2)
+    grid = ed.loggrid(0.01, 20.0, 1.3)[:6]
+    for j in fp32:
+        reps_a, st_a = _run(ctx, cases, [j], 5, refine=2)
+        for a, b in zip(reps_a[j], reps_b[j]):
+            for k in KEYS:
+                assert a[k] == b[k], (j, k, a[k], b[k])
+        assert all(np.array_equal(x, y) for x, y in zip(st_a[j], st_b[j]))
+        for a, b in zip(reps_s[j], reps_b[j]):
+            assert abs(a["energy"] - b["energy"]) <= 1e-10 * abs(a["energy"]), (j, a["energy"], b["energy"])
+            assert (a["matvecs_fp64"], a["matvecs_lo"]) == (b["matvecs_fp64"], b["matvecs_lo"])
+        cs = cases[j]
+        _, o_reps = omps.evolve_grid(omps.product_state(cs["sp"]), cs["Wo"], grid,
+                                     omps.StepOptions(chi_max=cs["chi"], cutoff=1e-10))
+        for b, o in zip(reps_b[j], o_reps):
+            assert abs(b["energy"] - o.energy) <= 1e-8 * abs(o.energy)

@@ -67,8 +67,8 @@ def test_results_are_the_same_alone_and_in_the_mix():
         ids = [ite.ite_server_submit(srv, W, sp, chi, t0, t1, r, ite.ite_default_opts(**o))
                for (W, sp, chi, t0, t1, r, o) in reqs]
         infos = [ite.ite_server_wait(srv, i, 120.0) for i in ids]
-        for info in infos:
-            assert info["status"] == ite.REQ_DONE, info
+        for i, info in zip(ids, infos):
+            assert info["status"] == ite.REQ_DONE, (info, ite.ite_server_error(srv, i))
             assert info["n_steps"] == info["n_grid"]
         assert len({info["worker"] for info in infos}) > 1      # the work was spread over workers
         mixed = [(ite.ite_server_reports(srv, i), ite.ite_server_state(srv, i, [len(s) for s in q[1]]))
