@@ -261,21 +261,25 @@ int ite_imag_step(ite_mps* psi, const ite_mpo* H, double h,
 
 /* One implicit step (as ite_imag_step) of each of n independent states, run
  * as a batch: the sweeps advance in lockstep block by block, and the
- * fixed-budget FP64 GMRES local solves of a block slot run together -- one
+ * fixed-budget GMRES local solves of a block slot run together -- one
  * grouped launch per contraction stage for the H_eff products of all states
  * (uneven bond dimensions, tile size per GEMM shape from the library's
  * autotuner), one batched launch per Krylov vector operation, the small
- * least-squares solves on the device -- captured once as a HIP graph on a
+ * least-squares solves on the device -- captured as a HIP graph on a
  * private stream (ordered after ctx's stream) and replayed while the batch
- * keeps its size and budget.  Serving (Appendix D: many independent METTS
- * evolutions) advances its active requests this way.  Every state must be on
- * ctx; h[j] and opts[j] are state j's; reps (nullable) gets n reports,
- * status (nullable) each state's status (a failed state is left unchanged).
- * Local solves outside the batched kind (tolerance-driven, mixed precision,
- * Krylov dimension above 16 or not below the block's length, more than 128
- * MPO-stage inputs) run one by one within the same slots.  A state's result
- * is bitwise the same in any batch, alone included, and equals ite_imag_step's
- * to rounding.  Returns OK, or the first failing state's status, or EINVAL /
+ * keeps its size, budget and precision (the last four such graphs are kept;
+ * a capture that another thread's call invalidates is issued directly).
+ * FP64 solves and FP32 refinement with a fixed number of corrections
+ * (tol_refine = 0, max_cycles = 1: one cycle per correction, the Arnoldi
+ * products FP32) batch, each precision in its own group.  Serving
+ * (Appendix D: many independent METTS evolutions) advances its active
+ * requests this way.  Every state must be on ctx; h[j] and opts[j] are state
+ * j's; reps (nullable) gets n reports, status (nullable) each state's status
+ * (a failed state is left unchanged).  Local solves outside the batched kind
+ * (tolerance-driven, BF16 or tolerance-driven refinement, Krylov dimension
+ * above 16 or not below the block's length, more than 128 MPO-stage inputs)
+ * run one by one within the same slots.  A state's result is bitwise the
+ * same in any batch, alone included, and equals ite_imag_step's to rounding.  Returns OK, or the first failing state's status, or EINVAL /
  * ESTATE for bad arguments (nothing run). */
 int ite_step_batch(ite_ctx* ctx, int n, ite_mps* const* psi, const ite_mpo* const* H, const double* h,
                    const ite_step_opts* const* opts, ite_step_report* reps, int* status);
