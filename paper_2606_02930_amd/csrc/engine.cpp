@@ -148,20 +148,26 @@ struct CtxProbe final : LaunchProbe {
 
 }  // namespace
 
+// Concurrent workgroups of the GEMM kernels on the context's device (two per
+// compute unit).
+static int gemm_slots(ite_ctx* c) {
+    if (c->gemm_slots == 0) {
+        int cus = 0;
+        HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
+        c->gemm_slots = 2 * std::max(cus, 1);
+    }
+    return c->gemm_slots;
+}
+
 void gemm(ite_ctx* c, bool tA, bool tB, int M, int N, int K, double alpha, const double* A, long lda,
           const double* B, long ldb, double beta, const double* C, long ldc, double* D, long ldd) {
     Gemm g;
     g.M = M; g.N = N; g.K = K; g.tA = tA; g.tB = tB;
     g.alpha = alpha; g.beta = beta;
     g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc; g.D = D; g.ldd = ldd;
-    if (c->gemm_slots == 0) {
-        int cus = 0;
-        HIP_CHECK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device));
-        c->gemm_slots = 2 * std::max(cus, 1);
-    }
     // an output too small to fill the chip's workgroup slots but with a long
     // K: K parts as one batch, summed in a fixed order
-    const int parts = M > 0 && N > 0 ? splitk_parts(M, N, K, c->gemm_slots) : 1;
+    const int parts = M > 0 && N > 0 ? splitk_parts(M, N, K, gemm_slots(c)) : 1;
     double* work = parts > 1 ? slot_t<double>(c, SL_SPLITK, (size_t)parts * M * N) : nullptr;
     if (c->prof_on && M > 0 && N > 0) {
         CtxProbe pr(c);
@@ -211,8 +217,15 @@ static void gemm_lo(ite_ctx* c, Prec p, bool tA, bool tB, int M, int N, int K, d
     g.alpha = alpha; g.beta = beta;
     g.A = A; g.lda = lda; g.B = B; g.ldb = ldb; g.C = C; g.ldc = ldc; g.D = D; g.ldd = ldd;
     g.Df = Df;
-    if (p == Prec::F32) gemm_f32(g, c->stream);
-    else gemm_bf16(g, c->stream);
+    if (p == Prec::F32) {
+        // an FP64 output too small to fill the chip with a long K: K parts,
+        // as for the FP64 products
+        const int parts = !Df && M > 0 && N > 0 ? splitk_parts(M, N, K, gemm_slots(c)) : 1;
+        if (parts > 1) gemm_f32_splitk(g, parts, slot_t<double>(c, SL_SPLITK, (size_t)parts * M * N), c->stream);
+        else gemm_f32(g, c->stream);
+    } else {
+        gemm_bf16(g, c->stream);
+    }
 }
 
 void lo_shadows(ite_ctx* c, const HeffShape& s, Prec prec, const double* L, const double* R, const void** Llo,

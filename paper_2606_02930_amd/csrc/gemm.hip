@@ -591,9 +591,10 @@ int splitk_parts(int M, int N, int K, int slots) {
 }
 
 // The K parts of g (no C, alpha 1) as one batched launch: part k to
-// out + k part_stride with row stride ldo.
-static void gemm_f64_kparts(const Gemm& g, int parts, double* out, long ldo, long part_stride, hipStream_t s) {
-    if (g.batch != 1 || g.Df) ITE_FAIL(ITE_EINVAL, "gemm K parts: single FP64 problems only");
+// out + k part_stride (FP64) with row stride ldo.
+template <typename T>
+static void gemm_kparts(const Gemm& g, int parts, double* out, long ldo, long part_stride, hipStream_t s) {
+    if (g.batch != 1 || g.Df) ITE_FAIL(ITE_EINVAL, "gemm K parts: single problems with an FP64 output only");
     if (parts < 1 || g.K % parts != 0) ITE_FAIL(ITE_EINVAL, "gemm K parts: K must split evenly");
     const int kp = g.K / parts;
     Gemm h = g;
@@ -607,21 +608,25 @@ static void gemm_f64_kparts(const Gemm& g, int parts, double* out, long ldo, lon
     h.D = out;
     h.ldd = ldo;
     h.sD = part_stride;
-    launch<double>(h, s);
+    launch<T>(h, s);
 }
 
-void gemm_f64_splitk(const Gemm& g, int parts, double* work, hipStream_t s) {
+template <typename T>
+static void gemm_splitk(const Gemm& g, int parts, double* work, hipStream_t s) {
     if (parts <= 1) {
-        gemm_f64(g, s);
+        launch<T>(g, s);
         return;
     }
-    gemm_f64_kparts(g, parts, work, g.N, (long)g.M * g.N, s);
+    gemm_kparts<T>(g, parts, work, g.N, (long)g.M * g.N, s);
     const long n = (long)g.M * g.N;
     const int grid = (int)std::min<long>(4096, (n + 255) / 256);
     hipLaunchKernelGGL(splitk_sum_kernel, dim3(grid), dim3(256), 0, s, work, parts, g.M, g.N, g.alpha, g.C, g.ldc,
                        g.beta, g.D, g.ldd);
     HIP_CHECK(hipGetLastError());
 }
+
+void gemm_f64_splitk(const Gemm& g, int parts, double* work, hipStream_t s) { gemm_splitk<double>(g, parts, work, s); }
+void gemm_f32_splitk(const Gemm& g, int parts, double* work, hipStream_t s) { gemm_splitk<float>(g, parts, work, s); }
 
 size_t grouped_desc_bytes() { return sizeof(GroupDesc); }
 

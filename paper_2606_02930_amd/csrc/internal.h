@@ -61,13 +61,16 @@ struct Gemm {
 };
 // FP64 operands, FP64 MFMA.
 void gemm_f64(const Gemm& g, hipStream_t s);
-// Split-K for under-filled FP64 products: the number of K parts (1 = no
+// Split-K for under-filled products: the number of K parts (1 = no
 // split) when the 128 x 128 output tiles of M x N fill at most half of
 // `slots` concurrent workgroups and K is long; the parts (K / parts each, a
 // multiple of the K slice) run as one batched launch into `work`
 // (parts M N doubles) and are summed in a fixed order with alpha, beta, C.
 int splitk_parts(int M, int N, int K, int slots);
 void gemm_f64_splitk(const Gemm& g, int parts, double* work, hipStream_t s);
+// The same with FP32 operands (FP32 accumulation within a part, the parts
+// summed in FP64); FP64 output only.
+void gemm_f32_splitk(const Gemm& g, int parts, double* work, hipStream_t s);
 // Grouped FP64 GEMM: many problems (batch 1 each) in one persistent launch
 // of `grid` workgroups, with bs x bs output tiles (128 or 64; the same bits
 // either way).  The descriptors live in device memory (grouped_desc_bytes()

@@ -401,6 +401,30 @@ def test_heff_apply_low_precision(env, prec, bound, dims):
         assert rel_err(host(y), 0.3 * th - 0.25 * want) < bound
 
 
+@pytest.mark.parametrize("prec,bound", [(1, 1e-5), (2, 3e-2)])
+def test_heff_apply_low_precision_full_block_shape(env, prec, bound):
+    # the L=100, chi=1024 block in FP32 / BF16 operands: the second
+    # contraction (M=4096, N=1024, K=5120) fills half the GPU's workgroup
+    # slots, so the FP32 product runs it in two K parts summed in FP64.  For
+    # random operands the FP32 accumulation error grows like sqrt(K) 2^-24
+    # (K = 1024 and 2 x 2560 here: about 6e-6 for both contractions together)
+    torch, ctx = env
+    D = 1024
+    g = torch.Generator(device="cuda").manual_seed(4321)
+    Lm = torch.randn((D, 5, D), dtype=torch.float64, device="cuda", generator=g)
+    Rm = torch.randn((D, 5, D), dtype=torch.float64, device="cuda", generator=g)
+    th = torch.randn((D, 2, 2, D), dtype=torch.float64, device="cuda", generator=g)
+    W = ompo.heisenberg_mpo(4)
+    y = torch.zeros_like(th)
+    ite.ite_debug_heff_apply(ctx, Lm, W[1], W[2], Rm, th, 0.5, 2.0, y, prec=prec)
+    want = 0.5 * host(th) + 2.0 * omps.heff_apply(host(Lm), W[1], W[2], host(Rm), host(th))
+    err = rel_err(host(y), want)
+    assert 0.0 < err < bound
+    y2 = torch.zeros_like(y)
+    ite.ite_debug_heff_time(ctx, Lm, W[1], W[2], Rm, th, 0.5, 2.0, y2, prec=prec, reps=1)
+    assert torch.equal(y2, y)
+
+
 @pytest.mark.parametrize("prec", [1, 2])
 def test_local_solve_refinement_reaches_fp64(env, prec):
     # mixed precision refinement: FP64 residuals, low-precision GMRES
