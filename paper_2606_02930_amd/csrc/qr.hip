@@ -105,7 +105,7 @@ __global__ __launch_bounds__(64 * QPW) void qr_panel_kernel(double* __restrict__
                                                             double* __restrict__ VT, double* __restrict__ T) {
     constexpr int NT = 64 * QPW;
     __shared__ double Pc[QCH][QB + 1];
-    __shared__ double vs[64 * QRPL];
+    __shared__ double vs[2][64 * QRPL];   // reflectors j (buffer j mod 2)
     __shared__ double tau_s[QB];
     __shared__ double S[QB][QB + 1];
     __shared__ double Ts[QB][QB + 1];
@@ -140,21 +140,29 @@ __global__ __launch_bounds__(64 * QPW) void qr_panel_kernel(double* __restrict__
         }
         __syncthreads();
     }
+    // Look-ahead: after applying reflector j to its columns, the owner of
+    // column j + 1 forms reflector j + 1 into the other buffer before the
+    // barrier, so one barrier per column separates the reflectors (each
+    // column still sees the reflectors in order: the same arithmetic as
+    // without look-ahead).
+    if (nbw > 0 && w == 0) qr_reflector(a0, 0, lane, vs[0], tau_s, S);
+    __syncthreads();
     for (int j = 0; j < nbw; ++j) {
-        if (w == (j & (QPW - 1))) {
-            if (j < QPW)
-                qr_reflector(a0, j, lane, vs, tau_s, S);
-            else
-                qr_reflector(a1, j, lane, vs, tau_s, S);
-        }
-        __syncthreads();
-        for (int row = t; row < m; row += NT) VT[(long)j * m + row] = vs[row];
+        const double* vj = vs[j & 1];
+        for (int row = t; row < m; row += NT) VT[(long)j * m + row] = vj[row];
         double v[QRPL];
 #pragma unroll
-        for (int i = 0; i < QRPL; ++i) v[i] = vs[lane + 64 * i];
+        for (int i = 0; i < QRPL; ++i) v[i] = vj[lane + 64 * i];
         const double tau = tau_s[j];
         qr_column_step(a0, v, c0, j, nbw, lane, tau, S);
         qr_column_step(a1, v, c1, j, nbw, lane, tau, S);
+        const int jn = j + 1;
+        if (jn < nbw && w == (jn & (QPW - 1))) {
+            if (jn < QPW)
+                qr_reflector(a0, jn, lane, vs[jn & 1], tau_s, S);
+            else
+                qr_reflector(a1, jn, lane, vs[jn & 1], tau_s, S);
+        }
         __syncthreads();
     }
     // coalesced write-back of R and the zeros below it (the reflectors held
