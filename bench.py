@@ -531,12 +531,14 @@ def _serve_once(ite, hamiltonians, stream, workers, max_active, precision, label
                 t_last = time.perf_counter()
             time.sleep(0.02)
         infos = [done[i] for i in ids]
+        failed = [(i, info, ite.ite_server_error(srv, i)) for i, info in zip(ids, infos)
+                  if info["status"] != ite.REQ_DONE]
+        if failed:
+            raise RuntimeError(f"[{label}] {len(failed)} request(s) failed: " +
+                               "; ".join(f"request {i}: {msg} ({info})" for i, info, msg in failed))
         energies = [ite.ite_server_reports(srv, i)[-1]["energy"] for i in ids]
     finally:
         ite.ite_server_destroy(srv)
-    for info in infos:
-        if info["status"] != ite.REQ_DONE:
-            raise RuntimeError(f"request failed: {info}")
     lat = np.array([i["t_done"] - i["t_submit"] for i in infos])
     steps = sum(i["n_steps"] for i in infos)
     makespan = max(i["t_done"] for i in infos) - min(i["t_submit"] for i in infos)

@@ -19,7 +19,6 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
-#include <exception>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -416,31 +415,27 @@ void gmres_batch(ite_ctx* c, const std::vector<BatchItem>& items, int m, int max
         }
         hipGraph_t graph = nullptr;
         HIP_CHECK(hipStreamBeginCapture(c->side, hipStreamCaptureModeThreadLocal));
-        std::exception_ptr failed;
+        bool ok = true;
         try {
             issue(dev, lay, mm, max_cycles, c->side);
-        } catch (...) {
-            failed = std::current_exception();
+        } catch (const Error&) {
+            ok = false;
         }
-        const hipError_t ec = hipStreamEndCapture(c->side, &graph);
-        if (ec == hipErrorStreamCaptureInvalidated || ec == hipErrorStreamCaptureUnsupported) {
-            // a call elsewhere in the process that a capture does not allow
-            // ended it: nothing captured ran, so the same sequence is issued
-            // directly
-            if (graph) (void)hipGraphDestroy(graph);
+        if (hipStreamEndCapture(c->side, &graph) != hipSuccess || !graph) ok = false;
+        if (ok && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            ok = false;
+            exec = nullptr;
+        }
+        if (graph) (void)hipGraphDestroy(graph);
+        if (!ok) {
+            // a call on another thread that a capture does not allow can end
+            // or spoil it; nothing captured ran, so the same sequence is
+            // issued directly (where a genuine launch error surfaces)
             (void)hipGetLastError();
             c->graph_fallbacks++;
             issue(dev, lay, mm, max_cycles, c->stream);
             return;
         }
-        if (failed) {
-            if (graph) (void)hipGraphDestroy(graph);
-            std::rethrow_exception(failed);
-        }
-        HIP_CHECK(ec);
-        const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        HIP_CHECK(e);
         ite_ctx::BatchGraph ent;
         std::memcpy(ent.key, key, sizeof(key));
         ent.exec = exec;

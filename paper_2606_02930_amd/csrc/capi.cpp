@@ -62,9 +62,9 @@ struct TmpCsr {
         cs.val = reinterpret_cast<double*>(blk);
         cs.rowptr = reinterpret_cast<int*>(blk + vb);
         cs.col = reinterpret_cast<int*>(blk + vb + rb);
-        if (!val.empty()) HIP_CHECK(hipMemcpy(cs.val, val.data(), val.size() * 8, hipMemcpyHostToDevice));
-        HIP_CHECK(hipMemcpy(cs.rowptr, rowptr.data(), rowptr.size() * 4, hipMemcpyHostToDevice));
-        if (!col.empty()) HIP_CHECK(hipMemcpy(cs.col, col.data(), col.size() * 4, hipMemcpyHostToDevice));
+        h2d_wait(c, cs.val, val.data(), val.size() * 8);
+        h2d_wait(c, cs.rowptr, rowptr.data(), rowptr.size() * 4);
+        h2d_wait(c, cs.col, col.data(), col.size() * 4);
     }
     ~TmpCsr() {
         if (blk) {
@@ -261,7 +261,7 @@ int ite_mps_create(ite_ctx* c, int L, const int* d, const double* const* spinors
                     if (vv > 0.0) val -= 2.0 * v[r] * v[k] / vv;
                     A[(size_t)r * cols + k] = val;
                 }
-            HIP_CHECK(hipMemcpy(p->A[i], A.data(), A.size() * sizeof(double), hipMemcpyHostToDevice));
+            h2d_wait(c, p->A[i], A.data(), A.size() * sizeof(double));
         }
         p->tau = 0.0;
         p->e_valid = false;
@@ -285,7 +285,7 @@ int ite_mps_load(ite_ctx* c, int L, const int* d, const int* chi, const double* 
             ITE_REQUIRE(A[i] != nullptr, "mps_load: NULL tensor");
             const size_t n = (size_t)chi[i] * d[i] * chi[i + 1];
             for (size_t k = 0; k < n; ++k) ITE_REQUIRE(std::isfinite(A[i][k]), "mps_load: non-finite entry");
-            HIP_CHECK(hipMemcpy(p->A[i], A[i], n * sizeof(double), hipMemcpyHostToDevice));
+            h2d_wait(c, p->A[i], A[i], n * sizeof(double));
         }
         p->D.assign(chi, chi + L + 1);
         *out = p.release();
@@ -301,8 +301,7 @@ int ite_mps_export(ite_mps* p, int* chi, double* const* A) {
             sync(p->ctx);
             for (int i = 0; i < p->L; ++i) {
                 ITE_REQUIRE(A[i] != nullptr, "mps_export: NULL buffer");
-                HIP_CHECK(hipMemcpy(A[i], p->A[i], (size_t)p->D[i] * p->d[i] * p->D[i + 1] * sizeof(double),
-                                    hipMemcpyDeviceToHost));
+                d2h_wait(p->ctx, A[i], p->A[i], (size_t)p->D[i] * p->d[i] * p->D[i + 1] * sizeof(double));
             }
         }
     });

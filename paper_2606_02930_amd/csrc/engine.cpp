@@ -91,6 +91,19 @@ void d2h(ite_ctx* c, double* host, const double* dev, size_t n) {
 void h2d(ite_ctx* c, void* dev, const void* host, size_t bytes) {
     HIP_CHECK(hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, c->stream));
 }
+// Blocking copies through the context's stream (not the legacy stream, whose
+// implicit synchronisation can break a graph capture running on another
+// thread's stream).
+void h2d_wait(ite_ctx* c, void* dev, const void* host, size_t bytes) {
+    if (!bytes) return;
+    HIP_CHECK(hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, c->stream));
+    HIP_CHECK(hipStreamSynchronize(c->stream));
+}
+void d2h_wait(ite_ctx* c, void* host, const void* dev, size_t bytes) {
+    if (!bytes) return;
+    HIP_CHECK(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, c->stream));
+    HIP_CHECK(hipStreamSynchronize(c->stream));
+}
 void d2d(ite_ctx* c, double* dst, const double* src, size_t n) {
     if (n) HIP_CHECK(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
 }
@@ -768,7 +781,7 @@ std::vector<CsrDev> upload_csr(ite_ctx* c, const std::vector<CsrHost>& hs, void*
         out.push_back(dv);
     }
     try {
-        HIP_CHECK(hipMemcpy(*block, staging.data(), bytes, hipMemcpyHostToDevice));
+        h2d_wait(c, *block, staging.data(), bytes);
     } catch (...) {
         dev_free(c, *block);
         *block = nullptr;

@@ -228,6 +228,9 @@ double dot(ite_ctx* c, const double* x, const double* y, size_t n);
 // MPO stage on it (profiled like every contraction of the step).
 void d2h(ite_ctx* c, double* host, const double* dev, size_t n);
 void h2d(ite_ctx* c, void* dev, const void* host, size_t bytes);
+// Blocking copies through the context's stream.
+void h2d_wait(ite_ctx* c, void* dev, const void* host, size_t bytes);
+void d2h_wait(ite_ctx* c, void* host, const void* dev, size_t bytes);
 void d2d(ite_ctx* c, double* dst, const double* src, size_t n);
 void gemm(ite_ctx* c, bool tA, bool tB, int M, int N, int K, double alpha, const double* A, long lda,
           const double* B, long ldb, double beta, const double* C, long ldc, double* D, long ldd);
