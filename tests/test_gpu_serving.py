@@ -14,7 +14,12 @@ evolutions), through the C ABI.
   finishes first when a second worker is free.
 * A request that fails on the device is reported as failed with its message
   and leaves the server usable.
+* FP32-refinement requests batched on four workers while others are being
+  admitted (uploads on other threads during graph captures) all finish, with
+  their alone evolutions to rounding.
 """
+import time
+
 import numpy as np
 import pytest
 
@@ -120,6 +125,41 @@ def test_admission_by_footprint_serialises_when_only_one_fits():
         assert abs(info["footprint"] - fp) <= 1e-6 * fp
     for a, b in zip(infos, infos[1:]):
         assert b["t_admit"] >= a["t_done"]
+
+
+def test_fp32_requests_with_admissions_during_captures():
+    # four workers batching FP32 refinement (graph-captured batched solves,
+    # two precisions per slot) while further requests are admitted (MPO and
+    # state uploads on other threads): every request finishes, with the
+    # evolution it has when run alone to rounding
+    require_gpu()
+    reqs = []
+    for k in range(10):
+        L, chi = 10 + 2 * (k % 3), 16 + 8 * (k % 2)
+        o = dict(chi_max=chi, cutoff=1e-10, precision=ite.PREC_FP32_IR if k % 4 else ite.PREC_FP64)
+        reqs.append((hamiltonians.heisenberg(L), random_spinors(rng_for(9, k), L, 2), chi, 0.01, 1.0 + 0.5 * (k % 3),
+                     1.3, o))
+    srv = ite.ite_server_create(0, workers=4, max_active=2, mem_cap=50e9)
+    try:
+        ids = []
+        for (W, sp, chi, t0, t1, r, o) in reqs:
+            ids.append(ite.ite_server_submit(srv, W, sp, chi, t0, t1, r, ite.ite_default_opts(**o)))
+            time.sleep(0.05)
+        infos = [ite.ite_server_wait(srv, i, 120.0) for i in ids]
+        for i, info in zip(ids, infos):
+            assert info["status"] == ite.REQ_DONE, (info, ite.ite_server_error(srv, i))
+        mixed = [ite.ite_server_reports(srv, i) for i in ids]
+    finally:
+        ite.ite_server_destroy(srv)
+    ctx = ite.ite_ctx_create(0)
+    try:
+        for (W, sp, chi, t0, t1, r, o), reps_m in zip(reqs, mixed):
+            reps_a, _ = _alone(ctx, W, sp, chi, t0, t1, r, o)
+            assert len(reps_a) == len(reps_m)
+            for a, m in zip(reps_a, reps_m):
+                assert abs(a["energy"] - m["energy"]) <= 1e-10 * abs(a["energy"])
+    finally:
+        ite.ite_ctx_destroy(ctx)
 
 
 def test_short_request_overtakes_a_long_one():
