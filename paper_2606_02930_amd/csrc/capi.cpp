@@ -639,8 +639,9 @@ int ite_debug_gemm(ite_ctx* c, int transA, int transB, int M, int N, int K, doub
         g.alpha = alpha; g.beta = beta; g.C = C; g.ldc = ldc; g.D = D; g.ldd = ldd;
         g.lda = lda; g.ldb = ldb;
         if (prec == ITE_PREC_FP64) {
-            g.A = A; g.B = B;
-            gemm_f64(g, c->stream);
+            // the library's FP64 product dispatch (K parts for under-filled
+            // outputs with a long K)
+            gemm(c, g.tA, g.tB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, D, ldd);
         } else {
             const size_t na = (size_t)(transA ? K : M) * lda, nbb = (size_t)(transB ? N : K) * ldb;
             if (prec == ITE_PREC_FP32_IR) {

@@ -58,6 +58,26 @@ def test_gemm_f64(env, tA, tB, shape):
     assert rel_err(host(dD), want + (A.T if tA else A) @ (B.T if tB else B)) < 1e-13
 
 
+@pytest.mark.parametrize("tA,tB", [(0, 0), (0, 1), (1, 0)])
+@pytest.mark.parametrize("shape", [(5120, 2048, 1024), (4096, 1024, 5120), (5000, 2048, 1024)])
+def test_gemm_large_dispatch(env, tA, tB, shape):
+    # the library's FP64 dispatch at the block sizes of the 1024 bond: 640
+    # tiles on 512 workgroup slots (5000 rows: the last tile row partial) in
+    # one launch; 256 tiles with K = 5120 (half the slots): two K parts
+    # summed in a fixed order
+    torch, ctx = env
+    M, N, K = shape
+    rng = np.random.default_rng(M + N + K + 3 * tA + tB)
+    A = rng.standard_normal((K, M) if tA else (M, K))
+    B = rng.standard_normal((N, K) if tB else (K, N))
+    C = rng.standard_normal((M, N))
+    want = 0.75 * (A.T if tA else A) @ (B.T if tB else B) - 0.5 * C
+    dA, dB, dC = dev(torch, A), dev(torch, B), dev(torch, C)
+    dD = torch.zeros((M, N), dtype=torch.float64, device="cuda")
+    ite.ite_debug_gemm(ctx, tA, tB, M, N, K, 0.75, dA, A.shape[1], dB, B.shape[1], -0.5, dC, N, dD, N, 0)
+    assert rel_err(host(dD), want) < 1e-13
+
+
 @pytest.mark.parametrize("prec", [1, 2])
 @pytest.mark.parametrize("tA,tB", [(0, 0), (0, 1), (1, 0), (1, 1)])
 @pytest.mark.parametrize("shape", [(200, 136, 520), (37, 133, 517), (256, 128, 1024), (136, 200, 72)])
