@@ -165,7 +165,7 @@ int ite_ctx_profile(ite_ctx* ctx, int enable);
 int ite_ctx_profile_read(ite_ctx* ctx, long long* launches, double* ms, double* flops);
 /* Per-kernel launch profile since the last enable, by kind: 0 FP64
  * contraction GEMMs (every launch timed), 1 Jacobi Gram, 2 Jacobi inner
- * sweep, 3 Jacobi rotation (every 8th launch of a kind timed).  launches: all
+ * sweep, 3 Jacobi rotation (every 32nd launch of a kind timed).  launches: all
  * launches; timed, ms_timed: the timed ones and their summed device time;
  * flops, bytes: the algorithmic work of all launches (Jacobi: of the pairs
  * and column chunks the kernels actually processed). */

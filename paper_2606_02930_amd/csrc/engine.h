@@ -45,7 +45,7 @@ struct ite_ctx {
     // launch profiler (observability): FP64 GEMM launches are all timed,
     // Jacobi launches every `jac_period`-th of a kind; see LaunchProbe
     bool prof_on = false;
-    int jac_period = 8;
+    int jac_period = 32;
     std::vector<hipEvent_t> prof_events;
     size_t prof_used = 0;
     std::vector<int> prof_kind;                 // kind of each recorded event pair

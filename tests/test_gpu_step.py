@@ -225,6 +225,39 @@ def test_runs_are_deterministic(ctx):
     assert all(np.array_equal(a, b) for a, b in zip(out[0][1], out[1][1]))
 
 
+def test_launch_profiler_counts_and_times(ctx):
+    # full bonds of 64: 128-row splits take the multi-pair Jacobi (Gram,
+    # inner and fused rotation launches); every GEMM launch is timed, every
+    # 32nd Jacobi launch of a kind; the profile gives the same step bits
+    L, chi = 12, 64
+    sp = random_spinors(rng_for(1, 8), L, 2)
+    H = ite.ite_mpo_load(ctx, hamiltonians.heisenberg(L))
+    o = _opts(chi_max=chi, cutoff=0.0)
+    try:
+        runs = []
+        for prof in (False, True):
+            psi = ite.ite_mps_create(ctx, sp, chi, pad_full=True)
+            ite.ite_ctx_profile(ctx, prof)
+            r = ite.ite_imag_step(ctx, psi, H, 0.05, o)
+            kinds = [ite.ite_ctx_profile_kernel(ctx, k) for k in (ite.PROBE_GEMM, ite.PROBE_GRAM, ite.PROBE_INNER,
+                                                                 ite.PROBE_ROTATE)]
+            n, ms, fl = ite.ite_ctx_profile_read(ctx)
+            ite.ite_ctx_profile(ctx, False)
+            runs.append((r["energy"], ite.ite_mps_export(ctx, psi, [2] * L)))
+            ite.ite_mps_destroy(psi)
+        gemm, gram, inner, rot = kinds
+        assert gemm["launches"] > 0 and gemm["timed"] == gemm["launches"] == n
+        assert gemm["ms_timed"] > 0.0 and abs(gemm["ms_timed"] - ms) <= 1e-9 * ms and gemm["flops"] == fl > 0.0
+        for k in (gram, inner, rot):
+            assert k["launches"] > 0 and k["flops"] > 0.0
+            assert (k["launches"] + 31) // 32 >= k["timed"] >= k["launches"] // 32
+            assert k["timed"] == 0 or k["ms_timed"] > 0.0
+        assert runs[0][0] == runs[1][0]
+        assert all(np.array_equal(a, b) for a, b in zip(runs[0][1], runs[1][1]))
+    finally:
+        ite.ite_mpo_destroy(H)
+
+
 def test_boundary_error_paths(ctx):
     L = 6
     H = ite.ite_mpo_load(ctx, hamiltonians.heisenberg(L))
