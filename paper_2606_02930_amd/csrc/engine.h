@@ -54,8 +54,8 @@ struct ite_ctx {
     double prof_ms[ite::PK_COUNT] = {};
     double prof_flops[ite::PK_COUNT] = {}, prof_bytes[ite::PK_COUNT] = {};
     // batched solves: a private stream (ordered after `stream` by events) on
-    // which the launch sequence of a batch is captured once as a graph and
-    // replayed while the batch keeps its size and budget
+    // which the launch sequence of a batch is captured as a graph and
+    // replayed while the batch keeps its size, budget and precision
     bool use_graphs = true;
     hipStream_t side = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
