@@ -47,3 +47,16 @@ def test_block_equivalents_of_a_uniform_chain(L):
     chi = 8
     dims = [chi] * (L + 1)
     assert abs(bench.block_equivalents(dims, 2, 5) - 2 * (L - 1)) < 1e-12
+
+
+def test_cpu_baseline_reports_all_threads_and_one_thread():
+    # the oracle leg at a small bond (the bench runs it at the workload's):
+    # the all-thread block and the same block on one thread, both extrapolated
+    # by the same block equivalents
+    from paper_2606_02930_amd import hamiltonians
+    W = hamiltonians.heisenberg(8)
+    dims = [1, 2, 4, 8, 16, 8, 4, 2, 1]
+    cb = bench.cpu_baseline(dims, 2, W)
+    assert cb["kind"] == "oracle" and cb["value"] > 0.0 and cb["cores"] >= 1
+    single = cb["single_core"]
+    assert "error" in single or (single["cores"] == 1 and single["value"] > 0.0 and single["block_s"] > 0.0)
