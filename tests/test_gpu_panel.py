@@ -250,6 +250,34 @@ def test_gl_panel_at_complete_bonds_equals_dense_panel(ctx, p):
     assert 1 - abs(v @ states[-1]) < 1e-10
 
 
+@pytest.mark.parametrize("p", [4, 5])
+def test_gl_panel_many_nodes_matches_oracle(ctx, p):
+    # four and five nodes on a spin-1/2 chain: the node bond needs rank
+    # p + 1 > 4 while the first block's columns (site 1 and the bond of 2
+    # behind it) hold 4, so the single sweep is not the exact panel even at
+    # complete bonds (about 6e-6 from it here); the library follows the
+    # oracle's augmented sweep step for step (96-row splits: multi-pair Jacobi)
+    L, chi = 8, 64
+    sp = random_spinors(rng_for(0, 40 + p), L, 2)
+    grid = ed.loggrid(0.01, 20.0, 2.0)
+    kw = dict(shift_mode="track", chi_max=chi, cutoff=0.0, krylov_dim=10, max_cycles=400, tol_loc=1e-13)
+    psi = ite.ite_mps_create(ctx, sp, chi, pad_full=True)
+    Hm = ite.ite_mpo_load(ctx, hamiltonians.heisenberg(L))
+    try:
+        reps = ite.ite_evolve_grid(ctx, psi, Hm, grid, _opts(scheme="gl", gl_nodes=p, **kw))
+        out = ite.ite_mps_export(ctx, psi, [2] * L)
+    finally:
+        ite.ite_mps_destroy(psi)
+        ite.ite_mpo_destroy(Hm)
+    o_out, o_reps = gauss.gl_evolve(omps.product_state(sp, chi, pad_full=True), ompo.heisenberg_mpo(L), grid, p,
+                                    omps.StepOptions(**kw))
+    assert len(reps) == len(o_reps) == len(grid) - 1
+    for r, orr in zip(reps, o_reps):
+        assert r["max_chi"] == orr.max_chi
+        assert abs(r["energy"] - orr.energy) <= 1e-10 * abs(orr.energy)
+    assert 1 - abs(mps_overlap(out, o_out)) <= 1e-10
+
+
 @pytest.mark.parametrize("p", [2, 3])
 def test_gl_panel_paper_budget_matches_oracle(ctx, p):
     L, chi = 10, 16
