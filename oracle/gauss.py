@@ -39,6 +39,12 @@ Readings (the paper leaves the details to a later publication):
     level.)
   * the MPO of (H - s) is the direct sum of H's MPO and -s times the identity
     (bond dimension w + 1), which needs no knowledge of H's MPO layout;
+  * the node bond needs rank p + 1, but the first block of the sweep can
+    give it at most d_1 D_2 (with psi's bonds): when p + 1 is larger (p >= 4
+    on a spin-1/2 chain), the augmented state's bonds that are complete
+    within chi_max are widened to complete before the sweep by zero-weight
+    orthonormal completions (``augmented_state``), without which the panel
+    is not exact even at complete bonds;
   * after the contraction the bonds near the left end can be larger than
     the chain can need (the augmented left space is p + 1 times larger):
     every bond up to the last one above min(prod d left, prod d right,
@@ -153,10 +159,36 @@ def augmented_mpo(W, p: int, s: float):
     return [At.reshape(1, 1, p + 1, p + 1)] + shifted_mpo(W, s)
 
 
-def augmented_state(psi, p: int):
-    """(1 / sqrt(p + 1)) (1, .., 1) (x) psi as an MPS on L + 1 sites."""
+def augmented_state(psi, p: int, chi_max: int | None = None):
+    """(1 / sqrt(p + 1)) (1, .., 1) (x) psi as an MPS on L + 1 sites.
+
+    The sweep can give the node bond rank at most d_1 D_2 in its first block
+    (site 1's dimension times the bond behind it); when p + 1 exceeds that,
+    the bonds whose complete dimension in the augmented chain is at most
+    chi_max are widened to it before the sweep, right to left: a widened
+    right bond gets zero columns, and a widened left bond gets the trailing
+    columns of the Householder Q of the site's rows transposed (an
+    orthonormal completion of its rows, as numpy's complete QR computes it).
+    The added basis states carry no weight, so the state is the same and
+    stays right-orthonormal with the centre on the node site."""
     node = np.full((1, p + 1, 1), 1.0 / math.sqrt(p + 1))
-    return [node] + [a.copy() for a in psi]
+    A = [node] + [a.copy() for a in psi]
+    if chi_max is None or p + 1 <= psi[0].shape[1] * psi[0].shape[2]:
+        return A
+    n = len(A)
+    complete = omps.full_dims(n, [a.shape[1] for a in A], 2 ** 62)
+    cur = omps.bond_dims(A)
+    tgt = [complete[k] if complete[k] <= chi_max else cur[k] for k in range(n + 1)]
+    for i in range(n - 1, -1, -1):
+        Dl, d, Dr = A[i].shape
+        if tgt[i + 1] > Dr:
+            A[i] = np.concatenate([A[i], np.zeros((Dl, d, tgt[i + 1] - Dr))], axis=2)
+            Dr = tgt[i + 1]
+        if i > 0 and tgt[i] > Dl:
+            R = A[i].reshape(Dl, d * Dr)
+            Q, _ = np.linalg.qr(R.T, mode="complete")
+            A[i] = np.concatenate([R, Q[:, Dl:tgt[i]].T], axis=0).reshape(tgt[i], d, Dr)
+    return A
 
 
 def contract_node(aug, v):
@@ -195,8 +227,8 @@ def gl_step(psi, W, dtau: float, p: int, opts):
     with the energy and shift of the physical chain."""
     s = omps.expectation(psi, W) if opts.shift_mode == "track" else opts.shift
     Wa = augmented_mpo(W, p, s)
-    xa, rep = omps.imag_step(augmented_state(psi, p), Wa, dtau, replace(opts, scheme="be", shift_mode="fixed",
-                                                                          shift=0.0))
+    xa, rep = omps.imag_step(augmented_state(psi, p, opts.chi_max), Wa, dtau,
+                             replace(opts, scheme="be", shift_mode="fixed", shift=0.0))
     r_inf, w = end_weights(p)
     out = recompress(contract_node(xa, np.concatenate([[r_inf], w])), opts.chi_max, opts.tie_rel)
     nrm = float(np.linalg.norm(out[0]))

@@ -2,8 +2,9 @@
 quadrature and collocation order conditions, the diagonal Pade approximant of
 the exponential in closed form, the one-node case against the trapezoid step,
 the convergence order, the right-end read-off, the shifted and augmented MPOs
-against their dense operators, and the MPS panel at complete bonds against
-the dense panel."""
+against their dense operators, the widened augmented state (the same state,
+right-orthonormal), and the MPS panel at complete bonds against the dense
+panel (with four and five nodes only through the widening)."""
 import math
 
 import numpy as np
@@ -119,7 +120,26 @@ def test_augmented_state_and_node_contraction():
     assert np.abs(mps.to_vector(gauss.contract_node(aug, coef)) - 0.5 * coef.sum() * v).max() < 1e-15
 
 
-@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("p", [4, 5, 7])
+def test_widened_augmented_state_is_the_same_state(p):
+    # p + 1 > d_1 D_2 = 4: the bonds complete within chi_max are widened by
+    # zero-weight orthonormal completions; same vector, right-orthonormal
+    # sites, the complete bond dimensions (capped where they exceed chi_max)
+    L, chi = 6, 24
+    psi = mps.product_state(random_spinors(rng_for(0, 12), L, 2), 64, pad_full=True)
+    plain = gauss.augmented_state(psi, p)
+    wide = gauss.augmented_state(psi, p, chi)
+    assert np.abs(mps.to_vector(wide) - mps.to_vector(plain)).max() < 1e-14
+    for a in wide[1:]:
+        assert mps.right_orthonormality_error(a) < 1e-13
+    complete = mps.full_dims(L + 1, [p + 1] + [2] * L, 2 ** 62)
+    want = [c if c <= chi else b for c, b in zip(complete, mps.bond_dims(plain))]
+    assert mps.bond_dims(wide) == want and max(want) > max(mps.bond_dims(plain))
+    # p + 1 <= 4: left as it is
+    assert mps.bond_dims(gauss.augmented_state(psi, 3, chi)) == mps.bond_dims(gauss.augmented_state(psi, 3))
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("shift_mode", ["fixed", "track"])
 def test_mps_panel_equals_dense_panel_at_complete_bonds(p, shift_mode):
     L = 6
