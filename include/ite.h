@@ -253,11 +253,12 @@ int ite_mps_set_tau(ite_mps* psi, double tau);
  * (p, p) Pade approximant of exp(-h (H - s)) applied to psi; w = A^-T b for
  * the Gauss weights b, r_inf = 1 - b^T A^-1 1) is the node site contracted
  * into site 1, with the bonds cut back to the chain's own by exact two-site
- * splits; then normalised.  tau advances by h.  The one sweep gives the
- * panel exactly (at complete bonds and a converged local solve) only while
- * p + 1 <= d_1 D_2, the column dimension of the first block at the sweep's
- * start (p <= 3 for a spin-1/2 chain): beyond that the node bond cannot take
- * its full rank in the first half sweep.
+ * splits; then normalised.  tau advances by h.  When p + 1 exceeds d_1 D_2
+ * (the most rank the sweep's first block can give the node bond with psi's
+ * bonds), the augmented state's bonds are first widened by zero-weight
+ * orthonormal completions: to complete where that is within chi_max, else
+ * to what the node rank needs to pass; so the sweep gives the panel exactly
+ * at complete bonds for any p.
  * Errors: EINVAL (h <= 0 or non-finite, bad options), ESTATE (L or d of psi
  * and H differ), ENOMEM, EDEVICE, ENONFINITE (psi left unchanged). */
 int ite_imag_step(ite_mps* psi, const ite_mpo* H, double h,

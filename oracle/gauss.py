@@ -165,10 +165,13 @@ def augmented_state(psi, p: int, chi_max: int | None = None):
     The sweep can give the node bond rank at most d_1 D_2 in its first block
     (site 1's dimension times the bond behind it); when p + 1 exceeds that,
     the bonds whose complete dimension in the augmented chain is at most
-    chi_max are widened to it before the sweep, right to left: a widened
-    right bond gets zero columns, and a widened left bond gets the trailing
-    columns of the Householder Q of the site's rows transposed (an
-    orthonormal completion of its rows, as numpy's complete QR computes it).
+    chi_max are widened to it before the sweep, and the others to at least
+    what the node rank needs to pass (p + 1 over the site dimensions
+    between; a bond at most d_i times the widened bond right of site i),
+    right to left: a widened right bond gets
+    zero columns, and a widened left bond gets the trailing columns of the
+    Householder Q of the site's rows transposed (an orthonormal completion
+    of its rows, as numpy's complete QR computes it).
     The added basis states carry no weight, so the state is the same and
     stays right-orthonormal with the centre on the node site."""
     node = np.full((1, p + 1, 1), 1.0 / math.sqrt(p + 1))
@@ -176,9 +179,19 @@ def augmented_state(psi, p: int, chi_max: int | None = None):
     if chi_max is None or p + 1 <= psi[0].shape[1] * psi[0].shape[2]:
         return A
     n = len(A)
-    complete = omps.full_dims(n, [a.shape[1] for a in A], 2 ** 62)
+    dims = [a.shape[1] for a in A]
+    complete = omps.full_dims(n, dims, 2 ** 62)
     cur = omps.bond_dims(A)
-    tgt = [complete[k] if complete[k] <= chi_max else cur[k] for k in range(n + 1)]
+    # bonds complete within chi_max: complete; others at least what the node
+    # rank p + 1 needs to pass (p + 1 over the dimensions between)
+    need = [1] * (n + 1)
+    need[1] = p + 1
+    for k in range(2, n):
+        need[k] = -(-need[k - 1] // dims[k - 1])
+    tgt = [complete[k] if complete[k] <= chi_max else max(cur[k], min(need[k], chi_max)) for k in range(n + 1)]
+    # a site's rows can be completed only within d_i times its right bond
+    for k in range(n - 1, 0, -1):
+        tgt[k] = max(cur[k], min(tgt[k], dims[k] * tgt[k + 1]))
     for i in range(n - 1, -1, -1):
         Dl, d, Dr = A[i].shape
         if tgt[i + 1] > Dr:

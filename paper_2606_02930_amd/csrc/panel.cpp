@@ -193,6 +193,61 @@ ite_mps* ensure_aux(ite_mps* psi, int L, const std::vector<int>& d) {
     return psi->aux;
 }
 
+// Widen the bonds of the augmented state that are complete within chi to
+// complete, the others to at least what the node rank needs to pass (the
+// node site first, of dimension p + 1; every other site right-orthonormal;
+// a bond at most d_i times the widened bond right of site i): right to left, a
+// widened right bond gets zero columns and a widened left bond the trailing
+// rows of Q^T for the Householder QR of the site's rows transposed (an
+// orthonormal completion of its rows).  The added basis states carry no
+// weight: the same state, still right-orthonormal.
+void widen_augmented(ite_ctx* c, ite_mps* a, int chi) {
+    const int n = a->L;
+    // what the node rank needs at each bond to pass: p + 1 over the
+    // dimensions between
+    std::vector<int> need(n + 1, 1);
+    need[1] = a->d[0];
+    for (int k = 2; k < n; ++k) need[k] = (need[k - 1] + a->d[k - 1] - 1) / a->d[k - 1];
+    std::vector<int> tgt(n + 1);
+    for (int k = 0; k <= n; ++k) {
+        double left = 1.0, right = 1.0;
+        for (int i = 0; i < k; ++i) left *= a->d[i];
+        for (int i = k; i < n; ++i) right *= a->d[i];
+        const double complete = std::min(left, right);
+        tgt[k] = complete <= (double)chi ? (int)complete : std::max(a->D[k], std::min(need[k], chi));
+        tgt[k] = std::min(std::max(tgt[k], a->D[k]), a->Dcap[k]);
+    }
+    // a site's rows can be completed only within d_i times its right bond
+    for (int k = n - 1; k >= 1; --k) tgt[k] = std::max(a->D[k], std::min(tgt[k], a->d[k] * tgt[k + 1]));
+    const std::vector<int> D0 = a->D;   // the tensors' shapes before widening
+    for (int i = n - 1; i >= 0; --i) {
+        const int Dl = D0[i], di = a->d[i], Dr = D0[i + 1];
+        const int Tl = i == 0 ? Dl : tgt[i], Tr = tgt[i + 1];
+        if (Tl == Dl && Tr == Dr) continue;
+        const size_t ncol = (size_t)di * Tr;
+        double* w = slot_t<double>(c, SL_TPSI, (size_t)Tl * ncol);
+        // the site's rows with zero columns for the widened right bond
+        fill(w, 0.0, (size_t)Tl * ncol, c->stream);
+        HIP_CHECK(hipMemcpy2DAsync(w, sizeof(double) * Tr, a->A[i], sizeof(double) * Dr, sizeof(double) * Dr,
+                                   (size_t)Dl * di, hipMemcpyDeviceToDevice, c->stream));
+        if (Tl > Dl) {
+            // Z = [R^T | I] -> Q^T Z; rows Dl.. of Q^T complete R's rows
+            const int pz = (int)ncol, qz = Dl, ldz = pz + qz;
+            ITE_REQUIRE(pz <= 2048, "gl panel: bond widening beyond 2048 rows");
+            double* Z = slot_t<double>(c, SL_Z, (size_t)pz * ldz);
+            double* ws = slot_t<double>(c, SL_QR, householder_workspace(pz, qz, ldz));
+            jacobi_input(w, Dl, pz, 1, Z, c->stream);
+            householder_rows(Z, pz, qz, ldz, ws, c->stream);
+            HIP_CHECK(hipMemcpy2DAsync(w + (size_t)Dl * ncol, sizeof(double) * ncol, Z + (size_t)Dl * ldz + qz,
+                                       sizeof(double) * ldz, sizeof(double) * ncol, (size_t)(Tl - Dl),
+                                       hipMemcpyDeviceToDevice, c->stream));
+        }
+        d2d(c, a->A[i], w, (size_t)Tl * ncol);
+    }
+    tgt[0] = D0[0];
+    a->D = tgt;
+}
+
 // Milliseconds since t0 after the context's stream has drained.
 double ms_since(ite_ctx* c, std::chrono::steady_clock::time_point t0) {
     sync(c);
@@ -246,6 +301,11 @@ void gl_panel(ite_mps* psi, const ite_mpo* H, double dt, const ite_step_opts& o,
     }
     aug->tau = 0.0;
     aug->e_valid = false;
+    // the node bond needs rank p + 1, and the sweep's first block can give
+    // it at most d_1 D_2 with psi's bonds: then the bonds complete within
+    // chi_max are widened first (the same state)
+    const int chi_w = std::min(o.chi_max, psi->chi_max);
+    if (p + 1 > d[0] * psi->D[1]) widen_augmented(c, aug, chi_w);
     ite_step_opts oa = o;
     oa.scheme = ITE_SCHEME_BE;
     oa.shift_mode = ITE_SHIFT_FIXED;

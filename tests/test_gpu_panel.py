@@ -221,11 +221,13 @@ def test_mps_rhs_step_paper_budget_matches_oracle(ctx, model):
 # Gauss-Legendre panel
 # ---------------------------------------------------------------------------
 
-@pytest.mark.parametrize("p", [1, 2, 3])
-def test_gl_panel_at_complete_bonds_equals_dense_panel(ctx, p):
-    # chi 32 holds the augmented state (node site of dimension p + 1 <= 4)
-    # exactly; the chain's own bonds stay at most 16
-    L, chi = 8, 32
+@pytest.mark.parametrize("p,chi", [(1, 32), (2, 32), (3, 32), (4, 64), (5, 64)])
+def test_gl_panel_at_complete_bonds_equals_dense_panel(ctx, p, chi):
+    # chi holds the augmented state exactly (node site of dimension p + 1:
+    # bonds up to 32); with p + 1 > 4 the augmented state's bonds are first
+    # widened to complete (the first block could not give the node bond its
+    # rank otherwise); the chain's own bonds stay at most 16
+    L = 8
     H = ed.heisenberg_dense(L)
     sp = random_spinors(rng_for(0, 40 + p), L, 2)
     grid = ed.loggrid(0.01, 20.0, 2.0)
@@ -254,9 +256,9 @@ def test_gl_panel_at_complete_bonds_equals_dense_panel(ctx, p):
 def test_gl_panel_many_nodes_matches_oracle(ctx, p):
     # four and five nodes on a spin-1/2 chain: the node bond needs rank
     # p + 1 > 4 while the first block's columns (site 1 and the bond of 2
-    # behind it) hold 4, so the single sweep is not the exact panel even at
-    # complete bonds (about 6e-6 from it here); the library follows the
-    # oracle's augmented sweep step for step (96-row splits: multi-pair Jacobi)
+    # behind it) hold 4, so both sides widen the augmented state's bonds by
+    # the same Householder completion before the sweep; the library follows
+    # the oracle step for step (splits of up to 128 rows: multi-pair Jacobi)
     L, chi = 8, 64
     sp = random_spinors(rng_for(0, 40 + p), L, 2)
     grid = ed.loggrid(0.01, 20.0, 2.0)

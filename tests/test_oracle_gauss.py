@@ -137,6 +137,16 @@ def test_widened_augmented_state_is_the_same_state(p):
     assert mps.bond_dims(wide) == want and max(want) > max(mps.bond_dims(plain))
     # p + 1 <= 4: left as it is
     assert mps.bond_dims(gauss.augmented_state(psi, 3, chi)) == mps.bond_dims(gauss.augmented_state(psi, 3))
+    # a product state (bonds 1): p + 1 > d_1 = 2 already for two nodes; the
+    # widening stops where a site's right bond leaves no room (d_i times it)
+    prod = mps.product_state(random_spinors(rng_for(0, 13), 10, 2), 16)
+    for q in (2, 5):
+        wide = gauss.augmented_state(prod, q, 16)
+        assert np.abs(mps.to_vector(wide) - mps.to_vector(gauss.augmented_state(prod, q))).max() < 1e-14
+        dims = mps.bond_dims(wide)
+        assert dims[1] == q + 1 and all(dims[k] <= 2 * dims[k + 1] for k in range(1, len(wide)))
+        for a in wide[1:]:
+            assert mps.right_orthonormality_error(a) < 1e-13
 
 
 @pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
