@@ -165,7 +165,8 @@ def augmented_state(psi, p: int, chi_max: int | None = None):
     The sweep can give the node bond rank at most d_1 D_2 in its first block
     (site 1's dimension times the bond behind it); when p + 1 exceeds that,
     the bonds whose complete dimension in the augmented chain is at most
-    chi_max are widened to it before the sweep, and the others to at least
+    chi_max and above the chain's own are widened to it before the sweep,
+    and the others to at least
     what the node rank needs to pass (p + 1 over the site dimensions
     between; a bond at most d_i times the widened bond right of site i),
     right to left: a widened right bond gets
@@ -188,7 +189,12 @@ def augmented_state(psi, p: int, chi_max: int | None = None):
     need[1] = p + 1
     for k in range(2, n):
         need[k] = -(-need[k - 1] // dims[k - 1])
-    tgt = [complete[k] if complete[k] <= chi_max else max(cur[k], min(need[k], chi_max)) for k in range(n + 1)]
+    # (only where the augmented chain's complete bond exceeds the chain's own:
+    # towards the right end both are the product of the dimensions right of
+    # the bond)
+    own = [1] + omps.full_dims(n - 1, dims[1:], 2 ** 62)
+    tgt = [complete[k] if complete[k] <= chi_max and complete[k] > own[k] else max(cur[k], min(need[k], chi_max))
+           for k in range(n + 1)]
     # a site's rows can be completed only within d_i times its right bond
     for k in range(n - 1, 0, -1):
         tgt[k] = max(cur[k], min(tgt[k], dims[k] * tgt[k + 1]))

@@ -193,8 +193,9 @@ ite_mps* ensure_aux(ite_mps* psi, int L, const std::vector<int>& d) {
     return psi->aux;
 }
 
-// Widen the bonds of the augmented state that are complete within chi to
-// complete, the others to at least what the node rank needs to pass (the
+// Widen the bonds of the augmented state that are complete within chi and
+// above the chain's own complete bond to complete, the others to at least
+// what the node rank needs to pass (the
 // node site first, of dimension p + 1; every other site right-orthonormal;
 // a bond at most d_i times the widened bond right of site i): right to left, a
 // widened right bond gets zero columns and a widened left bond the trailing
@@ -214,7 +215,11 @@ void widen_augmented(ite_ctx* c, ite_mps* a, int chi) {
         for (int i = 0; i < k; ++i) left *= a->d[i];
         for (int i = k; i < n; ++i) right *= a->d[i];
         const double complete = std::min(left, right);
-        tgt[k] = complete <= (double)chi ? (int)complete : std::max(a->D[k], std::min(need[k], chi));
+        // the chain's own complete bond (the node's dimension left out of
+        // the left product): towards the right end the two are the same
+        const double own = k == 0 ? 1.0 : std::min(left / a->d[0], right);
+        tgt[k] = complete <= (double)chi && complete > own ? (int)complete
+                                                           : std::max(a->D[k], std::min(need[k], chi));
         tgt[k] = std::min(std::max(tgt[k], a->D[k]), a->Dcap[k]);
     }
     // a site's rows can be completed only within d_i times its right bond
